@@ -1,0 +1,217 @@
+"""FP64 CPU oracle for the checkerboard Metropolis chain -- TEST INFRASTRUCTURE.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  The product library (paper_1107_5463_amd) never imports,
+links or calls it, and it shares no code with the HIP path.
+
+The arithmetic lives in smc_oracle.c (plain C, double precision, natural site
+order i = x + L*y + L*L*z); this module only marshals numpy arrays through
+ctypes.  Spins: int8 [N] for Ising, float64 [n, N] for XY / Heisenberg.
+Couplings: int8 [d, N] (+-1, scaled by J0) or float32 [d, N] (bond (i, i+mu)).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+J_UNIFORM, J_PM, J_FP32 = 0, 1, 2
+
+
+class _Params(C.Structure):
+    _fields_ = [("d", C.c_int32), ("n", C.c_int32), ("L", C.c_int32), ("J_kind", C.c_int32),
+                ("seed", C.c_uint64), ("replica", C.c_uint32), ("renorm_every", C.c_int32),
+                ("J0", C.c_double), ("J_sigma", C.c_double), ("delta", C.c_double)]
+
+
+class _Stats(C.Structure):
+    _fields_ = [("n_attempt", C.c_int64), ("n_accept", C.c_int64), ("dE_units", C.c_int64),
+                ("dE", C.c_double), ("n_near", C.c_int64)]
+
+
+class _Obs(C.Structure):
+    _fields_ = [("E_int", C.c_int64), ("M_int", C.c_int64), ("E", C.c_double),
+                ("M", C.c_double * 3), ("absM", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        from . import build as _b  # noqa: F401  (build on first use)
+        _b.build()
+    lib = C.CDLL(LIB_PATH)
+    P = C.POINTER(_Params)
+    vp = C.c_void_p
+    lib.oracle_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                         C.POINTER(C.c_uint32)]
+    lib.oracle_philox4x32_10.restype = None
+    lib.oracle_u01.argtypes = [C.c_uint32]
+    lib.oracle_u01.restype = C.c_double
+    lib.oracle_threshold.argtypes = [C.c_double, C.c_double]
+    lib.oracle_threshold.restype = C.c_uint64
+    lib.oracle_init_ising.argtypes = [P, C.c_int, vp]
+    lib.oracle_init_continuous.argtypes = [P, C.c_int, vp]
+    lib.oracle_init_couplings.argtypes = [P, vp]
+    lib.oracle_half_sweep.argtypes = [P, vp, vp, C.c_double, C.c_uint64, C.c_int,
+                                      C.POINTER(_Stats), vp]
+    lib.oracle_renormalize.argtypes = [P, vp]
+    lib.oracle_renormalize.restype = None
+    lib.oracle_measure.argtypes = [P, vp, vp, C.POINTER(_Obs)]
+    lib.oracle_measure.restype = None
+    lib.oracle_bond_accumulate.argtypes = [P, vp, vp]
+    lib.oracle_bond_accumulate.restype = None
+    lib.oracle_sweeps.argtypes = [P, vp, vp, C.c_double, C.c_uint64, C.c_int64, C.c_int64,
+                                  C.POINTER(_Obs), C.POINTER(_Stats)]
+    lib.oracle_ensemble_ising.argtypes = [P, vp, vp, C.c_double, C.c_uint64, C.c_int64,
+                                          C.c_int64, vp]
+    lib.oracle_num_threads.restype = C.c_int
+    for f in ("oracle_init_ising", "oracle_init_continuous", "oracle_init_couplings",
+              "oracle_half_sweep", "oracle_sweeps", "oracle_ensemble_ising"):
+        getattr(lib, f).restype = C.c_int
+    return lib
+
+
+_LIB = None
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        _LIB = _load()
+    return _LIB
+
+
+def philox4x32_10(counter, key):
+    """Raw Philox4x32-10 block: counter (4 x u32), key (2 x u32) -> 4 x u32."""
+    c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in counter])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (C.c_uint32 * 4)()
+    lib().oracle_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def u01(w: int) -> float:
+    return float(lib().oracle_u01(int(w) & 0xFFFFFFFF))
+
+
+def threshold(beta: float, dE: float) -> int:
+    """ceil(2^32 exp(-beta dE)) for dE > 0 (2^32 means always accept)."""
+    return int(lib().oracle_threshold(float(beta), float(dE)))
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
+
+
+@dataclasses.dataclass
+class Obs:
+    E_int: int
+    M_int: int
+    E: float
+    M: tuple
+    absM: float
+
+
+def _obs(o: _Obs) -> Obs:
+    return Obs(int(o.E_int), int(o.M_int), float(o.E), tuple(float(v) for v in o.M),
+               float(o.absM))
+
+
+@dataclasses.dataclass
+class Stats:
+    n_attempt: int = 0
+    n_accept: int = 0
+    dE_units: int = 0
+    dE: float = 0.0
+    n_near: int = 0
+
+
+class OracleLattice:
+    """A lattice held by the oracle, in natural site order."""
+
+    def __init__(self, d: int, n: int, L: int, seed: int, *, J_kind: int = J_UNIFORM,
+                 J0: float = 1.0, J_sigma: float = 0.0, delta: float = 0.0,
+                 renorm_every: int = 100, replica: int = 0, init: str = "hot",
+                 spins=None, J=None):
+        self.p = _Params(d, n, L, J_kind, seed & 0xFFFFFFFFFFFFFFFF, replica, renorm_every,
+                         J0, J_sigma, delta)
+        self.d, self.n, self.L = d, n, L
+        self.N = L ** d
+        self.t = 0
+        if J_kind == J_UNIFORM:
+            self.J = None
+        elif J is not None:
+            self.J = np.ascontiguousarray(J, dtype=np.int8 if J_kind == J_PM else np.float32)
+            assert self.J.shape == (d, self.N)
+        else:
+            self.J = np.zeros((d, self.N), dtype=np.int8 if J_kind == J_PM else np.float32)
+            rc = lib().oracle_init_couplings(C.byref(self.p), self.J.ctypes.data)
+            assert rc == 0
+        if spins is not None:
+            self.s = np.ascontiguousarray(spins, dtype=np.int8 if n == 1 else np.float64).copy()
+        elif n == 1:
+            self.s = np.zeros(self.N, dtype=np.int8)
+            rc = lib().oracle_init_ising(C.byref(self.p), 1 if init == "hot" else 0,
+                                         self.s.ctypes.data)
+            assert rc == 0
+        else:
+            self.s = np.zeros((n, self.N), dtype=np.float64)
+            rc = lib().oracle_init_continuous(C.byref(self.p), 1 if init == "hot" else 0,
+                                              self.s.ctypes.data)
+            assert rc == 0
+
+    @property
+    def _Jp(self):
+        return None if self.J is None else self.J.ctypes.data
+
+    def half_sweep(self, beta: float, colour: int, t: int | None = None, want_margin=False):
+        t = self.t if t is None else t
+        st = _Stats()
+        margin = np.full(self.N, np.nan) if want_margin else None
+        rc = lib().oracle_half_sweep(C.byref(self.p), self.s.ctypes.data, self._Jp, float(beta),
+                                     int(t), int(colour), C.byref(st),
+                                     None if margin is None else margin.ctypes.data)
+        if rc != 0:
+            raise ValueError(f"oracle_half_sweep rejected its arguments (rc={rc})")
+        out = Stats(st.n_attempt, st.n_accept, st.dE_units, st.dE, st.n_near)
+        return (out, margin) if want_margin else out
+
+    def sweep(self, beta: float, n_sweeps: int = 1, measure_every: int = 0):
+        nser = n_sweeps // measure_every if measure_every > 0 else 0
+        series = (_Obs * max(nser, 1))()
+        st = _Stats()
+        rc = lib().oracle_sweeps(C.byref(self.p), self.s.ctypes.data, self._Jp, float(beta),
+                                 int(self.t), int(n_sweeps), int(measure_every), series,
+                                 C.byref(st))
+        if rc != 0:
+            raise ValueError(f"oracle_sweeps rejected its arguments (rc={rc})")
+        self.t += n_sweeps
+        return [_obs(series[k]) for k in range(nser)], Stats(st.n_attempt, st.n_accept,
+                                                             st.dE_units, st.dE, st.n_near)
+
+    def renormalize(self):
+        lib().oracle_renormalize(C.byref(self.p), self.s.ctypes.data)
+
+    def measure(self) -> Obs:
+        o = _Obs()
+        lib().oracle_measure(C.byref(self.p), self.s.ctypes.data, self._Jp, C.byref(o))
+        return _obs(o)
+
+    def bond_accumulate(self, acc: np.ndarray):
+        assert acc.dtype == (np.int64 if self.n == 1 else np.float64)
+        assert acc.shape == (self.d, self.N) and acc.flags.c_contiguous
+        lib().oracle_bond_accumulate(C.byref(self.p), self.s.ctypes.data, acc.ctypes.data)
+
+    def ensemble(self, beta: float, n_sweeps: int, n_chains: int, t0: int = 0) -> np.ndarray:
+        """n_chains independent copies (replica = replica0 + k) of n_sweeps from self.s."""
+        assert self.n == 1
+        out = np.zeros((n_chains, self.N), dtype=np.int8)
+        rc = lib().oracle_ensemble_ising(C.byref(self.p), self.s.ctypes.data, self._Jp,
+                                         float(beta), int(t0), int(n_sweeps), int(n_chains),
+                                         out.ctypes.data)
+        assert rc == 0
+        return out
