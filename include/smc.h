@@ -1,0 +1,179 @@
+/*
+ * smc.h -- C ABI of libsmc: checkerboard single-spin-flip Metropolis sweeps of
+ * nearest-neighbour O(n) spin models on one MI355X (gfx950) GPU.
+ *
+ * Model (Weigel & Yavors'kii, "GPU accelerated Monte Carlo simulations of
+ * lattice spin models", Sec. 2, Eq. (1)): H = -sum_<ij> J_ij s_i . s_j with
+ * n = 1 (Ising, s = +-1), n = 2 (XY) or n = 3 (Heisenberg) unit-vector spins
+ * on a periodic square (d = 2) or simple-cubic (d = 3) lattice of edge L.
+ * Update (Eq. (2)): single-spin Metropolis moves accepted with probability
+ * min[1, exp(-beta dE)], all sites of one checkerboard colour at once, then
+ * the other colour (Sec. 2, checkerboard decomposition).  One sweep = colour
+ * 0 then colour 1 = N attempts.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Sites.  i = x + L*y + L*L*z, colour c = (x + y + z) mod 2, and the index of
+ *   site i within its colour is j = i >> 1 (L even), 0 <= j < N/2.
+ * Device buffers (all caller-owned, all on the device of `stream`; the
+ *   library never allocates, frees or reallocates device memory):
+ *   spins  Ising: int8 [2][N/2], plane c holds the spins +1/-1 of colour c.
+ *          XY / Heisenberg: float [n][2][N/2], component k of site (c, j) at
+ *          k*N + c*N/2 + j.  Aligned to 16 bytes.
+ *   J      SMC_J_UNIFORM: NULL (every bond has J0).
+ *          SMC_J_PM: int8 [d][2][N/2], J[mu][c][j] = +-1 scales J0 on the bond
+ *          from site (c, j) to its +mu neighbour.
+ *          SMC_J_FP32: float [d][2][N/2], the coupling of that bond.
+ *   workspace  at least smc_workspace_bytes(p) bytes, 256-byte aligned:
+ *          reduction partials, an observable slot and, for the fused schedule,
+ *          the second spin buffer.
+ * Random numbers.  Philox4x32-10 (Salmon et al., SC'11), key = seed, counter
+ *   = (block, sweep t, replica, colour | purpose << 1); the same (seed,
+ *   replica) gives the same chain whatever the launch geometry or schedule.
+ * Streams.  Every call enqueues its work on the handle's stream and returns
+ *   without synchronising, except smc_measure, smc_validate and
+ *   smc_get_samples-free reads noted below.
+ * Errors.  0 = SMC_OK, negative codes otherwise; no exception or abort
+ *   crosses the ABI; smc_last_error() gives the calling thread's last message.
+ *   Calls are re-entrant per handle but a handle must not be used from two
+ *   threads at once.
+ */
+#ifndef SMC_H
+#define SMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum smc_status {
+  SMC_OK = 0,
+  SMC_EINVAL = -1,  /* bad d/n/L/beta/delta, NULL or misaligned pointer, small workspace */
+  SMC_ERANGE = -2,  /* sweep counter would pass 2^32 - 1 */
+  SMC_EDEVICE = -3, /* a HIP call failed (its message is in smc_last_error) */
+  SMC_ESTATE = -4   /* smc_validate found a spin or coupling out of range */
+};
+
+enum smc_J_kind { SMC_J_UNIFORM = 0, SMC_J_PM = 1, SMC_J_FP32 = 2 };
+enum smc_init_kind { SMC_INIT_HOT = 0, SMC_INIT_COLD = 1, SMC_INIT_KEEP = 2 };
+
+enum smc_flags {
+  SMC_FLAG_FAST_MATH = 1,        /* hardware transcendentals for continuous spins */
+  SMC_FLAG_SCHEDULE_FUSED = 2,   /* Ising: one kernel per sweep with ping-pong buffers */
+  SMC_FLAG_GENERIC_KERNEL = 4,   /* force the one-site-per-thread kernels (testing) */
+  SMC_FLAG_COUPLINGS_KEEP = 8    /* do not generate J at init; use the caller's values */
+};
+
+enum smc_bond_op { SMC_BOND_RESET = 0, SMC_BOND_ACCUMULATE = 1, SMC_BOND_READ = 2 };
+
+typedef struct smc_params {
+  int32_t d;            /* 2 or 3 */
+  int32_t n;            /* 1 Ising, 2 XY, 3 Heisenberg */
+  int32_t L;            /* even, >= 4 */
+  int32_t J_kind;       /* enum smc_J_kind */
+  uint64_t seed;        /* Philox key */
+  uint32_t replica;     /* third counter word: chain / disorder-sample id */
+  int32_t init;         /* enum smc_init_kind */
+  double J0;            /* uniform coupling, or the scale of +-1 couplings, or the
+                           mean of Gaussian couplings */
+  double J_sigma;       /* standard deviation of Gaussian couplings */
+  double delta;         /* XY: max rotation angle (rad); Heisenberg: cap half-angle */
+  int32_t renorm_every; /* continuous spins: renormalise after sweeps with t % R == 0
+                           (0 = never) */
+  int32_t flags;        /* enum smc_flags */
+} smc_params;
+
+typedef struct smc_obs {
+  int64_t E_int;  /* Ising, uniform or +-1 couplings: -sum_<ij> sign(J_ij) s_i s_j */
+  int64_t M_int;  /* Ising: sum_i s_i */
+  double E;       /* energy (E_int * J0 for integer couplings) */
+  double M[3];    /* magnetisation vector */
+  double absM;    /* |M| */
+} smc_obs;
+
+typedef struct smc_lattice smc_lattice;
+
+/* Bytes of the caller-owned buffers for parameters p (0 if p is invalid). */
+size_t smc_spin_bytes(const smc_params* p);
+size_t smc_coupling_bytes(const smc_params* p);
+size_t smc_workspace_bytes(const smc_params* p);
+/* Bytes of the bond-correlation accumulator: d*N int64 (Ising) or double. */
+size_t smc_bond_bytes(const smc_params* p);
+
+/*
+ * Create a handle bound to caller-owned device buffers and a stream
+ * (hipStream_t passed as void*; NULL = the null stream).  With init HOT or COLD
+ * the library fills `spins` (hot start from the Philox init draws, cold = all
+ * along +x / +1); with KEEP it leaves them.  For SMC_J_PM / SMC_J_FP32 the
+ * couplings are generated from the seed unless SMC_FLAG_COUPLINGS_KEEP.
+ * The sweep counter starts at 0.  The handle is host memory owned by the
+ * library until smc_destroy.  Enqueues work; does not synchronise.
+ */
+int smc_init_lattice(smc_lattice** out, const smc_params* p, void* spins, void* J,
+                     void* workspace, size_t workspace_bytes, void* stream);
+
+/* Rebind the stream used by later calls (hipStream_t as void*). */
+int smc_set_stream(smc_lattice* h, void* stream);
+
+/*
+ * n_sweeps sweeps (Sec. 2: colour 0 then colour 1, Eq. (2) acceptance) at
+ * inverse temperature beta (finite and >= 0, or +infinity for a quench).
+ * Sweep k uses counter t + k; afterwards t += n_sweeps.  Continuous spins are
+ * renormalised after each sweep whose new t is a multiple of renorm_every.
+ * Fails with SMC_ERANGE if t + n_sweeps > 2^32.  Asynchronous.
+ */
+int smc_sweep(smc_lattice* h, double beta, int64_t n_sweeps);
+
+/* One colour only, with counter t (t is not advanced).  Test hook used by the
+ * single-spin and half-sweep parity protocols.  Asynchronous. */
+int smc_half_sweep(smc_lattice* h, double beta, int colour);
+
+/* Energy and magnetisation (Eq. (1)) of the current state, summed in int64
+ * (Ising with integer couplings) or double.  Synchronises the stream. */
+int smc_measure(smc_lattice* h, smc_obs* out);
+
+/* Same, written as an smc_obs to device memory dev_obs (8-byte aligned)
+ * without synchronising. */
+int smc_measure_async(smc_lattice* h, void* dev_obs);
+
+/*
+ * Bond correlations s_i . s_{i+mu} for every bond (the per-bond statistic
+ * behind d ln Z / d J_ij = beta <s_i . s_j>).  acc: caller-owned device buffer
+ * of smc_bond_bytes(p) bytes, laid out [d][2][N/2] like J (int64 for Ising,
+ * double otherwise).
+ *   SMC_BOND_RESET       zero acc and the handle's sample count;
+ *   SMC_BOND_ACCUMULATE  acc += s_i . s_{i+mu} for the current state, count += 1;
+ *   SMC_BOND_READ        out_mean (device, double [d][2][N/2]) = acc / count.
+ * Asynchronous.
+ */
+int smc_bond_correlations(smc_lattice* h, int op, void* acc, void* out_mean);
+int smc_get_samples(const smc_lattice* h, int64_t* samples);
+
+/* Continuous spins: s <- s / |s| now (asynchronous). */
+int smc_renormalize(smc_lattice* h);
+
+/* Check the state: Ising spins in {+1, -1}; continuous | |s| - 1 | < 1e-4 and
+ * finite; couplings finite (and +-1 for SMC_J_PM).  Synchronises.  Returns
+ * SMC_ESTATE if anything is out of range. */
+int smc_validate(smc_lattice* h);
+
+/* Checkpoint / resume: the whole state is (params, t, spins, J, accumulators,
+ * sample count); the random numbers are stateless. */
+int smc_get_sweep_index(const smc_lattice* h, uint64_t* t);
+int smc_set_sweep_index(smc_lattice* h, uint64_t t);
+int smc_set_samples(smc_lattice* h, int64_t samples);
+
+/* Free the handle (never the caller's buffers). */
+int smc_destroy(smc_lattice* h);
+
+/* The calling thread's last error message ("" if none). */
+const char* smc_last_error(void);
+const char* smc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMC_H */

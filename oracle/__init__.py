@@ -215,3 +215,19 @@ class OracleLattice:
                                          out.ctypes.data)
         assert rc == 0
         return out
+
+
+def ising_sweep_sites(lat: "OracleLattice", beta: float, t: int, sites) -> np.ndarray:
+    """Spins of the given natural sites after one sweep with counter t, from
+    lat.s as the state before the sweep (lat is not modified)."""
+    import numpy as _np
+    sites = _np.ascontiguousarray(sites, dtype=_np.int64)
+    out = _np.zeros(len(sites), dtype=_np.int8)
+    f = lib().oracle_ising_sweep_sites
+    f.argtypes = [C.POINTER(_Params), C.c_void_p, C.c_void_p, C.c_double, C.c_uint64, C.c_int64,
+                  C.c_void_p, C.c_void_p]
+    f.restype = C.c_int
+    rc = f(C.byref(lat.p), lat.s.ctypes.data, lat._Jp, float(beta), int(t), len(sites),
+           sites.ctypes.data, out.ctypes.data)
+    assert rc == 0
+    return out

@@ -219,6 +219,7 @@ ORACLE_API uint64_t oracle_threshold(double beta, double dE) {
 ORACLE_API int oracle_init_ising(const oracle_params *p, int hot, int8_t *s) {
   if (!valid(p) || p->n != 1) return -1;
   int64_t N = n_sites(p);
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < N; ++i) {
     if (!hot) { s[i] = 1; continue; }
     uint32_t w[4];
@@ -235,6 +236,7 @@ ORACLE_API int oracle_init_continuous(const oracle_params *p, int hot, double *s
   if (!valid(p) || p->n < 2) return -1;
   int64_t N = n_sites(p);
   const double two_pi = 6.283185307179586476925286766559;
+#pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < N; ++i) {
     double v[3] = {1.0, 0.0, 0.0};
     if (hot) {
@@ -259,7 +261,9 @@ ORACLE_API int oracle_init_couplings(const oracle_params *p, void *J) {
   if (!valid(p)) return -1;
   int64_t N = n_sites(p);
   const double two_pi = 6.283185307179586476925286766559;
+  if (p->J_kind != J_PM && p->J_kind != J_FP32) return -1;
   for (int mu = 0; mu < p->d; ++mu) {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < N; ++i) {
       uint32_t w[4];
       if (p->J_kind == J_PM) {
@@ -271,8 +275,6 @@ ORACLE_API int oracle_init_couplings(const oracle_params *p, void *J) {
         draw(p->seed, (uint32_t)i, (uint32_t)mu, p->replica, (uint32_t)(PURPOSE_COUPLING << 1), w);
         double g = sqrt(-2.0 * log(u01(w[0]))) * cos(two_pi * u01(w[1]));
         ((float *)J)[mu * N + i] = (float)(p->J0 + p->J_sigma * g);
-      } else {
-        return -1;
       }
     }
   }
@@ -295,28 +297,6 @@ static void local_field(const oracle_params *p, const double *s, const void *J, 
   }
 }
 
-/* Ising: m_i = s_i * sum_b sign(J_b) s_b over the 2d bonds of i, so that
- * dE = 2 J0 m_i for uniform and +-J couplings. */
-static int ising_m(const oracle_params *p, const int8_t *s, const void *J, int64_t i) {
-  int sum = 0;
-  for (int mu = 0; mu < p->d; ++mu) {
-    int64_t ip = neighbour(p, i, mu, +1), im = neighbour(p, i, mu, -1);
-    sum += coupling_sign(p, J, mu, i) * s[ip];
-    sum += coupling_sign(p, J, mu, im) * s[im];
-  }
-  return s[i] * sum;
-}
-
-static double ising_h_fp(const oracle_params *p, const int8_t *s, const void *J, int64_t i) {
-  double h = 0.0;
-  for (int mu = 0; mu < p->d; ++mu) {
-    int64_t ip = neighbour(p, i, mu, +1), im = neighbour(p, i, mu, -1);
-    h += coupling(p, J, mu, i) * (double)s[ip];
-    h += coupling(p, J, mu, im) * (double)s[im];
-  }
-  return h;
-}
-
 /* ------------------------------------------------------------------------ */
 /* One half-sweep: every site of colour c attempts one Metropolis move      */
 /* against the current configuration of the other colour (Sec. 2).  Sites of */
@@ -327,58 +307,131 @@ static double ising_h_fp(const oracle_params *p, const int8_t *s, const void *J,
 /* ------------------------------------------------------------------------ */
 static uint32_t site_index_in_colour(int64_t i) { return (uint32_t)(i >> 1); }
 
+/* Decision for Ising site i of colour c whose 2d neighbours (order +x, -x, +y,
+ * -y, +z, -z) hold the spins nb[].  With integer couplings the move is
+ * described by m_i = s_i * sum_b sign(J_b) s_b, dE = 2 J0 m_i.  T: thresholds per m in [-2d, 2d] (integer
+ * couplings).  Returns 1 to flip.  m_out / dE_out / margin (optional) report
+ * the move. */
+static int ising_decide(const oracle_params *p, const void *J, double beta, const uint64_t *T,
+                        uint32_t t, int c, int64_t i, int si, const int nb[6], int *m_out,
+                        double *dE_out, double *margin) {
+  int d = p->d;
+  uint32_t j = site_index_in_colour(i);
+  if (p->J_kind == J_FP32) {
+    double h = 0.0;
+    for (int mu = 0; mu < d; ++mu) {
+      int64_t im = neighbour(p, i, mu, -1);
+      h += coupling(p, J, mu, i) * (double)nb[2 * mu];
+      h += coupling(p, J, mu, im) * (double)nb[2 * mu + 1];
+    }
+    double dE = 2.0 * (double)si * h;
+    uint32_t w[4];
+    draw(p->seed, j >> 2, t, p->replica, (uint32_t)(c | (PURPOSE_CONTINUOUS << 1)), w);
+    double u = u01(w[j & 3]);
+    if (dE_out) *dE_out = dE;
+    if (m_out) *m_out = 0;
+    if (dE <= 0.0) {
+      if (margin) *margin = NAN;
+      return 1;
+    }
+    double pr = exp(-beta * dE);
+    if (margin) *margin = u - pr;
+    return u < pr;
+  }
+  int sum = 0;
+  for (int mu = 0; mu < d; ++mu) {
+    int64_t im = neighbour(p, i, mu, -1);
+    sum += coupling_sign(p, J, mu, i) * nb[2 * mu];
+    sum += coupling_sign(p, J, mu, im) * nb[2 * mu + 1];
+  }
+  int m = si * sum;
+  uint32_t wp[4], wr[4];
+  draw(p->seed, j >> 4, t, p->replica, (uint32_t)(c | (PURPOSE_ISING_PREFIX << 1)), wp);
+  draw(p->seed, j, t, p->replica, (uint32_t)(c | (PURPOSE_ISING_REFINE << 1)), wr);
+  uint32_t prefix = (wp[(j >> 2) & 3] >> (8 * (j & 3))) & 0xffu;
+  uint64_t u32 = ((uint64_t)prefix << 24) | (wr[0] & 0xffffffu);
+  if (m_out) *m_out = m;
+  if (dE_out) *dE_out = 2.0 * p->J0 * m;
+  if (margin) *margin = NAN;
+  return u32 < T[m + 2 * d];
+}
+
+static void gather_ising(const oracle_params *p, const int8_t *s, int64_t i, int nb[6]) {
+  for (int mu = 0; mu < p->d; ++mu) {
+    nb[2 * mu] = s[neighbour(p, i, mu, +1)];
+    nb[2 * mu + 1] = s[neighbour(p, i, mu, -1)];
+  }
+}
+
+static void ising_table(const oracle_params *p, double beta, uint64_t T[13]) {
+  int d = p->d;
+  for (int m = -2 * d; m <= 2 * d; ++m) T[m + 2 * d] = oracle_threshold(beta, 2.0 * p->J0 * m);
+}
+
 static int half_sweep_ising(const oracle_params *p, int8_t *s, const void *J, double beta,
                             uint32_t t, int c, oracle_stats *st, double *margin) {
   int64_t N = n_sites(p);
-  int d = p->d;
-  /* threshold per m in [-2d, 2d]; dE = 2 J0 m (integer couplings) */
   uint64_t T[13];
-  for (int m = -2 * d; m <= 2 * d; ++m) T[m + 2 * d] = oracle_threshold(beta, 2.0 * p->J0 * m);
+  ising_table(p, beta, T);
   int64_t n_att = 0, n_acc = 0, dEu = 0, n_near = 0;
   double dEsum = 0.0;
 #pragma omp parallel for schedule(static) if (N >= 65536) reduction(+ : n_att, n_acc, dEu, n_near, dEsum)
   for (int64_t i = 0; i < N; ++i) {
     if (colour_of(p, i) != c) continue;
-    uint32_t j = site_index_in_colour(i);
     n_att++;
-    int accept;
-    if (p->J_kind == J_FP32) {
-      double dE = 2.0 * (double)s[i] * ising_h_fp(p, s, J, i);
-      uint32_t w[4];
-      draw(p->seed, j >> 2, t, p->replica, (uint32_t)(c | (PURPOSE_CONTINUOUS << 1)), w);
-      double u = u01(w[j & 3]);
-      if (dE <= 0.0) {
-        accept = 1;
-        if (margin) margin[i] = NAN;
-      } else {
-        double pr = exp(-beta * dE);
-        accept = u < pr;
-        if (margin) margin[i] = u - pr;
-        if (fabs(u - pr) < 1e-6) n_near++;
-      }
-      if (accept) dEsum += dE;
-    } else {
-      int m = ising_m(p, s, J, i);
-      uint32_t wp[4], wr[4];
-      draw(p->seed, j >> 4, t, p->replica, (uint32_t)(c | (PURPOSE_ISING_PREFIX << 1)), wp);
-      draw(p->seed, j, t, p->replica, (uint32_t)(c | (PURPOSE_ISING_REFINE << 1)), wr);
-      uint32_t prefix = (wp[(j >> 2) & 3] >> (8 * (j & 3))) & 0xffu;
-      uint64_t u32 = ((uint64_t)prefix << 24) | (wr[0] & 0xffffffu);
-      accept = u32 < T[m + 2 * d];
-      if (margin) margin[i] = NAN;
-      if (accept) {
-        dEu += m;
-        dEsum += 2.0 * p->J0 * m;
-      }
-    }
+    int nb[6], m;
+    double dE, mg;
+    gather_ising(p, s, i, nb);
+    int accept = ising_decide(p, J, beta, T, t, c, i, s[i], nb, &m, &dE, &mg);
+    if (margin) margin[i] = mg;
+    if (!isnan(mg) && fabs(mg) < 1e-6) n_near++;
     if (accept) {
       s[i] = (int8_t)-s[i];
       n_acc++;
+      dEu += m;
+      dEsum += dE;
     }
   }
   if (st) {
     st->n_attempt += n_att; st->n_accept += n_acc; st->dE_units += dEu;
     st->dE += dEsum; st->n_near += n_near;
+  }
+  return 0;
+}
+
+/* Spins of selected sites after one full sweep with counter t, computed from
+ * the state s before the sweep (which is not modified): a colour-0 site needs
+ * only its own update; a colour-1 site is updated against the colour-0
+ * neighbours as the first half-sweep leaves them. */
+ORACLE_API int oracle_ising_sweep_sites(const oracle_params *p, const int8_t *s, const void *J,
+                                        double beta, uint64_t t, int64_t n_sel,
+                                        const int64_t *sites, int8_t *out) {
+  if (!valid(p) || p->n != 1 || t > 0xffffffffull) return -1;
+  uint64_t T[13];
+  ising_table(p, beta, T);
+  int64_t N = n_sites(p);
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < n_sel; ++k) {
+    int64_t i = sites[k];
+    if (i < 0 || i >= N) { out[k] = 0; continue; }
+    int nb[6];
+    if (colour_of(p, i) == 0) {
+      gather_ising(p, s, i, nb);
+      int acc = ising_decide(p, J, beta, T, (uint32_t)t, 0, i, s[i], nb, NULL, NULL, NULL);
+      out[k] = acc ? (int8_t)-s[i] : s[i];
+      continue;
+    }
+    for (int mu = 0; mu < p->d; ++mu) {
+      for (int dir = 0; dir < 2; ++dir) {
+        int64_t q = neighbour(p, i, mu, dir == 0 ? +1 : -1);
+        int nq[6];
+        gather_ising(p, s, q, nq);
+        int acc = ising_decide(p, J, beta, T, (uint32_t)t, 0, q, s[q], nq, NULL, NULL, NULL);
+        nb[2 * mu + dir] = acc ? -s[q] : s[q];
+      }
+    }
+    int acc = ising_decide(p, J, beta, T, (uint32_t)t, 1, i, s[i], nb, NULL, NULL, NULL);
+    out[k] = acc ? (int8_t)-s[i] : s[i];
   }
   return 0;
 }
@@ -502,6 +555,7 @@ ORACLE_API void oracle_measure(const oracle_params *p, const void *s, const void
     const int8_t *si = (const int8_t *)s;
     int64_t Ei = 0, Mi = 0;
     double Ef = 0.0;
+#pragma omp parallel for schedule(static) if (N >= 65536) reduction(+ : Ei, Mi, Ef)
     for (int64_t i = 0; i < N; ++i) {
       Mi += si[i];
       for (int mu = 0; mu < p->d; ++mu) {
@@ -520,9 +574,12 @@ ORACLE_API void oracle_measure(const oracle_params *p, const void *s, const void
     return;
   }
   const double *sv = (const double *)s;
-  double E = 0.0, M[3] = {0.0, 0.0, 0.0};
+  double E = 0.0, M0 = 0.0, M1 = 0.0, M2 = 0.0;
+#pragma omp parallel for schedule(static) if (N >= 65536) reduction(+ : E, M0, M1, M2)
   for (int64_t i = 0; i < N; ++i) {
-    for (int k = 0; k < p->n; ++k) M[k] += sv[k * N + i];
+    M0 += sv[i];
+    M1 += sv[N + i];
+    if (p->n == 3) M2 += sv[2 * N + i];
     for (int mu = 0; mu < p->d; ++mu) {
       int64_t ip = neighbour(p, i, mu, +1);
       double dp = 0.0;
@@ -531,8 +588,8 @@ ORACLE_API void oracle_measure(const oracle_params *p, const void *s, const void
     }
   }
   out->E = E;
-  for (int k = 0; k < 3; ++k) out->M[k] = M[k];
-  out->absM = sqrt(M[0] * M[0] + M[1] * M[1] + M[2] * M[2]);
+  out->M[0] = M0; out->M[1] = M1; out->M[2] = M2;
+  out->absM = sqrt(M0 * M0 + M1 * M1 + M2 * M2);
 }
 
 /* Bond correlations: acc[mu][i] += s_i . s_{i+mu}.  int64 for Ising, double
@@ -540,6 +597,7 @@ ORACLE_API void oracle_measure(const oracle_params *p, const void *s, const void
 ORACLE_API void oracle_bond_accumulate(const oracle_params *p, const void *s, void *acc) {
   int64_t N = n_sites(p);
   for (int mu = 0; mu < p->d; ++mu) {
+#pragma omp parallel for schedule(static) if (N >= 65536)
     for (int64_t i = 0; i < N; ++i) {
       int64_t ip = neighbour(p, i, mu, +1);
       if (p->n == 1) {

@@ -1,0 +1,320 @@
+"""Python binding of libsmc: checkerboard Metropolis sweeps of O(n) lattice spin
+models on MI355X.
+
+Argument marshalling only: buffers are torch tensors on the GPU, their
+pointers and the current torch stream are handed to the C ABI of
+include/smc.h, and every step of the update runs in the HIP kernels of
+libsmc.so.  There is no CPU fallback: without the built library (python -m
+paper_1107_5463_amd.build) every call raises.
+
+Layouts (see include/smc.h): site i = x + L*y + L*L*z has colour
+c = (x+y+z) % 2 and index j = i // 2 within its colour.
+  Ising spins        int8    [2, N/2]          (+1 / -1)
+  XY / Heisenberg    float32 [n, 2, N/2]
+  couplings          int8 / float32 [d, 2, N/2] (bond from (c, j) to its +mu neighbour)
+  bond accumulators  int64 / float64 [d, 2, N/2]
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import math
+import os
+
+__all__ = ["Lattice", "SmcError", "load_library", "lib_path", "Obs", "J_UNIFORM", "J_PM",
+           "J_FP32", "EXPORTS"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsmc.so")
+
+J_UNIFORM, J_PM, J_FP32 = 0, 1, 2
+INIT_HOT, INIT_COLD, INIT_KEEP = 0, 1, 2
+FLAG_FAST_MATH, FLAG_SCHEDULE_FUSED, FLAG_GENERIC_KERNEL, FLAG_COUPLINGS_KEEP = 1, 2, 4, 8
+BOND_RESET, BOND_ACCUMULATE, BOND_READ = 0, 1, 2
+SMC_OK, SMC_EINVAL, SMC_ERANGE, SMC_EDEVICE, SMC_ESTATE = 0, -1, -2, -3, -4
+
+# every symbol declared in include/smc.h
+EXPORTS = ["smc_spin_bytes", "smc_coupling_bytes", "smc_workspace_bytes", "smc_bond_bytes",
+           "smc_init_lattice", "smc_set_stream", "smc_sweep", "smc_half_sweep", "smc_measure",
+           "smc_measure_async", "smc_bond_correlations", "smc_get_samples", "smc_set_samples",
+           "smc_renormalize", "smc_validate", "smc_get_sweep_index", "smc_set_sweep_index",
+           "smc_destroy", "smc_last_error", "smc_version"]
+
+
+class SmcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"smc error {code}: {msg}")
+        self.code = code
+        self.msg = msg
+
+
+class Params(C.Structure):
+    _fields_ = [("d", C.c_int32), ("n", C.c_int32), ("L", C.c_int32), ("J_kind", C.c_int32),
+                ("seed", C.c_uint64), ("replica", C.c_uint32), ("init", C.c_int32),
+                ("J0", C.c_double), ("J_sigma", C.c_double), ("delta", C.c_double),
+                ("renorm_every", C.c_int32), ("flags", C.c_int32)]
+
+
+class _ObsC(C.Structure):
+    _fields_ = [("E_int", C.c_int64), ("M_int", C.c_int64), ("E", C.c_double),
+                ("M", C.c_double * 3), ("absM", C.c_double)]
+
+
+@dataclasses.dataclass
+class Obs:
+    E_int: int
+    M_int: int
+    E: float
+    M: tuple
+    absM: float
+
+
+_LIB = None
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load libsmc.so (built in-tree); raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"libsmc.so not built at {_LIB_PATH}; run python -m paper_1107_5463_amd.build")
+    lib = C.CDLL(_LIB_PATH)
+    P = C.POINTER(Params)
+    vp = C.c_void_p
+    sz = C.c_size_t
+    for f in ("smc_spin_bytes", "smc_coupling_bytes", "smc_workspace_bytes", "smc_bond_bytes"):
+        getattr(lib, f).argtypes = [P]
+        getattr(lib, f).restype = sz
+    lib.smc_init_lattice.argtypes = [C.POINTER(vp), P, vp, vp, vp, sz, vp]
+    lib.smc_set_stream.argtypes = [vp, vp]
+    lib.smc_sweep.argtypes = [vp, C.c_double, C.c_int64]
+    lib.smc_half_sweep.argtypes = [vp, C.c_double, C.c_int]
+    lib.smc_measure.argtypes = [vp, C.POINTER(_ObsC)]
+    lib.smc_measure_async.argtypes = [vp, vp]
+    lib.smc_bond_correlations.argtypes = [vp, C.c_int, vp, vp]
+    lib.smc_get_samples.argtypes = [vp, C.POINTER(C.c_int64)]
+    lib.smc_set_samples.argtypes = [vp, C.c_int64]
+    lib.smc_renormalize.argtypes = [vp]
+    lib.smc_validate.argtypes = [vp]
+    lib.smc_get_sweep_index.argtypes = [vp, C.POINTER(C.c_uint64)]
+    lib.smc_set_sweep_index.argtypes = [vp, C.c_uint64]
+    lib.smc_destroy.argtypes = [vp]
+    lib.smc_last_error.restype = C.c_char_p
+    lib.smc_version.restype = C.c_char_p
+    for f in EXPORTS:
+        if f not in ("smc_spin_bytes", "smc_coupling_bytes", "smc_workspace_bytes", "smc_bond_bytes",
+                     "smc_last_error", "smc_version"):
+            getattr(lib, f).restype = C.c_int
+    _LIB = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != SMC_OK:
+        raise SmcError(rc, load_library().smc_last_error().decode())
+
+
+def _kind(J_kind) -> int:
+    if isinstance(J_kind, str):
+        return {"uniform": J_UNIFORM, "pm": J_PM, "fp32": J_FP32, "gaussian": J_FP32}[J_kind]
+    return int(J_kind)
+
+
+def make_params(d, n, L, seed=0, *, J_kind=J_UNIFORM, J0=1.0, J_sigma=0.0, init="hot",
+                delta=None, renorm_every=100, replica=0, flags=0) -> Params:
+    if delta is None:
+        delta = 1.0 if n > 1 else 0.0
+    init_k = {"hot": INIT_HOT, "cold": INIT_COLD, "keep": INIT_KEEP}[init] if isinstance(init, str) else init
+    return Params(d, n, L, _kind(J_kind), seed & 0xFFFFFFFFFFFFFFFF, replica, init_k, float(J0),
+                  float(J_sigma), float(delta), renorm_every, flags)
+
+
+class Lattice:
+    """One lattice on the current GPU, its state in torch tensors.
+
+    All work is enqueued on the torch stream current at construction (or the
+    one passed); nothing synchronises except measure() and validate()."""
+
+    def __init__(self, d: int, n: int, L: int, seed: int = 0, *, J_kind=J_UNIFORM, J0: float = 1.0,
+                 J_sigma: float = 0.0, init="hot", delta=None, renorm_every: int = 100,
+                 replica: int = 0, fast_math: bool = False, fused: bool = False,
+                 generic: bool = False, spins=None, J=None, device=None, stream=None):
+        import torch
+        lib = load_library()
+        self.torch = torch
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        flags = (FLAG_FAST_MATH if fast_math else 0) | (FLAG_SCHEDULE_FUSED if fused else 0) | (
+            FLAG_GENERIC_KERNEL if generic else 0)
+        if J is not None:
+            flags |= FLAG_COUPLINGS_KEEP
+        if spins is not None and init == "hot":
+            init = "keep"
+        self.params = make_params(d, n, L, seed, J_kind=J_kind, J0=J0, J_sigma=J_sigma, init=init,
+                                  delta=delta, renorm_every=renorm_every, replica=replica,
+                                  flags=flags)
+        p = self.params
+        self.d, self.n, self.L = d, n, L
+        self.N = L ** d
+        if lib.smc_spin_bytes(C.byref(p)) == 0:
+            # let the library produce the error message
+            h = C.c_void_p()
+            _check(lib.smc_init_lattice(C.byref(h), C.byref(p), None, None, None, 0, None))
+        shape = (2, self.N // 2) if n == 1 else (n, 2, self.N // 2)
+        dt = torch.int8 if n == 1 else torch.float32
+        if spins is not None:
+            spins = spins.to(self.device, dt).contiguous().view(shape)
+            self.spins = spins.clone()
+        else:
+            self.spins = torch.empty(shape, dtype=dt, device=self.device)
+        kind = p.J_kind
+        if kind == J_UNIFORM:
+            self.J = None
+        else:
+            jdt = torch.int8 if kind == J_PM else torch.float32
+            if J is not None:
+                self.J = J.to(self.device, jdt).contiguous().view(d, 2, self.N // 2).clone()
+            else:
+                self.J = torch.empty((d, 2, self.N // 2), dtype=jdt, device=self.device)
+        wsb = lib.smc_workspace_bytes(C.byref(p))
+        self.workspace = torch.empty(wsb + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.workspace.data_ptr()) % 256
+        self._ws_ptr = self.workspace.data_ptr() + off
+        self._ws_bytes = wsb
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._h = C.c_void_p()
+        _check(lib.smc_init_lattice(C.byref(self._h), C.byref(p), C.c_void_p(self.spins.data_ptr()),
+                                    None if self.J is None else C.c_void_p(self.J.data_ptr()),
+                                    C.c_void_p(self._ws_ptr), wsb, C.c_void_p(self.stream.cuda_stream)))
+        self._acc = None
+
+    # ------------------------------------------------------------------
+    def _lib(self):
+        return load_library()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib().smc_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def t(self) -> int:
+        v = C.c_uint64()
+        _check(self._lib().smc_get_sweep_index(self._h, C.byref(v)))
+        return int(v.value)
+
+    @t.setter
+    def t(self, value: int):
+        _check(self._lib().smc_set_sweep_index(self._h, int(value)))
+
+    def set_stream(self, stream):
+        self.stream = stream
+        _check(self._lib().smc_set_stream(self._h, C.c_void_p(stream.cuda_stream)))
+
+    def sweep(self, beta: float, n_sweeps: int = 1):
+        _check(self._lib().smc_sweep(self._h, float(beta), int(n_sweeps)))
+
+    def half_sweep(self, beta: float, colour: int):
+        _check(self._lib().smc_half_sweep(self._h, float(beta), int(colour)))
+
+    def measure(self) -> Obs:
+        o = _ObsC()
+        _check(self._lib().smc_measure(self._h, C.byref(o)))
+        return Obs(int(o.E_int), int(o.M_int), float(o.E), tuple(float(v) for v in o.M),
+                   float(o.absM))
+
+    def measure_async(self, dev_slot):
+        """Write the observables (8 x 8-byte smc_obs layout) into a device tensor
+        slot (>= 64 bytes) without synchronising."""
+        assert dev_slot.is_cuda and dev_slot.numel() * dev_slot.element_size() >= 64
+        _check(self._lib().smc_measure_async(self._h, C.c_void_p(dev_slot.data_ptr())))
+
+    @staticmethod
+    def decode_obs(buf) -> list:
+        """Decode a [k, 8] int64 CPU tensor of smc_obs records."""
+        import numpy as np
+        a = buf.cpu().numpy()
+        out = []
+        for row in a.reshape(-1, 8):
+            f = row.view(np.float64)
+            out.append(Obs(int(row[0]), int(row[1]), float(f[2]), (float(f[3]), float(f[4]),
+                                                                    float(f[5])), float(f[6])))
+        return out
+
+    # ------------------------------------------------------------------
+    def bond_accumulator(self):
+        if self._acc is None:
+            t = self.torch
+            self._acc = t.zeros((self.d, 2, self.N // 2),
+                                dtype=t.int64 if self.n == 1 else t.float64, device=self.device)
+        return self._acc
+
+    def bond_reset(self):
+        acc = self.bond_accumulator()
+        _check(self._lib().smc_bond_correlations(self._h, BOND_RESET, C.c_void_p(acc.data_ptr()), None))
+
+    def bond_accumulate(self):
+        acc = self.bond_accumulator()
+        _check(self._lib().smc_bond_correlations(self._h, BOND_ACCUMULATE,
+                                                 C.c_void_p(acc.data_ptr()), None))
+
+    def bond_mean(self):
+        acc = self.bond_accumulator()
+        out = self.torch.empty((self.d, 2, self.N // 2), dtype=self.torch.float64, device=self.device)
+        _check(self._lib().smc_bond_correlations(self._h, BOND_READ, C.c_void_p(acc.data_ptr()),
+                                                 C.c_void_p(out.data_ptr())))
+        return out
+
+    @property
+    def samples(self) -> int:
+        v = C.c_int64()
+        _check(self._lib().smc_get_samples(self._h, C.byref(v)))
+        return int(v.value)
+
+    @samples.setter
+    def samples(self, value: int):
+        _check(self._lib().smc_set_samples(self._h, int(value)))
+
+    def renormalize(self):
+        _check(self._lib().smc_renormalize(self._h))
+
+    def validate(self):
+        _check(self._lib().smc_validate(self._h))
+
+    # ------------------------------------------------------------------
+    def state_dict(self) -> dict:
+        """Everything needed to resume bit-identically (the RNG is stateless)."""
+        d = {"t": self.t, "spins": self.spins.clone(), "samples": self.samples}
+        if self.J is not None:
+            d["J"] = self.J.clone()
+        if self._acc is not None:
+            d["acc"] = self._acc.clone()
+        return d
+
+    def load_state_dict(self, sd: dict):
+        self.spins.copy_(sd["spins"])
+        if "J" in sd and self.J is not None:
+            self.J.copy_(sd["J"])
+        if "acc" in sd:
+            self.bond_accumulator().copy_(sd["acc"])
+        self.t = sd["t"]
+        self.samples = sd.get("samples", 0)
+
+
+def version() -> str:
+    return load_library().smc_version().decode()
+
+
+def beta_c_2d() -> float:
+    """Onsager's critical coupling of the square-lattice Ising model."""
+    return 0.5 * math.log(1.0 + math.sqrt(2.0))

@@ -1,0 +1,87 @@
+// kernels.hpp -- host-side launchers of the libsmc kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device.hpp"
+
+namespace smc {
+
+struct RngKey {
+  uint32_t k0, k1;   // seed low / high word
+  uint32_t replica;  // counter word 2
+};
+
+// Exact unsigned 32-bit division by a runtime constant (Granlund-Montgomery):
+// q = (hi + ((n - hi) >> 1)) >> (l - 1) with hi = umulhi(m, n).
+struct FastDiv {
+  uint32_t d, m, s;
+};
+FastDiv make_fastdiv(uint32_t d);
+
+struct IsingLaunch {
+  Geom g;
+  RngKey key;
+  IsingTable tab;    // integer thresholds (uniform and +-1 couplings)
+  int J_kind;        // 0 uniform, 1 +-1 int8, 2 FP32
+  const void* J;     // [d][2][N/2] or null
+  float beta;        // FP32 couplings only
+  int generic;       // force the one-site-per-thread kernel
+  FastDiv divQ;      // chunks per plane row
+  FastDiv divL;      // edge length
+};
+
+hipError_t launch_ising_half_sweep(const IsingLaunch& a, int8_t* spins, uint32_t t,
+                                   uint32_t colour, hipStream_t st);
+// Chunk kernel requires L % 32 == 0 (plane rows are whole 16-byte chunks).
+bool ising_chunk_supported(const Geom& g, int J_kind);
+
+struct ContLaunch {
+  Geom g;
+  int n;             // 2 or 3
+  RngKey key;
+  int J_kind;
+  float J0;
+  const void* J;
+  float beta;
+  float delta;       // XY max angle
+  float one_minus_cos_cap;  // Heisenberg 1 - cos(theta_max)
+  int fast_math;
+};
+
+hipError_t launch_cont_half_sweep(const ContLaunch& a, float* spins, uint32_t t,
+                                  uint32_t colour, hipStream_t st);
+hipError_t launch_renormalize(const Geom& g, int n, float* spins, hipStream_t st);
+
+hipError_t launch_init_ising(const Geom& g, RngKey key, int hot, int8_t* spins, hipStream_t st);
+hipError_t launch_init_continuous(const Geom& g, int n, RngKey key, int hot, float* spins,
+                                  hipStream_t st);
+hipError_t launch_init_couplings(const Geom& g, int J_kind, RngKey key, double J0, double sigma,
+                                 void* J, hipStream_t st);
+
+struct MeasureLaunch {
+  Geom g;
+  int n;
+  int J_kind;
+  const void* J;
+  double J0;
+};
+
+// Number of per-block partials the measurement writes (workspace sizing).
+int64_t measure_partials(const Geom& g);
+// Reduce to an smc_obs-layout struct at dev_obs; partials: workspace scratch.
+hipError_t launch_measure(const MeasureLaunch& a, const void* spins, void* partials,
+                          void* dev_obs, hipStream_t st);
+
+hipError_t launch_bond_accumulate(const MeasureLaunch& a, const void* spins, void* acc,
+                                  hipStream_t st);
+hipError_t launch_bond_mean(const MeasureLaunch& a, const void* acc, int64_t samples,
+                            double* out, hipStream_t st);
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
+
+// Counts entries out of range into *dev_count (uint32 in device memory).
+hipError_t launch_validate(const MeasureLaunch& a, const void* spins, uint32_t* dev_count,
+                           hipStream_t st);
+
+}  // namespace smc

@@ -1,0 +1,407 @@
+// measure.hip -- energy and magnetisation (Eq. (1)), bond correlations,
+// state validation.
+//
+// Every bond of the bipartite lattice (L even) has exactly one colour-1 end,
+// so E = -sum over colour-1 sites i of sum_b J_b s_i . s_b (all 2d bonds of i),
+// and every colour-0 site is the same-index partner (c = 0, j) of exactly one
+// colour-1 site (c = 1, j): one pass over colour 1 gives both E and M.
+// Partials: one per block, summed in int64 (Ising with integer couplings) or
+// double (FP32 products promoted exactly), then reduced by a single block in a
+// fixed order, so the result is deterministic.
+#include "chunk.hpp"
+
+namespace smc {
+
+struct Partial {
+  int64_t Ei;   // integer energy (uniform / +-1)
+  int64_t Mi;   // integer magnetisation
+  double E;     // double energy (FP32 couplings, continuous spins)
+  double M[3];  // continuous magnetisation
+};
+
+struct ObsOut {  // layout of smc_obs
+  int64_t E_int;
+  int64_t M_int;
+  double E;
+  double M[3];
+  double absM;
+};
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// Block of 256 threads: reduce each field, thread 0 writes the partial.
+__device__ __forceinline__ void block_partial(Partial v, Partial* out) {
+  __shared__ Partial sh[4];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  v.Ei = wave_sum(v.Ei);
+  v.Mi = wave_sum(v.Mi);
+  v.E = wave_sum(v.E);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) v.M[k] = wave_sum(v.M[k]);
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Partial a = sh[0];
+    for (int w = 1; w < 4; ++w) {
+      a.Ei += sh[w].Ei;
+      a.Mi += sh[w].Mi;
+      a.E += sh[w].E;
+      for (int k = 0; k < 3; ++k) a.M[k] += sh[w].M[k];
+    }
+    out[blockIdx.x] = a;
+  }
+}
+
+// Ising, one colour-1 site per thread, any L / coupling kind.
+template <int D, int JK>
+__global__ __launch_bounds__(256) void measure_ising_site(const Geom g, const int8_t* __restrict__ s,
+                                                          const void* __restrict__ J, Partial* out) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  Partial v{0, 0, 0.0, {0.0, 0.0, 0.0}};
+  if (j < g.Nh) {
+    const int64_t Nh = g.Nh;
+    const int8_t* s1 = s + Nh;
+    const int8_t* s0 = s;
+    int32_t x, y, z;
+    site_coords(g, 1u, j, x, y, z);
+    const int si = s1[j];
+    int64_t e = 0;
+    double ef = 0.0;
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) {
+      int32_t xp = x, yp = y, zp = z, xm = x, ym = y, zm = z;
+      if (mu == 0) { xp = wrap(x + 1, g.L); xm = wrap(x - 1, g.L); }
+      if (mu == 1) { yp = wrap(y + 1, g.L); ym = wrap(y - 1, g.L); }
+      if (mu == 2) { zp = wrap(z + 1, g.L); zm = wrap(z - 1, g.L); }
+      const int64_t ip = plane_index(g, xp, yp, zp);
+      const int64_t im = plane_index(g, xm, ym, zm);
+      const int sp = s0[ip], sm = s0[im];
+      if (JK == 2) {
+        const float* Jf = (const float*)J;
+        ef -= (double)Jf[((int64_t)mu * 2 + 1) * Nh + j] * (double)(si * sp);
+        ef -= (double)Jf[((int64_t)mu * 2 + 0) * Nh + im] * (double)(si * sm);
+      } else {
+        int sgp = 1, sgm = 1;
+        if (JK == 1) {
+          const int8_t* Jb = (const int8_t*)J;
+          sgp = Jb[((int64_t)mu * 2 + 1) * Nh + j];
+          sgm = Jb[((int64_t)mu * 2 + 0) * Nh + im];
+        }
+        e -= sgp * si * sp + sgm * si * sm;
+      }
+    }
+    v.Ei = e;
+    v.E = ef;
+    v.Mi = si + s0[j];
+  }
+  block_partial(v, out + 0);
+}
+
+// Ising, one colour-1 chunk of 16 sites per thread (L % 32 == 0, integer J).
+template <int D, bool PM>
+__global__ __launch_bounds__(256) void measure_ising_chunk(const Geom g, const int8_t* __restrict__ s,
+                                                           const int8_t* __restrict__ J,
+                                                           const FastDiv divQ, const FastDiv divL,
+                                                           Partial* out) {
+  const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
+  Partial v{0, 0, 0.0, {0.0, 0.0, 0.0}};
+  if (gid < (uint32_t)(g.Nh >> 4)) {
+    int64_t base;
+    Chunk o, ctr;
+    uint32_t kk[4];
+    chunk_counts<D, PM>(g, s, J, divQ, divL, 1u, gid, base, o, ctr, kk);
+    uint32_t unsat = 0, down = 0;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      unsat = __builtin_amdgcn_sad_u8(kk[w], 0u, unsat);
+      down = __builtin_amdgcn_sad_u8(o.w[w] & kBit1, 0u, down);
+      down = __builtin_amdgcn_sad_u8(ctr.w[w] & kBit1, 0u, down);
+    }
+    // each site: s_i h_i = 2d - 2k; M: 32 sites, down counted twice (bit value 2)
+    v.Ei = -(int64_t)(16 * 2 * D) + 2 * (int64_t)unsat;
+    v.Mi = 32 - (int64_t)down;
+  }
+  block_partial(v, out);
+}
+
+// Continuous spins, one colour-1 site per thread.
+template <int D, int N, int JK>
+__global__ __launch_bounds__(256) void measure_cont_site(const Geom g, const float* __restrict__ s,
+                                                         const void* __restrict__ J, const double J0,
+                                                         Partial* out) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  Partial v{0, 0, 0.0, {0.0, 0.0, 0.0}};
+  if (j < g.Nh) {
+    const int64_t Nh = g.Nh, Nfull = 2 * Nh;
+    const float* s1 = s + Nh;
+    const float* s0 = s;
+    int32_t x, y, z;
+    site_coords(g, 1u, j, x, y, z);
+    double si[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < N; ++k) si[k] = (double)s1[k * Nfull + j];
+    double e = 0.0;
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) {
+      int32_t xp = x, yp = y, zp = z, xm = x, ym = y, zm = z;
+      if (mu == 0) { xp = wrap(x + 1, g.L); xm = wrap(x - 1, g.L); }
+      if (mu == 1) { yp = wrap(y + 1, g.L); ym = wrap(y - 1, g.L); }
+      if (mu == 2) { zp = wrap(z + 1, g.L); zm = wrap(z - 1, g.L); }
+      const int64_t ip = plane_index(g, xp, yp, zp);
+      const int64_t im = plane_index(g, xm, ym, zm);
+      double dp = 0.0, dm = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        dp += si[k] * (double)s0[k * Nfull + ip];
+        dm += si[k] * (double)s0[k * Nfull + im];
+      }
+      double jp = J0, jm = J0;
+      if (JK == 1) {
+        const int8_t* Jb = (const int8_t*)J;
+        jp = J0 * Jb[((int64_t)mu * 2 + 1) * Nh + j];
+        jm = J0 * Jb[((int64_t)mu * 2 + 0) * Nh + im];
+      } else if (JK == 2) {
+        const float* Jf = (const float*)J;
+        jp = Jf[((int64_t)mu * 2 + 1) * Nh + j];
+        jm = Jf[((int64_t)mu * 2 + 0) * Nh + im];
+      }
+      e -= jp * dp + jm * dm;
+    }
+    v.E = e;
+#pragma unroll
+    for (int k = 0; k < N; ++k) v.M[k] = si[k] + (double)s0[k * Nfull + j];
+  }
+  block_partial(v, out);
+}
+
+__global__ __launch_bounds__(256) void finish_kernel(const Partial* __restrict__ parts,
+                                                     const int64_t nparts, const int ising,
+                                                     const int int_couplings, const double J0,
+                                                     ObsOut* __restrict__ obs) {
+  Partial v{0, 0, 0.0, {0.0, 0.0, 0.0}};
+  for (int64_t b = threadIdx.x; b < nparts; b += 256) {
+    const Partial p = parts[b];
+    v.Ei += p.Ei;
+    v.Mi += p.Mi;
+    v.E += p.E;
+    for (int k = 0; k < 3; ++k) v.M[k] += p.M[k];
+  }
+  __shared__ Partial sh[256];
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Partial a = sh[0];
+    for (int w = 1; w < 256; ++w) {
+      a.Ei += sh[w].Ei;
+      a.Mi += sh[w].Mi;
+      a.E += sh[w].E;
+      for (int k = 0; k < 3; ++k) a.M[k] += sh[w].M[k];
+    }
+    ObsOut o;
+    if (ising) {
+      o.E_int = int_couplings ? a.Ei : 0;
+      o.M_int = a.Mi;
+      o.E = int_couplings ? J0 * (double)a.Ei : a.E;
+      o.M[0] = (double)a.Mi;
+      o.M[1] = 0.0;
+      o.M[2] = 0.0;
+      o.absM = fabs((double)a.Mi);
+    } else {
+      o.E_int = 0;
+      o.M_int = 0;
+      o.E = a.E;
+      for (int k = 0; k < 3; ++k) o.M[k] = a.M[k];
+      o.absM = sqrt(a.M[0] * a.M[0] + a.M[1] * a.M[1] + a.M[2] * a.M[2]);
+    }
+    *obs = o;
+  }
+}
+
+int64_t measure_partials(const Geom& g) { return (g.Nh + 255) / 256; }
+
+template <int D>
+static void launch_measure_d(const MeasureLaunch& a, const void* spins, Partial* parts,
+                             int64_t& nparts, hipStream_t st) {
+  const Geom& g = a.g;
+  if (a.n == 1) {
+    if (a.J_kind != 2 && g.L % 32 == 0) {
+      const uint32_t nchunks = (uint32_t)(g.Nh >> 4);
+      nparts = (nchunks + 255) / 256;
+      const FastDiv dq = make_fastdiv((uint32_t)(g.R / 16)), dl = make_fastdiv((uint32_t)g.L);
+      if (a.J_kind == 1)
+        hipLaunchKernelGGL((measure_ising_chunk<D, true>), dim3((unsigned)nparts), dim3(256), 0,
+                           st, g, (const int8_t*)spins, (const int8_t*)a.J, dq, dl, parts);
+      else
+        hipLaunchKernelGGL((measure_ising_chunk<D, false>), dim3((unsigned)nparts), dim3(256), 0,
+                           st, g, (const int8_t*)spins, (const int8_t*)a.J, dq, dl, parts);
+      return;
+    }
+    nparts = (g.Nh + 255) / 256;
+    const dim3 grid((unsigned)nparts);
+    if (a.J_kind == 0)
+      hipLaunchKernelGGL((measure_ising_site<D, 0>), grid, dim3(256), 0, st, g,
+                         (const int8_t*)spins, a.J, parts);
+    else if (a.J_kind == 1)
+      hipLaunchKernelGGL((measure_ising_site<D, 1>), grid, dim3(256), 0, st, g,
+                         (const int8_t*)spins, a.J, parts);
+    else
+      hipLaunchKernelGGL((measure_ising_site<D, 2>), grid, dim3(256), 0, st, g,
+                         (const int8_t*)spins, a.J, parts);
+    return;
+  }
+  nparts = (g.Nh + 255) / 256;
+  const dim3 grid((unsigned)nparts);
+  const float* sf = (const float*)spins;
+#define SMC_MC(N, JK) \
+  hipLaunchKernelGGL((measure_cont_site<D, N, JK>), grid, dim3(256), 0, st, g, sf, a.J, a.J0, parts)
+  if (a.n == 2) {
+    if (a.J_kind == 0) SMC_MC(2, 0); else if (a.J_kind == 1) SMC_MC(2, 1); else SMC_MC(2, 2);
+  } else {
+    if (a.J_kind == 0) SMC_MC(3, 0); else if (a.J_kind == 1) SMC_MC(3, 1); else SMC_MC(3, 2);
+  }
+#undef SMC_MC
+}
+
+hipError_t launch_measure(const MeasureLaunch& a, const void* spins, void* partials,
+                          void* dev_obs, hipStream_t st) {
+  Partial* parts = (Partial*)partials;
+  int64_t nparts = 0;
+  if (a.g.d == 2)
+    launch_measure_d<2>(a, spins, parts, nparts, st);
+  else
+    launch_measure_d<3>(a, spins, parts, nparts, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, st, parts, nparts, a.n == 1 ? 1 : 0,
+                     a.J_kind != 2 ? 1 : 0, a.J0, (ObsOut*)dev_obs);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Bond correlations acc[mu][c][j] += s_(c,j) . s_(c,j)+mu
+// ---------------------------------------------------------------------------
+template <int D, int N>
+__global__ __launch_bounds__(256) void bond_acc_kernel(const Geom g, const void* __restrict__ spins,
+                                                       void* __restrict__ acc) {
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t Nh = g.Nh, Nfull = 2 * Nh;
+  if (gid >= Nfull) return;
+  const uint32_t c = gid >= Nh ? 1u : 0u;
+  const int64_t j = gid - (int64_t)c * Nh;
+  int32_t x, y, z;
+  site_coords(g, c, j, x, y, z);
+#pragma unroll
+  for (int mu = 0; mu < D; ++mu) {
+    int32_t xp = x, yp = y, zp = z;
+    if (mu == 0) xp = wrap(x + 1, g.L);
+    if (mu == 1) yp = wrap(y + 1, g.L);
+    if (mu == 2) zp = wrap(z + 1, g.L);
+    const int64_t ip = (int64_t)(1 - c) * Nh + plane_index(g, xp, yp, zp);
+    const int64_t slot = (int64_t)mu * Nfull + gid;
+    if (N == 1) {
+      const int8_t* s = (const int8_t*)spins;
+      ((int64_t*)acc)[slot] += (int64_t)(s[gid] * s[ip]);
+    } else {
+      const float* s = (const float*)spins;
+      double dp = 0.0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) dp += (double)s[k * Nfull + gid] * (double)s[k * Nfull + ip];
+      ((double*)acc)[slot] += dp;
+    }
+  }
+}
+
+hipError_t launch_bond_accumulate(const MeasureLaunch& a, const void* spins, void* acc,
+                                  hipStream_t st) {
+  const dim3 grid((unsigned)((2 * a.g.Nh + 255) / 256));
+#define SMC_BA(D, N) hipLaunchKernelGGL((bond_acc_kernel<D, N>), grid, dim3(256), 0, st, a.g, spins, acc)
+  if (a.g.d == 2) {
+    if (a.n == 1) SMC_BA(2, 1); else if (a.n == 2) SMC_BA(2, 2); else SMC_BA(2, 3);
+  } else {
+    if (a.n == 1) SMC_BA(3, 1); else if (a.n == 2) SMC_BA(3, 2); else SMC_BA(3, 3);
+  }
+#undef SMC_BA
+  return hipGetLastError();
+}
+
+// mean = accumulated sum / number of samples (a correctly rounded division)
+__global__ __launch_bounds__(256) void bond_mean_kernel(const int64_t total, const int ising,
+                                                        const void* __restrict__ acc,
+                                                        const double count, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  const double v = ising ? (double)((const int64_t*)acc)[i] : ((const double*)acc)[i];
+  out[i] = count > 0.0 ? v / count : 0.0;
+}
+
+hipError_t launch_bond_mean(const MeasureLaunch& a, const void* acc, int64_t samples, double* out,
+                            hipStream_t st) {
+  const int64_t total = 2 * a.g.Nh * a.g.d;
+  hipLaunchKernelGGL(bond_mean_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st,
+                     total, a.n == 1 ? 1 : 0, acc, (double)samples, out);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void fill_zero_kernel(uint32_t* __restrict__ p, const int64_t nwords) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < nwords) p[i] = 0u;
+}
+
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st) {
+  const int64_t nwords = (int64_t)(bytes / 4);
+  if (nwords == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, st,
+                     (uint32_t*)p, nwords);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Validation: count out-of-range spins / couplings.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void validate_kernel(const Geom g, const int n, const int J_kind,
+                                                       const void* __restrict__ spins,
+                                                       const void* __restrict__ J,
+                                                       uint32_t* __restrict__ count) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t Nfull = 2 * g.Nh;
+  if (i >= Nfull) return;
+  uint32_t bad = 0;
+  if (n == 1) {
+    const int8_t v = ((const int8_t*)spins)[i];
+    bad += (v != 1 && v != -1);
+  } else {
+    const float* s = (const float*)spins;
+    float q = 0.0f;
+    bool fin = true;
+    for (int k = 0; k < n; ++k) {
+      const float v = s[k * Nfull + i];
+      fin = fin && isfinite(v);
+      q += v * v;
+    }
+    bad += (!fin || fabsf(sqrtf(q) - 1.0f) >= 1e-4f);
+  }
+  for (int mu = 0; mu < g.d; ++mu) {
+    if (J_kind == 1) {
+      const int8_t v = ((const int8_t*)J)[mu * Nfull + i];
+      bad += (v != 1 && v != -1);
+    } else if (J_kind == 2) {
+      bad += !isfinite(((const float*)J)[mu * Nfull + i]);
+    }
+  }
+  if (bad) atomicAdd(count, bad);
+}
+
+hipError_t launch_validate(const MeasureLaunch& a, const void* spins, uint32_t* dev_count,
+                           hipStream_t st) {
+  const dim3 grid((unsigned)((2 * a.g.Nh + 255) / 256));
+  hipLaunchKernelGGL(validate_kernel, grid, dim3(256), 0, st, a.g, a.n, a.J_kind, spins, a.J,
+                     dev_count);
+  return hipGetLastError();
+}
+
+}  // namespace smc

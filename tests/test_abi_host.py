@@ -1,0 +1,112 @@
+"""Host-side checks of the C-ABI library (no GPU compute): it loads, exports
+every function include/smc.h declares, sizes buffers and rejects invalid
+parameters before touching any device."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def smc_host():
+    import paper_1107_5463_amd as smc
+    if not os.path.exists(smc.lib_path()):
+        from paper_1107_5463_amd import build
+        build.build()
+    try:
+        smc.load_library()
+    except OSError as e:  # pragma: no cover - HIP runtime missing on this host
+        pytest.skip(f"cannot load libsmc.so: {e}")
+    return smc
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "smc.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(smc_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_exports(smc_host):
+    assert declared_functions() == sorted(smc_host.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(smc_host):
+    out = subprocess.run(["nm", "-D", "--defined-only", smc_host.lib_path()], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (smc_\w+)", out))
+    missing = set(declared_functions()) - exported
+    assert not missing, missing
+    lib = smc_host.load_library()
+    for f in declared_functions():
+        assert hasattr(lib, f)
+
+
+def test_library_does_not_link_the_oracle(smc_host):
+    out = subprocess.run(["nm", "-D", smc_host.lib_path()], capture_output=True, text=True).stdout
+    assert "oracle_" not in out
+    ldd = subprocess.run(["ldd", smc_host.lib_path()], capture_output=True, text=True).stdout
+    assert "liboracle" not in ldd
+
+
+def test_buffer_sizes(smc_host):
+    lib = smc_host.load_library()
+    p = smc_host.make_params(2, 1, 16384, 1)
+    assert lib.smc_spin_bytes(C.byref(p)) == 16384 ** 2
+    assert lib.smc_coupling_bytes(C.byref(p)) == 0
+    assert lib.smc_bond_bytes(C.byref(p)) == 2 * 16384 ** 2 * 8
+    assert lib.smc_workspace_bytes(C.byref(p)) > 0
+    q = smc_host.make_params(3, 3, 256, 1, J_kind=smc_host.J_FP32)
+    assert lib.smc_spin_bytes(C.byref(q)) == 3 * 4 * 256 ** 3
+    assert lib.smc_coupling_bytes(C.byref(q)) == 3 * 4 * 256 ** 3
+    q2 = smc_host.make_params(2, 1, 64, 1, J_kind=smc_host.J_PM)
+    assert lib.smc_coupling_bytes(C.byref(q2)) == 2 * 64 * 64
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(d=4), b"d must be"),
+    (dict(n=4), b"n must be"),
+    (dict(L=31), b"L must be even"),
+    (dict(L=2), b"L must be even"),
+    (dict(L=65536, d=3), b"too large"),
+    (dict(J_kind=7), b"J_kind"),
+    (dict(n=2, delta=0.0), b"delta"),
+    (dict(n=3, delta=4.0), b"cap"),
+    (dict(J0=float("inf")), b"J0"),
+    (dict(renorm_every=-1), b"renorm"),
+])
+def test_invalid_params_rejected(smc_host, kw, msg):
+    lib = smc_host.load_library()
+    args = dict(d=2, n=1, L=32)
+    args.update({k: v for k, v in kw.items() if k in ("d", "n", "L")})
+    p = smc_host.make_params(args["d"], args["n"], args["L"], 1,
+                             **{k: v for k, v in kw.items() if k not in ("d", "n", "L")})
+    assert lib.smc_workspace_bytes(C.byref(p)) == 0
+    h = C.c_void_p()
+    rc = lib.smc_init_lattice(C.byref(h), C.byref(p), None, None, None, 0, None)
+    assert rc == smc_host.SMC_EINVAL
+    assert msg in lib.smc_last_error()
+    assert not h.value
+
+
+def test_null_handle_calls_fail_cleanly(smc_host):
+    lib = smc_host.load_library()
+    assert lib.smc_sweep(None, 0.4, 1) == smc_host.SMC_EINVAL
+    assert lib.smc_half_sweep(None, 0.4, 0) == smc_host.SMC_EINVAL
+    assert lib.smc_destroy(None) == smc_host.SMC_OK
+    assert b"handle" in lib.smc_last_error() or lib.smc_last_error() == b""
+    assert lib.smc_version().startswith(b"libsmc")
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    import importlib
+
+    import paper_1107_5463_amd as smc
+    monkeypatch.setattr(smc, "_LIB", None)
+    monkeypatch.setattr(smc, "_LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        smc.load_library()
+    importlib.reload(smc)

@@ -1,0 +1,178 @@
+"""GPU parity tests for XY / Heisenberg spins (FP32 on the GPU, FP64 oracle).
+
+Protocol: start both sides from the same FP32 state (the oracle's, rounded to
+FP32), run one half-sweep, and require
+  * the same accept / reject decision at every site whose margin
+    |u - exp(-beta dE)| (oracle, FP64) is at least 1e-6;
+  * spin components within 1e-5 of the oracle's at every site that both
+    updated;
+sites inside the 1e-6 band are counted and reported, not failed.  Longer
+runs diverge chaotically, so they are compared statistically (4 sigma).
+"""
+import numpy as np
+import pytest
+
+import inputs
+import layout
+
+import oracle.exact as ex
+
+pytestmark = pytest.mark.gpu
+
+BAND = 1e-6
+TOL = 1e-5
+
+
+def nat(lat):
+    return layout.to_natural(lat.spins.cpu().numpy().astype(np.float64), lat.d, lat.L)
+
+
+def upload(smc_gpu, ref, **kw):
+    import torch
+    d, L, n = ref.d, ref.L, ref.n
+    Jt = None if ref.J is None else torch.from_numpy(layout.to_split(ref.J, d, L))
+    sp = torch.from_numpy(layout.to_split(ref.s.astype(np.float32), d, L))
+    return smc_gpu.Lattice(d, n, L, seed=int(ref.p.seed), J_kind=int(ref.p.J_kind), J0=ref.p.J0,
+                           J_sigma=ref.p.J_sigma, delta=ref.p.delta, replica=int(ref.p.replica),
+                           renorm_every=int(ref.p.renorm_every), spins=sp, J=Jt, **kw)
+
+
+@pytest.mark.parametrize("d,n,L", [(2, 2, 64), (3, 3, 16), (2, 3, 32), (3, 2, 8)])
+def test_init_parity(smc_gpu, oracle_mod, d, n, L):
+    lat = smc_gpu.Lattice(d, n, L, seed=55, delta=1.0)
+    ref = oracle_mod.OracleLattice(d, n, L, 55, delta=1.0)
+    g = nat(lat).astype(np.float32)
+    o = ref.s.astype(np.float32)
+    ulps = np.abs(g.view(np.int32).astype(np.int64) - o.view(np.int32).astype(np.int64))
+    assert ulps.max() <= 1
+    lat.validate()
+
+
+CASES = [  # d, n, L, beta, delta, J_kind, fast
+    (2, 2, 64, 1.12, 1.0, 0, False),
+    (3, 3, 16, 0.693, 1.0, 0, False),
+    (2, 3, 32, 0.8, 0.7, 0, False),
+    (3, 2, 8, 0.5, 2.0, 1, False),
+    (2, 2, 32, 1.0, 1.5, 2, False),
+    (3, 3, 8, 0.7, 1.2, 2, False),
+    (2, 2, 64, 1.12, 1.0, 0, True),
+    (3, 3, 16, 0.693, 1.0, 0, True),
+]
+
+
+@pytest.mark.parametrize("d,n,L,beta,delta,kind,fast", CASES)
+def test_half_sweep_protocol(smc_gpu, oracle_mod, d, n, L, beta, delta, kind, fast):
+    import torch
+    print(f"half-sweep protocol d={d} n={n} L={L} kind={kind} fast={fast}", flush=True)
+    band = 1e-5 if fast else BAND
+    tol = 1e-4 if fast else TOL
+    ref = oracle_mod.OracleLattice(d, n, L, 19, delta=delta, J_kind=kind, J_sigma=0.2,
+                                   renorm_every=0)
+    lat = upload(smc_gpu, ref, fast_math=fast)
+    near = 0
+    for t in range(4):
+        for c in (0, 1):
+            ref.s = ref.s.astype(np.float32).astype(np.float64)
+            s0 = ref.s.copy()
+            lat.spins.copy_(torch.from_numpy(layout.to_split(s0.astype(np.float32), d, L)))
+            lat.t = t
+            lat.half_sweep(beta, c)
+            _, margin = ref.half_sweep(beta, c, t, want_margin=True)
+            g = nat(lat)
+            moved_g = np.any(g != s0, axis=0)
+            moved_o = np.any(ref.s != s0, axis=0)
+            clear = ~(np.abs(margin) < band)  # NaN margin (dE <= 0) counts as clear
+            assert np.array_equal(moved_g[clear], moved_o[clear]), (t, c)
+            both = moved_g & moved_o
+            assert np.abs(g[:, both] - ref.s[:, both]).max(initial=0.0) <= tol
+            near += int(np.sum(np.abs(margin) < band))
+    print(f"near-threshold sites (|u-p| < {band}): {near} of {8 * L ** d // 2}")
+
+
+@pytest.mark.parametrize("n,d,beta,delta,single", [
+    (2, 2, 0.3, 1.0, ex.xy_single_spin_mean),
+    (3, 3, 0.2, 1.5, ex.heisenberg_single_spin_mean),
+    (3, 2, 0.25, 1.0, ex.heisenberg_single_spin_mean),
+])
+def test_single_spin_in_frozen_field(smc_gpu, n, d, beta, delta, single):
+    import torch
+    L = 64 if d == 2 else 16
+    lat = smc_gpu.Lattice(d, n, L, seed=8, init="cold", delta=delta, renorm_every=0)
+    steps = 3000
+    acc = torch.zeros(L ** d // 2, dtype=torch.float64, device=lat.device)
+    for t in range(200 + steps):
+        lat.t = t
+        lat.half_sweep(beta, 0)
+        if t >= 200:
+            acc += lat.spins[0, 0].double()
+    per_site = (acc / steps).cpu().numpy()
+    m, se = per_site.mean(), per_site.std(ddof=1) / np.sqrt(len(per_site))
+    want = single(beta * 2 * d)
+    assert abs(m - want) < 4 * se, (m, want, se)
+
+
+def test_ising_single_spin_in_frozen_field(smc_gpu):
+    import torch
+    lat = smc_gpu.Lattice(2, 1, 64, seed=8, init="cold")
+    beta, steps = 0.1, 3000
+    acc = torch.zeros(64 * 64 // 2, dtype=torch.float64, device=lat.device)
+    for t in range(steps):
+        lat.t = t
+        lat.half_sweep(beta, 0)
+        acc += lat.spins[0].double()
+    per_site = (acc / steps).cpu().numpy()
+    m, se = per_site.mean(), per_site.std(ddof=1) / np.sqrt(len(per_site))
+    assert abs(m - np.tanh(4 * beta)) < 4 * se
+
+
+def test_renormalisation(smc_gpu):
+    lat = smc_gpu.Lattice(2, 3, 32, seed=4, delta=1.0, renorm_every=5)
+    lat.spins.mul_(1.001)
+    lat.sweep(0.7, 5)
+    norms = lat.spins.double().pow(2).sum(0).sqrt().cpu().numpy()
+    assert np.abs(norms - 1).max() < 1e-6
+    lat.validate()
+
+
+@pytest.mark.parametrize("d,n,L,kind", [(2, 2, 32, 0), (3, 3, 8, 1), (2, 3, 16, 2)])
+def test_measure_and_bonds_match_oracle(smc_gpu, oracle_mod, d, n, L, kind):
+    s = inputs.random_unit_vectors(n, L ** d, seed=L + n)
+    ref = oracle_mod.OracleLattice(d, n, L, 3, J_kind=kind, J_sigma=0.3, spins=s, delta=1.0)
+    lat = upload(smc_gpu, ref)
+    o, r = lat.measure(), ref.measure()
+    assert abs(o.E - r.E) <= 1e-12 * max(1.0, abs(r.E)) * L ** d
+    assert np.allclose(o.M[:n], r.M[:n], rtol=0, atol=1e-9 * L ** d)
+    lat.bond_reset()
+    lat.bond_accumulate()
+    acc = np.zeros((d, L ** d))
+    ref.bond_accumulate(acc)
+    got = layout.to_natural(lat.bond_accumulator().cpu().numpy(), d, L)
+    assert np.abs(got - acc).max() <= 1e-12
+
+
+def _binned(x, nbins=40):
+    x = np.asarray(x)
+    m = len(x) // nbins
+    b = x[: m * nbins].reshape(nbins, m).mean(axis=1)
+    return b.mean(), b.std(ddof=1) / np.sqrt(nbins)
+
+
+@pytest.mark.parametrize("d,n,L,beta,delta", [(2, 2, 16, 1.12, 1.0), (3, 3, 8, 0.693, 1.0)])
+def test_long_run_statistics_match_oracle(smc_gpu, oracle_mod, d, n, L, beta, delta):
+    import torch
+    sweeps = 8000
+    lat = smc_gpu.Lattice(d, n, L, seed=61, delta=delta)
+    lat.sweep(beta, 500)
+    slots = torch.zeros((sweeps, 8), dtype=torch.int64, device=lat.device)
+    for k in range(sweeps):
+        lat.sweep(beta, 1)
+        lat.measure_async(slots[k])
+    g = smc_gpu.Lattice.decode_obs(slots)
+    ref = oracle_mod.OracleLattice(d, n, L, 62, delta=delta)
+    ref.sweep(beta, 500)
+    r, _ = ref.sweep(beta, sweeps, 1)
+    N = L ** d
+    for key in ("E", "absM"):
+        mg, sg = _binned([getattr(o, key) / N for o in g])
+        mo, so = _binned([getattr(o, key) / N for o in r])
+        assert abs(mg - mo) < 4 * np.hypot(sg, so), (key, mg, mo, sg, so)
