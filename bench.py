@@ -37,7 +37,10 @@ def parse():
     ap.add_argument("--d", type=int, default=2)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--beta", type=float, default=BETA)
-    ap.add_argument("--cpu-sweeps", type=int, default=2, help="oracle sweeps for the CPU baseline (0 = skip)")
+    ap.add_argument("--schedule", choices=["fused", "two-pass"], default="fused",
+                    help="fused: one kernel per sweep with ping-pong buffers (2 B/attempt); "
+                         "two-pass: one in-place kernel per colour (3 B/attempt)")
+    ap.add_argument("--cpu-sweeps", type=int, default=12, help="oracle sweeps for the CPU baseline (0 = skip)")
     return ap.parse_args()
 
 
@@ -55,14 +58,14 @@ def main():
     smc.load_library()
     d, L = args.d, args.L
     N = L ** d
-    lat = smc.Lattice(d, 1, L, seed=args.seed)
+    fused = args.schedule == "fused"
+    lat = smc.Lattice(d, 1, L, seed=args.seed, fused=fused)
     st = lat.stream
     K, W, S = args.steps, args.warmup, args.sweeps_per_step
     ring = torch.zeros((max(K, 1), 8), dtype=torch.int64, device=lat.device)
 
     for _ in range(W):
-        lat.sweep(args.beta, S)
-        lat.measure_async(ring[0])
+        lat.sweep_measure(args.beta, S, ring[0])
     torch.cuda.synchronize()
 
     ev_start = torch.cuda.Event(enable_timing=True)
@@ -74,9 +77,8 @@ def main():
     ev_start.record(st)
     for k in range(K):
         ev_a[k].record(st)
-        lat.sweep(args.beta, S)
+        lat.sweep_measure(args.beta, S, ring[k])
         ev_b[k].record(st)
-        lat.measure_async(ring[k])
     ev_end.record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -85,9 +87,17 @@ def main():
     sweeps = K * S
     attempts = N * sweeps
     value = attempts / (total_ms * 1e6)
-    launches = 2 * sweeps
+    kname, band_rows = lat.kernel()
+    if kname == "ising_fused":
+        # each launch is one sweep: both colours read and written once
+        launches, bytes_per_launch = sweeps, 2.0 * N
+        schedule = "fused one-pass, ping-pong buffers"
+    else:
+        # each launch is one colour: own colour read + written, other colour read
+        launches, bytes_per_launch = 2 * sweeps, 1.5 * N
+        schedule = "two-pass colour-split, in place"
+    # step time includes the measurement finish kernel: a conservative kernel average
     kernel_ms = sweep_ms / launches
-    bytes_per_launch = 1.5 * N  # own colour read + written (N/2 each), other colour read (N/2)
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
     obs = smc.Lattice.decode_obs(ring[K - 1:K])[0] if K else None
 
@@ -108,8 +118,9 @@ def main():
             "workload": f"{d}D Ising L={L} (N={N}), J=1, beta={args.beta}, hot start seed {args.seed}, "
                         f"{sweeps} checkerboard sweeps, E/M every {S} sweeps",
             "d": d, "L": L, "sweeps": sweeps, "measure_every": S,
-            "schedule": "two-pass colour-split, in place",
-            "kernel": "ising_chunk_kernel",
+            "schedule": schedule,
+            "kernel": kname,
+            "rows_per_band": band_rows,
         },
         "roofline": {
             "bound": "hbm",

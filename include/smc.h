@@ -61,7 +61,9 @@ enum smc_init_kind { SMC_INIT_HOT = 0, SMC_INIT_COLD = 1, SMC_INIT_KEEP = 2 };
 
 enum smc_flags {
   SMC_FLAG_FAST_MATH = 1,        /* hardware transcendentals for continuous spins */
-  SMC_FLAG_SCHEDULE_FUSED = 2,   /* Ising: one kernel per sweep with ping-pong buffers */
+  SMC_FLAG_SCHEDULE_FUSED = 2,   /* 2D Ising, uniform J, L % 2048 == 0: one kernel per sweep,
+                                    ping-ponging through the workspace (bit-identical
+                                    results; other shapes keep the two-pass schedule) */
   SMC_FLAG_GENERIC_KERNEL = 4,   /* force the one-site-per-thread kernels (testing) */
   SMC_FLAG_COUPLINGS_KEEP = 8    /* do not generate J at init; use the caller's values */
 };
@@ -126,6 +128,15 @@ int smc_set_stream(smc_lattice* h, void* stream);
  */
 int smc_sweep(smc_lattice* h, double beta, int64_t n_sweeps);
 
+/*
+ * smc_sweep followed by the observables of the final state, written as an
+ * smc_obs to device memory dev_obs (8-byte aligned), without synchronising.
+ * The reduction is fused into the last sweep's kernel where the kernel
+ * supports it (no extra pass over the lattice); otherwise a separate
+ * measurement runs.  n_sweeps = 0 measures the current state.
+ */
+int smc_sweep_measure(smc_lattice* h, double beta, int64_t n_sweeps, void* dev_obs);
+
 /* One colour only, with counter t (t is not advanced).  Test hook used by the
  * single-spin and half-sweep parity protocols.  Asynchronous. */
 int smc_half_sweep(smc_lattice* h, double beta, int colour);
@@ -164,6 +175,11 @@ int smc_validate(smc_lattice* h);
 int smc_get_sweep_index(const smc_lattice* h, uint64_t* t);
 int smc_set_sweep_index(smc_lattice* h, uint64_t t);
 int smc_set_samples(smc_lattice* h, int64_t samples);
+
+/* Name of the kernel the handle's sweeps launch ("ising_fused",
+ * "ising_stream", "ising_chunk", "ising_site", "xy_site", "heisenberg_site")
+ * and, for the banded Ising kernels, the rows each lane walks (0 otherwise). */
+const char* smc_kernel_name(const smc_lattice* h, uint32_t* rows_per_band);
 
 /* Free the handle (never the caller's buffers). */
 int smc_destroy(smc_lattice* h);

@@ -35,10 +35,11 @@ SMC_OK, SMC_EINVAL, SMC_ERANGE, SMC_EDEVICE, SMC_ESTATE = 0, -1, -2, -3, -4
 
 # every symbol declared in include/smc.h
 EXPORTS = ["smc_spin_bytes", "smc_coupling_bytes", "smc_workspace_bytes", "smc_bond_bytes",
-           "smc_init_lattice", "smc_set_stream", "smc_sweep", "smc_half_sweep", "smc_measure",
+           "smc_init_lattice", "smc_set_stream", "smc_sweep", "smc_sweep_measure", "smc_half_sweep",
+           "smc_measure",
            "smc_measure_async", "smc_bond_correlations", "smc_get_samples", "smc_set_samples",
            "smc_renormalize", "smc_validate", "smc_get_sweep_index", "smc_set_sweep_index",
-           "smc_destroy", "smc_last_error", "smc_version"]
+           "smc_kernel_name", "smc_destroy", "smc_last_error", "smc_version"]
 
 
 class SmcError(RuntimeError):
@@ -93,6 +94,7 @@ def load_library():
     lib.smc_init_lattice.argtypes = [C.POINTER(vp), P, vp, vp, vp, sz, vp]
     lib.smc_set_stream.argtypes = [vp, vp]
     lib.smc_sweep.argtypes = [vp, C.c_double, C.c_int64]
+    lib.smc_sweep_measure.argtypes = [vp, C.c_double, C.c_int64, vp]
     lib.smc_half_sweep.argtypes = [vp, C.c_double, C.c_int]
     lib.smc_measure.argtypes = [vp, C.POINTER(_ObsC)]
     lib.smc_measure_async.argtypes = [vp, vp]
@@ -103,12 +105,14 @@ def load_library():
     lib.smc_validate.argtypes = [vp]
     lib.smc_get_sweep_index.argtypes = [vp, C.POINTER(C.c_uint64)]
     lib.smc_set_sweep_index.argtypes = [vp, C.c_uint64]
+    lib.smc_kernel_name.argtypes = [vp, C.POINTER(C.c_uint32)]
+    lib.smc_kernel_name.restype = C.c_char_p
     lib.smc_destroy.argtypes = [vp]
     lib.smc_last_error.restype = C.c_char_p
     lib.smc_version.restype = C.c_char_p
     for f in EXPORTS:
         if f not in ("smc_spin_bytes", "smc_coupling_bytes", "smc_workspace_bytes", "smc_bond_bytes",
-                     "smc_last_error", "smc_version"):
+                     "smc_last_error", "smc_version", "smc_kernel_name"):
             getattr(lib, f).restype = C.c_int
     _LIB = lib
     return lib
@@ -217,12 +221,25 @@ class Lattice:
     def t(self, value: int):
         _check(self._lib().smc_set_sweep_index(self._h, int(value)))
 
+    def kernel(self):
+        """(name, rows_per_band) of the half-sweep kernel this lattice launches."""
+        rows = C.c_uint32()
+        name = self._lib().smc_kernel_name(self._h, C.byref(rows)).decode()
+        return name, int(rows.value)
+
     def set_stream(self, stream):
         self.stream = stream
         _check(self._lib().smc_set_stream(self._h, C.c_void_p(stream.cuda_stream)))
 
     def sweep(self, beta: float, n_sweeps: int = 1):
         _check(self._lib().smc_sweep(self._h, float(beta), int(n_sweeps)))
+
+    def sweep_measure(self, beta: float, n_sweeps: int, dev_slot):
+        """n_sweeps sweeps, then the observables of the final state written to
+        dev_slot (device tensor of >= 64 bytes) without synchronising."""
+        assert dev_slot.is_cuda and dev_slot.numel() * dev_slot.element_size() >= 64
+        _check(self._lib().smc_sweep_measure(self._h, float(beta), int(n_sweeps),
+                                             C.c_void_p(dev_slot.data_ptr())))
 
     def half_sweep(self, beta: float, colour: int):
         _check(self._lib().smc_half_sweep(self._h, float(beta), int(colour)))

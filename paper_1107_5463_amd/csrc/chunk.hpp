@@ -48,10 +48,206 @@ __device__ __forceinline__ Chunk shift_prev(const Chunk& c, uint32_t edge) {
   return o;
 }
 
+// Blocks are dealt to the 8 XCDs round-robin (block b runs on XCD b % 8).
+// Renumber them so that each XCD receives a contiguous range of logical
+// blocks, i.e. neighbouring rows of the lattice share one L2.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t nb) {
+  const uint32_t q = nb >> 3, rem = nb & 7u, x = b & 7u, k = b >> 3;
+  return x * q + (x < rem ? x : rem) + k;
+}
+
 constexpr uint32_t kBit1 = 0x02020202u;  // bit 1 of a +-1 byte: set for -1
 constexpr uint32_t kHigh = 0x80808080u;
 constexpr uint32_t kOnes = 0x01010101u;
 
+
+__device__ __forceinline__ uint32_t pick4(const Rand4& r, uint32_t i) {
+  const uint32_t a = (i & 1) ? r.w[1] : r.w[0];
+  const uint32_t b = (i & 1) ? r.w[3] : r.w[2];
+  return (i & 2) ? b : a;
+}
+
+__device__ __forceinline__ uint32_t table_byte(uint32_t lo, uint32_t hi, uint32_t k) {
+  return ((k < 4 ? lo : hi) >> (8 * (k & 3))) & 0xFFu;
+}
+
+__device__ __forceinline__ uint32_t frac_of(const IsingTable& tab, uint32_t k) {
+  uint32_t v = tab.frac[0];
+  v = k == 1 ? tab.frac[1] : v;
+  v = k == 2 ? tab.frac[2] : v;
+  v = k == 3 ? tab.frac[3] : v;
+  v = k == 4 ? tab.frac[4] : v;
+  v = k == 5 ? tab.frac[5] : v;
+  v = k == 6 ? tab.frac[6] : v;
+  return v;
+}
+
+// Per-byte decision for 4 sites: k = unsatisfied-bond counts (bytes), P = 4
+// prefix bytes.  Returns the spin word after the accepted flips, and the tie
+// mask candidates (bit 7 of bytes that may need the refinement draw).
+__device__ __forceinline__ uint32_t decide4(const IsingTable& tab, uint32_t own, uint32_t k,
+                                            uint32_t P, uint32_t& tie) {
+  const uint32_t Th = __builtin_amdgcn_perm(tab.th_hi, tab.th_lo, k);
+  const uint32_t Al = __builtin_amdgcn_perm(tab.al_hi, tab.al_lo, k);
+  // bit 7 of each byte: P >= Th (unsigned bytes)
+  const uint32_t dlow = (P | kHigh) - (Th & ~kHigh);
+  const uint32_t x = P ^ Th;
+  const uint32_t ge = (x & P) | (~x & dlow);
+  const uint32_t acc = (~ge | Al) & kHigh;
+  // candidate exact ties P == Th on classes that are not always accepted
+  const uint32_t zz = x | Al;
+  tie = (zz - kOnes) & ~zz & kHigh;
+  return own ^ ((acc - (acc >> 7)) << 1);  // 0xFE flips +1 <-> -1
+}
+
+// Exact per-byte tie mask: bit 7 of each byte where P == Th and the class is
+// not always accepted (no carries cross bytes).
+__device__ __forceinline__ uint32_t tie_bytes(const IsingTable& tab, uint32_t k, uint32_t P) {
+  const uint32_t Th = __builtin_amdgcn_perm(tab.th_hi, tab.th_lo, k);
+  const uint32_t Al = __builtin_amdgcn_perm(tab.al_hi, tab.al_lo, k);
+  const uint32_t z = (P ^ Th) | Al;
+  const uint32_t nz = (((z & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | z) & kHigh;
+  return ~nz & kHigh;
+}
+
+// 16-bit mask (bit 4w+b) of sites whose prefix byte ties its threshold byte.
+__device__ __forceinline__ uint32_t tie_mask16(const IsingTable& tab, const uint32_t kk[4],
+                                               const Rand4& rp) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const uint32_t t7 = tie_bytes(tab, kk[w], rp.w[w]);
+    const uint32_t nib = ((t7 >> 7) | (t7 >> 14) | (t7 >> 21) | (t7 >> 28)) & 0xFu;
+    m |= nib << (4 * w);
+  }
+  return m;
+}
+
+// Resolve the rare ties with each site's 24-bit refinement draw.
+__device__ __forceinline__ void resolve_ties(const IsingTable& tab, const RngKey& key, uint32_t t,
+                                             uint32_t c, uint32_t jbase, const uint32_t kk[4],
+                                             uint32_t mask, uint32_t nw[4]) {
+  while (mask) {
+    const uint32_t idx = __builtin_ctz(mask);
+    mask &= mask - 1;
+    const uint32_t w = idx >> 2, b = idx & 3u;
+    const uint32_t kw = w == 0 ? kk[0] : (w == 1 ? kk[1] : (w == 2 ? kk[2] : kk[3]));
+    const uint32_t k = (kw >> (8 * b)) & 0xFFu;
+    const Rand4 rr = philox(jbase + idx, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
+    if ((rr.w[0] & 0xFFFFFFu) < frac_of(tab, k)) {
+      const uint32_t f = 0xFEu << (8 * b);
+      nw[0] ^= w == 0 ? f : 0u;
+      nw[1] ^= w == 1 ? f : 0u;
+      nw[2] ^= w == 2 ? f : 0u;
+      nw[3] ^= w == 3 ? f : 0u;
+    }
+  }
+}
+
+// Per-byte decision for 4 sites testing the threshold byte only (classes that
+// always accept carry threshold byte 0xFF and refinement fraction 2^24).
+// Returns the spin word after the flips decided by the prefix bytes; tie7
+// flags (bit 7) the bytes where the prefix may equal the threshold byte: every
+// exact tie, plus occasional false alarms directly above one, which the slow
+// path re-checks.
+__device__ __forceinline__ uint32_t decide4_fast(uint32_t th_lo, uint32_t th_hi, uint32_t own,
+                                                 uint32_t k, uint32_t P, uint32_t& tie7) {
+  const uint32_t Th = __builtin_amdgcn_perm(th_hi, th_lo, k);
+  const uint32_t x = P ^ Th;
+  const uint32_t dlow = (P | kHigh) - (Th & ~kHigh);
+  const uint32_t ge = (x & P) | (~x & dlow);  // bit 7 of each byte: P >= Th
+  // 0xFF in every byte whose bit 7 of ge is set (sign-replicating selectors)
+  const uint32_t rej = __builtin_amdgcn_perm(ge, ge << 8, 0x0B090A08u);
+  tie7 = (x - kOnes) & ~x & kHigh;
+  return own ^ (~rej & 0xFEFEFEFEu);
+}
+
+// Deferred tie resolutions of one lane (at most 4 held; more are resolved on
+// the spot by the caller).
+struct PendingTies {
+  uint32_t j[4];
+  uint32_t k;  // nibble p = class of entry p
+  uint32_t n;
+};
+
+// Unsatisfied-bond counts of a chunk of 2D sites from its four neighbour
+// chunks (x+1 / x-1 as centre and shifted chunk, y-1, y+1): byte b of kk[w].
+__device__ __forceinline__ void counts2d(const Chunk& o, const Chunk& ctr, const Chunk& sh,
+                                         const Chunk& up, const Chunk& dn, uint32_t kk[4]) {
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const uint32_t ow = o.w[w];
+    const uint32_t k2 = ((ow ^ ctr.w[w]) & kBit1) + ((ow ^ sh.w[w]) & kBit1) +
+                        ((ow ^ up.w[w]) & kBit1) + ((ow ^ dn.w[w]) & kBit1);
+    kk[w] = k2 >> 1;
+  }
+}
+
+// Exact 16-bit mask (bit 4w+b) of sites whose prefix byte equals the threshold
+// byte of their class.
+__device__ __forceinline__ uint32_t exact_ties16(uint32_t th_lo, uint32_t th_hi,
+                                                 const uint32_t kk[4], const Rand4& rp) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const uint32_t z7 = rp.w[w] ^ __builtin_amdgcn_perm(th_hi, th_lo, kk[w]);
+    const uint32_t t7 = ~((((z7 & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | z7)) & kHigh;
+    m |= (((t7 >> 7) | (t7 >> 14) | (t7 >> 21) | (t7 >> 28)) & 0xFu) << (4 * w);
+  }
+  return m;
+}
+
+// Metropolis update of one chunk given its unsatisfied-bond counts: one
+// Philox block for the 16 prefix bytes; the refinement draw only for the rare
+// exact ties, resolved on the spot.
+__device__ __forceinline__ Chunk update_chunk(const IsingTable& tab, const RngKey& key, uint32_t t,
+                                              uint32_t c, uint32_t jbase, const Chunk& o,
+                                              const uint32_t kk[4]) {
+  const Rand4 rp = philox(jbase >> 4, t, key.replica, tag(c, kIsingPrefix), key.k0, key.k1);
+  uint32_t nw[4], anytie = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    uint32_t t7;
+    nw[w] = decide4_fast(tab.th_lo, tab.th_hi, o.w[w], kk[w], rp.w[w], t7);
+    anytie |= t7;
+  }
+  if (anytie) {
+    uint32_t m = exact_ties16(tab.th_lo, tab.th_hi, kk, rp);
+    while (m) {
+      const uint32_t idx = __builtin_ctz(m);
+      m &= m - 1;
+      const uint32_t w = idx >> 2, b = idx & 3u;
+      const uint32_t kw = w == 0 ? kk[0] : (w == 1 ? kk[1] : (w == 2 ? kk[2] : kk[3]));
+      const Rand4 rr = philox(jbase + idx, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
+      if ((rr.w[0] & 0xFFFFFFu) < frac_of(tab, (kw >> (8 * b)) & 0xFu)) {
+        const uint32_t f = 0xFEu << (8 * b);
+        nw[0] ^= w == 0 ? f : 0u;
+        nw[1] ^= w == 1 ? f : 0u;
+        nw[2] ^= w == 2 ? f : 0u;
+        nw[3] ^= w == 3 ? f : 0u;
+      }
+    }
+  }
+  Chunk n;
+  n.w[0] = nw[0]; n.w[1] = nw[1]; n.w[2] = nw[2]; n.w[3] = nw[3];
+  return n;
+}
+
+// Sum of the +-1 spins of a chunk.
+__device__ __forceinline__ int32_t chunk_spin_sum(const Chunk& o) {
+  uint32_t down2 = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) down2 = __builtin_amdgcn_sad_u8(o.w[w] & kBit1, 0u, down2);
+  return 16 - (int32_t)down2;  // down2 counts 2 per -1 spin
+}
+
+// Sum of the per-site unsatisfied-bond counts of a chunk.
+__device__ __forceinline__ int32_t chunk_count_sum(const uint32_t kk[4]) {
+  uint32_t s = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) s = __builtin_amdgcn_sad_u8(kk[w], 0u, s);
+  return (int32_t)s;
+}
 
 // Unsatisfied-bond counts of the 16 sites of chunk gid of colour c: byte b of
 // kk[w] = number of bonds of site 4w+b with J_b s_i s_b < 0.  Also returns the

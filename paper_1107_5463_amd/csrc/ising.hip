@@ -20,6 +20,7 @@
 //    bytes come from a v_perm byte lookup; one Philox block supplies the 16
 //    prefix bytes.
 #include "chunk.hpp"
+#include "reduce.hpp"
 
 namespace smc {
 
@@ -32,27 +33,6 @@ FastDiv make_fastdiv(uint32_t d) {
   f.m = (uint32_t)(num / d + 1);
   f.s = l - 1;
   return f;
-}
-
-__device__ __forceinline__ uint32_t pick4(const Rand4& r, uint32_t i) {
-  const uint32_t a = (i & 1) ? r.w[1] : r.w[0];
-  const uint32_t b = (i & 1) ? r.w[3] : r.w[2];
-  return (i & 2) ? b : a;
-}
-
-__device__ __forceinline__ uint32_t table_byte(uint32_t lo, uint32_t hi, uint32_t k) {
-  return ((k < 4 ? lo : hi) >> (8 * (k & 3))) & 0xFFu;
-}
-
-__device__ __forceinline__ uint32_t frac_of(const IsingTable& tab, uint32_t k) {
-  uint32_t v = tab.frac[0];
-  v = k == 1 ? tab.frac[1] : v;
-  v = k == 2 ? tab.frac[2] : v;
-  v = k == 3 ? tab.frac[3] : v;
-  v = k == 4 ? tab.frac[4] : v;
-  v = k == 5 ? tab.frac[5] : v;
-  v = k == 6 ? tab.frac[6] : v;
-  return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -129,24 +109,6 @@ __global__ __launch_bounds__(256) void ising_site_kernel(const Geom g, const Rng
 // ---------------------------------------------------------------------------
 // 16 sites per lane.
 // ---------------------------------------------------------------------------
-// Per-byte decision for 4 sites: k = unsatisfied-bond counts (bytes), P = 4
-// prefix bytes.  Returns the spin word after the accepted flips, and the tie
-// mask candidates (bit 7 of bytes that may need the refinement draw).
-__device__ __forceinline__ uint32_t decide4(const IsingTable& tab, uint32_t own, uint32_t k,
-                                            uint32_t P, uint32_t& tie) {
-  const uint32_t Th = __builtin_amdgcn_perm(tab.th_hi, tab.th_lo, k);
-  const uint32_t Al = __builtin_amdgcn_perm(tab.al_hi, tab.al_lo, k);
-  // bit 7 of each byte: P >= Th (unsigned bytes)
-  const uint32_t dlow = (P | kHigh) - (Th & ~kHigh);
-  const uint32_t x = P ^ Th;
-  const uint32_t ge = (x & P) | (~x & dlow);
-  const uint32_t acc = (~ge | Al) & kHigh;
-  // candidate exact ties P == Th on classes that are not always accepted
-  const uint32_t zz = x | Al;
-  tie = (zz - kOnes) & ~zz & kHigh;
-  return own ^ ((acc - (acc >> 7)) << 1);  // 0xFE flips +1 <-> -1
-}
-
 template <int D, bool PM>
 __global__ __launch_bounds__(256) void ising_chunk_kernel(const Geom g, const RngKey key,
                                                           const IsingTable tab,
@@ -154,7 +116,7 @@ __global__ __launch_bounds__(256) void ising_chunk_kernel(const Geom g, const Rn
                                                           const FastDiv divQ, const FastDiv divL,
                                                           int8_t* __restrict__ s,
                                                           const uint32_t t, const uint32_t c) {
-  const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
+  const uint32_t gid = xcd_remap(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
   if (gid >= (uint32_t)(g.Nh >> 4)) return;
   int64_t base;
   Chunk o, ctr;
@@ -188,6 +150,161 @@ __global__ __launch_bounds__(256) void ising_chunk_kernel(const Geom g, const Rn
     }
   }
   st16(own + base, nw);
+}
+
+
+// ---------------------------------------------------------------------------
+// Streaming half-sweep (uniform couplings, L % 32 == 0).  Lane (band, q) owns
+// chunk column q of plane rows band*H .. band*H + H - 1 (H divides L, so a
+// band stays inside one z-plane) and walks down them, keeping the other
+// colour's rows y-1, y, y+1 of its column in registers: per row it loads one
+// new other-colour chunk, its own chunk (both one row ahead), one edge word,
+// and in 3D the two z-neighbour chunks.  Bands of neighbouring rows fall in
+// the same XCD (xcd_remap), so the band halo rows and the z-neighbour rows
+// are L2 hits.
+// ---------------------------------------------------------------------------
+template <int D, bool MEASURE>
+__global__ __launch_bounds__(256) void ising_stream_kernel(const Geom g, const RngKey key,
+                                                           const IsingTable tab,
+                                                           const FastDiv divQ, const FastDiv divL,
+                                                           const uint32_t H, const uint32_t nbands,
+                                                           int8_t* __restrict__ s,
+                                                           const uint32_t t, const uint32_t c,
+                                                           Partial* __restrict__ parts) {
+  const uint32_t tid = xcd_remap(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
+  const uint32_t band = fdiv(tid, divQ);
+  int64_t Esum = 0, Msum = 0;
+  if (band < nbands) {
+    const uint32_t Q = divQ.d;
+    const uint32_t q = tid - band * Q;
+    const uint32_t L = (uint32_t)g.L;
+    const uint32_t R = (uint32_t)g.R;
+    const uint32_t r0 = band * H;
+    uint32_t z = 0, y0 = r0;
+    if (D == 3) {
+      z = fdiv(r0, divL);
+      y0 = r0 - z * L;
+    }
+    int8_t* own = s + (int64_t)c * g.Nh;
+    const int8_t* oth = s + (int64_t)(1 - c) * g.Nh;
+    const uint32_t col = 16 * q;
+    const uint32_t zrow = L * z;  // row index of (y = 0, z)
+    const uint32_t qn = q + 1 == Q ? 0u : q + 1, qp = q == 0 ? Q - 1 : q - 1;
+    const uint32_t edge_next = 16 * qn, edge_prev = 16 * qp + 12;
+    auto roff = [&](uint32_t y) -> uint32_t { return (zrow + y) * R; };
+    auto wrapy = [&](uint32_t y) -> uint32_t { return y >= L ? y - L : y; };
+    uint32_t zm_row = 0, zp_row = 0;
+    if (D == 3) {
+      zm_row = L * (z == 0 ? L - 1 : z - 1);
+      zp_row = L * (z + 1 == L ? 0 : z + 1);
+    }
+    const uint32_t th_lo = tab.th_lo, th_hi = tab.th_hi;
+    PendingTies pend;
+    pend.k = 0;
+    pend.n = 0;
+    pend.j[0] = pend.j[1] = pend.j[2] = pend.j[3] = 0;
+
+    Chunk up = ld16(oth + roff(y0 == 0 ? L - 1 : y0 - 1) + col);
+    Chunk ct = ld16(oth + roff(y0) + col);
+    Chunk dn = ld16(oth + roff(wrapy(y0 + 1)) + col);
+    Chunk o = ld16(own + roff(y0) + col);
+    for (uint32_t i = 0; i < H; ++i) {
+      const uint32_t y = y0 + i;
+      const uint32_t ro = roff(y);
+      // one row ahead: the other colour's row y + 2 and our own row y + 1
+      const Chunk dn2 = ld16(oth + roff(wrapy(wrapy(y + 1) + 1)) + col);
+      const Chunk o2 = ld16(own + roff(wrapy(y + 1)) + col);
+      const uint32_t p = (c + y + z) & 1u;
+      const uint32_t e = *reinterpret_cast<const uint32_t*>(oth + ro + (p ? edge_next : edge_prev));
+      Chunk fz, bz;
+      if (D == 3) {
+        fz = ld16(oth + (zm_row + y) * R + col);
+        bz = ld16(oth + (zp_row + y) * R + col);
+      }
+      const Chunk sh = p ? shift_next(ct, e) : shift_prev(ct, e);
+      const uint32_t jbase = ro + col;
+      const Rand4 rp = philox(jbase >> 4, t, key.replica, tag(c, kIsingPrefix), key.k0, key.k1);
+      uint32_t kk[4], nw[4], tie[4];
+      uint32_t anytie = 0;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const uint32_t ow = o.w[w];
+        uint32_t k2 = ((ow ^ ct.w[w]) & kBit1) + ((ow ^ sh.w[w]) & kBit1) +
+                      ((ow ^ up.w[w]) & kBit1) + ((ow ^ dn.w[w]) & kBit1);
+        if (D == 3) k2 += ((ow ^ fz.w[w]) & kBit1) + ((ow ^ bz.w[w]) & kBit1);
+        kk[w] = k2 >> 1;
+        nw[w] = decide4_fast(th_lo, th_hi, ow, kk[w], rp.w[w], tie[w]);
+        anytie |= tie[w];
+      }
+      if (anytie) {
+        // rare: a prefix byte may equal its threshold byte; queue the exact
+        // ties for the refinement draw at the end of the band
+        uint32_t m = exact_ties16(th_lo, th_hi, kk, rp);
+        while (m) {
+          const uint32_t idx = __builtin_ctz(m);
+          m &= m - 1;
+          const uint32_t w = idx >> 2, b = idx & 3u;
+          const uint32_t kw = w == 0 ? kk[0] : (w == 1 ? kk[1] : (w == 2 ? kk[2] : kk[3]));
+          const uint32_t k = (kw >> (8 * b)) & 0xFu;
+          const uint32_t js = jbase + idx;
+          if (pend.n < 4) {
+            pend.j[0] = pend.n == 0 ? js : pend.j[0];
+            pend.j[1] = pend.n == 1 ? js : pend.j[1];
+            pend.j[2] = pend.n == 2 ? js : pend.j[2];
+            pend.j[3] = pend.n == 3 ? js : pend.j[3];
+            pend.k |= k << (4 * pend.n);
+            pend.n += 1;
+          } else {
+            const Rand4 rr = philox(js, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
+            if ((rr.w[0] & 0xFFFFFFu) < frac_of(tab, k)) {
+              const uint32_t f = 0xFEu << (8 * b);
+              nw[0] ^= w == 0 ? f : 0u;
+              nw[1] ^= w == 1 ? f : 0u;
+              nw[2] ^= w == 2 ? f : 0u;
+              nw[3] ^= w == 3 ? f : 0u;
+            }
+          }
+        }
+      }
+      st16(own + jbase, nw);
+      if (MEASURE) {
+        // colour 1 after its update: every bond has one colour-1 end, and the
+        // colour-0 chunk at the same position covers each colour-0 site once
+        uint32_t kn[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          uint32_t k2 = ((nw[w] ^ ct.w[w]) & kBit1) + ((nw[w] ^ sh.w[w]) & kBit1) +
+                        ((nw[w] ^ up.w[w]) & kBit1) + ((nw[w] ^ dn.w[w]) & kBit1);
+          if (D == 3) k2 += ((nw[w] ^ fz.w[w]) & kBit1) + ((nw[w] ^ bz.w[w]) & kBit1);
+          kn[w] = k2 >> 1;
+        }
+        Chunk nc;
+        nc.w[0] = nw[0]; nc.w[1] = nw[1]; nc.w[2] = nw[2]; nc.w[3] = nw[3];
+        Esum += -(int64_t)(16 * 2 * D) + 2 * (int64_t)chunk_count_sum(kn);
+        Msum += chunk_spin_sum(nc) + chunk_spin_sum(ct);
+      }
+      up = ct;
+      ct = dn;
+      dn = dn2;
+      o = o2;
+    }
+    // deferred ties: the site belongs to this lane's column of its own colour,
+    // which no other lane of this launch touches
+    for (uint32_t e = 0; e < pend.n; ++e) {
+      const uint32_t js = e == 0 ? pend.j[0] : (e == 1 ? pend.j[1] : (e == 2 ? pend.j[2] : pend.j[3]));
+      const uint32_t k = (pend.k >> (4 * e)) & 0xFu;
+      const Rand4 rr = philox(js, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
+      if ((rr.w[0] & 0xFFFFFFu) < frac_of(tab, k)) {
+        const int8_t v = own[js];
+        own[js] = (int8_t)(-v);
+        if (MEASURE) {
+          Esum += 4 * (int64_t)(D - (int)k);  // the flipped site's bonds all change sign
+          Msum -= 2 * (int64_t)v;
+        }
+      }
+    }
+  }
+  if (MEASURE) block_partial_int(Esum, Msum, parts, blockIdx.x);
 }
 
 bool ising_chunk_supported(const Geom& g, int J_kind) {
@@ -229,12 +346,70 @@ static hipError_t launch_chunk(const IsingLaunch& a, int8_t* spins, uint32_t t, 
   return hipGetLastError();
 }
 
+// Rows per band of the streaming kernel: the largest divisor of L up to 64
+// that still gives at least `min_waves` waves.
+uint32_t stream_rows_per_band(const Geom& g, uint32_t min_waves) {
+  const uint32_t Q = (uint32_t)(g.R / 16);
+  uint32_t best = 1;
+  for (uint32_t H = 1; H <= 64; H *= 2) {
+    if (g.L % H) break;
+    const uint64_t waves = (uint64_t)Q * (uint64_t)(g.rows / H) / 64;
+    if (waves >= min_waves) best = H;
+  }
+  return best;
+}
+
+template <int D>
+static hipError_t launch_stream(const IsingLaunch& a, int8_t* spins, uint32_t t, uint32_t c,
+                                hipStream_t st, void* partials = nullptr, int64_t* nparts = nullptr) {
+  const uint32_t H = a.rows_per_band;
+  const uint32_t nbands = (uint32_t)a.g.rows / H;
+  const uint64_t threads = (uint64_t)nbands * a.divQ.d;
+  const dim3 grid((unsigned)((threads + 255) / 256));
+  if (partials) {
+    hipLaunchKernelGGL((ising_stream_kernel<D, true>), grid, dim3(256), 0, st, a.g, a.key, a.tab,
+                       a.divQ, a.divL, H, nbands, spins, t, c, (Partial*)partials);
+    if (nparts) *nparts = grid.x;
+  } else {
+    hipLaunchKernelGGL((ising_stream_kernel<D, false>), grid, dim3(256), 0, st, a.g, a.key, a.tab,
+                       a.divQ, a.divL, H, nbands, spins, t, c, (Partial*)nullptr);
+  }
+  return hipGetLastError();
+}
+
+// Colour-1 half-sweep of the streaming kernel with the observables of the
+// resulting state reduced on the way; false if the handle's kernel is not
+// the streaming one (the caller measures separately).
+bool ising_half_sweep_measured(const IsingLaunch& a, int8_t* spins, uint32_t t, void* partials,
+                               int64_t* nparts, hipStream_t st, hipError_t* err) {
+  if (ising_variant_used(a) != kVariantStream) return false;
+  *err = a.g.d == 2 ? launch_stream<2>(a, spins, t, 1u, st, partials, nparts)
+                    : launch_stream<3>(a, spins, t, 1u, st, partials, nparts);
+  return true;
+}
+
+int ising_variant_used(const IsingLaunch& a) {
+  int v = a.variant;
+  const bool chunk_ok = ising_chunk_supported(a.g, a.J_kind);
+  if (v == kVariantAuto) v = !chunk_ok ? kVariantSite : (a.J_kind == 0 ? kVariantStream : kVariantChunk);
+  if (v == kVariantStream && !(chunk_ok && a.J_kind == 0 && a.rows_per_band >= 1 &&
+                               a.g.L % a.rows_per_band == 0))
+    v = chunk_ok ? kVariantChunk : kVariantSite;
+  if (v == kVariantChunk && !chunk_ok) v = kVariantSite;
+  return v;
+}
+
 hipError_t launch_ising_half_sweep(const IsingLaunch& a, int8_t* spins, uint32_t t,
                                    uint32_t colour, hipStream_t st) {
-  const bool chunk = !a.generic && ising_chunk_supported(a.g, a.J_kind);
-  if (a.g.d == 2)
-    return chunk ? launch_chunk<2>(a, spins, t, colour, st) : launch_site<2>(a, spins, t, colour, st);
-  return chunk ? launch_chunk<3>(a, spins, t, colour, st) : launch_site<3>(a, spins, t, colour, st);
+  const int v = ising_variant_used(a);
+  if (a.g.d == 2) {
+    if (v == kVariantStream) return launch_stream<2>(a, spins, t, colour, st);
+    if (v == kVariantChunk) return launch_chunk<2>(a, spins, t, colour, st);
+    return launch_site<2>(a, spins, t, colour, st);
+  }
+  if (v == kVariantStream) return launch_stream<3>(a, spins, t, colour, st);
+  if (v == kVariantChunk) return launch_chunk<3>(a, spins, t, colour, st);
+  return launch_site<3>(a, spins, t, colour, st);
 }
 
 }  // namespace smc

@@ -20,6 +20,8 @@ struct FastDiv {
 };
 FastDiv make_fastdiv(uint32_t d);
 
+enum IsingVariant { kVariantAuto = 0, kVariantSite = 1, kVariantChunk = 2, kVariantStream = 3 };
+
 struct IsingLaunch {
   Geom g;
   RngKey key;
@@ -27,10 +29,22 @@ struct IsingLaunch {
   int J_kind;        // 0 uniform, 1 +-1 int8, 2 FP32
   const void* J;     // [d][2][N/2] or null
   float beta;        // FP32 couplings only
-  int generic;       // force the one-site-per-thread kernel
+  int variant;       // IsingVariant
+  uint32_t rows_per_band;  // streaming kernel: rows walked by one lane (divides L)
   FastDiv divQ;      // chunks per plane row
   FastDiv divL;      // edge length
 };
+
+uint32_t stream_rows_per_band(const Geom& g, uint32_t min_waves);
+int ising_variant_used(const IsingLaunch& a);  // the variant a launch resolves to
+bool ising_half_sweep_measured(const IsingLaunch& a, int8_t* spins, uint32_t t, void* partials,
+                               int64_t* nparts, hipStream_t st, hipError_t* err);
+
+// Fused one-pass sweep (2D, uniform couplings): src -> dst, both [2][N/2].
+bool ising_fused_supported(const Geom& g, int J_kind, uint32_t rows_per_band);
+uint32_t fused_rows_per_band(const Geom& g, uint32_t min_blocks);
+hipError_t launch_ising_sweep_fused(const IsingLaunch& a, const int8_t* src, int8_t* dst,
+                                    uint32_t t, void* partials, int64_t* nparts, hipStream_t st);
 
 hipError_t launch_ising_half_sweep(const IsingLaunch& a, int8_t* spins, uint32_t t,
                                    uint32_t colour, hipStream_t st);
@@ -73,6 +87,9 @@ int64_t measure_partials(const Geom& g);
 // Reduce to an smc_obs-layout struct at dev_obs; partials: workspace scratch.
 hipError_t launch_measure(const MeasureLaunch& a, const void* spins, void* partials,
                           void* dev_obs, hipStream_t st);
+// Reduce nparts partials (written by a measuring sweep kernel) into dev_obs.
+hipError_t launch_finish(const MeasureLaunch& a, const void* partials, int64_t nparts,
+                         void* dev_obs, hipStream_t st);
 
 hipError_t launch_bond_accumulate(const MeasureLaunch& a, const void* spins, void* acc,
                                   hipStream_t st);

@@ -9,53 +9,9 @@
 // double (FP32 products promoted exactly), then reduced by a single block in a
 // fixed order, so the result is deterministic.
 #include "chunk.hpp"
+#include "reduce.hpp"
 
 namespace smc {
-
-struct Partial {
-  int64_t Ei;   // integer energy (uniform / +-1)
-  int64_t Mi;   // integer magnetisation
-  double E;     // double energy (FP32 couplings, continuous spins)
-  double M[3];  // continuous magnetisation
-};
-
-struct ObsOut {  // layout of smc_obs
-  int64_t E_int;
-  int64_t M_int;
-  double E;
-  double M[3];
-  double absM;
-};
-
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  return v;
-}
-
-// Block of 256 threads: reduce each field, thread 0 writes the partial.
-__device__ __forceinline__ void block_partial(Partial v, Partial* out) {
-  __shared__ Partial sh[4];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  v.Ei = wave_sum(v.Ei);
-  v.Mi = wave_sum(v.Mi);
-  v.E = wave_sum(v.E);
-#pragma unroll
-  for (int k = 0; k < 3; ++k) v.M[k] = wave_sum(v.M[k]);
-  if (lane == 0) sh[wv] = v;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    Partial a = sh[0];
-    for (int w = 1; w < 4; ++w) {
-      a.Ei += sh[w].Ei;
-      a.Mi += sh[w].Mi;
-      a.E += sh[w].E;
-      for (int k = 0; k < 3; ++k) a.M[k] += sh[w].M[k];
-    }
-    out[blockIdx.x] = a;
-  }
-}
 
 // Ising, one colour-1 site per thread, any L / coupling kind.
 template <int D, int JK>
@@ -277,8 +233,13 @@ hipError_t launch_measure(const MeasureLaunch& a, const void* spins, void* parti
     launch_measure_d<3>(a, spins, parts, nparts, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, st, parts, nparts, a.n == 1 ? 1 : 0,
-                     a.J_kind != 2 ? 1 : 0, a.J0, (ObsOut*)dev_obs);
+  return launch_finish(a, parts, nparts, dev_obs, st);
+}
+
+hipError_t launch_finish(const MeasureLaunch& a, const void* partials, int64_t nparts,
+                         void* dev_obs, hipStream_t st) {
+  hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, st, (const Partial*)partials, nparts,
+                     a.n == 1 ? 1 : 0, a.J_kind != 2 ? 1 : 0, a.J0, (ObsOut*)dev_obs);
   return hipGetLastError();
 }
 

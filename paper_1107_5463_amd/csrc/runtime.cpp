@@ -9,6 +9,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 
@@ -31,6 +32,10 @@ struct smc_lattice {
   double tab_beta;
   IsingTable tab;
   FastDiv divQ, divL;
+  int ising_variant;         // IsingVariant (SMC_ISING_KERNEL overrides the automatic choice)
+  uint32_t rows_per_band;    // streaming kernel band height (SMC_STREAM_ROWS overrides)
+  bool use_fused;            // SMC_FLAG_SCHEDULE_FUSED and the fused kernel supports the shape
+  uint32_t fused_rows;       // fused kernel band height (SMC_FUSED_ROWS overrides)
   // workspace carve-up
   void* obs_slot;      // smc_obs (64 B)
   uint32_t* counter;   // validation counter
@@ -133,7 +138,12 @@ void build_table(smc_lattice* h, double beta) {
       else T = (uint64_t)c;
     }
     if (always) {
+      // the fast kernels test only the threshold byte: 0xFF with a refinement
+      // fraction of 2^24 accepts on every draw (prefix < 255, or prefix = 255
+      // and any 24-bit refinement word)
       al[k] = 0xFF;
+      th[k] = 0xFF;
+      tab.frac[k] = 0x1000000u;
     } else {
       th[k] = (uint8_t)(T >> 24);
       tab.frac[k] = (uint32_t)(T & 0xFFFFFFu);
@@ -158,19 +168,25 @@ MeasureLaunch measure_args(const smc_lattice* h) {
   return m;
 }
 
+IsingLaunch ising_args(smc_lattice* h, double beta) {
+  if (h->p.J_kind != SMC_J_FP32) build_table(h, beta);
+  IsingLaunch a;
+  a.g = h->g;
+  a.key = key_of(h);
+  a.tab = h->tab;
+  a.J_kind = h->p.J_kind;
+  a.J = h->J;
+  a.beta = (float)beta;
+  a.variant = (h->p.flags & SMC_FLAG_GENERIC_KERNEL) ? kVariantSite : h->ising_variant;
+  a.rows_per_band = h->rows_per_band;
+  a.divQ = h->divQ;
+  a.divL = h->divL;
+  return a;
+}
+
 int half_sweep_impl(smc_lattice* h, double beta, uint32_t t, uint32_t colour) {
   if (h->p.n == 1) {
-    if (h->p.J_kind != SMC_J_FP32) build_table(h, beta);
-    IsingLaunch a;
-    a.g = h->g;
-    a.key = key_of(h);
-    a.tab = h->tab;
-    a.J_kind = h->p.J_kind;
-    a.J = h->J;
-    a.beta = (float)beta;
-    a.generic = (h->p.flags & SMC_FLAG_GENERIC_KERNEL) ? 1 : 0;
-    a.divQ = h->divQ;
-    a.divL = h->divL;
+    const IsingLaunch a = ising_args(h, beta);
     return check(launch_ising_half_sweep(a, (int8_t*)h->spins, t, colour, h->stream),
                  "Ising half-sweep launch");
   }
@@ -187,6 +203,87 @@ int half_sweep_impl(smc_lattice* h, double beta, uint32_t t, uint32_t colour) {
   a.fast_math = (h->p.flags & SMC_FLAG_FAST_MATH) ? 1 : 0;
   return check(launch_cont_half_sweep(a, (float*)h->spins, t, colour, h->stream),
                "continuous half-sweep launch");
+}
+
+// One in-place two-pass sweep with counter t; with dev_obs the observables of
+// the result are written there (fused into the colour-1 pass when the
+// streaming kernel runs, else by a separate measurement).
+int two_pass_sweep(smc_lattice* h, double beta, uint32_t t, void* dev_obs) {
+  int rc = half_sweep_impl(h, beta, t, 0u);
+  if (rc != SMC_OK) return rc;
+  if (dev_obs && h->p.n == 1) {
+    const IsingLaunch a = ising_args(h, beta);
+    int64_t nparts = 0;
+    hipError_t err = hipSuccess;
+    if (ising_half_sweep_measured(a, (int8_t*)h->spins, t, h->partials, &nparts, h->stream, &err)) {
+      rc = check(err, "measured Ising half-sweep launch");
+      if (rc != SMC_OK) return rc;
+      return check(launch_finish(measure_args(h), h->partials, nparts, dev_obs, h->stream),
+                   "measurement finish launch");
+    }
+  }
+  rc = half_sweep_impl(h, beta, t, 1u);
+  if (rc != SMC_OK) return rc;
+  if (dev_obs)
+    return check(launch_measure(measure_args(h), h->spins, h->partials, dev_obs, h->stream),
+                 "measurement launch");
+  return SMC_OK;
+}
+
+// n sweeps from t with the fused kernel, ping-ponging through the workspace
+// buffer; an odd count starts with one in-place two-pass sweep so that the
+// state always ends in the caller's buffer.
+int fused_sweeps(smc_lattice* h, double beta, int64_t n, void* dev_obs) {
+  int64_t k = 0;
+  if (n % 2 == 1) {
+    const int rc = two_pass_sweep(h, beta, (uint32_t)h->t, n == 1 ? dev_obs : nullptr);
+    if (rc != SMC_OK) return rc;
+    h->t += 1;
+    k = 1;
+  }
+  const IsingLaunch a = ising_args(h, beta);
+  IsingLaunch af = a;
+  af.rows_per_band = h->fused_rows;
+  int8_t* A = (int8_t*)h->spins;
+  int8_t* B = (int8_t*)h->alt_spins;
+  for (; k < n; k += 2) {
+    const bool last = k + 2 >= n;
+    int rc = check(launch_ising_sweep_fused(af, A, B, (uint32_t)h->t, nullptr, nullptr, h->stream),
+                   "fused sweep launch");
+    if (rc != SMC_OK) return rc;
+    int64_t nparts = 0;
+    void* parts = (last && dev_obs) ? h->partials : nullptr;
+    rc = check(launch_ising_sweep_fused(af, B, A, (uint32_t)h->t + 1, parts, &nparts, h->stream),
+               "fused sweep launch");
+    if (rc != SMC_OK) return rc;
+    h->t += 2;
+    if (parts) {
+      rc = check(launch_finish(measure_args(h), h->partials, nparts, dev_obs, h->stream),
+                 "measurement finish launch");
+      if (rc != SMC_OK) return rc;
+    }
+  }
+  return SMC_OK;
+}
+
+int sweeps_impl(smc_lattice* h, double beta, int64_t n_sweeps, void* dev_obs) {
+  if (h->use_fused) return fused_sweeps(h, beta, n_sweeps, dev_obs);
+  for (int64_t k = 0; k < n_sweeps; ++k) {
+    const bool last = k + 1 == n_sweeps;
+    const bool renorm = h->p.n > 1 && h->p.renorm_every > 0 &&
+                        (h->t + 1) % (uint64_t)h->p.renorm_every == 0;
+    int rc = two_pass_sweep(h, beta, (uint32_t)h->t, (last && !renorm) ? dev_obs : nullptr);
+    if (rc != SMC_OK) return rc;
+    h->t += 1;
+    if (renorm) {
+      rc = check(launch_renormalize(h->g, h->p.n, (float*)h->spins, h->stream), "renormalisation launch");
+      if (rc != SMC_OK) return rc;
+      if (last && dev_obs)
+        return check(launch_measure(measure_args(h), h->spins, h->partials, dev_obs, h->stream),
+                     "measurement launch");
+    }
+  }
+  return SMC_OK;
 }
 
 }  // namespace
@@ -233,8 +330,6 @@ int smc_init_lattice(smc_lattice** out, const smc_params* p, void* spins, void* 
   if (workspace_bytes < smc_workspace_bytes(p))
     return fail(SMC_EINVAL, "workspace too small: need " + std::to_string(smc_workspace_bytes(p)) +
                                 " bytes");
-  if (p->flags & SMC_FLAG_SCHEDULE_FUSED)
-    return fail(SMC_EINVAL, "fused schedule is not available in this build");
   smc_lattice* h = new (std::nothrow) smc_lattice();
   if (!h) return fail(SMC_EINVAL, "out of host memory");
   h->p = *p;
@@ -249,10 +344,30 @@ int smc_init_lattice(smc_lattice** out, const smc_params* p, void* spins, void* 
   h->tab_valid = false;
   h->divQ = make_fastdiv((uint32_t)(h->g.R / 16 > 0 ? h->g.R / 16 : 1));
   h->divL = make_fastdiv((uint32_t)h->g.L);
+  h->ising_variant = kVariantAuto;
+  if (const char* v = std::getenv("SMC_ISING_KERNEL")) {
+    const std::string s(v);
+    h->ising_variant = s == "site" ? kVariantSite : s == "chunk" ? kVariantChunk
+                     : s == "stream" ? kVariantStream : kVariantAuto;
+  }
+  h->rows_per_band = stream_rows_per_band(h->g, 8192);
+  if (const char* v = std::getenv("SMC_STREAM_ROWS")) {
+    const long H = std::strtol(v, nullptr, 10);
+    if (H >= 1 && H <= h->g.L && h->g.L % H == 0) h->rows_per_band = (uint32_t)H;
+  }
   h->obs_slot = h->ws;
   h->counter = (uint32_t*)(h->ws + kAlign);
   h->partials = h->ws + 2 * kAlign;
-  h->alt_spins = nullptr;
+  h->alt_spins = (p->flags & SMC_FLAG_SCHEDULE_FUSED) ? (void*)(h->ws + 2 * kAlign + partial_bytes(p))
+                                                      : nullptr;
+  h->fused_rows = fused_rows_per_band(h->g, 1024);
+  if (const char* v = std::getenv("SMC_FUSED_ROWS")) {
+    const long H = std::strtol(v, nullptr, 10);
+    if (H >= 1 && H <= h->g.L && h->g.L % H == 0) h->fused_rows = (uint32_t)H;
+  }
+  h->use_fused = p->n == 1 && (p->flags & SMC_FLAG_SCHEDULE_FUSED) &&
+                 !(p->flags & SMC_FLAG_GENERIC_KERNEL) &&
+                 ising_fused_supported(h->g, p->J_kind, h->fused_rows);
   const RngKey key = key_of(h);
   int rc = SMC_OK;
   if (p->J_kind != SMC_J_UNIFORM && !(p->flags & SMC_FLAG_COUPLINGS_KEEP))
@@ -286,20 +401,20 @@ int smc_sweep(smc_lattice* h, double beta, int64_t n_sweeps) {
   if (n_sweeps < 0) return fail(SMC_EINVAL, "n_sweeps must be >= 0");
   if (h->t + (uint64_t)n_sweeps > 4294967296ull)
     return fail(SMC_ERANGE, "sweep counter would exceed 2^32");
-  for (int64_t k = 0; k < n_sweeps; ++k) {
-    const uint32_t t = (uint32_t)h->t;
-    for (uint32_t c = 0; c < 2; ++c) {
-      const int rc = half_sweep_impl(h, beta, t, c);
-      if (rc != SMC_OK) return rc;
-    }
-    h->t += 1;
-    if (h->p.n > 1 && h->p.renorm_every > 0 && h->t % (uint64_t)h->p.renorm_every == 0) {
-      const int rc = check(launch_renormalize(h->g, h->p.n, (float*)h->spins, h->stream),
-                           "renormalisation launch");
-      if (rc != SMC_OK) return rc;
-    }
-  }
-  return SMC_OK;
+  return sweeps_impl(h, beta, n_sweeps, nullptr);
+}
+
+int smc_sweep_measure(smc_lattice* h, double beta, int64_t n_sweeps, void* dev_obs) {
+  if (!h) return fail(SMC_EINVAL, "handle is NULL");
+  if (!beta_ok(beta)) return fail(SMC_EINVAL, "beta must be >= 0 (or +inf), not NaN");
+  if (n_sweeps < 0) return fail(SMC_EINVAL, "n_sweeps must be >= 0");
+  if (!dev_obs || ((uintptr_t)dev_obs & 7)) return fail(SMC_EINVAL, "dev_obs must be 8-byte aligned");
+  if (h->t + (uint64_t)n_sweeps > 4294967296ull)
+    return fail(SMC_ERANGE, "sweep counter would exceed 2^32");
+  if (n_sweeps == 0)
+    return check(launch_measure(measure_args(h), h->spins, h->partials, dev_obs, h->stream),
+                 "measurement launch");
+  return sweeps_impl(h, beta, n_sweeps, dev_obs);
 }
 
 int smc_half_sweep(smc_lattice* h, double beta, int colour) {
@@ -399,6 +514,29 @@ int smc_set_sweep_index(smc_lattice* h, uint64_t t) {
   if (t > 4294967296ull) return fail(SMC_ERANGE, "sweep index must be <= 2^32");
   h->t = t;
   return SMC_OK;
+}
+
+const char* smc_kernel_name(const smc_lattice* h, uint32_t* rows_per_band) {
+  if (rows_per_band) *rows_per_band = 0;
+  if (!h) return "";
+  if (h->p.n == 2) return "xy_site";
+  if (h->p.n == 3) return "heisenberg_site";
+  if (h->use_fused) {
+    if (rows_per_band) *rows_per_band = h->fused_rows;
+    return "ising_fused";
+  }
+  IsingLaunch a;
+  a.g = h->g;
+  a.J_kind = h->p.J_kind;
+  a.variant = (h->p.flags & SMC_FLAG_GENERIC_KERNEL) ? kVariantSite : h->ising_variant;
+  a.rows_per_band = h->rows_per_band;
+  switch (ising_variant_used(a)) {
+    case kVariantStream:
+      if (rows_per_band) *rows_per_band = h->rows_per_band;
+      return "ising_stream";
+    case kVariantChunk: return "ising_chunk";
+    default: return "ising_site";
+  }
 }
 
 int smc_destroy(smc_lattice* h) {

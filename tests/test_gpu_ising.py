@@ -258,3 +258,71 @@ def test_abi_errors_on_device(smc_gpu):
     with pytest.raises(smc_gpu.SmcError) as e:
         lat2.validate()
     assert e.value.code == smc_gpu.SMC_ESTATE
+
+
+@pytest.mark.parametrize("d,L", [(2, 64), (2, 96), (3, 32), (2, 512), (3, 64)])
+def test_kernel_variants_bit_identical(smc_gpu, oracle_mod, d, L, monkeypatch):
+    """Every half-sweep kernel (one site per thread, one chunk per lane,
+    streaming bands of every height) produces the oracle's chain: the same
+    bits whatever the launch geometry -- this doubles as the race check."""
+    ref = oracle_mod.OracleLattice(d, 1, L, 88)
+    ref.sweep(0.3, 4)
+    seen = set()
+    for variant, rows in [("site", None), ("chunk", None), ("stream", "1"), ("stream", "2"),
+                          ("stream", "8"), ("stream", "32"), ("stream", None)]:
+        monkeypatch.setenv("SMC_ISING_KERNEL", variant)
+        if rows is None:
+            monkeypatch.delenv("SMC_STREAM_ROWS", raising=False)
+        else:
+            monkeypatch.setenv("SMC_STREAM_ROWS", rows)
+        lat = smc_gpu.Lattice(d, 1, L, seed=88)
+        seen.add(lat.kernel())
+        lat.sweep(0.3, 4)
+        assert np.array_equal(nat(lat), ref.s), (variant, rows, lat.kernel())
+    assert {name for name, _ in seen} == {"ising_site", "ising_chunk", "ising_stream"}
+
+
+@pytest.mark.parametrize("L,n,rows", [(2048, 4, None), (2048, 5, "1"), (4096, 3, "4"),
+                                      (2048, 2, "64"), (4096, 1, None)])
+def test_fused_schedule_matches_oracle(smc_gpu, oracle_mod, L, n, rows, monkeypatch):
+    """The one-kernel-per-sweep schedule (ping-pong buffers, LDS edge
+    exchange, redundant band-edge rows) gives the oracle's chain bit for bit,
+    for odd and even sweep counts and any band height; the energy and
+    magnetisation reduced inside the last fused sweep equal the oracle's."""
+    import torch
+    if rows is None:
+        monkeypatch.delenv("SMC_FUSED_ROWS", raising=False)
+    else:
+        monkeypatch.setenv("SMC_FUSED_ROWS", rows)
+    lat = smc_gpu.Lattice(2, 1, L, seed=12, fused=True)
+    assert lat.kernel()[0] == "ising_fused"
+    ref = oracle_mod.OracleLattice(2, 1, L, 12)
+    lat.sweep(BETA_C, n)
+    ref.sweep(BETA_C, n)
+    assert np.array_equal(nat(lat), ref.s)
+    slot = torch.zeros(8, dtype=torch.int64, device=lat.device)
+    lat.sweep_measure(BETA_C, n, slot)
+    ref.sweep(BETA_C, n)
+    o = smc_gpu.Lattice.decode_obs(slot)[0]
+    r = ref.measure()
+    assert (o.E_int, o.M_int) == (r.E_int, r.M_int)
+    assert np.array_equal(nat(lat), ref.s)
+    assert lat.t == 2 * n
+
+
+@pytest.mark.parametrize("d,L,variant", [(2, 64, "stream"), (2, 64, "chunk"), (2, 64, "site"),
+                                         (3, 32, "stream"), (3, 32, "chunk"), (2, 10, "site"),
+                                         (3, 16, "stream")])
+def test_sweep_measure_matches_oracle(smc_gpu, oracle_mod, d, L, variant, monkeypatch):
+    import torch
+    monkeypatch.setenv("SMC_ISING_KERNEL", variant)
+    lat = smc_gpu.Lattice(d, 1, L, seed=14)
+    ref = oracle_mod.OracleLattice(d, 1, L, 14)
+    slots = torch.zeros((3, 8), dtype=torch.int64, device=lat.device)
+    for k, n in enumerate((1, 3, 0)):
+        lat.sweep_measure(0.35, n, slots[k])
+    got = smc_gpu.Lattice.decode_obs(slots)
+    for k, n in enumerate((1, 3, 0)):
+        ref.sweep(0.35, n)
+        r = ref.measure()
+        assert (got[k].E_int, got[k].M_int) == (r.E_int, r.M_int), (k, variant)
