@@ -184,6 +184,54 @@ const char* smc_kernel_name(const smc_lattice* h, uint32_t* rows_per_band);
 /* Free the handle (never the caller's buffers). */
 int smc_destroy(smc_lattice* h);
 
+/* ------------------------------------------------------------------------ */
+/* Batches: many independent Ising lattices of uneven edge, temperature and */
+/* disorder realisation swept together by one persistent launch (Sec. 2:   */
+/* parallelisation over disorder realisations on top of the checkerboard   */
+/* decomposition).  Lattice r (0 <= r < n_lattices) has edge L[r] (even,    */
+/* 4..40 in 3D, 4..256 in 2D: L[r]^d <= 64 KiB), inverse temperature        */
+/* beta[r] and replica replica[r] (r if NULL), and follows exactly the       */
+/* single-lattice chain of smc_init_lattice with those parameters.          */
+/* Buffers (caller-owned, device):                                          */
+/*   spins  int8, lattice r's [2][N_r/2] planes at byte offset S_r;         */
+/*   J      NULL (uniform J0) or int8 +-1, lattice r's [d][2][N_r/2] at C_r;  */
+/*   offsets from smc_batch_offsets (each lattice starts 16-byte aligned).   */
+/* ------------------------------------------------------------------------ */
+typedef struct smc_batch smc_batch;
+
+size_t smc_batch_spin_bytes(int32_t d, int32_t n_lattices, const int32_t* L);
+size_t smc_batch_coupling_bytes(int32_t d, int32_t n_lattices, const int32_t* L);
+/* Descriptor table, schedule and an autotuning copy of the spins. */
+size_t smc_batch_workspace_bytes(int32_t d, int32_t n_lattices, const int32_t* L);
+int smc_batch_offsets(int32_t d, int32_t n_lattices, const int32_t* L, int64_t* spin_offsets,
+                      int64_t* coupling_offsets);
+
+/* J_kind: SMC_J_UNIFORM or SMC_J_PM; init HOT / COLD / KEEP; with PM the
+ * couplings are generated from (seed, replica[r]) unless couplings_keep. */
+int smc_batch_init(smc_batch** out, int32_t d, int32_t J_kind, uint64_t seed, double J0,
+                   int32_t init, int32_t couplings_keep, int32_t n_lattices, const int32_t* L,
+                   const double* beta, const uint32_t* replica, void* spins, void* J,
+                   void* workspace, size_t workspace_bytes, void* stream);
+
+/* n_sweeps sweeps of every lattice in one launch (asynchronous).  With
+ * dev_obs (n_lattices smc_obs, 8-byte aligned) the energy and magnetisation
+ * of each lattice's final state are written there by the same launch. */
+int smc_batch_sweep(smc_batch* b, int64_t n_sweeps, void* dev_obs);
+
+/* Time the workgroup sizes 64..512 and the lattice orders (largest first,
+ * as given) on a scratch copy of the spins and keep the fastest.  Results do
+ * not depend on the choice.  Synchronises the stream. */
+int smc_batch_autotune(smc_batch* b, int32_t* threads_out, int32_t* largest_first_out);
+
+/* With enable != 0 later smc_batch_sweep calls replay one instantiated
+ * hipGraph holding the launch (rebuilt when n_sweeps, dev_obs or the
+ * sweep counter's host copy change shape). */
+int smc_batch_use_graph(smc_batch* b, int32_t enable);
+
+int smc_batch_get_sweep_index(const smc_batch* b, uint64_t* t);
+int smc_batch_set_sweep_index(smc_batch* b, uint64_t t);
+int smc_batch_destroy(smc_batch* b);
+
 /* The calling thread's last error message ("" if none). */
 const char* smc_last_error(void);
 const char* smc_version(void);

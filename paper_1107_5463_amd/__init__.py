@@ -21,7 +21,7 @@ import dataclasses
 import math
 import os
 
-__all__ = ["Lattice", "SmcError", "load_library", "lib_path", "Obs", "J_UNIFORM", "J_PM",
+__all__ = ["Lattice", "Batch", "SmcError", "load_library", "lib_path", "Obs", "J_UNIFORM", "J_PM",
            "J_FP32", "EXPORTS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -39,7 +39,11 @@ EXPORTS = ["smc_spin_bytes", "smc_coupling_bytes", "smc_workspace_bytes", "smc_b
            "smc_measure",
            "smc_measure_async", "smc_bond_correlations", "smc_get_samples", "smc_set_samples",
            "smc_renormalize", "smc_validate", "smc_get_sweep_index", "smc_set_sweep_index",
-           "smc_kernel_name", "smc_destroy", "smc_last_error", "smc_version"]
+           "smc_kernel_name", "smc_destroy", "smc_last_error", "smc_version",
+           "smc_batch_spin_bytes", "smc_batch_coupling_bytes", "smc_batch_workspace_bytes",
+           "smc_batch_offsets", "smc_batch_init", "smc_batch_sweep", "smc_batch_autotune",
+           "smc_batch_use_graph", "smc_batch_get_sweep_index", "smc_batch_set_sweep_index",
+           "smc_batch_destroy"]
 
 
 class SmcError(RuntimeError):
@@ -108,11 +112,27 @@ def load_library():
     lib.smc_kernel_name.argtypes = [vp, C.POINTER(C.c_uint32)]
     lib.smc_kernel_name.restype = C.c_char_p
     lib.smc_destroy.argtypes = [vp]
+    i32p = C.POINTER(C.c_int32)
+    for f in ("smc_batch_spin_bytes", "smc_batch_coupling_bytes", "smc_batch_workspace_bytes"):
+        getattr(lib, f).argtypes = [C.c_int32, C.c_int32, i32p]
+        getattr(lib, f).restype = sz
+    lib.smc_batch_offsets.argtypes = [C.c_int32, C.c_int32, i32p, C.POINTER(C.c_int64),
+                                      C.POINTER(C.c_int64)]
+    lib.smc_batch_init.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32, C.c_uint64, C.c_double,
+                                   C.c_int32, C.c_int32, C.c_int32, i32p, C.POINTER(C.c_double),
+                                   C.POINTER(C.c_uint32), vp, vp, vp, sz, vp]
+    lib.smc_batch_sweep.argtypes = [vp, C.c_int64, vp]
+    lib.smc_batch_autotune.argtypes = [vp, i32p, i32p]
+    lib.smc_batch_use_graph.argtypes = [vp, C.c_int32]
+    lib.smc_batch_get_sweep_index.argtypes = [vp, C.POINTER(C.c_uint64)]
+    lib.smc_batch_set_sweep_index.argtypes = [vp, C.c_uint64]
+    lib.smc_batch_destroy.argtypes = [vp]
     lib.smc_last_error.restype = C.c_char_p
     lib.smc_version.restype = C.c_char_p
     for f in EXPORTS:
         if f not in ("smc_spin_bytes", "smc_coupling_bytes", "smc_workspace_bytes", "smc_bond_bytes",
-                     "smc_last_error", "smc_version", "smc_kernel_name"):
+                     "smc_last_error", "smc_version", "smc_kernel_name", "smc_batch_spin_bytes",
+                     "smc_batch_coupling_bytes", "smc_batch_workspace_bytes"):
             getattr(lib, f).restype = C.c_int
     _LIB = lib
     return lib
@@ -326,6 +346,113 @@ class Lattice:
             self.bond_accumulator().copy_(sd["acc"])
         self.t = sd["t"]
         self.samples = sd.get("samples", 0)
+
+
+class Batch:
+    """Many independent Ising lattices (edges L[r], inverse temperatures
+    beta[r], replicas replica[r] or r) swept together by one persistent
+    launch; lattice r follows the single-lattice chain with those parameters.
+    Spins and couplings live in two flat int8 tensors; lattice views are
+    available through spins_of(r) / couplings_of(r)."""
+
+    def __init__(self, d: int, L, beta, seed: int = 0, *, J_kind=J_PM, J0: float = 1.0,
+                 init="hot", replica=None, spins=None, J=None, device=None, stream=None):
+        import numpy as np
+        import torch
+        lib = load_library()
+        self.torch = torch
+        self.d = d
+        self.L = [int(v) for v in L]
+        self.n = len(self.L)
+        self.beta = [float(v) for v in beta]
+        assert len(self.beta) == self.n
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        Larr = (C.c_int32 * self.n)(*self.L)
+        self._Larr = Larr
+        sb = lib.smc_batch_spin_bytes(d, self.n, Larr)
+        if sb == 0:
+            h = C.c_void_p()
+            _check(lib.smc_batch_init(C.byref(h), d, 0, 0, 1.0, 0, 0, self.n, Larr, None, None,
+                                      None, None, None, 0, None))
+        jb = lib.smc_batch_coupling_bytes(d, self.n, Larr)
+        wb = lib.smc_batch_workspace_bytes(d, self.n, Larr)
+        so = (C.c_int64 * self.n)()
+        jo = (C.c_int64 * self.n)()
+        _check(lib.smc_batch_offsets(d, self.n, Larr, so, jo))
+        self.spin_offsets = [int(v) for v in so]
+        self.coupling_offsets = [int(v) for v in jo]
+        kind = _kind(J_kind)
+        self.J_kind = kind
+        self.spins = torch.zeros(sb, dtype=torch.int8, device=self.device)
+        if spins is not None:
+            self.spins.copy_(spins.to(self.device, torch.int8).view(-1))
+            init = "keep"
+        self.J = torch.zeros(jb, dtype=torch.int8, device=self.device) if kind == J_PM else None
+        keep_J = 0
+        if J is not None and self.J is not None:
+            self.J.copy_(J.to(self.device, torch.int8).view(-1))
+            keep_J = 1
+        self.workspace = torch.empty(wb + 256, dtype=torch.uint8, device=self.device)
+        ws = self.workspace.data_ptr() + (-self.workspace.data_ptr()) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        init_k = {"hot": INIT_HOT, "cold": INIT_COLD, "keep": INIT_KEEP}[init]
+        betas = (C.c_double * self.n)(*self.beta)
+        reps = None if replica is None else (C.c_uint32 * self.n)(*[int(v) for v in replica])
+        self._h = C.c_void_p()
+        _check(lib.smc_batch_init(C.byref(self._h), d, kind, seed & 0xFFFFFFFFFFFFFFFF, float(J0),
+                                  init_k, keep_J, self.n, Larr, betas, reps,
+                                  C.c_void_p(self.spins.data_ptr()),
+                                  None if self.J is None else C.c_void_p(self.J.data_ptr()),
+                                  C.c_void_p(ws), wb, C.c_void_p(self.stream.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().smc_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def spins_of(self, r: int):
+        N = self.L[r] ** self.d
+        o = self.spin_offsets[r]
+        return self.spins[o:o + N].view(2, N // 2)
+
+    def couplings_of(self, r: int):
+        N = self.L[r] ** self.d
+        o = self.coupling_offsets[r]
+        return self.J[o:o + self.d * N].view(self.d, 2, N // 2)
+
+    def sweep(self, n_sweeps: int, obs=None):
+        """n_sweeps sweeps of every lattice; with obs (device int64 tensor of
+        [n_lattices, 8]) the final observables of each lattice are written."""
+        ptr = None
+        if obs is not None:
+            assert obs.is_cuda and obs.numel() >= 8 * self.n
+            ptr = C.c_void_p(obs.data_ptr())
+        _check(load_library().smc_batch_sweep(self._h, int(n_sweeps), ptr))
+
+    def autotune(self):
+        th = C.c_int32()
+        lf = C.c_int32()
+        _check(load_library().smc_batch_autotune(self._h, C.byref(th), C.byref(lf)))
+        return int(th.value), bool(lf.value)
+
+    def use_graph(self, enable: bool = True):
+        _check(load_library().smc_batch_use_graph(self._h, 1 if enable else 0))
+
+    @property
+    def t(self) -> int:
+        v = C.c_uint64()
+        _check(load_library().smc_batch_get_sweep_index(self._h, C.byref(v)))
+        return int(v.value)
+
+    @t.setter
+    def t(self, value: int):
+        _check(load_library().smc_batch_set_sweep_index(self._h, int(value)))
 
 
 def version() -> str:

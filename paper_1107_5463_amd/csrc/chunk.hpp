@@ -144,22 +144,25 @@ __device__ __forceinline__ void resolve_ties(const IsingTable& tab, const RngKey
   }
 }
 
-// Per-byte decision for 4 sites testing the threshold byte only (classes that
-// always accept carry threshold byte 0xFF and refinement fraction 2^24).
-// Returns the spin word after the flips decided by the prefix bytes; tie7
-// flags (bit 7) the bytes where the prefix may equal the threshold byte: every
-// exact tie, plus occasional false alarms directly above one, which the slow
-// path re-checks.
-__device__ __forceinline__ uint32_t decide4_fast(uint32_t th_lo, uint32_t th_hi, uint32_t own,
-                                                 uint32_t k, uint32_t P, uint32_t& tie7) {
+// Per-byte decision for 4 sites testing the threshold byte only.  Classes
+// that always accept carry threshold byte 0xFF and refinement fraction 2^24,
+// and are also flagged in Al: they flip whatever the prefix.  Returns the spin
+// word after the flips decided by the prefix bytes; tie7 flags (bit 7) the
+// bytes of refusable classes whose prefix may equal the threshold byte -- every
+// exact tie (2^-8 of the uphill attempts) plus occasional false alarms directly
+// above one, which the slow path re-checks.
+__device__ __forceinline__ uint32_t decide4_fast(uint32_t th_lo, uint32_t th_hi, uint32_t al_lo,
+                                                 uint32_t al_hi, uint32_t own, uint32_t k,
+                                                 uint32_t P, uint32_t& tie7) {
   const uint32_t Th = __builtin_amdgcn_perm(th_hi, th_lo, k);
+  const uint32_t Al = __builtin_amdgcn_perm(al_hi, al_lo, k);
   const uint32_t x = P ^ Th;
   const uint32_t dlow = (P | kHigh) - (Th & ~kHigh);
   const uint32_t ge = (x & P) | (~x & dlow);  // bit 7 of each byte: P >= Th
   // 0xFF in every byte whose bit 7 of ge is set (sign-replicating selectors)
   const uint32_t rej = __builtin_amdgcn_perm(ge, ge << 8, 0x0B090A08u);
-  tie7 = (x - kOnes) & ~x & kHigh;
-  return own ^ (~rej & 0xFEFEFEFEu);
+  tie7 = (x - kOnes) & ~x & ~Al & kHigh;
+  return own ^ ((~rej | Al) & 0xFEFEFEFEu);
 }
 
 // Deferred tie resolutions of one lane (at most 4 held; more are resolved on
@@ -183,6 +186,34 @@ __device__ __forceinline__ void counts2d(const Chunk& o, const Chunk& ctr, const
   }
 }
 
+// The refinement fractions of the 7 classes held in scalar registers, as
+// named scalars: with an array the compiler turns the select chain back into
+// an indexed memory load.
+struct FracRegs {
+  uint32_t f0, f1, f2, f3, f4, f5, f6;
+};
+
+__device__ __forceinline__ FracRegs frac_regs(const IsingTable& tab) {
+  FracRegs r;
+  r.f0 = __builtin_amdgcn_readfirstlane(tab.frac[0]);
+  r.f1 = __builtin_amdgcn_readfirstlane(tab.frac[1]);
+  r.f2 = __builtin_amdgcn_readfirstlane(tab.frac[2]);
+  r.f3 = __builtin_amdgcn_readfirstlane(tab.frac[3]);
+  r.f4 = __builtin_amdgcn_readfirstlane(tab.frac[4]);
+  r.f5 = __builtin_amdgcn_readfirstlane(tab.frac[5]);
+  r.f6 = __builtin_amdgcn_readfirstlane(tab.frac[6]);
+  return r;
+}
+
+__device__ __forceinline__ uint32_t frac_sel(const FracRegs& r, uint32_t k) {
+  const uint32_t a = (k & 1) ? r.f1 : r.f0;
+  const uint32_t b = (k & 1) ? r.f3 : r.f2;
+  const uint32_t c = (k & 1) ? r.f5 : r.f4;
+  const uint32_t lo = (k & 2) ? b : a;
+  const uint32_t hi = (k & 2) ? r.f6 : c;
+  return (k & 4) ? hi : lo;
+}
+
 // Exact 16-bit mask (bit 4w+b) of sites whose prefix byte equals the threshold
 // byte of their class.
 __device__ __forceinline__ uint32_t exact_ties16(uint32_t th_lo, uint32_t th_hi,
@@ -197,40 +228,116 @@ __device__ __forceinline__ uint32_t exact_ties16(uint32_t th_lo, uint32_t th_hi,
   return m;
 }
 
-// Metropolis update of one chunk given its unsatisfied-bond counts: one
-// Philox block for the 16 prefix bytes; the refinement draw only for the rare
-// exact ties, resolved on the spot.
-__device__ __forceinline__ Chunk update_chunk(const IsingTable& tab, const RngKey& key, uint32_t t,
-                                              uint32_t c, uint32_t jbase, const Chunk& o,
-                                              const uint32_t kk[4]) {
-  const Rand4 rp = philox(jbase >> 4, t, key.replica, tag(c, kIsingPrefix), key.k0, key.k1);
-  uint32_t nw[4], anytie = 0;
-#pragma unroll
-  for (int w = 0; w < 4; ++w) {
-    uint32_t t7;
-    nw[w] = decide4_fast(tab.th_lo, tab.th_hi, o.w[w], kk[w], rp.w[w], t7);
-    anytie |= t7;
+// Threshold bytes, always-accept flags and refinement fractions pinned in
+// scalar registers.
+struct TabRegs {
+  uint32_t th_lo, th_hi, al_lo, al_hi;
+  FracRegs fr;
+};
+
+__device__ __forceinline__ TabRegs tab_regs(const IsingTable& tab) {
+  TabRegs r;
+  r.th_lo = __builtin_amdgcn_readfirstlane(tab.th_lo);
+  r.th_hi = __builtin_amdgcn_readfirstlane(tab.th_hi);
+  r.al_lo = __builtin_amdgcn_readfirstlane(tab.al_lo);
+  r.al_hi = __builtin_amdgcn_readfirstlane(tab.al_hi);
+  r.fr = frac_regs(tab);
+  return r;
+}
+
+// Flip byte b of word w of a chunk's new spins (static register indices).
+__device__ __forceinline__ void flip_byte(uint32_t nw[4], uint32_t w, uint32_t b) {
+  const uint32_t f = 0xFEu << (8 * b);
+  nw[0] ^= w == 0 ? f : 0u;
+  nw[1] ^= w == 1 ? f : 0u;
+  nw[2] ^= w == 2 ? f : 0u;
+  nw[3] ^= w == 3 ? f : 0u;
+}
+
+// Queue an exact tie for the end of the band, or resolve it now if the queue
+// is full.  Returns true if it was resolved now and the move accepted.
+__device__ __forceinline__ bool queue_tie(PendingTies& pend, const TabRegs& tab, const RngKey& key,
+                                          uint32_t t, uint32_t c, uint32_t js, uint32_t k) {
+  if (pend.n < 4) {
+    pend.j[0] = pend.n == 0 ? js : pend.j[0];
+    pend.j[1] = pend.n == 1 ? js : pend.j[1];
+    pend.j[2] = pend.n == 2 ? js : pend.j[2];
+    pend.j[3] = pend.n == 3 ? js : pend.j[3];
+    pend.k |= k << (4 * pend.n);
+    pend.n += 1;
+    return false;
   }
-  if (anytie) {
-    uint32_t m = exact_ties16(tab.th_lo, tab.th_hi, kk, rp);
+  const Rand4 rr = philox(js, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
+  return (rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k);
+}
+
+// Visit the tie candidates of one chunk: exact ties (prefix byte == threshold
+// byte of the site's class) are resolved at once (DEFER = false) or queued.
+template <bool DEFER>
+__device__ __forceinline__ void handle_ties(const TabRegs& tab, const RngKey& key, uint32_t t,
+                                            uint32_t c, uint32_t jbase, const uint32_t kk[4],
+                                            const Rand4& rp, const uint32_t tie7[4],
+                                            uint32_t nw[4], PendingTies& pend) {
+#pragma unroll
+  for (uint32_t w = 0; w < 4; ++w) {
+    uint32_t m = tie7[w];
     while (m) {
-      const uint32_t idx = __builtin_ctz(m);
+      const uint32_t b = __builtin_ctz(m) >> 3;
       m &= m - 1;
-      const uint32_t w = idx >> 2, b = idx & 3u;
-      const uint32_t kw = w == 0 ? kk[0] : (w == 1 ? kk[1] : (w == 2 ? kk[2] : kk[3]));
-      const Rand4 rr = philox(jbase + idx, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
-      if ((rr.w[0] & 0xFFFFFFu) < frac_of(tab, (kw >> (8 * b)) & 0xFu)) {
-        const uint32_t f = 0xFEu << (8 * b);
-        nw[0] ^= w == 0 ? f : 0u;
-        nw[1] ^= w == 1 ? f : 0u;
-        nw[2] ^= w == 2 ? f : 0u;
-        nw[3] ^= w == 3 ? f : 0u;
+      const uint32_t k = (kk[w] >> (8 * b)) & 0xFu;
+      if (((rp.w[w] >> (8 * b)) & 0xFFu) != table_byte(tab.th_lo, tab.th_hi, k)) continue;
+      const uint32_t js = jbase + 4 * w + b;
+      bool acc;
+      if (DEFER) {
+        acc = queue_tie(pend, tab, key, t, c, js, k);
+      } else {
+        const Rand4 rr = philox(js, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
+        acc = (rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k);
       }
+      if (acc) flip_byte(nw, w, b);
     }
   }
+}
+
+// Metropolis update of one chunk given its unsatisfied-bond counts: one
+// Philox block for the 16 prefix bytes; the refinement draw only for the rare
+// exact ties, resolved on the spot (DEFER = false) or queued in pend.
+template <bool DEFER>
+__device__ __forceinline__ Chunk update_chunk(const TabRegs& tab, const RngKey& key, uint32_t t,
+                                              uint32_t c, uint32_t jbase, const Chunk& o,
+                                              const uint32_t kk[4], PendingTies& pend) {
+  const Rand4 rp = philox(jbase >> 4, t, key.replica, tag(c, kIsingPrefix), key.k0, key.k1);
+  uint32_t nw[4], tie7[4], anytie = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    nw[w] = decide4_fast(tab.th_lo, tab.th_hi, tab.al_lo, tab.al_hi, o.w[w], kk[w], rp.w[w], tie7[w]);
+    anytie |= tie7[w];
+  }
+  if (anytie) handle_ties<DEFER>(tab, key, t, c, jbase, kk, rp, tie7, nw, pend);
   Chunk n;
   n.w[0] = nw[0]; n.w[1] = nw[1]; n.w[2] = nw[2]; n.w[3] = nw[3];
   return n;
+}
+
+// Resolve a lane's queued ties against its own colour plane (bytes of plane
+// `own` that no other lane of the launch touches).  Returns the change of the
+// unsatisfied-bond sum of the flipped sites' energy and of their spin sum
+// through dE / dM (for a fused measurement).
+template <int D>
+__device__ __forceinline__ void resolve_pending(const PendingTies& pend, const TabRegs& tab,
+                                                const RngKey& key, uint32_t t, uint32_t c,
+                                                int8_t* own, int64_t& dE, int64_t& dM) {
+  for (uint32_t e = 0; e < pend.n; ++e) {
+    const uint32_t js = e == 0 ? pend.j[0] : (e == 1 ? pend.j[1] : (e == 2 ? pend.j[2] : pend.j[3]));
+    const uint32_t k = (pend.k >> (4 * e)) & 0xFu;
+    const Rand4 rr = philox(js, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
+    if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) {
+      const int8_t v = own[js];
+      own[js] = (int8_t)(-v);
+      dE += 4 * (int64_t)(D - (int)k);  // all 2d bonds of the site change sign
+      dM -= 2 * (int64_t)v;
+    }
+  }
 }
 
 // Sum of the +-1 spins of a chunk.

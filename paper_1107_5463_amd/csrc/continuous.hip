@@ -11,7 +11,7 @@
 // (seed, t, replica, colour): XY block j>>1 words 2(j&1) (accept) and
 // 2(j&1)+1 (proposal); Heisenberg block j words 0 (accept), 1, 2.  An XY
 // thread updates the two sites of one block.
-#include "kernels.hpp"
+#include "chunk.hpp"
 
 namespace smc {
 
@@ -29,62 +29,107 @@ __device__ __forceinline__ void sincos_f(float x, float* s, float* c) {
   }
 }
 
+// Site geometry of a row-based launch: block -> (plane row r = y + L z,
+// segment), lane -> in-row index jx.  The row decomposition is a scalar
+// division per block; neighbours are row offsets plus jx or jx +- 1.
+struct RowSite {
+  int64_t j;          // in-colour index of the site
+  int64_t row_ym, row_yp, row_zm, row_zp;  // plane offsets of the neighbour rows (+ jx)
+  int64_t xp, xm;     // plane offsets of the x+1 / x-1 neighbours
+  int32_t jx;
+};
+
+template <int D>
+__device__ __forceinline__ RowSite row_site(const Geom& g, uint32_t c, uint32_t r, int32_t jx) {
+  const int32_t L = g.L, R = g.R;
+  const int32_t y = (int32_t)(r % (uint32_t)L), z = (int32_t)(r / (uint32_t)L);  // uniform
+  const int32_t p = (int32_t)((c + (uint32_t)y + (uint32_t)z) & 1u);
+  RowSite s;
+  s.jx = jx;
+  const int64_t rowoff = (int64_t)r * R;
+  s.j = rowoff + jx;
+  // x+1 / x-1 neighbours: in-row indices jx + p and jx + p - 1 (periodic)
+  const int32_t jxp = jx + p == R ? 0 : jx + p;
+  const int32_t jxm = jx + p - 1 < 0 ? R - 1 : jx + p - 1;
+  s.xp = rowoff + jxp;
+  s.xm = rowoff + jxm;
+  const int32_t ym = y == 0 ? L - 1 : y - 1, yp = y + 1 == L ? 0 : y + 1;
+  s.row_ym = ((int64_t)z * L + ym) * R + jx;
+  s.row_yp = ((int64_t)z * L + yp) * R + jx;
+  s.row_zm = s.row_zp = 0;
+  if (D == 3) {
+    const int32_t zm = z == 0 ? L - 1 : z - 1, zp = z + 1 == L ? 0 : z + 1;
+    s.row_zm = ((int64_t)zm * L + y) * R + jx;
+    s.row_zp = ((int64_t)zp * L + y) * R + jx;
+  }
+  return s;
+}
+
+// Coupling of the bond from site (cc, jj) to its +mu neighbour.
+template <int JK>
+__device__ __forceinline__ float bond(const void* J, float J0, int64_t Nh, int mu, uint32_t cc,
+                                      int64_t jj) {
+  if (JK == 1) return J0 * (float)((const int8_t*)J)[((int64_t)mu * 2 + cc) * Nh + jj];
+  if (JK == 2) return ((const float*)J)[((int64_t)mu * 2 + cc) * Nh + jj];
+  return J0;
+}
+
 // Local field h = sum_mu [J(i,mu) s_{i+mu} + J(i-mu,mu) s_{i-mu}] in the order
 // +x, -x, +y, -y, +z, -z.
 template <int D, int N, int JK>
-__device__ __forceinline__ void field(const Geom& g, const float* __restrict__ s, const void* J,
-                                      float J0, uint32_t c, int64_t j, int32_t x, int32_t y,
-                                      int32_t z, float h[3]) {
+__device__ __forceinline__ void field_row(const Geom& g, const float* __restrict__ s, const void* J,
+                                          float J0, uint32_t c, const RowSite& st, float h[3]) {
   const int64_t Nh = g.Nh, Nfull = 2 * Nh;
   const float* oth = s + (int64_t)(1 - c) * Nh;
+  const int64_t ip[3] = {st.xp, st.row_yp, st.row_zp};
+  const int64_t im[3] = {st.xm, st.row_ym, st.row_zm};
   h[0] = h[1] = h[2] = 0.0f;
 #pragma unroll
   for (int mu = 0; mu < D; ++mu) {
-    int32_t xp = x, yp = y, zp = z, xm = x, ym = y, zm = z;
-    if (mu == 0) { xp = wrap(x + 1, g.L); xm = wrap(x - 1, g.L); }
-    if (mu == 1) { yp = wrap(y + 1, g.L); ym = wrap(y - 1, g.L); }
-    if (mu == 2) { zp = wrap(z + 1, g.L); zm = wrap(z - 1, g.L); }
-    const int64_t ip = plane_index(g, xp, yp, zp);
-    const int64_t im = plane_index(g, xm, ym, zm);
-    float jp = J0, jm = J0;
-    if (JK == 1) {
-      const int8_t* Jb = (const int8_t*)J;
-      jp = J0 * (float)Jb[((int64_t)mu * 2 + c) * Nh + j];
-      jm = J0 * (float)Jb[((int64_t)mu * 2 + (1 - c)) * Nh + im];
-    } else if (JK == 2) {
-      const float* Jf = (const float*)J;
-      jp = Jf[((int64_t)mu * 2 + c) * Nh + j];
-      jm = Jf[((int64_t)mu * 2 + (1 - c)) * Nh + im];
-    }
+    const float jp = bond<JK>(J, J0, Nh, mu, c, st.j);
+    const float jm = bond<JK>(J, J0, Nh, mu, 1 - c, im[mu]);
 #pragma unroll
-    for (int k = 0; k < N; ++k) h[k] += jp * oth[k * Nfull + ip];
+    for (int k = 0; k < N; ++k) h[k] += jp * oth[k * Nfull + ip[mu]];
 #pragma unroll
-    for (int k = 0; k < N; ++k) h[k] += jm * oth[k * Nfull + im];
+    for (int k = 0; k < N; ++k) h[k] += jm * oth[k * Nfull + im[mu]];
   }
 }
 
-template <int D, int JK, bool FAST>
+// Blocks of 256 lanes over (row, segment); segments per row = ceil(R / (256 spt)).
+__device__ __forceinline__ void row_block(uint32_t segs, uint32_t& r, uint32_t& seg) {
+  const uint32_t b = xcd_remap(blockIdx.x, gridDim.x);
+  r = b / segs;  // wave-uniform: scalar division
+  seg = b - r * segs;
+}
+
+// XY.  PAIRED (L/2 even): a lane updates the two in-row sites (jx, jx + 1)
+// that share Philox block j >> 1; otherwise one site per lane, drawing its
+// words 2(j&1), 2(j&1)+1 of block j >> 1.
+template <int D, int JK, bool FAST, bool PAIRED>
 __global__ __launch_bounds__(256) void xy_kernel(const Geom g, const RngKey key,
                                                  const void* __restrict__ J, const float J0,
                                                  const float beta, const float delta,
-                                                 float* __restrict__ s, const uint32_t t,
-                                                 const uint32_t c) {
-  const int64_t pair = (int64_t)blockIdx.x * 256 + threadIdx.x;
+                                                 const uint32_t segs, float* __restrict__ s,
+                                                 const uint32_t t, const uint32_t c) {
+  uint32_t r, seg;
+  row_block(segs, r, seg);
+  constexpr int SPL = PAIRED ? 2 : 1;  // sites per lane
+  const int32_t jx0 = (int32_t)(seg * 256 * SPL + SPL * threadIdx.x);
+  if (jx0 >= g.R) return;
   const int64_t Nh = g.Nh, Nfull = 2 * Nh;
-  if (2 * pair >= Nh) return;
-  const Rand4 r = philox((uint32_t)pair, t, key.replica, tag(c, kContinuous), key.k0, key.k1);
   float* own = s + (int64_t)c * Nh;
+  const int64_t j0 = (int64_t)r * g.R + jx0;
+  const Rand4 rnd = philox((uint32_t)(j0 >> 1), t, key.replica, tag(c, kContinuous), key.k0,
+                           key.k1);
 #pragma unroll
-  for (int half = 0; half < 2; ++half) {
-    const int64_t j = 2 * pair + half;
-    if (j >= Nh) break;
-    int32_t x, y, z;
-    site_coords(g, c, j, x, y, z);
+  for (int half = 0; half < SPL; ++half) {
+    const RowSite st = row_site<D>(g, c, r, jx0 + half);
     float h[3];
-    field<D, 2, JK>(g, s, J, J0, c, j, x, y, z, h);
-    const float s0 = own[j], s1 = own[Nfull + j];
-    const uint32_t wacc = half ? r.w[2] : r.w[0];
-    const uint32_t wprop = half ? r.w[3] : r.w[1];
+    field_row<D, 2, JK>(g, s, J, J0, c, st, h);
+    const float s0 = own[st.j], s1 = own[Nfull + st.j];
+    const bool odd = PAIRED ? half == 1 : (st.j & 1) != 0;
+    const uint32_t wacc = odd ? rnd.w[2] : rnd.w[0];
+    const uint32_t wprop = odd ? rnd.w[3] : rnd.w[1];
     const float D_ = delta * (2.0f * u01f(wprop) - 1.0f);
     float sD, cD;
     sincos_f<FAST>(D_, &sD, &cD);
@@ -93,8 +138,8 @@ __global__ __launch_bounds__(256) void xy_kernel(const Geom g, const RngKey key,
     const float dE = -((n0 - s0) * h[0] + (n1 - s1) * h[1]);
     const bool accept = dE <= 0.0f || u01f(wacc) < exp_f<FAST>(-beta * dE);
     if (accept) {
-      own[j] = n0;
-      own[Nfull + j] = n1;
+      own[st.j] = n0;
+      own[Nfull + st.j] = n1;
     }
   }
 }
@@ -103,21 +148,22 @@ template <int D, int JK, bool FAST>
 __global__ __launch_bounds__(256) void heis_kernel(const Geom g, const RngKey key,
                                                    const void* __restrict__ J, const float J0,
                                                    const float beta, const float omc,
-                                                   float* __restrict__ s, const uint32_t t,
-                                                   const uint32_t c) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+                                                   const uint32_t segs, float* __restrict__ s,
+                                                   const uint32_t t, const uint32_t c) {
+  uint32_t r, seg;
+  row_block(segs, r, seg);
+  const int32_t jx = (int32_t)(seg * 256 + threadIdx.x);
+  if (jx >= g.R) return;
   const int64_t Nh = g.Nh, Nfull = 2 * Nh;
-  if (j >= Nh) return;
-  const Rand4 r = philox((uint32_t)j, t, key.replica, tag(c, kContinuous), key.k0, key.k1);
   float* own = s + (int64_t)c * Nh;
-  int32_t x, y, z;
-  site_coords(g, c, j, x, y, z);
+  const RowSite st = row_site<D>(g, c, r, jx);
+  const Rand4 rnd = philox((uint32_t)st.j, t, key.replica, tag(c, kContinuous), key.k0, key.k1);
   float h[3];
-  field<D, 3, JK>(g, s, J, J0, c, j, x, y, z, h);
-  const float sv[3] = {own[j], own[Nfull + j], own[2 * Nfull + j]};
-  const float ca = 1.0f - u01f(r.w[1]) * omc;
+  field_row<D, 3, JK>(g, s, J, J0, c, st, h);
+  const float sv[3] = {own[st.j], own[Nfull + st.j], own[2 * Nfull + st.j]};
+  const float ca = 1.0f - u01f(rnd.w[1]) * omc;
   const float sa = sqrtf(fmaxf(0.0f, 1.0f - ca * ca));
-  const float ph = 6.28318530717958647692f * u01f(r.w[2]);
+  const float ph = 6.28318530717958647692f * u01f(rnd.w[2]);
   // frame axis: smallest |s_k|, lowest k on ties
   const float a0 = fabsf(sv[0]), a1 = fabsf(sv[1]), a2 = fabsf(sv[2]);
   int k = 0;
@@ -139,35 +185,39 @@ __global__ __launch_bounds__(256) void heis_kernel(const Geom g, const RngKey ke
 #pragma unroll
   for (int q = 0; q < 3; ++q) nv[q] = ca * sv[q] + sa * (cph * e1[q] + sph * e2[q]);
   const float dE = -((nv[0] - sv[0]) * h[0] + (nv[1] - sv[1]) * h[1] + (nv[2] - sv[2]) * h[2]);
-  const bool accept = dE <= 0.0f || u01f(r.w[0]) < exp_f<FAST>(-beta * dE);
+  const bool accept = dE <= 0.0f || u01f(rnd.w[0]) < exp_f<FAST>(-beta * dE);
   if (accept) {
-    own[j] = nv[0];
-    own[Nfull + j] = nv[1];
-    own[2 * Nfull + j] = nv[2];
+    own[st.j] = nv[0];
+    own[Nfull + st.j] = nv[1];
+    own[2 * Nfull + st.j] = nv[2];
   }
 }
 
 template <int D, int JK>
 static hipError_t launch_cont_dj(const ContLaunch& a, float* s, uint32_t t, uint32_t c,
                                  hipStream_t st) {
+  const bool paired = a.n == 2 && (a.g.R % 2) == 0;
+  const uint32_t per_block = paired ? 512u : 256u;  // sites per block
+  const uint32_t segs = ((uint32_t)a.g.R + per_block - 1) / per_block;
+  const dim3 grid((unsigned)((uint64_t)a.g.rows * segs));
+#define SMC_XY(F, P)                                                                        \
+  hipLaunchKernelGGL((xy_kernel<D, JK, F, P>), grid, dim3(256), 0, st, a.g, a.key, a.J, a.J0, \
+                     a.beta, a.delta, segs, s, t, c)
   if (a.n == 2) {
-    const int64_t pairs = (a.g.Nh + 1) / 2;
-    const dim3 grid((unsigned)((pairs + 255) / 256));
-    if (a.fast_math)
-      hipLaunchKernelGGL((xy_kernel<D, JK, true>), grid, dim3(256), 0, st, a.g, a.key, a.J, a.J0,
-                         a.beta, a.delta, s, t, c);
-    else
-      hipLaunchKernelGGL((xy_kernel<D, JK, false>), grid, dim3(256), 0, st, a.g, a.key, a.J,
-                         a.J0, a.beta, a.delta, s, t, c);
+    if (a.fast_math) {
+      if (paired) SMC_XY(true, true); else SMC_XY(true, false);
+    } else {
+      if (paired) SMC_XY(false, true); else SMC_XY(false, false);
+    }
   } else {
-    const dim3 grid((unsigned)((a.g.Nh + 255) / 256));
     if (a.fast_math)
       hipLaunchKernelGGL((heis_kernel<D, JK, true>), grid, dim3(256), 0, st, a.g, a.key, a.J,
-                         a.J0, a.beta, a.one_minus_cos_cap, s, t, c);
+                         a.J0, a.beta, a.one_minus_cos_cap, segs, s, t, c);
     else
       hipLaunchKernelGGL((heis_kernel<D, JK, false>), grid, dim3(256), 0, st, a.g, a.key, a.J,
-                         a.J0, a.beta, a.one_minus_cos_cap, s, t, c);
+                         a.J0, a.beta, a.one_minus_cos_cap, segs, s, t, c);
   }
+#undef SMC_XY
   return hipGetLastError();
 }
 

@@ -15,6 +15,8 @@
 // result is bit-identical to the two-pass schedule.  With MEASURE the energy
 // and magnetisation of the new state are reduced on the way (every bond has
 // exactly one colour-1 end).
+#include <type_traits>
+
 #include "chunk.hpp"
 #include "reduce.hpp"
 
@@ -22,86 +24,77 @@ namespace smc {
 
 template <bool MEASURE>
 __global__ __launch_bounds__(1024) void ising_fused2d_kernel(const Geom g, const RngKey key,
-                                                             const IsingTable tab,
+                                                             const IsingTable table,
                                                              const uint32_t H,
                                                              const int8_t* __restrict__ A,
                                                              int8_t* __restrict__ B,
                                                              const uint32_t t,
                                                              Partial* __restrict__ parts) {
-  __shared__ uint32_t edge[2][2][1024];  // [buffer][old colour-1 row, new colour-0 row][lane]
-  const uint32_t band = xcd_remap(blockIdx.x, gridDim.x);
+  __shared__ uint32_t edge[2][2][1024];  // [step parity][old colour-1 row, new colour-0 row][lane]
+  const int8_t* A0 = A;
+  const int8_t* A1g = A + g.Nh;
+  int8_t* B0 = B;
+  int8_t* B1 = B + g.Nh;
+  const uint32_t R = (uint32_t)g.R;
+  const uint32_t L = (uint32_t)g.L;
   const uint32_t q = threadIdx.x;
   const uint32_t Q = blockDim.x;
-  const uint32_t L = (uint32_t)g.L;
-  const int64_t R = g.R, Nh = g.Nh;
-  const int8_t* A0 = A;
-  const int8_t* A1 = A + Nh;
-  int8_t* B0 = B;
-  int8_t* B1 = B + Nh;
-  const int64_t col = 16 * (int64_t)q;
-  const uint32_t qn = q + 1 == Q ? 0u : q + 1, qp = q == 0 ? Q - 1 : q - 1;
-  const uint32_t y0 = band * H;
-  auto wr = [&](int64_t y) -> uint32_t { return (uint32_t)(y < 0 ? y + L : (y >= L ? y - L : y)); };
-  auto off = [&](uint32_t y) -> int64_t { return (int64_t)y * R + col; };
-  auto publish = [&](uint32_t buf, uint32_t kind, uint32_t p, const Chunk& c) {
-    edge[buf][kind][q] = p ? c.w[0] : c.w[3];
-  };
-  auto neighbour_edge = [&](uint32_t buf, uint32_t kind, uint32_t p) -> uint32_t {
-    return edge[buf][kind][p ? qn : qp];
-  };
+  const uint32_t col = 16 * q;
+  const uint32_t qn = q + 1 == Q ? 0u : q + 1;
+  const uint32_t qp = q == 0 ? Q - 1 : q - 1;
+  const TabRegs tab = tab_regs(table);
+  const uint32_t band = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t y0 = band * H;  // a multiple of 4
+  // offset of plane row y (0 <= y < 2L) for this lane's chunk column
+  auto frow = [&](uint32_t y) -> uint32_t { return (y >= L ? y - L : y) * R + col; };
 
-  // prologue: new colour-0 row y0 - 1 (formed, not stored)
-  const uint32_t ym1 = wr((int64_t)y0 - 1);
-  Chunk a1m = ld16(A1 + off(wr((int64_t)y0 - 2)));
-  Chunk a1c = ld16(A1 + off(ym1));
-  Chunk a1p = ld16(A1 + off(y0));
-  Chunk a0c = ld16(A0 + off(ym1));
-  Chunk n0m1, n0m2;
-  {
-    const uint32_t p = ym1 & 1u;
-    publish(1, 0, p, a1c);
-    __syncthreads();
-    const Chunk sh = p ? shift_next(a1c, neighbour_edge(1, 0, p)) : shift_prev(a1c, neighbour_edge(1, 0, p));
-    uint32_t kk[4];
-    counts2d(a0c, a1c, sh, a1m, a1p, kk);
-    n0m1 = update_chunk(tab, key, t, 0u, (uint32_t)off(ym1), a0c, kk);
-  }
-  // slide the old colour-1 window to rows y0-1, y0, y0+1
-  a1m = a1c;
-  a1c = a1p;
-  a1p = ld16(A1 + off(wr((int64_t)y0 + 1)));
-  a0c = ld16(A0 + off(y0));
-  n0m2 = n0m1;  // unused before it is overwritten
-
+  // Rings: A1[y & 3] old colour-1 row y, A0[y & 1] old colour-0 row y,
+  // N0[y & 3] new colour-0 row y.
+  Chunk A1[4], A0r[2], N0[4];
   int64_t Esum = 0, Msum = 0;
-  for (uint32_t i = 0; i <= H; ++i) {
-    const uint32_t y = wr((int64_t)y0 + i);
-    const uint32_t p = y & 1u;  // parity of colour 0 at row y and of colour 1 at row y-1
-    const uint32_t buf = i & 1u;
-    // next step's rows, one ahead
-    const Chunk a1n = ld16(A1 + off(wr((int64_t)y + 2)));
-    const Chunk a0n = ld16(A0 + off(wr((int64_t)y + 1)));
-    publish(buf, 0, p, a1c);
-    publish(buf, 1, p, n0m1);
+  // colour-1 ties are queued (nothing in this launch reads the new colour 1);
+  // colour-0 ties are resolved at once (the new colour 0 feeds colour 1)
+  PendingTies pend;
+  pend.k = 0;
+  pend.n = 0;
+  pend.j[0] = pend.j[1] = pend.j[2] = pend.j[3] = 0;
+
+  // One step at row y = y0 + i (y & 3 == PH): new colour 0 at row y, then
+  // (i >= 1) new colour 1 at row y - 1; then refill the dead ring slots with
+  // the old colour-1 row y + 3 and the old colour-0 row y + 2.
+  auto step = [&](auto phase, uint32_t y, bool store0, bool do1) {
+    constexpr int PH = decltype(phase)::value;
+    constexpr uint32_t p = PH & 1;    // parity of colour 0 at y = parity of colour 1 at y - 1
+    constexpr uint32_t buf = PH & 1;  // LDS buffer of this step (steps alternate)
+    const Chunk& a1m = A1[(PH + 3) & 3];
+    const Chunk& a1c = A1[PH];
+    const Chunk& a1p = A1[(PH + 1) & 3];
+    const Chunk& a0c = A0r[PH & 1];
+    const Chunk& n0m1 = N0[(PH + 3) & 3];
+    const Chunk& n0m2 = N0[(PH + 2) & 3];
+    edge[buf][0][q] = p ? a1c.w[0] : a1c.w[3];
+    edge[buf][1][q] = p ? n0m1.w[0] : n0m1.w[3];
     __syncthreads();
-    const uint32_t e_a = neighbour_edge(buf, 0, p);
-    const uint32_t e_n = neighbour_edge(buf, 1, p);
+    const uint32_t e_a = edge[buf][0][p ? qn : qp];
+    const uint32_t e_n = edge[buf][1][p ? qn : qp];
     // new colour 0, row y
     const Chunk sha = p ? shift_next(a1c, e_a) : shift_prev(a1c, e_a);
     uint32_t kk[4];
     counts2d(a0c, a1c, sha, a1m, a1p, kk);
-    const Chunk n0c = update_chunk(tab, key, t, 0u, (uint32_t)off(y), a0c, kk);
-    if (i < H) {
-      st16(B0 + off(y), n0c.w);
+    const uint32_t off0 = frow(y);
+    N0[PH] = update_chunk<false>(tab, key, t, 0u, off0, a0c, kk, pend);
+    const Chunk& n0c = N0[PH];
+    if (store0) {
+      st16(B0 + off0, n0c.w);
       if (MEASURE) Msum += chunk_spin_sum(n0c);
     }
     // new colour 1, row y - 1
-    if (i >= 1) {
-      const uint32_t yb = wr((int64_t)y - 1);
+    if (do1) {
+      const uint32_t off1 = frow(y + L - 1);
       const Chunk shn = p ? shift_next(n0m1, e_n) : shift_prev(n0m1, e_n);
       counts2d(a1m, n0m1, shn, n0m2, n0c, kk);
-      const Chunk n1 = update_chunk(tab, key, t, 1u, (uint32_t)off(yb), a1m, kk);
-      st16(B1 + off(yb), n1.w);
+      const Chunk n1 = update_chunk<true>(tab, key, t, 1u, off1, a1m, kk, pend);
+      st16(B1 + off1, n1.w);
       if (MEASURE) {
         uint32_t kn[4];
         counts2d(n1, n0m1, shn, n0m2, n0c, kn);
@@ -109,27 +102,57 @@ __global__ __launch_bounds__(1024) void ising_fused2d_kernel(const Geom g, const
         Msum += chunk_spin_sum(n1);
       }
     }
-    n0m2 = n0m1;
-    n0m1 = n0c;
-    a1m = a1c;
-    a1c = a1p;
-    a1p = a1n;
-    a0c = a0n;
+    A1[(PH + 3) & 3] = ld16(A1g + frow(y + 3));
+    A0r[PH & 1] = ld16(A0 + frow(y + 2));
+  };
+
+  A1[2] = ld16(A1g + frow(y0 + L - 2));  // row y0 - 2 (frow takes rows < 2L)
+  A1[3] = ld16(A1g + frow(y0 + L - 1));
+  A1[0] = ld16(A1g + frow(y0));
+  A1[1] = ld16(A1g + frow(y0 + 1));
+  A0r[1] = ld16(A0 + frow(y0 + L - 1));
+  A0r[0] = ld16(A0 + frow(y0));
+  N0[0] = N0[1] = N0[2] = A0r[0];
+  {
+    // prologue: new colour-0 row y0 - 1 (odd row: parity 1), formed, not stored
+    edge[1][0][q] = A1[3].w[0];
+    __syncthreads();
+    const Chunk sh = shift_next(A1[3], edge[1][0][qn]);
+    uint32_t kk[4];
+    counts2d(A0r[1], A1[3], sh, A1[2], A1[0], kk);
+    N0[3] = update_chunk<false>(tab, key, t, 0u, frow(y0 + L - 1), A0r[1], kk, pend);
+    A1[2] = ld16(A1g + frow(y0 + 2));
+    A0r[1] = ld16(A0 + frow(y0 + 1));
+  }
+  for (uint32_t i = 0; i < H; i += 4) {
+    const uint32_t y = y0 + i;
+    step(std::integral_constant<int, 0>(), y, true, i >= 1);
+    step(std::integral_constant<int, 1>(), y + 1, true, true);
+    step(std::integral_constant<int, 2>(), y + 2, true, true);
+    step(std::integral_constant<int, 3>(), y + 3, true, true);
+  }
+  // last step: new colour 0 at row y0 + H (formed, not stored), colour 1 at y0 + H - 1
+  step(std::integral_constant<int, 0>(), y0 + H, false, true);
+  {
+    int64_t dE = 0, dM = 0;
+    resolve_pending<2>(pend, tab, key, t, 1u, B1, dE, dM);
+    Esum += dE;
+    Msum += dM;
   }
   if (MEASURE) block_partial_int(Esum, Msum, parts, blockIdx.x);
 }
 
 bool ising_fused_supported(const Geom& g, int J_kind, uint32_t H) {
   const uint32_t Q = (uint32_t)(g.R / 16);
-  return g.d == 2 && J_kind == 0 && g.L % 32 == 0 && Q % 64 == 0 && Q <= 1024 && H >= 1 &&
-         g.L % H == 0 && g.L / H >= 2;
+  return g.d == 2 && J_kind == 0 && g.L % 32 == 0 && Q % 64 == 0 && Q <= 1024 && H >= 4 &&
+         H % 4 == 0 && g.L % H == 0 && g.L / H >= 2;
 }
 
 // Rows per band: the largest divisor of L up to 64 leaving at least
 // `min_blocks` workgroups.
 uint32_t fused_rows_per_band(const Geom& g, uint32_t min_blocks) {
-  uint32_t best = 1;
-  for (uint32_t H = 1; H <= 64; H *= 2) {
+  uint32_t best = 4;
+  for (uint32_t H = 4; H <= 64; H *= 2) {
     if (g.L % H) break;
     if ((uint32_t)g.L / H >= min_blocks) best = H;
   }

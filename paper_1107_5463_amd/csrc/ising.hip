@@ -165,7 +165,7 @@ __global__ __launch_bounds__(256) void ising_chunk_kernel(const Geom g, const Rn
 // ---------------------------------------------------------------------------
 template <int D, bool MEASURE>
 __global__ __launch_bounds__(256) void ising_stream_kernel(const Geom g, const RngKey key,
-                                                           const IsingTable tab,
+                                                           const IsingTable table,
                                                            const FastDiv divQ, const FastDiv divL,
                                                            const uint32_t H, const uint32_t nbands,
                                                            int8_t* __restrict__ s,
@@ -190,118 +190,107 @@ __global__ __launch_bounds__(256) void ising_stream_kernel(const Geom g, const R
     const uint32_t col = 16 * q;
     const uint32_t zrow = L * z;  // row index of (y = 0, z)
     const uint32_t qn = q + 1 == Q ? 0u : q + 1, qp = q == 0 ? Q - 1 : q - 1;
-    const uint32_t edge_next = 16 * qn, edge_prev = 16 * qp + 12;
-    auto roff = [&](uint32_t y) -> uint32_t { return (zrow + y) * R; };
-    auto wrapy = [&](uint32_t y) -> uint32_t { return y >= L ? y - L : y; };
+    // the in-row neighbour chunk's edge word: next chunk's word 0 (parity 1)
+    // or previous chunk's word 3 (parity 0); parity alternates with y
+    const uint32_t pz = (c + z) & 1u;
+    const uint32_t edge_even = pz ? 16 * qn : 16 * qp + 12;  // rows with y even
+    const uint32_t edge_odd = pz ? 16 * qp + 12 : 16 * qn;
+    auto roff = [&](uint32_t y) -> uint32_t {  // y in [0, 2L)
+      return (zrow + (y >= L ? y - L : y)) * R;
+    };
     uint32_t zm_row = 0, zp_row = 0;
     if (D == 3) {
       zm_row = L * (z == 0 ? L - 1 : z - 1);
       zp_row = L * (z + 1 == L ? 0 : z + 1);
     }
-    const uint32_t th_lo = tab.th_lo, th_hi = tab.th_hi;
+    auto zoff = [&](uint32_t zr, uint32_t y) -> uint32_t { return (zr + (y >= L ? y - L : y)) * R + col; };
+    const TabRegs tab = tab_regs(table);
     PendingTies pend;
     pend.k = 0;
     pend.n = 0;
     pend.j[0] = pend.j[1] = pend.j[2] = pend.j[3] = 0;
 
-    Chunk up = ld16(oth + roff(y0 == 0 ? L - 1 : y0 - 1) + col);
-    Chunk ct = ld16(oth + roff(y0) + col);
-    Chunk dn = ld16(oth + roff(wrapy(y0 + 1)) + col);
-    Chunk o = ld16(own + roff(y0) + col);
-    for (uint32_t i = 0; i < H; ++i) {
-      const uint32_t y = y0 + i;
-      const uint32_t ro = roff(y);
-      // one row ahead: the other colour's row y + 2 and our own row y + 1
-      const Chunk dn2 = ld16(oth + roff(wrapy(wrapy(y + 1) + 1)) + col);
-      const Chunk o2 = ld16(own + roff(wrapy(y + 1)) + col);
-      const uint32_t p = (c + y + z) & 1u;
-      const uint32_t e = *reinterpret_cast<const uint32_t*>(oth + ro + (p ? edge_next : edge_prev));
-      Chunk fz, bz;
-      if (D == 3) {
-        fz = ld16(oth + (zm_row + y) * R + col);
-        bz = ld16(oth + (zp_row + y) * R + col);
-      }
-      const Chunk sh = p ? shift_next(ct, e) : shift_prev(ct, e);
-      const uint32_t jbase = ro + col;
-      const Rand4 rp = philox(jbase >> 4, t, key.replica, tag(c, kIsingPrefix), key.k0, key.k1);
-      uint32_t kk[4], nw[4], tie[4];
-      uint32_t anytie = 0;
+    // Software pipeline: slot y & 3 of Ro holds the other colour's row y,
+    // slot y & 1 of Ow / Ed / Fz / Bz our own row y, its edge word and its
+    // z-neighbours.  A load is issued only into a slot whose row is dead and
+    // is consumed at least one full row later, so no wait stalls the stream.
+    Chunk Ro[4], Ow[2], Fz[2], Bz[2];
+    uint32_t Ed[2];
+    const uint32_t ym1 = y0 == 0 ? L - 1 : y0 - 1;
+    Ro[3] = ld16(oth + roff(ym1) + col);
+    Ro[0] = ld16(oth + roff(y0) + col);
+    Ro[1] = ld16(oth + roff(y0 + 1) + col);
+    Ro[2] = ld16(oth + roff(y0 + 2) + col);
+    Ow[0] = ld16(own + roff(y0) + col);
+    Ow[1] = ld16(own + roff(y0 + 1) + col);
+    Ed[0] = *reinterpret_cast<const uint32_t*>(oth + roff(y0) + edge_even);
+    Ed[1] = *reinterpret_cast<const uint32_t*>(oth + roff(y0 + 1) + edge_odd);
+    if (D == 3) {
+      Fz[0] = ld16(oth + zoff(zm_row, y0));
+      Fz[1] = ld16(oth + zoff(zm_row, y0 + 1));
+      Bz[0] = ld16(oth + zoff(zp_row, y0));
+      Bz[1] = ld16(oth + zoff(zp_row, y0 + 1));
+    }
+    for (uint32_t i = 0; i < H; i += 4) {
 #pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        const uint32_t ow = o.w[w];
-        uint32_t k2 = ((ow ^ ct.w[w]) & kBit1) + ((ow ^ sh.w[w]) & kBit1) +
-                      ((ow ^ up.w[w]) & kBit1) + ((ow ^ dn.w[w]) & kBit1);
-        if (D == 3) k2 += ((ow ^ fz.w[w]) & kBit1) + ((ow ^ bz.w[w]) & kBit1);
-        kk[w] = k2 >> 1;
-        nw[w] = decide4_fast(th_lo, th_hi, ow, kk[w], rp.w[w], tie[w]);
-        anytie |= tie[w];
-      }
-      if (anytie) {
-        // rare: a prefix byte may equal its threshold byte; queue the exact
-        // ties for the refinement draw at the end of the band
-        uint32_t m = exact_ties16(th_lo, th_hi, kk, rp);
-        while (m) {
-          const uint32_t idx = __builtin_ctz(m);
-          m &= m - 1;
-          const uint32_t w = idx >> 2, b = idx & 3u;
-          const uint32_t kw = w == 0 ? kk[0] : (w == 1 ? kk[1] : (w == 2 ? kk[2] : kk[3]));
-          const uint32_t k = (kw >> (8 * b)) & 0xFu;
-          const uint32_t js = jbase + idx;
-          if (pend.n < 4) {
-            pend.j[0] = pend.n == 0 ? js : pend.j[0];
-            pend.j[1] = pend.n == 1 ? js : pend.j[1];
-            pend.j[2] = pend.n == 2 ? js : pend.j[2];
-            pend.j[3] = pend.n == 3 ? js : pend.j[3];
-            pend.k |= k << (4 * pend.n);
-            pend.n += 1;
-          } else {
-            const Rand4 rr = philox(js, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
-            if ((rr.w[0] & 0xFFFFFFu) < frac_of(tab, k)) {
-              const uint32_t f = 0xFEu << (8 * b);
-              nw[0] ^= w == 0 ? f : 0u;
-              nw[1] ^= w == 1 ? f : 0u;
-              nw[2] ^= w == 2 ? f : 0u;
-              nw[3] ^= w == 3 ? f : 0u;
-            }
-          }
-        }
-      }
-      st16(own + jbase, nw);
-      if (MEASURE) {
-        // colour 1 after its update: every bond has one colour-1 end, and the
-        // colour-0 chunk at the same position covers each colour-0 site once
-        uint32_t kn[4];
+      for (int ph = 0; ph < 4; ++ph) {
+        const uint32_t y = y0 + i + ph;  // y0 and i are multiples of 4: y & 3 == ph
+        const uint32_t p = (pz + ph) & 1u;
+        const Chunk& up = Ro[(ph + 3) & 3];
+        const Chunk& ct = Ro[ph];
+        const Chunk& dn = Ro[(ph + 1) & 3];
+        const Chunk& o = Ow[ph & 1];
+        const uint32_t e = Ed[ph & 1];
+        const Chunk sh = p ? shift_next(ct, e) : shift_prev(ct, e);
+        const uint32_t jbase = roff(y) + col;
+        uint32_t kk[4];
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-          uint32_t k2 = ((nw[w] ^ ct.w[w]) & kBit1) + ((nw[w] ^ sh.w[w]) & kBit1) +
-                        ((nw[w] ^ up.w[w]) & kBit1) + ((nw[w] ^ dn.w[w]) & kBit1);
-          if (D == 3) k2 += ((nw[w] ^ fz.w[w]) & kBit1) + ((nw[w] ^ bz.w[w]) & kBit1);
-          kn[w] = k2 >> 1;
+          const uint32_t ow = o.w[w];
+          uint32_t k2 = ((ow ^ ct.w[w]) & kBit1) + ((ow ^ sh.w[w]) & kBit1) +
+                        ((ow ^ up.w[w]) & kBit1) + ((ow ^ dn.w[w]) & kBit1);
+          if (D == 3) k2 += ((ow ^ Fz[ph & 1].w[w]) & kBit1) + ((ow ^ Bz[ph & 1].w[w]) & kBit1);
+          kk[w] = k2 >> 1;
         }
-        Chunk nc;
-        nc.w[0] = nw[0]; nc.w[1] = nw[1]; nc.w[2] = nw[2]; nc.w[3] = nw[3];
-        Esum += -(int64_t)(16 * 2 * D) + 2 * (int64_t)chunk_count_sum(kn);
-        Msum += chunk_spin_sum(nc) + chunk_spin_sum(ct);
+        // rare exact ties are queued and resolved at the end of the band
+        const Chunk nc = update_chunk<true>(tab, key, t, c, jbase, o, kk, pend);
+        uint32_t nw[4] = {nc.w[0], nc.w[1], nc.w[2], nc.w[3]};
+        st16(own + jbase, nw);
+        if (MEASURE) {
+          // colour 1 after its update: every bond has one colour-1 end, and the
+          // colour-0 chunk at the same position covers each colour-0 site once
+          uint32_t kn[4];
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            uint32_t k2 = ((nw[w] ^ ct.w[w]) & kBit1) + ((nw[w] ^ sh.w[w]) & kBit1) +
+                          ((nw[w] ^ up.w[w]) & kBit1) + ((nw[w] ^ dn.w[w]) & kBit1);
+            if (D == 3)
+              k2 += ((nw[w] ^ Fz[ph & 1].w[w]) & kBit1) + ((nw[w] ^ Bz[ph & 1].w[w]) & kBit1);
+            kn[w] = k2 >> 1;
+          }
+          Chunk nc;
+          nc.w[0] = nw[0]; nc.w[1] = nw[1]; nc.w[2] = nw[2]; nc.w[3] = nw[3];
+          Esum += -(int64_t)(16 * 2 * D) + 2 * (int64_t)chunk_count_sum(kn);
+          Msum += chunk_spin_sum(nc) + chunk_spin_sum(ct);
+        }
+        // refill the dead slots: other row y + 3, own row y + 2 with its edge
+        // word and z-neighbours (rows past the band are read, never used)
+        Ro[(ph + 3) & 3] = ld16(oth + roff(y + 3) + col);
+        Ow[ph & 1] = ld16(own + roff(y + 2) + col);
+        Ed[ph & 1] = *reinterpret_cast<const uint32_t*>(oth + roff(y + 2) + ((ph & 1) ? edge_odd : edge_even));
+        if (D == 3) {
+          Fz[ph & 1] = ld16(oth + zoff(zm_row, y + 2));
+          Bz[ph & 1] = ld16(oth + zoff(zp_row, y + 2));
+        }
       }
-      up = ct;
-      ct = dn;
-      dn = dn2;
-      o = o2;
     }
     // deferred ties: the site belongs to this lane's column of its own colour,
     // which no other lane of this launch touches
-    for (uint32_t e = 0; e < pend.n; ++e) {
-      const uint32_t js = e == 0 ? pend.j[0] : (e == 1 ? pend.j[1] : (e == 2 ? pend.j[2] : pend.j[3]));
-      const uint32_t k = (pend.k >> (4 * e)) & 0xFu;
-      const Rand4 rr = philox(js, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
-      if ((rr.w[0] & 0xFFFFFFu) < frac_of(tab, k)) {
-        const int8_t v = own[js];
-        own[js] = (int8_t)(-v);
-        if (MEASURE) {
-          Esum += 4 * (int64_t)(D - (int)k);  // the flipped site's bonds all change sign
-          Msum -= 2 * (int64_t)v;
-        }
-      }
+    int64_t dE = 0, dM = 0;
+    resolve_pending<D>(pend, tab, key, t, c, own, dE, dM);
+    if (MEASURE) {
+      Esum += dE;
+      Msum += dM;
     }
   }
   if (MEASURE) block_partial_int(Esum, Msum, parts, blockIdx.x);
@@ -350,8 +339,8 @@ static hipError_t launch_chunk(const IsingLaunch& a, int8_t* spins, uint32_t t, 
 // that still gives at least `min_waves` waves.
 uint32_t stream_rows_per_band(const Geom& g, uint32_t min_waves) {
   const uint32_t Q = (uint32_t)(g.R / 16);
-  uint32_t best = 1;
-  for (uint32_t H = 1; H <= 64; H *= 2) {
+  uint32_t best = 4;
+  for (uint32_t H = 4; H <= 64; H *= 2) {
     if (g.L % H) break;
     const uint64_t waves = (uint64_t)Q * (uint64_t)(g.rows / H) / 64;
     if (waves >= min_waves) best = H;
@@ -392,8 +381,8 @@ int ising_variant_used(const IsingLaunch& a) {
   int v = a.variant;
   const bool chunk_ok = ising_chunk_supported(a.g, a.J_kind);
   if (v == kVariantAuto) v = !chunk_ok ? kVariantSite : (a.J_kind == 0 ? kVariantStream : kVariantChunk);
-  if (v == kVariantStream && !(chunk_ok && a.J_kind == 0 && a.rows_per_band >= 1 &&
-                               a.g.L % a.rows_per_band == 0))
+  if (v == kVariantStream && !(chunk_ok && a.J_kind == 0 && a.rows_per_band >= 4 &&
+                               a.rows_per_band % 4 == 0 && a.g.L % a.rows_per_band == 0))
     v = chunk_ok ? kVariantChunk : kVariantSite;
   if (v == kVariantChunk && !chunk_ok) v = kVariantSite;
   return v;

@@ -74,6 +74,36 @@ hipError_t launch_init_continuous(const Geom& g, int n, RngKey key, int hot, flo
 hipError_t launch_init_couplings(const Geom& g, int J_kind, RngKey key, double J0, double sigma,
                                  void* J, hipStream_t st);
 
+// One lattice of a batch (device table, written by the host runtime).
+struct BatchDesc {
+  uint32_t L, R, Nh, replica;
+  uint32_t divR_m, divR_s, divL_m, divL_s;  // FastDiv constants for R and L
+  uint32_t th_lo, th_hi;                    // threshold bytes (always-accept classes: 0xFF)
+  uint32_t spin_off_lo, spin_off_hi;        // byte offset of its [2][Nh] spins
+  uint32_t J_off_lo, J_off_hi;              // byte offset of its [d][2][Nh] couplings
+  uint32_t frac[7];                         // refinement fractions (2^24: always)
+  uint32_t pad;
+  double J0;
+};
+
+struct BatchLaunch {
+  int d;
+  bool pm;                 // +-1 couplings (else uniform)
+  uint32_t n_lattices;
+  uint32_t threads;        // workgroup size (one workgroup per lattice)
+  size_t max_sites;        // dynamic LDS bytes: the largest L^d
+  const BatchDesc* descs;  // device
+  const uint32_t* order;   // device: workgroup -> lattice
+  RngKey key;              // replica is taken from each descriptor
+};
+
+hipError_t launch_batch(const BatchLaunch& a, int8_t* spins, const int8_t* J, uint32_t t0,
+                        uint32_t n_sweeps, void* dev_obs, hipStream_t st);
+hipError_t batch_allow_lds(size_t bytes);
+// The kernel a batch launch uses (for building graph nodes); its arguments are
+// (descs, order, key, spins, J, t0, n_sweeps, obs).
+const void* batch_kernel_fn(int d, bool pm, bool measure);
+
 struct MeasureLaunch {
   Geom g;
   int n;

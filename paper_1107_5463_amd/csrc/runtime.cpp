@@ -11,7 +11,10 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <numeric>
 #include <string>
+#include <vector>
+#include <algorithm>
 
 #include "kernels.hpp"
 #include "smc.h"
@@ -117,14 +120,14 @@ RngKey key_of(const smc_lattice* h) {
   return RngKey{(uint32_t)(h->p.seed & 0xffffffffu), (uint32_t)(h->p.seed >> 32), h->p.replica};
 }
 
-void build_table(smc_lattice* h, double beta) {
-  if (h->tab_valid && h->tab_beta == beta) return;
+// Integer Boltzmann thresholds per class k of unsatisfied bonds (k = 0..2d),
+// dE_k = 4 J0 (d - k): T = ceil(2^32 exp(-beta dE)) in long double.
+IsingTable make_table(int d, double J0, double beta) {
   IsingTable tab;
   std::memset(&tab, 0, sizeof(tab));
   uint8_t th[8] = {0}, al[8] = {0};
-  const int d = h->p.d;
   for (int k = 0; k <= 2 * d; ++k) {
-    const long double dE = 4.0L * (long double)h->p.J0 * (long double)(d - k);
+    const long double dE = 4.0L * (long double)J0 * (long double)(d - k);
     bool always = false;
     uint64_t T = 0;
     if (!(dE > 0.0L)) {
@@ -153,7 +156,12 @@ void build_table(smc_lattice* h, double beta) {
   tab.th_hi = th[4] | (th[5] << 8) | (th[6] << 16) | ((uint32_t)th[7] << 24);
   tab.al_lo = al[0] | (al[1] << 8) | (al[2] << 16) | ((uint32_t)al[3] << 24);
   tab.al_hi = al[4] | (al[5] << 8) | (al[6] << 16) | ((uint32_t)al[7] << 24);
-  h->tab = tab;
+  return tab;
+}
+
+void build_table(smc_lattice* h, double beta) {
+  if (h->tab_valid && h->tab_beta == beta) return;
+  h->tab = make_table(h->p.d, h->p.J0, beta);
   h->tab_beta = beta;
   h->tab_valid = true;
 }
@@ -547,5 +555,388 @@ int smc_destroy(smc_lattice* h) {
 const char* smc_last_error(void) { return g_err.c_str(); }
 
 const char* smc_version(void) { return "libsmc 0.1 (gfx950)"; }
+
+}  // extern "C"
+
+// ===========================================================================
+// Batches
+// ===========================================================================
+struct smc_batch {
+  int d, J_kind;
+  uint64_t seed;
+  double J0;
+  int32_t n;
+  std::vector<int32_t> L;
+  std::vector<int64_t> soff, joff;
+  std::vector<BatchDesc> desc;
+  std::vector<uint32_t> orders;  // [largest first | as given]
+  void* spins;
+  void* J;
+  hipStream_t stream;
+  uint64_t t;
+  BatchDesc* desc_dev;
+  uint32_t* order_dev;
+  void* scratch;
+  size_t spin_bytes, max_sites;
+  uint32_t threads;
+  bool largest_first;
+  bool use_graph;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  hipGraphNode_t node;
+  int64_t graph_n;
+  void* graph_obs;
+  uint32_t graph_threads;
+  bool graph_largest;
+};
+
+namespace {
+
+size_t round16(size_t v) { return (v + 15) / 16 * 16; }
+
+bool batch_shape_ok(int32_t d, int32_t n, const int32_t* L, std::string& why) {
+  if (d != 2 && d != 3) { why = "d must be 2 or 3"; return false; }
+  if (n < 1 || !L) { why = "need n_lattices >= 1 and an edge array"; return false; }
+  for (int32_t r = 0; r < n; ++r) {
+    if (L[r] < 4 || (L[r] & 1)) { why = "every L must be even and >= 4"; return false; }
+    const double N = std::pow((double)L[r], d);
+    if (N > 65536.0) { why = "every lattice must have L^d <= 65536 sites"; return false; }
+  }
+  return true;
+}
+
+void batch_layout(int32_t d, int32_t n, const int32_t* L, std::vector<int64_t>& so,
+                  std::vector<int64_t>& jo, size_t& sbytes, size_t& jbytes) {
+  so.resize(n);
+  jo.resize(n);
+  size_t s = 0, j = 0;
+  for (int32_t r = 0; r < n; ++r) {
+    size_t N = 1;
+    for (int k = 0; k < d; ++k) N *= (size_t)L[r];
+    so[r] = (int64_t)s;
+    jo[r] = (int64_t)j;
+    s += round16(N);
+    j += round16(N * d);
+  }
+  sbytes = s;
+  jbytes = j;
+}
+
+size_t batch_ws_parts(int32_t d, int32_t n, const int32_t* L, size_t* desc_b, size_t* order_b,
+                      size_t* scratch_b) {
+  std::vector<int64_t> so, jo;
+  size_t sb, jb;
+  batch_layout(d, n, L, so, jo, sb, jb);
+  *desc_b = round_up(sizeof(BatchDesc) * (size_t)n, kAlign);
+  *order_b = round_up(sizeof(uint32_t) * 2 * (size_t)n, kAlign);
+  *scratch_b = round_up(sb, kAlign);
+  return *desc_b + *order_b + *scratch_b;
+}
+
+int batch_launch(smc_batch* b, int8_t* spins, uint32_t t0, uint32_t n_sweeps, void* dev_obs,
+                 uint32_t threads, bool largest_first) {
+  BatchLaunch a;
+  a.d = b->d;
+  a.pm = b->J_kind == SMC_J_PM;
+  a.n_lattices = (uint32_t)b->n;
+  a.threads = threads;
+  a.max_sites = b->max_sites;
+  a.descs = b->desc_dev;
+  a.order = b->order_dev + (largest_first ? 0 : b->n);
+  a.key = RngKey{(uint32_t)(b->seed & 0xffffffffu), (uint32_t)(b->seed >> 32), 0u};
+  return check(launch_batch(a, spins, (const int8_t*)b->J, t0, n_sweeps, dev_obs, b->stream),
+               "batch sweep launch");
+}
+
+void batch_drop_graph(smc_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->node = nullptr;
+}
+
+// One graph node holding the batch kernel; its arguments are refreshed in
+// the instantiated graph before every replay.
+int batch_graph_sweep(smc_batch* b, uint32_t n_sweeps, void* dev_obs) {
+  const BatchDesc* descs = b->desc_dev;
+  const uint32_t* order = b->order_dev + (b->largest_first ? 0 : b->n);
+  RngKey key{(uint32_t)(b->seed & 0xffffffffu), (uint32_t)(b->seed >> 32), 0u};
+  int8_t* spins = (int8_t*)b->spins;
+  const int8_t* J = (const int8_t*)b->J;
+  uint32_t t0 = (uint32_t)b->t;
+  void* obs = dev_obs;
+  void* args[] = {&descs, &order, &key, &spins, &J, &t0, &n_sweeps, &obs};
+  hipKernelNodeParams kp;
+  std::memset(&kp, 0, sizeof(kp));
+  kp.func = const_cast<void*>(batch_kernel_fn(b->d, b->J_kind == SMC_J_PM, dev_obs != nullptr));
+  kp.gridDim = dim3((unsigned)b->n);
+  kp.blockDim = dim3(b->threads);
+  kp.sharedMemBytes = (unsigned)b->max_sites;
+  kp.kernelParams = args;
+  kp.extra = nullptr;
+  const bool same = b->exec && b->graph_n == (int64_t)n_sweeps && b->graph_obs == dev_obs &&
+                    b->graph_threads == b->threads && b->graph_largest == b->largest_first;
+  if (!same) {
+    batch_drop_graph(b);
+    int rc = check(hipGraphCreate(&b->graph, 0), "graph create");
+    if (rc != SMC_OK) return rc;
+    rc = check(hipGraphAddKernelNode(&b->node, b->graph, nullptr, 0, &kp), "graph kernel node");
+    if (rc != SMC_OK) return rc;
+    rc = check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate");
+    if (rc != SMC_OK) return rc;
+    b->graph_n = n_sweeps;
+    b->graph_obs = dev_obs;
+    b->graph_threads = b->threads;
+    b->graph_largest = b->largest_first;
+  } else {
+    const int rc = check(hipGraphExecKernelNodeSetParams(b->exec, b->node, &kp), "graph node update");
+    if (rc != SMC_OK) return rc;
+  }
+  return check(hipGraphLaunch(b->exec, b->stream), "graph launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t smc_batch_spin_bytes(int32_t d, int32_t n, const int32_t* L) {
+  std::string why;
+  if (!batch_shape_ok(d, n, L, why)) return 0;
+  std::vector<int64_t> so, jo;
+  size_t sb, jb;
+  batch_layout(d, n, L, so, jo, sb, jb);
+  return sb;
+}
+
+size_t smc_batch_coupling_bytes(int32_t d, int32_t n, const int32_t* L) {
+  std::string why;
+  if (!batch_shape_ok(d, n, L, why)) return 0;
+  std::vector<int64_t> so, jo;
+  size_t sb, jb;
+  batch_layout(d, n, L, so, jo, sb, jb);
+  return jb;
+}
+
+size_t smc_batch_workspace_bytes(int32_t d, int32_t n, const int32_t* L) {
+  std::string why;
+  if (!batch_shape_ok(d, n, L, why)) return 0;
+  size_t a, o, s;
+  return batch_ws_parts(d, n, L, &a, &o, &s);
+}
+
+int smc_batch_offsets(int32_t d, int32_t n, const int32_t* L, int64_t* spin_offsets,
+                      int64_t* coupling_offsets) {
+  std::string why;
+  if (!batch_shape_ok(d, n, L, why)) return fail(SMC_EINVAL, why);
+  std::vector<int64_t> so, jo;
+  size_t sb, jb;
+  batch_layout(d, n, L, so, jo, sb, jb);
+  for (int32_t r = 0; r < n; ++r) {
+    if (spin_offsets) spin_offsets[r] = so[r];
+    if (coupling_offsets) coupling_offsets[r] = jo[r];
+  }
+  return SMC_OK;
+}
+
+int smc_batch_init(smc_batch** out, int32_t d, int32_t J_kind, uint64_t seed, double J0,
+                   int32_t init, int32_t couplings_keep, int32_t n, const int32_t* L,
+                   const double* beta, const uint32_t* replica, void* spins, void* J,
+                   void* workspace, size_t workspace_bytes, void* stream) {
+  g_err.clear();
+  if (!out) return fail(SMC_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  if (!batch_shape_ok(d, n, L, why)) return fail(SMC_EINVAL, why);
+  if (J_kind != SMC_J_UNIFORM && J_kind != SMC_J_PM)
+    return fail(SMC_EINVAL, "batches take uniform or +-1 couplings");
+  if (!std::isfinite(J0)) return fail(SMC_EINVAL, "J0 must be finite");
+  if (init < 0 || init > 2) return fail(SMC_EINVAL, "init must be HOT, COLD or KEEP");
+  if (!beta) return fail(SMC_EINVAL, "beta array is NULL");
+  for (int32_t r = 0; r < n; ++r)
+    if (!beta_ok(beta[r])) return fail(SMC_EINVAL, "every beta must be >= 0 (or +inf), not NaN");
+  if (!spins || ((uintptr_t)spins & 15)) return fail(SMC_EINVAL, "spins must be 16-byte aligned");
+  if (J_kind == SMC_J_PM && (!J || ((uintptr_t)J & 15)))
+    return fail(SMC_EINVAL, "J must be non-NULL and 16-byte aligned for +-1 couplings");
+  size_t desc_b, order_b, scratch_b;
+  const size_t need = batch_ws_parts(d, n, L, &desc_b, &order_b, &scratch_b);
+  if (!workspace || ((uintptr_t)workspace & (kAlign - 1)))
+    return fail(SMC_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+  if (workspace_bytes < need)
+    return fail(SMC_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
+  smc_batch* b = new (std::nothrow) smc_batch();
+  if (!b) return fail(SMC_EINVAL, "out of host memory");
+  b->d = d;
+  b->J_kind = J_kind;
+  b->seed = seed;
+  b->J0 = J0;
+  b->n = n;
+  b->L.assign(L, L + n);
+  size_t jb;
+  batch_layout(d, n, L, b->soff, b->joff, b->spin_bytes, jb);
+  b->spins = spins;
+  b->J = J_kind == SMC_J_PM ? J : nullptr;
+  b->stream = (hipStream_t)stream;
+  b->t = 0;
+  b->desc_dev = (BatchDesc*)workspace;
+  b->order_dev = (uint32_t*)((char*)workspace + desc_b);
+  b->scratch = (char*)workspace + desc_b + order_b;
+  b->threads = 256;
+  b->largest_first = true;
+  b->use_graph = false;
+  b->graph = nullptr;
+  b->exec = nullptr;
+  b->node = nullptr;
+  b->graph_n = -1;
+  b->graph_obs = nullptr;
+  b->max_sites = 0;
+  b->desc.resize(n);
+  for (int32_t r = 0; r < n; ++r) {
+    BatchDesc& x = b->desc[r];
+    std::memset(&x, 0, sizeof(x));
+    const uint32_t Lr = (uint32_t)L[r];
+    size_t N = 1;
+    for (int k = 0; k < d; ++k) N *= Lr;
+    b->max_sites = std::max(b->max_sites, N);
+    x.L = Lr;
+    x.R = Lr / 2;
+    x.Nh = (uint32_t)(N / 2);
+    x.replica = replica ? replica[r] : (uint32_t)r;
+    const FastDiv dr = make_fastdiv(x.R), dl = make_fastdiv(Lr);
+    x.divR_m = dr.m;
+    x.divR_s = dr.s;
+    x.divL_m = dl.m;
+    x.divL_s = dl.s;
+    const IsingTable tab = make_table(d, J0, beta[r]);
+    x.th_lo = tab.th_lo;
+    x.th_hi = tab.th_hi;
+    for (int k = 0; k < 7; ++k) x.frac[k] = tab.frac[k];
+    x.spin_off_lo = (uint32_t)((uint64_t)b->soff[r] & 0xffffffffu);
+    x.spin_off_hi = (uint32_t)((uint64_t)b->soff[r] >> 32);
+    x.J_off_lo = (uint32_t)((uint64_t)b->joff[r] & 0xffffffffu);
+    x.J_off_hi = (uint32_t)((uint64_t)b->joff[r] >> 32);
+    x.J0 = J0;
+  }
+  std::vector<uint32_t> idx(n);
+  std::iota(idx.begin(), idx.end(), 0u);
+  std::vector<uint32_t> largest = idx;
+  std::stable_sort(largest.begin(), largest.end(),
+                   [&](uint32_t a, uint32_t c) { return b->desc[a].Nh > b->desc[c].Nh; });
+  b->orders = largest;
+  b->orders.insert(b->orders.end(), idx.begin(), idx.end());
+  int rc = check(hipMemcpyAsync(b->desc_dev, b->desc.data(), sizeof(BatchDesc) * n,
+                                hipMemcpyHostToDevice, b->stream), "descriptor upload");
+  if (rc == SMC_OK)
+    rc = check(hipMemcpyAsync(b->order_dev, b->orders.data(), sizeof(uint32_t) * 2 * n,
+                              hipMemcpyHostToDevice, b->stream), "schedule upload");
+  for (int32_t r = 0; rc == SMC_OK && r < n; ++r) {
+    smc_params p;
+    std::memset(&p, 0, sizeof(p));
+    p.d = d;
+    p.n = 1;
+    p.L = L[r];
+    const Geom g = make_geom(&p);
+    const RngKey key{(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), b->desc[r].replica};
+    if (J_kind == SMC_J_PM && !couplings_keep)
+      rc = check(launch_init_couplings(g, SMC_J_PM, key, J0, 0.0, (int8_t*)J + b->joff[r], b->stream),
+                 "coupling init launch");
+    if (rc == SMC_OK && init != SMC_INIT_KEEP)
+      rc = check(launch_init_ising(g, key, init == SMC_INIT_HOT, (int8_t*)spins + b->soff[r], b->stream),
+                 "spin init launch");
+  }
+  if (rc == SMC_OK) rc = check(hipStreamSynchronize(b->stream), "stream synchronise");
+  if (rc != SMC_OK) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return SMC_OK;
+}
+
+int smc_batch_sweep(smc_batch* b, int64_t n_sweeps, void* dev_obs) {
+  if (!b) return fail(SMC_EINVAL, "handle is NULL");
+  if (n_sweeps < 0) return fail(SMC_EINVAL, "n_sweeps must be >= 0");
+  if (dev_obs && ((uintptr_t)dev_obs & 7)) return fail(SMC_EINVAL, "dev_obs must be 8-byte aligned");
+  if (b->t + (uint64_t)n_sweeps > 4294967296ull)
+    return fail(SMC_ERANGE, "sweep counter would exceed 2^32");
+  if (n_sweeps == 0 && !dev_obs) return SMC_OK;
+  int rc;
+  if (b->use_graph)
+    rc = batch_graph_sweep(b, (uint32_t)n_sweeps, dev_obs);
+  else
+    rc = batch_launch(b, (int8_t*)b->spins, (uint32_t)b->t, (uint32_t)n_sweeps, dev_obs, b->threads,
+                      b->largest_first);
+  if (rc == SMC_OK) b->t += (uint64_t)n_sweeps;
+  return rc;
+}
+
+int smc_batch_autotune(smc_batch* b, int32_t* threads_out, int32_t* largest_first_out) {
+  if (!b) return fail(SMC_EINVAL, "handle is NULL");
+  int rc = check(hipMemcpyAsync(b->scratch, b->spins, b->spin_bytes, hipMemcpyDeviceToDevice,
+                                b->stream), "scratch copy");
+  if (rc != SMC_OK) return rc;
+  hipEvent_t e0, e1;
+  if ((rc = check(hipEventCreate(&e0), "event create")) != SMC_OK) return rc;
+  if ((rc = check(hipEventCreate(&e1), "event create")) != SMC_OK) {
+    (void)hipEventDestroy(e0);
+    return rc;
+  }
+  float best = 1e30f;
+  uint32_t best_threads = b->threads;
+  bool best_largest = b->largest_first;
+  const uint32_t cand[4] = {64, 128, 256, 512};
+  for (int lf = 1; lf >= 0 && rc == SMC_OK; --lf) {
+    for (int c = 0; c < 4 && rc == SMC_OK; ++c) {
+      // the chain on the scratch copy is discarded: any counter will do
+      rc = batch_launch(b, (int8_t*)b->scratch, (uint32_t)b->t, 1, nullptr, cand[c], lf != 0);
+      if (rc != SMC_OK) break;
+      rc = check(hipEventRecord(e0, b->stream), "event record");
+      if (rc == SMC_OK) rc = batch_launch(b, (int8_t*)b->scratch, (uint32_t)b->t, 4, nullptr, cand[c], lf != 0);
+      if (rc == SMC_OK) rc = check(hipEventRecord(e1, b->stream), "event record");
+      if (rc == SMC_OK) rc = check(hipEventSynchronize(e1), "event synchronise");
+      float ms = 0.0f;
+      if (rc == SMC_OK) rc = check(hipEventElapsedTime(&ms, e0, e1), "event time");
+      if (rc == SMC_OK && ms < best) {
+        best = ms;
+        best_threads = cand[c];
+        best_largest = lf != 0;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != SMC_OK) return rc;
+  b->threads = best_threads;
+  b->largest_first = best_largest;
+  if (threads_out) *threads_out = (int32_t)best_threads;
+  if (largest_first_out) *largest_first_out = best_largest ? 1 : 0;
+  return SMC_OK;
+}
+
+int smc_batch_use_graph(smc_batch* b, int32_t enable) {
+  if (!b) return fail(SMC_EINVAL, "handle is NULL");
+  b->use_graph = enable != 0;
+  if (!b->use_graph) batch_drop_graph(b);
+  return SMC_OK;
+}
+
+int smc_batch_get_sweep_index(const smc_batch* b, uint64_t* t) {
+  if (!b || !t) return fail(SMC_EINVAL, "NULL argument");
+  *t = b->t;
+  return SMC_OK;
+}
+
+int smc_batch_set_sweep_index(smc_batch* b, uint64_t t) {
+  if (!b) return fail(SMC_EINVAL, "handle is NULL");
+  if (t > 4294967296ull) return fail(SMC_ERANGE, "sweep index must be <= 2^32");
+  b->t = t;
+  return SMC_OK;
+}
+
+int smc_batch_destroy(smc_batch* b) {
+  if (b) batch_drop_graph(b);
+  delete b;
+  return SMC_OK;
+}
 
 }  // extern "C"

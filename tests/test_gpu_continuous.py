@@ -55,6 +55,9 @@ CASES = [  # d, n, L, beta, delta, J_kind, fast
     (3, 2, 8, 0.5, 2.0, 1, False),
     (2, 2, 32, 1.0, 1.5, 2, False),
     (3, 3, 8, 0.7, 1.2, 2, False),
+    (2, 2, 6, 1.0, 1.0, 0, False),      # L/2 odd: one XY site per lane
+    (3, 2, 10, 0.6, 1.5, 1, False),
+    (2, 3, 6, 0.9, 1.0, 2, False),
     (2, 2, 64, 1.12, 1.0, 0, True),
     (3, 3, 16, 0.693, 1.0, 0, True),
 ]

@@ -268,8 +268,8 @@ def test_kernel_variants_bit_identical(smc_gpu, oracle_mod, d, L, monkeypatch):
     ref = oracle_mod.OracleLattice(d, 1, L, 88)
     ref.sweep(0.3, 4)
     seen = set()
-    for variant, rows in [("site", None), ("chunk", None), ("stream", "1"), ("stream", "2"),
-                          ("stream", "8"), ("stream", "32"), ("stream", None)]:
+    for variant, rows in [("site", None), ("chunk", None), ("stream", "4"), ("stream", "8"),
+                          ("stream", "16"), ("stream", "32"), ("stream", None)]:
         monkeypatch.setenv("SMC_ISING_KERNEL", variant)
         if rows is None:
             monkeypatch.delenv("SMC_STREAM_ROWS", raising=False)
@@ -282,7 +282,7 @@ def test_kernel_variants_bit_identical(smc_gpu, oracle_mod, d, L, monkeypatch):
     assert {name for name, _ in seen} == {"ising_site", "ising_chunk", "ising_stream"}
 
 
-@pytest.mark.parametrize("L,n,rows", [(2048, 4, None), (2048, 5, "1"), (4096, 3, "4"),
+@pytest.mark.parametrize("L,n,rows", [(2048, 4, None), (2048, 5, "4"), (4096, 3, "8"),
                                       (2048, 2, "64"), (4096, 1, None)])
 def test_fused_schedule_matches_oracle(smc_gpu, oracle_mod, L, n, rows, monkeypatch):
     """The one-kernel-per-sweep schedule (ping-pong buffers, LDS edge
