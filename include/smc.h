@@ -93,6 +93,7 @@ typedef struct smc_obs {
   double E;       /* energy (E_int * J0 for integer couplings) */
   double M[3];    /* magnetisation vector */
   double absM;    /* |M| */
+  int64_t sweep;  /* sweep counter t of the measured state (sweeps done since t = 0) */
 } smc_obs;
 
 typedef struct smc_lattice smc_lattice;

@@ -62,7 +62,7 @@ class Params(C.Structure):
 
 class _ObsC(C.Structure):
     _fields_ = [("E_int", C.c_int64), ("M_int", C.c_int64), ("E", C.c_double),
-                ("M", C.c_double * 3), ("absM", C.c_double)]
+                ("M", C.c_double * 3), ("absM", C.c_double), ("sweep", C.c_int64)]
 
 
 @dataclasses.dataclass
@@ -72,6 +72,7 @@ class Obs:
     E: float
     M: tuple
     absM: float
+    sweep: int = -1  # sweep counter of the measured state
 
 
 _LIB = None
@@ -268,7 +269,7 @@ class Lattice:
         o = _ObsC()
         _check(self._lib().smc_measure(self._h, C.byref(o)))
         return Obs(int(o.E_int), int(o.M_int), float(o.E), tuple(float(v) for v in o.M),
-                   float(o.absM))
+                   float(o.absM), int(o.sweep))
 
     def measure_async(self, dev_slot):
         """Write the observables (8 x 8-byte smc_obs layout) into a device tensor
@@ -285,7 +286,7 @@ class Lattice:
         for row in a.reshape(-1, 8):
             f = row.view(np.float64)
             out.append(Obs(int(row[0]), int(row[1]), float(f[2]), (float(f[3]), float(f[4]),
-                                                                    float(f[5])), float(f[6])))
+                                                                    float(f[5])), float(f[6]), int(row[7])))
         return out
 
     # ------------------------------------------------------------------

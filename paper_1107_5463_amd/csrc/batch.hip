@@ -187,6 +187,7 @@ __global__ __launch_bounds__(512) void batch_kernel(const BatchDesc* __restrict_
       o.M[1] = 0.0;
       o.M[2] = 0.0;
       o.absM = fabs((double)part[0].Mi);
+      o.sweep = (int64_t)t0 + n_sweeps;
       obs[li] = o;
     }
   }

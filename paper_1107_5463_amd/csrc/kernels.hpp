@@ -110,6 +110,7 @@ struct MeasureLaunch {
   int J_kind;
   const void* J;
   double J0;
+  int64_t sweep;  // sweep counter of the measured state
 };
 
 // Number of per-block partials the measurement writes (workspace sizing).

@@ -138,6 +138,7 @@ __global__ __launch_bounds__(256) void measure_cont_site(const Geom g, const flo
 __global__ __launch_bounds__(256) void finish_kernel(const Partial* __restrict__ parts,
                                                      const int64_t nparts, const int ising,
                                                      const int int_couplings, const double J0,
+                                                     const int64_t sweep,
                                                      ObsOut* __restrict__ obs) {
   Partial v{0, 0, 0.0, {0.0, 0.0, 0.0}};
   for (int64_t b = threadIdx.x; b < nparts; b += 256) {
@@ -174,6 +175,7 @@ __global__ __launch_bounds__(256) void finish_kernel(const Partial* __restrict__
       for (int k = 0; k < 3; ++k) o.M[k] = a.M[k];
       o.absM = sqrt(a.M[0] * a.M[0] + a.M[1] * a.M[1] + a.M[2] * a.M[2]);
     }
+    o.sweep = sweep;
     *obs = o;
   }
 }
@@ -239,7 +241,7 @@ hipError_t launch_measure(const MeasureLaunch& a, const void* spins, void* parti
 hipError_t launch_finish(const MeasureLaunch& a, const void* partials, int64_t nparts,
                          void* dev_obs, hipStream_t st) {
   hipLaunchKernelGGL(finish_kernel, dim3(1), dim3(256), 0, st, (const Partial*)partials, nparts,
-                     a.n == 1 ? 1 : 0, a.J_kind != 2 ? 1 : 0, a.J0, (ObsOut*)dev_obs);
+                     a.n == 1 ? 1 : 0, a.J_kind != 2 ? 1 : 0, a.J0, a.sweep, (ObsOut*)dev_obs);
   return hipGetLastError();
 }
 

@@ -18,7 +18,9 @@ struct ObsOut {  // layout of smc_obs
   double E;
   double M[3];
   double absM;
+  int64_t sweep;
 };
+static_assert(sizeof(ObsOut) == 64, "ObsOut mirrors the 64-byte smc_obs");
 
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {

@@ -19,6 +19,8 @@
 #include "kernels.hpp"
 #include "smc.h"
 
+static_assert(sizeof(smc_obs) == 64, "smc_obs is eight 8-byte fields");
+
 using namespace smc;
 
 struct smc_lattice {
@@ -166,13 +168,14 @@ void build_table(smc_lattice* h, double beta) {
   h->tab_valid = true;
 }
 
-MeasureLaunch measure_args(const smc_lattice* h) {
+MeasureLaunch measure_args(const smc_lattice* h, int64_t sweep) {
   MeasureLaunch m;
   m.g = h->g;
   m.n = h->p.n;
   m.J_kind = h->p.J_kind;
   m.J = h->J;
   m.J0 = h->p.J0;
+  m.sweep = sweep;
   return m;
 }
 
@@ -226,14 +229,14 @@ int two_pass_sweep(smc_lattice* h, double beta, uint32_t t, void* dev_obs) {
     if (ising_half_sweep_measured(a, (int8_t*)h->spins, t, h->partials, &nparts, h->stream, &err)) {
       rc = check(err, "measured Ising half-sweep launch");
       if (rc != SMC_OK) return rc;
-      return check(launch_finish(measure_args(h), h->partials, nparts, dev_obs, h->stream),
+      return check(launch_finish(measure_args(h, (int64_t)t + 1), h->partials, nparts, dev_obs, h->stream),
                    "measurement finish launch");
     }
   }
   rc = half_sweep_impl(h, beta, t, 1u);
   if (rc != SMC_OK) return rc;
   if (dev_obs)
-    return check(launch_measure(measure_args(h), h->spins, h->partials, dev_obs, h->stream),
+    return check(launch_measure(measure_args(h, (int64_t)t + 1), h->spins, h->partials, dev_obs, h->stream),
                  "measurement launch");
   return SMC_OK;
 }
@@ -266,7 +269,7 @@ int fused_sweeps(smc_lattice* h, double beta, int64_t n, void* dev_obs) {
     if (rc != SMC_OK) return rc;
     h->t += 2;
     if (parts) {
-      rc = check(launch_finish(measure_args(h), h->partials, nparts, dev_obs, h->stream),
+      rc = check(launch_finish(measure_args(h, h->t), h->partials, nparts, dev_obs, h->stream),
                  "measurement finish launch");
       if (rc != SMC_OK) return rc;
     }
@@ -287,7 +290,7 @@ int sweeps_impl(smc_lattice* h, double beta, int64_t n_sweeps, void* dev_obs) {
       rc = check(launch_renormalize(h->g, h->p.n, (float*)h->spins, h->stream), "renormalisation launch");
       if (rc != SMC_OK) return rc;
       if (last && dev_obs)
-        return check(launch_measure(measure_args(h), h->spins, h->partials, dev_obs, h->stream),
+        return check(launch_measure(measure_args(h, h->t), h->spins, h->partials, dev_obs, h->stream),
                      "measurement launch");
     }
   }
@@ -420,7 +423,7 @@ int smc_sweep_measure(smc_lattice* h, double beta, int64_t n_sweeps, void* dev_o
   if (h->t + (uint64_t)n_sweeps > 4294967296ull)
     return fail(SMC_ERANGE, "sweep counter would exceed 2^32");
   if (n_sweeps == 0)
-    return check(launch_measure(measure_args(h), h->spins, h->partials, dev_obs, h->stream),
+    return check(launch_measure(measure_args(h, h->t), h->spins, h->partials, dev_obs, h->stream),
                  "measurement launch");
   return sweeps_impl(h, beta, n_sweeps, dev_obs);
 }
@@ -436,7 +439,7 @@ int smc_half_sweep(smc_lattice* h, double beta, int colour) {
 int smc_measure_async(smc_lattice* h, void* dev_obs) {
   if (!h) return fail(SMC_EINVAL, "handle is NULL");
   if (!dev_obs || ((uintptr_t)dev_obs & 7)) return fail(SMC_EINVAL, "dev_obs must be 8-byte aligned");
-  return check(launch_measure(measure_args(h), h->spins, h->partials, dev_obs, h->stream),
+  return check(launch_measure(measure_args(h, h->t), h->spins, h->partials, dev_obs, h->stream),
                "measurement launch");
 }
 
@@ -458,7 +461,7 @@ int smc_measure(smc_lattice* h, smc_obs* out) {
 int smc_bond_correlations(smc_lattice* h, int op, void* acc, void* out_mean) {
   if (!h) return fail(SMC_EINVAL, "handle is NULL");
   if (!acc || ((uintptr_t)acc & 7)) return fail(SMC_EINVAL, "acc must be non-NULL and 8-byte aligned");
-  const MeasureLaunch m = measure_args(h);
+  const MeasureLaunch m = measure_args(h, h->t);
   switch (op) {
     case SMC_BOND_RESET:
       h->samples = 0;
@@ -500,7 +503,7 @@ int smc_validate(smc_lattice* h) {
   if (!h) return fail(SMC_EINVAL, "handle is NULL");
   int rc = check(launch_fill_zero(h->counter, 4, h->stream), "counter reset");
   if (rc != SMC_OK) return rc;
-  rc = check(launch_validate(measure_args(h), h->spins, h->counter, h->stream), "validate launch");
+  rc = check(launch_validate(measure_args(h, h->t), h->spins, h->counter, h->stream), "validate launch");
   if (rc != SMC_OK) return rc;
   uint32_t bad = 0;
   rc = check(hipMemcpyAsync(&bad, h->counter, 4, hipMemcpyDeviceToHost, h->stream), "counter copy");

@@ -110,3 +110,15 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     with pytest.raises(ImportError):
         smc.load_library()
     importlib.reload(smc)
+
+
+def test_obs_record_layout_matches_header(smc_host):
+    """smc_obs is eight 8-byte fields (records packed back to back in a batch),
+    in the order the header declares them."""
+    src = open(os.path.join(ROOT, "include", "smc.h")).read()
+    body = re.search(r"typedef struct smc_obs \{(.*?)\} smc_obs;", src, re.S).group(1)
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names = re.findall(r"\b([A-Za-z_]+)(?:\[\d+\])?\s*;", body)
+    fields = [f[0] for f in smc_host._ObsC._fields_]
+    assert names == fields
+    assert C.sizeof(smc_host._ObsC) == 64

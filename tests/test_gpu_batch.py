@@ -28,6 +28,7 @@ def _check(smc_gpu, oracle_mod, b, d, L, beta, kind, sweeps, seed, obs=None):
         if obs is not None:
             o = ref.measure()
             assert (obs[r].E_int, obs[r].M_int) == (o.E_int, o.M_int), r
+            assert obs[r].sweep == sweeps
 
 
 @pytest.mark.parametrize("d,kind,n", [(3, 1, 15), (2, 1, 12), (3, 0, 10), (2, 0, 7)])

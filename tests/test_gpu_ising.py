@@ -59,6 +59,7 @@ def test_c1_trajectory_bit_exact(smc_gpu, oracle_mod, generic):
     got = np.array([(o.E_int, o.M_int, o.absM) for o in series])
     want = np.array([(o.E_int, o.M_int, o.absM) for o in rser])
     assert np.array_equal(got, want)
+    assert [o.sweep for o in series] == list(range(1, 1001))
     assert np.array_equal(nat(lat), ref.s)
     assert lat.t == 1000
 
@@ -306,6 +307,7 @@ def test_fused_schedule_matches_oracle(smc_gpu, oracle_mod, L, n, rows, monkeypa
     o = smc_gpu.Lattice.decode_obs(slot)[0]
     r = ref.measure()
     assert (o.E_int, o.M_int) == (r.E_int, r.M_int)
+    assert o.sweep == 2 * n
     assert np.array_equal(nat(lat), ref.s)
     assert lat.t == 2 * n
 
@@ -326,3 +328,4 @@ def test_sweep_measure_matches_oracle(smc_gpu, oracle_mod, d, L, variant, monkey
         ref.sweep(0.35, n)
         r = ref.measure()
         assert (got[k].E_int, got[k].M_int) == (r.E_int, r.M_int), (k, variant)
+    assert [o.sweep for o in got] == [1, 4, 4]
