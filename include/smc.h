@@ -61,7 +61,7 @@ enum smc_init_kind { SMC_INIT_HOT = 0, SMC_INIT_COLD = 1, SMC_INIT_KEEP = 2 };
 
 enum smc_flags {
   SMC_FLAG_FAST_MATH = 1,        /* hardware transcendentals for continuous spins */
-  SMC_FLAG_SCHEDULE_FUSED = 2,   /* 2D Ising, uniform J, L % 2048 == 0: one kernel per sweep,
+  SMC_FLAG_SCHEDULE_FUSED = 2,   /* 2D Ising, uniform J, L % 2048 == 0, L <= 16384: one kernel per sweep,
                                     ping-ponging through the workspace (bit-identical
                                     results; other shapes keep the two-pass schedule) */
   SMC_FLAG_GENERIC_KERNEL = 4,   /* force the one-site-per-thread kernels (testing) */

@@ -82,97 +82,6 @@ __device__ __forceinline__ uint32_t frac_of(const IsingTable& tab, uint32_t k) {
   return v;
 }
 
-// Per-byte decision for 4 sites: k = unsatisfied-bond counts (bytes), P = 4
-// prefix bytes.  Returns the spin word after the accepted flips, and the tie
-// mask candidates (bit 7 of bytes that may need the refinement draw).
-__device__ __forceinline__ uint32_t decide4(const IsingTable& tab, uint32_t own, uint32_t k,
-                                            uint32_t P, uint32_t& tie) {
-  const uint32_t Th = __builtin_amdgcn_perm(tab.th_hi, tab.th_lo, k);
-  const uint32_t Al = __builtin_amdgcn_perm(tab.al_hi, tab.al_lo, k);
-  // bit 7 of each byte: P >= Th (unsigned bytes)
-  const uint32_t dlow = (P | kHigh) - (Th & ~kHigh);
-  const uint32_t x = P ^ Th;
-  const uint32_t ge = (x & P) | (~x & dlow);
-  const uint32_t acc = (~ge | Al) & kHigh;
-  // candidate exact ties P == Th on classes that are not always accepted
-  const uint32_t zz = x | Al;
-  tie = (zz - kOnes) & ~zz & kHigh;
-  return own ^ ((acc - (acc >> 7)) << 1);  // 0xFE flips +1 <-> -1
-}
-
-// Exact per-byte tie mask: bit 7 of each byte where P == Th and the class is
-// not always accepted (no carries cross bytes).
-__device__ __forceinline__ uint32_t tie_bytes(const IsingTable& tab, uint32_t k, uint32_t P) {
-  const uint32_t Th = __builtin_amdgcn_perm(tab.th_hi, tab.th_lo, k);
-  const uint32_t Al = __builtin_amdgcn_perm(tab.al_hi, tab.al_lo, k);
-  const uint32_t z = (P ^ Th) | Al;
-  const uint32_t nz = (((z & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | z) & kHigh;
-  return ~nz & kHigh;
-}
-
-// 16-bit mask (bit 4w+b) of sites whose prefix byte ties its threshold byte.
-__device__ __forceinline__ uint32_t tie_mask16(const IsingTable& tab, const uint32_t kk[4],
-                                               const Rand4& rp) {
-  uint32_t m = 0;
-#pragma unroll
-  for (int w = 0; w < 4; ++w) {
-    const uint32_t t7 = tie_bytes(tab, kk[w], rp.w[w]);
-    const uint32_t nib = ((t7 >> 7) | (t7 >> 14) | (t7 >> 21) | (t7 >> 28)) & 0xFu;
-    m |= nib << (4 * w);
-  }
-  return m;
-}
-
-// Resolve the rare ties with each site's 24-bit refinement draw.
-__device__ __forceinline__ void resolve_ties(const IsingTable& tab, const RngKey& key, uint32_t t,
-                                             uint32_t c, uint32_t jbase, const uint32_t kk[4],
-                                             uint32_t mask, uint32_t nw[4]) {
-  while (mask) {
-    const uint32_t idx = __builtin_ctz(mask);
-    mask &= mask - 1;
-    const uint32_t w = idx >> 2, b = idx & 3u;
-    const uint32_t kw = w == 0 ? kk[0] : (w == 1 ? kk[1] : (w == 2 ? kk[2] : kk[3]));
-    const uint32_t k = (kw >> (8 * b)) & 0xFFu;
-    const Rand4 rr = philox(jbase + idx, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
-    if ((rr.w[0] & 0xFFFFFFu) < frac_of(tab, k)) {
-      const uint32_t f = 0xFEu << (8 * b);
-      nw[0] ^= w == 0 ? f : 0u;
-      nw[1] ^= w == 1 ? f : 0u;
-      nw[2] ^= w == 2 ? f : 0u;
-      nw[3] ^= w == 3 ? f : 0u;
-    }
-  }
-}
-
-// Per-byte decision for 4 sites testing the threshold byte only.  Classes
-// that always accept carry threshold byte 0xFF and refinement fraction 2^24,
-// and are also flagged in Al: they flip whatever the prefix.  Returns the spin
-// word after the flips decided by the prefix bytes; tie7 flags (bit 7) the
-// bytes of refusable classes whose prefix may equal the threshold byte -- every
-// exact tie (2^-8 of the uphill attempts) plus occasional false alarms directly
-// above one, which the slow path re-checks.
-__device__ __forceinline__ uint32_t decide4_fast(uint32_t th_lo, uint32_t th_hi, uint32_t al_lo,
-                                                 uint32_t al_hi, uint32_t own, uint32_t k,
-                                                 uint32_t P, uint32_t& tie7) {
-  const uint32_t Th = __builtin_amdgcn_perm(th_hi, th_lo, k);
-  const uint32_t Al = __builtin_amdgcn_perm(al_hi, al_lo, k);
-  const uint32_t x = P ^ Th;
-  const uint32_t dlow = (P | kHigh) - (Th & ~kHigh);
-  const uint32_t ge = (x & P) | (~x & dlow);  // bit 7 of each byte: P >= Th
-  // 0xFF in every byte whose bit 7 of ge is set (sign-replicating selectors)
-  const uint32_t rej = __builtin_amdgcn_perm(ge, ge << 8, 0x0B090A08u);
-  tie7 = (x - kOnes) & ~x & ~Al & kHigh;
-  return own ^ ((~rej | Al) & 0xFEFEFEFEu);
-}
-
-// Deferred tie resolutions of one lane (at most 4 held; more are resolved on
-// the spot by the caller).
-struct PendingTies {
-  uint32_t j[4];
-  uint32_t k;  // nibble p = class of entry p
-  uint32_t n;
-};
-
 // Unsatisfied-bond counts of a chunk of 2D sites from its four neighbour
 // chunks (x+1 / x-1 as centre and shifted chunk, y-1, y+1): byte b of kk[w].
 __device__ __forceinline__ void counts2d(const Chunk& o, const Chunk& ctr, const Chunk& sh,
@@ -205,27 +114,18 @@ __device__ __forceinline__ FracRegs frac_regs(const IsingTable& tab) {
   return r;
 }
 
-__device__ __forceinline__ uint32_t frac_sel(const FracRegs& r, uint32_t k) {
-  const uint32_t a = (k & 1) ? r.f1 : r.f0;
-  const uint32_t b = (k & 1) ? r.f3 : r.f2;
-  const uint32_t c = (k & 1) ? r.f5 : r.f4;
-  const uint32_t lo = (k & 2) ? b : a;
-  const uint32_t hi = (k & 2) ? r.f6 : c;
-  return (k & 4) ? hi : lo;
+// Selections below are written as masks, not conditionals: a select of two
+// fields of a register-held aggregate can be rewritten into one load through
+// a selected pointer, which puts the aggregate in scratch memory.
+__device__ __forceinline__ uint32_t mask_sel(uint32_t a, uint32_t b, uint32_t bit) {
+  return a ^ ((a ^ b) & (0u - bit));  // bit ? b : a (bit is 0 or 1)
 }
 
-// Exact 16-bit mask (bit 4w+b) of sites whose prefix byte equals the threshold
-// byte of their class.
-__device__ __forceinline__ uint32_t exact_ties16(uint32_t th_lo, uint32_t th_hi,
-                                                 const uint32_t kk[4], const Rand4& rp) {
-  uint32_t m = 0;
-#pragma unroll
-  for (int w = 0; w < 4; ++w) {
-    const uint32_t z7 = rp.w[w] ^ __builtin_amdgcn_perm(th_hi, th_lo, kk[w]);
-    const uint32_t t7 = ~((((z7 & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | z7)) & kHigh;
-    m |= (((t7 >> 7) | (t7 >> 14) | (t7 >> 21) | (t7 >> 28)) & 0xFu) << (4 * w);
-  }
-  return m;
+__device__ __forceinline__ uint32_t frac_sel(const FracRegs& r, uint32_t k) {
+  const uint32_t b0 = k & 1u, b1 = (k >> 1) & 1u, b2 = (k >> 2) & 1u;
+  const uint32_t lo = mask_sel(mask_sel(r.f0, r.f1, b0), mask_sel(r.f2, r.f3, b0), b1);
+  const uint32_t hi = mask_sel(mask_sel(r.f4, r.f5, b0), r.f6, b1);
+  return mask_sel(lo, hi, b2);
 }
 
 // Threshold bytes, always-accept flags and refinement fractions pinned in
@@ -245,99 +145,139 @@ __device__ __forceinline__ TabRegs tab_regs(const IsingTable& tab) {
   return r;
 }
 
-// Flip byte b of word w of a chunk's new spins (static register indices).
-__device__ __forceinline__ void flip_byte(uint32_t nw[4], uint32_t w, uint32_t b) {
-  const uint32_t f = 0xFEu << (8 * b);
-  nw[0] ^= w == 0 ? f : 0u;
-  nw[1] ^= w == 1 ? f : 0u;
-  nw[2] ^= w == 2 ? f : 0u;
-  nw[3] ^= w == 3 ? f : 0u;
+// Per-byte decision for 4 sites on the threshold byte alone.  Classes that
+// always accept are flagged in Al (bytes 0xFF): they flip whatever the prefix.
+// Returns the spin word after the flips the prefix bytes decide; a prefix
+// equal to the threshold byte of a refusable class is a tie (probability
+// 2^-8), left unflipped here and flagged in bit 7 of the bytes of `tie`
+// (the other bits of `tie` are garbage).
+__device__ __forceinline__ uint32_t decide4_tie(const TabRegs& tab, uint32_t own, uint32_t k,
+                                                uint32_t P, uint32_t& tie) {
+  const uint32_t Th = __builtin_amdgcn_perm(tab.th_hi, tab.th_lo, k);
+  const uint32_t Al = __builtin_amdgcn_perm(tab.al_hi, tab.al_lo, k);
+  const uint32_t x = P ^ Th;
+  const uint32_t dlow = (P | kHigh) - (Th & ~kHigh);
+  const uint32_t ge = (x & P) | (~x & dlow);  // bit 7 of each byte: P >= Th
+  // 0xFF in every byte whose bit 7 of ge is set (sign-replicating selectors)
+  const uint32_t rej = __builtin_amdgcn_perm(ge, ge << 8, 0x0B090A08u);
+  // bit 7 of z: the low 7 bits of the byte of x are not all zero
+  const uint32_t z = (x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
+  tie = ~(z | x | Al);  // bit 7: x byte == 0 and the class is refusable
+  return own ^ ((~rej | Al) & 0xFEFEFEFEu);
 }
 
-// Queue an exact tie for the end of the band, or resolve it now if the queue
-// is full.  Returns true if it was resolved now and the move accepted.
-__device__ __forceinline__ bool queue_tie(PendingTies& pend, const TabRegs& tab, const RngKey& key,
-                                          uint32_t t, uint32_t c, uint32_t js, uint32_t k) {
-  if (pend.n < 4) {
-    pend.j[0] = pend.n == 0 ? js : pend.j[0];
-    pend.j[1] = pend.n == 1 ? js : pend.j[1];
-    pend.j[2] = pend.n == 2 ? js : pend.j[2];
-    pend.j[3] = pend.n == 3 ? js : pend.j[3];
-    pend.k |= k << (4 * pend.n);
-    pend.n += 1;
-    return false;
-  }
-  const Rand4 rr = philox(js, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
-  return (rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k);
-}
-
-// Visit the tie candidates of one chunk: exact ties (prefix byte == threshold
-// byte of the site's class) are resolved at once (DEFER = false) or queued.
-template <bool DEFER>
-__device__ __forceinline__ void handle_ties(const TabRegs& tab, const RngKey& key, uint32_t t,
-                                            uint32_t c, uint32_t jbase, const uint32_t kk[4],
-                                            const Rand4& rp, const uint32_t tie7[4],
-                                            uint32_t nw[4], PendingTies& pend) {
-#pragma unroll
-  for (uint32_t w = 0; w < 4; ++w) {
-    uint32_t m = tie7[w];
-    while (m) {
-      const uint32_t b = __builtin_ctz(m) >> 3;
-      m &= m - 1;
-      const uint32_t k = (kk[w] >> (8 * b)) & 0xFu;
-      if (((rp.w[w] >> (8 * b)) & 0xFFu) != table_byte(tab.th_lo, tab.th_hi, k)) continue;
-      const uint32_t js = jbase + 4 * w + b;
-      bool acc;
-      if (DEFER) {
-        acc = queue_tie(pend, tab, key, t, c, js, k);
-      } else {
-        const Rand4 rr = philox(js, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
-        acc = (rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k);
-      }
-      if (acc) flip_byte(nw, w, b);
-    }
-  }
-}
-
-// Metropolis update of one chunk given its unsatisfied-bond counts: one
-// Philox block for the 16 prefix bytes; the refinement draw only for the rare
-// exact ties, resolved on the spot (DEFER = false) or queued in pend.
-template <bool DEFER>
-__device__ __forceinline__ Chunk update_chunk(const TabRegs& tab, const RngKey& key, uint32_t t,
-                                              uint32_t c, uint32_t jbase, const Chunk& o,
-                                              const uint32_t kk[4], PendingTies& pend) {
-  const Rand4 rp = philox(jbase >> 4, t, key.replica, tag(c, kIsingPrefix), key.k0, key.k1);
-  uint32_t nw[4], tie7[4], anytie = 0;
+// 16-bit mask (bit 4w + b) of the tie flags of a chunk.
+__device__ __forceinline__ uint32_t tie_mask16(const uint32_t tie[4]) {
+  uint32_t m = 0;
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
-    nw[w] = decide4_fast(tab.th_lo, tab.th_hi, tab.al_lo, tab.al_hi, o.w[w], kk[w], rp.w[w], tie7[w]);
-    anytie |= tie7[w];
+    const uint32_t t7 = tie[w] & kHigh;
+    m |= (((t7 >> 7) | (t7 >> 14) | (t7 >> 21) | (t7 >> 28)) & 0xFu) << (4 * w);
   }
-  if (anytie) handle_ties<DEFER>(tab, key, t, c, jbase, kk, rp, tie7, nw, pend);
+  return m;
+}
+
+__device__ __forceinline__ uint32_t word_of(const uint32_t v[4], uint32_t w) {
+  const uint32_t b0 = w & 1u, b1 = (w >> 1) & 1u;
+  return mask_sel(mask_sel(v[0], v[1], b0), mask_sel(v[2], v[3], b0), b1);
+}
+
+// Metropolis update of one chunk with its ties resolved on the spot by the
+// sites' refinement draws (used where the new spins are read again within
+// the same launch).
+__device__ __forceinline__ Chunk update_chunk_now(const TabRegs& tab, const RngKey& key,
+                                                  uint32_t t, uint32_t c, uint32_t jbase,
+                                                  const Chunk& o, const uint32_t kk[4]) {
+  const Rand4 rp = philox(jbase >> 4, t, key.replica, tag(c, kIsingPrefix), key.k0, key.k1);
+  uint32_t nw[4], tie[4];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) nw[w] = decide4_tie(tab, o.w[w], kk[w], rp.w[w], tie[w]);
+  if ((tie[0] | tie[1] | tie[2] | tie[3]) & kHigh) {
+    uint32_t m = tie_mask16(tie);
+    do {
+      const uint32_t idx = __builtin_ctz(m);
+      m &= m - 1;
+      const uint32_t w = idx >> 2, sh = 8 * (idx & 3u);
+      const uint32_t k = (word_of(kk, w) >> sh) & 0xFu;
+      const Rand4 rr = philox(jbase + idx, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
+      if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) {
+        const uint32_t f = 0xFEu << sh;
+        nw[0] ^= w == 0 ? f : 0u;
+        nw[1] ^= w == 1 ? f : 0u;
+        nw[2] ^= w == 2 ? f : 0u;
+        nw[3] ^= w == 3 ? f : 0u;
+      }
+    } while (m);
+  }
   Chunk n;
   n.w[0] = nw[0]; n.w[1] = nw[1]; n.w[2] = nw[2]; n.w[3] = nw[3];
   return n;
 }
 
-// Resolve a lane's queued ties against its own colour plane (bytes of plane
-// `own` that no other lane of the launch touches).  Returns the change of the
-// unsatisfied-bond sum of the flipped sites' energy and of their spin sum
-// through dE / dM (for a fused measurement).
+// Ties of one lane deferred to the end of its band: 16-bit entries in LDS
+// (slot i of lane l at slot[i * stride]), each holding the row within the
+// band (6 bits), the site within the chunk (4 bits), the class k (3 bits) and
+// whether the spin was -1 (1 bit).  Site of an entry: base + row * R + site.
+// Deferring is exact because no update of the same colour reads the site.
+constexpr uint32_t kTieSlots = 32;
+
+struct TieQueue {
+  uint16_t* slot;   // this lane's first slot
+  uint32_t stride;  // slots of one lane are `stride` entries apart
+  uint32_t n;       // queued entries
+  uint32_t base;    // plane offset of the lane's chunk in row 0 of the band
+  uint32_t R;       // plane row length
+  int64_t dE;       // change of the unsatisfied-bond sum by resolved flips
+  int64_t dM;       // change of the spin sum
+};
+
+// Draw the refinement of every queued tie and flip the accepted sites in the
+// plane `own` (bytes only this lane touches in this launch).
 template <int D>
-__device__ __forceinline__ void resolve_pending(const PendingTies& pend, const TabRegs& tab,
-                                                const RngKey& key, uint32_t t, uint32_t c,
-                                                int8_t* own, int64_t& dE, int64_t& dM) {
-  for (uint32_t e = 0; e < pend.n; ++e) {
-    const uint32_t js = e == 0 ? pend.j[0] : (e == 1 ? pend.j[1] : (e == 2 ? pend.j[2] : pend.j[3]));
-    const uint32_t k = (pend.k >> (4 * e)) & 0xFu;
+__device__ __forceinline__ void tie_flush(TieQueue& q, const TabRegs& tab, const RngKey& key,
+                                       uint32_t t, uint32_t c, int8_t* own) {
+  for (uint32_t i = 0; i < q.n; ++i) {
+    const uint32_t e = q.slot[i * q.stride];
+    const uint32_t js = q.base + (e >> 4 & 63u) * q.R + (e & 15u);
+    const uint32_t k = e >> 10 & 7u;
     const Rand4 rr = philox(js, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
     if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) {
-      const int8_t v = own[js];
+      const int v = (e >> 13 & 1u) ? -1 : 1;
       own[js] = (int8_t)(-v);
-      dE += 4 * (int64_t)(D - (int)k);  // all 2d bonds of the site change sign
-      dM -= 2 * (int64_t)v;
+      q.dE += 4 * (int64_t)(D - (int)k);  // all 2d bonds of the site change sign
+      q.dM -= 2 * (int64_t)v;
     }
   }
+  q.n = 0;
+}
+
+// Metropolis update of one chunk (plane row `row` of the band) with its ties
+// queued; a full queue is flushed first.
+template <int D>
+__device__ __forceinline__ Chunk update_chunk_deferred(const TabRegs& tab, const RngKey& key,
+                                                       uint32_t t, uint32_t c, uint32_t jbase,
+                                                       uint32_t row, const Chunk& o,
+                                                       const uint32_t kk[4], TieQueue& q,
+                                                       int8_t* own) {
+  const Rand4 rp = philox(jbase >> 4, t, key.replica, tag(c, kIsingPrefix), key.k0, key.k1);
+  Chunk n;
+  uint32_t tie[4];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) n.w[w] = decide4_tie(tab, o.w[w], kk[w], rp.w[w], tie[w]);
+  if ((tie[0] | tie[1] | tie[2] | tie[3]) & kHigh) {
+    uint32_t m = tie_mask16(tie);
+    do {
+      if (q.n == kTieSlots) tie_flush<D>(q, tab, key, t, c, own);
+      const uint32_t idx = __builtin_ctz(m);
+      m &= m - 1;
+      const uint32_t w = idx >> 2, sh = 8 * (idx & 3u);
+      const uint32_t k = (word_of(kk, w) >> sh) & 7u;
+      const uint32_t neg = (word_of(o.w, w) >> (sh + 1)) & 1u;  // bit 1 set for -1
+      q.slot[q.n * q.stride] = (uint16_t)((row << 4) | idx | (k << 10) | (neg << 13));
+      q.n += 1;
+    } while (m);
+  }
+  return n;
 }
 
 // Sum of the +-1 spins of a chunk.
@@ -402,8 +342,14 @@ __device__ __forceinline__ void chunk_counts(const Geom& g, const int8_t* __rest
     nzp = ld16(oth + off_zp);
   }
   // neighbours at x+1 / x-1
-  const Chunk& nxp = p ? sh : ctr;
-  const Chunk& nxm = p ? ctr : sh;
+  // (by value through masks: a conditional reference would put the chunks
+  // in scratch memory)
+  Chunk nxp, nxm;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    nxp.w[w] = mask_sel(ctr.w[w], sh.w[w], p);
+    nxm.w[w] = mask_sel(sh.w[w], ctr.w[w], p);
+  }
 
   Chunk jxp{}, jxm{}, jyp{}, jym{}, jzp{}, jzm{};
   if (PM) {

@@ -23,14 +23,15 @@
 namespace smc {
 
 template <bool MEASURE>
-__global__ __launch_bounds__(1024) void ising_fused2d_kernel(const Geom g, const RngKey key,
+__global__ __launch_bounds__(512) void ising_fused2d_kernel(const Geom g, const RngKey key,
                                                              const IsingTable table,
                                                              const uint32_t H,
                                                              const int8_t* __restrict__ A,
                                                              int8_t* __restrict__ B,
                                                              const uint32_t t,
                                                              Partial* __restrict__ parts) {
-  __shared__ uint32_t edge[2][2][1024];  // [step parity][old colour-1 row, new colour-0 row][lane]
+  __shared__ uint32_t edge[2][2][512];  // [step parity][old colour-1 row, new colour-0 row][lane]
+  extern __shared__ uint16_t tie_slots[];  // kTieSlots entries per lane
   const int8_t* A0 = A;
   const int8_t* A1g = A + g.Nh;
   int8_t* B0 = B;
@@ -54,10 +55,14 @@ __global__ __launch_bounds__(1024) void ising_fused2d_kernel(const Geom g, const
   int64_t Esum = 0, Msum = 0;
   // colour-1 ties are queued (nothing in this launch reads the new colour 1);
   // colour-0 ties are resolved at once (the new colour 0 feeds colour 1)
-  PendingTies pend;
-  pend.k = 0;
-  pend.n = 0;
-  pend.j[0] = pend.j[1] = pend.j[2] = pend.j[3] = 0;
+  TieQueue tq;
+  tq.slot = tie_slots + q;
+  tq.stride = Q;
+  tq.n = 0;
+  tq.base = y0 * R + col;
+  tq.R = R;
+  tq.dE = 0;
+  tq.dM = 0;
 
   // One step at row y = y0 + i (y & 3 == PH): new colour 0 at row y, then
   // (i >= 1) new colour 1 at row y - 1; then refill the dead ring slots with
@@ -82,7 +87,7 @@ __global__ __launch_bounds__(1024) void ising_fused2d_kernel(const Geom g, const
     uint32_t kk[4];
     counts2d(a0c, a1c, sha, a1m, a1p, kk);
     const uint32_t off0 = frow(y);
-    N0[PH] = update_chunk<false>(tab, key, t, 0u, off0, a0c, kk, pend);
+    N0[PH] = update_chunk_now(tab, key, t, 0u, off0, a0c, kk);
     const Chunk& n0c = N0[PH];
     if (store0) {
       st16(B0 + off0, n0c.w);
@@ -93,7 +98,7 @@ __global__ __launch_bounds__(1024) void ising_fused2d_kernel(const Geom g, const
       const uint32_t off1 = frow(y + L - 1);
       const Chunk shn = p ? shift_next(n0m1, e_n) : shift_prev(n0m1, e_n);
       counts2d(a1m, n0m1, shn, n0m2, n0c, kk);
-      const Chunk n1 = update_chunk<true>(tab, key, t, 1u, off1, a1m, kk, pend);
+      const Chunk n1 = update_chunk_deferred<2>(tab, key, t, 1u, off1, y - 1 - y0, a1m, kk, tq, B1);
       st16(B1 + off1, n1.w);
       if (MEASURE) {
         uint32_t kn[4];
@@ -120,7 +125,7 @@ __global__ __launch_bounds__(1024) void ising_fused2d_kernel(const Geom g, const
     const Chunk sh = shift_next(A1[3], edge[1][0][qn]);
     uint32_t kk[4];
     counts2d(A0r[1], A1[3], sh, A1[2], A1[0], kk);
-    N0[3] = update_chunk<false>(tab, key, t, 0u, frow(y0 + L - 1), A0r[1], kk, pend);
+    N0[3] = update_chunk_now(tab, key, t, 0u, frow(y0 + L - 1), A0r[1], kk);
     A1[2] = ld16(A1g + frow(y0 + 2));
     A0r[1] = ld16(A0 + frow(y0 + 1));
   }
@@ -133,19 +138,16 @@ __global__ __launch_bounds__(1024) void ising_fused2d_kernel(const Geom g, const
   }
   // last step: new colour 0 at row y0 + H (formed, not stored), colour 1 at y0 + H - 1
   step(std::integral_constant<int, 0>(), y0 + H, false, true);
-  {
-    int64_t dE = 0, dM = 0;
-    resolve_pending<2>(pend, tab, key, t, 1u, B1, dE, dM);
-    Esum += dE;
-    Msum += dM;
-  }
+  tie_flush<2>(tq, tab, key, t, 1u, B1);
+  Esum += tq.dE;
+  Msum += tq.dM;
   if (MEASURE) block_partial_int(Esum, Msum, parts, blockIdx.x);
 }
 
 bool ising_fused_supported(const Geom& g, int J_kind, uint32_t H) {
   const uint32_t Q = (uint32_t)(g.R / 16);
-  return g.d == 2 && J_kind == 0 && g.L % 32 == 0 && Q % 64 == 0 && Q <= 1024 && H >= 4 &&
-         H % 4 == 0 && g.L % H == 0 && g.L / H >= 2;
+  return g.d == 2 && J_kind == 0 && g.L % 32 == 0 && Q % 64 == 0 && Q <= 512 && H >= 4 &&
+         H <= 64 && H % 4 == 0 && g.L % H == 0 && g.L / H >= 2;
 }
 
 // Rows per band: the largest divisor of L up to 64 leaving at least
@@ -164,12 +166,13 @@ hipError_t launch_ising_sweep_fused(const IsingLaunch& a, const int8_t* src, int
   const uint32_t H = a.rows_per_band;
   const uint32_t Q = (uint32_t)(a.g.R / 16);
   const dim3 grid((unsigned)(a.g.L / H)), block(Q);
+  const size_t lds = (size_t)Q * kTieSlots * sizeof(uint16_t);
   if (partials) {
-    hipLaunchKernelGGL(ising_fused2d_kernel<true>, grid, block, 0, st, a.g, a.key, a.tab, H, src,
+    hipLaunchKernelGGL(ising_fused2d_kernel<true>, grid, block, lds, st, a.g, a.key, a.tab, H, src,
                        dst, t, (Partial*)partials);
     if (nparts) *nparts = grid.x;
   } else {
-    hipLaunchKernelGGL(ising_fused2d_kernel<false>, grid, block, 0, st, a.g, a.key, a.tab, H, src,
+    hipLaunchKernelGGL(ising_fused2d_kernel<false>, grid, block, lds, st, a.g, a.key, a.tab, H, src,
                        dst, t, (Partial*)nullptr);
   }
   return hipGetLastError();

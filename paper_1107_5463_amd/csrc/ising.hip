@@ -123,32 +123,10 @@ __global__ __launch_bounds__(256) void ising_chunk_kernel(const Geom g, const Rn
   uint32_t kk[4];
   chunk_counts<D, PM>(g, s, J, divQ, divL, c, gid, base, o, ctr, kk);
   int8_t* own = s + (int64_t)c * g.Nh;
-  const Rand4 rp = philox((uint32_t)(base >> 4), t, key.replica, tag(c, kIsingPrefix), key.k0,
-                          key.k1);
-  uint32_t nw[4], tie[4];
-  uint32_t tie_any = 0;
-#pragma unroll
-  for (int w = 0; w < 4; ++w) {
-    nw[w] = decide4(tab, o.w[w], kk[w], rp.w[w], tie[w]);
-    tie_any |= tie[w];
-  }
-  if (tie_any) {
-    // rare: some prefix byte equals its threshold byte on an uphill move;
-    // resolve exactly with the site's 24-bit refinement draw
-#pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      if (!tie[w]) continue;
-      for (int b = 0; b < 4; ++b) {
-        const uint32_t k = (kk[w] >> (8 * b)) & 0xFFu;
-        const uint32_t P = (rp.w[w] >> (8 * b)) & 0xFFu;
-        if (P != table_byte(tab.th_lo, tab.th_hi, k) || table_byte(tab.al_lo, tab.al_hi, k))
-          continue;
-        const uint32_t jsite = (uint32_t)base + 4u * w + b;
-        const Rand4 rr = philox(jsite, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
-        if ((rr.w[0] & 0xFFFFFFu) < frac_of(tab, k)) nw[w] ^= 0xFEu << (8 * b);
-      }
-    }
-  }
+  // rare prefix ties on uphill moves are resolved exactly by the sites'
+  // 24-bit refinement draws
+  const Chunk n = update_chunk_now(tab_regs(tab), key, t, c, (uint32_t)base, o, kk);
+  const uint32_t nw[4] = {n.w[0], n.w[1], n.w[2], n.w[3]};
   st16(own + base, nw);
 }
 
@@ -171,6 +149,7 @@ __global__ __launch_bounds__(256) void ising_stream_kernel(const Geom g, const R
                                                            int8_t* __restrict__ s,
                                                            const uint32_t t, const uint32_t c,
                                                            Partial* __restrict__ parts) {
+  __shared__ uint16_t tie_slots[kTieSlots * 256];
   const uint32_t tid = xcd_remap(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
   const uint32_t band = fdiv(tid, divQ);
   int64_t Esum = 0, Msum = 0;
@@ -205,10 +184,14 @@ __global__ __launch_bounds__(256) void ising_stream_kernel(const Geom g, const R
     }
     auto zoff = [&](uint32_t zr, uint32_t y) -> uint32_t { return (zr + (y >= L ? y - L : y)) * R + col; };
     const TabRegs tab = tab_regs(table);
-    PendingTies pend;
-    pend.k = 0;
-    pend.n = 0;
-    pend.j[0] = pend.j[1] = pend.j[2] = pend.j[3] = 0;
+    TieQueue tq;
+    tq.slot = tie_slots + threadIdx.x;
+    tq.stride = 256;
+    tq.n = 0;
+    tq.base = roff(y0) + col;
+    tq.R = R;
+    tq.dE = 0;
+    tq.dM = 0;
 
     // Software pipeline: slot y & 3 of Ro holds the other colour's row y,
     // slot y & 1 of Ow / Ed / Fz / Bz our own row y, its edge word and its
@@ -253,7 +236,7 @@ __global__ __launch_bounds__(256) void ising_stream_kernel(const Geom g, const R
           kk[w] = k2 >> 1;
         }
         // rare exact ties are queued and resolved at the end of the band
-        const Chunk nc = update_chunk<true>(tab, key, t, c, jbase, o, kk, pend);
+        const Chunk nc = update_chunk_deferred<D>(tab, key, t, c, jbase, i + ph, o, kk, tq, own);
         uint32_t nw[4] = {nc.w[0], nc.w[1], nc.w[2], nc.w[3]};
         st16(own + jbase, nw);
         if (MEASURE) {
@@ -286,11 +269,10 @@ __global__ __launch_bounds__(256) void ising_stream_kernel(const Geom g, const R
     }
     // deferred ties: the site belongs to this lane's column of its own colour,
     // which no other lane of this launch touches
-    int64_t dE = 0, dM = 0;
-    resolve_pending<D>(pend, tab, key, t, c, own, dE, dM);
+    tie_flush<D>(tq, tab, key, t, c, own);
     if (MEASURE) {
-      Esum += dE;
-      Msum += dM;
+      Esum += tq.dE;
+      Msum += tq.dM;
     }
   }
   if (MEASURE) block_partial_int(Esum, Msum, parts, blockIdx.x);
@@ -340,7 +322,7 @@ static hipError_t launch_chunk(const IsingLaunch& a, int8_t* spins, uint32_t t, 
 uint32_t stream_rows_per_band(const Geom& g, uint32_t min_waves) {
   const uint32_t Q = (uint32_t)(g.R / 16);
   uint32_t best = 4;
-  for (uint32_t H = 4; H <= 64; H *= 2) {
+  for (uint32_t H = 4; H <= 64; H *= 2) {  // the tie queue holds rows < 64
     if (g.L % H) break;
     const uint64_t waves = (uint64_t)Q * (uint64_t)(g.rows / H) / 64;
     if (waves >= min_waves) best = H;

@@ -364,7 +364,7 @@ int smc_init_lattice(smc_lattice** out, const smc_params* p, void* spins, void* 
   h->rows_per_band = stream_rows_per_band(h->g, 8192);
   if (const char* v = std::getenv("SMC_STREAM_ROWS")) {
     const long H = std::strtol(v, nullptr, 10);
-    if (H >= 1 && H <= h->g.L && h->g.L % H == 0) h->rows_per_band = (uint32_t)H;
+    if (H >= 1 && H <= 64 && H <= h->g.L && h->g.L % H == 0) h->rows_per_band = (uint32_t)H;
   }
   h->obs_slot = h->ws;
   h->counter = (uint32_t*)(h->ws + kAlign);
@@ -374,7 +374,7 @@ int smc_init_lattice(smc_lattice** out, const smc_params* p, void* spins, void* 
   h->fused_rows = fused_rows_per_band(h->g, 1024);
   if (const char* v = std::getenv("SMC_FUSED_ROWS")) {
     const long H = std::strtol(v, nullptr, 10);
-    if (H >= 1 && H <= h->g.L && h->g.L % H == 0) h->fused_rows = (uint32_t)H;
+    if (H >= 1 && H <= 64 && H <= h->g.L && h->g.L % H == 0) h->fused_rows = (uint32_t)H;
   }
   h->use_fused = p->n == 1 && (p->flags & SMC_FLAG_SCHEDULE_FUSED) &&
                  !(p->flags & SMC_FLAG_GENERIC_KERNEL) &&
