@@ -1,106 +1,286 @@
 #!/usr/bin/env python3
 """Throughput of the checkerboard Metropolis sweep on one MI355X.
 
-Workload (the throughput configuration of the method, Sec. 2 / Table 1 of the
-paper): 2D Ising model, L = 16384 (N = 2^28 int8 spins), J = 1, hot start from
-seed 2, beta = 0.4406868, 1000 sweeps with energy and magnetisation measured
-every 10 sweeps.  One step = 10 sweeps + one measurement written to a device
-ring (no host synchronisation inside the timed region).
+Default workload (the throughput configuration of the method, Sec. 2 /
+Table 1 of the paper): 2D Ising model, L = 16384 (N = 2^28 int8 spins),
+J = 1, hot start from seed 2, beta = 0.4406868, 1000 sweeps with energy and
+magnetisation measured every 10 sweeps.  One step = 10 sweeps + one
+measurement written to a device ring (no host synchronisation inside the
+timed region).  Other workloads (--workload): 3D Ising L = 512, 2D XY
+L = 4096, 3D Heisenberg L = 256 (FP32 spins), and the batched +-J spin
+glass (2048 lattices of L in {8,12,16,24,32}, 32 temperatures).
 
 Prints one JSON line:
   value     spin-flip attempts per ns over the whole timed region;
-  roofline  the half-sweep kernel (the dominant kernel): algorithmic HBM bytes
-            per launch (own plane read + write, other plane read) over its
-            average duration, measured with HIP events on the kernel's stream
-            inside the timed region, against the 8 TB/s HBM peak;
+  roofline  the dominant kernel: algorithmic HBM bytes per launch over its
+            average duration (step time over kernel launches, measured with
+            HIP events on the kernel's stream inside the timed region), against
+            the 8 TB/s HBM peak; `traffic` is the HBM bytes per launch read
+            from the committed rocprofv3 counter summary when it was taken on
+            the current kernel sources, else null;
   cpu_baseline  the FP64 CPU oracle timed on the host on a bounded sample of
-            the same workload (the first sweeps of the same lattice), whose
-            E and M are also compared with the GPU's after the same sweeps.
+            the same workload, whose result is also compared with the GPU's.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
 import time
 
-BETA = 0.4406868
+ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
+# 64 lanes x 256 CUs x 2.4 GHz: one 32-bit integer VALU op per lane per clock
+VALU_PEAK_TOPS = 64 * 256 * 2.4e9 / 1e12
+
+# Proposal widths giving 50 +- 5 % acceptance at the benchmark temperatures
+# (found with the oracle on small lattices; checked by a CPU test).
+XY_DELTA = 1.63        # rotation angle uniform in [-delta, delta]
+HEIS_DELTA = 2.058     # half-angle of the spherical cap
+
+WORKLOADS = {
+    "ising2d": dict(d=2, n=1, L=16384, seed=2, beta=0.4406868),
+    "ising3d": dict(d=3, n=1, L=512, seed=3, beta=0.2216546),
+    "xy": dict(d=2, n=2, L=4096, seed=5, beta=1.12, delta=XY_DELTA, renorm=100),
+    "heisenberg": dict(d=3, n=3, L=256, seed=6, beta=0.693, delta=HEIS_DELTA, renorm=100),
+    "batched": dict(d=3, n=1, lattices=2048, Ls=(8, 12, 16, 24, 32), seed=4, betas=32,
+                    beta_lo=0.5, beta_hi=3.0),
+}
+
+# Source files of each dominant kernel (a counter summary is valid only for
+# the sources it was taken on).
+KERNEL_SOURCES = {
+    "ising_stream": ["ising.hip", "chunk.hpp", "device.hpp", "kernels.hpp", "reduce.hpp"],
+    "ising_fused": ["fused.hip", "chunk.hpp", "device.hpp", "kernels.hpp", "reduce.hpp"],
+}
 
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100, help="timed steps (10 sweeps + 1 measurement each)")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="ising2d")
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps of 10 sweeps + 1 measurement (default: 100, i.e. 1000 "
+                         "sweeps; batched: 1000, i.e. 10^4 sweeps)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--sweeps-per-step", type=int, default=10)
-    ap.add_argument("--L", type=int, default=16384)
-    ap.add_argument("--d", type=int, default=2)
-    ap.add_argument("--seed", type=int, default=2)
-    ap.add_argument("--beta", type=float, default=BETA)
-    ap.add_argument("--schedule", choices=["fused", "two-pass"], default="fused",
-                    help="fused: one kernel per sweep with ping-pong buffers (2 B/attempt); "
-                         "two-pass: one in-place kernel per colour (3 B/attempt)")
-    ap.add_argument("--cpu-sweeps", type=int, default=12, help="oracle sweeps for the CPU baseline (0 = skip)")
+    ap.add_argument("--schedule", choices=["fused", "two-pass"], default="two-pass",
+                    help="2D Ising only -- fused: one kernel per sweep with ping-pong buffers "
+                         "(2 B/attempt); two-pass: one in-place kernel per colour (3 B/attempt)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="approximate host time of the oracle baseline (0 = skip)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one 1 GiB device copy before the timed region (calibrates the "
+                         "HBM byte counters of a profiler run)")
     return ap.parse_args()
 
 
-def main():
-    args = parse()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU (slab "
-                                   "halo-exchange) path is not built", "n_gpus": args.gpus}))
-        sys.exit(2)
-    import torch
+def sources_digest(kernel):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(kernel, []):
+        with open(os.path.join(ROOT, "paper_1107_5463_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
-    import paper_1107_5463_amd as smc
 
-    smc.load_library()
-    d, L = args.d, args.L
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current sources of the kernel."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("sources_sha256_16") != sources_digest(kernel):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def copy_probe(torch, device):
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device=device).fill_(1)
+    b = torch.empty(n, dtype=torch.uint8, device=device)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def oracle_rate(fn, attempts_per_call, budget_s):
+    """Calls fn until budget_s has passed (at least once); attempts/ns."""
+    t0 = time.perf_counter()
+    calls = 0
+    while True:
+        fn()
+        calls += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            return calls * attempts_per_call / (el * 1e9), calls, el
+
+
+def run_lattice(args, wl, torch, smc):
+    d, n, L = wl["d"], wl["n"], wl["L"]
     N = L ** d
-    fused = args.schedule == "fused"
-    lat = smc.Lattice(d, 1, L, seed=args.seed, fused=fused)
+    fused = args.schedule == "fused" and n == 1
+    kw = {}
+    if n > 1:
+        kw = dict(delta=wl["delta"], renorm_every=wl["renorm"])
+    lat = smc.Lattice(d, n, L, seed=wl["seed"], fused=fused, **kw)
+    if args.copy_probe:
+        copy_probe(torch, lat.device)
     st = lat.stream
-    K, W, S = args.steps, args.warmup, args.sweeps_per_step
+    K = args.steps if args.steps is not None else 100
+    W, S = args.warmup, args.sweeps_per_step
+    beta = wl["beta"]
     ring = torch.zeros((max(K, 1), 8), dtype=torch.int64, device=lat.device)
-
     for _ in range(W):
-        lat.sweep_measure(args.beta, S, ring[0])
+        lat.sweep_measure(beta, S, ring[0])
     torch.cuda.synchronize()
 
     ev_start = torch.cuda.Event(enable_timing=True)
     ev_end = torch.cuda.Event(enable_timing=True)
-    ev_a = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    ev_b = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev_start.record(st)
     for k in range(K):
-        ev_a[k].record(st)
-        lat.sweep_measure(args.beta, S, ring[k])
-        ev_b[k].record(st)
+        lat.sweep_measure(beta, S, ring[k])
     ev_end.record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     total_ms = ev_start.elapsed_time(ev_end)
-    sweep_ms = sum(ev_a[k].elapsed_time(ev_b[k]) for k in range(K))
     sweeps = K * S
     attempts = N * sweeps
-    value = attempts / (total_ms * 1e6)
     kname, band_rows = lat.kernel()
     if kname == "ising_fused":
-        # each launch is one sweep: both colours read and written once
         launches, bytes_per_launch = sweeps, 2.0 * N
         schedule = "fused one-pass, ping-pong buffers"
-    else:
-        # each launch is one colour: own colour read + written, other colour read
+    elif n == 1:
         launches, bytes_per_launch = 2 * sweeps, 1.5 * N
         schedule = "two-pass colour-split, in place"
-    # step time includes the measurement finish kernel: a conservative kernel average
-    kernel_ms = sweep_ms / launches
+    else:
+        # own colour read + written and other colour read, n FP32 components
+        launches, bytes_per_launch = 2 * sweeps, 1.5 * N * n * 4
+        schedule = "two-pass colour-split, in place, FP32 components"
+    # the step time also holds the measurement finish (and renormalisation)
+    # kernels: a conservative average of the dominant kernel
+    kernel_ms = total_ms / launches
     achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
+    traffic = measured_traffic(kname, args.workload)
     obs = smc.Lattice.decode_obs(ring[K - 1:K])[0] if K else None
+    what = {1: "Ising", 2: "XY", 3: "Heisenberg"}[n]
+    result = {
+        "metric": "spin-flip attempts/ns + %HBM peak, 2D Ising L=16384; batched vs plain",
+        "value": round(attempts / (total_ms * 1e6), 2),
+        "unit": "attempts/ns",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(total_ms / max(K, 1), 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8" if n == 1 else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{d}D {what} L={L} (N={N}), J=1, beta={beta}, "
+                        f"{'hot' if n == 1 else 'random'} start seed {wl['seed']}, {sweeps} "
+                        f"checkerboard sweeps, E/M every {S} sweeps"
+                        + (f", delta={wl['delta']}, renormalise every {wl['renorm']}" if n > 1 else ""),
+            "d": d, "n": n, "L": L, "sweeps": sweeps, "measure_every": S,
+            "schedule": schedule, "kernel": kname, "rows_per_band": band_rows,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": kname,
+            "kernel_avg_us": round(kernel_ms * 1e3, 3),
+            "algorithmic_bytes_per_launch": int(bytes_per_launch),
+        },
+        "pct_hbm_peak": round(100 * achieved / HBM_PEAK_GBS, 2),
+        "wall_s": round(wall, 3),
+        "final_obs": None if obs is None else {"E": obs.E, "M": list(obs.M[:n]), "sweep": obs.sweep},
+    }
 
+    if args.cpu_seconds > 0:
+        sys.path.insert(0, ROOT)
+        import oracle
+
+        kwo = {} if n == 1 else dict(delta=wl["delta"], renorm_every=wl["renorm"])
+        ref = oracle.OracleLattice(d, n, L, wl["seed"], **kwo)
+        rate, calls, el = oracle_rate(lambda: ref.sweep(beta, 1), N, args.cpu_seconds)
+        gpu = smc.Lattice(d, n, L, seed=wl["seed"], **kw)
+        gpu.sweep(beta, calls)
+        go, ro = gpu.measure(), ref.measure()
+        if n == 1:
+            parity = bool(go.E_int == ro.E_int and go.M_int == ro.M_int)
+            pname = "parity_E_M_after_sample"
+        else:
+            # FP32 chains leave the FP64 one after a few sweeps (near-threshold
+            # decisions); report the relative energy difference instead
+            parity = round(abs(go.E - ro.E) / max(1.0, abs(ro.E)), 6)
+            pname = "rel_E_diff_after_sample"
+        result["cpu_baseline"] = {
+            "value": round(rate, 4),
+            "unit": "attempts/ns",
+            "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"first {calls} sweeps of the same {d}D L={L} lattice from the same start "
+                      f"({N * calls} attempts, {el:.1f} s)",
+            pname: parity,
+        }
+    return result
+
+
+def run_batched(args, wl, torch, smc):
+    d, nl = wl["d"], wl["lattices"]
+    Ls = [wl["Ls"][r % len(wl["Ls"])] for r in range(nl)]
+    betas = [wl["beta_lo"] + (wl["beta_hi"] - wl["beta_lo"]) * (r % wl["betas"]) / (wl["betas"] - 1)
+             for r in range(nl)]
+    sites = sum(L ** d for L in Ls)
+    b = smc.Batch(d, Ls, betas, seed=wl["seed"], J_kind=smc.J_PM)
+    threads, largest_first = b.autotune()
+    b.use_graph(True)
+    st = b.stream
+    K = args.steps if args.steps is not None else 1000
+    W, S = args.warmup, args.sweeps_per_step
+    obs = torch.zeros((nl, 8), dtype=torch.int64, device=b.device)
+    for _ in range(W):
+        b.sweep(S, obs)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(st)
+    for _ in range(K):
+        b.sweep(S, obs)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = ev0.elapsed_time(ev1)
+    sweeps = K * S
+    value = sites * sweeps / (total_ms * 1e6)
+
+    # plain: the same kind of lattices one at a time through the single-lattice path
+    plain_lats = [smc.Lattice(d, 1, Ls[r], seed=wl["seed"], J_kind=smc.J_PM, replica=r)
+                  for r in range(2 * len(wl["Ls"]))]
+    ps = 20
+    for lt, r in zip(plain_lats, range(len(plain_lats))):
+        lt.sweep(betas[r], 2)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(plain_lats[0].stream)
+    for lt, r in zip(plain_lats, range(len(plain_lats))):
+        lt.sweep(betas[r], ps)
+    e1.record(plain_lats[0].stream)
+    torch.cuda.synchronize()
+    plain_ms = e0.elapsed_time(e1)
+    plain_value = sum(lt.N for lt in plain_lats) * ps / (plain_ms * 1e6)
+
+    # spins + couplings cross HBM once per call (staged in LDS for all sweeps)
+    cbytes = sum(L ** d for L in Ls) * (1 + d)
     result = {
         "metric": "spin-flip attempts/ns + %HBM peak, 2D Ising L=16384; batched vs plain",
         "value": round(value, 2),
@@ -115,49 +295,72 @@ def main():
         "dtype": "i8",
         "data": "synthetic",
         "config": {
-            "workload": f"{d}D Ising L={L} (N={N}), J=1, beta={args.beta}, hot start seed {args.seed}, "
-                        f"{sweeps} checkerboard sweeps, E/M every {S} sweeps",
-            "d": d, "L": L, "sweeps": sweeps, "measure_every": S,
-            "schedule": schedule,
-            "kernel": kname,
-            "rows_per_band": band_rows,
+            "workload": f"batched 3D +-J Edwards-Anderson: {nl} lattices, L in {list(wl['Ls'])} "
+                        f"(lattice r has L[r % 5]), beta_r = 0.5 + 2.5 (r % 32) / 31, seed "
+                        f"{wl['seed']}, {sweeps} sweeps, E/M of every lattice every {S} sweeps",
+            "sites": sites, "sweeps": sweeps, "threads_per_lattice": threads,
+            "largest_first": largest_first, "graph": True,
         },
+        "plain": {"value": round(plain_value, 3), "unit": "attempts/ns",
+                  "sample": f"{len(plain_lats)} of the lattices, one single-lattice sweep call "
+                            f"each, {ps} sweeps"},
+        "batched_vs_plain": round(value / plain_value, 1),
         "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "bound": "alu",
+            "achieved": None,
+            "peak": round(VALU_PEAK_TOPS, 2),
+            "unit": "Tops/s",
+            "frac": None,
             "traffic": None,
-            "kernel_avg_us": round(kernel_ms * 1e3, 3),
-            "algorithmic_bytes_per_launch": int(bytes_per_launch),
+            "kernel": "batch",
+            "kernel_avg_us": round(total_ms * 1e3 / max(K, 1), 3),
+            "hbm_bytes_per_launch": 2 * cbytes,
         },
-        "pct_hbm_peak": round(100 * achieved / HBM_PEAK_GBS, 2),
         "wall_s": round(wall, 3),
-        "final_obs": None if obs is None else {"E_int": obs.E_int, "M_int": obs.M_int},
     }
-
-    if args.cpu_sweeps > 0:
-        sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    if args.cpu_seconds > 0:
+        sys.path.insert(0, ROOT)
         import oracle
 
-        ref = oracle.OracleLattice(d, 1, L, args.seed)
-        t1 = time.perf_counter()
-        ref.sweep(args.beta, args.cpu_sweeps)
-        cpu_s = time.perf_counter() - t1
-        cpu_value = N * args.cpu_sweeps / (cpu_s * 1e9)
-        gpu = smc.Lattice(d, 1, L, seed=args.seed)
-        gpu.sweep(args.beta, args.cpu_sweeps)
-        go, ro = gpu.measure(), ref.measure()
+        done = []
+        r = 0
+        t0 = time.perf_counter()
+        att = 0
+        while time.perf_counter() - t0 < args.cpu_seconds and r < nl:
+            ref = oracle.OracleLattice(d, 1, Ls[r], wl["seed"], J_kind=1, replica=r)
+            ref.sweep(betas[r], 200)
+            att += Ls[r] ** d * 200
+            done.append(r)
+            r += 1
+        el = time.perf_counter() - t0
         result["cpu_baseline"] = {
-            "value": round(cpu_value, 4),
+            "value": round(att / (el * 1e9), 4),
             "unit": "attempts/ns",
             "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": f"first {args.cpu_sweeps} sweeps of the same {d}D L={L} lattice from the same "
-                      f"hot start ({N * args.cpu_sweeps} attempts, {cpu_s:.1f} s)",
-            "parity_E_M_after_sample": bool(go.E_int == ro.E_int and go.M_int == ro.M_int),
+            "sample": f"lattices 0..{len(done) - 1} of the batch, 200 sweeps each ({att} attempts, "
+                      f"{el:.1f} s)",
         }
+    return result
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the multi-GPU (slab "
+                                   "halo-exchange) path is not built", "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import paper_1107_5463_amd as smc
+
+    smc.load_library()
+    wl = WORKLOADS[args.workload]
+    if args.workload == "batched":
+        result = run_batched(args, wl, torch, smc)
+    else:
+        result = run_lattice(args, wl, torch, smc)
     print(json.dumps(result), flush=True)
 
 

@@ -361,7 +361,7 @@ int smc_init_lattice(smc_lattice** out, const smc_params* p, void* spins, void* 
     h->ising_variant = s == "site" ? kVariantSite : s == "chunk" ? kVariantChunk
                      : s == "stream" ? kVariantStream : kVariantAuto;
   }
-  h->rows_per_band = stream_rows_per_band(h->g, 8192);
+  h->rows_per_band = stream_rows_per_band(h->g, 4096);
   if (const char* v = std::getenv("SMC_STREAM_ROWS")) {
     const long H = std::strtol(v, nullptr, 10);
     if (H >= 1 && H <= 64 && H <= h->g.L && h->g.L % H == 0) h->rows_per_band = (uint32_t)H;
