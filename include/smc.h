@@ -233,6 +233,60 @@ int smc_batch_get_sweep_index(const smc_batch* b, uint64_t* t);
 int smc_batch_set_sweep_index(smc_batch* b, uint64_t t);
 int smc_batch_destroy(smc_batch* b);
 
+/* ------------------------------------------------------------------------ */
+/* Chains: many independent Metropolis chains of one small Ising lattice    */
+/* with shared real couplings J_b, for the derivatives of the partition     */
+/* function of Eq. (1), Z = sum_s exp(beta sum_b J_b x_b), x_b = s_i s_j:    */
+/*   d ln Z / d J_b  = beta <x_b>,                                          */
+/*   d ln Z / d beta = sum_b J_b <x_b> = -<H>,                              */
+/*   d <x_a> / d J_b = beta Cov(x_a, x_b)   (fluctuation-dissipation).      */
+/* Chain k (0 <= k < n_chains) uses replica replica0 + k and follows         */
+/* exactly the single-lattice chain of smc_init_lattice with FP32 couplings  */
+/* (SMC_J_FP32) and that replica.  Bond b = (mu, c, j) couples site (c, j)   */
+/* and its +mu neighbour; arrays over bonds have the coupling layout         */
+/* [d][2][N/2].  2D: L a multiple of 4; 3D: L even; L^d (1 + 8 d) bytes must  */
+/* fit one workgroup's LDS (160 KiB): 2D L <= 96, 3D L <= 18.                */
+/* Buffers (caller-owned, device):                                          */
+/*   J      float [d][2][N/2], read at every call (may be changed between);  */
+/*   spins  int8, chain k's [2][N/2] planes at byte offset k N.              */
+/* ------------------------------------------------------------------------ */
+typedef struct smc_chains smc_chains;
+
+size_t smc_chains_spin_bytes(int32_t d, int32_t L, int32_t n_chains);
+size_t smc_chains_coupling_bytes(int32_t d, int32_t L);
+/* Bytes of an array over bonds of int64 or double: 8 d N. */
+size_t smc_chains_bond_bytes(int32_t d, int32_t L);
+/* Per-chain covariance partials: 8 d N n_chains + 16 n_chains bytes. */
+size_t smc_chains_workspace_bytes(int32_t d, int32_t L, int32_t n_chains);
+
+/* init HOT / COLD / KEEP (hot starts from (seed, replica0 + k)). */
+int smc_chains_init(smc_chains** out, int32_t d, int32_t L, int32_t n_chains, uint64_t seed,
+                    uint32_t replica0, int32_t init, const float* J, void* spins,
+                    void* workspace, size_t workspace_bytes, void* stream);
+
+/* n_sweeps sweeps of every chain (asynchronous).  With dev_bond_sum (int64
+ * [d][2][N/2], 8-byte aligned) the bond products x_b of every chain after
+ * every sweep are added to it: after the call it has grown by
+ * sum_{chains, sweeps} x_b.  NULL: sweeps only (burn-in). */
+int smc_chains_sample(smc_chains* h, double beta, int64_t n_sweeps, int64_t* dev_bond_sum);
+
+/* Replay of n_sweeps sampling sweeps from the current state and counter
+ * (asynchronous): for every chain and sweep, with the sample's
+ * G = sum_b g_b x_b - g_center, adds G x_b to dev_cov_acc[b] and G, G^2 to
+ * dev_G_acc[0], dev_G_acc[1] (double, 8-byte aligned; summed over chains in
+ * chain order, deterministic).  Started from the state and counter a
+ * smc_chains_sample call started from, it visits the same configurations,
+ * so that Cov(G, x_b) = cov_acc[b] / S - (G_acc[0] / S) <x_b> over its
+ * S = n_chains n_sweeps samples, and the vector-Jacobian product of the
+ * correlations is beta Cov(G, x_b).  g_center (e.g. sum_b g_b <x_b>) only
+ * conditions the sums. */
+int smc_chains_covariance(smc_chains* h, double beta, int64_t n_sweeps, const double* dev_g,
+                          double g_center, double* dev_cov_acc, double* dev_G_acc);
+
+int smc_chains_get_sweep_index(const smc_chains* h, uint64_t* t);
+int smc_chains_set_sweep_index(smc_chains* h, uint64_t t);
+int smc_chains_destroy(smc_chains* h);
+
 /* The calling thread's last error message ("" if none). */
 const char* smc_last_error(void);
 const char* smc_version(void);

@@ -217,6 +217,53 @@ class OracleLattice:
         return out
 
 
+def chains_ising(d: int, L: int, seed: int, J: np.ndarray, beta: float, s0: np.ndarray,
+                 n_sweeps: int, t0: int = 0, replica0: int = 0, want_samples: bool = False):
+    """Independent Ising chains with shared FP32 couplings J[mu][i] (natural
+    order); chain k uses replica replica0 + k and starts from s0[k].
+
+    Returns (final states [n, N], bond-product sums over chains and sweeps
+    [d, N] int64, per-sweep bond products [n, n_sweeps, d, N] int8 or None,
+    smallest decision margin)."""
+    s0 = np.ascontiguousarray(s0, dtype=np.int8)
+    n_chains, N = s0.shape
+    assert N == L ** d
+    Jf = np.ascontiguousarray(J, dtype=np.float32)
+    assert Jf.shape == (d, N)
+    p = _Params(d, 1, L, J_FP32, seed & 0xFFFFFFFFFFFFFFFF, replica0, 0, 1.0, 0.0, 0.0)
+    out = np.zeros((n_chains, N), dtype=np.int8)
+    bond_sum = np.zeros((d, N), dtype=np.int64)
+    samples = np.zeros((n_chains, n_sweeps, d, N), dtype=np.int8) if want_samples else None
+    mm = C.c_double(0.0)
+    f = lib().oracle_chains_ising
+    f.argtypes = [C.POINTER(_Params), C.c_void_p, C.c_void_p, C.c_double, C.c_uint64, C.c_int64,
+                  C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]
+    f.restype = C.c_int
+    rc = f(C.byref(p), s0.ctypes.data, Jf.ctypes.data, float(beta), int(t0), int(n_sweeps),
+           int(n_chains), out.ctypes.data, bond_sum.ctypes.data,
+           None if samples is None else samples.ctypes.data, C.byref(mm))
+    assert rc == 0, rc
+    return out, bond_sum, samples, float(mm.value)
+
+
+def init_ising(d: int, L: int, seed: int, replica: int = 0, hot: bool = True) -> np.ndarray:
+    """Start state of one Ising lattice (natural order) from (seed, replica)."""
+    p = _Params(d, 1, L, J_UNIFORM, seed & 0xFFFFFFFFFFFFFFFF, replica, 0, 1.0, 0.0, 0.0)
+    s = np.zeros(L ** d, dtype=np.int8)
+    assert lib().oracle_init_ising(C.byref(p), 1 if hot else 0, s.ctypes.data) == 0
+    return s
+
+
+def bond_covariance(samples: np.ndarray, g: np.ndarray):
+    """Sample covariance Cov(G, x_b) over all chains and sweeps, with x the
+    per-sweep bond products and G = sum_b g_b x_b: the definition, written out
+    (mean of G x_b minus the product of the means)."""
+    x = samples.reshape(-1, samples.shape[-2] * samples.shape[-1]).astype(np.float64)
+    G = x @ np.asarray(g, dtype=np.float64).reshape(-1)
+    cov = (G[:, None] * x).mean(axis=0) - G.mean() * x.mean(axis=0)
+    return cov.reshape(samples.shape[-2], samples.shape[-1])
+
+
 def ising_sweep_sites(lat: "OracleLattice", beta: float, t: int, sites) -> np.ndarray:
     """Spins of the given natural sites after one sweep with counter t, from
     lat.s as the state before the sweep (lat is not modified)."""

@@ -229,3 +229,41 @@ def xy_single_spin_mean(beta_h: float) -> float:
 def heisenberg_single_spin_mean(beta_h: float) -> float:
     """<s . h_hat> of a classical 3-vector in field h: coth(beta h) - 1/(beta h)."""
     return 1.0 / math.tanh(beta_h) - 1.0 / beta_h
+
+
+# --------------------------------------------------------------------------
+# Real couplings: bond moments of the L x L torus by enumeration
+# --------------------------------------------------------------------------
+
+def torus_bond_products(L: int) -> np.ndarray:
+    """x_b = s_i s_{i+mu} for every state of the L x L torus and every bond
+    b = (mu, i) (site i = x + L y to its +x (mu = 0) or +y (mu = 1)
+    neighbour): int8 [2^N, 2, N], state index bits as in enumerate_torus."""
+    N = L * L
+    assert N <= 20
+    states = np.arange(1 << N, dtype=np.int64)
+    spins = (1 - 2 * ((states[:, None] >> np.arange(N)[None, :]) & 1)).astype(np.int8)
+    x = np.empty((len(states), 2, N), dtype=np.int8)
+    for i in range(N):
+        cx, cy = i % L, i // L
+        x[:, 0, i] = spins[:, i] * spins[:, (cx + 1) % L + L * cy]
+        x[:, 1, i] = spins[:, i] * spins[:, cx + L * ((cy + 1) % L)]
+    return x
+
+
+def exact_bond_moments(L: int, J: np.ndarray, beta: float, x: np.ndarray | None = None):
+    """Boltzmann moments of the bond products on the L x L torus with per-bond
+    couplings J[mu][i]: weights exp(beta sum_b J_b x_b) (Eq. (1)).  Returns
+    (<x> [2, N], Cov(x_a, x_b) [2N, 2N], ln Z), in float64 with the weights
+    shifted by their maximum before exponentiation."""
+    if x is None:
+        x = torus_bond_products(L)
+    X = x.reshape(len(x), -1).astype(np.float64)
+    a = beta * (X @ np.asarray(J, dtype=np.float64).reshape(-1))
+    amax = a.max()
+    w = np.exp(a - amax)
+    Zs = w.sum()
+    p = w / Zs
+    mean = p @ X
+    cov = (X * p[:, None]).T @ X - np.outer(mean, mean)
+    return mean.reshape(2, L * L), cov, float(np.log(Zs) + amax)

@@ -660,6 +660,60 @@ ORACLE_API int oracle_ensemble_ising(const oracle_params *p, const int8_t *s0, c
   return 0;
 }
 
+/* Chains for derivatives of ln Z (Eq. (1)): n_chains independent chains of
+ * one small lattice, chain k with replica p->replica + k, its own start state
+ * s0[k] and the shared couplings J.  After every sweep the bond products
+ * s_i s_{i+mu} of every chain are added to bond_sum[mu][i] (natural order)
+ * and, if samples is not NULL, stored in samples[k][w][mu][i].  min_margin
+ * receives the smallest |u - exp(-beta dE)| over all uphill decisions (how
+ * close an FP32 implementation could come to deciding differently); it is
+ * +inf when no decision used a threshold. */
+ORACLE_API int oracle_chains_ising(const oracle_params *p, const int8_t *s0, const void *J,
+                                   double beta, uint64_t t0, int64_t n_sweeps, int64_t n_chains,
+                                   int8_t *out, int64_t *bond_sum, int8_t *samples,
+                                   double *min_margin) {
+  if (!valid(p) || p->n != 1 || n_sweeps < 0 || n_chains < 1) return -1;
+  if (t0 + (uint64_t)n_sweeps > 0x100000000ull) return -1;
+  int64_t N = n_sites(p);
+  int d = p->d;
+  int64_t *part = (int64_t *)calloc((size_t)(n_chains * d * N), sizeof(int64_t));
+  double *mins = (double *)malloc((size_t)n_chains * sizeof(double));
+  if (!part || !mins) { free(part); free(mins); return -2; }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t k = 0; k < n_chains; ++k) {
+    oracle_params q = *p;
+    q.replica = p->replica + (uint32_t)k;
+    int8_t *s = out + k * N;
+    memcpy(s, s0 + k * N, (size_t)N);
+    double *mg = (double *)malloc((size_t)N * sizeof(double));
+    double mn = INFINITY;
+    for (int64_t w = 0; w < n_sweeps; ++w) {
+      for (int c = 0; c < 2; ++c) {
+        half_sweep_ising(&q, s, J, beta, (uint32_t)(t0 + (uint64_t)w), c, NULL, mg);
+        for (int64_t i = 0; i < N; ++i)
+          if (colour_of(p, i) == c && !isnan(mg[i]) && fabs(mg[i]) < mn) mn = fabs(mg[i]);
+      }
+      for (int mu = 0; mu < d; ++mu)
+        for (int64_t i = 0; i < N; ++i) {
+          int8_t v = (int8_t)(s[i] * s[neighbour(p, i, mu, +1)]);
+          part[(k * d + mu) * N + i] += v;
+          if (samples) samples[((k * n_sweeps + w) * d + mu) * N + i] = v;
+        }
+    }
+    mins[k] = mn;
+    free(mg);
+  }
+  double mn = INFINITY;
+  for (int64_t k = 0; k < n_chains; ++k) {
+    for (int64_t b = 0; b < d * N; ++b) bond_sum[b] += part[k * d * N + b];
+    if (mins[k] < mn) mn = mins[k];
+  }
+  if (min_margin) *min_margin = mn;
+  free(part);
+  free(mins);
+  return 0;
+}
+
 ORACLE_API int oracle_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -21,7 +21,7 @@ import dataclasses
 import math
 import os
 
-__all__ = ["Lattice", "Batch", "SmcError", "load_library", "lib_path", "Obs", "J_UNIFORM", "J_PM",
+__all__ = ["Lattice", "Batch", "Chains", "SmcError", "load_library", "lib_path", "Obs", "J_UNIFORM", "J_PM",
            "J_FP32", "EXPORTS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -43,7 +43,11 @@ EXPORTS = ["smc_spin_bytes", "smc_coupling_bytes", "smc_workspace_bytes", "smc_b
            "smc_batch_spin_bytes", "smc_batch_coupling_bytes", "smc_batch_workspace_bytes",
            "smc_batch_offsets", "smc_batch_init", "smc_batch_sweep", "smc_batch_autotune",
            "smc_batch_use_graph", "smc_batch_get_sweep_index", "smc_batch_set_sweep_index",
-           "smc_batch_destroy"]
+           "smc_batch_destroy",
+           "smc_chains_spin_bytes", "smc_chains_coupling_bytes", "smc_chains_bond_bytes",
+           "smc_chains_workspace_bytes", "smc_chains_init", "smc_chains_sample",
+           "smc_chains_covariance", "smc_chains_get_sweep_index", "smc_chains_set_sweep_index",
+           "smc_chains_destroy"]
 
 
 class SmcError(RuntimeError):
@@ -128,6 +132,19 @@ def load_library():
     lib.smc_batch_get_sweep_index.argtypes = [vp, C.POINTER(C.c_uint64)]
     lib.smc_batch_set_sweep_index.argtypes = [vp, C.c_uint64]
     lib.smc_batch_destroy.argtypes = [vp]
+    for f in ("smc_chains_spin_bytes", "smc_chains_workspace_bytes"):
+        getattr(lib, f).argtypes = [C.c_int32, C.c_int32, C.c_int32]
+        getattr(lib, f).restype = sz
+    for f in ("smc_chains_coupling_bytes", "smc_chains_bond_bytes"):
+        getattr(lib, f).argtypes = [C.c_int32, C.c_int32]
+        getattr(lib, f).restype = sz
+    lib.smc_chains_init.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
+                                    C.c_uint32, C.c_int32, vp, vp, vp, sz, vp]
+    lib.smc_chains_sample.argtypes = [vp, C.c_double, C.c_int64, vp]
+    lib.smc_chains_covariance.argtypes = [vp, C.c_double, C.c_int64, vp, C.c_double, vp, vp]
+    lib.smc_chains_get_sweep_index.argtypes = [vp, C.POINTER(C.c_uint64)]
+    lib.smc_chains_set_sweep_index.argtypes = [vp, C.c_uint64]
+    lib.smc_chains_destroy.argtypes = [vp]
     lib.smc_last_error.restype = C.c_char_p
     lib.smc_version.restype = C.c_char_p
     for f in EXPORTS:
@@ -454,6 +471,95 @@ class Batch:
     @t.setter
     def t(self, value: int):
         _check(load_library().smc_batch_set_sweep_index(self._h, int(value)))
+
+
+class Chains:
+    """n_chains independent Metropolis chains of one small d-dimensional Ising
+    lattice with shared FP32 couplings J[mu][c][j] (bond from site (c, j) to
+    its +mu neighbour), for derivatives of ln Z.  Chain k uses replica
+    replica0 + k.  spins: int8 [n_chains, 2, N/2] (colour planes)."""
+
+    def __init__(self, d: int, L: int, n_chains: int, seed: int = 0, *, J=None,
+                 replica0: int = 0, init="hot", spins=None, device=None, stream=None):
+        import torch
+        lib = load_library()
+        self.torch = torch
+        self.d, self.L, self.n_chains = d, L, n_chains
+        self.N = L ** d
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        sb = lib.smc_chains_spin_bytes(d, L, n_chains)
+        if sb == 0:
+            h = C.c_void_p()
+            _check(lib.smc_chains_init(C.byref(h), d, L, n_chains, 0, 0, 0, None, None, None, 0,
+                                       None))
+        self.J = torch.ones((d, 2, self.N // 2), dtype=torch.float32, device=self.device)
+        if J is not None:
+            self.J.copy_(J)
+        self.spins = torch.zeros((n_chains, 2, self.N // 2), dtype=torch.int8, device=self.device)
+        init_k = INIT_KEEP if spins is not None else {"hot": INIT_HOT, "cold": INIT_COLD}[init]
+        if spins is not None:
+            self.spins.copy_(spins.view(n_chains, 2, self.N // 2))
+        wb = lib.smc_chains_workspace_bytes(d, L, n_chains)
+        self.workspace = torch.empty(wb + 256, dtype=torch.uint8, device=self.device)
+        ws = self.workspace.data_ptr() + (-self.workspace.data_ptr()) % 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._h = C.c_void_p()
+        _check(lib.smc_chains_init(C.byref(self._h), d, L, n_chains, seed & 0xFFFFFFFFFFFFFFFF,
+                                   replica0, init_k, C.c_void_p(self.J.data_ptr()),
+                                   C.c_void_p(self.spins.data_ptr()), C.c_void_p(ws), wb,
+                                   C.c_void_p(self.stream.cuda_stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().smc_chains_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def bond_zeros(self, dtype=None):
+        t = self.torch
+        return t.zeros((self.d, 2, self.N // 2), dtype=dtype or t.int64, device=self.device)
+
+    def set_couplings(self, J):
+        self.J.copy_(J)
+
+    def sample(self, beta: float, n_sweeps: int, bond_sum=None):
+        """n_sweeps sweeps of every chain; with bond_sum (int64 [d, 2, N/2]
+        device tensor) the bond products after every sweep are added to it."""
+        ptr = None
+        if bond_sum is not None:
+            assert bond_sum.dtype == self.torch.int64 and bond_sum.is_contiguous()
+            assert bond_sum.numel() == self.d * self.N
+            ptr = C.c_void_p(bond_sum.data_ptr())
+        _check(load_library().smc_chains_sample(self._h, float(beta), int(n_sweeps), ptr))
+
+    def covariance(self, beta: float, n_sweeps: int, g, g_center: float, cov_acc, G_acc):
+        """Replay of n_sweeps sampling sweeps accumulating (G - g_center) x_b
+        into cov_acc and G - g_center, (G - g_center)^2 into G_acc (float64
+        device tensors [d, 2, N/2] and [2]), G = sum_b g_b x_b."""
+        t = self.torch
+        for a in (g, cov_acc, G_acc):
+            assert a.dtype == t.float64 and a.is_contiguous() and a.is_cuda
+        assert g.numel() == self.d * self.N and cov_acc.numel() == self.d * self.N
+        assert G_acc.numel() >= 2
+        _check(load_library().smc_chains_covariance(self._h, float(beta), int(n_sweeps),
+                                                    C.c_void_p(g.data_ptr()), float(g_center),
+                                                    C.c_void_p(cov_acc.data_ptr()),
+                                                    C.c_void_p(G_acc.data_ptr())))
+
+    @property
+    def t(self) -> int:
+        v = C.c_uint64()
+        _check(load_library().smc_chains_get_sweep_index(self._h, C.byref(v)))
+        return int(v.value)
+
+    @t.setter
+    def t(self, value: int):
+        _check(load_library().smc_chains_set_sweep_index(self._h, int(value)))
 
 
 def version() -> str:

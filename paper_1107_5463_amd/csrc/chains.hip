@@ -1,0 +1,256 @@
+// chains.hip -- many independent Metropolis chains of one small Ising lattice
+// with shared real couplings J_b, for the derivatives of ln Z (Eq. (1)):
+//   d ln Z / d J_b = beta <x_b>,  d ln Z / d beta = sum_b J_b <x_b> = -<H>,
+// with x_b = s_i s_j the product across bond b; and for the gradient of the
+// correlations themselves (fluctuation-dissipation):
+//   d <x_a> / d J_b = beta Cov(x_a, x_b).
+//
+// One workgroup runs one chain entirely in LDS: both colour planes, plus a
+// per-bond accumulator (int32 sums of x_b for sampling, FP64 sums of
+// (G - c) x_b for the covariance pass).  Chain k uses replica replica0 + k in
+// the Philox counter, so chain k reproduces the single-lattice chain with FP32
+// couplings and that replica bit for bit (same site rule: local field summed
+// in FP32 over +x, -x, +y, -y, +z, -z; accept iff dE <= 0 or
+// u < exp(-beta dE) with word j & 3 of block j >> 2).  A lane handles groups
+// of 4 consecutive same-colour sites (one Philox block each) and always the
+// same groups, so the bonds of its colour-0 sites (every bond has exactly one
+// colour-0 end) are its own accumulator entries.
+//
+// The covariance pass replays the sampling sweeps: with the same start state
+// and counters it visits exactly the same configurations, and needs no stored
+// samples.  Per sample it forms G = sum_b g_b x_b (a workgroup reduction in a
+// fixed order), then adds (G - c) x_b to bond b's accumulator.
+#include "chunk.hpp"
+
+namespace smc {
+
+template <int D, int MODE>  // MODE 0: sample, 1: covariance, 2: sweeps only
+__global__ __launch_bounds__(256) void chains_kernel(const ChainsLaunch a, int8_t* __restrict__ spins,
+                                                     const uint32_t t0, const uint32_t n_sweeps,
+                                                     int64_t* __restrict__ bond_sum,
+                                                     const double* __restrict__ gvec,
+                                                     const double gc, double* __restrict__ part,
+                                                     double* __restrict__ gpart) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Geom g = a.g;
+  const int64_t Nh = g.Nh;
+  const uint32_t N = 2u * (uint32_t)Nh;
+  const uint32_t nb = (uint32_t)D * N;  // bonds
+  const uint32_t chain = blockIdx.x;
+  const uint32_t replica = a.key.replica + chain;
+  int8_t* gs = spins + (uint64_t)chain * N;
+  // LDS: 16 doubles of reduction scratch, the accumulator (4 or 8 bytes per
+  // bond), then both colour planes
+  double* red = reinterpret_cast<double*>(smem);
+  int32_t* acc_i = reinterpret_cast<int32_t*>(smem + 16 * sizeof(double));
+  double* acc_d = reinterpret_cast<double*>(smem + 16 * sizeof(double));
+  int8_t* lat = reinterpret_cast<int8_t*>(smem + 16 * sizeof(double) + (size_t)nb * (MODE == 0 ? 4 : 8));
+  const float* J = a.J;
+  const float beta = a.beta;
+
+  for (uint32_t w = threadIdx.x; w < N / 4; w += blockDim.x)
+    reinterpret_cast<uint32_t*>(lat)[w] = reinterpret_cast<const uint32_t*>(gs)[w];
+  for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
+    if (MODE == 0) acc_i[b] = 0;
+    else acc_d[b] = 0.0;
+  }
+  __syncthreads();
+
+  const uint32_t groups = (uint32_t)Nh / 4;
+  double Gsum = 0.0, G2sum = 0.0;
+  for (uint32_t sw = 0; sw < n_sweeps; ++sw) {
+    const uint32_t t = t0 + sw;
+    for (uint32_t c = 0; c < 2; ++c) {
+      int8_t* own = lat + c * Nh;
+      const int8_t* oth = lat + (1 - c) * Nh;
+      for (uint32_t gi = threadIdx.x; gi < groups; gi += blockDim.x) {
+        const Rand4 r = philox(gi, t, replica, tag(c, kContinuous), a.key.k0, a.key.k1);
+#pragma unroll
+        for (uint32_t b = 0; b < 4; ++b) {
+          const int64_t j = 4 * (int64_t)gi + b;
+          int32_t x, y, z;
+          site_coords(g, c, j, x, y, z);
+          const int si = own[j];
+          float h = 0.0f;
+#pragma unroll
+          for (int mu = 0; mu < D; ++mu) {
+            int32_t xp = x, yp = y, zp = z, xm = x, ym = y, zm = z;
+            if (mu == 0) { xp = wrap(x + 1, g.L); xm = wrap(x - 1, g.L); }
+            if (mu == 1) { yp = wrap(y + 1, g.L); ym = wrap(y - 1, g.L); }
+            if (mu == 2) { zp = wrap(z + 1, g.L); zm = wrap(z - 1, g.L); }
+            const int64_t ip = plane_index(g, xp, yp, zp);
+            const int64_t im = plane_index(g, xm, ym, zm);
+            const float jp = J[((int64_t)mu * 2 + c) * Nh + j];
+            const float jm = J[((int64_t)mu * 2 + (1 - c)) * Nh + im];
+            h += jp * (float)oth[ip];
+            h += jm * (float)oth[im];
+          }
+          const float dE = 2.0f * (float)si * h;
+          const bool accept = dE <= 0.0f || u01f(r.w[b]) < expf(-beta * dE);
+          if (accept) own[j] = (int8_t)(-si);
+        }
+      }
+      __syncthreads();
+    }
+    if (MODE == 2) continue;
+    // bond products of the new configuration, from the colour-0 ends
+    double Gp = 0.0;
+    for (int pass = 0; pass < (MODE == 0 ? 1 : 2); ++pass) {
+      double Gc = 0.0;
+      if (MODE == 1 && pass == 1) Gc = red[0] - gc;
+      for (uint32_t gi = threadIdx.x; gi < groups; gi += blockDim.x) {
+#pragma unroll
+        for (uint32_t b = 0; b < 4; ++b) {
+          const int64_t j = 4 * (int64_t)gi + b;
+          int32_t x, y, z;
+          site_coords(g, 0u, j, x, y, z);
+          const int s0 = lat[j];
+#pragma unroll
+          for (int mu = 0; mu < D; ++mu) {
+            int32_t xp = x, yp = y, zp = z, xm = x, ym = y, zm = z;
+            if (mu == 0) { xp = wrap(x + 1, g.L); xm = wrap(x - 1, g.L); }
+            if (mu == 1) { yp = wrap(y + 1, g.L); ym = wrap(y - 1, g.L); }
+            if (mu == 2) { zp = wrap(z + 1, g.L); zm = wrap(z - 1, g.L); }
+            const int64_t ip = plane_index(g, xp, yp, zp);
+            const int64_t im = plane_index(g, xm, ym, zm);
+            const int xpv = s0 * lat[Nh + ip];  // bond (mu, colour 0, j)
+            const int xmv = s0 * lat[Nh + im];  // bond (mu, colour 1, im)
+            const int64_t bp = ((int64_t)mu * 2) * Nh + j;
+            const int64_t bm = ((int64_t)mu * 2 + 1) * Nh + im;
+            if (MODE == 0) {
+              acc_i[bp] += xpv;
+              acc_i[bm] += xmv;
+            } else if (pass == 0) {
+              Gp += gvec[bp] * (double)xpv;
+              Gp += gvec[bm] * (double)xmv;
+            } else {
+              acc_d[bp] += Gc * (double)xpv;
+              acc_d[bm] += Gc * (double)xmv;
+            }
+          }
+        }
+      }
+      if (MODE == 1 && pass == 0) {
+        // G of this sample: wave sums, then the waves in order
+        double v = Gp;
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        const uint32_t wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+        if ((threadIdx.x & 63) == 0) red[1 + wave] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+          double s = 0.0;
+          for (uint32_t k = 0; k < nw; ++k) s += red[1 + k];
+          red[0] = s;
+          const double gcen = s - gc;
+          Gsum += gcen;
+          G2sum += gcen * gcen;
+        }
+        __syncthreads();
+      }
+    }
+    // the next colour-0 pass writes only sites whose bonds this lane owns
+  }
+  __syncthreads();
+  for (uint32_t w = threadIdx.x; w < N / 4; w += blockDim.x)
+    reinterpret_cast<uint32_t*>(gs)[w] = reinterpret_cast<const uint32_t*>(lat)[w];
+  if (MODE == 0) {
+    for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x)
+      if (acc_i[b] != 0)
+        atomicAdd(reinterpret_cast<unsigned long long*>(bond_sum + b),
+                  (unsigned long long)(int64_t)acc_i[b]);
+  } else if (MODE == 1) {
+    double* pc = part + (uint64_t)chain * nb;
+    for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) pc[b] = acc_d[b];
+    if (threadIdx.x == 0) {
+      gpart[2 * chain] = Gsum;
+      gpart[2 * chain + 1] = G2sum;
+    }
+  }
+}
+
+// Sum the per-chain covariance partials into the caller's accumulators in
+// chain order (deterministic).
+__global__ __launch_bounds__(256) void chains_reduce_kernel(const double* __restrict__ part,
+                                                            const double* __restrict__ gpart,
+                                                            const uint32_t n_chains,
+                                                            const uint32_t nb,
+                                                            double* __restrict__ cov_acc,
+                                                            double* __restrict__ G_acc) {
+  const uint32_t b = blockIdx.x * 256 + threadIdx.x;
+  if (b < nb) {
+    double s = 0.0;
+    for (uint32_t k = 0; k < n_chains; ++k) s += part[(uint64_t)k * nb + b];
+    cov_acc[b] += s;
+  }
+  if (blockIdx.x == 0 && threadIdx.x < 2) {
+    double s = 0.0;
+    for (uint32_t k = 0; k < n_chains; ++k) s += gpart[2 * k + threadIdx.x];
+    G_acc[threadIdx.x] += s;
+  }
+}
+
+size_t chains_lds_bytes(const Geom& g, int mode) {
+  const size_t N = 2 * (size_t)g.Nh;
+  return (size_t)g.d * N * (mode == 0 ? 4 : 8) + N + 16 * sizeof(double);
+}
+
+static const void* chains_fn(int d, int mode) {
+  if (d == 2)
+    return mode == 0 ? (const void*)chains_kernel<2, 0>
+                     : (mode == 1 ? (const void*)chains_kernel<2, 1> : (const void*)chains_kernel<2, 2>);
+  return mode == 0 ? (const void*)chains_kernel<3, 0>
+                   : (mode == 1 ? (const void*)chains_kernel<3, 1> : (const void*)chains_kernel<3, 2>);
+}
+
+hipError_t chains_allow_lds(int d, size_t bytes) {
+  for (int mode = 0; mode < 3; ++mode) {
+    const hipError_t e = hipFuncSetAttribute(chains_fn(d, mode),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_chains_sample(const ChainsLaunch& a, int8_t* spins, uint32_t t0,
+                                uint32_t n_sweeps, int64_t* bond_sum, hipStream_t st) {
+  const dim3 grid(a.n_chains), block(256);
+  const size_t lds = chains_lds_bytes(a.g, 0);
+  if (a.g.d == 2) {
+    if (bond_sum)
+      hipLaunchKernelGGL((chains_kernel<2, 0>), grid, block, lds, st, a, spins, t0, n_sweeps,
+                         bond_sum, nullptr, 0.0, nullptr, nullptr);
+    else
+      hipLaunchKernelGGL((chains_kernel<2, 2>), grid, block, lds, st, a, spins, t0, n_sweeps,
+                         nullptr, nullptr, 0.0, nullptr, nullptr);
+  } else {
+    if (bond_sum)
+      hipLaunchKernelGGL((chains_kernel<3, 0>), grid, block, lds, st, a, spins, t0, n_sweeps,
+                         bond_sum, nullptr, 0.0, nullptr, nullptr);
+    else
+      hipLaunchKernelGGL((chains_kernel<3, 2>), grid, block, lds, st, a, spins, t0, n_sweeps,
+                         nullptr, nullptr, 0.0, nullptr, nullptr);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_chains_covariance(const ChainsLaunch& a, int8_t* spins, uint32_t t0,
+                                    uint32_t n_sweeps, const double* g, double gc, double* part,
+                                    double* gpart, double* cov_acc, double* G_acc,
+                                    hipStream_t st) {
+  const dim3 grid(a.n_chains), block(256);
+  const size_t lds = chains_lds_bytes(a.g, 1);
+  if (a.g.d == 2)
+    hipLaunchKernelGGL((chains_kernel<2, 1>), grid, block, lds, st, a, spins, t0, n_sweeps,
+                       nullptr, g, gc, part, gpart);
+  else
+    hipLaunchKernelGGL((chains_kernel<3, 1>), grid, block, lds, st, a, spins, t0, n_sweeps,
+                       nullptr, g, gc, part, gpart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const uint32_t nb = (uint32_t)(a.g.d * 2 * a.g.Nh);
+  hipLaunchKernelGGL(chains_reduce_kernel, dim3((nb + 255) / 256), dim3(256), 0, st, part, gpart,
+                     a.n_chains, nb, cov_acc, G_acc);
+  return hipGetLastError();
+}
+
+}  // namespace smc

@@ -132,4 +132,21 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_validate(const MeasureLaunch& a, const void* spins, uint32_t* dev_count,
                            hipStream_t st);
 
+// Independent chains of one small Ising lattice with shared FP32 couplings.
+struct ChainsLaunch {
+  Geom g;
+  RngKey key;        // key.replica = replica of chain 0
+  const float* J;    // [d][2][Nh]
+  float beta;
+  uint32_t n_chains;
+};
+size_t chains_lds_bytes(const Geom& g, int mode);
+hipError_t chains_allow_lds(int d, size_t bytes);
+hipError_t launch_chains_sample(const ChainsLaunch& a, int8_t* spins, uint32_t t0,
+                                uint32_t n_sweeps, int64_t* bond_sum, hipStream_t st);
+hipError_t launch_chains_covariance(const ChainsLaunch& a, int8_t* spins, uint32_t t0,
+                                    uint32_t n_sweeps, const double* g, double gc, double* part,
+                                    double* gpart, double* cov_acc, double* G_acc,
+                                    hipStream_t st);
+
 }  // namespace smc

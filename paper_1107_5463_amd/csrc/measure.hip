@@ -151,14 +151,20 @@ __global__ __launch_bounds__(256) void finish_kernel(const Partial* __restrict__
   __shared__ Partial sh[256];
   sh[threadIdx.x] = v;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    Partial a = sh[0];
-    for (int w = 1; w < 256; ++w) {
-      a.Ei += sh[w].Ei;
-      a.Mi += sh[w].Mi;
-      a.E += sh[w].E;
-      for (int k = 0; k < 3; ++k) a.M[k] += sh[w].M[k];
+  // pairwise tree in a fixed order (deterministic)
+  for (unsigned s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      Partial& a = sh[threadIdx.x];
+      const Partial& b = sh[threadIdx.x + s];
+      a.Ei += b.Ei;
+      a.Mi += b.Mi;
+      a.E += b.E;
+      for (int k = 0; k < 3; ++k) a.M[k] += b.M[k];
     }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const Partial a = sh[0];
     ObsOut o;
     if (ising) {
       o.E_int = int_couplings ? a.Ei : 0;

@@ -371,7 +371,7 @@ int smc_init_lattice(smc_lattice** out, const smc_params* p, void* spins, void* 
   h->partials = h->ws + 2 * kAlign;
   h->alt_spins = (p->flags & SMC_FLAG_SCHEDULE_FUSED) ? (void*)(h->ws + 2 * kAlign + partial_bytes(p))
                                                       : nullptr;
-  h->fused_rows = fused_rows_per_band(h->g, 1024);
+  h->fused_rows = fused_rows_per_band(h->g, 512);
   if (const char* v = std::getenv("SMC_FUSED_ROWS")) {
     const long H = std::strtol(v, nullptr, 10);
     if (H >= 1 && H <= 64 && H <= h->g.L && h->g.L % H == 0) h->fused_rows = (uint32_t)H;
@@ -939,6 +939,204 @@ int smc_batch_set_sweep_index(smc_batch* b, uint64_t t) {
 int smc_batch_destroy(smc_batch* b) {
   if (b) batch_drop_graph(b);
   delete b;
+  return SMC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Chains of one small lattice with shared FP32 couplings (derivatives of ln Z)
+// ---------------------------------------------------------------------------
+struct smc_chains {
+  int d, L;
+  int32_t n_chains;
+  Geom g;
+  RngKey key;  // replica = replica of chain 0
+  const float* J;
+  void* spins;
+  double* part;   // [n_chains][d N] covariance partials
+  double* gpart;  // [n_chains][2]
+  hipStream_t stream;
+  uint64_t t;
+};
+
+namespace {
+
+bool chains_shape_ok(int32_t d, int32_t L, int32_t n_chains, std::string& why) {
+  if (d != 2 && d != 3) return why = "d must be 2 or 3", false;
+  if (L < 4 || L > 1024) return why = "L must be in [4, 1024]", false;
+  if (d == 2 ? (L % 4) : (L % 2)) return why = d == 2 ? "L must be a multiple of 4" : "L must be even", false;
+  if (n_chains < 1 || n_chains > (1 << 20)) return why = "n_chains must be in [1, 2^20]", false;
+  smc_params p;
+  std::memset(&p, 0, sizeof(p));
+  p.d = d;
+  p.n = 1;
+  p.L = L;
+  const Geom g = make_geom(&p);
+  if (chains_lds_bytes(g, 1) > 160 * 1024)
+    return why = "lattice too large for one workgroup's LDS (L^d (1 + 8 d) bytes > 160 KiB)", false;
+  return true;
+}
+
+size_t chains_sites(int32_t d, int32_t L) {
+  size_t N = 1;
+  for (int k = 0; k < d; ++k) N *= (size_t)L;
+  return N;
+}
+
+ChainsLaunch chains_args(const smc_chains* h, double beta) {
+  ChainsLaunch a;
+  a.g = h->g;
+  a.key = h->key;
+  a.J = h->J;
+  a.beta = (float)beta;
+  a.n_chains = (uint32_t)h->n_chains;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t smc_chains_spin_bytes(int32_t d, int32_t L, int32_t n_chains) {
+  std::string why;
+  if (!chains_shape_ok(d, L, n_chains, why)) return 0;
+  return chains_sites(d, L) * (size_t)n_chains;
+}
+
+size_t smc_chains_coupling_bytes(int32_t d, int32_t L) {
+  std::string why;
+  if (!chains_shape_ok(d, L, 1, why)) return 0;
+  return chains_sites(d, L) * (size_t)d * sizeof(float);
+}
+
+size_t smc_chains_bond_bytes(int32_t d, int32_t L) {
+  std::string why;
+  if (!chains_shape_ok(d, L, 1, why)) return 0;
+  return chains_sites(d, L) * (size_t)d * 8;
+}
+
+size_t smc_chains_workspace_bytes(int32_t d, int32_t L, int32_t n_chains) {
+  std::string why;
+  if (!chains_shape_ok(d, L, n_chains, why)) return 0;
+  return round_up((size_t)n_chains * chains_sites(d, L) * d * sizeof(double), kAlign) +
+         round_up((size_t)n_chains * 2 * sizeof(double), kAlign);
+}
+
+int smc_chains_init(smc_chains** out, int32_t d, int32_t L, int32_t n_chains, uint64_t seed,
+                    uint32_t replica0, int32_t init, const float* J, void* spins,
+                    void* workspace, size_t workspace_bytes, void* stream) {
+  g_err.clear();
+  if (!out) return fail(SMC_EINVAL, "out is NULL");
+  *out = nullptr;
+  std::string why;
+  if (!chains_shape_ok(d, L, n_chains, why)) return fail(SMC_EINVAL, why);
+  if (init < 0 || init > 2) return fail(SMC_EINVAL, "init must be HOT, COLD or KEEP");
+  if (!J || ((uintptr_t)J & 3)) return fail(SMC_EINVAL, "J must be non-NULL and 4-byte aligned");
+  if (!spins || ((uintptr_t)spins & 15)) return fail(SMC_EINVAL, "spins must be 16-byte aligned");
+  if ((uint64_t)replica0 + (uint64_t)n_chains > 4294967296ull)
+    return fail(SMC_EINVAL, "replica0 + n_chains must not exceed 2^32");
+  const size_t need = smc_chains_workspace_bytes(d, L, n_chains);
+  if (!workspace || ((uintptr_t)workspace & (kAlign - 1)))
+    return fail(SMC_EINVAL, "workspace must be non-NULL and 256-byte aligned");
+  if (workspace_bytes < need)
+    return fail(SMC_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
+  smc_chains* h = new (std::nothrow) smc_chains();
+  if (!h) return fail(SMC_EINVAL, "out of host memory");
+  smc_params p;
+  std::memset(&p, 0, sizeof(p));
+  p.d = d;
+  p.n = 1;
+  p.L = L;
+  h->d = d;
+  h->L = L;
+  h->n_chains = n_chains;
+  h->g = make_geom(&p);
+  h->key = RngKey{(uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), replica0};
+  h->J = J;
+  h->spins = spins;
+  h->part = (double*)workspace;
+  h->gpart = (double*)((char*)workspace +
+                       round_up((size_t)n_chains * chains_sites(d, L) * d * sizeof(double), kAlign));
+  h->stream = (hipStream_t)stream;
+  h->t = 0;
+  int rc = check(chains_allow_lds(d, chains_lds_bytes(h->g, 1)), "chains LDS attribute");
+  const size_t N = chains_sites(d, L);
+  for (int32_t k = 0; rc == SMC_OK && init != SMC_INIT_KEEP && k < n_chains; ++k) {
+    const RngKey key{h->key.k0, h->key.k1, replica0 + (uint32_t)k};
+    rc = check(launch_init_ising(h->g, key, init == SMC_INIT_HOT, (int8_t*)spins + (size_t)k * N,
+                                 h->stream),
+               "spin init launch");
+  }
+  if (rc == SMC_OK) rc = check(hipStreamSynchronize(h->stream), "stream synchronise");
+  if (rc != SMC_OK) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return SMC_OK;
+}
+
+int smc_chains_sample(smc_chains* h, double beta, int64_t n_sweeps, int64_t* dev_bond_sum) {
+  if (!h) return fail(SMC_EINVAL, "handle is NULL");
+  if (!beta_ok(beta)) return fail(SMC_EINVAL, "beta must be >= 0 (or +inf), not NaN");
+  if (n_sweeps < 0) return fail(SMC_EINVAL, "n_sweeps must be >= 0");
+  if (dev_bond_sum && ((uintptr_t)dev_bond_sum & 7))
+    return fail(SMC_EINVAL, "bond_sum must be 8-byte aligned");
+  if (h->t + (uint64_t)n_sweeps > 4294967296ull)
+    return fail(SMC_ERANGE, "sweep counter would exceed 2^32");
+  const ChainsLaunch a = chains_args(h, beta);
+  int64_t left = n_sweeps;
+  while (left > 0) {
+    // int32 per-bond sums in LDS: at most 2^30 sweeps per launch
+    const uint32_t n = (uint32_t)std::min<int64_t>(left, (int64_t)1 << 30);
+    const int rc = check(launch_chains_sample(a, (int8_t*)h->spins, (uint32_t)h->t, n,
+                                              dev_bond_sum, h->stream),
+                         "chains sample launch");
+    if (rc != SMC_OK) return rc;
+    h->t += n;
+    left -= n;
+  }
+  return SMC_OK;
+}
+
+int smc_chains_covariance(smc_chains* h, double beta, int64_t n_sweeps, const double* dev_g,
+                          double g_center, double* dev_cov_acc, double* dev_G_acc) {
+  if (!h) return fail(SMC_EINVAL, "handle is NULL");
+  if (!beta_ok(beta)) return fail(SMC_EINVAL, "beta must be >= 0 (or +inf), not NaN");
+  if (n_sweeps < 0) return fail(SMC_EINVAL, "n_sweeps must be >= 0");
+  if (!std::isfinite(g_center)) return fail(SMC_EINVAL, "g_center must be finite");
+  if (!dev_g || !dev_cov_acc || !dev_G_acc || ((uintptr_t)dev_g & 7) ||
+      ((uintptr_t)dev_cov_acc & 7) || ((uintptr_t)dev_G_acc & 7))
+    return fail(SMC_EINVAL, "g, cov_acc and G_acc must be non-NULL and 8-byte aligned");
+  if (h->t + (uint64_t)n_sweeps > 4294967296ull)
+    return fail(SMC_ERANGE, "sweep counter would exceed 2^32");
+  if (n_sweeps == 0) return SMC_OK;
+  const ChainsLaunch a = chains_args(h, beta);
+  const int rc = check(launch_chains_covariance(a, (int8_t*)h->spins, (uint32_t)h->t,
+                                                (uint32_t)n_sweeps, dev_g, g_center, h->part,
+                                                h->gpart, dev_cov_acc, dev_G_acc, h->stream),
+                       "chains covariance launch");
+  if (rc != SMC_OK) return rc;
+  h->t += (uint64_t)n_sweeps;
+  return SMC_OK;
+}
+
+int smc_chains_get_sweep_index(const smc_chains* h, uint64_t* t) {
+  if (!h || !t) return fail(SMC_EINVAL, "NULL argument");
+  *t = h->t;
+  return SMC_OK;
+}
+
+int smc_chains_set_sweep_index(smc_chains* h, uint64_t t) {
+  if (!h) return fail(SMC_EINVAL, "handle is NULL");
+  if (t > 4294967296ull) return fail(SMC_ERANGE, "sweep index must be <= 2^32");
+  h->t = t;
+  return SMC_OK;
+}
+
+int smc_chains_destroy(smc_chains* h) {
+  delete h;
   return SMC_OK;
 }
 

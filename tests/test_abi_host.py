@@ -122,3 +122,28 @@ def test_obs_record_layout_matches_header(smc_host):
     fields = [f[0] for f in smc_host._ObsC._fields_]
     assert names == fields
     assert C.sizeof(smc_host._ObsC) == 64
+
+
+def test_chain_buffer_sizes_and_shapes(smc_host):
+    lib = smc_host.load_library()
+    assert lib.smc_chains_spin_bytes(2, 64, 256) == 256 * 64 * 64
+    assert lib.smc_chains_coupling_bytes(2, 64) == 2 * 64 * 64 * 4
+    assert lib.smc_chains_bond_bytes(3, 16) == 3 * 16 ** 3 * 8
+    assert lib.smc_chains_workspace_bytes(2, 64, 256) >= 256 * 2 * 64 * 64 * 8 + 256 * 16
+    # 2D needs L % 4 == 0, 3D even L; one chain must fit a workgroup's LDS
+    for d, L in ((2, 6), (2, 2), (3, 5), (2, 100), (3, 20), (4, 8)):
+        assert lib.smc_chains_spin_bytes(d, L, 1) == 0, (d, L)
+    assert lib.smc_chains_spin_bytes(2, 96, 1) == 96 * 96
+    assert lib.smc_chains_spin_bytes(3, 18, 1) == 18 ** 3
+    assert lib.smc_chains_spin_bytes(2, 64, 0) == 0
+
+
+def test_chain_init_rejects_bad_arguments(smc_host):
+    lib = smc_host.load_library()
+    h = C.c_void_p()
+    assert lib.smc_chains_init(C.byref(h), 2, 6, 4, 0, 0, 0, None, None, None, 0, None) == smc_host.SMC_EINVAL
+    assert b"multiple of 4" in lib.smc_last_error()
+    assert lib.smc_chains_init(C.byref(h), 2, 8, 4, 0, 0, 0, None, None, None, 0, None) == smc_host.SMC_EINVAL
+    assert b"J must be" in lib.smc_last_error()
+    assert lib.smc_chains_sample(None, 0.4, 1, None) == smc_host.SMC_EINVAL
+    assert lib.smc_chains_covariance(None, 0.4, 1, None, 0.0, None, None) == smc_host.SMC_EINVAL

@@ -1,0 +1,190 @@
+"""GPU parity of the real-coupling chains (derivatives of ln Z).
+
+* Chains against the oracle's chains on the same seeded inputs: start states,
+  final states and the summed bond products bit-exact (the FP32 decisions
+  equal the FP64 ones whenever no uphill decision came within 1e-6 of its
+  threshold, which the oracle reports and the test requires).
+* Chain k equals the single-lattice chain with FP32 couplings and replica k.
+* The covariance replay equals the oracle's sample covariance over the same
+  samples.
+* At L = 4, the estimates of <x_b>, of the gradient of the correlations and
+  of ln Z's gradients agree with exact enumeration within their statistical
+  errors, and moment matching recovers hidden couplings.
+"""
+import numpy as np
+import pytest
+
+import layout
+
+import oracle.exact as ex
+
+pytestmark = pytest.mark.gpu
+
+
+def split(a, d, L):
+    return layout.to_split(np.ascontiguousarray(a), d, L)
+
+
+def natural(a, d, L):
+    return layout.to_natural(np.ascontiguousarray(a), d, L)
+
+
+def make(smc_gpu, oracle_mod, d, L, nch, seed, replica0, J_nat):
+    import torch
+    Jt = torch.from_numpy(split(J_nat, d, L)).cuda()
+    ch = smc_gpu.Chains(d, L, nch, seed, J=Jt, replica0=replica0)
+    s0 = np.stack([oracle_mod.init_ising(d, L, seed, replica=replica0 + k) for k in range(nch)])
+    return ch, s0
+
+
+CASES = [  # d, L, chains, sweeps, beta, seed
+    (2, 8, 6, 40, 0.45, 3),
+    (3, 4, 5, 30, 0.25, 4),
+    (2, 64, 2, 10, 0.4, 5),
+    (3, 6, 3, 20, 0.3, 6),
+    (2, 4, 9, 50, 0.5, 7),
+]
+
+
+@pytest.mark.parametrize("d,L,nch,nsw,beta,seed", CASES)
+def test_chains_match_oracle(smc_gpu, oracle_mod, d, L, nch, nsw, beta, seed):
+    print(f"chains d={d} L={L} chains={nch} sweeps={nsw}", flush=True)
+    rng = np.random.default_rng(seed)
+    J = rng.normal(1.0, 0.2, size=(d, L ** d)).astype(np.float32)
+    ch, s0 = make(smc_gpu, oracle_mod, d, L, nch, seed, 100, J)
+    got0 = np.stack([natural(ch.spins[k].cpu().numpy(), d, L) for k in range(nch)])
+    assert np.array_equal(got0, s0)
+    # burn-in without accumulation, then accumulate
+    ch.sample(beta, 3)
+    st, _, _, m1 = oracle_mod.chains_ising(d, L, seed, J, beta, s0, 3, replica0=100)
+    acc = ch.bond_zeros()
+    ch.sample(beta, nsw, acc)
+    out, bsum, _, m2 = oracle_mod.chains_ising(d, L, seed, J, beta, st, nsw, t0=3, replica0=100)
+    assert min(m1, m2) > 1e-6, "a decision came within 1e-6 of its threshold"
+    got = np.stack([natural(ch.spins[k].cpu().numpy(), d, L) for k in range(nch)])
+    assert np.array_equal(got, out)
+    assert np.array_equal(natural(acc.cpu().numpy(), d, L), bsum)
+    assert ch.t == 3 + nsw
+
+
+def test_chain_equals_single_lattice_chain(smc_gpu, oracle_mod):
+    import torch
+    d, L, nch, seed, beta = 2, 16, 4, 9, 0.42
+    rng = np.random.default_rng(1)
+    J = rng.normal(1.0, 0.1, size=(d, L ** d)).astype(np.float32)
+    ch, _ = make(smc_gpu, oracle_mod, d, L, nch, seed, 7, J)
+    ch.sample(beta, 25)
+    Jt = torch.from_numpy(split(J, d, L)).cuda()
+    for k in range(nch):
+        lat = smc_gpu.Lattice(d, 1, L, seed=seed, J_kind=smc_gpu.J_FP32, J=Jt, replica=7 + k)
+        lat.sweep(beta, 25)
+        assert torch.equal(lat.spins.view(-1).cpu(), ch.spins[k].view(-1).cpu()), k
+
+
+@pytest.mark.parametrize("d,L,nch,nsw,beta,seed", [(2, 8, 6, 40, 0.45, 3), (3, 4, 5, 30, 0.25, 4)])
+def test_covariance_replay_matches_oracle(smc_gpu, oracle_mod, d, L, nch, nsw, beta, seed):
+    import torch
+    rng = np.random.default_rng(seed + 50)
+    J = rng.normal(1.0, 0.2, size=(d, L ** d)).astype(np.float32)
+    ch, s0 = make(smc_gpu, oracle_mod, d, L, nch, seed, 0, J)
+    start = ch.spins.clone()
+    acc = ch.bond_zeros()
+    ch.sample(beta, nsw, acc)
+    _, bsum, samples, mm = oracle_mod.chains_ising(d, L, seed, J, beta, s0, nsw,
+                                                   want_samples=True)
+    assert mm > 1e-6
+    assert np.array_equal(natural(acc.cpu().numpy(), d, L), bsum)
+    g_nat = rng.normal(size=(d, L ** d))
+    mean_nat = bsum / (nch * nsw)
+    gc = float((g_nat * mean_nat).sum())
+    end = ch.spins.clone()
+    ch.spins.copy_(start)
+    ch.t = 0
+    g = torch.from_numpy(split(g_nat, d, L)).cuda()
+    cov_acc = ch.bond_zeros(torch.float64)
+    G_acc = torch.zeros(2, dtype=torch.float64, device=ch.device)
+    ch.covariance(beta, nsw, g, gc, cov_acc, G_acc)
+    assert torch.equal(ch.spins, end)
+    S = nch * nsw
+    cov = natural((cov_acc / S).cpu().numpy(), d, L) - (float(G_acc[0]) / S) * mean_nat
+    want = oracle_mod.bond_covariance(samples, g_nat)
+    assert np.abs(cov - want).max() <= 1e-11 * max(1.0, np.abs(want).max())
+    # G moments: sum (G - c) and sum (G - c)^2 over the samples
+    X = samples.reshape(S, -1).astype(np.float64)
+    Gs = X @ g_nat.reshape(-1) - gc
+    assert abs(float(G_acc[0]) - Gs.sum()) < 1e-9 * max(1.0, np.abs(Gs).sum())
+    assert abs(float(G_acc[1]) - (Gs ** 2).sum()) < 1e-9 * (Gs ** 2).sum()
+
+
+@pytest.fixture(scope="module")
+def x4():
+    return ex.torus_bond_products(4)
+
+
+def test_autograd_against_exact_enumeration(smc_gpu, x4):
+    import torch
+    from paper_1107_5463_amd import autodiff
+    rng = np.random.default_rng(21)
+    d, L, beta = 2, 4, 0.4
+    J_nat = rng.normal(1.0, 0.2, size=(d, 16))
+    mean, cov, _ = ex.exact_bond_moments(L, J_nat, beta, x4)
+    nch, nsw = 256, 2000
+    ch = smc_gpu.Chains(d, L, nch, 31)
+    J = torch.from_numpy(split(J_nat.astype(np.float32), d, L)).cuda().requires_grad_(True)
+    b = torch.tensor(beta, dtype=torch.float64, requires_grad=True)
+    m = autodiff.bond_correlations(J, b, ch, nsw, n_burn=200)
+    S = nch * nsw
+    tau = 10.0  # generous integrated autocorrelation time (sweeps)
+    var = np.diag(cov)
+    got = natural(m.detach().cpu().numpy().astype(np.float64), d, L)
+    tol = 6 * np.sqrt(var * tau / S) + 1e-6
+    assert np.all(np.abs(got - mean) < tol), np.max(np.abs(got - mean) / tol)
+    g_nat = rng.normal(size=(d, 16))
+    m.backward(torch.from_numpy(split(g_nat.astype(np.float32), d, L)).cuda())
+    want = beta * (cov @ g_nat.reshape(-1)).reshape(d, 16)
+    EG2 = g_nat.reshape(-1) @ (cov + np.outer(mean.reshape(-1), mean.reshape(-1))) @ g_nat.reshape(-1)
+    gtol = 6 * beta * np.sqrt(EG2 * tau / S) + 1e-6
+    gotJ = natural(J.grad.cpu().numpy().astype(np.float64), d, L)
+    assert np.all(np.abs(gotJ - want) < gtol), np.max(np.abs(gotJ - want) / gtol)
+    want_b = float((cov @ g_nat.reshape(-1)) @ J_nat.reshape(-1))
+    Jv = J_nat.reshape(-1)
+    EH2 = Jv @ (cov + np.outer(mean.reshape(-1), mean.reshape(-1))) @ Jv
+    assert abs(float(b.grad) - want_b) < 6 * np.sqrt(EG2 * EH2 * tau / S)
+
+
+def test_log_partition_gradients(smc_gpu, x4):
+    import torch
+    from paper_1107_5463_amd import autodiff
+    rng = np.random.default_rng(4)
+    J_nat = rng.normal(1.0, 0.1, size=(2, 16))
+    beta = 0.35
+    mean, _, _ = ex.exact_bond_moments(4, J_nat, beta, x4)
+    J = torch.from_numpy(split(J_nat.astype(np.float32), 2, 4)).cuda().requires_grad_(True)
+    b = torch.tensor(beta, dtype=torch.float64, requires_grad=True)
+    ch = smc_gpu.Chains(2, 4, 128, 5)
+    z = autodiff.log_partition(J, b, ch, 2000, n_burn=100)
+    assert float(z) == 0.0
+    z.backward()
+    ch2 = smc_gpu.Chains(2, 4, 128, 5)
+    gJ, gb = autodiff.log_partition_grad(J.detach(), beta, ch2, 2000, n_burn=100)
+    assert torch.allclose(J.grad.double(), gJ.float().double(), rtol=0, atol=1e-6)
+    assert abs(float(b.grad) - gb) < 1e-6 * max(1.0, abs(gb))
+    got = natural(gJ.cpu().numpy(), 2, 4) / beta
+    assert np.abs(got - mean).max() < 0.02
+
+
+def test_moment_matching_recovers_hidden_couplings(smc_gpu, x4):
+    import torch
+    from paper_1107_5463_amd import autodiff
+    rng = np.random.default_rng(7)
+    J_star = rng.normal(1.0, 0.1, size=(2, 16))
+    beta = 0.4
+    target_nat, _, _ = ex.exact_bond_moments(4, J_star, beta, x4)
+    target = torch.from_numpy(split(target_nat, 2, 4)).cuda()
+    ch = smc_gpu.Chains(2, 4, 256, 13)
+    hist = []
+    autodiff.fit_couplings(target, beta, ch, steps=60, lr=2.5, n_sweeps=500, n_burn=20,
+                           J_init=torch.ones((2, 2, 8), device="cuda"), history=hist)
+    J_fit = torch.stack(hist[-15:]).mean(0)
+    err = np.abs(natural(J_fit.cpu().numpy().astype(np.float64), 2, 4) - J_star)
+    assert err.max() < 0.05, err.max()
