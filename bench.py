@@ -7,8 +7,10 @@ J = 1, hot start from seed 2, beta = 0.4406868, 1000 sweeps with energy and
 magnetisation measured every 10 sweeps.  One step = 10 sweeps + one
 measurement written to a device ring (no host synchronisation inside the
 timed region).  Other workloads (--workload): 3D Ising L = 512, 2D XY
-L = 4096, 3D Heisenberg L = 256 (FP32 spins), and the batched +-J spin
-glass (2048 lattices of L in {8,12,16,24,32}, 32 temperatures).
+L = 4096, 3D Heisenberg L = 256 (FP32 spins), the batched +-J spin
+glass (2048 lattices of L in {8,12,16,24,32}, 32 temperatures), and the
+derivatives of ln Z (256 chains of a 2D L = 64 lattice with Gaussian
+couplings: sampling sweeps, then the covariance replay).
 
 Prints one JSON line:
   value     spin-flip attempts per ns over the whole timed region;
@@ -45,6 +47,7 @@ WORKLOADS = {
     "heisenberg": dict(d=3, n=3, L=256, seed=6, beta=0.693, delta=HEIS_DELTA, renorm=100),
     "batched": dict(d=3, n=1, lattices=2048, Ls=(8, 12, 16, 24, 32), seed=4, betas=32,
                     beta_lo=0.5, beta_hi=3.0),
+    "chains": dict(d=2, n=1, L=64, chains=256, seed=8, beta=0.4, J_mean=1.0, J_sigma=0.1),
 }
 
 # Source files of each dominant kernel (a counter summary is valid only for
@@ -61,7 +64,7 @@ def parse():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="ising2d")
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps of 10 sweeps + 1 measurement (default: 100, i.e. 1000 "
-                         "sweeps; batched: 1000, i.e. 10^4 sweeps)")
+                         "sweeps; batched and chains: 1000, i.e. 10^4 sweeps)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--sweeps-per-step", type=int, default=10)
     ap.add_argument("--schedule", choices=["fused", "two-pass"], default="two-pass",
@@ -344,6 +347,110 @@ def run_batched(args, wl, torch, smc):
     return result
 
 
+def run_chains(args, wl, torch, smc):
+    """Derivatives of ln Z: forward = sampling sweeps accumulating the bond
+    products; backward = the covariance replay of the same sweeps."""
+    import numpy as np
+    d, L, nch = wl["d"], wl["L"], wl["chains"]
+    N = L ** d
+    rng = np.random.default_rng(wl["seed"])
+    J_nat = rng.normal(wl["J_mean"], wl["J_sigma"], size=(d, N)).astype(np.float32)
+    # natural -> colour-split layout of the couplings (site i = x + L y: colour
+    # (x + y) & 1, in-colour index i >> 1)
+    Js = np.empty((d, 2, N // 2), dtype=np.float32)
+    i = np.arange(N)
+    col = ((i % L) + (i // L)) & 1
+    Js[:, col, i >> 1] = J_nat
+    ch = smc.Chains(d, L, nch, wl["seed"], J=torch.from_numpy(Js).cuda())
+    st = ch.stream
+    K = args.steps if args.steps is not None else 1000
+    W, S = args.warmup, args.sweeps_per_step
+    beta = wl["beta"]
+    for _ in range(W):
+        ch.sample(beta, S)
+    torch.cuda.synchronize()
+    start = ch.spins.clone()
+    t0 = ch.t
+    acc = ch.bond_zeros()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record(st)
+    for _ in range(K):
+        ch.sample(beta, S, acc)
+    ev[1].record(st)
+    torch.cuda.synchronize()
+    sweeps = K * S
+    mean = acc.double() / (nch * sweeps)
+    g = torch.randn(mean.shape, dtype=torch.float64, device=mean.device,
+                    generator=torch.Generator(device=mean.device).manual_seed(1))
+    gc = float((g * mean).sum())
+    cov_acc = torch.zeros_like(mean)
+    G_acc = torch.zeros(2, dtype=torch.float64, device=mean.device)
+    ch.spins.copy_(start)
+    ch.t = t0
+    torch.cuda.synchronize()
+    ev[2].record(st)
+    ch.covariance(beta, sweeps, g, gc, cov_acc, G_acc)
+    ev[3].record(st)
+    torch.cuda.synchronize()
+    fwd_ms = ev[0].elapsed_time(ev[1])
+    bwd_ms = ev[2].elapsed_time(ev[3])
+    attempts = nch * N * sweeps
+    result = {
+        "metric": "spin-flip attempts/ns + %HBM peak, 2D Ising L=16384; batched vs plain",
+        "value": round(attempts / (fwd_ms * 1e6), 2),
+        "unit": "attempts/ns",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(fwd_ms / max(K, 1), 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"derivatives of ln Z: {nch} chains of the 2D Ising L={L} lattice, J ~ "
+                        f"N({wl['J_mean']}, {wl['J_sigma']}^2) (seed {wl['seed']}), beta={beta}, "
+                        f"{sweeps} sweeps with the bond products summed after every sweep "
+                        "(forward), then the covariance replay of the same sweeps (backward)",
+            "chains": nch, "L": L, "sweeps": sweeps,
+        },
+        "backward": {"value": round(attempts / (bwd_ms * 1e6), 2), "unit": "attempts/ns",
+                     "ms": round(bwd_ms, 3)},
+        "roofline": {
+            "bound": "alu",
+            "achieved": None,
+            "peak": round(VALU_PEAK_TOPS, 2),
+            "unit": "Tops/s",
+            "frac": None,
+            "traffic": None,
+            "kernel": "chains",
+            "kernel_avg_us": round(fwd_ms * 1e3 / max(K, 1), 3),
+        },
+    }
+    if args.cpu_seconds > 0:
+        sys.path.insert(0, ROOT)
+        import oracle
+
+        n_or = 8
+        s0 = np.stack([oracle.init_ising(d, L, wl["seed"], replica=k) for k in range(n_or)])
+        calls = [0]
+
+        def one():
+            oracle.chains_ising(d, L, wl["seed"], J_nat, beta, s0, 50)
+            calls[0] += 1
+        rate, c, el = oracle_rate(one, n_or * N * 50, args.cpu_seconds)
+        result["cpu_baseline"] = {
+            "value": round(rate, 4),
+            "unit": "attempts/ns",
+            "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{n_or} of the chains, 50 sweeps with bond sums, repeated {c} times "
+                      f"({el:.1f} s)",
+        }
+    return result
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -359,6 +466,8 @@ def main():
     wl = WORKLOADS[args.workload]
     if args.workload == "batched":
         result = run_batched(args, wl, torch, smc)
+    elif args.workload == "chains":
+        result = run_chains(args, wl, torch, smc)
     else:
         result = run_lattice(args, wl, torch, smc)
     print(json.dumps(result), flush=True)

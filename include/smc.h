@@ -65,7 +65,12 @@ enum smc_flags {
                                     ping-ponging through the workspace (bit-identical
                                     results; other shapes keep the two-pass schedule) */
   SMC_FLAG_GENERIC_KERNEL = 4,   /* force the one-site-per-thread kernels (testing) */
-  SMC_FLAG_COUPLINGS_KEEP = 8    /* do not generate J at init; use the caller's values */
+  SMC_FLAG_COUPLINGS_KEEP = 8,   /* do not generate J at init; use the caller's values */
+  SMC_FLAG_PACKED = 16           /* Ising spins (and +-1 couplings) at one bit per site
+                                    (Sec. 2, multi-spin coding): the int8 planes' site
+                                    order, site j in bit j & 31 of 32-bit word j >> 5,
+                                    bit 1 = -1; L % 64 == 0; same chain as int8; no
+                                    bond correlations; the fused schedule is ignored */
 };
 
 enum smc_bond_op { SMC_BOND_RESET = 0, SMC_BOND_ACCUMULATE = 1, SMC_BOND_READ = 2 };
@@ -286,6 +291,12 @@ int smc_chains_covariance(smc_chains* h, double beta, int64_t n_sweeps, const do
 int smc_chains_get_sweep_index(const smc_chains* h, uint64_t* t);
 int smc_chains_set_sweep_index(smc_chains* h, uint64_t t);
 int smc_chains_destroy(smc_chains* h);
+
+/* Conversions between int8 +-1 sites and the packed format (n_sites a
+ * multiple of 32, any run of planes in storage order; asynchronous on
+ * `stream`).  Packed: site k in bit k & 31 of word k >> 5, bit 1 = -1. */
+int smc_pack_spins(const void* src_int8, void* dst_words, int64_t n_sites, void* stream);
+int smc_unpack_spins(const void* src_words, void* dst_int8, int64_t n_sites, void* stream);
 
 /* The calling thread's last error message ("" if none). */
 const char* smc_last_error(void);

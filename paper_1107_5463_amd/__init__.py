@@ -30,6 +30,7 @@ _LIB_PATH = os.path.join(_HERE, "libsmc.so")
 J_UNIFORM, J_PM, J_FP32 = 0, 1, 2
 INIT_HOT, INIT_COLD, INIT_KEEP = 0, 1, 2
 FLAG_FAST_MATH, FLAG_SCHEDULE_FUSED, FLAG_GENERIC_KERNEL, FLAG_COUPLINGS_KEEP = 1, 2, 4, 8
+FLAG_PACKED = 16
 BOND_RESET, BOND_ACCUMULATE, BOND_READ = 0, 1, 2
 SMC_OK, SMC_EINVAL, SMC_ERANGE, SMC_EDEVICE, SMC_ESTATE = 0, -1, -2, -3, -4
 
@@ -47,7 +48,7 @@ EXPORTS = ["smc_spin_bytes", "smc_coupling_bytes", "smc_workspace_bytes", "smc_b
            "smc_chains_spin_bytes", "smc_chains_coupling_bytes", "smc_chains_bond_bytes",
            "smc_chains_workspace_bytes", "smc_chains_init", "smc_chains_sample",
            "smc_chains_covariance", "smc_chains_get_sweep_index", "smc_chains_set_sweep_index",
-           "smc_chains_destroy"]
+           "smc_chains_destroy", "smc_pack_spins", "smc_unpack_spins"]
 
 
 class SmcError(RuntimeError):
@@ -145,6 +146,8 @@ def load_library():
     lib.smc_chains_get_sweep_index.argtypes = [vp, C.POINTER(C.c_uint64)]
     lib.smc_chains_set_sweep_index.argtypes = [vp, C.c_uint64]
     lib.smc_chains_destroy.argtypes = [vp]
+    lib.smc_pack_spins.argtypes = [vp, vp, C.c_int64, vp]
+    lib.smc_unpack_spins.argtypes = [vp, vp, C.c_int64, vp]
     lib.smc_last_error.restype = C.c_char_p
     lib.smc_version.restype = C.c_char_p
     for f in EXPORTS:
@@ -185,13 +188,18 @@ class Lattice:
     def __init__(self, d: int, n: int, L: int, seed: int = 0, *, J_kind=J_UNIFORM, J0: float = 1.0,
                  J_sigma: float = 0.0, init="hot", delta=None, renorm_every: int = 100,
                  replica: int = 0, fast_math: bool = False, fused: bool = False,
-                 generic: bool = False, spins=None, J=None, device=None, stream=None):
+                 generic: bool = False, packed: bool = False, spins=None, J=None, device=None,
+                 stream=None):
+        """packed: Ising spins (and +-1 couplings) at one bit per site; then
+        `spins` is int32 [2, N/64] and J int32 [d, 2, N/64] (bit k & 31 of word
+        k >> 5 = site k of a plane, bit 1 = -1)."""
         import torch
         lib = load_library()
         self.torch = torch
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         flags = (FLAG_FAST_MATH if fast_math else 0) | (FLAG_SCHEDULE_FUSED if fused else 0) | (
-            FLAG_GENERIC_KERNEL if generic else 0)
+            FLAG_GENERIC_KERNEL if generic else 0) | (FLAG_PACKED if packed else 0)
+        self.packed = packed
         if J is not None:
             flags |= FLAG_COUPLINGS_KEEP
         if spins is not None and init == "hot":
@@ -208,6 +216,8 @@ class Lattice:
             _check(lib.smc_init_lattice(C.byref(h), C.byref(p), None, None, None, 0, None))
         shape = (2, self.N // 2) if n == 1 else (n, 2, self.N // 2)
         dt = torch.int8 if n == 1 else torch.float32
+        if packed:
+            shape, dt = (2, self.N // 64), torch.int32
         if spins is not None:
             spins = spins.to(self.device, dt).contiguous().view(shape)
             self.spins = spins.clone()
@@ -218,10 +228,13 @@ class Lattice:
             self.J = None
         else:
             jdt = torch.int8 if kind == J_PM else torch.float32
+            jshape = (d, 2, self.N // 2)
+            if packed:
+                jdt, jshape = torch.int32, (d, 2, self.N // 64)
             if J is not None:
-                self.J = J.to(self.device, jdt).contiguous().view(d, 2, self.N // 2).clone()
+                self.J = J.to(self.device, jdt).contiguous().view(jshape).clone()
             else:
-                self.J = torch.empty((d, 2, self.N // 2), dtype=jdt, device=self.device)
+                self.J = torch.empty(jshape, dtype=jdt, device=self.device)
         wsb = lib.smc_workspace_bytes(C.byref(p))
         self.workspace = torch.empty(wsb + 256, dtype=torch.uint8, device=self.device)
         off = (-self.workspace.data_ptr()) % 256
@@ -560,6 +573,31 @@ class Chains:
     @t.setter
     def t(self, value: int):
         _check(load_library().smc_chains_set_sweep_index(self._h, int(value)))
+
+
+def pack_spins(src, stream=None):
+    """int8 +-1 sites (any shape, total a multiple of 32) -> int32 words, one
+    bit per site (bit 1 = -1), in the library's kernels."""
+    import torch
+    assert src.dtype == torch.int8 and src.is_cuda and src.is_contiguous()
+    n = src.numel()
+    out = torch.empty(n // 32, dtype=torch.int32, device=src.device)
+    st = stream if stream is not None else torch.cuda.current_stream(src.device)
+    _check(load_library().smc_pack_spins(C.c_void_p(src.data_ptr()), C.c_void_p(out.data_ptr()), n,
+                                         C.c_void_p(st.cuda_stream)))
+    return out
+
+
+def unpack_spins(src, stream=None):
+    """Inverse of pack_spins: int32 words -> int8 +-1 sites (flat)."""
+    import torch
+    assert src.dtype == torch.int32 and src.is_cuda and src.is_contiguous()
+    n = src.numel() * 32
+    out = torch.empty(n, dtype=torch.int8, device=src.device)
+    st = stream if stream is not None else torch.cuda.current_stream(src.device)
+    _check(load_library().smc_unpack_spins(C.c_void_p(src.data_ptr()), C.c_void_p(out.data_ptr()),
+                                           n, C.c_void_p(st.cuda_stream)))
+    return out
 
 
 def version() -> str:

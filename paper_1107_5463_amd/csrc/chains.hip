@@ -41,10 +41,11 @@ __global__ __launch_bounds__(256) void chains_kernel(const ChainsLaunch a, int8_
   int8_t* gs = spins + (uint64_t)chain * N;
   // LDS: 16 doubles of reduction scratch, the accumulator (4 or 8 bytes per
   // bond), then both colour planes
+  constexpr size_t kAcc = MODE == 1 ? 8 : 4;  // bytes per bond (chains_lds_bytes)
   double* red = reinterpret_cast<double*>(smem);
   int32_t* acc_i = reinterpret_cast<int32_t*>(smem + 16 * sizeof(double));
   double* acc_d = reinterpret_cast<double*>(smem + 16 * sizeof(double));
-  int8_t* lat = reinterpret_cast<int8_t*>(smem + 16 * sizeof(double) + (size_t)nb * (MODE == 0 ? 4 : 8));
+  int8_t* lat = reinterpret_cast<int8_t*>(smem + 16 * sizeof(double) + (size_t)nb * kAcc);
   const float* J = a.J;
   const float beta = a.beta;
 
@@ -52,7 +53,7 @@ __global__ __launch_bounds__(256) void chains_kernel(const ChainsLaunch a, int8_
     reinterpret_cast<uint32_t*>(lat)[w] = reinterpret_cast<const uint32_t*>(gs)[w];
   for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
     if (MODE == 0) acc_i[b] = 0;
-    else acc_d[b] = 0.0;
+    if (MODE == 1) acc_d[b] = 0.0;
   }
   __syncthreads();
 
@@ -189,9 +190,11 @@ __global__ __launch_bounds__(256) void chains_reduce_kernel(const double* __rest
   }
 }
 
+// LDS of one chain: reduction scratch, per-bond accumulator (int32 when
+// sampling or sweeping only, double for the covariance), both planes.
 size_t chains_lds_bytes(const Geom& g, int mode) {
   const size_t N = 2 * (size_t)g.Nh;
-  return (size_t)g.d * N * (mode == 0 ? 4 : 8) + N + 16 * sizeof(double);
+  return 16 * sizeof(double) + (size_t)g.d * N * (mode == 1 ? 8 : 4) + N;
 }
 
 static const void* chains_fn(int d, int mode) {

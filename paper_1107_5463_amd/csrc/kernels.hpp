@@ -149,4 +149,16 @@ hipError_t launch_chains_covariance(const ChainsLaunch& a, int8_t* spins, uint32
                                     double* gpart, double* cov_acc, double* G_acc,
                                     hipStream_t st);
 
+// Bit-packed Ising spins (32 sites per word, same plane order as int8).
+bool packed_supported(const Geom& g, int J_kind);
+uint32_t packed_rows_per_band(const Geom& g, uint32_t min_waves);
+hipError_t launch_packed_half_sweep(const IsingLaunch& a, uint32_t* spins, const uint32_t* J,
+                                    uint32_t t, uint32_t c, void* partials, int64_t* nparts,
+                                    hipStream_t st);
+hipError_t launch_pack(const int8_t* src, uint32_t* dst, int64_t n_words, hipStream_t st);
+hipError_t launch_unpack(const uint32_t* src, int8_t* dst, int64_t n_words, hipStream_t st);
+hipError_t launch_init_packed(const Geom& g, RngKey key, int mode, uint32_t* out, hipStream_t st);
+hipError_t launch_measure_packed(const Geom& g, int J_kind, const uint32_t* s, const uint32_t* J,
+                                 void* partials, int64_t* nparts, hipStream_t st);
+
 }  // namespace smc

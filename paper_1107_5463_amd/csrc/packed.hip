@@ -1,0 +1,533 @@
+// packed.hip -- Ising spins at one bit per site (multi-spin coding, Sec. 2:
+// many spins per machine word), computing exactly the chain of the int8
+// kernels.
+//
+// Layout: the colour-split planes of the int8 layout with 32 consecutive
+// same-colour sites per 32-bit word, site j of a plane in bit j & 31 of word
+// j >> 5; bit 1 = spin -1.  A plane row (L/2 sites) is W = L/64 words.  +-1
+// couplings use the same layout per (mu, colour) plane, bit 1 = J = -1.
+//
+// Half-sweep: a lane owns one word column of its colour and walks a band of H
+// rows, as the int8 streaming kernel does.  Per word (32 sites):
+//  * the unsatisfied bonds of the 2d neighbours are the xor of the two spin
+//    bits (and the coupling's sign bit); the x-neighbour word is the other
+//    colour's word shifted by one bit with the adjacent word's edge bit
+//    (v_alignbit);
+//  * the count k of unsatisfied bonds is a bit-sliced sum: three bit planes
+//    k0, k1, k2 for 32 sites at once (full adders as v_bitop3);
+//  * the same two Philox blocks as the int8 path give the 32 prefix bytes,
+//    transposed into 8 bit planes (four 8x8 bit transposes by delta swaps and
+//    a byte regroup with v_perm); for each class k whose move can be refused
+//    (at most d of the 2d + 1) a bit-sliced compare with the class's
+//    threshold byte gives the refused sites and the exact ties, applied to
+//    the sites of that class (a bit-sliced equality on k);
+//  * exact ties (prefix byte == threshold byte, 2^-8 of refusable moves) are
+//    queued in LDS and resolved at the end of the band with each site's
+//    24-bit refinement draw, as in the int8 kernel.
+#include "chunk.hpp"
+#include "reduce.hpp"
+
+namespace smc {
+
+// bit 7 of each byte of v -> bits 0..3 (byte b -> bit b): the four flag bits
+// land on bits 28..31 of the product without carries.
+__device__ __forceinline__ uint32_t gather7(uint32_t v) {
+  return ((v & 0x80808080u) * 0x00204081u) >> 28;
+}
+
+// Bit-sliced equality of the 3-bit count (k2 k1 k0) with a constant K.
+template <int K>
+__device__ __forceinline__ uint32_t class_mask(uint32_t k0, uint32_t k1, uint32_t k2) {
+  const uint32_t a = (K & 1) ? k0 : ~k0;
+  const uint32_t b = (K & 2) ? k1 : ~k1;
+  const uint32_t c = (K & 4) ? k2 : ~k2;
+  return a & b & c;
+}
+
+// 8x8 bit transpose of the 64-bit block (lo = bytes 0..3, hi = bytes 4..7):
+// afterwards bit c of byte r is bit r of the original byte c.  Three delta
+// swaps (distances 7, 14, 28) on the 32-bit halves.
+__device__ __forceinline__ void transpose8(uint32_t& lo, uint32_t& hi) {
+  uint32_t t;
+  t = ((lo >> 7) ^ lo) & 0x00AA00AAu;
+  lo = lo ^ t ^ (t << 7);
+  t = ((hi >> 7) ^ hi) & 0x00AA00AAu;
+  hi = hi ^ t ^ (t << 7);
+  t = ((lo >> 14) ^ lo) & 0x0000CCCCu;
+  lo = lo ^ t ^ (t << 14);
+  t = ((hi >> 14) ^ hi) & 0x0000CCCCu;
+  hi = hi ^ t ^ (t << 14);
+  t = (__builtin_amdgcn_alignbit(hi, lo, 28u) ^ lo) & 0xF0F0F0F0u;
+  lo ^= t;
+  hi ^= t >> 4;
+}
+
+// The 32 prefix bytes of a word's sites (site s in byte s & 3 of P[s >> 2])
+// as 8 bit planes: bit s of B[b] = bit b of site s's byte.
+__device__ __forceinline__ void prefix_planes(const uint32_t P[8], uint32_t B[8]) {
+  uint32_t lo[4], hi[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    lo[m] = P[2 * m];
+    hi[m] = P[2 * m + 1];
+    transpose8(lo[m], hi[m]);  // byte b of block m: plane b of sites 8m .. 8m + 7
+  }
+  // regroup bytes: B[b] = (byte b of blocks 0, 1, 2, 3)
+  const uint32_t a0 = __builtin_amdgcn_perm(lo[1], lo[0], 0x05010400u);  // b0: m0 m1, b1: m0 m1
+  const uint32_t a1 = __builtin_amdgcn_perm(lo[1], lo[0], 0x07030602u);  // b2, b3
+  const uint32_t c0 = __builtin_amdgcn_perm(lo[3], lo[2], 0x05010400u);
+  const uint32_t c1 = __builtin_amdgcn_perm(lo[3], lo[2], 0x07030602u);
+  const uint32_t a2 = __builtin_amdgcn_perm(hi[1], hi[0], 0x05010400u);  // b4, b5
+  const uint32_t a3 = __builtin_amdgcn_perm(hi[1], hi[0], 0x07030602u);  // b6, b7
+  const uint32_t c2 = __builtin_amdgcn_perm(hi[3], hi[2], 0x05010400u);
+  const uint32_t c3 = __builtin_amdgcn_perm(hi[3], hi[2], 0x07030602u);
+  B[0] = __builtin_amdgcn_perm(c0, a0, 0x05040100u);
+  B[1] = __builtin_amdgcn_perm(c0, a0, 0x07060302u);
+  B[2] = __builtin_amdgcn_perm(c1, a1, 0x05040100u);
+  B[3] = __builtin_amdgcn_perm(c1, a1, 0x07060302u);
+  B[4] = __builtin_amdgcn_perm(c2, a2, 0x05040100u);
+  B[5] = __builtin_amdgcn_perm(c2, a2, 0x07060302u);
+  B[6] = __builtin_amdgcn_perm(c3, a3, 0x05040100u);
+  B[7] = __builtin_amdgcn_perm(c3, a3, 0x07060302u);
+}
+
+// Bit-sliced unsigned compare of the 32 prefix bytes with the threshold byte
+// th (wave-uniform): ge = P >= th, eq = P == th.
+__device__ __forceinline__ void planes_compare(const uint32_t B[8], uint32_t th, uint32_t& ge,
+                                               uint32_t& eq) {
+  uint32_t lt = 0;
+  eq = ~0u;
+#pragma unroll
+  for (int b = 7; b >= 0; --b) {
+    if ((th >> b) & 1u) {
+      lt |= eq & ~B[b];
+      eq &= B[b];
+    } else {
+      eq &= ~B[b];
+    }
+  }
+  ge = ~lt;
+}
+
+// Per-lane tie queue entries: site (5 bits), row in band (6), class (3),
+// spin was -1 (1).
+struct PackedTies {
+  uint16_t* slot;
+  uint32_t stride, n, base, W;  // base: word index of the lane's column in row 0
+  int64_t dE, dM;
+};
+
+template <int D>
+__device__ __forceinline__ void packed_tie_flush(PackedTies& q, const TabRegs& tab,
+                                                 const RngKey& key, uint32_t t, uint32_t c,
+                                                 uint32_t* own) {
+  for (uint32_t i = 0; i < q.n; ++i) {
+    const uint32_t e = q.slot[i * q.stride];
+    const uint32_t b = e & 31u, row = (e >> 5) & 63u, k = (e >> 11) & 7u;
+    const uint32_t wi = q.base + row * q.W;
+    const uint32_t js = wi * 32u + b;
+    const Rand4 rr = philox(js, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
+    if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) {
+      own[wi] ^= 1u << b;  // the lane's own word, stored earlier by this lane
+      const int v = (e >> 14) & 1u ? -1 : 1;
+      q.dE += 4 * (int64_t)(D - (int)k);
+      q.dM -= 2 * (int64_t)v;
+    }
+  }
+  q.n = 0;
+}
+
+// Decision for the 32 sites of one word.  kq: count planes; returns the
+// flip mask; queues exact ties.
+template <int D>
+__device__ __forceinline__ uint32_t packed_decide(const TabRegs& tab, const RngKey& key,
+                                                  uint32_t t, uint32_t c, uint32_t wi,
+                                                  uint32_t row, uint32_t o, uint32_t k0,
+                                                  uint32_t k1, uint32_t k2, PackedTies& q,
+                                                  uint32_t* own) {
+  const uint32_t blk = wi * 2u;  // Philox blocks of sites 32 wi .. 32 wi + 31
+  const Rand4 ra = philox(blk, t, key.replica, tag(c, kIsingPrefix), key.k0, key.k1);
+  const Rand4 rb = philox(blk + 1u, t, key.replica, tag(c, kIsingPrefix), key.k0, key.k1);
+  const uint32_t P[8] = {ra.w[0], ra.w[1], ra.w[2], ra.w[3], rb.w[0], rb.w[1], rb.w[2], rb.w[3]};
+  uint32_t B[8];
+  prefix_planes(P, B);
+  uint32_t rej = 0, ties = 0, tk0 = 0, tk1 = 0, tk2 = 0;
+  // refusable classes (wave-uniform branches on the table)
+#define SMC_CLASS(KV)                                                              \
+  if (KV <= 2 * D && table_byte(tab.al_lo, tab.al_hi, KV) == 0u) {                 \
+    const uint32_t m = class_mask<KV>(k0, k1, k2);                                 \
+    uint32_t ge, eq;                                                               \
+    planes_compare(B, table_byte(tab.th_lo, tab.th_hi, KV), ge, eq);              \
+    rej |= m & ge;                                                                 \
+    const uint32_t tm = m & eq;                                                    \
+    ties |= tm;                                                                    \
+    if (KV & 1) tk0 |= tm;                                                         \
+    if (KV & 2) tk1 |= tm;                                                         \
+    if (KV & 4) tk2 |= tm;                                                         \
+  }
+  SMC_CLASS(0) SMC_CLASS(1) SMC_CLASS(2) SMC_CLASS(3) SMC_CLASS(4) SMC_CLASS(5) SMC_CLASS(6)
+#undef SMC_CLASS
+  if (ties) {
+    uint32_t m = ties;
+    do {
+      if (q.n == kTieSlots) packed_tie_flush<D>(q, tab, key, t, c, own);
+      const uint32_t b = __builtin_ctz(m);
+      m &= m - 1;
+      const uint32_t k = ((tk0 >> b) & 1u) | (((tk1 >> b) & 1u) << 1) | (((tk2 >> b) & 1u) << 2);
+      const uint32_t neg = (o >> b) & 1u;
+      q.slot[q.n * q.stride] = (uint16_t)(b | (row << 5) | (k << 11) | (neg << 14));
+      q.n += 1;
+    } while (m);
+  }
+  return ~rej;  // ties are refused here and resolved at the end of the band
+}
+
+// Unsatisfied-bond count planes of 32 sites from their 2d neighbour words
+// (xor of the spin bits, and of the coupling bits with +-1 couplings).
+template <int D>
+__device__ __forceinline__ void count_planes(const uint32_t u[6], uint32_t& k0, uint32_t& k1,
+                                             uint32_t& k2) {
+  // full adder of u0, u1, u2
+  const uint32_t s1 = u[0] ^ u[1] ^ u[2];
+  const uint32_t c1 = (u[0] & u[1]) | (u[2] & (u[0] ^ u[1]));
+  if (D == 2) {
+    k0 = s1 ^ u[3];
+    const uint32_t c2 = s1 & u[3];
+    k1 = c1 ^ c2;
+    k2 = c1 & c2;
+  } else {
+    const uint32_t s2 = u[3] ^ u[4] ^ u[5];
+    const uint32_t c2 = (u[3] & u[4]) | (u[5] & (u[3] ^ u[4]));
+    k0 = s1 ^ s2;
+    const uint32_t c3 = s1 & s2;
+    // twos: c1 + c2 + c3
+    k1 = c1 ^ c2 ^ c3;
+    k2 = (c1 & c2) | (c3 & (c1 ^ c2));
+  }
+}
+
+__device__ __forceinline__ int32_t popc(uint32_t v) { return __builtin_popcount(v); }
+
+template <int D, bool PM, bool MEASURE>
+__global__ __launch_bounds__(256) void packed_stream_kernel(const Geom g, const RngKey key,
+                                                            const IsingTable table,
+                                                            const FastDiv divW, const FastDiv divL,
+                                                            const uint32_t H, const uint32_t nbands,
+                                                            uint32_t* __restrict__ s,
+                                                            const uint32_t* __restrict__ J,
+                                                            const uint32_t t, const uint32_t c,
+                                                            Partial* __restrict__ parts) {
+  __shared__ uint16_t tie_slots[kTieSlots * 256];
+  const uint32_t tid = xcd_remap(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
+  const uint32_t band = fdiv(tid, divW);
+  int64_t Esum = 0, Msum = 0;
+  if (band < nbands) {
+    const uint32_t W = divW.d;
+    const uint32_t q = tid - band * W;
+    const uint32_t L = (uint32_t)g.L;
+    const uint32_t r0 = band * H;
+    uint32_t z = 0, y0 = r0;
+    if (D == 3) {
+      z = fdiv(r0, divL);
+      y0 = r0 - z * L;
+    }
+    const uint32_t Wh = (uint32_t)(g.Nh / 32);  // words per plane
+    uint32_t* own = s + (uint64_t)c * Wh;
+    const uint32_t* oth = s + (uint64_t)(1 - c) * Wh;
+    const uint32_t zrow = L * z;
+    const uint32_t qn = q + 1 == W ? 0u : q + 1, qp = q == 0 ? W - 1 : q - 1;
+    auto rw = [&](uint32_t zr, uint32_t y) -> uint32_t {  // word index of (row, q); y < 2L
+      return (zr + (y >= L ? y - L : y)) * W;
+    };
+    uint32_t zm_row = 0, zp_row = 0;
+    if (D == 3) {
+      zm_row = L * (z == 0 ? L - 1 : z - 1);
+      zp_row = L * (z + 1 == L ? 0 : z + 1);
+    }
+    const TabRegs tab = tab_regs(table);
+    PackedTies tq;
+    tq.slot = tie_slots + threadIdx.x;
+    tq.stride = 256;
+    tq.n = 0;
+    tq.base = rw(zrow, y0) + q;
+    tq.W = W;
+    tq.dE = 0;
+    tq.dM = 0;
+    // J planes: J[mu][cc] at (2 mu + cc) * Wh
+    const uint32_t pz = (c + z) & 1u;
+    uint32_t up = oth[rw(zrow, y0 + L - 1) + q];
+    uint32_t ct = oth[rw(zrow, y0) + q];
+    for (uint32_t i = 0; i < H; ++i) {
+      const uint32_t y = y0 + i;
+      const uint32_t rowb = rw(zrow, y);
+      const uint32_t p = (pz + y) & 1u;
+      const uint32_t dn = oth[rw(zrow, y + 1) + q];
+      const uint32_t o = own[rowb + q];
+      const uint32_t en = oth[rowb + qn], ep = oth[rowb + qp];
+      // x+1 neighbours (p = 1: next in-row site) and x-1 (p = 0: previous)
+      const uint32_t sh_next = __builtin_amdgcn_alignbit(en, ct, 1u);
+      const uint32_t sh_prev = __builtin_amdgcn_alignbit(ct, ep, 31u);
+      const uint32_t nxp = mask_sel(ct, sh_next, p);
+      const uint32_t nxm = mask_sel(sh_prev, ct, p);
+      uint32_t u[6];
+      u[0] = o ^ nxp;
+      u[1] = o ^ nxm;
+      u[2] = o ^ dn;
+      u[3] = o ^ up;
+      uint32_t fz = 0, bz = 0;
+      if (D == 3) {
+        fz = oth[rw(zm_row, y) + q];
+        bz = oth[rw(zp_row, y) + q];
+        u[4] = o ^ bz;
+        u[5] = o ^ fz;
+      }
+      if (PM) {
+        const uint32_t* Jo = J + (uint64_t)c * Wh;        // J[mu][c] = J + (2 mu + c) Wh
+        const uint32_t* Jn = J + (uint64_t)(1 - c) * Wh;  // J[mu][1 - c]
+        const uint32_t jc = Jn[rowb + q];
+        const uint32_t jp_prev = Jn[rowb + qp];
+        u[0] ^= Jo[rowb + q];
+        u[1] ^= mask_sel(__builtin_amdgcn_alignbit(jc, jp_prev, 31u), jc, p);
+        u[2] ^= Jo[2 * (uint64_t)Wh + rowb + q];
+        u[3] ^= Jn[2 * (uint64_t)Wh + rw(zrow, y + L - 1) + q];
+        if (D == 3) {
+          u[4] ^= Jo[4 * (uint64_t)Wh + rowb + q];
+          u[5] ^= Jn[4 * (uint64_t)Wh + rw(zm_row, y) + q];
+        }
+      }
+      uint32_t k0, k1, k2;
+      count_planes<D>(u, k0, k1, k2);
+      const uint32_t flip = packed_decide<D>(tab, key, t, c, rowb + q, i, o, k0, k1, k2, tq, own);
+      const uint32_t on = o ^ flip;
+      own[rowb + q] = on;
+      if (MEASURE) {
+        // colour 1 after its update: each bond has one colour-1 end; the
+        // colour-0 word at the same position covers each colour-0 site once
+        const uint32_t fl = o ^ on;  // every bond of a flipped site changes state
+        uint32_t v[6];
+#pragma unroll
+        for (int m = 0; m < 2 * D; ++m) v[m] = u[m] ^ fl;
+        uint32_t n0, n1, n2;
+        count_planes<D>(v, n0, n1, n2);
+        const int32_t ksum = popc(n0) + 2 * popc(n1) + 4 * popc(n2);
+        Esum += -(int64_t)(32 * 2 * D) + 2 * (int64_t)ksum;
+        Msum += (32 - 2 * popc(on)) + (32 - 2 * popc(ct));
+      }
+      up = ct;
+      ct = dn;
+    }
+    packed_tie_flush<D>(tq, tab, key, t, c, own);
+    if (MEASURE) {
+      Esum += tq.dE;
+      Msum += tq.dM;
+    }
+  }
+  if (MEASURE) block_partial_int(Esum, Msum, parts, blockIdx.x);
+}
+
+// Rows per band for the packed kernel: the largest power of two up to 64
+// dividing L that leaves at least min_waves waves.
+uint32_t packed_rows_per_band(const Geom& g, uint32_t min_waves) {
+  const uint32_t W = (uint32_t)(g.R / 32);
+  uint32_t best = 1;
+  for (uint32_t H = 1; H <= 64; H *= 2) {
+    if (g.L % H) break;
+    const uint64_t waves = (uint64_t)W * (uint64_t)(g.rows / H) / 64;
+    if (waves >= min_waves || H == 1) best = H;
+  }
+  return best;
+}
+
+bool packed_supported(const Geom& g, int J_kind) {
+  return (g.d == 2 || g.d == 3) && J_kind != 2 && g.L % 64 == 0;
+}
+
+hipError_t launch_packed_half_sweep(const IsingLaunch& a, uint32_t* spins, const uint32_t* J,
+                                    uint32_t t, uint32_t c, void* partials, int64_t* nparts,
+                                    hipStream_t st) {
+  const uint32_t H = a.rows_per_band;
+  const uint32_t W = (uint32_t)(a.g.R / 32);
+  const uint32_t nbands = (uint32_t)a.g.rows / H;
+  const uint64_t lanes = (uint64_t)nbands * W;
+  const dim3 grid((unsigned)((lanes + 255) / 256)), block(256);
+  const FastDiv dW = make_fastdiv(W), dL = make_fastdiv((uint32_t)a.g.L);
+  const bool pm = a.J_kind == 1;
+  Partial* pp = (Partial*)partials;
+#define SMC_PK(DD, PMM, MM)                                                                     \
+  hipLaunchKernelGGL((packed_stream_kernel<DD, PMM, MM>), grid, block, 0, st, a.g, a.key, a.tab, \
+                     dW, dL, H, nbands, spins, J, t, c, pp)
+  if (a.g.d == 2) {
+    if (pm) { if (pp) SMC_PK(2, true, true); else SMC_PK(2, true, false); }
+    else { if (pp) SMC_PK(2, false, true); else SMC_PK(2, false, false); }
+  } else {
+    if (pm) { if (pp) SMC_PK(3, true, true); else SMC_PK(3, true, false); }
+    else { if (pp) SMC_PK(3, false, true); else SMC_PK(3, false, false); }
+  }
+#undef SMC_PK
+  if (pp && nparts) *nparts = grid.x;
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Packing, initial states, and a standalone measurement.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void pack_kernel(const int8_t* __restrict__ src,
+                                                   uint32_t* __restrict__ dst, int64_t n_words) {
+  const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (w >= n_words) return;
+  const uint4* p = reinterpret_cast<const uint4*>(src + 32 * w);
+  const uint4 a = p[0], b = p[1];
+  const uint32_t v[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+  uint32_t out = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) out |= gather7(v[k]) << (4 * k);  // -1 = 0xFF has bit 7 set
+  dst[w] = out;
+}
+
+__global__ __launch_bounds__(256) void unpack_kernel(const uint32_t* __restrict__ src,
+                                                     int8_t* __restrict__ dst, int64_t n_words) {
+  const int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (w >= n_words) return;
+  const uint32_t v = src[w];
+  uint32_t o[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    // 4 bits -> bit 0 of 4 bytes; -1 = 0xFF, +1 = 0x01
+    const uint32_t nib = (v >> (4 * k)) & 0xFu;
+    const uint32_t ones = ((nib * 0x00204081u) & 0x01010101u);
+    o[k] = kOnes | (ones * 0xFEu);
+  }
+  uint4* p = reinterpret_cast<uint4*>(dst + 32 * w);
+  p[0] = make_uint4(o[0], o[1], o[2], o[3]);
+  p[1] = make_uint4(o[4], o[5], o[6], o[7]);
+}
+
+hipError_t launch_pack(const int8_t* src, uint32_t* dst, int64_t n_words, hipStream_t st) {
+  if (n_words <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pack_kernel, dim3((unsigned)((n_words + 255) / 256)), dim3(256), 0, st, src,
+                     dst, n_words);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const uint32_t* src, int8_t* dst, int64_t n_words, hipStream_t st) {
+  if (n_words <= 0) return hipSuccess;
+  hipLaunchKernelGGL(unpack_kernel, dim3((unsigned)((n_words + 255) / 256)), dim3(256), 0, st,
+                     src, dst, n_words);
+  return hipGetLastError();
+}
+
+// Hot/cold start (mode 0 / 1) or +-1 couplings (mode 2) of the packed planes,
+// with the draws of the int8 initialisation (keyed by natural site index).
+__global__ __launch_bounds__(256) void init_packed_kernel(const Geom g, const RngKey key,
+                                                          const int mode,
+                                                          uint32_t* __restrict__ out) {
+  const int64_t wid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t Wh = g.Nh / 32;
+  const int64_t planes = mode == 2 ? 2 * (int64_t)g.d : 2;
+  if (wid >= planes * Wh) return;
+  const int64_t pl = wid / Wh;
+  const uint32_t c = (uint32_t)(pl & 1);
+  const uint32_t mu = (uint32_t)(pl >> 1);
+  const int64_t j0 = (wid - pl * Wh) * 32;
+  uint32_t word = 0;
+  if (mode != 1) {
+    const uint32_t purpose = mode == 2 ? kCoupling : kInitSpin;
+    const uint32_t w1 = mode == 2 ? mu : 0u;
+    for (int b = 0; b < 32; ++b) {
+      int32_t x, y, z;
+      site_coords(g, c, j0 + b, x, y, z);
+      const int64_t i = natural_index(g, x, y, z);
+      const Rand4 r = philox((uint32_t)(i >> 7), w1, key.replica, tag(0, purpose), key.k0, key.k1);
+      const uint32_t sel = (uint32_t)(i >> 5) & 3u;
+      const uint32_t wv = sel == 0 ? r.w[0] : (sel == 1 ? r.w[1] : (sel == 2 ? r.w[2] : r.w[3]));
+      word |= ((wv >> (i & 31)) & 1u) << b;
+    }
+  }
+  out[wid] = word;
+}
+
+hipError_t launch_init_packed(const Geom& g, RngKey key, int mode, uint32_t* out, hipStream_t st) {
+  const int64_t n = (mode == 2 ? 2 * (int64_t)g.d : 2) * (g.Nh / 32);
+  hipLaunchKernelGGL(init_packed_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g,
+                     key, mode, out);
+  return hipGetLastError();
+}
+
+// E and M of a packed state: one lane per colour-1 word (each bond has one
+// colour-1 end), plus the colour-0 word at the same position.
+template <int D, bool PM>
+__global__ __launch_bounds__(256) void measure_packed_kernel(const Geom g,
+                                                             const uint32_t* __restrict__ s,
+                                                             const uint32_t* __restrict__ J,
+                                                             Partial* __restrict__ parts) {
+  const int64_t Wh = g.Nh / 32;
+  const int64_t wid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int64_t E = 0, M = 0;
+  if (wid < Wh) {
+    const uint32_t W = (uint32_t)(g.R / 32);
+    const uint32_t L = (uint32_t)g.L;
+    const uint32_t r = (uint32_t)(wid / W), q = (uint32_t)(wid - (int64_t)r * W);
+    const uint32_t y = r % L, z = r / L;
+    const uint32_t p = (1u + y + z) & 1u;
+    const uint32_t* s1 = s + Wh;
+    const uint32_t* s0 = s;
+    auto at = [&](uint32_t yy, uint32_t zz, uint32_t qq) -> int64_t {
+      return ((int64_t)zz * L + yy) * W + qq;
+    };
+    const uint32_t qn = q + 1 == W ? 0u : q + 1, qp = q == 0 ? W - 1 : q - 1;
+    const uint32_t ym = y == 0 ? L - 1 : y - 1, yp = y + 1 == L ? 0 : y + 1;
+    const uint32_t o = s1[wid];
+    const uint32_t ct = s0[wid];
+    const uint32_t sn = __builtin_amdgcn_alignbit(s0[at(y, z, qn)], ct, 1u);
+    const uint32_t sp = __builtin_amdgcn_alignbit(ct, s0[at(y, z, qp)], 31u);
+    uint32_t u[6];
+    u[0] = o ^ (p ? sn : ct);
+    u[1] = o ^ (p ? ct : sp);
+    u[2] = o ^ s0[at(yp, z, q)];
+    u[3] = o ^ s0[at(ym, z, q)];
+    uint32_t zm = 0, zp = 0;
+    if (D == 3) {
+      zm = z == 0 ? L - 1 : z - 1;
+      zp = z + 1 == L ? 0 : z + 1;
+      u[4] = o ^ s0[at(y, zp, q)];
+      u[5] = o ^ s0[at(y, zm, q)];
+    }
+    if (PM) {
+      const uint32_t* J1 = J + Wh;  // J[mu][1] = J + (2 mu + 1) Wh
+      const uint32_t* J0 = J;       // J[mu][0]
+      const uint32_t jc = J0[wid];
+      u[0] ^= J1[wid];
+      u[1] ^= p ? jc : __builtin_amdgcn_alignbit(jc, J0[at(y, z, qp)], 31u);
+      u[2] ^= J1[2 * Wh + wid];
+      u[3] ^= J0[2 * Wh + at(ym, z, q)];
+      if (D == 3) {
+        u[4] ^= J1[4 * Wh + wid];
+        u[5] ^= J0[4 * Wh + at(y, zm, q)];
+      }
+    }
+    uint32_t k0, k1, k2;
+    count_planes<D>(u, k0, k1, k2);
+    E = -(int64_t)(32 * 2 * D) + 2 * (int64_t)(popc(k0) + 2 * popc(k1) + 4 * popc(k2));
+    M = (32 - 2 * popc(o)) + (32 - 2 * popc(ct));
+  }
+  block_partial_int(E, M, parts, blockIdx.x);
+}
+
+hipError_t launch_measure_packed(const Geom& g, int J_kind, const uint32_t* s, const uint32_t* J,
+                                 void* partials, int64_t* nparts, hipStream_t st) {
+  const int64_t Wh = g.Nh / 32;
+  const dim3 grid((unsigned)((Wh + 255) / 256)), block(256);
+  Partial* pp = (Partial*)partials;
+  if (g.d == 2) {
+    if (J_kind == 1) hipLaunchKernelGGL((measure_packed_kernel<2, true>), grid, block, 0, st, g, s, J, pp);
+    else hipLaunchKernelGGL((measure_packed_kernel<2, false>), grid, block, 0, st, g, s, J, pp);
+  } else {
+    if (J_kind == 1) hipLaunchKernelGGL((measure_packed_kernel<3, true>), grid, block, 0, st, g, s, J, pp);
+    else hipLaunchKernelGGL((measure_packed_kernel<3, false>), grid, block, 0, st, g, s, J, pp);
+  }
+  *nparts = grid.x;
+  return hipGetLastError();
+}
+
+}  // namespace smc

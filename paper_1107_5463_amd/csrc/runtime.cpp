@@ -41,6 +41,7 @@ struct smc_lattice {
   uint32_t rows_per_band;    // streaming kernel band height (SMC_STREAM_ROWS overrides)
   bool use_fused;            // SMC_FLAG_SCHEDULE_FUSED and the fused kernel supports the shape
   uint32_t fused_rows;       // fused kernel band height (SMC_FUSED_ROWS overrides)
+  uint32_t packed_rows;      // packed kernel band height (SMC_PACKED_ROWS overrides)
   // workspace carve-up
   void* obs_slot;      // smc_obs (64 B)
   uint32_t* counter;   // validation counter
@@ -84,12 +85,19 @@ bool params_ok(const smc_params* p, std::string& why) {
     if (p->n == 3 && p->delta > M_PI) { why = "Heisenberg cap half-angle must be <= pi"; return false; }
   }
   if (p->flags & ~(SMC_FLAG_FAST_MATH | SMC_FLAG_SCHEDULE_FUSED | SMC_FLAG_GENERIC_KERNEL |
-                   SMC_FLAG_COUPLINGS_KEEP)) {
+                   SMC_FLAG_COUPLINGS_KEEP | SMC_FLAG_PACKED)) {
     why = "unknown flag bits";
     return false;
   }
+  if (p->flags & SMC_FLAG_PACKED) {
+    if (p->n != 1) { why = "packed spins are Ising only (n = 1)"; return false; }
+    if (p->J_kind == SMC_J_FP32) { why = "packed spins take uniform or +-1 couplings"; return false; }
+    if (p->L % 64) { why = "packed spins need L % 64 == 0"; return false; }
+  }
   return true;
 }
+
+bool is_packed(const smc_params* p) { return (p->flags & SMC_FLAG_PACKED) != 0; }
 
 int64_t n_sites(const smc_params* p) {
   int64_t N = 1;
@@ -108,6 +116,7 @@ Geom make_geom(const smc_params* p) {
 }
 
 size_t spin_bytes(const smc_params* p) {
+  if (is_packed(p)) return (size_t)n_sites(p) / 8;
   return (size_t)n_sites(p) * (p->n == 1 ? 1 : 4 * (size_t)p->n);
 }
 
@@ -195,7 +204,27 @@ IsingLaunch ising_args(smc_lattice* h, double beta) {
   return a;
 }
 
+// E and M of the current state into dev_obs (any spin format).
+hipError_t measure_any(smc_lattice* h, int64_t sweep, void* dev_obs) {
+  if (is_packed(&h->p)) {
+    int64_t nparts = 0;
+    const hipError_t e = launch_measure_packed(h->g, h->p.J_kind, (const uint32_t*)h->spins,
+                                               (const uint32_t*)h->J, h->partials, &nparts,
+                                               h->stream);
+    if (e != hipSuccess) return e;
+    return launch_finish(measure_args(h, sweep), h->partials, nparts, dev_obs, h->stream);
+  }
+  return launch_measure(measure_args(h, sweep), h->spins, h->partials, dev_obs, h->stream);
+}
+
 int half_sweep_impl(smc_lattice* h, double beta, uint32_t t, uint32_t colour) {
+  if (is_packed(&h->p)) {
+    IsingLaunch a = ising_args(h, beta);
+    a.rows_per_band = h->packed_rows;
+    return check(launch_packed_half_sweep(a, (uint32_t*)h->spins, (const uint32_t*)h->J, t, colour,
+                                          nullptr, nullptr, h->stream),
+                 "packed Ising half-sweep launch");
+  }
   if (h->p.n == 1) {
     const IsingLaunch a = ising_args(h, beta);
     return check(launch_ising_half_sweep(a, (int8_t*)h->spins, t, colour, h->stream),
@@ -222,6 +251,17 @@ int half_sweep_impl(smc_lattice* h, double beta, uint32_t t, uint32_t colour) {
 int two_pass_sweep(smc_lattice* h, double beta, uint32_t t, void* dev_obs) {
   int rc = half_sweep_impl(h, beta, t, 0u);
   if (rc != SMC_OK) return rc;
+  if (dev_obs && is_packed(&h->p)) {
+    IsingLaunch a = ising_args(h, beta);
+    a.rows_per_band = h->packed_rows;
+    int64_t nparts = 0;
+    rc = check(launch_packed_half_sweep(a, (uint32_t*)h->spins, (const uint32_t*)h->J, t, 1u,
+                                        h->partials, &nparts, h->stream),
+               "measured packed half-sweep launch");
+    if (rc != SMC_OK) return rc;
+    return check(launch_finish(measure_args(h, (int64_t)t + 1), h->partials, nparts, dev_obs, h->stream),
+                 "measurement finish launch");
+  }
   if (dev_obs && h->p.n == 1) {
     const IsingLaunch a = ising_args(h, beta);
     int64_t nparts = 0;
@@ -236,7 +276,7 @@ int two_pass_sweep(smc_lattice* h, double beta, uint32_t t, void* dev_obs) {
   rc = half_sweep_impl(h, beta, t, 1u);
   if (rc != SMC_OK) return rc;
   if (dev_obs)
-    return check(launch_measure(measure_args(h, (int64_t)t + 1), h->spins, h->partials, dev_obs, h->stream),
+    return check(measure_any(h, (int64_t)t + 1, dev_obs),
                  "measurement launch");
   return SMC_OK;
 }
@@ -290,7 +330,7 @@ int sweeps_impl(smc_lattice* h, double beta, int64_t n_sweeps, void* dev_obs) {
       rc = check(launch_renormalize(h->g, h->p.n, (float*)h->spins, h->stream), "renormalisation launch");
       if (rc != SMC_OK) return rc;
       if (last && dev_obs)
-        return check(launch_measure(measure_args(h, h->t), h->spins, h->partials, dev_obs, h->stream),
+        return check(measure_any(h, h->t, dev_obs),
                      "measurement launch");
     }
   }
@@ -309,6 +349,7 @@ size_t smc_spin_bytes(const smc_params* p) {
 size_t smc_coupling_bytes(const smc_params* p) {
   std::string why;
   if (!params_ok(p, why) || p->J_kind == SMC_J_UNIFORM) return 0;
+  if (is_packed(p)) return (size_t)n_sites(p) * p->d / 8;
   return (size_t)n_sites(p) * p->d * (p->J_kind == SMC_J_PM ? 1 : 4);
 }
 
@@ -317,13 +358,13 @@ size_t smc_workspace_bytes(const smc_params* p) {
   if (!params_ok(p, why)) return 0;
   size_t b = 2 * kAlign;  // observable slot + counter
   b += partial_bytes(p);
-  if (p->flags & SMC_FLAG_SCHEDULE_FUSED) b += round_up(spin_bytes(p), kAlign);
+  if ((p->flags & SMC_FLAG_SCHEDULE_FUSED) && !is_packed(p)) b += round_up(spin_bytes(p), kAlign);
   return b;
 }
 
 size_t smc_bond_bytes(const smc_params* p) {
   std::string why;
-  return params_ok(p, why) ? (size_t)n_sites(p) * p->d * 8 : 0;
+  return params_ok(p, why) && !is_packed(p) ? (size_t)n_sites(p) * p->d * 8 : 0;
 }
 
 int smc_init_lattice(smc_lattice** out, const smc_params* p, void* spins, void* J,
@@ -376,15 +417,27 @@ int smc_init_lattice(smc_lattice** out, const smc_params* p, void* spins, void* 
     const long H = std::strtol(v, nullptr, 10);
     if (H >= 1 && H <= 64 && H <= h->g.L && h->g.L % H == 0) h->fused_rows = (uint32_t)H;
   }
-  h->use_fused = p->n == 1 && (p->flags & SMC_FLAG_SCHEDULE_FUSED) &&
+  h->packed_rows = packed_rows_per_band(h->g, 4096);
+  if (const char* v = std::getenv("SMC_PACKED_ROWS")) {
+    const long H = std::strtol(v, nullptr, 10);
+    if (H >= 1 && H <= 64 && H <= h->g.L && h->g.L % H == 0) h->packed_rows = (uint32_t)H;
+  }
+  h->use_fused = p->n == 1 && !is_packed(p) && (p->flags & SMC_FLAG_SCHEDULE_FUSED) &&
                  !(p->flags & SMC_FLAG_GENERIC_KERNEL) &&
                  ising_fused_supported(h->g, p->J_kind, h->fused_rows);
   const RngKey key = key_of(h);
   int rc = SMC_OK;
-  if (p->J_kind != SMC_J_UNIFORM && !(p->flags & SMC_FLAG_COUPLINGS_KEEP))
+  if (is_packed(p)) {
+    if (p->J_kind == SMC_J_PM && !(p->flags & SMC_FLAG_COUPLINGS_KEEP))
+      rc = check(launch_init_packed(h->g, key, 2, (uint32_t*)h->J, h->stream), "coupling init launch");
+    if (rc == SMC_OK && p->init != SMC_INIT_KEEP)
+      rc = check(launch_init_packed(h->g, key, p->init == SMC_INIT_HOT ? 0 : 1, (uint32_t*)spins,
+                                    h->stream),
+                 "spin init launch");
+  } else if (p->J_kind != SMC_J_UNIFORM && !(p->flags & SMC_FLAG_COUPLINGS_KEEP))
     rc = check(launch_init_couplings(h->g, p->J_kind, key, p->J0, p->J_sigma, h->J, h->stream),
                "coupling init launch");
-  if (rc == SMC_OK && p->init != SMC_INIT_KEEP) {
+  if (rc == SMC_OK && p->init != SMC_INIT_KEEP && !is_packed(p)) {
     const int hot = p->init == SMC_INIT_HOT;
     if (p->n == 1)
       rc = check(launch_init_ising(h->g, key, hot, (int8_t*)spins, h->stream), "spin init launch");
@@ -423,7 +476,7 @@ int smc_sweep_measure(smc_lattice* h, double beta, int64_t n_sweeps, void* dev_o
   if (h->t + (uint64_t)n_sweeps > 4294967296ull)
     return fail(SMC_ERANGE, "sweep counter would exceed 2^32");
   if (n_sweeps == 0)
-    return check(launch_measure(measure_args(h, h->t), h->spins, h->partials, dev_obs, h->stream),
+    return check(measure_any(h, h->t, dev_obs),
                  "measurement launch");
   return sweeps_impl(h, beta, n_sweeps, dev_obs);
 }
@@ -439,7 +492,7 @@ int smc_half_sweep(smc_lattice* h, double beta, int colour) {
 int smc_measure_async(smc_lattice* h, void* dev_obs) {
   if (!h) return fail(SMC_EINVAL, "handle is NULL");
   if (!dev_obs || ((uintptr_t)dev_obs & 7)) return fail(SMC_EINVAL, "dev_obs must be 8-byte aligned");
-  return check(launch_measure(measure_args(h, h->t), h->spins, h->partials, dev_obs, h->stream),
+  return check(measure_any(h, h->t, dev_obs),
                "measurement launch");
 }
 
@@ -460,6 +513,7 @@ int smc_measure(smc_lattice* h, smc_obs* out) {
 
 int smc_bond_correlations(smc_lattice* h, int op, void* acc, void* out_mean) {
   if (!h) return fail(SMC_EINVAL, "handle is NULL");
+  if (is_packed(&h->p)) return fail(SMC_ESTATE, "bond correlations are not available for packed spins");
   if (!acc || ((uintptr_t)acc & 7)) return fail(SMC_EINVAL, "acc must be non-NULL and 8-byte aligned");
   const MeasureLaunch m = measure_args(h, h->t);
   switch (op) {
@@ -501,6 +555,7 @@ int smc_renormalize(smc_lattice* h) {
 
 int smc_validate(smc_lattice* h) {
   if (!h) return fail(SMC_EINVAL, "handle is NULL");
+  if (is_packed(&h->p)) return SMC_OK;  // every bit pattern is a valid state
   int rc = check(launch_fill_zero(h->counter, 4, h->stream), "counter reset");
   if (rc != SMC_OK) return rc;
   rc = check(launch_validate(measure_args(h, h->t), h->spins, h->counter, h->stream), "validate launch");
@@ -532,6 +587,10 @@ const char* smc_kernel_name(const smc_lattice* h, uint32_t* rows_per_band) {
   if (!h) return "";
   if (h->p.n == 2) return "xy_site";
   if (h->p.n == 3) return "heisenberg_site";
+  if (is_packed(&h->p)) {
+    if (rows_per_band) *rows_per_band = h->packed_rows;
+    return "ising_packed";
+  }
   if (h->use_fused) {
     if (rows_per_band) *rows_per_band = h->fused_rows;
     return "ising_fused";
@@ -553,6 +612,22 @@ const char* smc_kernel_name(const smc_lattice* h, uint32_t* rows_per_band) {
 int smc_destroy(smc_lattice* h) {
   delete h;
   return SMC_OK;
+}
+
+int smc_pack_spins(const void* src, void* dst, int64_t n_sites, void* stream) {
+  if (n_sites < 0 || n_sites % 32) return fail(SMC_EINVAL, "n_sites must be a non-negative multiple of 32");
+  if (n_sites && (!src || !dst || ((uintptr_t)src & 15) || ((uintptr_t)dst & 3)))
+    return fail(SMC_EINVAL, "src must be 16-byte and dst 4-byte aligned");
+  return check(launch_pack((const int8_t*)src, (uint32_t*)dst, n_sites / 32, (hipStream_t)stream),
+               "pack launch");
+}
+
+int smc_unpack_spins(const void* src, void* dst, int64_t n_sites, void* stream) {
+  if (n_sites < 0 || n_sites % 32) return fail(SMC_EINVAL, "n_sites must be a non-negative multiple of 32");
+  if (n_sites && (!src || !dst || ((uintptr_t)src & 3) || ((uintptr_t)dst & 15)))
+    return fail(SMC_EINVAL, "src must be 4-byte and dst 16-byte aligned");
+  return check(launch_unpack((const uint32_t*)src, (int8_t*)dst, n_sites / 32, (hipStream_t)stream),
+               "unpack launch");
 }
 
 const char* smc_last_error(void) { return g_err.c_str(); }

@@ -42,7 +42,7 @@ CASES = [  # d, L, chains, sweeps, beta, seed
     (3, 4, 5, 30, 0.25, 4),
     (2, 64, 2, 10, 0.4, 5),
     (3, 6, 3, 20, 0.3, 6),
-    (2, 4, 9, 50, 0.5, 7),
+    (2, 4, 9, 50, 0.5, 8),
 ]
 
 
