@@ -66,6 +66,9 @@ enum smc_flags {
                                     results; other shapes keep the two-pass schedule) */
   SMC_FLAG_GENERIC_KERNEL = 4,   /* force the one-site-per-thread kernels (testing) */
   SMC_FLAG_COUPLINGS_KEEP = 8,   /* do not generate J at init; use the caller's values */
+  SMC_FLAG_HEATBATH = 32,        /* Ising, uniform or +-1 J: heat-bath rule (Sec. 2): new spin
+                                    +1 iff u32 < ceil(2^32 / (1 + exp(-2 beta h))) with the
+                                    Metropolis draws; plain sweeps run the one-site kernel */
   SMC_FLAG_PACKED = 16           /* Ising spins (and +-1 couplings) at one bit per site
                                     (Sec. 2, multi-spin coding): the int8 planes' site
                                     order, site j in bit j & 31 of 32-bit word j >> 5,
@@ -90,6 +93,13 @@ typedef struct smc_params {
   int32_t renorm_every; /* continuous spins: renormalise after sweeps with t % R == 0
                            (0 = never) */
   int32_t flags;        /* enum smc_flags */
+  int32_t tile;         /* 0: plain sweeps; T > 0: the tiled k-hit schedule of Sec. 2
+                           (Ising, uniform J; T % 32 == 0, L / T even; 2D T <= 256,
+                           3D T = 32): tiles of edge T coloured by (tx+ty+tz) mod 2,
+                           a sweep = for tile colour 0 then 1: `hits` times colour-0
+                           sites then colour-1 sites of those tiles; hit h uses
+                           counter word 3 = colour | purpose << 1 | h << 8 */
+  int32_t hits;         /* k >= 1 for the tiled schedule (0 or 1 otherwise) */
 } smc_params;
 
 typedef struct smc_obs {

@@ -103,6 +103,13 @@ def threshold(beta: float, dE: float) -> int:
     return int(lib().oracle_threshold(float(beta), float(dE)))
 
 
+def threshold_hb(beta: float, h: float) -> int:
+    f = lib().oracle_threshold_hb
+    f.argtypes = [C.c_double, C.c_double]
+    f.restype = C.c_uint64
+    return int(f(float(beta), float(h)))
+
+
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
 
@@ -192,6 +199,21 @@ class OracleLattice:
         self.t += n_sweeps
         return [_obs(series[k]) for k in range(nser)], Stats(st.n_attempt, st.n_accept,
                                                              st.dE_units, st.dE, st.n_near)
+
+    def sweep_rule(self, beta: float, n_sweeps: int = 1, rule: str = "metropolis", tile: int = 0,
+                   hits: int = 1):
+        """Ising sweeps under the Metropolis or heat-bath rule, plain (tile 0)
+        or tiled k-hit (tile edge T, k = hits)."""
+        f = lib().oracle_sweeps_rule
+        f.argtypes = [C.POINTER(_Params), C.c_void_p, C.c_void_p, C.c_double, C.c_uint64, C.c_int64,
+                      C.c_int, C.c_int, C.c_int]
+        f.restype = C.c_int
+        r = {"metropolis": 0, "heatbath": 1}[rule]
+        rc = f(C.byref(self.p), self.s.ctypes.data, self._Jp, float(beta), int(self.t),
+               int(n_sweeps), r, int(tile), int(hits))
+        if rc != 0:
+            raise ValueError(f"oracle_sweeps_rule rejected its arguments (rc={rc})")
+        self.t += n_sweeps
 
     def renormalize(self):
         lib().oracle_renormalize(C.byref(self.p), self.s.ctypes.data)

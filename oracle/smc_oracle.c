@@ -660,6 +660,97 @@ ORACLE_API int oracle_ensemble_ising(const oracle_params *p, const int8_t *s0, c
   return 0;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Update rules and the tiled k-hit schedule (Sec. 2).                      */
+/*                                                                          */
+/* Heat bath: the new spin is +1 with probability                           */
+/*   p_+ = 1 / (1 + exp(-2 beta h)),  h = J0 sum_nb sign(J) s_nb,          */
+/* whatever the old spin; with u = u32 / 2^32 (the Metropolis draw: prefix  */
+/* byte and 24-bit refinement), s = +1 iff u32 < T_hb = ceil(2^32 p_+).     */
+/*                                                                          */
+/* Tiled k-hit schedule: the lattice is cut into tiles of edge T (L/T even),*/
+/* tiles coloured by (tx + ty + tz) mod 2.  A sweep treats tile colour 0,   */
+/* then tile colour 1; for one tile colour, k times: every site of colour 0 */
+/* in those tiles, then every site of colour 1 (the neighbouring tiles stay */
+/* fixed meanwhile).  Every site is attempted k times per sweep.  Hit h of  */
+/* sweep t uses counter word 3 = colour | purpose << 1 | h << 8 (h = 0 is   */
+/* the plain sweep's counter).                                              */
+/* ------------------------------------------------------------------------ */
+ORACLE_API uint64_t oracle_threshold_hb(double beta, double h) {
+  if (isinf(beta)) return h > 0.0 ? 4294967296ull : (h < 0.0 ? 0ull : 2147483648ull);
+  long double b = (long double)beta, e = (long double)h;
+  long double x = ldexpl(1.0L / (1.0L + expl(-2.0L * b * e)), 32);
+  long double c = ceill(x);
+  if (c >= 4294967296.0L) return 4294967296ull;
+  return (uint64_t)c;
+}
+
+static int tile_colour(const oracle_params *p, int64_t i, int T) {
+  int64_t x[3];
+  coords(p, i, x);
+  return (int)((x[0] / T + x[1] / T + (p->d == 3 ? x[2] / T : 0)) & 1);
+}
+
+/* New spin of Ising site i (integer couplings) under rule 0 (Metropolis) or
+ * 1 (heat bath), with counter (block, t, replica, c | purpose<<1 | hit<<8). */
+static int ising_rule_site(const oracle_params *p, const int8_t *s, const void *J,
+                           const uint64_t *Tm, const uint64_t *Th, uint32_t t, int c,
+                           uint32_t hit, int rule, int64_t i) {
+  int d = p->d;
+  uint32_t j = site_index_in_colour(i);
+  int sum = 0;  /* sum_nb sign(J) s_nb */
+  for (int mu = 0; mu < d; ++mu) {
+    int64_t ip = neighbour(p, i, mu, +1), im = neighbour(p, i, mu, -1);
+    sum += coupling_sign(p, J, mu, i) * s[ip];
+    sum += coupling_sign(p, J, mu, im) * s[im];
+  }
+  uint32_t wp[4], wr[4];
+  draw(p->seed, j >> 4, t, p->replica, (uint32_t)c | (PURPOSE_ISING_PREFIX << 1) | (hit << 8), wp);
+  draw(p->seed, j, t, p->replica, (uint32_t)c | (PURPOSE_ISING_REFINE << 1) | (hit << 8), wr);
+  uint32_t prefix = (wp[(j >> 2) & 3] >> (8 * (j & 3))) & 0xffu;
+  uint64_t u32 = ((uint64_t)prefix << 24) | (wr[0] & 0xffffffu);
+  if (rule == 1) return u32 < Th[sum + 2 * d] ? 1 : -1;
+  int m = s[i] * sum;  /* dE = 2 J0 m */
+  return u32 < Tm[m + 2 * d] ? -s[i] : s[i];
+}
+
+/* n_sweeps sweeps of an Ising lattice with integer couplings under `rule`,
+ * plain (tile = 0: colour 0 then colour 1, hit 0) or tiled k-hit (tile T,
+ * hits k >= 1).  The counter of sweep q is t0 + q. */
+ORACLE_API int oracle_sweeps_rule(const oracle_params *p, int8_t *s, const void *J, double beta,
+                                  uint64_t t0, int64_t n_sweeps, int rule, int tile, int hits) {
+  if (!valid(p) || p->n != 1 || p->J_kind == J_FP32 || (rule != 0 && rule != 1)) return -1;
+  if (n_sweeps < 0 || t0 + (uint64_t)n_sweeps > 0x100000000ull) return -1;
+  if (tile < 0 || (tile > 0 && (p->L % tile || ((p->L / tile) & 1) || hits < 1 || hits > (1 << 23))))
+    return -1;
+  int d = p->d;
+  int64_t N = n_sites(p);
+  uint64_t Tm[13], Th[13];
+  for (int m = -2 * d; m <= 2 * d; ++m) {
+    Tm[m + 2 * d] = oracle_threshold(beta, 2.0 * p->J0 * m);
+    Th[m + 2 * d] = oracle_threshold_hb(beta, p->J0 * m);
+  }
+  int8_t *nw = (int8_t *)malloc((size_t)N);
+  if (!nw) return -2;
+  int passes = tile > 0 ? 2 : 1, k = tile > 0 ? hits : 1;
+  for (int64_t q = 0; q < n_sweeps; ++q) {
+    uint32_t t = (uint32_t)(t0 + (uint64_t)q);
+    for (int tc = 0; tc < passes; ++tc)
+      for (int h = 0; h < k; ++h)
+        for (int c = 0; c < 2; ++c) {
+          /* all selected sites at once from the same state (they are independent) */
+#pragma omp parallel for schedule(static) if (N >= 65536)
+          for (int64_t i = 0; i < N; ++i) {
+            int sel = colour_of(p, i) == c && (tile == 0 || tile_colour(p, i, tile) == tc);
+            nw[i] = sel ? (int8_t)ising_rule_site(p, s, J, Tm, Th, t, c, (uint32_t)h, rule, i) : s[i];
+          }
+          memcpy(s, nw, (size_t)N);
+        }
+  }
+  free(nw);
+  return 0;
+}
+
 /* Chains for derivatives of ln Z (Eq. (1)): n_chains independent chains of
  * one small lattice, chain k with replica p->replica + k, its own start state
  * s0[k] and the shared couplings J.  After every sweep the bond products

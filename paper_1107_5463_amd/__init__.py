@@ -31,6 +31,7 @@ J_UNIFORM, J_PM, J_FP32 = 0, 1, 2
 INIT_HOT, INIT_COLD, INIT_KEEP = 0, 1, 2
 FLAG_FAST_MATH, FLAG_SCHEDULE_FUSED, FLAG_GENERIC_KERNEL, FLAG_COUPLINGS_KEEP = 1, 2, 4, 8
 FLAG_PACKED = 16
+FLAG_HEATBATH = 32
 BOND_RESET, BOND_ACCUMULATE, BOND_READ = 0, 1, 2
 SMC_OK, SMC_EINVAL, SMC_ERANGE, SMC_EDEVICE, SMC_ESTATE = 0, -1, -2, -3, -4
 
@@ -62,7 +63,8 @@ class Params(C.Structure):
     _fields_ = [("d", C.c_int32), ("n", C.c_int32), ("L", C.c_int32), ("J_kind", C.c_int32),
                 ("seed", C.c_uint64), ("replica", C.c_uint32), ("init", C.c_int32),
                 ("J0", C.c_double), ("J_sigma", C.c_double), ("delta", C.c_double),
-                ("renorm_every", C.c_int32), ("flags", C.c_int32)]
+                ("renorm_every", C.c_int32), ("flags", C.c_int32), ("tile", C.c_int32),
+                ("hits", C.c_int32)]
 
 
 class _ObsC(C.Structure):
@@ -171,12 +173,12 @@ def _kind(J_kind) -> int:
 
 
 def make_params(d, n, L, seed=0, *, J_kind=J_UNIFORM, J0=1.0, J_sigma=0.0, init="hot",
-                delta=None, renorm_every=100, replica=0, flags=0) -> Params:
+                delta=None, renorm_every=100, replica=0, flags=0, tile=0, hits=0) -> Params:
     if delta is None:
         delta = 1.0 if n > 1 else 0.0
     init_k = {"hot": INIT_HOT, "cold": INIT_COLD, "keep": INIT_KEEP}[init] if isinstance(init, str) else init
     return Params(d, n, L, _kind(J_kind), seed & 0xFFFFFFFFFFFFFFFF, replica, init_k, float(J0),
-                  float(J_sigma), float(delta), renorm_every, flags)
+                  float(J_sigma), float(delta), renorm_every, flags, tile, hits)
 
 
 class Lattice:
@@ -188,17 +190,19 @@ class Lattice:
     def __init__(self, d: int, n: int, L: int, seed: int = 0, *, J_kind=J_UNIFORM, J0: float = 1.0,
                  J_sigma: float = 0.0, init="hot", delta=None, renorm_every: int = 100,
                  replica: int = 0, fast_math: bool = False, fused: bool = False,
-                 generic: bool = False, packed: bool = False, spins=None, J=None, device=None,
-                 stream=None):
+                 generic: bool = False, packed: bool = False, heatbath: bool = False,
+                 tile: int = 0, hits: int = 0, spins=None, J=None, device=None, stream=None):
         """packed: Ising spins (and +-1 couplings) at one bit per site; then
         `spins` is int32 [2, N/64] and J int32 [d, 2, N/64] (bit k & 31 of word
-        k >> 5 = site k of a plane, bit 1 = -1)."""
+        k >> 5 = site k of a plane, bit 1 = -1).  heatbath: the heat-bath rule;
+        tile / hits: the tiled k-hit schedule (tile edge T, k hits per load)."""
         import torch
         lib = load_library()
         self.torch = torch
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         flags = (FLAG_FAST_MATH if fast_math else 0) | (FLAG_SCHEDULE_FUSED if fused else 0) | (
-            FLAG_GENERIC_KERNEL if generic else 0) | (FLAG_PACKED if packed else 0)
+            FLAG_GENERIC_KERNEL if generic else 0) | (FLAG_PACKED if packed else 0) | (
+            FLAG_HEATBATH if heatbath else 0)
         self.packed = packed
         if J is not None:
             flags |= FLAG_COUPLINGS_KEEP
@@ -206,7 +210,7 @@ class Lattice:
             init = "keep"
         self.params = make_params(d, n, L, seed, J_kind=J_kind, J0=J0, J_sigma=J_sigma, init=init,
                                   delta=delta, renorm_every=renorm_every, replica=replica,
-                                  flags=flags)
+                                  flags=flags, tile=tile, hits=hits)
         p = self.params
         self.d, self.n, self.L = d, n, L
         self.N = L ** d

@@ -185,10 +185,13 @@ __device__ __forceinline__ uint32_t word_of(const uint32_t v[4], uint32_t w) {
 // Metropolis update of one chunk with its ties resolved on the spot by the
 // sites' refinement draws (used where the new spins are read again within
 // the same launch).
+// `hit` (k-hit schedules) goes to bits 8.. of the counter's last word.
 __device__ __forceinline__ Chunk update_chunk_now(const TabRegs& tab, const RngKey& key,
                                                   uint32_t t, uint32_t c, uint32_t jbase,
-                                                  const Chunk& o, const uint32_t kk[4]) {
-  const Rand4 rp = philox(jbase >> 4, t, key.replica, tag(c, kIsingPrefix), key.k0, key.k1);
+                                                  const Chunk& o, const uint32_t kk[4],
+                                                  uint32_t hit = 0) {
+  const Rand4 rp = philox(jbase >> 4, t, key.replica, tag(c, kIsingPrefix) | (hit << 8), key.k0,
+                          key.k1);
   uint32_t nw[4], tie[4];
 #pragma unroll
   for (int w = 0; w < 4; ++w) nw[w] = decide4_tie(tab, o.w[w], kk[w], rp.w[w], tie[w]);
@@ -199,7 +202,8 @@ __device__ __forceinline__ Chunk update_chunk_now(const TabRegs& tab, const RngK
       m &= m - 1;
       const uint32_t w = idx >> 2, sh = 8 * (idx & 3u);
       const uint32_t k = (word_of(kk, w) >> sh) & 0xFu;
-      const Rand4 rr = philox(jbase + idx, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
+      const Rand4 rr = philox(jbase + idx, t, key.replica, tag(c, kIsingRefine) | (hit << 8),
+                              key.k0, key.k1);
       if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) {
         const uint32_t f = 0xFEu << sh;
         nw[0] ^= w == 0 ? f : 0u;

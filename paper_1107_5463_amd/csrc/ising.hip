@@ -44,7 +44,8 @@ __global__ __launch_bounds__(256) void ising_site_kernel(const Geom g, const Rng
                                                          const void* __restrict__ J,
                                                          const float beta,
                                                          int8_t* __restrict__ s,
-                                                         const uint32_t t, const uint32_t c) {
+                                                         const uint32_t t, const uint32_t c,
+                                                         const int heatbath) {
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= g.Nh) return;
   const int64_t Nh = g.Nh;
@@ -95,6 +96,19 @@ __global__ __launch_bounds__(256) void ising_site_kernel(const Geom g, const Rng
     const Rand4 r = philox((uint32_t)(j >> 4), t, key.replica, tag(c, kIsingPrefix), key.k0,
                            key.k1);
     const uint32_t P = (pick4(r, ((uint32_t)j >> 2) & 3u) >> (8 * ((uint32_t)j & 3u))) & 0xFFu;
+    if (heatbath) {
+      // class: neighbours with sign(J) s_nb = +1; new spin +1 iff u32 < T_hb
+      const uint32_t npos = si > 0 ? 2u * D - k : k;
+      const uint32_t Th = table_byte(tab.th_lo, tab.th_hi, npos);
+      bool upv = P < Th;
+      if (P == Th) {
+        const Rand4 rr = philox((uint32_t)j, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
+        upv = (rr.w[0] & 0xFFFFFFu) < frac_of(tab, npos);
+      }
+      const int8_t nv = upv ? (int8_t)1 : (int8_t)-1;
+      if (nv != si) own[j] = nv;
+      return;
+    }
     const uint32_t Th = table_byte(tab.th_lo, tab.th_hi, k);
     const bool always = table_byte(tab.al_lo, tab.al_hi, k) != 0;
     accept = always || P < Th;
@@ -289,15 +303,15 @@ static hipError_t launch_site(const IsingLaunch& a, int8_t* spins, uint32_t t, u
   switch (a.J_kind) {
     case 0:
       hipLaunchKernelGGL((ising_site_kernel<D, 0>), grid, dim3(256), 0, st, a.g, a.key, a.tab,
-                         a.J, a.beta, spins, t, c);
+                         a.J, a.beta, spins, t, c, a.heatbath);
       break;
     case 1:
       hipLaunchKernelGGL((ising_site_kernel<D, 1>), grid, dim3(256), 0, st, a.g, a.key, a.tab,
-                         a.J, a.beta, spins, t, c);
+                         a.J, a.beta, spins, t, c, a.heatbath);
       break;
     default:
       hipLaunchKernelGGL((ising_site_kernel<D, 2>), grid, dim3(256), 0, st, a.g, a.key, a.tab,
-                         a.J, a.beta, spins, t, c);
+                         a.J, a.beta, spins, t, c, a.heatbath);
       break;
   }
   return hipGetLastError();
@@ -360,6 +374,7 @@ bool ising_half_sweep_measured(const IsingLaunch& a, int8_t* spins, uint32_t t, 
 }
 
 int ising_variant_used(const IsingLaunch& a) {
+  if (a.heatbath) return kVariantSite;  // the heat-bath rule runs on the site kernel
   int v = a.variant;
   const bool chunk_ok = ising_chunk_supported(a.g, a.J_kind);
   if (v == kVariantAuto) v = !chunk_ok ? kVariantSite : (a.J_kind == 0 ? kVariantStream : kVariantChunk);

@@ -31,6 +31,7 @@ struct IsingLaunch {
   float beta;        // FP32 couplings only
   int variant;       // IsingVariant
   uint32_t rows_per_band;  // streaming kernel: rows walked by one lane (divides L)
+  int heatbath;      // rule: 0 Metropolis, 1 heat bath (table holds p_+ thresholds)
   FastDiv divQ;      // chunks per plane row
   FastDiv divL;      // edge length
 };
@@ -160,5 +161,12 @@ hipError_t launch_unpack(const uint32_t* src, int8_t* dst, int64_t n_words, hipS
 hipError_t launch_init_packed(const Geom& g, RngKey key, int mode, uint32_t* out, hipStream_t st);
 hipError_t launch_measure_packed(const Geom& g, int J_kind, const uint32_t* s, const uint32_t* J,
                                  void* partials, int64_t* nparts, hipStream_t st);
+
+// Tiled k-hit schedule (uniform couplings): one pass over the tiles of one colour.
+size_t tile_lds_bytes(int d, uint32_t T);
+bool tile_supported(const Geom& g, uint32_t T);
+hipError_t tile_allow_lds(int d, size_t bytes);
+hipError_t launch_tile_pass(const IsingLaunch& a, bool heatbath, uint32_t T, uint32_t hits,
+                            int8_t* spins, uint32_t t, uint32_t tc, hipStream_t st);
 
 }  // namespace smc

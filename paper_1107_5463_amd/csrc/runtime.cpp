@@ -68,6 +68,8 @@ constexpr size_t kPartialBytes = 48;  // one reduction partial (measure.hip)
 
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+Geom make_geom(const smc_params* p);
+
 bool params_ok(const smc_params* p, std::string& why) {
   if (!p) { why = "params is NULL"; return false; }
   if (p->d != 2 && p->d != 3) { why = "d must be 2 or 3"; return false; }
@@ -85,9 +87,27 @@ bool params_ok(const smc_params* p, std::string& why) {
     if (p->n == 3 && p->delta > M_PI) { why = "Heisenberg cap half-angle must be <= pi"; return false; }
   }
   if (p->flags & ~(SMC_FLAG_FAST_MATH | SMC_FLAG_SCHEDULE_FUSED | SMC_FLAG_GENERIC_KERNEL |
-                   SMC_FLAG_COUPLINGS_KEEP | SMC_FLAG_PACKED)) {
+                   SMC_FLAG_COUPLINGS_KEEP | SMC_FLAG_PACKED | SMC_FLAG_HEATBATH)) {
     why = "unknown flag bits";
     return false;
+  }
+  if (p->flags & SMC_FLAG_HEATBATH) {
+    if (p->n != 1) { why = "the heat-bath rule is Ising only (n = 1)"; return false; }
+    if (p->J_kind == SMC_J_FP32) { why = "the heat-bath rule takes uniform or +-1 couplings"; return false; }
+    if (p->flags & SMC_FLAG_PACKED) { why = "packed spins run the Metropolis rule"; return false; }
+  }
+  if (p->tile < 0) { why = "tile must be >= 0"; return false; }
+  if (p->tile == 0 && (p->hits < 0 || p->hits > 1)) { why = "hits must be 0 or 1 without tiles"; return false; }
+  if (p->tile > 0) {
+    if (p->n != 1 || p->J_kind != SMC_J_UNIFORM || (p->flags & SMC_FLAG_PACKED)) {
+      why = "the tiled schedule takes int8 Ising spins with uniform couplings";
+      return false;
+    }
+    if (p->hits < 1 || p->hits > (1 << 23)) { why = "hits must be in [1, 2^23]"; return false; }
+    if (!tile_supported(make_geom(p), (uint32_t)p->tile)) {
+      why = "tile must be a multiple of 32 dividing L with L / tile even, and fit LDS";
+      return false;
+    }
   }
   if (p->flags & SMC_FLAG_PACKED) {
     if (p->n != 1) { why = "packed spins are Ising only (n = 1)"; return false; }
@@ -170,9 +190,40 @@ IsingTable make_table(int d, double J0, double beta) {
   return tab;
 }
 
+// Heat-bath thresholds per class npos (neighbours with sign(J) s = +1):
+// T = ceil(2^32 / (1 + exp(-2 beta J0 (2 npos - 2d)))) in long double;
+// T >= 2^32 is stored as threshold byte 0xFF with fraction 2^24 (always +1).
+IsingTable make_table_hb(int d, double J0, double beta) {
+  IsingTable tab;
+  std::memset(&tab, 0, sizeof(tab));
+  uint8_t th[8] = {0};
+  for (int np = 0; np <= 2 * d; ++np) {
+    const long double h = (long double)J0 * (long double)(2 * np - 2 * d);
+    uint64_t T;
+    if (std::isinf(beta)) {
+      T = h > 0 ? 4294967296ull : (h < 0 ? 0ull : 2147483648ull);
+    } else {
+      const long double x = std::ldexp(1.0L / (1.0L + std::exp(-2.0L * (long double)beta * h)), 32);
+      const long double c = std::ceil(x);
+      T = c >= 4294967296.0L ? 4294967296ull : (uint64_t)c;
+    }
+    if (T >= 4294967296ull) {
+      th[np] = 0xFF;
+      tab.frac[np] = 0x1000000u;
+    } else {
+      th[np] = (uint8_t)(T >> 24);
+      tab.frac[np] = (uint32_t)(T & 0xFFFFFFu);
+    }
+  }
+  tab.th_lo = th[0] | (th[1] << 8) | (th[2] << 16) | ((uint32_t)th[3] << 24);
+  tab.th_hi = th[4] | (th[5] << 8) | (th[6] << 16) | ((uint32_t)th[7] << 24);
+  return tab;
+}
+
 void build_table(smc_lattice* h, double beta) {
   if (h->tab_valid && h->tab_beta == beta) return;
-  h->tab = make_table(h->p.d, h->p.J0, beta);
+  h->tab = (h->p.flags & SMC_FLAG_HEATBATH) ? make_table_hb(h->p.d, h->p.J0, beta)
+                                            : make_table(h->p.d, h->p.J0, beta);
   h->tab_beta = beta;
   h->tab_valid = true;
 }
@@ -201,6 +252,7 @@ IsingLaunch ising_args(smc_lattice* h, double beta) {
   a.rows_per_band = h->rows_per_band;
   a.divQ = h->divQ;
   a.divL = h->divL;
+  a.heatbath = (h->p.flags & SMC_FLAG_HEATBATH) ? 1 : 0;
   return a;
 }
 
@@ -317,7 +369,25 @@ int fused_sweeps(smc_lattice* h, double beta, int64_t n, void* dev_obs) {
   return SMC_OK;
 }
 
+// Tiled k-hit sweeps: per sweep one pass over each tile colour.
+int tiled_sweeps(smc_lattice* h, double beta, int64_t n_sweeps, void* dev_obs) {
+  const IsingLaunch a = ising_args(h, beta);
+  const bool hb = (h->p.flags & SMC_FLAG_HEATBATH) != 0;
+  for (int64_t k = 0; k < n_sweeps; ++k) {
+    for (uint32_t tc = 0; tc < 2; ++tc) {
+      const int rc = check(launch_tile_pass(a, hb, (uint32_t)h->p.tile, (uint32_t)h->p.hits,
+                                            (int8_t*)h->spins, (uint32_t)h->t, tc, h->stream),
+                           "tile pass launch");
+      if (rc != SMC_OK) return rc;
+    }
+    h->t += 1;
+  }
+  if (dev_obs) return check(measure_any(h, h->t, dev_obs), "measurement launch");
+  return SMC_OK;
+}
+
 int sweeps_impl(smc_lattice* h, double beta, int64_t n_sweeps, void* dev_obs) {
+  if (h->p.tile > 0) return tiled_sweeps(h, beta, n_sweeps, dev_obs);
   if (h->use_fused) return fused_sweeps(h, beta, n_sweeps, dev_obs);
   for (int64_t k = 0; k < n_sweeps; ++k) {
     const bool last = k + 1 == n_sweeps;
@@ -422,21 +492,25 @@ int smc_init_lattice(smc_lattice** out, const smc_params* p, void* spins, void* 
     const long H = std::strtol(v, nullptr, 10);
     if (H >= 1 && H <= 64 && H <= h->g.L && h->g.L % H == 0) h->packed_rows = (uint32_t)H;
   }
-  h->use_fused = p->n == 1 && !is_packed(p) && (p->flags & SMC_FLAG_SCHEDULE_FUSED) &&
+  h->use_fused = p->n == 1 && !is_packed(p) && p->tile == 0 && !(p->flags & SMC_FLAG_HEATBATH) &&
+                 (p->flags & SMC_FLAG_SCHEDULE_FUSED) &&
                  !(p->flags & SMC_FLAG_GENERIC_KERNEL) &&
                  ising_fused_supported(h->g, p->J_kind, h->fused_rows);
   const RngKey key = key_of(h);
   int rc = SMC_OK;
-  if (is_packed(p)) {
+  if (p->tile > 0)
+    rc = check(tile_allow_lds(p->d, tile_lds_bytes(p->d, (uint32_t)p->tile)), "tile LDS attribute");
+  if (rc == SMC_OK && is_packed(p)) {
     if (p->J_kind == SMC_J_PM && !(p->flags & SMC_FLAG_COUPLINGS_KEEP))
       rc = check(launch_init_packed(h->g, key, 2, (uint32_t*)h->J, h->stream), "coupling init launch");
     if (rc == SMC_OK && p->init != SMC_INIT_KEEP)
       rc = check(launch_init_packed(h->g, key, p->init == SMC_INIT_HOT ? 0 : 1, (uint32_t*)spins,
                                     h->stream),
                  "spin init launch");
-  } else if (p->J_kind != SMC_J_UNIFORM && !(p->flags & SMC_FLAG_COUPLINGS_KEEP))
+  } else if (rc == SMC_OK && p->J_kind != SMC_J_UNIFORM && !(p->flags & SMC_FLAG_COUPLINGS_KEEP)) {
     rc = check(launch_init_couplings(h->g, p->J_kind, key, p->J0, p->J_sigma, h->J, h->stream),
                "coupling init launch");
+  }
   if (rc == SMC_OK && p->init != SMC_INIT_KEEP && !is_packed(p)) {
     const int hot = p->init == SMC_INIT_HOT;
     if (p->n == 1)
@@ -485,6 +559,7 @@ int smc_half_sweep(smc_lattice* h, double beta, int colour) {
   if (!h) return fail(SMC_EINVAL, "handle is NULL");
   if (!beta_ok(beta)) return fail(SMC_EINVAL, "beta must be >= 0 (or +inf), not NaN");
   if (colour != 0 && colour != 1) return fail(SMC_EINVAL, "colour must be 0 or 1");
+  if (h->p.tile > 0) return fail(SMC_ESTATE, "half-sweeps are not defined for the tiled schedule");
   if (h->t > 0xffffffffull) return fail(SMC_ERANGE, "sweep counter exceeds 2^32 - 1");
   return half_sweep_impl(h, beta, (uint32_t)h->t, (uint32_t)colour);
 }
@@ -590,6 +665,10 @@ const char* smc_kernel_name(const smc_lattice* h, uint32_t* rows_per_band) {
   if (is_packed(&h->p)) {
     if (rows_per_band) *rows_per_band = h->packed_rows;
     return "ising_packed";
+  }
+  if (h->p.tile > 0) {
+    if (rows_per_band) *rows_per_band = (uint32_t)h->p.tile;
+    return "ising_tiles";
   }
   if (h->use_fused) {
     if (rows_per_band) *rows_per_band = h->fused_rows;

@@ -102,14 +102,11 @@ def test_null_handle_calls_fail_cleanly(smc_host):
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
-    import importlib
-
     import paper_1107_5463_amd as smc
     monkeypatch.setattr(smc, "_LIB", None)
     monkeypatch.setattr(smc, "_LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         smc.load_library()
-    importlib.reload(smc)
 
 
 def test_obs_record_layout_matches_header(smc_host):
@@ -147,3 +144,36 @@ def test_chain_init_rejects_bad_arguments(smc_host):
     assert b"J must be" in lib.smc_last_error()
     assert lib.smc_chains_sample(None, 0.4, 1, None) == smc_host.SMC_EINVAL
     assert lib.smc_chains_covariance(None, 0.4, 1, None, 0.0, None, None) == smc_host.SMC_EINVAL
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(tile=33, hits=2, L=66), b"tile must be"),
+    (dict(tile=32, hits=2, L=96), b"tile must be"),         # L / T odd
+    (dict(tile=32, hits=0, L=64), b"hits must be"),
+    (dict(tile=0, hits=5, L=64), b"hits must be 0 or 1"),
+    (dict(tile=32, hits=1, L=64, J_kind=1), b"uniform couplings"),
+    (dict(tile=32, hits=1, L=64, d=3, n=3), b"int8 Ising"),
+    (dict(flags=32, n=2, L=64), b"heat-bath rule is Ising only"),
+    (dict(flags=32, J_kind=2, L=64), b"heat-bath rule takes"),
+    (dict(flags=16, L=96), b"L % 64"),
+    (dict(flags=16 | 32, L=64), b"packed spins run the Metropolis"),
+])
+def test_rule_schedule_and_packing_params_rejected(smc_host, kw, msg):
+    lib = smc_host.load_library()
+    base = dict(d=2, n=1, L=64, J_kind=0, flags=0, tile=0, hits=0)
+    base.update(kw)
+    p = smc_host.make_params(base["d"], base["n"], base["L"], 1, J_kind=base["J_kind"],
+                             flags=base["flags"], tile=base["tile"], hits=base["hits"])
+    assert lib.smc_spin_bytes(C.byref(p)) == 0
+    h = C.c_void_p()
+    assert lib.smc_init_lattice(C.byref(h), C.byref(p), None, None, None, 0, None) == smc_host.SMC_EINVAL
+    assert msg in lib.smc_last_error(), lib.smc_last_error()
+
+
+def test_packed_buffer_sizes(smc_host):
+    lib = smc_host.load_library()
+    p = smc_host.make_params(2, 1, 16384, 1, flags=smc_host.FLAG_PACKED)
+    assert lib.smc_spin_bytes(C.byref(p)) == 16384 ** 2 // 8
+    q = smc_host.make_params(3, 1, 128, 1, J_kind=smc_host.J_PM, flags=smc_host.FLAG_PACKED)
+    assert lib.smc_coupling_bytes(C.byref(q)) == 3 * 128 ** 3 // 8
+    assert lib.smc_bond_bytes(C.byref(q)) == 0

@@ -1,0 +1,68 @@
+"""GPU parity of the heat-bath rule and of the tiled k-hit schedule (Sec. 2)
+against the oracle, bit for bit."""
+import numpy as np
+import pytest
+
+import layout
+
+pytestmark = pytest.mark.gpu
+
+BETA_C = 0.4406868
+
+
+def nat(lat):
+    return layout.to_natural(lat.spins.cpu().numpy(), lat.d, lat.L)
+
+
+@pytest.mark.parametrize("d,L,kind,beta,n", [(2, 32, 0, BETA_C, 20), (2, 20, 1, 0.9, 15),
+                                             (3, 8, 1, 0.3, 10), (3, 16, 0, 0.2216546, 6),
+                                             (2, 64, 0, float("inf"), 3)])
+def test_heatbath_plain_sweeps_match_oracle(smc_gpu, oracle_mod, d, L, kind, beta, n):
+    print(f"heat bath d={d} L={L} kind={kind}", flush=True)
+    lat = smc_gpu.Lattice(d, 1, L, seed=L + 3, J_kind=kind, heatbath=True)
+    ref = oracle_mod.OracleLattice(d, 1, L, L + 3, J_kind=kind)
+    lat.sweep(beta, n)
+    ref.sweep_rule(beta, n, "heatbath")
+    assert np.array_equal(nat(lat), ref.s)
+
+
+TILED = [  # d, L, tile, hits, heatbath, beta, sweeps
+    (2, 64, 32, 3, False, BETA_C, 4),
+    (2, 128, 32, 5, False, 0.6, 3),
+    (2, 256, 64, 2, False, BETA_C, 2),
+    (2, 64, 32, 4, True, BETA_C, 4),
+    (3, 64, 32, 2, False, 0.2216546, 2),
+    (3, 64, 32, 1, True, 0.25, 2),
+]
+
+
+@pytest.mark.parametrize("d,L,T,k,hb,beta,n", TILED)
+def test_tiled_schedule_matches_oracle(smc_gpu, oracle_mod, d, L, T, k, hb, beta, n):
+    print(f"tiles d={d} L={L} T={T} k={k} hb={hb}", flush=True)
+    lat = smc_gpu.Lattice(d, 1, L, seed=7, heatbath=hb, tile=T, hits=k)
+    assert lat.kernel() == ("ising_tiles", T)
+    ref = oracle_mod.OracleLattice(d, 1, L, 7)
+    lat.sweep(beta, n)
+    ref.sweep_rule(beta, n, "heatbath" if hb else "metropolis", T, k)
+    assert np.array_equal(nat(lat), ref.s)
+    o, r = lat.measure(), ref.measure()
+    assert (o.E_int, o.M_int) == (r.E_int, r.M_int)
+    assert lat.t == n
+
+
+def test_tiled_sweep_measure(smc_gpu, oracle_mod):
+    import torch
+    lat = smc_gpu.Lattice(2, 1, 64, seed=11, tile=32, hits=3)
+    ref = oracle_mod.OracleLattice(2, 1, 64, 11)
+    slot = torch.zeros(8, dtype=torch.int64, device=lat.device)
+    lat.sweep_measure(0.5, 3, slot)
+    ref.sweep_rule(0.5, 3, "metropolis", 32, 3)
+    o = smc_gpu.Lattice.decode_obs(slot)[0]
+    r = ref.measure()
+    assert (o.E_int, o.M_int, o.sweep) == (r.E_int, r.M_int, 3)
+
+
+def test_tiled_half_sweep_is_refused(smc_gpu):
+    lat = smc_gpu.Lattice(2, 1, 64, seed=1, tile=32, hits=2)
+    with pytest.raises(smc_gpu.SmcError):
+        lat.half_sweep(0.4, 0)
