@@ -20,7 +20,8 @@ struct FastDiv {
 };
 FastDiv make_fastdiv(uint32_t d);
 
-enum IsingVariant { kVariantAuto = 0, kVariantSite = 1, kVariantChunk = 2, kVariantStream = 3 };
+enum IsingVariant { kVariantAuto = 0, kVariantSite = 1, kVariantChunk = 2, kVariantStream = 3,
+                    kVariantFusedLds = 4 };  // fused schedule: workgroup-row kernel with LDS edges
 
 struct IsingLaunch {
   Geom g;

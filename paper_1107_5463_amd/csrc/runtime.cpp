@@ -470,7 +470,8 @@ int smc_init_lattice(smc_lattice** out, const smc_params* p, void* spins, void* 
   if (const char* v = std::getenv("SMC_ISING_KERNEL")) {
     const std::string s(v);
     h->ising_variant = s == "site" ? kVariantSite : s == "chunk" ? kVariantChunk
-                     : s == "stream" ? kVariantStream : kVariantAuto;
+                     : s == "stream" ? kVariantStream : s == "fused_lds" ? kVariantFusedLds
+                     : kVariantAuto;
   }
   h->rows_per_band = stream_rows_per_band(h->g, 4096);
   if (const char* v = std::getenv("SMC_STREAM_ROWS")) {

@@ -283,9 +283,13 @@ def test_kernel_variants_bit_identical(smc_gpu, oracle_mod, d, L, monkeypatch):
     assert {name for name, _ in seen} == {"ising_site", "ising_chunk", "ising_stream"}
 
 
-@pytest.mark.parametrize("L,n,rows", [(2048, 4, None), (2048, 5, "4"), (4096, 3, "8"),
-                                      (2048, 2, "64"), (4096, 1, None)])
-def test_fused_schedule_matches_oracle(smc_gpu, oracle_mod, L, n, rows, monkeypatch):
+@pytest.mark.parametrize("L,n,rows,kernel", [(2048, 4, None, None), (2048, 5, "4", None),
+                                             (4096, 3, "8", None), (2048, 2, "64", None),
+                                             (4096, 1, None, None), (2048, 4, "16", "fused_lds"),
+                                             (4096, 3, None, "fused_lds")])
+def test_fused_schedule_matches_oracle(smc_gpu, oracle_mod, L, n, rows, kernel, monkeypatch):
+    if kernel is not None:
+        monkeypatch.setenv("SMC_ISING_KERNEL", kernel)
     """The one-kernel-per-sweep schedule (ping-pong buffers, LDS edge
     exchange, redundant band-edge rows) gives the oracle's chain bit for bit,
     for odd and even sweep counts and any band height; the energy and
