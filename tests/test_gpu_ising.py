@@ -288,13 +288,14 @@ def test_kernel_variants_bit_identical(smc_gpu, oracle_mod, d, L, monkeypatch):
                                              (4096, 1, None, None), (2048, 4, "16", "fused_lds"),
                                              (4096, 3, None, "fused_lds")])
 def test_fused_schedule_matches_oracle(smc_gpu, oracle_mod, L, n, rows, kernel, monkeypatch):
-    if kernel is not None:
-        monkeypatch.setenv("SMC_ISING_KERNEL", kernel)
-    """The one-kernel-per-sweep schedule (ping-pong buffers, LDS edge
-    exchange, redundant band-edge rows) gives the oracle's chain bit for bit,
+    """The one-kernel-per-sweep schedule (ping-pong buffers, redundant
+    band-edge rows; wave segments with recomputed halo chunks, or whole-row
+    workgroups with LDS edge exchange) gives the oracle's chain bit for bit,
     for odd and even sweep counts and any band height; the energy and
     magnetisation reduced inside the last fused sweep equal the oracle's."""
     import torch
+    if kernel is not None:
+        monkeypatch.setenv("SMC_ISING_KERNEL", kernel)
     if rows is None:
         monkeypatch.delenv("SMC_FUSED_ROWS", raising=False)
     else:
