@@ -70,6 +70,12 @@ def parse():
     ap.add_argument("--schedule", choices=["fused", "two-pass"], default="two-pass",
                     help="2D Ising only -- fused: one kernel per sweep with ping-pong buffers "
                          "(2 B/attempt); two-pass: one in-place kernel per colour (3 B/attempt)")
+    ap.add_argument("--packed", action="store_true",
+                    help="Ising workloads: spins at one bit per site (same chain)")
+    ap.add_argument("--tile", type=int, default=0,
+                    help="Ising workloads: the tiled k-hit schedule with tiles of this edge")
+    ap.add_argument("--hits", type=int, default=100, help="k of the tiled schedule")
+    ap.add_argument("--heatbath", action="store_true", help="Ising workloads: heat-bath rule")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate host time of the oracle baseline (0 = skip)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -124,10 +130,13 @@ def oracle_rate(fn, attempts_per_call, budget_s):
 def run_lattice(args, wl, torch, smc):
     d, n, L = wl["d"], wl["n"], wl["L"]
     N = L ** d
-    fused = args.schedule == "fused" and n == 1
+    fused = args.schedule == "fused" and n == 1 and not (args.packed or args.tile or args.heatbath)
     kw = {}
     if n > 1:
         kw = dict(delta=wl["delta"], renorm_every=wl["renorm"])
+    else:
+        kw = dict(packed=args.packed, heatbath=args.heatbath, tile=args.tile,
+                  hits=args.hits if args.tile else 0)
     lat = smc.Lattice(d, n, L, seed=wl["seed"], fused=fused, **kw)
     if args.copy_probe:
         copy_probe(torch, lat.device)
@@ -152,9 +161,17 @@ def run_lattice(args, wl, torch, smc):
     wall = time.perf_counter() - t0
     total_ms = ev_start.elapsed_time(ev_end)
     sweeps = K * S
-    attempts = N * sweeps
+    hits = args.hits if (n == 1 and args.tile) else 1
+    attempts = N * sweeps * hits
     kname, band_rows = lat.kernel()
-    if kname == "ising_fused":
+    if kname == "ising_tiles":
+        # one launch per tile colour: its half of both planes read and written once
+        launches, bytes_per_launch = 2 * sweeps, 1.0 * N
+        schedule = f"tiled k-hit, T={args.tile}, k={args.hits}"
+    elif kname == "ising_packed":
+        launches, bytes_per_launch = 2 * sweeps, 1.5 * N / 8
+        schedule = "two-pass colour-split, in place, one bit per site"
+    elif kname == "ising_fused":
         launches, bytes_per_launch = sweeps, 2.0 * N
         schedule = "fused one-pass, ping-pong buffers"
     elif n == 1:
@@ -182,11 +199,14 @@ def run_lattice(args, wl, torch, smc):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "i8" if n == 1 else "f32",
+        "dtype": ("u32 bits" if args.packed else "i8") if n == 1 else "f32",
         "data": "synthetic",
         "config": {
             "workload": f"{d}D {what} L={L} (N={N}), J=1, beta={beta}, "
-                        f"{'hot' if n == 1 else 'random'} start seed {wl['seed']}, {sweeps} "
+                        + ("heat bath, " if args.heatbath and n == 1 else "")
+                        + (f"tiles T={args.tile} k={args.hits} ({hits} attempts per site "
+                           "per sweep), " if args.tile and n == 1 else "")
+                        + f"{'hot' if n == 1 else 'random'} start seed {wl['seed']}, {sweeps} "
                         f"checkerboard sweeps, E/M every {S} sweeps"
                         + (f", delta={wl['delta']}, renormalise every {wl['renorm']}" if n > 1 else ""),
             "d": d, "n": n, "L": L, "sweeps": sweeps, "measure_every": S,
@@ -214,7 +234,12 @@ def run_lattice(args, wl, torch, smc):
 
         kwo = {} if n == 1 else dict(delta=wl["delta"], renorm_every=wl["renorm"])
         ref = oracle.OracleLattice(d, n, L, wl["seed"], **kwo)
-        rate, calls, el = oracle_rate(lambda: ref.sweep(beta, 1), N, args.cpu_seconds)
+        if n == 1 and (args.tile or args.heatbath):
+            rule = "heatbath" if args.heatbath else "metropolis"
+            one = lambda: ref.sweep_rule(beta, 1, rule, args.tile, args.hits if args.tile else 1)
+        else:
+            one = lambda: ref.sweep(beta, 1)
+        rate, calls, el = oracle_rate(one, N * hits, args.cpu_seconds)
         gpu = smc.Lattice(d, n, L, seed=wl["seed"], **kw)
         gpu.sweep(beta, calls)
         go, ro = gpu.measure(), ref.measure()
