@@ -135,7 +135,7 @@ def test_autograd_against_exact_enumeration(smc_gpu, x4):
     m = autodiff.bond_correlations(J, b, ch, nsw, n_burn=200)
     S = nch * nsw
     tau = 10.0  # generous integrated autocorrelation time (sweeps)
-    var = np.diag(cov)
+    var = np.diag(cov).reshape(d, 16)
     got = natural(m.detach().cpu().numpy().astype(np.float64), d, L)
     tol = 6 * np.sqrt(var * tau / S) + 1e-6
     assert np.all(np.abs(got - mean) < tol), np.max(np.abs(got - mean) / tol)
