@@ -676,10 +676,12 @@ const char* smc_kernel_name(const smc_lattice* h, uint32_t* rows_per_band) {
     return "ising_fused";
   }
   IsingLaunch a;
+  std::memset(&a, 0, sizeof(a));
   a.g = h->g;
   a.J_kind = h->p.J_kind;
   a.variant = (h->p.flags & SMC_FLAG_GENERIC_KERNEL) ? kVariantSite : h->ising_variant;
   a.rows_per_band = h->rows_per_band;
+  a.heatbath = (h->p.flags & SMC_FLAG_HEATBATH) ? 1 : 0;
   switch (ising_variant_used(a)) {
     case kVariantStream:
       if (rows_per_band) *rows_per_band = h->rows_per_band;
