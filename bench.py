@@ -2,24 +2,29 @@
 """Throughput of the checkerboard Metropolis sweep on one MI355X.
 
 Default workload (the throughput configuration of the method, Sec. 2 /
-Table 1 of the paper): 2D Ising model, L = 16384 (N = 2^28 int8 spins),
-J = 1, hot start from seed 2, beta = 0.4406868, 1000 sweeps with energy and
+Table 1 of the paper): 2D Ising model, L = 16384 (N = 2^28 spins), J = 1, hot
+start from seed 2, beta = 0.4406868, 1000 sweeps with energy and
 magnetisation measured every 10 sweeps.  One step = 10 sweeps + one
 measurement written to a device ring (no host synchronisation inside the
-timed region).  Other workloads (--workload): 3D Ising L = 512, 2D XY
-L = 4096, 3D Heisenberg L = 256 (FP32 spins), the batched +-J spin
-glass (2048 lattices of L in {8,12,16,24,32}, 32 temperatures), and the
-derivatives of ln Z (256 chains of a 2D L = 64 lattice with Gaussian
-couplings: sampling sweeps, then the covariance replay).
+timed region).  Ising spins are stored at one bit per site by default (the
+same chain, bit for bit, as int8 spins); the int8 two-pass schedule, which is
+HBM-bound, is measured beside it in the same run.  Other workloads
+(--workload): 3D Ising L = 512, 2D XY L = 4096, 3D Heisenberg L = 256 (FP32
+spins), the batched +-J spin glass (2048 lattices of L in {8,12,16,24,32},
+32 temperatures), and the derivatives of ln Z (256 chains of a 2D L = 64
+lattice with Gaussian couplings: sampling sweeps, then the covariance replay).
 
 Prints one JSON line:
   value     spin-flip attempts per ns over the whole timed region;
-  roofline  the dominant kernel: algorithmic HBM bytes per launch over its
-            average duration (step time over kernel launches, measured with
-            HIP events on the kernel's stream inside the timed region), against
-            the 8 TB/s HBM peak; `traffic` is the HBM bytes per launch read
+  roofline  the dominant kernel's average launch time (step time over kernel
+            launches, HIP events on the kernel's stream inside the timed
+            region) against its bound: HBM (algorithmic bytes per launch over
+            8 TB/s) or, for the bit-packed and tiled kernels, the VALU (issued
+            32-bit lane operations from the committed rocprofv3 instruction
+            count over 78.6 Tops/s); `traffic` is the HBM bytes per launch read
             from the committed rocprofv3 counter summary when it was taken on
             the current kernel sources, else null;
+  int8_two_pass  the same workload with int8 spins (its HBM roofline);
   cpu_baseline  the FP64 CPU oracle timed on the host on a bounded sample of
             the same workload, whose result is also compared with the GPU's.
 """
@@ -32,8 +37,10 @@ import time
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
-# 64 lanes x 256 CUs x 2.4 GHz: one 32-bit integer VALU op per lane per clock
-VALU_PEAK_TOPS = 64 * 256 * 2.4e9 / 1e12
+# VALU peak in 32-bit lane operations per second: the FP32 vector rate of
+# 157.3 TFLOP/s counts an FMA as two flops, i.e. 78.6e12 lane operations/s
+# (256 CUs x 2.4 GHz x 128 lanes)
+VALU_PEAK_TOPS = 78.6
 
 # Proposal widths giving 50 +- 5 % acceptance at the benchmark temperatures
 # (found with the oracle on small lattices; checked by a CPU test).
@@ -55,6 +62,8 @@ WORKLOADS = {
 KERNEL_SOURCES = {
     "ising_stream": ["ising.hip", "chunk.hpp", "device.hpp", "kernels.hpp", "reduce.hpp"],
     "ising_fused": ["fused.hip", "chunk.hpp", "device.hpp", "kernels.hpp", "reduce.hpp"],
+    "ising_packed": ["packed.hip", "chunk.hpp", "device.hpp", "kernels.hpp", "reduce.hpp"],
+    "ising_tiles": ["tiles.hip", "chunk.hpp", "device.hpp", "kernels.hpp"],
 }
 
 
@@ -70,8 +79,11 @@ def parse():
     ap.add_argument("--schedule", choices=["fused", "two-pass"], default="two-pass",
                     help="2D Ising only -- fused: one kernel per sweep with ping-pong buffers "
                          "(2 B/attempt); two-pass: one in-place kernel per colour (3 B/attempt)")
-    ap.add_argument("--packed", action="store_true",
-                    help="Ising workloads: spins at one bit per site (same chain)")
+    ap.add_argument("--spins", choices=["packed", "int8"], default="packed",
+                    help="Ising plain sweeps: one bit per site (default; the int8 two-pass "
+                         "line is measured beside it) or int8 -- the same chain")
+    ap.add_argument("--no-int8-line", action="store_true",
+                    help="skip the int8 two-pass comparison line of a packed run")
     ap.add_argument("--tile", type=int, default=0,
                     help="Ising workloads: the tiled k-hit schedule with tiles of this edge")
     ap.add_argument("--hits", type=int, default=100, help="k of the tiled schedule")
@@ -127,31 +139,17 @@ def oracle_rate(fn, attempts_per_call, budget_s):
             return calls * attempts_per_call / (el * 1e9), calls, el
 
 
-def run_lattice(args, wl, torch, smc):
-    d, n, L = wl["d"], wl["n"], wl["L"]
-    N = L ** d
-    fused = args.schedule == "fused" and n == 1 and not (args.packed or args.tile or args.heatbath)
-    kw = {}
-    if n > 1:
-        kw = dict(delta=wl["delta"], renorm_every=wl["renorm"])
-    else:
-        kw = dict(packed=args.packed, heatbath=args.heatbath, tile=args.tile,
-                  hits=args.hits if args.tile else 0)
-    lat = smc.Lattice(d, n, L, seed=wl["seed"], fused=fused, **kw)
-    if args.copy_probe:
-        copy_probe(torch, lat.device)
+def timed_steps(lat, beta, K, W, S, torch):
+    """W untimed steps, then K timed steps of S sweeps + one measurement into
+    a device ring; HIP events on the lattice's stream.  Returns (ms, wall s,
+    last observables)."""
     st = lat.stream
-    K = args.steps if args.steps is not None else 100
-    W, S = args.warmup, args.sweeps_per_step
-    beta = wl["beta"]
     ring = torch.zeros((max(K, 1), 8), dtype=torch.int64, device=lat.device)
     for _ in range(W):
         lat.sweep_measure(beta, S, ring[0])
     torch.cuda.synchronize()
-
     ev_start = torch.cuda.Event(enable_timing=True)
     ev_end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     ev_start.record(st)
     for k in range(K):
@@ -159,34 +157,98 @@ def run_lattice(args, wl, torch, smc):
     ev_end.record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    total_ms = ev_start.elapsed_time(ev_end)
+    obs = lat.decode_obs(ring[K - 1:K])[0] if K else None
+    return ev_start.elapsed_time(ev_end), wall, obs
+
+
+def kernel_model(kname, n, N, sweeps, tile, hits):
+    """(launches, algorithmic HBM bytes per launch, schedule) of the dominant kernel."""
+    if kname == "ising_tiles":
+        # one launch per tile colour: its half of both planes read and written once
+        return 2 * sweeps, 1.0 * N, f"tiled k-hit, T={tile}, k={hits}"
+    if kname == "ising_packed":
+        return 2 * sweeps, 1.5 * N / 8, "two-pass colour-split, in place, one bit per site"
+    if kname == "ising_fused":
+        return sweeps, 2.0 * N, "fused one-pass, ping-pong buffers"
+    if n == 1:
+        return 2 * sweeps, 1.5 * N, "two-pass colour-split, in place"
+    # own colour read + written and other colour read, n FP32 components
+    return 2 * sweeps, 1.5 * N * n * 4, "two-pass colour-split, in place, FP32 components"
+
+
+def hbm_roofline(kname, workload, bytes_per_launch, kernel_ms):
+    achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
+    return {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": measured_traffic(kname, workload),
+        "kernel": kname,
+        "kernel_avg_us": round(kernel_ms * 1e3, 3),
+        "algorithmic_bytes_per_launch": int(bytes_per_launch),
+    }
+
+
+def valu_roofline(kname, workload, kernel_ms, bytes_per_launch):
+    """VALU-bound kernels: issued 32-bit lane operations per second from the
+    committed VALU instruction count per launch (rocprofv3 SQ_INSTS_VALU x 64
+    lanes), valid only for the kernel sources it was taken on."""
+    rec = None
+    path = os.path.join(ROOT, "profiles", f"{kname}_{workload}_valu.json")
+    if os.path.exists(path):
+        with open(path) as fh:
+            rec = json.load(fh)
+        if rec.get("sources_sha256_16") != sources_digest(kname):
+            rec = None
+    achieved = None
+    if rec is not None:
+        achieved = rec["valu_lane_ops_per_launch"] / (kernel_ms * 1e-3) / 1e12
+    return {
+        "bound": "alu",
+        "achieved": None if achieved is None else round(achieved, 2),
+        "peak": VALU_PEAK_TOPS,
+        "unit": "Tops/s",
+        "frac": None if achieved is None else round(achieved / VALU_PEAK_TOPS, 4),
+        "traffic": measured_traffic(kname, workload),
+        "kernel": kname,
+        "kernel_avg_us": round(kernel_ms * 1e3, 3),
+        "algorithmic_bytes_per_launch": int(bytes_per_launch),
+        "hbm_frac": round(bytes_per_launch / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+    }
+
+
+def run_lattice(args, wl, torch, smc):
+    d, n, L = wl["d"], wl["n"], wl["L"]
+    N = L ** d
+    special = bool(args.tile or args.heatbath or args.schedule == "fused")
+    packed = n == 1 and args.spins == "packed" and not special
+    fused = args.schedule == "fused" and n == 1 and not (args.tile or args.heatbath)
+    if n > 1:
+        kw = dict(delta=wl["delta"], renorm_every=wl["renorm"])
+    else:
+        kw = dict(packed=packed, heatbath=args.heatbath, tile=args.tile,
+                  hits=args.hits if args.tile else 0)
+    lat = smc.Lattice(d, n, L, seed=wl["seed"], fused=fused, **kw)
+    if args.copy_probe:
+        copy_probe(torch, lat.device)
+    K = args.steps if args.steps is not None else 100
+    W, S = args.warmup, args.sweeps_per_step
+    beta = wl["beta"]
+    total_ms, wall, obs = timed_steps(lat, beta, K, W, S, torch)
     sweeps = K * S
     hits = args.hits if (n == 1 and args.tile) else 1
     attempts = N * sweeps * hits
     kname, band_rows = lat.kernel()
-    if kname == "ising_tiles":
-        # one launch per tile colour: its half of both planes read and written once
-        launches, bytes_per_launch = 2 * sweeps, 1.0 * N
-        schedule = f"tiled k-hit, T={args.tile}, k={args.hits}"
-    elif kname == "ising_packed":
-        launches, bytes_per_launch = 2 * sweeps, 1.5 * N / 8
-        schedule = "two-pass colour-split, in place, one bit per site"
-    elif kname == "ising_fused":
-        launches, bytes_per_launch = sweeps, 2.0 * N
-        schedule = "fused one-pass, ping-pong buffers"
-    elif n == 1:
-        launches, bytes_per_launch = 2 * sweeps, 1.5 * N
-        schedule = "two-pass colour-split, in place"
-    else:
-        # own colour read + written and other colour read, n FP32 components
-        launches, bytes_per_launch = 2 * sweeps, 1.5 * N * n * 4
-        schedule = "two-pass colour-split, in place, FP32 components"
+    launches, bytes_per_launch, schedule = kernel_model(kname, n, N, sweeps, args.tile, args.hits)
     # the step time also holds the measurement finish (and renormalisation)
     # kernels: a conservative average of the dominant kernel
     kernel_ms = total_ms / launches
-    achieved = bytes_per_launch / (kernel_ms * 1e-3) / 1e9
-    traffic = measured_traffic(kname, args.workload)
-    obs = smc.Lattice.decode_obs(ring[K - 1:K])[0] if K else None
+    if kname in ("ising_packed", "ising_tiles"):
+        roof = valu_roofline(kname, args.workload, kernel_ms, bytes_per_launch)
+    else:
+        roof = hbm_roofline(kname, args.workload, bytes_per_launch, kernel_ms)
     what = {1: "Ising", 2: "XY", 3: "Heisenberg"}[n]
     result = {
         "metric": "spin-flip attempts/ns + %HBM peak, 2D Ising L=16384; batched vs plain",
@@ -199,10 +261,11 @@ def run_lattice(args, wl, torch, smc):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("u32 bits" if args.packed else "i8") if n == 1 else "f32",
+        "dtype": ("u1" if packed else "i8") if n == 1 else "f32",
         "data": "synthetic",
         "config": {
             "workload": f"{d}D {what} L={L} (N={N}), J=1, beta={beta}, "
+                        + ("spins at one bit per site, " if packed else "")
                         + ("heat bath, " if args.heatbath and n == 1 else "")
                         + (f"tiles T={args.tile} k={args.hits} ({hits} attempts per site "
                            "per sweep), " if args.tile and n == 1 else "")
@@ -212,21 +275,27 @@ def run_lattice(args, wl, torch, smc):
             "d": d, "n": n, "L": L, "sweeps": sweeps, "measure_every": S,
             "schedule": schedule, "kernel": kname, "rows_per_band": band_rows,
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "kernel": kname,
-            "kernel_avg_us": round(kernel_ms * 1e3, 3),
-            "algorithmic_bytes_per_launch": int(bytes_per_launch),
-        },
-        "pct_hbm_peak": round(100 * achieved / HBM_PEAK_GBS, 2),
+        "roofline": roof,
+        "pct_hbm_peak": round(100 * bytes_per_launch / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
         "wall_s": round(wall, 3),
         "final_obs": None if obs is None else {"E": obs.E, "M": list(obs.M[:n]), "sweep": obs.sweep},
     }
+    if packed and not args.no_int8_line:
+        # the same chain with int8 spins: the HBM-bound two-pass schedule
+        lat8 = smc.Lattice(d, n, L, seed=wl["seed"])
+        ms8, _, obs8 = timed_steps(lat8, beta, K, W, S, torch)
+        k8, rows8 = lat8.kernel()
+        l8, b8, sch8 = kernel_model(k8, n, N, sweeps, 0, 1)
+        result["int8_two_pass"] = {
+            "value": round(attempts / (ms8 * 1e6), 2),
+            "unit": "attempts/ns",
+            "ms_per_step": round(ms8 / max(K, 1), 4),
+            "schedule": sch8, "rows_per_band": rows8,
+            "roofline": hbm_roofline(k8, args.workload, b8, ms8 / l8),
+            "same_final_state": bool(obs8 is not None and obs is not None and obs8.E_int == obs.E_int
+                                     and obs8.M_int == obs.M_int),
+        }
+        del lat8
 
     if args.cpu_seconds > 0:
         sys.path.insert(0, ROOT)
@@ -257,7 +326,7 @@ def run_lattice(args, wl, torch, smc):
             "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": f"first {calls} sweeps of the same {d}D L={L} lattice from the same start "
-                      f"({N * calls} attempts, {el:.1f} s)",
+                      f"({N * calls * hits} attempts, {el:.1f} s)",
             pname: parity,
         }
     return result

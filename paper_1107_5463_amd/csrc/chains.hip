@@ -24,6 +24,34 @@
 
 namespace smc {
 
+// In-plane indices of the 2d neighbours (+x, -x, +y, -y, +z, -z) of site
+// (c, j) of the other colour's plane, in 32-bit arithmetic.
+template <int D>
+__device__ __forceinline__ void neighbours32(uint32_t j, uint32_t c, const FastDiv& dR,
+                                             const FastDiv& dL, uint32_t nb[6]) {
+  const uint32_t R = dR.d, L = dL.d;
+  const uint32_t r = fdiv(j, dR);
+  const uint32_t jx = j - r * R;
+  uint32_t y = r, z = 0;
+  if (D == 3) {
+    z = fdiv(r, dL);
+    y = r - z * L;
+  }
+  const uint32_t p = (c + y + z) & 1u;
+  const uint32_t rowb = r * R;
+  nb[0] = rowb + (jx + p == R ? 0u : jx + p);           // x + 1
+  nb[1] = rowb + (jx + p == 0 ? R - 1 : jx + p - 1);    // x - 1
+  const uint32_t yp = y + 1 == L ? 0u : y + 1, ym = y == 0 ? L - 1 : y - 1;
+  nb[2] = (z * L + yp) * R + jx;
+  nb[3] = (z * L + ym) * R + jx;
+  nb[4] = nb[5] = 0;
+  if (D == 3) {
+    const uint32_t zp = z + 1 == L ? 0u : z + 1, zm = z == 0 ? L - 1 : z - 1;
+    nb[4] = (zp * L + y) * R + jx;
+    nb[5] = (zm * L + y) * R + jx;
+  }
+}
+
 template <int D, int MODE>  // MODE 0: sample, 1: covariance, 2: sweeps only
 __global__ __launch_bounds__(256) void chains_kernel(const ChainsLaunch a, int8_t* __restrict__ spins,
                                                      const uint32_t t0, const uint32_t n_sweeps,
@@ -34,7 +62,8 @@ __global__ __launch_bounds__(256) void chains_kernel(const ChainsLaunch a, int8_
   extern __shared__ __align__(16) unsigned char smem[];
   const Geom g = a.g;
   const int64_t Nh = g.Nh;
-  const uint32_t N = 2u * (uint32_t)Nh;
+  const uint32_t NhU = (uint32_t)Nh;
+  const uint32_t N = 2u * NhU;
   const uint32_t nb = (uint32_t)D * N;  // bonds
   const uint32_t chain = blockIdx.x;
   const uint32_t replica = a.key.replica + chain;
@@ -68,23 +97,17 @@ __global__ __launch_bounds__(256) void chains_kernel(const ChainsLaunch a, int8_
         const Rand4 r = philox(gi, t, replica, tag(c, kContinuous), a.key.k0, a.key.k1);
 #pragma unroll
         for (uint32_t b = 0; b < 4; ++b) {
-          const int64_t j = 4 * (int64_t)gi + b;
-          int32_t x, y, z;
-          site_coords(g, c, j, x, y, z);
+          const uint32_t j = 4 * gi + b;
+          uint32_t nb[6];
+          neighbours32<D>(j, c, a.divR, a.divL, nb);
           const int si = own[j];
           float h = 0.0f;
 #pragma unroll
           for (int mu = 0; mu < D; ++mu) {
-            int32_t xp = x, yp = y, zp = z, xm = x, ym = y, zm = z;
-            if (mu == 0) { xp = wrap(x + 1, g.L); xm = wrap(x - 1, g.L); }
-            if (mu == 1) { yp = wrap(y + 1, g.L); ym = wrap(y - 1, g.L); }
-            if (mu == 2) { zp = wrap(z + 1, g.L); zm = wrap(z - 1, g.L); }
-            const int64_t ip = plane_index(g, xp, yp, zp);
-            const int64_t im = plane_index(g, xm, ym, zm);
-            const float jp = J[((int64_t)mu * 2 + c) * Nh + j];
-            const float jm = J[((int64_t)mu * 2 + (1 - c)) * Nh + im];
-            h += jp * (float)oth[ip];
-            h += jm * (float)oth[im];
+            const float jp = J[(2 * mu + c) * NhU + j];
+            const float jm = J[(2 * mu + 1 - c) * NhU + nb[2 * mu + 1]];
+            h += jp * (float)oth[nb[2 * mu]];
+            h += jm * (float)oth[nb[2 * mu + 1]];
           }
           const float dE = 2.0f * (float)si * h;
           const bool accept = dE <= 0.0f || u01f(r.w[b]) < expf(-beta * dE);
@@ -102,22 +125,17 @@ __global__ __launch_bounds__(256) void chains_kernel(const ChainsLaunch a, int8_
       for (uint32_t gi = threadIdx.x; gi < groups; gi += blockDim.x) {
 #pragma unroll
         for (uint32_t b = 0; b < 4; ++b) {
-          const int64_t j = 4 * (int64_t)gi + b;
-          int32_t x, y, z;
-          site_coords(g, 0u, j, x, y, z);
+          const uint32_t j = 4 * gi + b;
+          uint32_t nb[6];
+          neighbours32<D>(j, 0u, a.divR, a.divL, nb);
           const int s0 = lat[j];
 #pragma unroll
           for (int mu = 0; mu < D; ++mu) {
-            int32_t xp = x, yp = y, zp = z, xm = x, ym = y, zm = z;
-            if (mu == 0) { xp = wrap(x + 1, g.L); xm = wrap(x - 1, g.L); }
-            if (mu == 1) { yp = wrap(y + 1, g.L); ym = wrap(y - 1, g.L); }
-            if (mu == 2) { zp = wrap(z + 1, g.L); zm = wrap(z - 1, g.L); }
-            const int64_t ip = plane_index(g, xp, yp, zp);
-            const int64_t im = plane_index(g, xm, ym, zm);
-            const int xpv = s0 * lat[Nh + ip];  // bond (mu, colour 0, j)
-            const int xmv = s0 * lat[Nh + im];  // bond (mu, colour 1, im)
-            const int64_t bp = ((int64_t)mu * 2) * Nh + j;
-            const int64_t bm = ((int64_t)mu * 2 + 1) * Nh + im;
+            const uint32_t ip = nb[2 * mu], im = nb[2 * mu + 1];
+            const int xpv = s0 * lat[NhU + ip];  // bond (mu, colour 0, j)
+            const int xmv = s0 * lat[NhU + im];  // bond (mu, colour 1, im)
+            const uint32_t bp = (2 * mu) * NhU + j;
+            const uint32_t bm = (2 * mu + 1) * NhU + im;
             if (MODE == 0) {
               acc_i[bp] += xpv;
               acc_i[bm] += xmv;

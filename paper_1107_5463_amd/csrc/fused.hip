@@ -292,7 +292,7 @@ hipError_t launch_ising_sweep_fused(const IsingLaunch& a, const int8_t* src, int
                                     uint32_t t, void* partials, int64_t* nparts, hipStream_t st) {
   const uint32_t H = a.rows_per_band;
   const uint32_t Q = (uint32_t)(a.g.R / 16);
-  if (a.variant != kVariantFusedLds) {
+  if (a.variant == kVariantFusedWave) {
     const uint32_t S = (Q + 61) / 62;  // wave segments per band
     const uint32_t nbands = (uint32_t)a.g.L / H;
     const uint32_t waves = nbands * S;

@@ -375,7 +375,7 @@ bool ising_half_sweep_measured(const IsingLaunch& a, int8_t* spins, uint32_t t, 
 
 int ising_variant_used(const IsingLaunch& a) {
   if (a.heatbath) return kVariantSite;  // the heat-bath rule runs on the site kernel
-  int v = a.variant == kVariantFusedLds ? kVariantAuto : a.variant;
+  int v = a.variant == kVariantFusedWave ? kVariantAuto : a.variant;
   const bool chunk_ok = ising_chunk_supported(a.g, a.J_kind);
   if (v == kVariantAuto) v = !chunk_ok ? kVariantSite : (a.J_kind == 0 ? kVariantStream : kVariantChunk);
   if (v == kVariantStream && !(chunk_ok && a.J_kind == 0 && a.rows_per_band >= 4 &&

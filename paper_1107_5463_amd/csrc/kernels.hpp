@@ -21,7 +21,7 @@ struct FastDiv {
 FastDiv make_fastdiv(uint32_t d);
 
 enum IsingVariant { kVariantAuto = 0, kVariantSite = 1, kVariantChunk = 2, kVariantStream = 3,
-                    kVariantFusedLds = 4 };  // fused schedule: workgroup-row kernel with LDS edges
+                    kVariantFusedWave = 4 };  // fused schedule: wave-segment kernel (no barriers)
 
 struct IsingLaunch {
   Geom g;
@@ -141,6 +141,7 @@ struct ChainsLaunch {
   const float* J;    // [d][2][Nh]
   float beta;
   uint32_t n_chains;
+  FastDiv divR, divL;  // plane row length L/2, edge L
 };
 size_t chains_lds_bytes(const Geom& g, int mode);
 hipError_t chains_allow_lds(int d, size_t bytes);

@@ -470,7 +470,7 @@ int smc_init_lattice(smc_lattice** out, const smc_params* p, void* spins, void* 
   if (const char* v = std::getenv("SMC_ISING_KERNEL")) {
     const std::string s(v);
     h->ising_variant = s == "site" ? kVariantSite : s == "chunk" ? kVariantChunk
-                     : s == "stream" ? kVariantStream : s == "fused_lds" ? kVariantFusedLds
+                     : s == "stream" ? kVariantStream : s == "fused_wave" ? kVariantFusedWave
                      : kVariantAuto;
   }
   h->rows_per_band = stream_rows_per_band(h->g, 4096);
@@ -1148,6 +1148,8 @@ ChainsLaunch chains_args(const smc_chains* h, double beta) {
   a.J = h->J;
   a.beta = (float)beta;
   a.n_chains = (uint32_t)h->n_chains;
+  a.divR = make_fastdiv((uint32_t)h->g.R);
+  a.divL = make_fastdiv((uint32_t)h->g.L);
   return a;
 }
 
