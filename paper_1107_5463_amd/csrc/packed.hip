@@ -92,21 +92,20 @@ __device__ __forceinline__ void prefix_planes(const uint32_t P[8], uint32_t B[8]
 }
 
 // Bit-sliced unsigned compare of the 32 prefix bytes with the threshold byte
-// th (wave-uniform): ge = P >= th, eq = P == th.
+// th (wave-uniform), most significant bit first: eq tracks "equal so far",
+// and a bit where the threshold has 1 and the prefix 0 decides "below".
+// Branch-free, with the threshold bits as scalar all-ones/zero masks.
 __device__ __forceinline__ void planes_compare(const uint32_t B[8], uint32_t th, uint32_t& ge,
                                                uint32_t& eq) {
-  uint32_t lt = 0;
+  uint32_t lt[8];
   eq = ~0u;
 #pragma unroll
   for (int b = 7; b >= 0; --b) {
-    if ((th >> b) & 1u) {
-      lt |= eq & ~B[b];
-      eq &= B[b];
-    } else {
-      eq &= ~B[b];
-    }
+    const uint32_t tb = __builtin_amdgcn_readfirstlane(0u - ((th >> b) & 1u));
+    lt[b] = eq & ~B[b] & tb;   // first difference here, prefix bit 0 < threshold bit 1
+    eq = eq & ~(B[b] ^ tb);    // still equal
   }
-  ge = ~lt;
+  ge = ~((lt[0] | lt[1] | lt[2]) | (lt[3] | lt[4] | lt[5]) | (lt[6] | lt[7]));
 }
 
 // Per-lane tie queue entries: site (5 bits), row in band (6), class (3),
