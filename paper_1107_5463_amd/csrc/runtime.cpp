@@ -488,7 +488,7 @@ int smc_init_lattice(smc_lattice** out, const smc_params* p, void* spins, void* 
     const long H = std::strtol(v, nullptr, 10);
     if (H >= 1 && H <= 64 && H <= h->g.L && h->g.L % H == 0) h->fused_rows = (uint32_t)H;
   }
-  h->packed_rows = packed_rows_per_band(h->g, 4096);
+  h->packed_rows = packed_rows_per_band(h->g, 8192);
   if (const char* v = std::getenv("SMC_PACKED_ROWS")) {
     const long H = std::strtol(v, nullptr, 10);
     if (H >= 1 && H <= 64 && H <= h->g.L && h->g.L % H == 0) h->packed_rows = (uint32_t)H;
