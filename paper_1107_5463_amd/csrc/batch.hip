@@ -50,11 +50,59 @@ __global__ __launch_bounds__(512) void batch_kernel(const BatchDesc* __restrict_
   const int8_t* gJ = J + joff;
   const uint32_t N = 2 * Nh;  // L^d, a multiple of 4 (L even)
 
-  // stage both planes into LDS
-  for (uint32_t w = threadIdx.x; w < N / 4; w += blockDim.x)
-    reinterpret_cast<uint32_t*>(lat)[w] = reinterpret_cast<const uint32_t*>(gs)[w];
+  // Stage both planes into LDS as one byte per site: bit 0 = spin -1, bit
+  // 1 + m = coupling of bond m negative (m = +x, -x, +y, -y, +z, -z), so the
+  // sweep reads couplings from LDS together with the spins.
+  auto nbr = [&](uint32_t c, uint32_t j, uint32_t nbi[6]) {  // in-plane neighbour indices
+    const uint32_t r = fdiv(j, divR);
+    const uint32_t jx = j - r * R;
+    const uint32_t z = D == 3 ? fdiv(r, divL) : 0u;
+    const uint32_t y = r - z * L;
+    const uint32_t p = (c + y + z) & 1u;
+    const uint32_t rowb = r * R;
+    nbi[0] = rowb + (jx + p == R ? 0u : jx + p);
+    nbi[1] = rowb + (jx + p == 0 ? R - 1 : jx + p - 1);
+    const uint32_t ym = y == 0 ? L - 1 : y - 1, yp = y + 1 == L ? 0 : y + 1;
+    nbi[2] = (z * L + yp) * R + jx;
+    nbi[3] = (z * L + ym) * R + jx;
+    nbi[4] = nbi[5] = 0;
+    if (D == 3) {
+      const uint32_t zm = z == 0 ? L - 1 : z - 1, zp = z + 1 == L ? 0 : z + 1;
+      nbi[4] = (zp * L + y) * R + jx;
+      nbi[5] = (zm * L + y) * R + jx;
+    }
+  };
+  for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) {
+    const uint32_t c = i >= Nh ? 1u : 0u;
+    const uint32_t j = i - c * Nh;
+    uint32_t v = gs[i] < 0 ? 1u : 0u;
+    if (PM) {
+      uint32_t nbi[6];
+      nbr(c, j, nbi);
+      const int8_t* Jo = gJ + (uint64_t)c * Nh;        // J[mu][c] = gJ + (2 mu + c) Nh
+      const int8_t* Jn = gJ + (uint64_t)(1 - c) * Nh;  // J[mu][1 - c]
+#pragma unroll
+      for (int mu = 0; mu < D; ++mu) {
+        v |= (Jo[2 * (uint64_t)mu * Nh + j] < 0 ? 1u : 0u) << (1 + 2 * mu);
+        v |= (Jn[2 * (uint64_t)mu * Nh + nbi[2 * mu + 1]] < 0 ? 1u : 0u) << (2 + 2 * mu);
+      }
+    }
+    lat[i] = (int8_t)v;
+  }
   __syncthreads();
 
+  // One site: k = bonds with J s_i s_nb < 0 from the combined bytes.
+  auto site_k = [&](const int8_t* own, const int8_t* oth, uint32_t c, uint32_t j,
+                    uint32_t& o) -> uint32_t {
+    uint32_t nbi[6];
+    nbr(c, j, nbi);
+    o = (uint8_t)own[j];
+    uint32_t nm = 0;
+#pragma unroll
+    for (int m = 0; m < 2 * D; ++m) nm |= ((uint32_t)(uint8_t)oth[nbi[m]] & 1u) << m;
+    const uint32_t om = (0u - (o & 1u)) & ((1u << (2 * D)) - 1u);
+    return __builtin_popcount(nm ^ om ^ (PM ? (o >> 1) : 0u));
+  };
   const uint32_t ngroups = (Nh + 15) / 16;
   for (uint32_t sw = 0; sw < n_sweeps; ++sw) {
     const uint32_t t = t0 + sw;
@@ -64,63 +112,28 @@ __global__ __launch_bounds__(512) void batch_kernel(const BatchDesc* __restrict_
       for (uint32_t g = threadIdx.x; g < ngroups; g += blockDim.x) {
         const uint32_t j0 = 16 * g;
         const Rand4 rp = philox(g, t, replica, tag(c, kIsingPrefix), key.k0, key.k1);
-        // coordinates of j0, then stepped along the group
-        uint32_t r = fdiv(j0, divR);
-        uint32_t jx = j0 - r * R;
-        uint32_t z = D == 3 ? fdiv(r, divL) : 0u;
-        uint32_t y = r - z * L;
-        for (uint32_t jj = 0; jj < 16; ++jj) {
+        const uint32_t nj = Nh - j0 < 16 ? Nh - j0 : 16u;
+        auto one = [&](uint32_t jj, uint32_t word) {
           const uint32_t j = j0 + jj;
-          if (j >= Nh) break;
-          const uint32_t p = (c + y + z) & 1u;
-          const uint32_t jxp = jx + p == R ? 0u : jx + p;          // x + 1
-          const uint32_t jxm = jx + p == 0 ? R - 1 : jx + p - 1;   // x - 1
-          const uint32_t rowb = r * R;
-          const uint32_t ym = y == 0 ? L - 1 : y - 1, yp = y + 1 == L ? 0 : y + 1;
-          const uint32_t iym = ((z * L) + ym) * R + jx, iyp = ((z * L) + yp) * R + jx;
-          uint32_t izm = 0, izp = 0;
-          if (D == 3) {
-            const uint32_t zm = z == 0 ? L - 1 : z - 1, zp = z + 1 == L ? 0 : z + 1;
-            izm = (zm * L + y) * R + jx;
-            izp = (zp * L + y) * R + jx;
-          }
-          const int si = own[j];
-          const int nb[6] = {oth[rowb + jxp], oth[rowb + jxm], oth[iyp], oth[iym],
-                             D == 3 ? oth[izp] : 0, D == 3 ? oth[izm] : 0};
-          int sgn[6] = {1, 1, 1, 1, 1, 1};
-          if (PM) {
-            const int8_t* Jo = gJ + (uint64_t)c * Nh;          // J[mu][c]: + 2 mu Nh
-            const int8_t* Jn = gJ + (uint64_t)(1 - c) * Nh;    // J[mu][1-c]
-            sgn[0] = Jo[j];
-            sgn[1] = Jn[rowb + jxm];
-            sgn[2] = Jo[2 * (uint64_t)Nh + j];
-            sgn[3] = Jn[2 * (uint64_t)Nh + iym];
-            if (D == 3) {
-              sgn[4] = Jo[4 * (uint64_t)Nh + j];
-              sgn[5] = Jn[4 * (uint64_t)Nh + izm];
-            }
-          }
-          uint32_t k = 0;
-#pragma unroll
-          for (int b = 0; b < 2 * D; ++b) k += (sgn[b] * si * nb[b]) < 0;
-          const uint32_t wlo = (jj & 4) ? rp.w[1] : rp.w[0];
-          const uint32_t whi = (jj & 4) ? rp.w[3] : rp.w[2];
-          const uint32_t P = (((jj & 8) ? whi : wlo) >> (8 * (jj & 3))) & 0xFFu;
+          uint32_t o;
+          const uint32_t k = site_k(own, oth, c, j, o);
+          const uint32_t P = (word >> (8 * (jj & 3))) & 0xFFu;
           const uint32_t Th = table_byte(th_lo, th_hi, k);
           bool accept = P < Th;
           if (P == Th) {
             const Rand4 rr = philox(j, t, replica, tag(c, kIsingRefine), key.k0, key.k1);
             accept = (rr.w[0] & 0xFFFFFFu) < dp->frac[k];  // rare: read from the table
           }
-          if (accept) own[j] = (int8_t)(-si);
-          // step to the next site of the group
-          if (++jx == R) {
-            jx = 0;
-            ++r;
-            if (++y == L) {
-              y = 0;
-              ++z;
-            }
+          if (accept) own[j] = (int8_t)(o ^ 1u);
+        };
+        if (nj == 16) {
+#pragma unroll
+          for (uint32_t jj = 0; jj < 16; ++jj) one(jj, rp.w[jj >> 2]);
+        } else {
+          for (uint32_t jj = 0; jj < nj; ++jj) {
+            const uint32_t wlo = (jj & 4) ? rp.w[1] : rp.w[0];
+            const uint32_t whi = (jj & 4) ? rp.w[3] : rp.w[2];
+            one(jj, (jj & 8) ? whi : wlo);
           }
         }
       }
@@ -128,53 +141,18 @@ __global__ __launch_bounds__(512) void batch_kernel(const BatchDesc* __restrict_
     }
   }
 
-  // write both planes back
-  for (uint32_t w = threadIdx.x; w < N / 4; w += blockDim.x)
-    reinterpret_cast<uint32_t*>(gs)[w] = reinterpret_cast<const uint32_t*>(lat)[w];
+  // write both planes back as +-1 bytes
+  for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) gs[i] = (lat[i] & 1) ? (int8_t)-1 : (int8_t)1;
 
   if (MEASURE) {
-    // E = -sum over colour-1 sites of s_i h_i (each bond once), M = sum s
+    // E = sum over colour-1 sites of (unsatisfied - satisfied) bonds (each
+    // bond once), M = sum of the spins of both colours
     int64_t Esum = 0, Msum = 0;
-    const int8_t* s1 = lat + Nh;
-    const int8_t* s0 = lat;
     for (uint32_t j = threadIdx.x; j < Nh; j += blockDim.x) {
-      const uint32_t r = fdiv(j, divR);
-      const uint32_t jx = j - r * R;
-      const uint32_t z = D == 3 ? fdiv(r, divL) : 0u;
-      const uint32_t y = r - z * L;
-      const uint32_t p = (1 + y + z) & 1u;
-      const uint32_t jxp = jx + p == R ? 0u : jx + p;
-      const uint32_t jxm = jx + p == 0 ? R - 1 : jx + p - 1;
-      const uint32_t rowb = r * R;
-      const uint32_t ym = y == 0 ? L - 1 : y - 1, yp = y + 1 == L ? 0 : y + 1;
-      const uint32_t iym = ((z * L) + ym) * R + jx, iyp = ((z * L) + yp) * R + jx;
-      uint32_t izm = 0, izp = 0;
-      if (D == 3) {
-        const uint32_t zm = z == 0 ? L - 1 : z - 1, zp = z + 1 == L ? 0 : z + 1;
-        izm = (zm * L + y) * R + jx;
-        izp = (zp * L + y) * R + jx;
-      }
-      const int si = s1[j];
-      const int nb[6] = {s0[rowb + jxp], s0[rowb + jxm], s0[iyp], s0[iym],
-                         D == 3 ? s0[izp] : 0, D == 3 ? s0[izm] : 0};
-      int sgn[6] = {1, 1, 1, 1, 1, 1};
-      if (PM) {
-        const int8_t* Jo = gJ + Nh;  // J[mu][1]
-        const int8_t* Jn = gJ;       // J[mu][0]
-        sgn[0] = Jo[j];
-        sgn[1] = Jn[rowb + jxm];
-        sgn[2] = Jo[2 * (uint64_t)Nh + j];
-        sgn[3] = Jn[2 * (uint64_t)Nh + iym];
-        if (D == 3) {
-          sgn[4] = Jo[4 * (uint64_t)Nh + j];
-          sgn[5] = Jn[4 * (uint64_t)Nh + izm];
-        }
-      }
-      int e = 0;
-#pragma unroll
-      for (int b = 0; b < 2 * D; ++b) e -= sgn[b] * si * nb[b];
-      Esum += e;
-      Msum += si + s0[j];
+      uint32_t o;
+      const uint32_t k = site_k(lat + Nh, lat, 1u, j, o);
+      Esum += 2 * (int64_t)k - 2 * D;
+      Msum += (1 - 2 * (int32_t)(o & 1u)) + (1 - 2 * (int32_t)(lat[j] & 1));
     }
     __shared__ Partial part[1];
     block_partial_int(Esum, Msum, part, 0);
