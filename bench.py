@@ -64,6 +64,8 @@ KERNEL_SOURCES = {
     "ising_fused": ["fused.hip", "chunk.hpp", "device.hpp", "kernels.hpp", "reduce.hpp"],
     "ising_packed": ["packed.hip", "chunk.hpp", "device.hpp", "kernels.hpp", "reduce.hpp"],
     "ising_tiles": ["tiles.hip", "chunk.hpp", "device.hpp", "kernels.hpp"],
+    "xy_stream": ["continuous.hip", "chunk.hpp", "device.hpp", "kernels.hpp"],
+    "heisenberg_stream": ["continuous.hip", "chunk.hpp", "device.hpp", "kernels.hpp"],
 }
 
 

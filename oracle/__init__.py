@@ -172,6 +172,16 @@ class OracleLattice:
             assert rc == 0
 
     @property
+    def s(self):
+        return self._s
+
+    @s.setter
+    def s(self, value):
+        # the C routines take the array's buffer: keep it C-contiguous, in
+        # the dtype they read
+        self._s = np.ascontiguousarray(value, dtype=np.int8 if self.n == 1 else np.float64)
+
+    @property
     def _Jp(self):
         return None if self.J is None else self.J.ctypes.data
 

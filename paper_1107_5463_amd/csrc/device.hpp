@@ -81,10 +81,12 @@ struct Geom {
 // Coordinates of site (c, j): returns x, y, z.
 __device__ __forceinline__ void site_coords(const Geom& g, uint32_t c, int64_t j, int32_t& x,
                                             int32_t& y, int32_t& z) {
-  const int64_t r = j / g.R;
-  const int32_t jx = (int32_t)(j - r * g.R);
-  y = (int32_t)(r % g.L);
-  z = (int32_t)(r / g.L);
+  // plane indices are below N/2 < 2^31: 32-bit divisions
+  const uint32_t ju = (uint32_t)j, R = (uint32_t)g.R, L = (uint32_t)g.L;
+  const uint32_t r = ju / R;
+  const int32_t jx = (int32_t)(ju - r * R);
+  z = (int32_t)(r / L);
+  y = (int32_t)(r - (uint32_t)z * L);
   const int32_t p = (int32_t)((c + (uint32_t)y + (uint32_t)z) & 1u);
   x = 2 * jx + p;
 }

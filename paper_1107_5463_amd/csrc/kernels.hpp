@@ -64,7 +64,23 @@ struct ContLaunch {
   float delta;       // XY max angle
   float one_minus_cos_cap;  // Heisenberg 1 - cos(theta_max)
   int fast_math;
+  int variant;              // ContVariant
+  uint32_t rows_per_band;   // streaming kernel band height
+  FastDiv divQ;             // lanes per plane row (R / sites per lane)
+  FastDiv divL;             // edge length
+  double J0d;               // uniform coupling in FP64 (fused measurement)
 };
+
+enum ContVariant { kContAuto = 0, kContRow = 1, kContStream = 2 };
+uint32_t cont_sites_per_lane(int n);
+bool cont_stream_supported(const Geom& g, int n, uint32_t H);
+uint32_t cont_rows_per_band(const Geom& g, int n, uint32_t min_waves);
+int cont_variant_used(const ContLaunch& a);
+// Colour-1 half-sweep of the continuous streaming kernel with E and M of the
+// resulting state reduced on the way (partials per block); false if the
+// handle's kernel is not the streaming one.
+bool cont_half_sweep_measured(const ContLaunch& a, float* spins, uint32_t t, void* partials,
+                              int64_t* nparts, hipStream_t st, hipError_t* err);
 
 hipError_t launch_cont_half_sweep(const ContLaunch& a, float* spins, uint32_t t,
                                   uint32_t colour, hipStream_t st);

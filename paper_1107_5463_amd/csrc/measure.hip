@@ -11,6 +11,8 @@
 #include "chunk.hpp"
 #include "reduce.hpp"
 
+#include <algorithm>
+
 namespace smc {
 
 // Ising, one colour-1 site per thread, any L / coupling kind.
@@ -85,14 +87,15 @@ __global__ __launch_bounds__(256) void measure_ising_chunk(const Geom g, const i
   block_partial(v, out);
 }
 
-// Continuous spins, one colour-1 site per thread.
+// Continuous spins: colour-1 sites j = gid, gid + stride, ... per thread
+// (a bounded grid, so the finish kernel reads few partials).
 template <int D, int N, int JK>
 __global__ __launch_bounds__(256) void measure_cont_site(const Geom g, const float* __restrict__ s,
                                                          const void* __restrict__ J, const double J0,
                                                          Partial* out) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * 256;
   Partial v{0, 0, 0.0, {0.0, 0.0, 0.0}};
-  if (j < g.Nh) {
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < g.Nh; j += stride) {
     const int64_t Nh = g.Nh, Nfull = 2 * Nh;
     const float* s1 = s + Nh;
     const float* s0 = s;
@@ -128,9 +131,9 @@ __global__ __launch_bounds__(256) void measure_cont_site(const Geom g, const flo
       }
       e -= jp * dp + jm * dm;
     }
-    v.E = e;
+    v.E += e;
 #pragma unroll
-    for (int k = 0; k < N; ++k) v.M[k] = si[k] + (double)s0[k * Nfull + j];
+    for (int k = 0; k < N; ++k) v.M[k] += si[k] + (double)s0[k * Nfull + j];
   }
   block_partial(v, out);
 }
@@ -188,6 +191,9 @@ __global__ __launch_bounds__(256) void finish_kernel(const Partial* __restrict__
 
 int64_t measure_partials(const Geom& g) { return (g.Nh + 255) / 256; }
 
+// grid of the continuous measurement (each thread then takes several sites)
+constexpr int64_t kMeasureBlocks = 2048;
+
 template <int D>
 static void launch_measure_d(const MeasureLaunch& a, const void* spins, Partial* parts,
                              int64_t& nparts, hipStream_t st) {
@@ -218,7 +224,7 @@ static void launch_measure_d(const MeasureLaunch& a, const void* spins, Partial*
                          (const int8_t*)spins, a.J, parts);
     return;
   }
-  nparts = (g.Nh + 255) / 256;
+  nparts = std::min<int64_t>((g.Nh + 255) / 256, kMeasureBlocks);
   const dim3 grid((unsigned)nparts);
   const float* sf = (const float*)spins;
 #define SMC_MC(N, JK) \

@@ -42,6 +42,9 @@ struct smc_lattice {
   bool use_fused;            // SMC_FLAG_SCHEDULE_FUSED and the fused kernel supports the shape
   uint32_t fused_rows;       // fused kernel band height (SMC_FUSED_ROWS overrides)
   uint32_t packed_rows;      // packed kernel band height (SMC_PACKED_ROWS overrides)
+  int cont_variant;          // ContVariant (SMC_CONT_KERNEL overrides the automatic choice)
+  uint32_t cont_rows;        // continuous streaming band height (SMC_CONT_ROWS overrides)
+  FastDiv divQc;             // continuous streaming lanes per plane row
   // workspace carve-up
   void* obs_slot;      // smc_obs (64 B)
   uint32_t* counter;   // validation counter
@@ -269,6 +272,27 @@ hipError_t measure_any(smc_lattice* h, int64_t sweep, void* dev_obs) {
   return launch_measure(measure_args(h, sweep), h->spins, h->partials, dev_obs, h->stream);
 }
 
+ContLaunch cont_args(const smc_lattice* h, double beta) {
+  ContLaunch a;
+  std::memset(&a, 0, sizeof(a));
+  a.g = h->g;
+  a.n = h->p.n;
+  a.key = key_of(h);
+  a.J_kind = h->p.J_kind;
+  a.J0 = (float)h->p.J0;
+  a.J0d = h->p.J0;
+  a.J = h->J;
+  a.beta = (float)beta;
+  a.delta = (float)h->p.delta;
+  a.one_minus_cos_cap = (float)(1.0 - std::cos(h->p.delta));
+  a.fast_math = (h->p.flags & SMC_FLAG_FAST_MATH) ? 1 : 0;
+  a.variant = h->cont_variant;
+  a.rows_per_band = h->cont_rows;
+  a.divQ = h->divQc;
+  a.divL = h->divL;
+  return a;
+}
+
 int half_sweep_impl(smc_lattice* h, double beta, uint32_t t, uint32_t colour) {
   if (is_packed(&h->p)) {
     IsingLaunch a = ising_args(h, beta);
@@ -282,17 +306,7 @@ int half_sweep_impl(smc_lattice* h, double beta, uint32_t t, uint32_t colour) {
     return check(launch_ising_half_sweep(a, (int8_t*)h->spins, t, colour, h->stream),
                  "Ising half-sweep launch");
   }
-  ContLaunch a;
-  a.g = h->g;
-  a.n = h->p.n;
-  a.key = key_of(h);
-  a.J_kind = h->p.J_kind;
-  a.J0 = (float)h->p.J0;
-  a.J = h->J;
-  a.beta = (float)beta;
-  a.delta = (float)h->p.delta;
-  a.one_minus_cos_cap = (float)(1.0 - std::cos(h->p.delta));
-  a.fast_math = (h->p.flags & SMC_FLAG_FAST_MATH) ? 1 : 0;
+  const ContLaunch a = cont_args(h, beta);
   return check(launch_cont_half_sweep(a, (float*)h->spins, t, colour, h->stream),
                "continuous half-sweep launch");
 }
@@ -320,6 +334,17 @@ int two_pass_sweep(smc_lattice* h, double beta, uint32_t t, void* dev_obs) {
     hipError_t err = hipSuccess;
     if (ising_half_sweep_measured(a, (int8_t*)h->spins, t, h->partials, &nparts, h->stream, &err)) {
       rc = check(err, "measured Ising half-sweep launch");
+      if (rc != SMC_OK) return rc;
+      return check(launch_finish(measure_args(h, (int64_t)t + 1), h->partials, nparts, dev_obs, h->stream),
+                   "measurement finish launch");
+    }
+  }
+  if (dev_obs && h->p.n > 1) {
+    const ContLaunch a = cont_args(h, beta);
+    int64_t nparts = 0;
+    hipError_t err = hipSuccess;
+    if (cont_half_sweep_measured(a, (float*)h->spins, t, h->partials, &nparts, h->stream, &err)) {
+      rc = check(err, "measured continuous half-sweep launch");
       if (rc != SMC_OK) return rc;
       return check(launch_finish(measure_args(h, (int64_t)t + 1), h->partials, nparts, dev_obs, h->stream),
                    "measurement finish launch");
@@ -493,6 +518,22 @@ int smc_init_lattice(smc_lattice** out, const smc_params* p, void* spins, void* 
     const long H = std::strtol(v, nullptr, 10);
     if (H >= 1 && H <= 64 && H <= h->g.L && h->g.L % H == 0) h->packed_rows = (uint32_t)H;
   }
+  h->cont_variant = (p->flags & SMC_FLAG_GENERIC_KERNEL) ? kContRow : kContAuto;
+  if (const char* v = std::getenv("SMC_CONT_KERNEL")) {
+    const std::string s(v);
+    if (s == "row") h->cont_variant = kContRow;
+    if (s == "stream") h->cont_variant = kContStream;
+  }
+  h->cont_rows = p->n > 1 ? cont_rows_per_band(h->g, p->n, 2048) : 4;
+  if (const char* v = std::getenv("SMC_CONT_ROWS")) {
+    const long H = std::strtol(v, nullptr, 10);
+    if (H >= 4 && H <= 64 && H % 4 == 0 && H <= h->g.L && h->g.L % H == 0) h->cont_rows = (uint32_t)H;
+  }
+  {
+    const uint32_t V = p->n > 1 ? cont_sites_per_lane(p->n) : 1;
+    const uint32_t Qc = (uint32_t)h->g.R / V;
+    h->divQc = make_fastdiv(Qc > 0 ? Qc : 1);
+  }
   h->use_fused = p->n == 1 && !is_packed(p) && p->tile == 0 && !(p->flags & SMC_FLAG_HEATBATH) &&
                  (p->flags & SMC_FLAG_SCHEDULE_FUSED) &&
                  !(p->flags & SMC_FLAG_GENERIC_KERNEL) &&
@@ -661,8 +702,18 @@ int smc_set_sweep_index(smc_lattice* h, uint64_t t) {
 const char* smc_kernel_name(const smc_lattice* h, uint32_t* rows_per_band) {
   if (rows_per_band) *rows_per_band = 0;
   if (!h) return "";
-  if (h->p.n == 2) return "xy_site";
-  if (h->p.n == 3) return "heisenberg_site";
+  if (h->p.n > 1) {
+    ContLaunch a;
+    std::memset(&a, 0, sizeof(a));
+    a.g = h->g;
+    a.n = h->p.n;
+    a.variant = h->cont_variant;
+    a.rows_per_band = h->cont_rows;
+    const bool stream = cont_variant_used(a) == kContStream;
+    if (stream && rows_per_band) *rows_per_band = h->cont_rows;
+    if (h->p.n == 2) return stream ? "xy_stream" : "xy_site";
+    return stream ? "heisenberg_stream" : "heisenberg_site";
+  }
   if (is_packed(&h->p)) {
     if (rows_per_band) *rows_per_band = h->packed_rows;
     return "ising_packed";

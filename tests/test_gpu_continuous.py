@@ -63,15 +63,55 @@ CASES = [  # d, n, L, beta, delta, J_kind, fast
 ]
 
 
+# the streaming kernel at several band heights: many bands and blocks, ragged
+# last block (lanes past the last band idle)
+STREAM_CASES = [  # d, n, L, beta, delta, J_kind, fast, rows
+    (2, 2, 128, 1.12, 1.63, 0, False, 16),
+    (2, 2, 96, 1.0, 1.5, 2, False, 8),
+    (2, 3, 64, 0.8, 0.7, 1, False, 32),
+    (3, 3, 32, 0.693, 2.058, 0, False, 8),
+    (3, 2, 24, 0.6, 1.5, 2, False, 4),
+    (3, 3, 12, 0.7, 1.2, 1, False, 4),
+]
+
+
+def _set_kernel(monkeypatch, kernel, rows=None):
+    monkeypatch.setenv("SMC_CONT_KERNEL", kernel)
+    if rows is None:
+        monkeypatch.delenv("SMC_CONT_ROWS", raising=False)
+    else:
+        monkeypatch.setenv("SMC_CONT_ROWS", str(rows))
+
+
+@pytest.mark.parametrize("kernel", ["row", "stream"])
 @pytest.mark.parametrize("d,n,L,beta,delta,kind,fast", CASES)
-def test_half_sweep_protocol(smc_gpu, oracle_mod, d, n, L, beta, delta, kind, fast):
+def test_half_sweep_protocol(smc_gpu, oracle_mod, d, n, L, beta, delta, kind, fast, kernel,
+                             monkeypatch):
+    _set_kernel(monkeypatch, kernel)
+    _protocol(smc_gpu, oracle_mod, d, n, L, beta, delta, kind, fast, kernel)
+
+
+@pytest.mark.parametrize("d,n,L,beta,delta,kind,fast,rows", STREAM_CASES)
+def test_stream_kernel_protocol(smc_gpu, oracle_mod, d, n, L, beta, delta, kind, fast, rows,
+                                monkeypatch):
+    _set_kernel(monkeypatch, "stream", rows)
+    lat = _protocol(smc_gpu, oracle_mod, d, n, L, beta, delta, kind, fast, "stream")
+    assert lat.kernel()[1] == rows
+
+
+def _protocol(smc_gpu, oracle_mod, d, n, L, beta, delta, kind, fast, kernel):
     import torch
-    print(f"half-sweep protocol d={d} n={n} L={L} kind={kind} fast={fast}", flush=True)
+    print(f"half-sweep protocol d={d} n={n} L={L} kind={kind} fast={fast} kernel={kernel}",
+          flush=True)
     band = 1e-5 if fast else BAND
     tol = 1e-4 if fast else TOL
     ref = oracle_mod.OracleLattice(d, n, L, 19, delta=delta, J_kind=kind, J_sigma=0.2,
                                    renorm_every=0)
     lat = upload(smc_gpu, ref, fast_math=fast)
+    V = 4 if n == 2 else 2
+    name = lat.kernel()[0]
+    want = "stream" if kernel == "stream" and (L // 2) % V == 0 else "site"
+    assert name == ("xy_" if n == 2 else "heisenberg_") + want
     near = 0
     for t in range(4):
         for c in (0, 1):
@@ -90,6 +130,7 @@ def test_half_sweep_protocol(smc_gpu, oracle_mod, d, n, L, beta, delta, kind, fa
             assert np.abs(g[:, both] - ref.s[:, both]).max(initial=0.0) <= tol
             near += int(np.sum(np.abs(margin) < band))
     print(f"near-threshold sites (|u-p| < {band}): {near} of {8 * L ** d // 2}")
+    return lat
 
 
 @pytest.mark.parametrize("n,d,beta,delta,single", [
@@ -137,7 +178,8 @@ def test_renormalisation(smc_gpu):
     lat.validate()
 
 
-@pytest.mark.parametrize("d,n,L,kind", [(2, 2, 32, 0), (3, 3, 8, 1), (2, 3, 16, 2)])
+@pytest.mark.parametrize("d,n,L,kind", [(2, 2, 32, 0), (3, 3, 8, 1), (2, 3, 16, 2),
+                                         (2, 2, 1040, 0)])  # several sites per thread
 def test_measure_and_bonds_match_oracle(smc_gpu, oracle_mod, d, n, L, kind):
     s = inputs.random_unit_vectors(n, L ** d, seed=L + n)
     ref = oracle_mod.OracleLattice(d, n, L, 3, J_kind=kind, J_sigma=0.3, spins=s, delta=1.0)
@@ -179,3 +221,30 @@ def test_long_run_statistics_match_oracle(smc_gpu, oracle_mod, d, n, L, beta, de
         mg, sg = _binned([getattr(o, key) / N for o in g])
         mo, so = _binned([getattr(o, key) / N for o in r])
         assert abs(mg - mo) < 4 * np.hypot(sg, so), (key, mg, mo, sg, so)
+
+
+@pytest.mark.parametrize("d,n,L,kind,kernel,rows", [
+    (2, 2, 64, 0, "stream", 8), (3, 3, 16, 1, "stream", 4), (2, 3, 32, 2, "stream", 8),
+    (3, 2, 8, 2, "stream", 4), (2, 2, 96, 1, "stream", 16), (2, 2, 6, 0, "stream", None),
+    (2, 3, 32, 0, "row", None)])
+def test_sweep_measure_matches_oracle(smc_gpu, oracle_mod, d, n, L, kind, kernel, rows,
+                                      monkeypatch):
+    """E and M written by sweep_measure (fused into the colour-1 pass of the
+    streaming kernel, else measured separately) against the oracle's
+    measurement of the GPU's resulting state."""
+    import torch
+    _set_kernel(monkeypatch, kernel, rows)
+    s = inputs.random_unit_vectors(n, L ** d, seed=L + 7 * n)
+    ref = oracle_mod.OracleLattice(d, n, L, 3, J_kind=kind, J_sigma=0.3, spins=s, delta=1.0,
+                                   renorm_every=0)
+    lat = upload(smc_gpu, ref)
+    slots = torch.zeros((3, 8), dtype=torch.int64, device=lat.device)
+    for k in range(3):
+        lat.sweep_measure(0.7, 2, slots[k])
+        o = smc_gpu.Lattice.decode_obs(slots[k:k + 1])[0]
+        ref.s = nat(lat)
+        r = ref.measure()
+        assert o.sweep == 2 * (k + 1)
+        assert abs(o.E - r.E) <= 1e-12 * max(1.0, abs(r.E)) * L ** d, (k, o.E, r.E)
+        assert np.allclose(o.M[:n], r.M[:n], rtol=0, atol=1e-9 * L ** d), (k, o.M, r.M)
+        assert abs(o.absM - r.absM) <= 1e-9 * L ** d
