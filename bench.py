@@ -77,7 +77,10 @@ def parse():
                     help="timed steps of 10 sweeps + 1 measurement (default: 100, i.e. 1000 "
                          "sweeps; batched and chains: 1000, i.e. 10^4 sweeps)")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--sweeps-per-step", type=int, default=10)
+    ap.add_argument("--sweeps-per-step", type=int, default=None,
+                    help="sweeps per timed step (default 10; batched: 10000 in one launch)")
+    ap.add_argument("--measure-every", type=int, default=10,
+                    help="batched: E/M of every lattice every this many sweeps, inside the launch")
     ap.add_argument("--schedule", choices=["fused", "two-pass"], default="two-pass",
                     help="2D Ising only -- fused: one kernel per sweep with ping-pong buffers "
                          "(2 B/attempt); two-pass: one in-place kernel per colour (3 B/attempt)")
@@ -236,7 +239,8 @@ def run_lattice(args, wl, torch, smc):
     if args.copy_probe:
         copy_probe(torch, lat.device)
     K = args.steps if args.steps is not None else 100
-    W, S = args.warmup, args.sweeps_per_step
+    W = args.warmup
+    S = args.sweeps_per_step if args.sweeps_per_step is not None else 10
     beta = wl["beta"]
     total_ms, wall, obs = timed_steps(lat, beta, K, W, S, torch)
     sweeps = K * S
@@ -344,17 +348,23 @@ def run_batched(args, wl, torch, smc):
     threads, largest_first = b.autotune()
     b.use_graph(True)
     st = b.stream
-    K = args.steps if args.steps is not None else 1000
-    W, S = args.warmup, args.sweeps_per_step
-    obs = torch.zeros((nl, 8), dtype=torch.int64, device=b.device)
+    # one step = one persistent launch of S sweeps recording E and M of every
+    # lattice every `every` sweeps
+    K = args.steps if args.steps is not None else 1
+    W = args.warmup
+    S = args.sweeps_per_step if args.sweeps_per_step is not None else 10000
+    every = args.measure_every
+    if every < 1 or S % every:
+        sys.exit("--measure-every must divide --sweeps-per-step")
+    obs = torch.zeros((S // every, nl, 8), dtype=torch.int64, device=b.device)
     for _ in range(W):
-        b.sweep(S, obs)
+        b.sweep(S, obs, every=every)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record(st)
     for _ in range(K):
-        b.sweep(S, obs)
+        b.sweep(S, obs, every=every)
     ev1.record(st)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -396,7 +406,8 @@ def run_batched(args, wl, torch, smc):
         "config": {
             "workload": f"batched 3D +-J Edwards-Anderson: {nl} lattices, L in {list(wl['Ls'])} "
                         f"(lattice r has L[r % 5]), beta_r = 0.5 + 2.5 (r % 32) / 31, seed "
-                        f"{wl['seed']}, {sweeps} sweeps, E/M of every lattice every {S} sweeps",
+                        f"{wl['seed']}, {sweeps} sweeps in {K} persistent graph-replayed launch(es) of {S}, "
+                        f"E/M of every lattice every {every} sweeps recorded inside the launch",
             "sites": sites, "sweeps": sweeps, "threads_per_lattice": threads,
             "largest_first": largest_first, "graph": True,
         },
@@ -460,7 +471,8 @@ def run_chains(args, wl, torch, smc):
     ch = smc.Chains(d, L, nch, wl["seed"], J=torch.from_numpy(Js).cuda())
     st = ch.stream
     K = args.steps if args.steps is not None else 1000
-    W, S = args.warmup, args.sweeps_per_step
+    W = args.warmup
+    S = args.sweeps_per_step if args.sweeps_per_step is not None else 10
     beta = wl["beta"]
     for _ in range(W):
         ch.sample(beta, S)

@@ -234,6 +234,15 @@ int smc_batch_init(smc_batch** out, int32_t d, int32_t J_kind, uint64_t seed, do
  * of each lattice's final state are written there by the same launch. */
 int smc_batch_sweep(smc_batch* b, int64_t n_sweeps, void* dev_obs);
 
+/* As smc_batch_sweep, with E and M of every lattice recorded inside the same
+ * launch after every measure_every sweeps (measure_every >= 1 dividing
+ * n_sweeps): dev_obs holds (n_sweeps / measure_every) x n_lattices smc_obs,
+ * record m * n_lattices + r = lattice r after sweep (m + 1) * measure_every
+ * of the call (its `sweep` field holds the absolute sweep index).  The
+ * series of Sec. 2's measurements without leaving the persistent launch.
+ * EINVAL on a bad measure_every or a misaligned dev_obs. */
+int smc_batch_sweep_series(smc_batch* b, int64_t n_sweeps, int64_t measure_every, void* dev_obs);
+
 /* Time the workgroup sizes 64..512 and the lattice orders (largest first,
  * as given) on a scratch copy of the spins and keep the fastest.  Results do
  * not depend on the choice.  Synchronises the stream. */

@@ -43,7 +43,8 @@ EXPORTS = ["smc_spin_bytes", "smc_coupling_bytes", "smc_workspace_bytes", "smc_b
            "smc_renormalize", "smc_validate", "smc_get_sweep_index", "smc_set_sweep_index",
            "smc_kernel_name", "smc_destroy", "smc_last_error", "smc_version",
            "smc_batch_spin_bytes", "smc_batch_coupling_bytes", "smc_batch_workspace_bytes",
-           "smc_batch_offsets", "smc_batch_init", "smc_batch_sweep", "smc_batch_autotune",
+           "smc_batch_offsets", "smc_batch_init", "smc_batch_sweep", "smc_batch_sweep_series",
+           "smc_batch_autotune",
            "smc_batch_use_graph", "smc_batch_get_sweep_index", "smc_batch_set_sweep_index",
            "smc_batch_destroy",
            "smc_chains_spin_bytes", "smc_chains_coupling_bytes", "smc_chains_bond_bytes",
@@ -130,6 +131,7 @@ def load_library():
                                    C.c_int32, C.c_int32, C.c_int32, i32p, C.POINTER(C.c_double),
                                    C.POINTER(C.c_uint32), vp, vp, vp, sz, vp]
     lib.smc_batch_sweep.argtypes = [vp, C.c_int64, vp]
+    lib.smc_batch_sweep_series.argtypes = [vp, C.c_int64, C.c_int64, vp]
     lib.smc_batch_autotune.argtypes = [vp, i32p, i32p]
     lib.smc_batch_use_graph.argtypes = [vp, C.c_int32]
     lib.smc_batch_get_sweep_index.argtypes = [vp, C.POINTER(C.c_uint64)]
@@ -461,14 +463,20 @@ class Batch:
         o = self.coupling_offsets[r]
         return self.J[o:o + self.d * N].view(self.d, 2, N // 2)
 
-    def sweep(self, n_sweeps: int, obs=None):
-        """n_sweeps sweeps of every lattice; with obs (device int64 tensor of
-        [n_lattices, 8]) the final observables of each lattice are written."""
+    def sweep(self, n_sweeps: int, obs=None, every: int | None = None):
+        """n_sweeps sweeps of every lattice in one launch.  With obs (device
+        int64 tensor) the observables are written: the final state's
+        ([n_lattices, 8]) or, with `every`, those after every `every` sweeps
+        ([n_sweeps / every, n_lattices, 8]), recorded inside the launch."""
         ptr = None
         if obs is not None:
-            assert obs.is_cuda and obs.numel() >= 8 * self.n
+            recs = 1 if every is None or n_sweeps == 0 or every <= 0 else n_sweeps // every
+            assert obs.is_cuda and obs.numel() >= 8 * self.n * recs
             ptr = C.c_void_p(obs.data_ptr())
-        _check(load_library().smc_batch_sweep(self._h, int(n_sweeps), ptr))
+        if every is None:
+            _check(load_library().smc_batch_sweep(self._h, int(n_sweeps), ptr))
+        else:
+            _check(load_library().smc_batch_sweep_series(self._h, int(n_sweeps), int(every), ptr))
 
     def autotune(self):
         th = C.c_int32()

@@ -12,12 +12,20 @@
 // with that replica bit for bit.  A lane walks groups of 16 consecutive
 // same-colour sites (one Philox block of prefix bytes per group); the
 // decision per site is the integer threshold test of the single-lattice
-// kernels with its exact tie refinement.  With MEASURE the workgroup also
-// reduces E and M of its final state from LDS.
+// kernels with its exact tie refinement.  Lattices whose plane rows are whole
+// 4-site words (L/2 % 4 == 0) take the decision four sites per 32-bit op:
+// neighbour words from LDS (the in-row neighbours as the centre word shifted
+// by one byte), unsatisfied-bond counts per byte, and the byte-wise threshold
+// compare of the single-lattice kernels.  With MEASURE the workgroup also
+// reduces E and M of its state from LDS after every `every` sweeps (record m
+// of the call at obs[m * n_lattices + lattice]; with no sweeps, one record of
+// the current state).
 #include "chunk.hpp"
 #include "reduce.hpp"
 
 namespace smc {
+
+constexpr uint32_t kBatchTieSlots = 4;  // deferred ties per lane before a flush
 
 template <int D, bool PM, bool MEASURE>
 __global__ __launch_bounds__(512) void batch_kernel(const BatchDesc* __restrict__ descs,
@@ -25,8 +33,10 @@ __global__ __launch_bounds__(512) void batch_kernel(const BatchDesc* __restrict_
                                                     const RngKey key, int8_t* __restrict__ spins,
                                                     const int8_t* __restrict__ J,
                                                     const uint32_t t0, const uint32_t n_sweeps,
+                                                    const uint32_t every, const uint32_t n_lattices,
                                                     ObsOut* __restrict__ obs) {
-  extern __shared__ int8_t lat[];  // [2][Nh] spins of this lattice
+  extern __shared__ uint32_t lat_words[];  // [2][Nh] spins of this lattice
+  int8_t* const lat = reinterpret_cast<int8_t*>(lat_words);
   const uint32_t li = __builtin_amdgcn_readfirstlane(order[blockIdx.x]);
   const BatchDesc* dp = descs + li;
   const uint32_t L = __builtin_amdgcn_readfirstlane(dp->L);
@@ -41,6 +51,8 @@ __global__ __launch_bounds__(512) void batch_kernel(const BatchDesc* __restrict_
   divL.s = (uint32_t)__builtin_amdgcn_readfirstlane(dp->divL_s);
   const uint32_t th_lo = __builtin_amdgcn_readfirstlane(dp->th_lo);
   const uint32_t th_hi = __builtin_amdgcn_readfirstlane(dp->th_hi);
+  const uint32_t al_lo = __builtin_amdgcn_readfirstlane(dp->al_lo);
+  const uint32_t al_hi = __builtin_amdgcn_readfirstlane(dp->al_hi);
   const uint32_t replica = __builtin_amdgcn_readfirstlane(dp->replica);
   const uint64_t soff = ((uint64_t)__builtin_amdgcn_readfirstlane(dp->spin_off_hi) << 32) |
                         __builtin_amdgcn_readfirstlane(dp->spin_off_lo);
@@ -53,23 +65,24 @@ __global__ __launch_bounds__(512) void batch_kernel(const BatchDesc* __restrict_
   // Stage both planes into LDS as one byte per site: bit 0 = spin -1, bit
   // 1 + m = coupling of bond m negative (m = +x, -x, +y, -y, +z, -z), so the
   // sweep reads couplings from LDS together with the spins.
+  // Row and plane strides (wave-uniform): neighbour rows are the own row's
+  // offset plus or minus a stride, with the periodic wrap as a select.
+  const uint32_t sYw = (L - 1) * R, sZ = L * R, sZw = (L - 1) * L * R;
   auto nbr = [&](uint32_t c, uint32_t j, uint32_t nbi[6]) {  // in-plane neighbour indices
     const uint32_t r = fdiv(j, divR);
-    const uint32_t jx = j - r * R;
+    const uint32_t rowb = r * R;
+    const uint32_t jx = j - rowb;
     const uint32_t z = D == 3 ? fdiv(r, divL) : 0u;
     const uint32_t y = r - z * L;
-    const uint32_t p = (c + y + z) & 1u;
-    const uint32_t rowb = r * R;
-    nbi[0] = rowb + (jx + p == R ? 0u : jx + p);
-    nbi[1] = rowb + (jx + p == 0 ? R - 1 : jx + p - 1);
-    const uint32_t ym = y == 0 ? L - 1 : y - 1, yp = y + 1 == L ? 0 : y + 1;
-    nbi[2] = (z * L + yp) * R + jx;
-    nbi[3] = (z * L + ym) * R + jx;
+    const uint32_t p = (c + r + z) & 1u;  // (c + y + z) & 1 with L even
+    nbi[0] = jx + p == R ? rowb : j + p;
+    nbi[1] = jx + p == 0 ? rowb + R - 1 : j + p - 1;
+    nbi[2] = y + 1 == L ? j - sYw : j + R;
+    nbi[3] = y == 0 ? j + sYw : j - R;
     nbi[4] = nbi[5] = 0;
     if (D == 3) {
-      const uint32_t zm = z == 0 ? L - 1 : z - 1, zp = z + 1 == L ? 0 : z + 1;
-      nbi[4] = (zp * L + y) * R + jx;
-      nbi[5] = (zm * L + y) * R + jx;
+      nbi[4] = z + 1 == L ? j - sZw : j + sZ;
+      nbi[5] = z == 0 ? j + sZw : j - sZ;
     }
   };
   for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) {
@@ -103,12 +116,153 @@ __global__ __launch_bounds__(512) void batch_kernel(const BatchDesc* __restrict_
     const uint32_t om = (0u - (o & 1u)) & ((1u << (2 * D)) - 1u);
     return __builtin_popcount(nm ^ om ^ (PM ? (o >> 1) : 0u));
   };
+  // Four sites j .. j + 3 of one plane row (j % 4 == 0, R % 4 == 0): new
+  // word of the own plane, decided by prefix word P; ties (prefix byte equal
+  // to the threshold byte of a refusable class) take the site's refinement
+  // draw on the spot.
+  auto ld = [&](const int8_t* base, uint32_t i) -> uint32_t {
+    return *reinterpret_cast<const uint32_t*>(base + i);
+  };
+  // unsatisfied-bond counts (byte b: site j + b) of a 4-site word of plane c
+  auto counts4 = [&](const int8_t* own, const int8_t* oth, uint32_t c, uint32_t j,
+                     uint32_t& W) -> uint32_t {
+    const uint32_t r = fdiv(j, divR);
+    const uint32_t rowb = r * R;
+    const uint32_t jx = j - rowb;
+    const uint32_t z = D == 3 ? fdiv(r, divL) : 0u;
+    const uint32_t y = r - z * L;
+    const uint32_t p = (c + r + z) & 1u;  // (c + y + z) & 1 with L even
+    W = ld(own, j);
+    const uint32_t C = ld(oth, j);
+    // in-row neighbours: p = 1 -> x+1 is the next word's first byte onwards
+    const uint32_t Ej = p ? (jx + 4 == R ? rowb : j + 4) : (jx == 0 ? rowb + R - 4 : j - 4);
+    const uint32_t E = ld(oth, Ej);
+    const uint32_t S = p ? __builtin_amdgcn_alignbyte(E, C, 1) : __builtin_amdgcn_alignbyte(C, E, 3);
+    uint32_t nb[6];
+    nb[0] = p ? S : C;  // +x
+    nb[1] = p ? C : S;  // -x
+    nb[2] = ld(oth, y + 1 == L ? j - sYw : j + R);
+    nb[3] = ld(oth, y == 0 ? j + sYw : j - R);
+    if (D == 3) {
+      nb[4] = ld(oth, z + 1 == L ? j - sZw : j + sZ);
+      nb[5] = ld(oth, z == 0 ? j + sZw : j - sZ);
+    }
+    // unsatisfied bonds per byte: spin bits differ, xor the bond's sign bit
+    uint32_t k = 0;
+#pragma unroll
+    for (int m = 0; m < 2 * D; ++m) {
+      uint32_t u = W ^ nb[m];
+      if (PM) u ^= W >> (1 + m);
+      k += u & kOnes;
+    }
+    return k;
+  };
+  // New word for prefix word P; `tie` gets bit 7 of each byte whose prefix
+  // equals the threshold byte of a refusable class (left unflipped), `kout`
+  // the counts.
+  auto word4 = [&](const int8_t* own, const int8_t* oth, uint32_t c, uint32_t j, uint32_t P,
+                   uint32_t& tie, uint32_t& kout) -> uint32_t {
+    uint32_t W;
+    const uint32_t k = counts4(own, oth, c, j, W);
+    kout = k;
+    const uint32_t Th = __builtin_amdgcn_perm(th_hi, th_lo, k);
+    const uint32_t Al = __builtin_amdgcn_perm(al_hi, al_lo, k);
+    const uint32_t x = P ^ Th;
+    const uint32_t dlow = (P | kHigh) - (Th & ~kHigh);
+    const uint32_t ge = (x & P) | (~x & dlow);  // bit 7 of each byte: P >= Th
+    const uint32_t rej = __builtin_amdgcn_perm(ge, ge << 8, 0x0B090A08u);
+    const uint32_t zb = (x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
+    tie = ~(zb | x | Al) & kHigh;
+    return W ^ ((~rej | Al) & kOnes);
+  };
+  // Ties wait in a per-lane LDS queue (entry (site << 3) | class, lane-major)
+  // and are resolved by their refinement draws before the colour's barrier:
+  // a lane alone writes the sites of its groups, so the late flip is
+  // race-free, and a wave pays for the longest queue of its lanes once per
+  // half-sweep instead of once per word.
+  uint32_t* const tq = lat_words + (N + 15) / 16 * 4 + threadIdx.x;
+  uint32_t nq = 0;
+  auto flush = [&](int8_t* own, uint32_t c, uint32_t t) {
+    for (uint32_t i = 0; i < nq; ++i) {
+      const uint32_t e = tq[i * blockDim.x];
+      const uint32_t js = e >> 3;
+      const Rand4 rr = philox(js, t, replica, tag(c, kIsingRefine), key.k0, key.k1);
+      if ((rr.w[0] & 0xFFFFFFu) < dp->frac[e & 7u]) own[js] ^= 1;
+    }
+    nq = 0;
+  };
+  const bool words = (R & 3u) == 0;
+  // E = sum over colour-1 sites of (unsatisfied - satisfied) bonds (each bond
+  // once), M = sum of the spins of both colours; record `slot` of this call
+  auto measure = [&](uint32_t slot, int64_t sweep) {
+    int64_t Esum = 0, Msum = 0;
+    if (words) {
+      for (uint32_t j = 4 * threadIdx.x; j < Nh; j += 4 * blockDim.x) {
+        uint32_t W;
+        const uint32_t k = counts4(lat + Nh, lat, 1u, j, W);
+        const uint32_t down = __builtin_popcount(W & kOnes) + __builtin_popcount(ld(lat, j) & kOnes);
+        Esum += 2 * (int64_t)__builtin_amdgcn_sad_u8(k, 0u, 0u) - 4 * 2 * D;
+        Msum += 8 - 2 * (int64_t)down;
+      }
+    } else {
+      for (uint32_t j = threadIdx.x; j < Nh; j += blockDim.x) {
+        uint32_t o;
+        const uint32_t k = site_k(lat + Nh, lat, 1u, j, o);
+        Esum += 2 * (int64_t)k - 2 * D;
+        Msum += (1 - 2 * (int32_t)(o & 1u)) + (1 - 2 * (int32_t)(lat[j] & 1));
+      }
+    }
+    __shared__ Partial part[1];
+    block_partial_int(Esum, Msum, part, 0);
+    if (threadIdx.x == 0) {
+      ObsOut o;
+      o.E_int = part[0].Ei;
+      o.M_int = part[0].Mi;
+      o.E = (double)part[0].Ei * dp->J0;
+      o.M[0] = (double)part[0].Mi;
+      o.M[1] = 0.0;
+      o.M[2] = 0.0;
+      o.absM = fabs((double)part[0].Mi);
+      o.sweep = sweep;
+      obs[(uint64_t)slot * n_lattices + li] = o;
+    }
+  };
   const uint32_t ngroups = (Nh + 15) / 16;
   for (uint32_t sw = 0; sw < n_sweeps; ++sw) {
     const uint32_t t = t0 + sw;
     for (uint32_t c = 0; c < 2; ++c) {
       int8_t* own = lat + c * Nh;
       const int8_t* oth = lat + (1 - c) * Nh;
+      if (words) {
+        // Nh is a multiple of 4: a group holds nj / 4 whole words
+        for (uint32_t g = threadIdx.x; g < ngroups; g += blockDim.x) {
+          const uint32_t j0 = 16 * g;
+          const Rand4 rp = philox(g, t, replica, tag(c, kIsingPrefix), key.k0, key.k1);
+          const uint32_t nwords = Nh - j0 < 16 ? (Nh - j0) >> 2 : 4u;
+#pragma unroll
+          for (uint32_t w = 0; w < 4; ++w) {
+            // lanes 8 apart start on different words of their groups: the
+            // words of a step then fall in different LDS banks
+            const uint32_t ws = (w + (threadIdx.x >> 3)) & 3u;
+            if (ws < nwords) {
+              const uint32_t j = j0 + 4 * ws;
+              uint32_t tie, k;
+              const uint32_t nw = word4(own, oth, c, j, word_of(rp.w, ws), tie, k);
+              *reinterpret_cast<uint32_t*>(own + j) = nw;
+              while (tie) {
+                const uint32_t b = (uint32_t)__builtin_ctz(tie) >> 3;
+                tie &= tie - 1;
+                if (nq == kBatchTieSlots) flush(own, c, t);
+                tq[nq * blockDim.x] = ((j + b) << 3) | ((k >> (8 * b)) & 7u);
+                ++nq;
+              }
+            }
+          }
+        }
+        flush(own, c, t);
+        __syncthreads();
+        continue;
+      }
       for (uint32_t g = threadIdx.x; g < ngroups; g += blockDim.x) {
         const uint32_t j0 = 16 * g;
         const Rand4 rp = philox(g, t, replica, tag(c, kIsingPrefix), key.k0, key.k1);
@@ -139,45 +293,28 @@ __global__ __launch_bounds__(512) void batch_kernel(const BatchDesc* __restrict_
       }
       __syncthreads();
     }
+    // every thread reaches the barrier inside the block reduction after its
+    // reads of the planes: none writes them again before all have read
+    if (MEASURE && (sw + 1) % every == 0) measure((sw + 1) / every - 1, (int64_t)t + 1);
   }
+  if (MEASURE && n_sweeps == 0) measure(0, (int64_t)t0);
 
   // write both planes back as +-1 bytes
   for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) gs[i] = (lat[i] & 1) ? (int8_t)-1 : (int8_t)1;
 
-  if (MEASURE) {
-    // E = sum over colour-1 sites of (unsatisfied - satisfied) bonds (each
-    // bond once), M = sum of the spins of both colours
-    int64_t Esum = 0, Msum = 0;
-    for (uint32_t j = threadIdx.x; j < Nh; j += blockDim.x) {
-      uint32_t o;
-      const uint32_t k = site_k(lat + Nh, lat, 1u, j, o);
-      Esum += 2 * (int64_t)k - 2 * D;
-      Msum += (1 - 2 * (int32_t)(o & 1u)) + (1 - 2 * (int32_t)(lat[j] & 1));
-    }
-    __shared__ Partial part[1];
-    block_partial_int(Esum, Msum, part, 0);
-    if (threadIdx.x == 0) {
-      ObsOut o;
-      o.E_int = part[0].Ei;
-      o.M_int = part[0].Mi;
-      o.E = (double)part[0].Ei * dp->J0;
-      o.M[0] = (double)part[0].Mi;
-      o.M[1] = 0.0;
-      o.M[2] = 0.0;
-      o.absM = fabs((double)part[0].Mi);
-      o.sweep = (int64_t)t0 + n_sweeps;
-      obs[li] = o;
-    }
-  }
+}
+
+size_t batch_lds_bytes(size_t max_sites, uint32_t threads) {
+  return (max_sites + 15) / 16 * 16 + (size_t)threads * kBatchTieSlots * 4;
 }
 
 hipError_t launch_batch(const BatchLaunch& a, int8_t* spins, const int8_t* J, uint32_t t0,
-                        uint32_t n_sweeps, void* dev_obs, hipStream_t st) {
+                        uint32_t n_sweeps, uint32_t every, void* dev_obs, hipStream_t st) {
   const dim3 grid(a.n_lattices), block(a.threads);
-  const size_t lds = a.max_sites;
+  const size_t lds = batch_lds_bytes(a.max_sites, a.threads);
 #define SMC_BK(DD, PMM, MM)                                                                      \
   hipLaunchKernelGGL((batch_kernel<DD, PMM, MM>), grid, block, lds, st, a.descs, a.order, a.key, \
-                     spins, J, t0, n_sweeps, (ObsOut*)dev_obs)
+                     spins, J, t0, n_sweeps, every, a.n_lattices, (ObsOut*)dev_obs)
   const bool m = dev_obs != nullptr;
   if (a.d == 2) {
     if (a.pm) { if (m) SMC_BK(2, true, true); else SMC_BK(2, true, false); }

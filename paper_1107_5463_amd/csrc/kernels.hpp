@@ -100,6 +100,7 @@ struct BatchDesc {
   uint32_t spin_off_lo, spin_off_hi;        // byte offset of its [2][Nh] spins
   uint32_t J_off_lo, J_off_hi;              // byte offset of its [d][2][Nh] couplings
   uint32_t frac[7];                         // refinement fractions (2^24: always)
+  uint32_t al_lo, al_hi;                    // byte k = 0xFF if class k always accepts
   uint32_t pad;
   double J0;
 };
@@ -115,11 +116,16 @@ struct BatchLaunch {
   RngKey key;              // replica is taken from each descriptor
 };
 
+// With dev_obs, E and M of every lattice after every `every` sweeps (record m
+// at dev_obs[m * n_lattices + lattice]; with n_sweeps = 0 one record).
 hipError_t launch_batch(const BatchLaunch& a, int8_t* spins, const int8_t* J, uint32_t t0,
-                        uint32_t n_sweeps, void* dev_obs, hipStream_t st);
+                        uint32_t n_sweeps, uint32_t every, void* dev_obs, hipStream_t st);
 hipError_t batch_allow_lds(size_t bytes);
+// Dynamic LDS of a batch launch: the largest lattice's planes plus the
+// per-lane tie queues.
+size_t batch_lds_bytes(size_t max_sites, uint32_t threads);
 // The kernel a batch launch uses (for building graph nodes); its arguments are
-// (descs, order, key, spins, J, t0, n_sweeps, obs).
+// (descs, order, key, spins, J, t0, n_sweeps, every, n_lattices, obs).
 const void* batch_kernel_fn(int d, bool pm, bool measure);
 
 struct MeasureLaunch {

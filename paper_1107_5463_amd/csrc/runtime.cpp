@@ -796,6 +796,7 @@ struct smc_batch {
   hipGraphExec_t exec;
   hipGraphNode_t node;
   int64_t graph_n;
+  uint32_t graph_every;
   void* graph_obs;
   uint32_t graph_threads;
   bool graph_largest;
@@ -844,8 +845,8 @@ size_t batch_ws_parts(int32_t d, int32_t n, const int32_t* L, size_t* desc_b, si
   return *desc_b + *order_b + *scratch_b;
 }
 
-int batch_launch(smc_batch* b, int8_t* spins, uint32_t t0, uint32_t n_sweeps, void* dev_obs,
-                 uint32_t threads, bool largest_first) {
+int batch_launch(smc_batch* b, int8_t* spins, uint32_t t0, uint32_t n_sweeps, uint32_t every,
+                 void* dev_obs, uint32_t threads, bool largest_first) {
   BatchLaunch a;
   a.d = b->d;
   a.pm = b->J_kind == SMC_J_PM;
@@ -855,7 +856,7 @@ int batch_launch(smc_batch* b, int8_t* spins, uint32_t t0, uint32_t n_sweeps, vo
   a.descs = b->desc_dev;
   a.order = b->order_dev + (largest_first ? 0 : b->n);
   a.key = RngKey{(uint32_t)(b->seed & 0xffffffffu), (uint32_t)(b->seed >> 32), 0u};
-  return check(launch_batch(a, spins, (const int8_t*)b->J, t0, n_sweeps, dev_obs, b->stream),
+  return check(launch_batch(a, spins, (const int8_t*)b->J, t0, n_sweeps, every, dev_obs, b->stream),
                "batch sweep launch");
 }
 
@@ -869,7 +870,7 @@ void batch_drop_graph(smc_batch* b) {
 
 // One graph node holding the batch kernel; its arguments are refreshed in
 // the instantiated graph before every replay.
-int batch_graph_sweep(smc_batch* b, uint32_t n_sweeps, void* dev_obs) {
+int batch_graph_sweep(smc_batch* b, uint32_t n_sweeps, uint32_t every, void* dev_obs) {
   const BatchDesc* descs = b->desc_dev;
   const uint32_t* order = b->order_dev + (b->largest_first ? 0 : b->n);
   RngKey key{(uint32_t)(b->seed & 0xffffffffu), (uint32_t)(b->seed >> 32), 0u};
@@ -877,16 +878,18 @@ int batch_graph_sweep(smc_batch* b, uint32_t n_sweeps, void* dev_obs) {
   const int8_t* J = (const int8_t*)b->J;
   uint32_t t0 = (uint32_t)b->t;
   void* obs = dev_obs;
-  void* args[] = {&descs, &order, &key, &spins, &J, &t0, &n_sweeps, &obs};
+  uint32_t nl = (uint32_t)b->n;
+  void* args[] = {&descs, &order, &key, &spins, &J, &t0, &n_sweeps, &every, &nl, &obs};
   hipKernelNodeParams kp;
   std::memset(&kp, 0, sizeof(kp));
   kp.func = const_cast<void*>(batch_kernel_fn(b->d, b->J_kind == SMC_J_PM, dev_obs != nullptr));
   kp.gridDim = dim3((unsigned)b->n);
   kp.blockDim = dim3(b->threads);
-  kp.sharedMemBytes = (unsigned)b->max_sites;
+  kp.sharedMemBytes = (unsigned)batch_lds_bytes(b->max_sites, b->threads);
   kp.kernelParams = args;
   kp.extra = nullptr;
   const bool same = b->exec && b->graph_n == (int64_t)n_sweeps && b->graph_obs == dev_obs &&
+                    b->graph_every == every &&
                     b->graph_threads == b->threads && b->graph_largest == b->largest_first;
   if (!same) {
     batch_drop_graph(b);
@@ -897,6 +900,7 @@ int batch_graph_sweep(smc_batch* b, uint32_t n_sweeps, void* dev_obs) {
     rc = check(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0), "graph instantiate");
     if (rc != SMC_OK) return rc;
     b->graph_n = n_sweeps;
+    b->graph_every = every;
     b->graph_obs = dev_obs;
     b->graph_threads = b->threads;
     b->graph_largest = b->largest_first;
@@ -999,6 +1003,7 @@ int smc_batch_init(smc_batch** out, int32_t d, int32_t J_kind, uint64_t seed, do
   b->exec = nullptr;
   b->node = nullptr;
   b->graph_n = -1;
+  b->graph_every = 0;
   b->graph_obs = nullptr;
   b->max_sites = 0;
   b->desc.resize(n);
@@ -1021,6 +1026,8 @@ int smc_batch_init(smc_batch** out, int32_t d, int32_t J_kind, uint64_t seed, do
     const IsingTable tab = make_table(d, J0, beta[r]);
     x.th_lo = tab.th_lo;
     x.th_hi = tab.th_hi;
+    x.al_lo = tab.al_lo;
+    x.al_hi = tab.al_hi;
     for (int k = 0; k < 7; ++k) x.frac[k] = tab.frac[k];
     x.spin_off_lo = (uint32_t)((uint64_t)b->soff[r] & 0xffffffffu);
     x.spin_off_hi = (uint32_t)((uint64_t)b->soff[r] >> 32);
@@ -1035,8 +1042,12 @@ int smc_batch_init(smc_batch** out, int32_t d, int32_t J_kind, uint64_t seed, do
                    [&](uint32_t a, uint32_t c) { return b->desc[a].Nh > b->desc[c].Nh; });
   b->orders = largest;
   b->orders.insert(b->orders.end(), idx.begin(), idx.end());
-  int rc = check(hipMemcpyAsync(b->desc_dev, b->desc.data(), sizeof(BatchDesc) * n,
-                                hipMemcpyHostToDevice, b->stream), "descriptor upload");
+  // the largest workgroup (512 lanes) with the largest lattice may pass the
+  // default 64 KiB of dynamic LDS
+  int rc = check(batch_allow_lds(batch_lds_bytes(b->max_sites, 512)), "batch LDS attribute");
+  if (rc == SMC_OK)
+    rc = check(hipMemcpyAsync(b->desc_dev, b->desc.data(), sizeof(BatchDesc) * n,
+                              hipMemcpyHostToDevice, b->stream), "descriptor upload");
   if (rc == SMC_OK)
     rc = check(hipMemcpyAsync(b->order_dev, b->orders.data(), sizeof(uint32_t) * 2 * n,
                               hipMemcpyHostToDevice, b->stream), "schedule upload");
@@ -1064,21 +1075,28 @@ int smc_batch_init(smc_batch** out, int32_t d, int32_t J_kind, uint64_t seed, do
   return SMC_OK;
 }
 
-int smc_batch_sweep(smc_batch* b, int64_t n_sweeps, void* dev_obs) {
+int smc_batch_sweep_series(smc_batch* b, int64_t n_sweeps, int64_t measure_every, void* dev_obs) {
   if (!b) return fail(SMC_EINVAL, "handle is NULL");
   if (n_sweeps < 0) return fail(SMC_EINVAL, "n_sweeps must be >= 0");
   if (dev_obs && ((uintptr_t)dev_obs & 7)) return fail(SMC_EINVAL, "dev_obs must be 8-byte aligned");
+  if (dev_obs && n_sweeps > 0 && (measure_every < 1 || n_sweeps % measure_every != 0))
+    return fail(SMC_EINVAL, "measure_every must be >= 1 and divide n_sweeps");
   if (b->t + (uint64_t)n_sweeps > 4294967296ull)
     return fail(SMC_ERANGE, "sweep counter would exceed 2^32");
   if (n_sweeps == 0 && !dev_obs) return SMC_OK;
+  const uint32_t every = dev_obs && n_sweeps > 0 ? (uint32_t)measure_every : 1u;
   int rc;
   if (b->use_graph)
-    rc = batch_graph_sweep(b, (uint32_t)n_sweeps, dev_obs);
+    rc = batch_graph_sweep(b, (uint32_t)n_sweeps, every, dev_obs);
   else
-    rc = batch_launch(b, (int8_t*)b->spins, (uint32_t)b->t, (uint32_t)n_sweeps, dev_obs, b->threads,
-                      b->largest_first);
+    rc = batch_launch(b, (int8_t*)b->spins, (uint32_t)b->t, (uint32_t)n_sweeps, every, dev_obs,
+                      b->threads, b->largest_first);
   if (rc == SMC_OK) b->t += (uint64_t)n_sweeps;
   return rc;
+}
+
+int smc_batch_sweep(smc_batch* b, int64_t n_sweeps, void* dev_obs) {
+  return smc_batch_sweep_series(b, n_sweeps, n_sweeps > 0 ? n_sweeps : 1, dev_obs);
 }
 
 int smc_batch_autotune(smc_batch* b, int32_t* threads_out, int32_t* largest_first_out) {
@@ -1099,10 +1117,10 @@ int smc_batch_autotune(smc_batch* b, int32_t* threads_out, int32_t* largest_firs
   for (int lf = 1; lf >= 0 && rc == SMC_OK; --lf) {
     for (int c = 0; c < 4 && rc == SMC_OK; ++c) {
       // the chain on the scratch copy is discarded: any counter will do
-      rc = batch_launch(b, (int8_t*)b->scratch, (uint32_t)b->t, 1, nullptr, cand[c], lf != 0);
+      rc = batch_launch(b, (int8_t*)b->scratch, (uint32_t)b->t, 1, 1, nullptr, cand[c], lf != 0);
       if (rc != SMC_OK) break;
       rc = check(hipEventRecord(e0, b->stream), "event record");
-      if (rc == SMC_OK) rc = batch_launch(b, (int8_t*)b->scratch, (uint32_t)b->t, 4, nullptr, cand[c], lf != 0);
+      if (rc == SMC_OK) rc = batch_launch(b, (int8_t*)b->scratch, (uint32_t)b->t, 4, 1, nullptr, cand[c], lf != 0);
       if (rc == SMC_OK) rc = check(hipEventRecord(e1, b->stream), "event record");
       if (rc == SMC_OK) rc = check(hipEventSynchronize(e1), "event synchronise");
       float ms = 0.0f;

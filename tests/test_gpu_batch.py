@@ -74,3 +74,41 @@ def test_batch_rejects_bad_shapes(smc_gpu):
         smc_gpu.Batch(3, [8, 42], [0.5, 0.5], seed=1)   # 42^3 > 65536 sites
     with pytest.raises(smc_gpu.SmcError):
         smc_gpu.Batch(3, [8, 9], [0.5, 0.5], seed=1)    # odd edge
+
+
+@pytest.mark.parametrize("d,kind,n,graph", [(3, 1, 10, False), (2, 0, 12, True), (3, 0, 5, True)])
+def test_batch_measurement_series_matches_oracle(smc_gpu, oracle_mod, d, kind, n, graph):
+    """E and M recorded inside one launch every `every` sweeps equal the
+    oracle's measurements of each lattice's chain at those sweeps."""
+    import torch
+    print(f"batch series d={d} kind={kind} n={n} graph={graph}", flush=True)
+    L, beta = _batch_params(d, n)
+    b = smc_gpu.Batch(d, L, beta, seed=41, J_kind=kind)
+    b.use_graph(graph)
+    every, sweeps = 3, 12
+    series = torch.zeros((sweeps // every, n, 8), dtype=torch.int64, device=b.device)
+    b.sweep(2)                                   # a counter offset before the series
+    b.sweep(sweeps, series, every=every)
+    assert b.t == 2 + sweeps
+    recs = [smc_gpu.Lattice.decode_obs(series[m]) for m in range(sweeps // every)]
+    for r in range(n):
+        ref = oracle_mod.OracleLattice(d, 1, L[r], 41, J_kind=kind, replica=r)
+        ref.sweep(beta[r], 2)
+        for m in range(sweeps // every):
+            ref.sweep(beta[r], every)
+            o = ref.measure()
+            got = recs[m][r]
+            assert (got.E_int, got.M_int, got.sweep) == (o.E_int, o.M_int, 2 + every * (m + 1)), (r, m)
+    _check(smc_gpu, oracle_mod, b, d, L, beta, kind, 2 + sweeps, 41)
+
+
+def test_batch_series_rejects_bad_every(smc_gpu):
+    import torch
+    L, beta = _batch_params(3, 3)
+    b = smc_gpu.Batch(3, L, beta, seed=1)
+    obs = torch.zeros((4, 3, 8), dtype=torch.int64, device=b.device)
+    with pytest.raises(smc_gpu.SmcError):
+        b.sweep(10, obs, every=3)   # 3 does not divide 10
+    with pytest.raises(smc_gpu.SmcError):
+        b.sweep(10, obs, every=0)
+    assert b.t == 0
