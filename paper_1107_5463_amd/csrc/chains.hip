@@ -31,29 +31,32 @@ __device__ __forceinline__ void neighbours32(uint32_t j, uint32_t c, const FastD
                                              const FastDiv& dL, uint32_t nb[6]) {
   const uint32_t R = dR.d, L = dL.d;
   const uint32_t r = fdiv(j, dR);
-  const uint32_t jx = j - r * R;
+  const uint32_t rowb = r * R;
+  const uint32_t jx = j - rowb;
   uint32_t y = r, z = 0;
   if (D == 3) {
     z = fdiv(r, dL);
     y = r - z * L;
   }
-  const uint32_t p = (c + y + z) & 1u;
-  const uint32_t rowb = r * R;
-  nb[0] = rowb + (jx + p == R ? 0u : jx + p);           // x + 1
-  nb[1] = rowb + (jx + p == 0 ? R - 1 : jx + p - 1);    // x - 1
-  const uint32_t yp = y + 1 == L ? 0u : y + 1, ym = y == 0 ? L - 1 : y - 1;
-  nb[2] = (z * L + yp) * R + jx;
-  nb[3] = (z * L + ym) * R + jx;
+  const uint32_t p = (c + r + z) & 1u;  // (c + y + z) & 1 with L even
+  // neighbour rows: the own row's offset plus or minus a row / plane stride,
+  // the periodic wrap as a select
+  const uint32_t sYw = (L - 1) * R, sZ = L * R, sZw = (L - 1) * L * R;
+  nb[0] = jx + p == R ? rowb : j + p;              // x + 1
+  nb[1] = jx + p == 0 ? rowb + R - 1 : j + p - 1;  // x - 1
+  nb[2] = y + 1 == L ? j - sYw : j + R;
+  nb[3] = y == 0 ? j + sYw : j - R;
   nb[4] = nb[5] = 0;
   if (D == 3) {
-    const uint32_t zp = z + 1 == L ? 0u : z + 1, zm = z == 0 ? L - 1 : z - 1;
-    nb[4] = (zp * L + y) * R + jx;
-    nb[5] = (zm * L + y) * R + jx;
+    nb[4] = z + 1 == L ? j - sZw : j + sZ;
+    nb[5] = z == 0 ? j + sZw : j - sZ;
   }
 }
 
-template <int D, int MODE>  // MODE 0: sample, 1: covariance, 2: sweeps only
-__global__ __launch_bounds__(256) void chains_kernel(const ChainsLaunch a, int8_t* __restrict__ spins,
+// JL: the couplings staged in LDS next to the chain (when they fit), else
+// read from global memory (L2-resident: all chains share them).
+template <int D, int MODE, bool JL>  // MODE 0: sample, 1: covariance, 2: sweeps only
+__global__ __launch_bounds__(512) void chains_kernel(const ChainsLaunch a, int8_t* __restrict__ spins,
                                                      const uint32_t t0, const uint32_t n_sweeps,
                                                      int64_t* __restrict__ bond_sum,
                                                      const double* __restrict__ gvec,
@@ -74,12 +77,16 @@ __global__ __launch_bounds__(256) void chains_kernel(const ChainsLaunch a, int8_
   double* red = reinterpret_cast<double*>(smem);
   int32_t* acc_i = reinterpret_cast<int32_t*>(smem + 16 * sizeof(double));
   double* acc_d = reinterpret_cast<double*>(smem + 16 * sizeof(double));
-  int8_t* lat = reinterpret_cast<int8_t*>(smem + 16 * sizeof(double) + (size_t)nb * kAcc);
-  const float* J = a.J;
+  float* Jl = reinterpret_cast<float*>(smem + 16 * sizeof(double) + (size_t)nb * kAcc);
+  int8_t* lat = reinterpret_cast<int8_t*>(smem + 16 * sizeof(double) + (size_t)nb * kAcc +
+                                          (JL ? (size_t)nb * 4 : 0));
+  const float* J = JL ? Jl : a.J;
   const float beta = a.beta;
 
   for (uint32_t w = threadIdx.x; w < N / 4; w += blockDim.x)
     reinterpret_cast<uint32_t*>(lat)[w] = reinterpret_cast<const uint32_t*>(gs)[w];
+  if (JL)
+    for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) Jl[b] = a.J[b];
   for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) {
     if (MODE == 0) acc_i[b] = 0;
     if (MODE == 1) acc_d[b] = 0.0;
@@ -215,18 +222,37 @@ size_t chains_lds_bytes(const Geom& g, int mode) {
   return 16 * sizeof(double) + (size_t)g.d * N * (mode == 1 ? 8 : 4) + N;
 }
 
-static const void* chains_fn(int d, int mode) {
-  if (d == 2)
-    return mode == 0 ? (const void*)chains_kernel<2, 0>
-                     : (mode == 1 ? (const void*)chains_kernel<2, 1> : (const void*)chains_kernel<2, 2>);
-  return mode == 0 ? (const void*)chains_kernel<3, 0>
-                   : (mode == 1 ? (const void*)chains_kernel<3, 1> : (const void*)chains_kernel<3, 2>);
+constexpr size_t kLdsMax = 160 * 1024;
+
+// The same with the couplings staged in LDS, if that fits (else 0).
+static size_t chains_lds_bytes_jl(const Geom& g, int mode) {
+  const size_t b = chains_lds_bytes(g, mode) + (size_t)g.d * 2 * (size_t)g.Nh * 4;
+  return b <= kLdsMax ? b : 0;
 }
 
-hipError_t chains_allow_lds(int d, size_t bytes) {
+// Workgroup size: one lane per group of four sites of a colour, in whole
+// waves, at most 512.
+static uint32_t chains_threads(const Geom& g) {
+  const uint32_t groups = (uint32_t)(g.Nh / 4);
+  const uint32_t t = (groups + 63) / 64 * 64;
+  return t < 64 ? 64 : (t > 512 ? 512 : t);
+}
+
+static const void* chains_fn(int d, int mode, bool jl) {
+#define SMC_CF(DD, JJ) \
+  (mode == 0 ? (const void*)chains_kernel<DD, 0, JJ> \
+             : (mode == 1 ? (const void*)chains_kernel<DD, 1, JJ> : (const void*)chains_kernel<DD, 2, JJ>))
+  if (d == 2) return jl ? SMC_CF(2, true) : SMC_CF(2, false);
+  return jl ? SMC_CF(3, true) : SMC_CF(3, false);
+#undef SMC_CF
+}
+
+hipError_t chains_allow_lds(const Geom& g) {
   for (int mode = 0; mode < 3; ++mode) {
-    const hipError_t e = hipFuncSetAttribute(chains_fn(d, mode),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const size_t ljl = chains_lds_bytes_jl(g, mode);
+    const size_t b = ljl ? ljl : chains_lds_bytes(g, mode);
+    const hipError_t e = hipFuncSetAttribute(chains_fn(g.d, mode, ljl != 0),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -234,23 +260,22 @@ hipError_t chains_allow_lds(int d, size_t bytes) {
 
 hipError_t launch_chains_sample(const ChainsLaunch& a, int8_t* spins, uint32_t t0,
                                 uint32_t n_sweeps, int64_t* bond_sum, hipStream_t st) {
-  const dim3 grid(a.n_chains), block(256);
-  const size_t lds = chains_lds_bytes(a.g, 0);
+  const int mode = bond_sum ? 0 : 2;
+  const size_t ljl = chains_lds_bytes_jl(a.g, mode);
+  const bool jl = ljl != 0;
+  const size_t lds = jl ? ljl : chains_lds_bytes(a.g, mode);
+  const dim3 grid(a.n_chains), block(chains_threads(a.g));
+#define SMC_CS(DD, MM, JJ)                                                                     \
+  hipLaunchKernelGGL((chains_kernel<DD, MM, JJ>), grid, block, lds, st, a, spins, t0, n_sweeps, \
+                     bond_sum, nullptr, 0.0, nullptr, nullptr)
   if (a.g.d == 2) {
-    if (bond_sum)
-      hipLaunchKernelGGL((chains_kernel<2, 0>), grid, block, lds, st, a, spins, t0, n_sweeps,
-                         bond_sum, nullptr, 0.0, nullptr, nullptr);
-    else
-      hipLaunchKernelGGL((chains_kernel<2, 2>), grid, block, lds, st, a, spins, t0, n_sweeps,
-                         nullptr, nullptr, 0.0, nullptr, nullptr);
+    if (mode == 0) { if (jl) SMC_CS(2, 0, true); else SMC_CS(2, 0, false); }
+    else { if (jl) SMC_CS(2, 2, true); else SMC_CS(2, 2, false); }
   } else {
-    if (bond_sum)
-      hipLaunchKernelGGL((chains_kernel<3, 0>), grid, block, lds, st, a, spins, t0, n_sweeps,
-                         bond_sum, nullptr, 0.0, nullptr, nullptr);
-    else
-      hipLaunchKernelGGL((chains_kernel<3, 2>), grid, block, lds, st, a, spins, t0, n_sweeps,
-                         nullptr, nullptr, 0.0, nullptr, nullptr);
+    if (mode == 0) { if (jl) SMC_CS(3, 0, true); else SMC_CS(3, 0, false); }
+    else { if (jl) SMC_CS(3, 2, true); else SMC_CS(3, 2, false); }
   }
+#undef SMC_CS
   return hipGetLastError();
 }
 
@@ -258,14 +283,19 @@ hipError_t launch_chains_covariance(const ChainsLaunch& a, int8_t* spins, uint32
                                     uint32_t n_sweeps, const double* g, double gc, double* part,
                                     double* gpart, double* cov_acc, double* G_acc,
                                     hipStream_t st) {
-  const dim3 grid(a.n_chains), block(256);
-  const size_t lds = chains_lds_bytes(a.g, 1);
-  if (a.g.d == 2)
-    hipLaunchKernelGGL((chains_kernel<2, 1>), grid, block, lds, st, a, spins, t0, n_sweeps,
-                       nullptr, g, gc, part, gpart);
-  else
-    hipLaunchKernelGGL((chains_kernel<3, 1>), grid, block, lds, st, a, spins, t0, n_sweeps,
-                       nullptr, g, gc, part, gpart);
+  const size_t ljl = chains_lds_bytes_jl(a.g, 1);
+  const bool jl = ljl != 0;
+  const size_t lds = jl ? ljl : chains_lds_bytes(a.g, 1);
+  const dim3 grid(a.n_chains), block(chains_threads(a.g));
+#define SMC_CC(DD, JJ)                                                                         \
+  hipLaunchKernelGGL((chains_kernel<DD, 1, JJ>), grid, block, lds, st, a, spins, t0, n_sweeps, \
+                     nullptr, g, gc, part, gpart)
+  if (a.g.d == 2) {
+    if (jl) SMC_CC(2, true); else SMC_CC(2, false);
+  } else {
+    if (jl) SMC_CC(3, true); else SMC_CC(3, false);
+  }
+#undef SMC_CC
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const uint32_t nb = (uint32_t)(a.g.d * 2 * a.g.Nh);

@@ -166,7 +166,8 @@ struct ChainsLaunch {
   FastDiv divR, divL;  // plane row length L/2, edge L
 };
 size_t chains_lds_bytes(const Geom& g, int mode);
-hipError_t chains_allow_lds(int d, size_t bytes);
+// Raise the dynamic-LDS limit of the chain kernels for lattice g.
+hipError_t chains_allow_lds(const Geom& g);
 hipError_t launch_chains_sample(const ChainsLaunch& a, int8_t* spins, uint32_t t0,
                                 uint32_t n_sweeps, int64_t* bond_sum, hipStream_t st);
 hipError_t launch_chains_covariance(const ChainsLaunch& a, int8_t* spins, uint32_t t0,

@@ -1288,7 +1288,7 @@ int smc_chains_init(smc_chains** out, int32_t d, int32_t L, int32_t n_chains, ui
                        round_up((size_t)n_chains * chains_sites(d, L) * d * sizeof(double), kAlign));
   h->stream = (hipStream_t)stream;
   h->t = 0;
-  int rc = check(chains_allow_lds(d, chains_lds_bytes(h->g, 1)), "chains LDS attribute");
+  int rc = check(chains_allow_lds(h->g), "chains LDS attribute");
   const size_t N = chains_sites(d, L);
   for (int32_t k = 0; rc == SMC_OK && init != SMC_INIT_KEEP && k < n_chains; ++k) {
     const RngKey key{h->key.k0, h->key.k1, replica0 + (uint32_t)k};

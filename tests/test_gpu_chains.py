@@ -81,7 +81,10 @@ def test_chain_equals_single_lattice_chain(smc_gpu, oracle_mod):
         assert torch.equal(lat.spins.view(-1).cpu(), ch.spins[k].view(-1).cpu()), k
 
 
-@pytest.mark.parametrize("d,L,nch,nsw,beta,seed", [(2, 8, 6, 40, 0.45, 3), (3, 4, 5, 30, 0.25, 4)])
+# the last two: couplings too large to share LDS with the covariance
+# accumulators, so the covariance pass reads them from global memory
+@pytest.mark.parametrize("d,L,nch,nsw,beta,seed", [(2, 8, 6, 40, 0.45, 3), (3, 4, 5, 30, 0.25, 4),
+                                                   (2, 84, 2, 4, 0.4, 9), (3, 18, 2, 3, 0.25, 11)])
 def test_covariance_replay_matches_oracle(smc_gpu, oracle_mod, d, L, nch, nsw, beta, seed):
     import torch
     rng = np.random.default_rng(seed + 50)
