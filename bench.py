@@ -66,6 +66,8 @@ KERNEL_SOURCES = {
     "ising_tiles": ["tiles.hip", "chunk.hpp", "device.hpp", "kernels.hpp"],
     "xy_stream": ["continuous.hip", "chunk.hpp", "device.hpp", "kernels.hpp"],
     "heisenberg_stream": ["continuous.hip", "chunk.hpp", "device.hpp", "kernels.hpp"],
+    "batch": ["batch.hip", "chunk.hpp", "device.hpp", "kernels.hpp", "reduce.hpp"],
+    "chains": ["chains.hip", "chunk.hpp", "device.hpp", "kernels.hpp"],
 }
 
 
@@ -415,17 +417,9 @@ def run_batched(args, wl, torch, smc):
                   "sample": f"{len(plain_lats)} of the lattices, one single-lattice sweep call "
                             f"each, {ps} sweeps"},
         "batched_vs_plain": round(value / plain_value, 1),
-        "roofline": {
-            "bound": "alu",
-            "achieved": None,
-            "peak": round(VALU_PEAK_TOPS, 2),
-            "unit": "Tops/s",
-            "frac": None,
-            "traffic": None,
-            "kernel": "batch",
-            "kernel_avg_us": round(total_ms * 1e3 / max(K, 1), 3),
-            "hbm_bytes_per_launch": 2 * cbytes,
-        },
+        # spins and couplings cross HBM once per launch (staged in LDS for all
+        # sweeps): VALU-bound
+        "roofline": valu_roofline("batch", "batched", total_ms / max(K, 1), 2 * cbytes),
         "wall_s": round(wall, 3),
     }
     if args.cpu_seconds > 0:
@@ -525,16 +519,9 @@ def run_chains(args, wl, torch, smc):
         },
         "backward": {"value": round(attempts / (bwd_ms * 1e6), 2), "unit": "attempts/ns",
                      "ms": round(bwd_ms, 3)},
-        "roofline": {
-            "bound": "alu",
-            "achieved": None,
-            "peak": round(VALU_PEAK_TOPS, 2),
-            "unit": "Tops/s",
-            "frac": None,
-            "traffic": None,
-            "kernel": "chains",
-            "kernel_avg_us": round(fwd_ms * 1e3 / max(K, 1), 3),
-        },
+        # each launch (S sweeps) reads and writes every chain's spins once and
+        # stages the shared couplings from L2: VALU / LDS-bound
+        "roofline": valu_roofline("chains", "chains", fwd_ms / max(K, 1), 2 * nch * N),
     }
     if args.cpu_seconds > 0:
         sys.path.insert(0, ROOT)
