@@ -11,10 +11,12 @@
 // the Philox counter, so chain k reproduces the single-lattice chain with FP32
 // couplings and that replica bit for bit (same site rule: local field summed
 // in FP32 over +x, -x, +y, -y, +z, -z; accept iff dE <= 0 or
-// u < exp(-beta dE) with word j & 3 of block j >> 2).  A lane handles groups
-// of 4 consecutive same-colour sites (one Philox block each) and always the
-// same groups, so the bonds of its colour-0 sites (every bond has exactly one
-// colour-0 end) are its own accumulator entries.
+// u < exp(-beta dE) with word j & 3 of block j >> 2).  A lane handles pairs
+// of consecutive same-colour sites (half of a four-site Philox block, which
+// both lanes of the block draw: twice the lanes of one block per lane, for a
+// latency-bound kernel) and always the same pairs, so the bonds of its
+// colour-0 sites (every bond has exactly one colour-0 end) are its own
+// accumulator entries.
 //
 // The covariance pass replays the sampling sweeps: with the same start state
 // and counters it visits exactly the same configurations, and needs no stored
@@ -23,6 +25,8 @@
 #include "chunk.hpp"
 
 namespace smc {
+
+constexpr size_t kRed = 32;  // doubles of reduction scratch (one per wave + the total)
 
 // In-plane indices of the 2d neighbours (+x, -x, +y, -y, +z, -z) of site
 // (c, j) of the other colour's plane, in 32-bit arithmetic.
@@ -56,7 +60,7 @@ __device__ __forceinline__ void neighbours32(uint32_t j, uint32_t c, const FastD
 // JL: the couplings staged in LDS next to the chain (when they fit), else
 // read from global memory (L2-resident: all chains share them).
 template <int D, int MODE, bool JL>  // MODE 0: sample, 1: covariance, 2: sweeps only
-__global__ __launch_bounds__(512) void chains_kernel(const ChainsLaunch a, int8_t* __restrict__ spins,
+__global__ __launch_bounds__(1024) void chains_kernel(const ChainsLaunch a, int8_t* __restrict__ spins,
                                                      const uint32_t t0, const uint32_t n_sweeps,
                                                      int64_t* __restrict__ bond_sum,
                                                      const double* __restrict__ gvec,
@@ -71,14 +75,14 @@ __global__ __launch_bounds__(512) void chains_kernel(const ChainsLaunch a, int8_
   const uint32_t chain = blockIdx.x;
   const uint32_t replica = a.key.replica + chain;
   int8_t* gs = spins + (uint64_t)chain * N;
-  // LDS: 16 doubles of reduction scratch, the accumulator (4 or 8 bytes per
-  // bond), then both colour planes
+  // LDS: kRed doubles of reduction scratch, the accumulator (4 or 8 bytes per
+  // bond), the couplings (JL), then both colour planes
   constexpr size_t kAcc = MODE == 1 ? 8 : 4;  // bytes per bond (chains_lds_bytes)
   double* red = reinterpret_cast<double*>(smem);
-  int32_t* acc_i = reinterpret_cast<int32_t*>(smem + 16 * sizeof(double));
-  double* acc_d = reinterpret_cast<double*>(smem + 16 * sizeof(double));
-  float* Jl = reinterpret_cast<float*>(smem + 16 * sizeof(double) + (size_t)nb * kAcc);
-  int8_t* lat = reinterpret_cast<int8_t*>(smem + 16 * sizeof(double) + (size_t)nb * kAcc +
+  int32_t* acc_i = reinterpret_cast<int32_t*>(smem + kRed * sizeof(double));
+  double* acc_d = reinterpret_cast<double*>(smem + kRed * sizeof(double));
+  float* Jl = reinterpret_cast<float*>(smem + kRed * sizeof(double) + (size_t)nb * kAcc);
+  int8_t* lat = reinterpret_cast<int8_t*>(smem + kRed * sizeof(double) + (size_t)nb * kAcc +
                                           (JL ? (size_t)nb * 4 : 0));
   const float* J = JL ? Jl : a.J;
   const float beta = a.beta;
@@ -93,18 +97,18 @@ __global__ __launch_bounds__(512) void chains_kernel(const ChainsLaunch a, int8_
   }
   __syncthreads();
 
-  const uint32_t groups = (uint32_t)Nh / 4;
+  const uint32_t pairs = (uint32_t)Nh / 2;
   double Gsum = 0.0, G2sum = 0.0;
   for (uint32_t sw = 0; sw < n_sweeps; ++sw) {
     const uint32_t t = t0 + sw;
     for (uint32_t c = 0; c < 2; ++c) {
       int8_t* own = lat + c * Nh;
       const int8_t* oth = lat + (1 - c) * Nh;
-      for (uint32_t gi = threadIdx.x; gi < groups; gi += blockDim.x) {
-        const Rand4 r = philox(gi, t, replica, tag(c, kContinuous), a.key.k0, a.key.k1);
+      for (uint32_t pi = threadIdx.x; pi < pairs; pi += blockDim.x) {
+        const Rand4 r = philox(pi >> 1, t, replica, tag(c, kContinuous), a.key.k0, a.key.k1);
 #pragma unroll
-        for (uint32_t b = 0; b < 4; ++b) {
-          const uint32_t j = 4 * gi + b;
+        for (uint32_t b = 0; b < 2; ++b) {
+          const uint32_t j = 2 * pi + b;
           uint32_t nb[6];
           neighbours32<D>(j, c, a.divR, a.divL, nb);
           const int si = own[j];
@@ -117,7 +121,7 @@ __global__ __launch_bounds__(512) void chains_kernel(const ChainsLaunch a, int8_
             h += jm * (float)oth[nb[2 * mu + 1]];
           }
           const float dE = 2.0f * (float)si * h;
-          const bool accept = dE <= 0.0f || u01f(r.w[b]) < expf(-beta * dE);
+          const bool accept = dE <= 0.0f || u01f(word_of(r.w, j & 3u)) < expf(-beta * dE);
           if (accept) own[j] = (int8_t)(-si);
         }
       }
@@ -129,10 +133,10 @@ __global__ __launch_bounds__(512) void chains_kernel(const ChainsLaunch a, int8_
     for (int pass = 0; pass < (MODE == 0 ? 1 : 2); ++pass) {
       double Gc = 0.0;
       if (MODE == 1 && pass == 1) Gc = red[0] - gc;
-      for (uint32_t gi = threadIdx.x; gi < groups; gi += blockDim.x) {
+      for (uint32_t pi = threadIdx.x; pi < pairs; pi += blockDim.x) {
 #pragma unroll
-        for (uint32_t b = 0; b < 4; ++b) {
-          const uint32_t j = 4 * gi + b;
+        for (uint32_t b = 0; b < 2; ++b) {
+          const uint32_t j = 2 * pi + b;
           uint32_t nb[6];
           neighbours32<D>(j, 0u, a.divR, a.divL, nb);
           const int s0 = lat[j];
@@ -219,7 +223,7 @@ __global__ __launch_bounds__(256) void chains_reduce_kernel(const double* __rest
 // sampling or sweeping only, double for the covariance), both planes.
 size_t chains_lds_bytes(const Geom& g, int mode) {
   const size_t N = 2 * (size_t)g.Nh;
-  return 16 * sizeof(double) + (size_t)g.d * N * (mode == 1 ? 8 : 4) + N;
+  return kRed * sizeof(double) + (size_t)g.d * N * (mode == 1 ? 8 : 4) + N;
 }
 
 constexpr size_t kLdsMax = 160 * 1024;
@@ -230,12 +234,12 @@ static size_t chains_lds_bytes_jl(const Geom& g, int mode) {
   return b <= kLdsMax ? b : 0;
 }
 
-// Workgroup size: one lane per group of four sites of a colour, in whole
-// waves, at most 512.
+// Workgroup size: one lane per pair of sites of a colour, in whole waves,
+// at most 1024.
 static uint32_t chains_threads(const Geom& g) {
-  const uint32_t groups = (uint32_t)(g.Nh / 4);
-  const uint32_t t = (groups + 63) / 64 * 64;
-  return t < 64 ? 64 : (t > 512 ? 512 : t);
+  const uint32_t pairs = (uint32_t)(g.Nh / 2);
+  const uint32_t t = (pairs + 63) / 64 * 64;
+  return t < 64 ? 64 : (t > 1024 ? 1024 : t);
 }
 
 static const void* chains_fn(int d, int mode, bool jl) {
