@@ -160,8 +160,11 @@ template <bool FAST>
 __device__ __forceinline__ bool heis_update(float sv[3], const float h[3], const uint32_t w0,
                                             const uint32_t w1, const uint32_t w2,
                                             const float beta, const float omc) {
-  const float ca = 1.0f - u01f(w1) * omc;
-  const float sa = sqrtf(fmaxf(0.0f, 1.0f - ca * ca));
+  // sin alpha from 1 - cos alpha directly: (1 - c)(1 + c) keeps its relative
+  // precision for small caps, where 1 - c^2 would cancel
+  const float omca = u01f(w1) * omc;
+  const float ca = 1.0f - omca;
+  const float sa = sqrtf(omca * (2.0f - omca));
   // frame axis: smallest |s_k|, lowest k on ties
   const float a0 = fabsf(sv[0]), a1 = fabsf(sv[1]), a2 = fabsf(sv[2]);
   int k = 0;

@@ -99,6 +99,40 @@ def test_stream_kernel_protocol(smc_gpu, oracle_mod, d, n, L, beta, delta, kind,
     assert lat.kernel()[1] == rows
 
 
+@pytest.mark.parametrize("d,n,L,beta,delta,seed", [(2, 2, 4096, 1.12, 1.63, 5),
+                                                   (3, 3, 256, 0.693, 2.058, 6)])
+def test_full_size_half_sweeps(smc_gpu, oracle_mod, d, n, L, beta, delta, seed, monkeypatch):
+    """The throughput sizes (XY L=4096, Heisenberg L=256) in the launch
+    configuration the benchmark times (default kernel and band height): both
+    half-sweeps of a late sweep from the seeded start, by the protocol."""
+    import torch
+    monkeypatch.delenv("SMC_CONT_KERNEL", raising=False)
+    monkeypatch.delenv("SMC_CONT_ROWS", raising=False)
+    print(f"full-size continuous d={d} n={n} L={L}", flush=True)
+    ref = oracle_mod.OracleLattice(d, n, L, seed, delta=delta, renorm_every=0)
+    ref.s = ref.s.astype(np.float32).astype(np.float64)
+    lat = upload(smc_gpu, ref)
+    assert lat.kernel()[0].endswith("_stream")
+    t = 777
+    near = 0
+    for c in (0, 1):
+        s0 = ref.s.copy()
+        lat.spins.copy_(torch.from_numpy(layout.to_split(s0.astype(np.float32), d, L)))
+        lat.t = t
+        lat.half_sweep(beta, c)
+        _, margin = ref.half_sweep(beta, c, t, want_margin=True)
+        g = nat(lat)
+        moved_g = np.any(g != s0, axis=0)
+        moved_o = np.any(ref.s != s0, axis=0)
+        clear = ~(np.abs(margin) < BAND)
+        assert np.array_equal(moved_g[clear], moved_o[clear]), c
+        both = moved_g & moved_o
+        assert np.abs(g[:, both] - ref.s[:, both]).max(initial=0.0) <= TOL
+        near += int(np.sum(np.abs(margin) < BAND))
+        ref.s = ref.s.astype(np.float32).astype(np.float64)
+    print(f"near-threshold sites (|u-p| < {BAND}): {near} of {L ** d}")
+
+
 def _protocol(smc_gpu, oracle_mod, d, n, L, beta, delta, kind, fast, kernel):
     import torch
     print(f"half-sweep protocol d={d} n={n} L={L} kind={kind} fast={fast} kernel={kernel}",

@@ -117,6 +117,18 @@ def test_full_size_2d_matches_oracle(smc_gpu, oracle_mod):
     assert np.array_equal(nat(smc_gpu, lat), ref.s)
 
 
+def test_full_size_3d_matches_oracle(smc_gpu, oracle_mod):
+    L = 512
+    print("packed full size 3D L=512, 2 sweeps", flush=True)
+    lat = smc_gpu.Lattice(3, 1, L, seed=3, packed=True)
+    ref = oracle_mod.OracleLattice(3, 1, L, 3)
+    lat.sweep(0.2216546, 2)
+    ref.sweep(0.2216546, 2)
+    o, r = lat.measure(), ref.measure()
+    assert (o.E_int, o.M_int) == (r.E_int, r.M_int)
+    assert np.array_equal(nat(smc_gpu, lat), ref.s)
+
+
 def test_packed_and_int8_chains_agree(smc_gpu):
     import torch
     a = smc_gpu.Lattice(3, 1, 128, seed=12, J_kind=1, packed=True)
