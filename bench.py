@@ -124,6 +124,20 @@ def measured_traffic(kernel, workload):
     return rec.get("hbm_bytes_per_launch")
 
 
+def host_cpu():
+    """CPU model and processor count of the host the oracle ran on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "nproc": os.cpu_count()}
+
+
 def copy_probe(torch, device):
     n = 1 << 30
     a = torch.empty(n, dtype=torch.uint8, device=device).fill_(1)
@@ -328,14 +342,28 @@ def run_lattice(args, wl, torch, smc):
             # decisions); report the relative energy difference instead
             parity = round(abs(go.E - ro.E) / max(1.0, abs(ro.E)), 6)
             pname = "rel_E_diff_after_sample"
+        cores = oracle.num_threads()
+        # the same oracle on one core (at least one sweep, about a third of
+        # the time budget), then all cores again
+        oracle.set_num_threads(1)
+        ref1 = oracle.OracleLattice(d, n, L, wl["seed"], **kwo)
+        if n == 1 and (args.tile or args.heatbath):
+            one1 = lambda: ref1.sweep_rule(beta, 1, rule, args.tile, args.hits if args.tile else 1)
+        else:
+            one1 = lambda: ref1.sweep(beta, 1)
+        rate1, calls1, el1 = oracle_rate(one1, N * hits, args.cpu_seconds / 3)
+        oracle.set_num_threads(cores)
         result["cpu_baseline"] = {
             "value": round(rate, 4),
             "unit": "attempts/ns",
-            "cores": oracle.num_threads(),
+            "cores": cores,
             "kind": "oracle",
             "sample": f"first {calls} sweeps of the same {d}D L={L} lattice from the same start "
                       f"({N * calls * hits} attempts, {el:.1f} s)",
             pname: parity,
+            "single_core": {"value": round(rate1, 4), "unit": "attempts/ns", "cores": 1,
+                            "sample": f"first {calls1} sweeps ({el1:.1f} s)"},
+            "host": host_cpu(),
         }
     return result
 

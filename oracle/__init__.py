@@ -114,6 +114,14 @@ def num_threads() -> int:
     return int(lib().oracle_num_threads())
 
 
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops (n <= 0: one per processor)."""
+    f = lib().oracle_set_num_threads
+    f.argtypes = [C.c_int]
+    f.restype = None
+    f(int(n))
+
+
 @dataclasses.dataclass
 class Obs:
     E_int: int

@@ -812,3 +812,13 @@ ORACLE_API int oracle_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Threads of the OpenMP loops (n <= 0: one per processor); for timing the
+ * oracle on one core and on all of them. */
+ORACLE_API void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : omp_get_num_procs());
+#else
+  (void)n;
+#endif
+}
