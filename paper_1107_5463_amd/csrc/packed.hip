@@ -17,10 +17,10 @@
 //    k0, k1, k2 for 32 sites at once (full adders as v_bitop3);
 //  * the same two Philox blocks as the int8 path give the 32 prefix bytes,
 //    transposed into 8 bit planes (four 8x8 bit transposes by delta swaps and
-//    a byte regroup with v_perm); for each class k whose move can be refused
-//    (at most d of the 2d + 1) a bit-sliced compare with the class's
-//    threshold byte gives the refused sites and the exact ties, applied to
-//    the sites of that class (a bit-sliced equality on k);
+//    a byte regroup with v_perm); the threshold bytes of the sites' classes
+//    (those whose move can be refused: at most d of the 2d + 1) are laid out
+//    as 8 bit planes too, and one bit-sliced compare against them gives the
+//    refused sites and the exact ties;
 //  * exact ties (prefix byte == threshold byte, 2^-8 of refusable moves) are
 //    queued in LDS and resolved at the end of the band with each site's
 //    24-bit refinement draw, as in the int8 kernel.
@@ -91,23 +91,6 @@ __device__ __forceinline__ void prefix_planes(const uint32_t P[8], uint32_t B[8]
   B[7] = __builtin_amdgcn_perm(c3, a3, 0x07060302u);
 }
 
-// Bit-sliced unsigned compare of the 32 prefix bytes with the threshold byte
-// th (wave-uniform), most significant bit first: eq tracks "equal so far",
-// and a bit where the threshold has 1 and the prefix 0 decides "below".
-// Branch-free, with the threshold bits as scalar all-ones/zero masks.
-__device__ __forceinline__ void planes_compare(const uint32_t B[8], uint32_t th, uint32_t& ge,
-                                               uint32_t& eq) {
-  uint32_t lt[8];
-  eq = ~0u;
-#pragma unroll
-  for (int b = 7; b >= 0; --b) {
-    const uint32_t tb = __builtin_amdgcn_readfirstlane(0u - ((th >> b) & 1u));
-    lt[b] = eq & ~B[b] & tb;   // first difference here, prefix bit 0 < threshold bit 1
-    eq = eq & ~(B[b] ^ tb);    // still equal
-  }
-  ge = ~((lt[0] | lt[1] | lt[2]) | (lt[3] | lt[4] | lt[5]) | (lt[6] | lt[7]));
-}
-
 // Per-lane tie queue entries: site (5 bits), row in band (6), class (3),
 // spin was -1 (1).
 struct PackedTies {
@@ -150,29 +133,37 @@ __device__ __forceinline__ uint32_t packed_decide(const TabRegs& tab, const RngK
   const uint32_t P[8] = {ra.w[0], ra.w[1], ra.w[2], ra.w[3], rb.w[0], rb.w[1], rb.w[2], rb.w[3]};
   uint32_t B[8];
   prefix_planes(P, B);
-  uint32_t rej = 0, ties = 0, tk0 = 0, tk1 = 0, tk2 = 0;
-  // refusable classes (wave-uniform branches on the table)
+  // Per-site threshold bit planes: T[b] holds bit b of the threshold byte of
+  // each site's class (refusable classes only; wave-uniform branches on the
+  // table), then one bit-sliced compare of the prefix planes against them.
+  uint32_t T[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+  uint32_t refus = 0;
 #define SMC_CLASS(KV)                                                              \
   if (KV <= 2 * D && table_byte(tab.al_lo, tab.al_hi, KV) == 0u) {                 \
     const uint32_t m = class_mask<KV>(k0, k1, k2);                                 \
-    uint32_t ge, eq;                                                               \
-    planes_compare(B, table_byte(tab.th_lo, tab.th_hi, KV), ge, eq);              \
-    rej |= m & ge;                                                                 \
-    const uint32_t tm = m & eq;                                                    \
-    ties |= tm;                                                                    \
-    if (KV & 1) tk0 |= tm;                                                         \
-    if (KV & 2) tk1 |= tm;                                                         \
-    if (KV & 4) tk2 |= tm;                                                         \
+    const uint32_t th = table_byte(tab.th_lo, tab.th_hi, KV);                      \
+    refus |= m;                                                                    \
+    _Pragma("unroll") for (int b = 0; b < 8; ++b)                                  \
+      T[b] |= m & __builtin_amdgcn_readfirstlane(0u - ((th >> b) & 1u));           \
   }
   SMC_CLASS(0) SMC_CLASS(1) SMC_CLASS(2) SMC_CLASS(3) SMC_CLASS(4) SMC_CLASS(5) SMC_CLASS(6)
 #undef SMC_CLASS
+  // most significant bit first: eq = equal so far, lt = prefix below threshold
+  uint32_t eq = ~0u, lt = 0u;
+#pragma unroll
+  for (int b = 7; b >= 0; --b) {
+    lt |= eq & ~B[b] & T[b];
+    eq &= ~(B[b] ^ T[b]);
+  }
+  const uint32_t rej = refus & ~lt;  // prefix >= threshold (ties included)
+  const uint32_t ties = refus & eq;
   if (ties) {
     uint32_t m = ties;
     do {
       if (q.n == kTieSlots) packed_tie_flush<D>(q, tab, key, t, c, own);
       const uint32_t b = __builtin_ctz(m);
       m &= m - 1;
-      const uint32_t k = ((tk0 >> b) & 1u) | (((tk1 >> b) & 1u) << 1) | (((tk2 >> b) & 1u) << 2);
+      const uint32_t k = ((k0 >> b) & 1u) | (((k1 >> b) & 1u) << 1) | (((k2 >> b) & 1u) << 2);
       const uint32_t neg = (o >> b) & 1u;
       q.slot[q.n * q.stride] = (uint16_t)(b | (row << 5) | (k << 11) | (neg << 14));
       q.n += 1;
