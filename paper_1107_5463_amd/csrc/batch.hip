@@ -13,13 +13,16 @@
 // same-colour sites (one Philox block of prefix bytes per group); the
 // decision per site is the integer threshold test of the single-lattice
 // kernels with its exact tie refinement.  Lattices whose plane rows are whole
-// 4-site words (L/2 % 4 == 0) take the decision four sites per 32-bit op:
+// 4-site words (L/2 % 4 == 0) take the decision four sites per 32-bit op
+// (rows of whole 2-site pairs, L/2 even, two sites per op):
 // neighbour words from LDS (the in-row neighbours as the centre word shifted
 // by one byte), unsatisfied-bond counts per byte, and the byte-wise threshold
 // compare of the single-lattice kernels.  With MEASURE the workgroup also
 // reduces E and M of its state from LDS after every `every` sweeps (record m
 // of the call at obs[m * n_lattices + lattice]; with no sweeps, one record of
 // the current state).
+#include <type_traits>
+
 #include "chunk.hpp"
 #include "reduce.hpp"
 
@@ -124,28 +127,42 @@ __global__ __launch_bounds__(512) void batch_kernel(const BatchDesc* __restrict_
     return *reinterpret_cast<const uint32_t*>(base + i);
   };
   // unsatisfied-bond counts (byte b: site j + b) of a 4-site word of plane c
-  auto counts4 = [&](const int8_t* own, const int8_t* oth, uint32_t c, uint32_t j,
-                     uint32_t& W) -> uint32_t {
+  // Unsatisfied-bond counts (byte b: site j + b) of a WB-site word of plane c
+  // (WB = 4: j % 4 == 0 and R % 4 == 0; WB = 2: j even and R even; the word
+  // lies in one plane row).  The in-row neighbours are the centre word
+  // shifted by one byte with the adjacent word's edge byte.
+  auto counts = [&](auto wb, const int8_t* own, const int8_t* oth, uint32_t c, uint32_t j,
+                    uint32_t& W) -> uint32_t {
+    constexpr uint32_t WB = decltype(wb)::value;
+    auto ldw = [&](const int8_t* base, uint32_t i) -> uint32_t {
+      if constexpr (WB == 4) return *reinterpret_cast<const uint32_t*>(base + i);
+      else return *reinterpret_cast<const uint16_t*>(base + i);
+    };
     const uint32_t r = fdiv(j, divR);
     const uint32_t rowb = r * R;
     const uint32_t jx = j - rowb;
     const uint32_t z = D == 3 ? fdiv(r, divL) : 0u;
     const uint32_t y = r - z * L;
     const uint32_t p = (c + r + z) & 1u;  // (c + y + z) & 1 with L even
-    W = ld(own, j);
-    const uint32_t C = ld(oth, j);
-    // in-row neighbours: p = 1 -> x+1 is the next word's first byte onwards
-    const uint32_t Ej = p ? (jx + 4 == R ? rowb : j + 4) : (jx == 0 ? rowb + R - 4 : j - 4);
-    const uint32_t E = ld(oth, Ej);
-    const uint32_t S = p ? __builtin_amdgcn_alignbyte(E, C, 1) : __builtin_amdgcn_alignbyte(C, E, 3);
+    W = ldw(own, j);
+    const uint32_t C = ldw(oth, j);
+    // p = 1: x+1 is the next word's first byte onwards; p = 0: x-1 ends with
+    // the previous word's last byte
+    const uint32_t Ej = p ? (jx + WB == R ? rowb : j + WB) : (jx == 0 ? rowb + R - WB : j - WB);
+    const uint32_t E = ldw(oth, Ej);
+    uint32_t S;
+    if constexpr (WB == 4)
+      S = p ? __builtin_amdgcn_alignbyte(E, C, 1) : __builtin_amdgcn_alignbyte(C, E, 3);
+    else
+      S = p ? ((C >> 8) | ((E & 0xFFu) << 8)) : (((C << 8) & 0xFF00u) | (E >> 8));
     uint32_t nb[6];
     nb[0] = p ? S : C;  // +x
     nb[1] = p ? C : S;  // -x
-    nb[2] = ld(oth, y + 1 == L ? j - sYw : j + R);
-    nb[3] = ld(oth, y == 0 ? j + sYw : j - R);
+    nb[2] = ldw(oth, y + 1 == L ? j - sYw : j + R);
+    nb[3] = ldw(oth, y == 0 ? j + sYw : j - R);
     if (D == 3) {
-      nb[4] = ld(oth, z + 1 == L ? j - sZw : j + sZ);
-      nb[5] = ld(oth, z == 0 ? j + sZw : j - sZ);
+      nb[4] = ldw(oth, z + 1 == L ? j - sZw : j + sZ);
+      nb[5] = ldw(oth, z == 0 ? j + sZw : j - sZ);
     }
     // unsatisfied bonds per byte: spin bits differ, xor the bond's sign bit
     uint32_t k = 0;
@@ -157,13 +174,15 @@ __global__ __launch_bounds__(512) void batch_kernel(const BatchDesc* __restrict_
     }
     return k;
   };
-  // New word for prefix word P; `tie` gets bit 7 of each byte whose prefix
-  // equals the threshold byte of a refusable class (left unflipped), `kout`
-  // the counts.
-  auto word4 = [&](const int8_t* own, const int8_t* oth, uint32_t c, uint32_t j, uint32_t P,
-                   uint32_t& tie, uint32_t& kout) -> uint32_t {
+  // New word for prefix bytes P (byte b: site j + b); `tie` gets bit 7 of
+  // each byte whose prefix equals the threshold byte of a refusable class
+  // (left unflipped), `kout` the counts.  Only the low WB bytes of the
+  // result are meaningful.
+  auto word = [&](auto wb, const int8_t* own, const int8_t* oth, uint32_t c, uint32_t j,
+                  uint32_t P, uint32_t& tie, uint32_t& kout) -> uint32_t {
+    constexpr uint32_t WB = decltype(wb)::value;
     uint32_t W;
-    const uint32_t k = counts4(own, oth, c, j, W);
+    const uint32_t k = counts(wb, own, oth, c, j, W);
     kout = k;
     const uint32_t Th = __builtin_amdgcn_perm(th_hi, th_lo, k);
     const uint32_t Al = __builtin_amdgcn_perm(al_hi, al_lo, k);
@@ -172,9 +191,11 @@ __global__ __launch_bounds__(512) void batch_kernel(const BatchDesc* __restrict_
     const uint32_t ge = (x & P) | (~x & dlow);  // bit 7 of each byte: P >= Th
     const uint32_t rej = __builtin_amdgcn_perm(ge, ge << 8, 0x0B090A08u);
     const uint32_t zb = (x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
-    tie = ~(zb | x | Al) & kHigh;
+    tie = ~(zb | x | Al) & (WB == 4 ? kHigh : 0x8080u);
     return W ^ ((~rej | Al) & kOnes);
   };
+  using W4 = std::integral_constant<uint32_t, 4>;
+  using W2 = std::integral_constant<uint32_t, 2>;
   // Ties wait in a per-lane LDS queue (entry (site << 3) | class, lane-major)
   // and are resolved by their refinement draws before the colour's barrier:
   // a lane alone writes the sites of its groups, so the late flip is
@@ -192,6 +213,7 @@ __global__ __launch_bounds__(512) void batch_kernel(const BatchDesc* __restrict_
     nq = 0;
   };
   const bool words = (R & 3u) == 0;
+  const bool pairs = !words && (R & 1u) == 0;
   // E = sum over colour-1 sites of (unsatisfied - satisfied) bonds (each bond
   // once), M = sum of the spins of both colours; record `slot` of this call
   auto measure = [&](uint32_t slot, int64_t sweep) {
@@ -199,10 +221,19 @@ __global__ __launch_bounds__(512) void batch_kernel(const BatchDesc* __restrict_
     if (words) {
       for (uint32_t j = 4 * threadIdx.x; j < Nh; j += 4 * blockDim.x) {
         uint32_t W;
-        const uint32_t k = counts4(lat + Nh, lat, 1u, j, W);
+        const uint32_t k = counts(W4{}, lat + Nh, lat, 1u, j, W);
         const uint32_t down = __builtin_popcount(W & kOnes) + __builtin_popcount(ld(lat, j) & kOnes);
         Esum += 2 * (int64_t)__builtin_amdgcn_sad_u8(k, 0u, 0u) - 4 * 2 * D;
         Msum += 8 - 2 * (int64_t)down;
+      }
+    } else if (pairs) {
+      for (uint32_t j = 2 * threadIdx.x; j < Nh; j += 2 * blockDim.x) {
+        uint32_t W;
+        const uint32_t k = counts(W2{}, lat + Nh, lat, 1u, j, W);
+        const uint32_t w0 = *reinterpret_cast<const uint16_t*>(lat + j);
+        const uint32_t down = __builtin_popcount(W & kOnes) + __builtin_popcount(w0 & kOnes);
+        Esum += 2 * (int64_t)__builtin_amdgcn_sad_u8(k, 0u, 0u) - 2 * 2 * D;
+        Msum += 4 - 2 * (int64_t)down;
       }
     } else {
       for (uint32_t j = threadIdx.x; j < Nh; j += blockDim.x) {
@@ -247,8 +278,40 @@ __global__ __launch_bounds__(512) void batch_kernel(const BatchDesc* __restrict_
             if (ws < nwords) {
               const uint32_t j = j0 + 4 * ws;
               uint32_t tie, k;
-              const uint32_t nw = word4(own, oth, c, j, word_of(rp.w, ws), tie, k);
+              const uint32_t nw = word(W4{}, own, oth, c, j, word_of(rp.w, ws), tie, k);
               *reinterpret_cast<uint32_t*>(own + j) = nw;
+              while (tie) {
+                const uint32_t b = (uint32_t)__builtin_ctz(tie) >> 3;
+                tie &= tie - 1;
+                if (nq == kBatchTieSlots) flush(own, c, t);
+                tq[nq * blockDim.x] = ((j + b) << 3) | ((k >> (8 * b)) & 7u);
+                ++nq;
+              }
+            }
+          }
+        }
+        flush(own, c, t);
+        __syncthreads();
+        continue;
+      }
+      if (pairs) {
+        // Nh is even: a group holds nj / 2 whole pairs
+        for (uint32_t g = threadIdx.x; g < ngroups; g += blockDim.x) {
+          const uint32_t j0 = 16 * g;
+          const Rand4 rp = philox(g, t, replica, tag(c, kIsingPrefix), key.k0, key.k1);
+          const uint32_t npairs = Nh - j0 < 16 ? (Nh - j0) >> 1 : 8u;
+          // not unrolled: the few lattices on this path must not raise the
+          // register count of the whole kernel
+#pragma unroll 1
+          for (uint32_t w = 0; w < 8; ++w) {
+            // lanes 8 apart start on different dwords of their groups
+            const uint32_t ps = (w + 2 * ((threadIdx.x >> 3) & 3u)) & 7u;
+            if (ps < npairs) {
+              const uint32_t j = j0 + 2 * ps;
+              const uint32_t P = word_of(rp.w, ps >> 1) >> (8 * (j & 2u));
+              uint32_t tie, k;
+              const uint32_t nw = word(W2{}, own, oth, c, j, P, tie, k);
+              *reinterpret_cast<uint16_t*>(own + j) = (uint16_t)nw;
               while (tie) {
                 const uint32_t b = (uint32_t)__builtin_ctz(tie) >> 3;
                 tie &= tie - 1;
@@ -280,16 +343,10 @@ __global__ __launch_bounds__(512) void batch_kernel(const BatchDesc* __restrict_
           }
           if (accept) own[j] = (int8_t)(o ^ 1u);
         };
-        if (nj == 16) {
-#pragma unroll
-          for (uint32_t jj = 0; jj < 16; ++jj) one(jj, rp.w[jj >> 2]);
-        } else {
-          for (uint32_t jj = 0; jj < nj; ++jj) {
-            const uint32_t wlo = (jj & 4) ? rp.w[1] : rp.w[0];
-            const uint32_t whi = (jj & 4) ? rp.w[3] : rp.w[2];
-            one(jj, (jj & 8) ? whi : wlo);
-          }
-        }
+        // not unrolled: the few lattices on this path must not raise the
+        // register count of the whole kernel
+#pragma unroll 1
+        for (uint32_t jj = 0; jj < nj; ++jj) one(jj, word_of(rp.w, jj >> 2));
       }
       __syncthreads();
     }

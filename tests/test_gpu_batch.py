@@ -112,3 +112,17 @@ def test_batch_series_rejects_bad_every(smc_gpu):
     with pytest.raises(smc_gpu.SmcError):
         b.sweep(10, obs, every=0)
     assert b.t == 0
+
+
+@pytest.mark.parametrize("d,Ls,kind", [(3, [4, 20, 12, 28, 6], 1), (2, [4, 20, 28, 44, 10, 36], 0)])
+def test_batch_pair_and_site_paths_match_oracle(smc_gpu, oracle_mod, d, Ls, kind):
+    """Lattices whose plane rows are whole 2-site pairs (L/2 = 2, 6, 10, 14,
+    ...), odd half-rows (one-site path) and whole words, side by side."""
+    import torch
+    n = len(Ls)
+    beta = [0.3 + 0.4 * r for r in range(n)]
+    b = smc_gpu.Batch(d, Ls, beta, seed=17, J_kind=kind)
+    obs = torch.zeros((3, n, 8), dtype=torch.int64, device=b.device)
+    b.sweep(9, obs, every=3)
+    _check(smc_gpu, oracle_mod, b, d, Ls, beta, kind, 9, 17,
+           smc_gpu.Lattice.decode_obs(obs[2]))
