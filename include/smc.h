@@ -243,7 +243,7 @@ int smc_batch_sweep(smc_batch* b, int64_t n_sweeps, void* dev_obs);
  * EINVAL on a bad measure_every or a misaligned dev_obs. */
 int smc_batch_sweep_series(smc_batch* b, int64_t n_sweeps, int64_t measure_every, void* dev_obs);
 
-/* Time the workgroup sizes 64..512 and the lattice orders (largest first,
+/* Time the workgroup sizes 64..1024 and the lattice orders (largest first,
  * as given) on a scratch copy of the spins and keep the fastest.  Results do
  * not depend on the choice.  Synchronises the stream. */
 int smc_batch_autotune(smc_batch* b, int32_t* threads_out, int32_t* largest_first_out);

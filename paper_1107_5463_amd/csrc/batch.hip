@@ -31,7 +31,7 @@ namespace smc {
 constexpr uint32_t kBatchTieSlots = 4;  // deferred ties per lane before a flush
 
 template <int D, bool PM, bool MEASURE>
-__global__ __launch_bounds__(512) void batch_kernel(const BatchDesc* __restrict__ descs,
+__global__ __launch_bounds__(1024) void batch_kernel(const BatchDesc* __restrict__ descs,
                                                     const uint32_t* __restrict__ order,
                                                     const RngKey key, int8_t* __restrict__ spins,
                                                     const int8_t* __restrict__ J,

@@ -1042,9 +1042,9 @@ int smc_batch_init(smc_batch** out, int32_t d, int32_t J_kind, uint64_t seed, do
                    [&](uint32_t a, uint32_t c) { return b->desc[a].Nh > b->desc[c].Nh; });
   b->orders = largest;
   b->orders.insert(b->orders.end(), idx.begin(), idx.end());
-  // the largest workgroup (512 lanes) with the largest lattice may pass the
+  // the largest workgroup (1024 lanes) with the largest lattice may pass the
   // default 64 KiB of dynamic LDS
-  int rc = check(batch_allow_lds(batch_lds_bytes(b->max_sites, 512)), "batch LDS attribute");
+  int rc = check(batch_allow_lds(batch_lds_bytes(b->max_sites, 1024)), "batch LDS attribute");
   if (rc == SMC_OK)
     rc = check(hipMemcpyAsync(b->desc_dev, b->desc.data(), sizeof(BatchDesc) * n,
                               hipMemcpyHostToDevice, b->stream), "descriptor upload");
@@ -1113,9 +1113,9 @@ int smc_batch_autotune(smc_batch* b, int32_t* threads_out, int32_t* largest_firs
   float best = 1e30f;
   uint32_t best_threads = b->threads;
   bool best_largest = b->largest_first;
-  const uint32_t cand[4] = {64, 128, 256, 512};
+  const uint32_t cand[5] = {64, 128, 256, 512, 1024};
   for (int lf = 1; lf >= 0 && rc == SMC_OK; --lf) {
-    for (int c = 0; c < 4 && rc == SMC_OK; ++c) {
+    for (int c = 0; c < 5 && rc == SMC_OK; ++c) {
       // the chain on the scratch copy is discarded: any counter will do
       rc = batch_launch(b, (int8_t*)b->scratch, (uint32_t)b->t, 1, 1, nullptr, cand[c], lf != 0);
       if (rc != SMC_OK) break;
