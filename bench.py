@@ -212,16 +212,17 @@ def hbm_roofline(kname, workload, bytes_per_launch, kernel_ms):
     }
 
 
-def valu_roofline(kname, workload, kernel_ms, bytes_per_launch):
+def valu_roofline(kname, workload, kernel_ms, bytes_per_launch, variant=None):
     """VALU-bound kernels: issued 32-bit lane operations per second from the
     committed VALU instruction count per launch (rocprofv3 SQ_INSTS_VALU x 64
-    lanes), valid only for the kernel sources it was taken on."""
+    lanes), valid only for the kernel sources and the variant (schedule, rule)
+    it was taken on."""
     rec = None
     path = os.path.join(ROOT, "profiles", f"{kname}_{workload}_valu.json")
     if os.path.exists(path):
         with open(path) as fh:
             rec = json.load(fh)
-        if rec.get("sources_sha256_16") != sources_digest(kname):
+        if rec.get("sources_sha256_16") != sources_digest(kname) or rec.get("variant") != variant:
             rec = None
     achieved = None
     if rec is not None:
@@ -268,7 +269,10 @@ def run_lattice(args, wl, torch, smc):
     # kernels: a conservative average of the dominant kernel
     kernel_ms = total_ms / launches
     if kname in ("ising_packed", "ising_tiles"):
-        roof = valu_roofline(kname, args.workload, kernel_ms, bytes_per_launch)
+        variant = None
+        if kname == "ising_tiles":
+            variant = f"T={args.tile} k={args.hits} {'heat bath' if args.heatbath else 'Metropolis'}"
+        roof = valu_roofline(kname, args.workload, kernel_ms, bytes_per_launch, variant)
     else:
         roof = hbm_roofline(kname, args.workload, bytes_per_launch, kernel_ms)
     what = {1: "Ising", 2: "XY", 3: "Heisenberg"}[n]
