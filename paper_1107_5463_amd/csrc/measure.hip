@@ -15,13 +15,18 @@
 
 namespace smc {
 
-// Ising, one colour-1 site per thread, any L / coupling kind.
+// grid of the stand-alone measurements (each thread then takes several
+// sites or chunks), so the finish kernel reads few partials
+constexpr int64_t kMeasureBlocks = 2048;
+
+// Ising, colour-1 sites j = gid, gid + stride, ... per thread, any L /
+// coupling kind.
 template <int D, int JK>
 __global__ __launch_bounds__(256) void measure_ising_site(const Geom g, const int8_t* __restrict__ s,
                                                           const void* __restrict__ J, Partial* out) {
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * 256;
   Partial v{0, 0, 0.0, {0.0, 0.0, 0.0}};
-  if (j < g.Nh) {
+  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < g.Nh; j += stride) {
     const int64_t Nh = g.Nh;
     const int8_t* s1 = s + Nh;
     const int8_t* s0 = s;
@@ -53,22 +58,23 @@ __global__ __launch_bounds__(256) void measure_ising_site(const Geom g, const in
         e -= sgp * si * sp + sgm * si * sm;
       }
     }
-    v.Ei = e;
-    v.E = ef;
-    v.Mi = si + s0[j];
+    v.Ei += e;
+    v.E += ef;
+    v.Mi += si + s0[j];
   }
   block_partial(v, out + 0);
 }
 
-// Ising, one colour-1 chunk of 16 sites per thread (L % 32 == 0, integer J).
+// Ising, colour-1 chunks of 16 sites gid, gid + stride, ... per thread
+// (L % 32 == 0, integer J).
 template <int D, bool PM>
 __global__ __launch_bounds__(256) void measure_ising_chunk(const Geom g, const int8_t* __restrict__ s,
                                                            const int8_t* __restrict__ J,
                                                            const FastDiv divQ, const FastDiv divL,
                                                            Partial* out) {
-  const uint32_t gid = blockIdx.x * 256u + threadIdx.x;
+  const uint32_t stride = gridDim.x * 256u;
   Partial v{0, 0, 0.0, {0.0, 0.0, 0.0}};
-  if (gid < (uint32_t)(g.Nh >> 4)) {
+  for (uint32_t gid = blockIdx.x * 256u + threadIdx.x; gid < (uint32_t)(g.Nh >> 4); gid += stride) {
     int64_t base;
     Chunk o, ctr;
     uint32_t kk[4];
@@ -81,8 +87,8 @@ __global__ __launch_bounds__(256) void measure_ising_chunk(const Geom g, const i
       down = __builtin_amdgcn_sad_u8(ctr.w[w] & kBit1, 0u, down);
     }
     // each site: s_i h_i = 2d - 2k; M: 32 sites, down counted twice (bit value 2)
-    v.Ei = -(int64_t)(16 * 2 * D) + 2 * (int64_t)unsat;
-    v.Mi = 32 - (int64_t)down;
+    v.Ei += -(int64_t)(16 * 2 * D) + 2 * (int64_t)unsat;
+    v.Mi += 32 - (int64_t)down;
   }
   block_partial(v, out);
 }
@@ -191,9 +197,6 @@ __global__ __launch_bounds__(256) void finish_kernel(const Partial* __restrict__
 
 int64_t measure_partials(const Geom& g) { return (g.Nh + 255) / 256; }
 
-// grid of the continuous measurement (each thread then takes several sites)
-constexpr int64_t kMeasureBlocks = 2048;
-
 template <int D>
 static void launch_measure_d(const MeasureLaunch& a, const void* spins, Partial* parts,
                              int64_t& nparts, hipStream_t st) {
@@ -201,7 +204,7 @@ static void launch_measure_d(const MeasureLaunch& a, const void* spins, Partial*
   if (a.n == 1) {
     if (a.J_kind != 2 && g.L % 32 == 0) {
       const uint32_t nchunks = (uint32_t)(g.Nh >> 4);
-      nparts = (nchunks + 255) / 256;
+      nparts = std::min<int64_t>((nchunks + 255) / 256, kMeasureBlocks);
       const FastDiv dq = make_fastdiv((uint32_t)(g.R / 16)), dl = make_fastdiv((uint32_t)g.L);
       if (a.J_kind == 1)
         hipLaunchKernelGGL((measure_ising_chunk<D, true>), dim3((unsigned)nparts), dim3(256), 0,
@@ -211,7 +214,7 @@ static void launch_measure_d(const MeasureLaunch& a, const void* spins, Partial*
                            st, g, (const int8_t*)spins, (const int8_t*)a.J, dq, dl, parts);
       return;
     }
-    nparts = (g.Nh + 255) / 256;
+    nparts = std::min<int64_t>((g.Nh + 255) / 256, kMeasureBlocks);
     const dim3 grid((unsigned)nparts);
     if (a.J_kind == 0)
       hipLaunchKernelGGL((measure_ising_site<D, 0>), grid, dim3(256), 0, st, g,
