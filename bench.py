@@ -148,6 +148,27 @@ def copy_probe(torch, device):
     del a, b
 
 
+def copy_ceiling(torch, device, nbytes):
+    """Device-to-device copy rate (read + write GB/s) of an nbytes buffer, the
+    best of 10 copies timed with HIP events: a ceiling for streaming kernels
+    of that footprint."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device=device).fill_(1)
+    b = torch.empty(nbytes, dtype=torch.uint8, device=device)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(10):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del a, b
+    return round(2 * nbytes / (best * 1e-3) / 1e9, 1)
+
+
 def oracle_rate(fn, attempts_per_call, budget_s):
     """Calls fn until budget_s has passed (at least once); attempts/ns."""
     t0 = time.perf_counter()
@@ -306,18 +327,26 @@ def run_lattice(args, wl, torch, smc):
         "wall_s": round(wall, 3),
         "final_obs": None if obs is None else {"E": obs.E, "M": list(obs.M[:n]), "sweep": obs.sweep},
     }
+    if roof["bound"] == "hbm":
+        # a plain device copy of the spin buffer's footprint, for context
+        # next to the 8 TB/s peak
+        roof["copy_ceiling_GBps"] = copy_ceiling(torch, lat.device,
+                                                 lat.spins.numel() * lat.spins.element_size())
     if packed and not args.no_int8_line:
         # the same chain with int8 spins: the HBM-bound two-pass schedule
         lat8 = smc.Lattice(d, n, L, seed=wl["seed"])
         ms8, _, obs8 = timed_steps(lat8, beta, K, W, S, torch)
         k8, rows8 = lat8.kernel()
         l8, b8, sch8 = kernel_model(k8, n, N, sweeps, 0, 1)
+        roof8 = hbm_roofline(k8, args.workload, b8, ms8 / l8)
+        roof8["copy_ceiling_GBps"] = copy_ceiling(torch, lat8.device,
+                                                  lat8.spins.numel() * lat8.spins.element_size())
         result["int8_two_pass"] = {
             "value": round(attempts / (ms8 * 1e6), 2),
             "unit": "attempts/ns",
             "ms_per_step": round(ms8 / max(K, 1), 4),
             "schedule": sch8, "rows_per_band": rows8,
-            "roofline": hbm_roofline(k8, args.workload, b8, ms8 / l8),
+            "roofline": roof8,
             "same_final_state": bool(obs8 is not None and obs is not None and obs8.E_int == obs.E_int
                                      and obs8.M_int == obs.M_int),
         }
