@@ -14,9 +14,11 @@
 // u < exp(-beta dE) with word j & 3 of block j >> 2).  A lane handles pairs
 // of consecutive same-colour sites (half of a four-site Philox block, which
 // both lanes of the block draw: twice the lanes of one block per lane, for a
-// latency-bound kernel) and always the same pairs, so the bonds of its
-// colour-0 sites (every bond has exactly one colour-0 end) are its own
-// accumulator entries.
+// latency-bound kernel) and always the same pairs.  Every bond has exactly
+// one colour-1 and one colour-0 end: the bond products of a sample are added
+// in the colour-1 pass by the lane that has just updated the colour-1 end
+// (no separate pass), and the covariance pass adds (G - c) x_b from the
+// colour-0 ends, so no accumulator entry has two writers.
 //
 // The covariance pass replays the sampling sweeps: with the same start state
 // and counters it visits exactly the same configurations, and needs no stored
@@ -101,6 +103,7 @@ __global__ __launch_bounds__(1024) void chains_kernel(const ChainsLaunch a, int8
   double Gsum = 0.0, G2sum = 0.0;
   for (uint32_t sw = 0; sw < n_sweeps; ++sw) {
     const uint32_t t = t0 + sw;
+    double Gp = 0.0;
     for (uint32_t c = 0; c < 2; ++c) {
       int8_t* own = lat + c * Nh;
       const int8_t* oth = lat + (1 - c) * Nh;
@@ -123,59 +126,67 @@ __global__ __launch_bounds__(1024) void chains_kernel(const ChainsLaunch a, int8
           const float dE = 2.0f * (float)si * h;
           const bool accept = dE <= 0.0f || u01f(word_of(r.w, j & 3u)) < expf(-beta * dE);
           if (accept) own[j] = (int8_t)(-si);
-        }
-      }
-      __syncthreads();
-    }
-    if (MODE == 2) continue;
-    // bond products of the new configuration, from the colour-0 ends
-    double Gp = 0.0;
-    for (int pass = 0; pass < (MODE == 0 ? 1 : 2); ++pass) {
-      double Gc = 0.0;
-      if (MODE == 1 && pass == 1) Gc = red[0] - gc;
-      for (uint32_t pi = threadIdx.x; pi < pairs; pi += blockDim.x) {
+          if (MODE != 2 && c == 1) {
+            // the sweep's configuration is final at this colour-1 site: the
+            // products across its 2d bonds (every bond has exactly one
+            // colour-1 end, so this lane alone adds to them)
+            const int sn = accept ? -si : si;
 #pragma unroll
-        for (uint32_t b = 0; b < 2; ++b) {
-          const uint32_t j = 2 * pi + b;
-          uint32_t nb[6];
-          neighbours32<D>(j, 0u, a.divR, a.divL, nb);
-          const int s0 = lat[j];
-#pragma unroll
-          for (int mu = 0; mu < D; ++mu) {
-            const uint32_t ip = nb[2 * mu], im = nb[2 * mu + 1];
-            const int xpv = s0 * lat[NhU + ip];  // bond (mu, colour 0, j)
-            const int xmv = s0 * lat[NhU + im];  // bond (mu, colour 1, im)
-            const uint32_t bp = (2 * mu) * NhU + j;
-            const uint32_t bm = (2 * mu + 1) * NhU + im;
-            if (MODE == 0) {
-              acc_i[bp] += xpv;
-              acc_i[bm] += xmv;
-            } else if (pass == 0) {
-              Gp += gvec[bp] * (double)xpv;
-              Gp += gvec[bm] * (double)xmv;
-            } else {
-              acc_d[bp] += Gc * (double)xpv;
-              acc_d[bm] += Gc * (double)xmv;
+            for (int mu = 0; mu < D; ++mu) {
+              const int xpv = sn * oth[nb[2 * mu]];      // bond (mu, colour 1, j)
+              const int xmv = sn * oth[nb[2 * mu + 1]];  // bond (mu, colour 0, -mu neighbour)
+              const uint32_t bp = (2 * mu + 1) * NhU + j;
+              const uint32_t bm = (2 * mu) * NhU + nb[2 * mu + 1];
+              if (MODE == 0) {
+                acc_i[bp] += xpv;
+                acc_i[bm] += xmv;
+              } else {
+                Gp += gvec[bp] * (double)xpv;
+                Gp += gvec[bm] * (double)xmv;
+              }
             }
           }
         }
       }
-      if (MODE == 1 && pass == 0) {
-        // G of this sample: wave sums, then the waves in order
-        double v = Gp;
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-        const uint32_t wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-        if ((threadIdx.x & 63) == 0) red[1 + wave] = v;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-          double s = 0.0;
-          for (uint32_t k = 0; k < nw; ++k) s += red[1 + k];
-          red[0] = s;
-          const double gcen = s - gc;
-          Gsum += gcen;
-          G2sum += gcen * gcen;
+      __syncthreads();
+    }
+    if (MODE != 1) continue;
+    {
+      // G of this sample: wave sums, then the waves in order
+      double v = Gp;
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+      const uint32_t wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+      if ((threadIdx.x & 63) == 0) red[1 + wave] = v;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (uint32_t k = 0; k < nw; ++k) s += red[1 + k];
+        red[0] = s;
+        const double gcen = s - gc;
+        Gsum += gcen;
+        G2sum += gcen * gcen;
+      }
+      __syncthreads();
+    }
+    // (G - c) x_b for every bond, owned by its colour-0 end (no lane writes a
+    // colour-0 site before the next sweep's colour-0 pass, in which the same
+    // lane owns it)
+    const double Gc = red[0] - gc;
+    for (uint32_t pi = threadIdx.x; pi < pairs; pi += blockDim.x) {
+#pragma unroll
+      for (uint32_t b = 0; b < 2; ++b) {
+        const uint32_t j = 2 * pi + b;
+        uint32_t nb[6];
+        neighbours32<D>(j, 0u, a.divR, a.divL, nb);
+        const int s0 = lat[j];
+#pragma unroll
+        for (int mu = 0; mu < D; ++mu) {
+          const uint32_t ip = nb[2 * mu], im = nb[2 * mu + 1];
+          const int xpv = s0 * lat[NhU + ip];  // bond (mu, colour 0, j)
+          const int xmv = s0 * lat[NhU + im];  // bond (mu, colour 1, im)
+          acc_d[(2 * mu) * NhU + j] += Gc * (double)xpv;
+          acc_d[(2 * mu + 1) * NhU + im] += Gc * (double)xmv;
         }
-        __syncthreads();
       }
     }
     // the next colour-0 pass writes only sites whose bonds this lane owns
