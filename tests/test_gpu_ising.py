@@ -286,7 +286,8 @@ def test_kernel_variants_bit_identical(smc_gpu, oracle_mod, d, L, monkeypatch):
 @pytest.mark.parametrize("L,n,rows,kernel", [(2048, 4, None, None), (2048, 5, "4", None),
                                              (4096, 3, "8", None), (2048, 2, "64", None),
                                              (4096, 1, None, None), (2048, 4, "16", "fused_wave"),
-                                             (4096, 3, None, "fused_wave"), (16384, 2, "32", "fused_wave")])
+                                             (4096, 3, None, "fused_wave"), (16384, 2, "32", "fused_wave"),
+                                             (16384, 2, None, None)])
 def test_fused_schedule_matches_oracle(smc_gpu, oracle_mod, L, n, rows, kernel, monkeypatch):
     """The one-kernel-per-sweep schedule (ping-pong buffers, redundant
     band-edge rows; wave segments with recomputed halo chunks, or whole-row
