@@ -126,3 +126,39 @@ def test_batch_pair_and_site_paths_match_oracle(smc_gpu, oracle_mod, d, Ls, kind
     b.sweep(9, obs, every=3)
     _check(smc_gpu, oracle_mod, b, d, Ls, beta, kind, 9, 17,
            smc_gpu.Lattice.decode_obs(obs[2]))
+
+
+@pytest.mark.parametrize("kind,beta,sweeps", [(0, 0.4406868, 1), (0, 0.4406868, 3), (1, 0.8, 2)])
+def test_batch_ensemble_matches_exact_propagation(smc_gpu, oracle_mod, kind, beta, sweeps):
+    """2^17 copies of one 4 x 4 lattice (the same start state and couplings,
+    replica = lattice index, so independent random streams) after a few sweeps
+    are distributed as the exact propagation of Eq. (2) over all 2^16 states
+    (chi^2 at p = 1e-4).  This pins the GPU chain to the dynamics without going
+    through the oracle's chain (the oracle only supplies the start state)."""
+    import torch
+    from scipy.stats import chi2
+
+    import oracle.exact as ex
+    from test_oracle_ising import _chi2_states
+
+    d, L, n = 2, 4, 1 << 17
+    N = L ** d
+    print(f"batch ensemble kind={kind} beta={beta} sweeps={sweeps}", flush=True)
+    ref = oracle_mod.OracleLattice(d, 1, L, 11, J_kind=kind)
+    b = smc_gpu.Batch(d, [L] * n, [beta] * n, seed=11, J_kind=kind, init="cold")
+    assert b.spin_offsets == [N * r for r in range(n)]
+    s0 = torch.from_numpy(layout.to_split(ref.s, d, L).reshape(-1).copy())
+    b.spins.view(n, N).copy_(s0.to(b.device).expand(n, N))
+    if kind == 1:
+        assert b.coupling_offsets == [d * N * r for r in range(n)]
+        J0 = torch.from_numpy(layout.to_split(ref.J, d, L).reshape(-1).copy())
+        b.J.view(n, d * N).copy_(J0.to(b.device).expand(n, d * N))
+    b.sweep(sweeps)
+    got = layout.to_natural(b.spins.view(n, 2, N // 2).cpu().numpy(), d, L)
+    chain = ex.SmallLatticeChain(d, L, beta, J=None if kind == 0 else ref.J)
+    pi = np.zeros(1 << N)
+    pi[ex.state_index(ref.s)] = 1.0
+    for _ in range(sweeps):
+        pi = chain.sweep(pi)
+    stat, dof = _chi2_states(ex.state_index(got), pi)
+    assert stat < chi2.ppf(1 - 1e-4, dof), (stat, dof)
