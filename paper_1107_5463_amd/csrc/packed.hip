@@ -16,14 +16,16 @@
 //  * the count k of unsatisfied bonds is a bit-sliced sum: three bit planes
 //    k0, k1, k2 for 32 sites at once (full adders as v_bitop3);
 //  * the same two Philox blocks as the int8 path give the 32 prefix bytes,
-//    transposed into 8 bit planes (four 8x8 bit transposes by delta swaps and
-//    a byte regroup with v_perm); the threshold bytes of the sites' classes
+//    transposed into 8 bit planes (a byte transpose with v_perm, then three
+//    bit swaps between word pairs); the threshold bytes of the sites' classes
 //    (those whose move can be refused: at most d of the 2d + 1) are laid out
 //    as 8 bit planes too, and one bit-sliced compare against them gives the
 //    refused sites and the exact ties;
 //  * exact ties (prefix byte == threshold byte, 2^-8 of refusable moves) are
 //    queued in LDS and resolved at the end of the band with each site's
 //    24-bit refinement draw, as in the int8 kernel.
+#include <type_traits>
+
 #include "chunk.hpp"
 #include "reduce.hpp"
 
@@ -44,51 +46,58 @@ __device__ __forceinline__ uint32_t class_mask(uint32_t k0, uint32_t k1, uint32_
   return a & b & c;
 }
 
-// 8x8 bit transpose of the 64-bit block (lo = bytes 0..3, hi = bytes 4..7):
-// afterwards bit c of byte r is bit r of the original byte c.  Three delta
-// swaps (distances 7, 14, 28) on the 32-bit halves.
-__device__ __forceinline__ void transpose8(uint32_t& lo, uint32_t& hi) {
-  uint32_t t;
-  t = ((lo >> 7) ^ lo) & 0x00AA00AAu;
-  lo = lo ^ t ^ (t << 7);
-  t = ((hi >> 7) ^ hi) & 0x00AA00AAu;
-  hi = hi ^ t ^ (t << 7);
-  t = ((lo >> 14) ^ lo) & 0x0000CCCCu;
-  lo = lo ^ t ^ (t << 14);
-  t = ((hi >> 14) ^ hi) & 0x0000CCCCu;
-  hi = hi ^ t ^ (t << 14);
-  t = (__builtin_amdgcn_alignbit(hi, lo, 28u) ^ lo) & 0xF0F0F0F0u;
-  lo ^= t;
-  hi ^= t >> 4;
+// Exchange of a word-index bit with bit k of the bit position (d = 2^k,
+// m = the positions whose bit k is 0) between the words a (index bit 0) and
+// b (index bit 1): afterwards a holds the bits whose position bit k was 0, b
+// those whose bit k was 1, and position bit k tells which word a bit came from.
+// (v_bitop3 with the table 0xE4 selects its first operand where the third is
+// 1 and its second elsewhere; the builtin keeps the compiler from splitting
+// the selects into separate masks.)
+template <int D>
+__device__ __forceinline__ void cross_swap(uint32_t& a, uint32_t& b, uint32_t m) {
+  const uint32_t na = __builtin_amdgcn_bitop3_b32(a, b << D, m, 0xE4);
+  const uint32_t nb = __builtin_amdgcn_bitop3_b32(a >> D, b, m, 0xE4);
+  a = na;
+  b = nb;
 }
 
 // The 32 prefix bytes of a word's sites (site s in byte s & 3 of P[s >> 2])
-// as 8 bit planes: bit s of B[b] = bit b of site s's byte.
+// as 8 bit planes: bit s of B[b] = bit b of site s's byte.  With site
+// s = 4w + i (word w, byte i) and the bit b of a byte, a byte of P sits at
+// word (w2 w1 w0), byte (i1 i0); a bit of the planes must end at word
+// (b2 b1 b0), position (w2 w1 w0 i1 i0).  A 4x4 byte transpose (v_perm)
+// among the words of equal w0 trades (w2 w1) for (i1 i0); three cross-word
+// bit swaps then trade the word bits (w0, i1, i0) for the bit-in-byte bits
+// (b2, b1, b0), which leaves every bit at its site's position.
 __device__ __forceinline__ void prefix_planes(const uint32_t P[8], uint32_t B[8]) {
-  uint32_t lo[4], hi[4];
+  uint32_t Q[2][4];  // Q[w0][i]: byte k = byte i of P[2k + w0]
 #pragma unroll
-  for (int m = 0; m < 4; ++m) {
-    lo[m] = P[2 * m];
-    hi[m] = P[2 * m + 1];
-    transpose8(lo[m], hi[m]);  // byte b of block m: plane b of sites 8m .. 8m + 7
+  for (int w0 = 0; w0 < 2; ++w0) {
+    const uint32_t g0 = P[w0], g1 = P[2 + w0], g2 = P[4 + w0], g3 = P[6 + w0];
+    const uint32_t t0 = __builtin_amdgcn_perm(g1, g0, 0x06020400u);  // g0.0 g1.0 g0.2 g1.2
+    const uint32_t t1 = __builtin_amdgcn_perm(g1, g0, 0x07030501u);  // g0.1 g1.1 g0.3 g1.3
+    const uint32_t t2 = __builtin_amdgcn_perm(g3, g2, 0x06020400u);
+    const uint32_t t3 = __builtin_amdgcn_perm(g3, g2, 0x07030501u);
+    Q[w0][0] = __builtin_amdgcn_perm(t2, t0, 0x05040100u);  // byte 0 of g0 .. g3
+    Q[w0][2] = __builtin_amdgcn_perm(t2, t0, 0x07060302u);
+    Q[w0][1] = __builtin_amdgcn_perm(t3, t1, 0x05040100u);
+    Q[w0][3] = __builtin_amdgcn_perm(t3, t1, 0x07060302u);
   }
-  // regroup bytes: B[b] = (byte b of blocks 0, 1, 2, 3)
-  const uint32_t a0 = __builtin_amdgcn_perm(lo[1], lo[0], 0x05010400u);  // b0: m0 m1, b1: m0 m1
-  const uint32_t a1 = __builtin_amdgcn_perm(lo[1], lo[0], 0x07030602u);  // b2, b3
-  const uint32_t c0 = __builtin_amdgcn_perm(lo[3], lo[2], 0x05010400u);
-  const uint32_t c1 = __builtin_amdgcn_perm(lo[3], lo[2], 0x07030602u);
-  const uint32_t a2 = __builtin_amdgcn_perm(hi[1], hi[0], 0x05010400u);  // b4, b5
-  const uint32_t a3 = __builtin_amdgcn_perm(hi[1], hi[0], 0x07030602u);  // b6, b7
-  const uint32_t c2 = __builtin_amdgcn_perm(hi[3], hi[2], 0x05010400u);
-  const uint32_t c3 = __builtin_amdgcn_perm(hi[3], hi[2], 0x07030602u);
-  B[0] = __builtin_amdgcn_perm(c0, a0, 0x05040100u);
-  B[1] = __builtin_amdgcn_perm(c0, a0, 0x07060302u);
-  B[2] = __builtin_amdgcn_perm(c1, a1, 0x05040100u);
-  B[3] = __builtin_amdgcn_perm(c1, a1, 0x07060302u);
-  B[4] = __builtin_amdgcn_perm(c2, a2, 0x05040100u);
-  B[5] = __builtin_amdgcn_perm(c2, a2, 0x07060302u);
-  B[6] = __builtin_amdgcn_perm(c3, a3, 0x05040100u);
-  B[7] = __builtin_amdgcn_perm(c3, a3, 0x07060302u);
+  // w0 <-> b2 (position bit 2), i1 <-> b1, i0 <-> b0
+#pragma unroll
+  for (int i = 0; i < 4; ++i) cross_swap<4>(Q[0][i], Q[1][i], 0x0F0F0F0Fu);
+#pragma unroll
+  for (int c2 = 0; c2 < 2; ++c2) {
+    cross_swap<2>(Q[c2][0], Q[c2][2], 0x33333333u);
+    cross_swap<2>(Q[c2][1], Q[c2][3], 0x33333333u);
+    // Q[c2][2 c1 + i0] now holds bit b2 = c2, b1 = c1 of the sites' bytes
+#pragma unroll
+    for (int c1 = 0; c1 < 2; ++c1) {
+      cross_swap<1>(Q[c2][2 * c1], Q[c2][2 * c1 + 1], 0x55555555u);
+      B[4 * c2 + 2 * c1] = Q[c2][2 * c1];
+      B[4 * c2 + 2 * c1 + 1] = Q[c2][2 * c1 + 1];
+    }
+  }
 }
 
 // Per-lane tie queue entries: site (5 bits), row in band (6), class (3),
@@ -134,20 +143,43 @@ __device__ __forceinline__ uint32_t packed_decide(const TabRegs& tab, const RngK
   uint32_t B[8];
   prefix_planes(P, B);
   // Per-site threshold bit planes: T[b] holds bit b of the threshold byte of
-  // each site's class (refusable classes only; wave-uniform branches on the
-  // table), then one bit-sliced compare of the prefix planes against them.
-  uint32_t T[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
+  // each site's class, then one bit-sliced compare of the prefix planes
+  // against them.  With J0 > 0 only the classes k < d (Delta E = 4 J0 (d - k)
+  // > 0) can refuse a move: they are added without branches, a class whose
+  // threshold reaches 2^32 (the table's always-accept flag, also every k < d
+  // when J0 <= 0) masked out by a wave-uniform mask.  The classes k > d refuse
+  // only when J0 < 0 and are added behind wave-uniform branches.
+  uint32_t T[8];
   uint32_t refus = 0;
-#define SMC_CLASS(KV)                                                              \
-  if (KV <= 2 * D && table_byte(tab.al_lo, tab.al_hi, KV) == 0u) {                 \
-    const uint32_t m = class_mask<KV>(k0, k1, k2);                                 \
-    const uint32_t th = table_byte(tab.th_lo, tab.th_hi, KV);                      \
-    refus |= m;                                                                    \
-    _Pragma("unroll") for (int b = 0; b < 8; ++b)                                  \
-      T[b] |= m & __builtin_amdgcn_readfirstlane(0u - ((th >> b) & 1u));           \
-  }
-  SMC_CLASS(0) SMC_CLASS(1) SMC_CLASS(2) SMC_CLASS(3) SMC_CLASS(4) SMC_CLASS(5) SMC_CLASS(6)
-#undef SMC_CLASS
+  auto add_class = [&](auto kv) {
+    constexpr int KV = decltype(kv)::value;
+    const uint32_t live =
+        __builtin_amdgcn_readfirstlane(table_byte(tab.al_lo, tab.al_hi, KV) == 0u ? ~0u : 0u);
+    const uint32_t m = class_mask<KV>(k0, k1, k2) & live;
+    const uint32_t th = table_byte(tab.th_lo, tab.th_hi, KV);
+    refus |= m;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const uint32_t tb = m & __builtin_amdgcn_readfirstlane(0u - ((th >> b) & 1u));
+      T[b] = KV == 0 ? tb : (T[b] | tb);
+    }
+  };
+  auto add_class_if = [&](auto kv) {
+    constexpr int KV = decltype(kv)::value;
+    if (table_byte(tab.al_lo, tab.al_hi, KV) == 0u) {
+      const uint32_t m = class_mask<KV>(k0, k1, k2);
+      const uint32_t th = table_byte(tab.th_lo, tab.th_hi, KV);
+      refus |= m;
+#pragma unroll
+      for (int b = 0; b < 8; ++b) T[b] |= m & __builtin_amdgcn_readfirstlane(0u - ((th >> b) & 1u));
+    }
+  };
+  add_class(std::integral_constant<int, 0>());
+  add_class(std::integral_constant<int, 1>());
+  if constexpr (D == 3) add_class(std::integral_constant<int, 2>());
+  add_class_if(std::integral_constant<int, D + 1>());
+  add_class_if(std::integral_constant<int, D + 2>());
+  if constexpr (D == 3) add_class_if(std::integral_constant<int, 6>());
   // most significant bit first: eq = equal so far, lt = prefix below threshold
   uint32_t eq = ~0u, lt = 0u;
 #pragma unroll
@@ -198,8 +230,12 @@ __device__ __forceinline__ void count_planes(const uint32_t u[6], uint32_t& k0, 
 
 __device__ __forceinline__ int32_t popc(uint32_t v) { return __builtin_popcount(v); }
 
+// The plain launches of a band height chosen for eight waves per SIMD ask the
+// compiler for that occupancy (64 registers); the +-1-coupling 3D kernel would
+// spill there and keeps the default.
 template <int D, bool PM, bool MEASURE>
-__global__ __launch_bounds__(256) void packed_stream_kernel(const Geom g, const RngKey key,
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void packed_stream_kernel(const Geom g, const RngKey key,
                                                             const IsingTable table,
                                                             const FastDiv divW, const FastDiv divL,
                                                             const uint32_t H, const uint32_t nbands,
@@ -224,6 +260,11 @@ __global__ __launch_bounds__(256) void packed_stream_kernel(const Geom g, const 
     const uint32_t Wh = (uint32_t)(g.Nh / 32);  // words per plane
     uint32_t* own = s + (uint64_t)c * Wh;
     const uint32_t* oth = s + (uint64_t)(1 - c) * Wh;
+    // word w of a plane at a 32-bit byte offset from the plane's (uniform)
+    // base: the loads and stores take the scalar-base + 32-bit-offset form
+    auto ldw = [](const uint32_t* base, uint32_t w) -> uint32_t {
+      return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(base) + (w << 2));
+    };
     const uint32_t zrow = L * z;
     const uint32_t qn = q + 1 == W ? 0u : q + 1, qp = q == 0 ? W - 1 : q - 1;
     auto rw = [&](uint32_t zr, uint32_t y) -> uint32_t {  // word index of (row, q); y < 2L
@@ -245,15 +286,15 @@ __global__ __launch_bounds__(256) void packed_stream_kernel(const Geom g, const 
     tq.dM = 0;
     // J planes: J[mu][cc] at (2 mu + cc) * Wh
     const uint32_t pz = (c + z) & 1u;
-    uint32_t up = oth[rw(zrow, y0 + L - 1) + q];
-    uint32_t ct = oth[rw(zrow, y0) + q];
+    uint32_t up = ldw(oth, rw(zrow, y0 + L - 1) + q);
+    uint32_t ct = ldw(oth, rw(zrow, y0) + q);
     for (uint32_t i = 0; i < H; ++i) {
       const uint32_t y = y0 + i;
       const uint32_t rowb = rw(zrow, y);
       const uint32_t p = (pz + y) & 1u;
-      const uint32_t dn = oth[rw(zrow, y + 1) + q];
-      const uint32_t o = own[rowb + q];
-      const uint32_t en = oth[rowb + qn], ep = oth[rowb + qp];
+      const uint32_t dn = ldw(oth, rw(zrow, y + 1) + q);
+      const uint32_t o = ldw(own, rowb + q);
+      const uint32_t en = ldw(oth, rowb + qn), ep = ldw(oth, rowb + qp);
       // x+1 neighbours (p = 1: next in-row site) and x-1 (p = 0: previous)
       const uint32_t sh_next = __builtin_amdgcn_alignbit(en, ct, 1u);
       const uint32_t sh_prev = __builtin_amdgcn_alignbit(ct, ep, 31u);
@@ -266,30 +307,30 @@ __global__ __launch_bounds__(256) void packed_stream_kernel(const Geom g, const 
       u[3] = o ^ up;
       uint32_t fz = 0, bz = 0;
       if (D == 3) {
-        fz = oth[rw(zm_row, y) + q];
-        bz = oth[rw(zp_row, y) + q];
+        fz = ldw(oth, rw(zm_row, y) + q);
+        bz = ldw(oth, rw(zp_row, y) + q);
         u[4] = o ^ bz;
         u[5] = o ^ fz;
       }
       if (PM) {
         const uint32_t* Jo = J + (uint64_t)c * Wh;        // J[mu][c] = J + (2 mu + c) Wh
         const uint32_t* Jn = J + (uint64_t)(1 - c) * Wh;  // J[mu][1 - c]
-        const uint32_t jc = Jn[rowb + q];
-        const uint32_t jp_prev = Jn[rowb + qp];
-        u[0] ^= Jo[rowb + q];
+        const uint32_t jc = ldw(Jn, rowb + q);
+        const uint32_t jp_prev = ldw(Jn, rowb + qp);
+        u[0] ^= ldw(Jo, rowb + q);
         u[1] ^= mask_sel(__builtin_amdgcn_alignbit(jc, jp_prev, 31u), jc, p);
-        u[2] ^= Jo[2 * (uint64_t)Wh + rowb + q];
-        u[3] ^= Jn[2 * (uint64_t)Wh + rw(zrow, y + L - 1) + q];
+        u[2] ^= ldw(Jo, 2 * Wh + rowb + q);
+        u[3] ^= ldw(Jn, 2 * Wh + rw(zrow, y + L - 1) + q);
         if (D == 3) {
-          u[4] ^= Jo[4 * (uint64_t)Wh + rowb + q];
-          u[5] ^= Jn[4 * (uint64_t)Wh + rw(zm_row, y) + q];
+          u[4] ^= ldw(Jo, 4 * Wh + rowb + q);
+          u[5] ^= ldw(Jn, 4 * Wh + rw(zm_row, y) + q);
         }
       }
       uint32_t k0, k1, k2;
       count_planes<D>(u, k0, k1, k2);
       const uint32_t flip = packed_decide<D>(tab, key, t, c, rowb + q, i, o, k0, k1, k2, tq, own);
       const uint32_t on = o ^ flip;
-      own[rowb + q] = on;
+      *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(own) + ((rowb + q) << 2)) = on;
       if (MEASURE) {
         // colour 1 after its update: each bond has one colour-1 end; the
         // colour-0 word at the same position covers each colour-0 site once
