@@ -94,8 +94,8 @@ typedef struct smc_params {
                            (0 = never) */
   int32_t flags;        /* enum smc_flags */
   int32_t tile;         /* 0: plain sweeps; T > 0: the tiled k-hit schedule of Sec. 2
-                           (Ising, uniform J; T % 32 == 0, L / T even; 2D T <= 256,
-                           3D T = 32): tiles of edge T coloured by (tx+ty+tz) mod 2,
+                           (Ising, uniform J; T = 16 or T % 32 == 0, L / T even;
+                           2D T <= 256, 3D T = 16 or 32): tiles of edge T coloured by (tx+ty+tz) mod 2,
                            a sweep = for tile colour 0 then 1: `hits` times colour-0
                            sites then colour-1 sites of those tiles; hit h uses
                            counter word 3 = colour | purpose << 1 | h << 8 */

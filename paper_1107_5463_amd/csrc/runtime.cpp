@@ -108,7 +108,7 @@ bool params_ok(const smc_params* p, std::string& why) {
     }
     if (p->hits < 1 || p->hits > (1 << 23)) { why = "hits must be in [1, 2^23]"; return false; }
     if (!tile_supported(make_geom(p), (uint32_t)p->tile)) {
-      why = "tile must be a multiple of 32 dividing L with L / tile even, and fit LDS";
+      why = "tile must be 16 or a multiple of 32 dividing L with L / tile even, and fit LDS";
       return false;
     }
   }

@@ -2,7 +2,7 @@
 // tile load (Sec. 2), for Ising spins with uniform couplings, under the
 // Metropolis or the heat-bath rule.
 //
-// The lattice is cut into tiles of edge T (T % 32 == 0, L / T even), coloured
+// The lattice is cut into tiles of edge T (T = 16 or T % 32 == 0, L / T even), coloured
 // by (tx + ty + tz) mod 2.  One launch treats every tile of one colour: a
 // workgroup stages its tile plus a one-site boundary layer in LDS (both colour
 // planes, rows of T/2 sites with 16 bytes of padding on each side so that
@@ -184,27 +184,164 @@ __global__ __launch_bounds__(256) void tile_kernel(const Geom g, const RngKey ke
   }
 }
 
+// Tiles of edge 16 (the tile size of the paper's measurements): a tile row
+// holds 8 sites of a colour, half of a 16-site chunk and of its Philox block.
+// A lane updates the whole 16-site chunk that holds its 8 sites and stores
+// back only those 8 bytes (the other half of the chunk is scratch): in its
+// 48-byte LDS row the tile's sites sit in the chunk's first half (even tx) or
+// second half (odd tx), the halo bytes next to them, so both in-row
+// neighbours of every tile site are read exactly as in the wide-tile kernel.
+// The workgroup's 256 lanes take one tile row each: 16 tiles per workgroup in
+// 2D, one in 3D.
+template <int D, bool HB>
+__global__ __launch_bounds__(256) void tile16_kernel(const Geom g, const RngKey key,
+                                                     const IsingTable table, const uint32_t hits,
+                                                     const uint32_t t, const uint32_t tc,
+                                                     const uint32_t ntiles, int8_t* __restrict__ s) {
+  constexpr uint32_t T = 16, TR = T + 2, RS = 48;
+  constexpr uint32_t NR = D == 3 ? TR * TR : TR;  // LDS rows per colour plane of a tile
+  constexpr uint32_t TROWS = D == 3 ? T * T : T;  // tile rows per colour
+  constexpr uint32_t G = 256 / TROWS;             // tiles per workgroup
+  constexpr uint32_t TB = 2 * NR * RS;            // LDS bytes per tile
+  extern __shared__ __align__(16) int8_t lds[];
+  const uint32_t L = (uint32_t)g.L, R = (uint32_t)g.R;
+  const uint32_t nt = L / T, half = nt / 2;
+  const uint64_t Nh = (uint64_t)g.Nh;
+  auto coords = [&](uint32_t b, uint32_t& tx, uint32_t& ty, uint32_t& tz) {
+    uint32_t rem = b;
+    tz = 0;
+    if (D == 3) {
+      tz = b / (nt * half);
+      rem = b - tz * nt * half;
+    }
+    ty = rem / half;
+    tx = 2 * (rem - ty * half) + ((ty + tz + tc) & 1u);
+  };
+  // stage both planes of each tile: 2 words per row plus the two halo bytes
+  for (uint32_t it = threadIdx.x; it < G * 2 * NR * 4; it += 256) {
+    const uint32_t gi = it / (2 * NR * 4);
+    const uint32_t b = blockIdx.x * G + gi;
+    if (b >= ntiles) continue;
+    uint32_t rest = it - gi * 2 * NR * 4;
+    const uint32_t cc = rest / (NR * 4);
+    rest -= cc * NR * 4;
+    const uint32_t r = rest / 4, wv = rest - r * 4;
+    uint32_t tx, ty, tz;
+    coords(b, tx, ty, tz);
+    const uint32_t ry = r % TR, rz = r / TR;
+    const uint32_t y = (ty * T + L - 1 + ry) % L;
+    const uint32_t z = D == 3 ? (tz * T + L - 1 + rz) % L : 0u;
+    const int8_t* src = s + cc * Nh + ((uint64_t)z * L + y) * R;
+    int8_t* dst = lds + gi * TB + (cc * NR + r) * RS + 16 + 8 * (tx & 1u);
+    const uint32_t x0 = tx * (T / 2);  // first in-colour index of the tile row
+    if (wv < 2) {
+      *reinterpret_cast<uint32_t*>(dst + 4 * wv) = *reinterpret_cast<const uint32_t*>(src + x0 + 4 * wv);
+    } else if (wv == 2) {
+      dst[-1] = src[x0 == 0 ? R - 1 : x0 - 1];
+    } else {
+      const uint32_t xr = x0 + T / 2;
+      dst[T / 2] = src[xr == R ? 0 : xr];
+    }
+  }
+  __syncthreads();
+
+  const TabRegs tab = tab_regs(table);
+  const uint32_t gi = threadIdx.x / TROWS, rowi = threadIdx.x - gi * TROWS;
+  const uint32_t b = blockIdx.x * G + gi;
+  const bool valid = b < ntiles;
+  uint32_t tx = 0, ty = 0, tz = 0;
+  if (valid) coords(b, tx, ty, tz);
+  const uint32_t odd = tx & 1u;
+  const uint32_t ry = 1 + rowi % T, rz = D == 3 ? 1 + rowi / T : 0u;
+  const uint32_t y = ty * T + ry - 1, z = D == 3 ? tz * T + rz - 1 : 0u;
+  const uint32_t r = ry + TR * rz;
+  // the chunk holding the tile row: LDS bytes 16..31, global in-colour index
+  const uint32_t jbase = (uint32_t)(((uint64_t)z * L + y) * R + tx * (T / 2) - 8 * odd);
+  for (uint32_t h = 0; h < hits; ++h) {
+    for (uint32_t c = 0; c < 2; ++c) {
+      if (valid) {
+        int8_t* own = lds + gi * TB + c * NR * RS;
+        const int8_t* oth = lds + gi * TB + (1 - c) * NR * RS;
+        const uint32_t p = (c + y + z) & 1u;
+        const Chunk o = lds16(own + r * RS + 16);
+        const Chunk ct = lds16(oth + r * RS + 16);
+        const Chunk up = lds16(oth + (r - 1) * RS + 16);
+        const Chunk dn = lds16(oth + (r + 1) * RS + 16);
+        const uint32_t e = *reinterpret_cast<const uint32_t*>(oth + r * RS + (p ? 32 : 12));
+        const Chunk sh = p ? shift_next(ct, e) : shift_prev(ct, e);
+        Chunk fz{}, bz{};
+        if (D == 3) {
+          fz = lds16(oth + (r - TR) * RS + 16);
+          bz = lds16(oth + (r + TR) * RS + 16);
+        }
+        uint32_t kk[4];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const uint32_t ow = o.w[w];
+          uint32_t k2 = ((ow ^ ct.w[w]) & kBit1) + ((ow ^ sh.w[w]) & kBit1) +
+                        ((ow ^ up.w[w]) & kBit1) + ((ow ^ dn.w[w]) & kBit1);
+          if (D == 3) k2 += ((ow ^ fz.w[w]) & kBit1) + ((ow ^ bz.w[w]) & kBit1);
+          kk[w] = k2 >> 1;
+        }
+        const Chunk nw = HB ? heatbath_chunk(tab, key, t, c, jbase, o, kk, 2 * D, h)
+                            : update_chunk_now(tab, key, t, c, jbase, o, kk, h);
+        *reinterpret_cast<uint2*>(own + r * RS + 16 + 8 * odd) =
+            odd ? make_uint2(nw.w[2], nw.w[3]) : make_uint2(nw.w[0], nw.w[1]);
+      }
+      __syncthreads();
+    }
+  }
+
+  // write back the tiles' own rows of both colours
+  for (uint32_t it = threadIdx.x; it < G * 2 * TROWS * 2; it += 256) {
+    const uint32_t gw = it / (2 * TROWS * 2);
+    const uint32_t bw = blockIdx.x * G + gw;
+    if (bw >= ntiles) continue;
+    uint32_t rest = it - gw * 2 * TROWS * 2;
+    const uint32_t cc = rest / (TROWS * 2);
+    rest -= cc * TROWS * 2;
+    const uint32_t ri = rest / 2, wv = rest - ri * 2;
+    uint32_t wx, wy, wz;
+    coords(bw, wx, wy, wz);
+    const uint32_t wry = 1 + ri % T, wrz = D == 3 ? 1 + ri / T : 0u;
+    const uint32_t wr = wry + TR * wrz;
+    const uint32_t yy = wy * T + wry - 1, zz = D == 3 ? wz * T + wrz - 1 : 0u;
+    int8_t* dst = s + cc * Nh + ((uint64_t)zz * L + yy) * R + wx * (T / 2) + 4 * wv;
+    *reinterpret_cast<uint32_t*>(dst) = *reinterpret_cast<const uint32_t*>(
+        lds + gw * TB + (cc * NR + wr) * RS + 16 + 8 * (wx & 1u) + 4 * wv);
+  }
+}
+
 size_t tile_lds_bytes(int d, uint32_t T) {
   const size_t TR = T + 2;
+  if (T == 16) {  // 48-byte rows, 256 / 16^(d-1) tiles per workgroup
+    const size_t G = d == 3 ? 1 : 16;
+    return G * 2 * (d == 3 ? TR * TR : TR) * 48;
+  }
   return 2 * (d == 3 ? TR * TR : TR) * (T / 2 + 32);
 }
 
 bool tile_supported(const Geom& g, uint32_t T) {
-  return T >= 32 && T % 32 == 0 && (uint32_t)g.L % T == 0 && ((uint32_t)g.L / T) % 2 == 0 &&
-         tile_lds_bytes(g.d, T) <= 160 * 1024;
+  return (T == 16 || (T >= 32 && T % 32 == 0)) && (uint32_t)g.L % T == 0 &&
+         ((uint32_t)g.L / T) % 2 == 0 && tile_lds_bytes(g.d, T) <= 160 * 1024;
 }
 
-static const void* tile_fn(int d, bool hb) {
+static const void* tile_fn(int d, bool hb, bool t16) {
+  if (t16) {
+    if (d == 2) return hb ? (const void*)tile16_kernel<2, true> : (const void*)tile16_kernel<2, false>;
+    return hb ? (const void*)tile16_kernel<3, true> : (const void*)tile16_kernel<3, false>;
+  }
   if (d == 2) return hb ? (const void*)tile_kernel<2, true> : (const void*)tile_kernel<2, false>;
   return hb ? (const void*)tile_kernel<3, true> : (const void*)tile_kernel<3, false>;
 }
 
 hipError_t tile_allow_lds(int d, size_t bytes) {
-  for (int hb = 0; hb < 2; ++hb) {
-    const hipError_t e = hipFuncSetAttribute(tile_fn(d, hb != 0),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-  }
+  for (int t16 = 0; t16 < 2; ++t16)
+    for (int hb = 0; hb < 2; ++hb) {
+      const hipError_t e = hipFuncSetAttribute(tile_fn(d, hb != 0, t16 != 0),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+      if (e != hipSuccess) return e;
+    }
   return hipSuccess;
 }
 
@@ -213,6 +350,23 @@ hipError_t launch_tile_pass(const IsingLaunch& a, bool heatbath, uint32_t T, uin
                             int8_t* spins, uint32_t t, uint32_t tc, hipStream_t st) {
   const uint32_t nt = (uint32_t)a.g.L / T;
   const uint32_t tiles = (a.g.d == 3 ? nt * nt * nt : nt * nt) / 2;
+  if (T == 16) {
+    const uint32_t G = a.g.d == 3 ? 1 : 16;
+    const dim3 grid((tiles + G - 1) / G), block(256);
+    const size_t lds = tile_lds_bytes(a.g.d, 16);
+    if (a.g.d == 2) {
+      if (heatbath)
+        hipLaunchKernelGGL((tile16_kernel<2, true>), grid, block, lds, st, a.g, a.key, a.tab, hits, t, tc, tiles, spins);
+      else
+        hipLaunchKernelGGL((tile16_kernel<2, false>), grid, block, lds, st, a.g, a.key, a.tab, hits, t, tc, tiles, spins);
+    } else {
+      if (heatbath)
+        hipLaunchKernelGGL((tile16_kernel<3, true>), grid, block, lds, st, a.g, a.key, a.tab, hits, t, tc, tiles, spins);
+      else
+        hipLaunchKernelGGL((tile16_kernel<3, false>), grid, block, lds, st, a.g, a.key, a.tab, hits, t, tc, tiles, spins);
+    }
+    return hipGetLastError();
+  }
   const uint32_t cpr = T / 32;
   const uint32_t nchunks = (a.g.d == 3 ? T * T : T) * cpr;
   const uint32_t threads = nchunks >= 256 ? 256 : (nchunks + 63) / 64 * 64;

@@ -148,6 +148,7 @@ def test_chain_init_rejects_bad_arguments(smc_host):
 
 @pytest.mark.parametrize("kw,msg", [
     (dict(tile=33, hits=2, L=66), b"tile must be"),
+    (dict(tile=48, hits=2, L=96), b"tile must be"),         # neither 16 nor a multiple of 32
     (dict(tile=32, hits=2, L=96), b"tile must be"),         # L / T odd
     (dict(tile=32, hits=0, L=64), b"hits must be"),
     (dict(tile=0, hits=5, L=64), b"hits must be 0 or 1"),
@@ -177,3 +178,11 @@ def test_packed_buffer_sizes(smc_host):
     q = smc_host.make_params(3, 1, 128, 1, J_kind=smc_host.J_PM, flags=smc_host.FLAG_PACKED)
     assert lib.smc_coupling_bytes(C.byref(q)) == 3 * 128 ** 3 // 8
     assert lib.smc_bond_bytes(C.byref(q)) == 0
+
+
+@pytest.mark.parametrize("d,L,T", [(2, 64, 16), (3, 32, 16), (2, 64, 32), (2, 512, 256)])
+def test_tile_sizes_accepted(smc_host, d, L, T):
+    """The paper's 16 x 16 tiles and multiples of 32 pass validation."""
+    lib = smc_host.load_library()
+    p = smc_host.make_params(d, 1, L, 1, tile=T, hits=3)
+    assert lib.smc_spin_bytes(C.byref(p)) == L ** d

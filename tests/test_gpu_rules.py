@@ -33,6 +33,11 @@ TILED = [  # d, L, tile, hits, heatbath, beta, sweeps
     (2, 64, 32, 4, True, BETA_C, 4),
     (3, 64, 32, 2, False, 0.2216546, 2),
     (3, 64, 32, 1, True, 0.25, 2),
+    (2, 64, 16, 3, False, BETA_C, 4),      # the paper's 16 x 16 tiles
+    (2, 160, 16, 2, False, 0.6, 3),        # 50 tiles per colour: a partly filled workgroup
+    (2, 64, 16, 2, True, BETA_C, 3),
+    (3, 32, 16, 2, False, 0.2216546, 2),
+    (3, 32, 16, 1, True, 0.25, 2),
 ]
 
 
