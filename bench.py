@@ -242,9 +242,11 @@ def valu_roofline(kname, workload, kernel_ms, bytes_per_launch, variant=None):
     path = os.path.join(ROOT, "profiles", f"{kname}_{workload}_valu.json")
     if os.path.exists(path):
         with open(path) as fh:
-            rec = json.load(fh)
-        if rec.get("sources_sha256_16") != sources_digest(kname) or rec.get("variant") != variant:
-            rec = None
+            recs = json.load(fh)
+        # one record, or a list of records of different variants
+        for r in recs if isinstance(recs, list) else [recs]:
+            if r.get("sources_sha256_16") == sources_digest(kname) and r.get("variant") == variant:
+                rec = r
     achieved = None
     if rec is not None:
         achieved = rec["valu_lane_ops_per_launch"] / (kernel_ms * 1e-3) / 1e12
