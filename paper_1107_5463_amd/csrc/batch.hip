@@ -17,7 +17,10 @@
 // (rows of whole 2-site pairs, L/2 even, two sites per op):
 // neighbour words from LDS (the in-row neighbours as the centre word shifted
 // by one byte), unsatisfied-bond counts per byte, and the byte-wise threshold
-// compare of the single-lattice kernels.  With MEASURE the workgroup also
+// compare of the single-lattice kernels.  The index arithmetic of a word
+// (its row, the periodic wraps of its neighbours) is formed once per call when
+// each lane holds one group, and once per group when a group is a whole part
+// of one plane row (L/2 % 16 == 0).  With MEASURE the workgroup also
 // reduces E and M of its state from LDS after every `every` sweeps (record m
 // of the call at obs[m * n_lattices + lattice]; with no sweeps, one record of
 // the current state).
@@ -126,7 +129,18 @@ __global__ __launch_bounds__(1024) void batch_kernel(const BatchDesc* __restrict
   auto ld = [&](const int8_t* base, uint32_t i) -> uint32_t {
     return *reinterpret_cast<const uint32_t*>(base + i);
   };
-  // unsatisfied-bond counts (byte b: site j + b) of a 4-site word of plane c
+  // Unsatisfied bonds per byte of the own word W against its 2d neighbour
+  // words: the spin bits differ, xor the bond's sign bit.
+  auto count_bytes = [&](uint32_t W, const uint32_t nb[6]) -> uint32_t {
+    uint32_t k = 0;
+#pragma unroll
+    for (int m = 0; m < 2 * D; ++m) {
+      uint32_t u = W ^ nb[m];
+      if (PM) u ^= W >> (1 + m);
+      k += u & kOnes;
+    }
+    return k;
+  };
   // Unsatisfied-bond counts (byte b: site j + b) of a WB-site word of plane c
   // (WB = 4: j % 4 == 0 and R % 4 == 0; WB = 2: j even and R even; the word
   // lies in one plane row).  The in-row neighbours are the centre word
@@ -164,26 +178,14 @@ __global__ __launch_bounds__(1024) void batch_kernel(const BatchDesc* __restrict
       nb[4] = ldw(oth, z + 1 == L ? j - sZw : j + sZ);
       nb[5] = ldw(oth, z == 0 ? j + sZw : j - sZ);
     }
-    // unsatisfied bonds per byte: spin bits differ, xor the bond's sign bit
-    uint32_t k = 0;
-#pragma unroll
-    for (int m = 0; m < 2 * D; ++m) {
-      uint32_t u = W ^ nb[m];
-      if (PM) u ^= W >> (1 + m);
-      k += u & kOnes;
-    }
-    return k;
+    return count_bytes(W, nb);
   };
   // New word for prefix bytes P (byte b: site j + b); `tie` gets bit 7 of
   // each byte whose prefix equals the threshold byte of a refusable class
   // (left unflipped), `kout` the counts.  Only the low WB bytes of the
   // result are meaningful.
-  auto word = [&](auto wb, const int8_t* own, const int8_t* oth, uint32_t c, uint32_t j,
-                  uint32_t P, uint32_t& tie, uint32_t& kout) -> uint32_t {
+  auto decide = [&](auto wb, uint32_t W, uint32_t k, uint32_t P, uint32_t& tie) -> uint32_t {
     constexpr uint32_t WB = decltype(wb)::value;
-    uint32_t W;
-    const uint32_t k = counts(wb, own, oth, c, j, W);
-    kout = k;
     const uint32_t Th = __builtin_amdgcn_perm(th_hi, th_lo, k);
     const uint32_t Al = __builtin_amdgcn_perm(al_hi, al_lo, k);
     const uint32_t x = P ^ Th;
@@ -193,6 +195,13 @@ __global__ __launch_bounds__(1024) void batch_kernel(const BatchDesc* __restrict
     const uint32_t zb = (x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
     tie = ~(zb | x | Al) & (WB == 4 ? kHigh : 0x8080u);
     return W ^ ((~rej | Al) & kOnes);
+  };
+  auto word = [&](auto wb, const int8_t* own, const int8_t* oth, uint32_t c, uint32_t j,
+                  uint32_t P, uint32_t& tie, uint32_t& kout) -> uint32_t {
+    uint32_t W;
+    const uint32_t k = counts(wb, own, oth, c, j, W);
+    kout = k;
+    return decide(wb, W, k, P, tie);
   };
   using W4 = std::integral_constant<uint32_t, 4>;
   using W2 = std::integral_constant<uint32_t, 2>;
@@ -259,11 +268,138 @@ __global__ __launch_bounds__(1024) void batch_kernel(const BatchDesc* __restrict
     }
   };
   const uint32_t ngroups = (Nh + 15) / 16;
+  // One group per lane (a lattice with no more groups than lanes): the lane
+  // sees the same four words in every half-sweep of the call, so their plane
+  // indices and those of their neighbour words (periodic wraps included) are
+  // formed once here.  Slot s holds word ws = (s + lane / 8) % 4 of the group
+  // (the bank-spreading order of the general path); fpar bit s is the
+  // word's (row + z) parity, fval bit s marks the words inside the plane.
+  const bool fast = words && ngroups <= blockDim.x;
+  uint32_t fj[4], fyp[4], fym[4], fzp[4], fzm[4], fe1[4], fe0[4];
+  uint32_t fpar = 0, fval = 0;
+  if (fast && threadIdx.x < ngroups) {
+#pragma unroll
+    for (uint32_t sl = 0; sl < 4; ++sl) {
+      const uint32_t ws = (sl + (threadIdx.x >> 3)) & 3u;
+      const uint32_t j = 16 * threadIdx.x + 4 * ws;
+      const uint32_t jc = j < Nh ? j : 0u;  // words past the plane's end: never used
+      fval |= (j < Nh ? 1u : 0u) << sl;
+      const uint32_t r = fdiv(jc, divR);
+      const uint32_t rowb = r * R;
+      const uint32_t jx = jc - rowb;
+      const uint32_t z = D == 3 ? fdiv(r, divL) : 0u;
+      const uint32_t y = r - z * L;
+      fpar |= ((r + z) & 1u) << sl;
+      fj[sl] = jc;
+      fe1[sl] = jx + 4 == R ? rowb : jc + 4;
+      fe0[sl] = jx == 0 ? rowb + R - 4 : jc - 4;
+      fyp[sl] = y + 1 == L ? jc - sYw : jc + R;
+      fym[sl] = y == 0 ? jc + sYw : jc - R;
+      fzp[sl] = fzm[sl] = 0;
+      if (D == 3) {
+        fzp[sl] = z + 1 == L ? jc - sZw : jc + sZ;
+        fzm[sl] = z == 0 ? jc + sZw : jc - sZ;
+      }
+    }
+  }
   for (uint32_t sw = 0; sw < n_sweeps; ++sw) {
     const uint32_t t = t0 + sw;
     for (uint32_t c = 0; c < 2; ++c) {
       int8_t* own = lat + c * Nh;
       const int8_t* oth = lat + (1 - c) * Nh;
+      if (fast) {
+        if (threadIdx.x < ngroups) {
+          const uint32_t g = threadIdx.x;
+          const Rand4 rp = philox(g, t, replica, tag(c, kIsingPrefix), key.k0, key.k1);
+#pragma unroll
+          for (uint32_t sl = 0; sl < 4; ++sl) {
+            if ((fval >> sl) & 1u) {
+              const uint32_t ws = (sl + (g >> 3)) & 3u;
+              const uint32_t j = fj[sl];
+              const uint32_t p = (c ^ (fpar >> sl)) & 1u;
+              const uint32_t W = ld(own, j);
+              const uint32_t C = ld(oth, j);
+              const uint32_t E = ld(oth, p ? fe1[sl] : fe0[sl]);
+              const uint32_t S = p ? __builtin_amdgcn_alignbyte(E, C, 1) : __builtin_amdgcn_alignbyte(C, E, 3);
+              uint32_t nb[6];
+              nb[0] = p ? S : C;  // +x
+              nb[1] = p ? C : S;  // -x
+              nb[2] = ld(oth, fyp[sl]);
+              nb[3] = ld(oth, fym[sl]);
+              nb[4] = nb[5] = 0;
+              if (D == 3) {
+                nb[4] = ld(oth, fzp[sl]);
+                nb[5] = ld(oth, fzm[sl]);
+              }
+              const uint32_t k = count_bytes(W, nb);
+              uint32_t tie;
+              const uint32_t nw = decide(W4{}, W, k, word_of(rp.w, ws), tie);
+              *reinterpret_cast<uint32_t*>(own + j) = nw;
+              while (tie) {
+                const uint32_t b = (uint32_t)__builtin_ctz(tie) >> 3;
+                tie &= tie - 1;
+                if (nq == kBatchTieSlots) flush(own, c, t);
+                tq[nq * blockDim.x] = ((j + b) << 3) | ((k >> (8 * b)) & 7u);
+                ++nq;
+              }
+            }
+          }
+        }
+        flush(own, c, t);
+        __syncthreads();
+        continue;
+      }
+      if (words && (R & 15u) == 0) {
+        // plane rows of whole groups: a group's four words share the row, its
+        // parity and the periodic wraps of their y and z neighbours, formed
+        // once per group
+        for (uint32_t g = threadIdx.x; g < ngroups; g += blockDim.x) {
+          const uint32_t j0 = 16 * g;
+          const Rand4 rp = philox(g, t, replica, tag(c, kIsingPrefix), key.k0, key.k1);
+          const uint32_t r = fdiv(j0, divR);
+          const uint32_t rowb = r * R;
+          const uint32_t jx0 = j0 - rowb;
+          const uint32_t z = D == 3 ? fdiv(r, divL) : 0u;
+          const uint32_t y = r - z * L;
+          const uint32_t p = (c + r + z) & 1u;
+          const uint32_t dyp = y + 1 == L ? 0u - sYw : R, dym = y == 0 ? sYw : 0u - R;
+          const uint32_t dzp = z + 1 == L ? 0u - sZw : sZ, dzm = z == 0 ? sZw : 0u - sZ;
+#pragma unroll
+          for (uint32_t w = 0; w < 4; ++w) {
+            const uint32_t ws = (w + (threadIdx.x >> 3)) & 3u;
+            const uint32_t j = j0 + 4 * ws;
+            const uint32_t jx = jx0 + 4 * ws;
+            const uint32_t W = ld(own, j);
+            const uint32_t C = ld(oth, j);
+            const uint32_t E = ld(oth, p ? (jx + 4 == R ? rowb : j + 4) : (jx == 0 ? rowb + R - 4 : j - 4));
+            const uint32_t S = p ? __builtin_amdgcn_alignbyte(E, C, 1) : __builtin_amdgcn_alignbyte(C, E, 3);
+            uint32_t nb[6];
+            nb[0] = p ? S : C;  // +x
+            nb[1] = p ? C : S;  // -x
+            nb[2] = ld(oth, j + dyp);
+            nb[3] = ld(oth, j + dym);
+            nb[4] = nb[5] = 0;
+            if (D == 3) {
+              nb[4] = ld(oth, j + dzp);
+              nb[5] = ld(oth, j + dzm);
+            }
+            const uint32_t k = count_bytes(W, nb);
+            uint32_t tie;
+            const uint32_t nw = decide(W4{}, W, k, word_of(rp.w, ws), tie);
+            *reinterpret_cast<uint32_t*>(own + j) = nw;
+            while (tie) {
+              const uint32_t b = (uint32_t)__builtin_ctz(tie) >> 3;
+              tie &= tie - 1;
+              if (nq == kBatchTieSlots) flush(own, c, t);
+              tq[nq * blockDim.x] = ((j + b) << 3) | ((k >> (8 * b)) & 7u);
+              ++nq;
+            }
+          }
+        }
+        flush(own, c, t);
+        __syncthreads();
+        continue;
+      }
       if (words) {
         // Nh is a multiple of 4: a group holds nj / 4 whole words
         for (uint32_t g = threadIdx.x; g < ngroups; g += blockDim.x) {
