@@ -22,6 +22,23 @@
 
 namespace smc {
 
+// Non-temporal 16-byte load and store: the whole-row kernel streams the old
+// state in and the new one out once per launch (its halo rows excepted), and
+// the two 256 MiB states of the L = 16384 lattice do not stay in the caches
+// between launches; on the MI355X these accesses raised the sweep rate by 8 %.
+__device__ __forceinline__ Chunk ld16nt(const int8_t* p) {
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u*>(p));
+  Chunk c;
+  c.w[0] = v.x; c.w[1] = v.y; c.w[2] = v.z; c.w[3] = v.w;
+  return c;
+}
+__device__ __forceinline__ void st16nt(int8_t* p, const uint32_t w[4]) {
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  v4u v = {w[0], w[1], w[2], w[3]};
+  __builtin_nontemporal_store(v, reinterpret_cast<v4u*>(p));
+}
+
 template <bool MEASURE>
 __global__ __launch_bounds__(512) void ising_fused2d_kernel(const Geom g, const RngKey key,
                                                              const IsingTable table,
@@ -90,7 +107,7 @@ __global__ __launch_bounds__(512) void ising_fused2d_kernel(const Geom g, const 
     N0[PH] = update_chunk_now(tab, key, t, 0u, off0, a0c, kk);
     const Chunk& n0c = N0[PH];
     if (store0) {
-      st16(B0 + off0, n0c.w);
+      st16nt(B0 + off0, n0c.w);
       if (MEASURE) Msum += chunk_spin_sum(n0c);
     }
     // new colour 1, row y - 1
@@ -99,7 +116,7 @@ __global__ __launch_bounds__(512) void ising_fused2d_kernel(const Geom g, const 
       const Chunk shn = p ? shift_next(n0m1, e_n) : shift_prev(n0m1, e_n);
       counts2d(a1m, n0m1, shn, n0m2, n0c, kk);
       const Chunk n1 = update_chunk_deferred<2>(tab, key, t, 1u, off1, y - 1 - y0, a1m, kk, tq, B1);
-      st16(B1 + off1, n1.w);
+      st16nt(B1 + off1, n1.w);
       if (MEASURE) {
         uint32_t kn[4];
         counts2d(n1, n0m1, shn, n0m2, n0c, kn);
@@ -107,16 +124,16 @@ __global__ __launch_bounds__(512) void ising_fused2d_kernel(const Geom g, const 
         Msum += chunk_spin_sum(n1);
       }
     }
-    A1[(PH + 3) & 3] = ld16(A1g + frow(y + 3));
-    A0r[PH & 1] = ld16(A0 + frow(y + 2));
+    A1[(PH + 3) & 3] = ld16nt(A1g + frow(y + 3));
+    A0r[PH & 1] = ld16nt(A0 + frow(y + 2));
   };
 
-  A1[2] = ld16(A1g + frow(y0 + L - 2));  // row y0 - 2 (frow takes rows < 2L)
-  A1[3] = ld16(A1g + frow(y0 + L - 1));
-  A1[0] = ld16(A1g + frow(y0));
-  A1[1] = ld16(A1g + frow(y0 + 1));
-  A0r[1] = ld16(A0 + frow(y0 + L - 1));
-  A0r[0] = ld16(A0 + frow(y0));
+  A1[2] = ld16nt(A1g + frow(y0 + L - 2));  // row y0 - 2 (frow takes rows < 2L)
+  A1[3] = ld16nt(A1g + frow(y0 + L - 1));
+  A1[0] = ld16nt(A1g + frow(y0));
+  A1[1] = ld16nt(A1g + frow(y0 + 1));
+  A0r[1] = ld16nt(A0 + frow(y0 + L - 1));
+  A0r[0] = ld16nt(A0 + frow(y0));
   N0[0] = N0[1] = N0[2] = A0r[0];
   {
     // prologue: new colour-0 row y0 - 1 (odd row: parity 1), formed, not stored
@@ -126,8 +143,8 @@ __global__ __launch_bounds__(512) void ising_fused2d_kernel(const Geom g, const 
     uint32_t kk[4];
     counts2d(A0r[1], A1[3], sh, A1[2], A1[0], kk);
     N0[3] = update_chunk_now(tab, key, t, 0u, frow(y0 + L - 1), A0r[1], kk);
-    A1[2] = ld16(A1g + frow(y0 + 2));
-    A0r[1] = ld16(A0 + frow(y0 + 1));
+    A1[2] = ld16nt(A1g + frow(y0 + 2));
+    A0r[1] = ld16nt(A0 + frow(y0 + 1));
   }
   for (uint32_t i = 0; i < H; i += 4) {
     const uint32_t y = y0 + i;
