@@ -97,6 +97,8 @@ def parse():
     ap.add_argument("--heatbath", action="store_true", help="Ising workloads: heat-bath rule")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="approximate host time of the oracle baseline (0 = skip)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="default 2D line: skip the batched spin-glass comparison attached to it")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB device copy before the timed region (calibrates the "
                          "HBM byte counters of a profiler run)")
@@ -628,6 +630,16 @@ def main():
         result = run_chains(args, wl, torch, smc)
     else:
         result = run_lattice(args, wl, torch, smc)
+        special = bool(args.tile or args.heatbath or args.schedule == "fused")
+        if args.workload == "ising2d" and not special and not args.no_batched:
+            # the second half of the metric: the batched spin-glass workload
+            # (one persistent launch of 10^4 sweeps) against the single-lattice path
+            bargs = argparse.Namespace(**vars(args))
+            bargs.steps, bargs.warmup, bargs.sweeps_per_step, bargs.cpu_seconds = 1, 1, None, 0
+            bres = run_batched(bargs, WORKLOADS["batched"], torch, smc)
+            result["batched"] = {k: bres[k] for k in ("value", "unit", "ms_per_step", "batched_vs_plain",
+                                                      "plain", "roofline")}
+            result["batched"]["workload"] = bres["config"]["workload"]
     print(json.dumps(result), flush=True)
 
 

@@ -162,3 +162,17 @@ def test_batch_ensemble_matches_exact_propagation(smc_gpu, oracle_mod, kind, bet
         pi = chain.sweep(pi)
     stat, dof = _chi2_states(ex.state_index(got), pi)
     assert stat < chi2.ppf(1 - 1e-4, dof), (stat, dof)
+
+
+@pytest.mark.parametrize("d,Ls,kind", [(2, [128, 96, 64, 32], 1), (3, [32, 24, 16], 0)])
+def test_batch_index_paths_match_oracle(smc_gpu, oracle_mod, d, Ls, kind):
+    """With 256 lanes per lattice: lattices of at most 256 groups of 16 sites
+    (indices formed once per call), longer ones whose plane rows hold whole
+    groups (L/2 % 16 == 0: formed once per group) and the rest (per word)."""
+    import torch
+    n = len(Ls)
+    beta = [0.35 + 0.3 * r for r in range(n)]
+    b = smc_gpu.Batch(d, Ls, beta, seed=23, J_kind=kind)
+    obs = torch.zeros((n, 8), dtype=torch.int64, device=b.device)
+    b.sweep(6, obs)
+    _check(smc_gpu, oracle_mod, b, d, Ls, beta, kind, 6, 23, smc_gpu.Lattice.decode_obs(obs))
