@@ -286,13 +286,17 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
     tq.dM = 0;
     // J planes: J[mu][cc] at (2 mu + cc) * Wh
     const uint32_t pz = (c + z) & 1u;
+    // a band stays inside its z-plane (H divides L): the rows' word offsets
+    // step by W, and only the y + 1 neighbour of row L - 1 wraps (to row 0)
+    const uint32_t row0 = rw(zrow, y0), wrap0 = zrow * W;
     uint32_t up = ldw(oth, rw(zrow, y0 + L - 1) + q);
-    uint32_t ct = ldw(oth, rw(zrow, y0) + q);
-    for (uint32_t i = 0; i < H; ++i) {
+    uint32_t ct = ldw(oth, row0 + q);
+    uint32_t rowb = row0;
+    uint32_t zmb = (zm_row + y0) * W, zpb = (zp_row + y0) * W;  // z - 1 and z + 1 rows (3D)
+    for (uint32_t i = 0; i < H; ++i, rowb += W, zmb += W, zpb += W) {
       const uint32_t y = y0 + i;
-      const uint32_t rowb = rw(zrow, y);
       const uint32_t p = (pz + y) & 1u;
-      const uint32_t dn = ldw(oth, rw(zrow, y + 1) + q);
+      const uint32_t dn = ldw(oth, (y + 1 == L ? wrap0 : rowb + W) + q);
       const uint32_t o = ldw(own, rowb + q);
       const uint32_t en = ldw(oth, rowb + qn), ep = ldw(oth, rowb + qp);
       // x+1 neighbours (p = 1: next in-row site) and x-1 (p = 0: previous)
@@ -307,8 +311,8 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
       u[3] = o ^ up;
       uint32_t fz = 0, bz = 0;
       if (D == 3) {
-        fz = ldw(oth, rw(zm_row, y) + q);
-        bz = ldw(oth, rw(zp_row, y) + q);
+        fz = ldw(oth, zmb + q);
+        bz = ldw(oth, zpb + q);
         u[4] = o ^ bz;
         u[5] = o ^ fz;
       }
@@ -320,10 +324,10 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
         u[0] ^= ldw(Jo, rowb + q);
         u[1] ^= mask_sel(__builtin_amdgcn_alignbit(jc, jp_prev, 31u), jc, p);
         u[2] ^= ldw(Jo, 2 * Wh + rowb + q);
-        u[3] ^= ldw(Jn, 2 * Wh + rw(zrow, y + L - 1) + q);
+        u[3] ^= ldw(Jn, 2 * Wh + (y == 0 ? rw(zrow, L - 1) : rowb - W) + q);
         if (D == 3) {
           u[4] ^= ldw(Jo, 4 * Wh + rowb + q);
-          u[5] ^= ldw(Jn, 4 * Wh + rw(zm_row, y) + q);
+          u[5] ^= ldw(Jn, 4 * Wh + zmb + q);
         }
       }
       uint32_t k0, k1, k2;
