@@ -525,8 +525,7 @@ hipError_t batch_allow_lds(size_t bytes) {
   hipError_t e = hipSuccess;
 #define SMC_BA(DD, PMM, MM)                                                                     \
   if (e == hipSuccess)                                                                          \
-    e = hipFuncSetAttribute((const void*)batch_kernel<DD, PMM, MM>,                             \
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes)
+    e = allow_dynamic_lds((const void*)batch_kernel<DD, PMM, MM>, bytes)
   SMC_BA(2, true, true); SMC_BA(2, true, false); SMC_BA(2, false, true); SMC_BA(2, false, false);
   SMC_BA(3, true, true); SMC_BA(3, true, false); SMC_BA(3, false, true); SMC_BA(3, false, false);
 #undef SMC_BA

@@ -266,8 +266,7 @@ hipError_t chains_allow_lds(const Geom& g) {
   for (int mode = 0; mode < 3; ++mode) {
     const size_t ljl = chains_lds_bytes_jl(g, mode);
     const size_t b = ljl ? ljl : chains_lds_bytes(g, mode);
-    const hipError_t e = hipFuncSetAttribute(chains_fn(g.d, mode, ljl != 0),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)b);
+    const hipError_t e = allow_dynamic_lds(chains_fn(g.d, mode, ljl != 0), b);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

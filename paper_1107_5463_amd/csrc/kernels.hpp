@@ -20,6 +20,11 @@ struct FastDiv {
 };
 FastDiv make_fastdiv(uint32_t d);
 
+// Raises kernel fn's dynamic-LDS limit on the current device to at least
+// `bytes`, never lowering it: handles of different sizes share the kernels,
+// and a later, smaller handle must not take LDS from an earlier one.
+hipError_t allow_dynamic_lds(const void* fn, size_t bytes);
+
 enum IsingVariant { kVariantAuto = 0, kVariantSite = 1, kVariantChunk = 2, kVariantStream = 3,
                     kVariantFusedWave = 4 };  // fused schedule: wave-segment kernel (no barriers)
 

@@ -15,6 +15,9 @@
 #include <string>
 #include <vector>
 #include <algorithm>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "kernels.hpp"
 #include "smc.h"
@@ -22,6 +25,20 @@
 static_assert(sizeof(smc_obs) == 64, "smc_obs is eight 8-byte fields");
 
 using namespace smc;
+
+hipError_t smc::allow_dynamic_lds(const void* fn, size_t bytes) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, size_t> granted;  // (device, kernel) -> limit set
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  size_t& g = granted[{dev, fn}];
+  if (bytes <= g) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) g = bytes;
+  return e;
+}
 
 struct smc_lattice {
   smc_params p;

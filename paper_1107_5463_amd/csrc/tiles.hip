@@ -338,8 +338,7 @@ static const void* tile_fn(int d, bool hb, bool t16) {
 hipError_t tile_allow_lds(int d, size_t bytes) {
   for (int t16 = 0; t16 < 2; ++t16)
     for (int hb = 0; hb < 2; ++hb) {
-      const hipError_t e = hipFuncSetAttribute(tile_fn(d, hb != 0, t16 != 0),
-                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+      const hipError_t e = allow_dynamic_lds(tile_fn(d, hb != 0, t16 != 0), bytes);
       if (e != hipSuccess) return e;
     }
   return hipSuccess;

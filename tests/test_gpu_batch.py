@@ -176,3 +176,13 @@ def test_batch_index_paths_match_oracle(smc_gpu, oracle_mod, d, Ls, kind):
     obs = torch.zeros((n, 8), dtype=torch.int64, device=b.device)
     b.sweep(6, obs)
     _check(smc_gpu, oracle_mod, b, d, Ls, beta, kind, 6, 23, smc_gpu.Lattice.decode_obs(obs))
+
+
+def test_batch_lds_limit_survives_a_smaller_batch(smc_gpu, oracle_mod):
+    """A batch holding a 65536-site lattice needs more than 64 KiB of LDS per
+    workgroup; a smaller batch created afterwards must not lower the limit."""
+    big = smc_gpu.Batch(2, [256, 8], [0.45, 0.7], seed=31, J_kind=1)
+    small = smc_gpu.Batch(2, [8, 12], [0.5, 0.6], seed=32, J_kind=1)
+    small.sweep(2)
+    big.sweep(2)
+    _check(smc_gpu, oracle_mod, big, 2, [256, 8], [0.45, 0.7], 1, 2, 31)

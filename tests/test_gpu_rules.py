@@ -71,3 +71,17 @@ def test_tiled_half_sweep_is_refused(smc_gpu):
     lat = smc_gpu.Lattice(2, 1, 64, seed=1, tile=32, hits=2)
     with pytest.raises(smc_gpu.SmcError):
         lat.half_sweep(0.4, 0)
+
+
+def test_tile_lds_limit_survives_a_smaller_handle(smc_gpu, oracle_mod):
+    """A lattice with 256 x 256 tiles needs more than 64 KiB of LDS per
+    workgroup; creating a lattice with small tiles afterwards must not lower
+    the kernels' LDS limit under it."""
+    print("tiles: T=256 lattice after a T=16 one", flush=True)
+    big = smc_gpu.Lattice(2, 1, 512, seed=5, tile=256, hits=2)
+    small = smc_gpu.Lattice(2, 1, 64, seed=6, tile=16, hits=2)
+    small.sweep(0.5, 1)
+    big.sweep(0.5, 1)
+    ref = oracle_mod.OracleLattice(2, 1, 512, 5)
+    ref.sweep_rule(0.5, 1, "metropolis", 256, 2)
+    assert np.array_equal(nat(big), ref.s)
