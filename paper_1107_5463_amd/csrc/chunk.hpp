@@ -256,7 +256,9 @@ __device__ __forceinline__ void tie_flush(TieQueue& q, const TabRegs& tab, const
 }
 
 // Metropolis update of one chunk (plane row `row` of the band) with its ties
-// queued; a full queue is flushed first.
+// queued.  A queue without room for the chunk's ties (at most 16, fewer than
+// the slots) is flushed before any of them is queued: a flush writes its
+// flips to the plane, so it must only hold ties of chunks already stored.
 template <int D>
 __device__ __forceinline__ Chunk update_chunk_deferred(const TabRegs& tab, const RngKey& key,
                                                        uint32_t t, uint32_t c, uint32_t jbase,
@@ -270,8 +272,8 @@ __device__ __forceinline__ Chunk update_chunk_deferred(const TabRegs& tab, const
   for (int w = 0; w < 4; ++w) n.w[w] = decide4_tie(tab, o.w[w], kk[w], rp.w[w], tie[w]);
   if ((tie[0] | tie[1] | tie[2] | tie[3]) & kHigh) {
     uint32_t m = tie_mask16(tie);
+    if (q.n + (uint32_t)__builtin_popcount(m) > kTieSlots) tie_flush<D>(q, tab, key, t, c, own);
     do {
-      if (q.n == kTieSlots) tie_flush<D>(q, tab, key, t, c, own);
       const uint32_t idx = __builtin_ctz(m);
       m &= m - 1;
       const uint32_t w = idx >> 2, sh = 8 * (idx & 3u);

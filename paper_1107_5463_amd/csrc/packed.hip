@@ -22,8 +22,8 @@
 //    as 8 bit planes too, and one bit-sliced compare against them gives the
 //    refused sites and the exact ties;
 //  * exact ties (prefix byte == threshold byte, 2^-8 of refusable moves) are
-//    queued in LDS and resolved at the end of the band with each site's
-//    24-bit refinement draw, as in the int8 kernel.
+//    queued in LDS once their word is stored and resolved at the end of the
+//    band with each site's 24-bit refinement draw, as in the int8 kernel.
 #include <type_traits>
 
 #include "chunk.hpp"
@@ -128,14 +128,15 @@ __device__ __forceinline__ void packed_tie_flush(PackedTies& q, const TabRegs& t
   q.n = 0;
 }
 
-// Decision for the 32 sites of one word.  kq: count planes; returns the
-// flip mask; queues exact ties.
+constexpr uint32_t kPackedTieSlots = 32;  // per-lane tie queue (a full queue is flushed by its lane)
+
+// Decision for the 32 sites of one word from the count planes k0, k1, k2:
+// returns the flip mask, with the exact ties (in `ties`) refused.
 template <int D>
 __device__ __forceinline__ uint32_t packed_decide(const TabRegs& tab, const RngKey& key,
                                                   uint32_t t, uint32_t c, uint32_t wi,
-                                                  uint32_t row, uint32_t o, uint32_t k0,
-                                                  uint32_t k1, uint32_t k2, PackedTies& q,
-                                                  uint32_t* own) {
+                                                  uint32_t k0, uint32_t k1, uint32_t k2,
+                                                  uint32_t& ties) {
   const uint32_t blk = wi * 2u;  // Philox blocks of sites 32 wi .. 32 wi + 31
   const Rand4 ra = philox(blk, t, key.replica, tag(c, kIsingPrefix), key.k0, key.k1);
   const Rand4 rb = philox(blk + 1u, t, key.replica, tag(c, kIsingPrefix), key.k0, key.k1);
@@ -188,20 +189,29 @@ __device__ __forceinline__ uint32_t packed_decide(const TabRegs& tab, const RngK
     eq &= ~(B[b] ^ T[b]);
   }
   const uint32_t rej = refus & ~lt;  // prefix >= threshold (ties included)
-  const uint32_t ties = refus & eq;
-  if (ties) {
-    uint32_t m = ties;
-    do {
-      if (q.n == kTieSlots) packed_tie_flush<D>(q, tab, key, t, c, own);
-      const uint32_t b = __builtin_ctz(m);
-      m &= m - 1;
-      const uint32_t k = ((k0 >> b) & 1u) | (((k1 >> b) & 1u) << 1) | (((k2 >> b) & 1u) << 2);
-      const uint32_t neg = (o >> b) & 1u;
-      q.slot[q.n * q.stride] = (uint16_t)(b | (row << 5) | (k << 11) | (neg << 14));
-      q.n += 1;
-    } while (m);
-  }
-  return ~rej;  // ties are refused here and resolved at the end of the band
+  ties = refus & eq;
+  return ~rej;  // ties are refused here; the caller queues them once the word is stored
+}
+
+// Queue the exact ties of a word already stored (a full queue is flushed by
+// its lane first: a flush writes its flips to the plane, so the word must be
+// there already).
+template <int D>
+__device__ __forceinline__ void packed_queue_ties(PackedTies& q, uint32_t ties, uint32_t row,
+                                                  uint32_t o, uint32_t k0, uint32_t k1,
+                                                  uint32_t k2, const TabRegs& tab,
+                                                  const RngKey& key, uint32_t t, uint32_t c,
+                                                  uint32_t* own) {
+  uint32_t m = ties;
+  do {
+    if (q.n == kPackedTieSlots) packed_tie_flush<D>(q, tab, key, t, c, own);
+    const uint32_t b = __builtin_ctz(m);
+    m &= m - 1;
+    const uint32_t k = ((k0 >> b) & 1u) | (((k1 >> b) & 1u) << 1) | (((k2 >> b) & 1u) << 2);
+    const uint32_t neg = (o >> b) & 1u;
+    q.slot[q.n * q.stride] = (uint16_t)(b | (row << 5) | (k << 11) | (neg << 14));
+    q.n += 1;
+  } while (m);
 }
 
 // Unsatisfied-bond count planes of 32 sites from their 2d neighbour words
@@ -243,12 +253,23 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
                                                             const uint32_t* __restrict__ J,
                                                             const uint32_t t, const uint32_t c,
                                                             Partial* __restrict__ parts) {
-  __shared__ uint16_t tie_slots[kTieSlots * 256];
+  __shared__ uint16_t tie_slots[kPackedTieSlots * 256];
   const uint32_t tid = xcd_remap(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
   const uint32_t band = fdiv(tid, divW);
   int64_t Esum = 0, Msum = 0;
+  const uint32_t W = divW.d;
+  const uint32_t Wh = (uint32_t)(g.Nh / 32);  // words per plane
+  uint32_t* own = s + (uint64_t)c * Wh;
+  const TabRegs tab = tab_regs(table);
+  PackedTies tq;
+  tq.slot = tie_slots + threadIdx.x;
+  tq.stride = 256;
+  tq.n = 0;
+  tq.base = 0;
+  tq.W = W;
+  tq.dE = 0;
+  tq.dM = 0;
   if (band < nbands) {
-    const uint32_t W = divW.d;
     const uint32_t q = tid - band * W;
     const uint32_t L = (uint32_t)g.L;
     const uint32_t r0 = band * H;
@@ -257,8 +278,6 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
       z = fdiv(r0, divL);
       y0 = r0 - z * L;
     }
-    const uint32_t Wh = (uint32_t)(g.Nh / 32);  // words per plane
-    uint32_t* own = s + (uint64_t)c * Wh;
     const uint32_t* oth = s + (uint64_t)(1 - c) * Wh;
     // word w of a plane at a 32-bit byte offset from the plane's (uniform)
     // base: the loads and stores take the scalar-base + 32-bit-offset form
@@ -275,15 +294,7 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
       zm_row = L * (z == 0 ? L - 1 : z - 1);
       zp_row = L * (z + 1 == L ? 0 : z + 1);
     }
-    const TabRegs tab = tab_regs(table);
-    PackedTies tq;
-    tq.slot = tie_slots + threadIdx.x;
-    tq.stride = 256;
-    tq.n = 0;
     tq.base = rw(zrow, y0) + q;
-    tq.W = W;
-    tq.dE = 0;
-    tq.dM = 0;
     // J planes: J[mu][cc] at (2 mu + cc) * Wh
     const uint32_t pz = (c + z) & 1u;
     // a band stays inside its z-plane (H divides L): the rows' word offsets
@@ -332,9 +343,11 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
       }
       uint32_t k0, k1, k2;
       count_planes<D>(u, k0, k1, k2);
-      const uint32_t flip = packed_decide<D>(tab, key, t, c, rowb + q, i, o, k0, k1, k2, tq, own);
+      uint32_t ties;
+      const uint32_t flip = packed_decide<D>(tab, key, t, c, rowb + q, k0, k1, k2, ties);
       const uint32_t on = o ^ flip;
       *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(own) + ((rowb + q) << 2)) = on;
+      if (ties) packed_queue_ties<D>(tq, ties, i, o, k0, k1, k2, tab, key, t, c, own);
       if (MEASURE) {
         // colour 1 after its update: each bond has one colour-1 end; the
         // colour-0 word at the same position covers each colour-0 site once
@@ -351,13 +364,13 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
       up = ct;
       ct = dn;
     }
-    packed_tie_flush<D>(tq, tab, key, t, c, own);
-    if (MEASURE) {
-      Esum += tq.dE;
-      Msum += tq.dM;
-    }
   }
-  if (MEASURE) block_partial_int(Esum, Msum, parts, blockIdx.x);
+  packed_tie_flush<D>(tq, tab, key, t, c, own);  // the band's queued ties
+  if (MEASURE) {
+    Esum += tq.dE;
+    Msum += tq.dM;
+    block_partial_int(Esum, Msum, parts, blockIdx.x);
+  }
 }
 
 // Rows per band for the packed kernel: the largest power of two up to 64
