@@ -515,7 +515,9 @@ int smc_init_lattice(smc_lattice** out, const smc_params* p, void* spins, void* 
                      : s == "stream" ? kVariantStream : s == "fused_wave" ? kVariantFusedWave
                      : kVariantAuto;
   }
-  h->rows_per_band = stream_rows_per_band(h->g, 4096);
+  // at least 2048 waves (two per SIMD): longer bands re-read fewer halo rows,
+  // and the software-pipelined ring keeps enough loads in flight per wave
+  h->rows_per_band = stream_rows_per_band(h->g, 2048);
   if (const char* v = std::getenv("SMC_STREAM_ROWS")) {
     const long H = std::strtol(v, nullptr, 10);
     if (H >= 1 && H <= 64 && H <= h->g.L && h->g.L % H == 0) h->rows_per_band = (uint32_t)H;
