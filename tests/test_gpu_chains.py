@@ -9,7 +9,8 @@
   samples.
 * At L = 4, the estimates of <x_b>, of the gradient of the correlations and
   of ln Z's gradients agree with exact enumeration within their statistical
-  errors, and moment matching recovers hidden couplings.
+  errors, common-random-number finite differences agree with beta Cov, and
+  moment matching recovers hidden couplings.
 """
 import numpy as np
 import pytest
@@ -191,3 +192,47 @@ def test_moment_matching_recovers_hidden_couplings(smc_gpu, x4):
     J_fit = torch.stack(hist[-15:]).mean(0)
     err = np.abs(natural(J_fit.cpu().numpy().astype(np.float64), 2, 4) - J_star)
     assert err.max() < 0.05, err.max()
+
+
+def test_common_random_number_finite_differences(smc_gpu, x4):
+    """Central finite differences of the sampled bond correlations under
+    common random numbers (the same seed, hence the same start states and
+    random streams, at J + eps e_b and J - eps e_b) equal the derivative
+    d<x_a>/dJ_b = beta Cov(x_a, x_b) -- that of exact enumeration and the
+    backward pass's covariance estimate -- at L = 4 within their errors."""
+    import torch
+    from paper_1107_5463_amd import autodiff
+    rng = np.random.default_rng(9)
+    d, L, beta, eps = 2, 4, 0.4, 0.25  # curvature error of the central difference ~3e-4
+    J_nat = rng.normal(1.0, 0.1, size=(d, 16))
+    bond = (0, 5)  # J_b: the +x bond of site 5
+    nch, nsw, burn = 256, 3000, 100
+    bt = torch.tensor(beta, dtype=torch.float64)
+
+    def means(Jn, seed):
+        ch = smc_gpu.Chains(d, L, nch, seed)
+        J = torch.from_numpy(split(Jn.astype(np.float32), d, L)).cuda()
+        m = autodiff.bond_correlations(J, bt, ch, nsw, n_burn=burn)
+        return natural(m.detach().cpu().numpy().astype(np.float64), d, L)
+
+    Jp, Jm = J_nat.copy(), J_nat.copy()
+    Jp[bond] += eps
+    Jm[bond] -= eps
+    fds = np.array([(means(Jp, s) - means(Jm, s)) / (2 * eps) for s in (41, 42, 43, 44)])
+    fd, se = fds.mean(0), fds.std(0, ddof=1) / 2
+    # exact: the central difference and the derivative differ by O(eps^2)
+    _, cov, _ = ex.exact_bond_moments(L, J_nat, beta, x4)
+    want = beta * cov[:, bond[0] * 16 + bond[1]].reshape(d, 16)
+    fd_exact = (ex.exact_bond_moments(L, Jp, beta, x4)[0] -
+                ex.exact_bond_moments(L, Jm, beta, x4)[0]) / (2 * eps)
+    assert np.abs(fd_exact - want).max() < 2e-3
+    assert np.all(np.abs(fd - fd_exact) < 6 * se + 5e-3), np.max(np.abs(fd - fd_exact) - 6 * se)
+    # the backward pass at J: J.grad for the cotangent e_b is column b of beta Cov
+    J = torch.from_numpy(split(J_nat.astype(np.float32), d, L)).cuda().requires_grad_(True)
+    m = autodiff.bond_correlations(J, bt, smc_gpu.Chains(d, L, 4 * nch, 45), nsw, n_burn=burn)
+    g = np.zeros((d, 16))
+    g[bond] = 1.0
+    m.backward(torch.from_numpy(split(g.astype(np.float32), d, L)).cuda())
+    bw = natural(J.grad.cpu().numpy().astype(np.float64), d, L)
+    assert np.abs(bw - want).max() < 0.02, np.abs(bw - want).max()
+    assert np.all(np.abs(fd - bw) < 6 * se + 0.02)
