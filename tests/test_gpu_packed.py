@@ -142,3 +142,22 @@ def test_bond_correlations_refused(smc_gpu):
     lat = smc_gpu.Lattice(2, 1, 64, seed=1, packed=True)
     with pytest.raises(smc_gpu.SmcError):
         lat.bond_reset()
+
+
+@pytest.mark.parametrize("d,L,kind,J0,beta,n", [(2, 64, 0, -1.0, BETA_C, 10), (3, 64, 0, -1.0, 0.25, 5),
+                                                (2, 64, 1, -0.7, 0.6, 10), (2, 64, 0, 0.5, 0.9, 10),
+                                                (3, 64, 1, 2.0, 0.15, 4)])
+@pytest.mark.parametrize("packed", [True, False])
+def test_coupling_scale_and_sign_match_oracle(smc_gpu, oracle_mod, d, L, kind, J0, beta, n, packed):
+    """Uniform or +-1 couplings scaled by J0, including J0 < 0 (the refusable
+    moves are then those with more than d unsatisfied bonds), bit for bit in
+    both spin layouts."""
+    print(f"J0 sweeps d={d} L={L} kind={kind} J0={J0} packed={packed}", flush=True)
+    lat = smc_gpu.Lattice(d, 1, L, seed=9 + kind, J_kind=kind, J0=J0, packed=packed)
+    ref = oracle_mod.OracleLattice(d, 1, L, 9 + kind, J_kind=kind, J0=J0)
+    lat.sweep(beta, n)
+    ref.sweep(beta, n)
+    got = nat(smc_gpu, lat) if packed else layout.to_natural(lat.spins.cpu().numpy(), d, L)
+    assert np.array_equal(got, ref.s)
+    o, r = lat.measure(), ref.measure()
+    assert o.M_int == r.M_int and o.E == r.E, (o.E, r.E)
