@@ -184,13 +184,85 @@ __global__ __launch_bounds__(256) void tile_kernel(const Geom g, const RngKey ke
   }
 }
 
+// The 8 sites of a 16-wide tile row: words h0 and h0 + 1 (h0 = 0 or 2) of
+// their 16-site chunk, whose Philox block (base jbase) gives the words h0,
+// h0 + 1 of prefix bytes.  Metropolis with the ties resolved on the spot.
+__device__ __forceinline__ uint2 update_half_now(const TabRegs& tab, const RngKey& key,
+                                                 uint32_t t, uint32_t c, uint32_t jbase,
+                                                 uint32_t h0, uint32_t o0, uint32_t o1,
+                                                 uint32_t k0, uint32_t k1, uint32_t hit) {
+  const Rand4 rp = philox(jbase >> 4, t, key.replica, tag(c, kIsingPrefix) | (hit << 8), key.k0,
+                          key.k1);
+  const uint32_t P0 = h0 ? rp.w[2] : rp.w[0], P1 = h0 ? rp.w[3] : rp.w[1];
+  uint32_t tie[4] = {0u, 0u, 0u, 0u};
+  uint32_t n0 = decide4_tie(tab, o0, k0, P0, tie[0]);
+  uint32_t n1 = decide4_tie(tab, o1, k1, P1, tie[1]);
+  if ((tie[0] | tie[1]) & kHigh) {
+    uint32_t m = tie_mask16(tie);  // bits 0..7: sites 4 h0 .. 4 h0 + 7 of the chunk
+    do {
+      const uint32_t idx = __builtin_ctz(m);
+      m &= m - 1;
+      const uint32_t w = idx >> 2, sh = 8 * (idx & 3u);
+      const uint32_t k = ((w ? k1 : k0) >> sh) & 0xFu;
+      const Rand4 rr = philox(jbase + 4 * h0 + idx, t, key.replica,
+                              tag(c, kIsingRefine) | (hit << 8), key.k0, key.k1);
+      if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) {
+        const uint32_t f = 0xFEu << sh;
+        n0 ^= w == 0 ? f : 0u;
+        n1 ^= w == 1 ? f : 0u;
+      }
+    } while (m);
+  }
+  return make_uint2(n0, n1);
+}
+
+// The heat-bath update of the same 8 sites (cf. heatbath_chunk).
+__device__ __forceinline__ uint2 heatbath_half(const TabRegs& tab, const RngKey& key, uint32_t t,
+                                               uint32_t c, uint32_t jbase, uint32_t h0,
+                                               uint32_t o0, uint32_t o1, uint32_t k0,
+                                               uint32_t k1, uint32_t two_d, uint32_t hit) {
+  const Rand4 rp = philox(jbase >> 4, t, key.replica, tag(c, kIsingPrefix) | (hit << 8), key.k0,
+                          key.k1);
+  const uint32_t o[2] = {o0, o1}, kk[2] = {k0, k1};
+  const uint32_t P[2] = {h0 ? rp.w[2] : rp.w[0], h0 ? rp.w[3] : rp.w[1]};
+  uint32_t n[2], idx[2], tie[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+  for (int w = 0; w < 2; ++w) {
+    const uint32_t negm = __builtin_amdgcn_perm(o[w], o[w] << 8, 0x0B090A08u);  // 0xFF: s = -1
+    idx[w] = (kk[w] & negm) | ((two_d * kOnes - kk[w]) & ~negm);
+    const uint32_t Th = __builtin_amdgcn_perm(tab.th_hi, tab.th_lo, idx[w]);
+    const uint32_t x = P[w] ^ Th;
+    const uint32_t dlow = (P[w] | kHigh) - (Th & ~kHigh);
+    const uint32_t ge = (x & P[w]) | (~x & dlow);  // bit 7: P >= Th -> spin -1
+    n[w] = __builtin_amdgcn_perm(ge, ge << 8, 0x0B090A08u) | kOnes;
+    const uint32_t z = (x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu;
+    tie[w] = ~(z | x) & kHigh;
+  }
+  if (tie[0] | tie[1]) {
+    uint32_t m = tie_mask16(tie);
+    do {
+      const uint32_t b = __builtin_ctz(m);
+      m &= m - 1;
+      const uint32_t w = b >> 2, sh = 8 * (b & 3u);
+      const uint32_t cls = ((w ? idx[1] : idx[0]) >> sh) & 0xFu;
+      const Rand4 rr = philox(jbase + 4 * h0 + b, t, key.replica,
+                              tag(c, kIsingRefine) | (hit << 8), key.k0, key.k1);
+      const uint32_t up = (rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, cls) ? 1u : 0u;
+      const uint32_t clear = ~(0xFFu << sh);
+      const uint32_t val = (up ? 0x01u : 0xFFu) << sh;
+      n[0] = w == 0 ? (n[0] & clear) | val : n[0];
+      n[1] = w == 1 ? (n[1] & clear) | val : n[1];
+    } while (m);
+  }
+  return make_uint2(n[0], n[1]);
+}
+
 // Tiles of edge 16 (the tile size of the paper's measurements): a tile row
 // holds 8 sites of a colour, half of a 16-site chunk and of its Philox block.
-// A lane updates the whole 16-site chunk that holds its 8 sites and stores
-// back only those 8 bytes (the other half of the chunk is scratch): in its
-// 48-byte LDS row the tile's sites sit in the chunk's first half (even tx) or
-// second half (odd tx), the halo bytes next to them, so both in-row
-// neighbours of every tile site are read exactly as in the wide-tile kernel.
+// A lane updates its 8 sites as words h0, h0 + 1 of their 16-site chunk
+// (h0 = 0 for even tx, 2 for odd), drawing the chunk's Philox block: in its
+// 48-byte LDS row the tile's sites sit where those words of the chunk would
+// (byte 16 or 24), the halo bytes next to them.
 // The workgroup's 256 lanes take one tile row each: 16 tiles per workgroup in
 // 2D, one in 3D.
 template <int D, bool HB>
@@ -263,30 +335,34 @@ __global__ __launch_bounds__(256) void tile16_kernel(const Geom g, const RngKey 
         int8_t* own = lds + gi * TB + c * NR * RS;
         const int8_t* oth = lds + gi * TB + (1 - c) * NR * RS;
         const uint32_t p = (c + y + z) & 1u;
-        const Chunk o = lds16(own + r * RS + 16);
-        const Chunk ct = lds16(oth + r * RS + 16);
-        const Chunk up = lds16(oth + (r - 1) * RS + 16);
-        const Chunk dn = lds16(oth + (r + 1) * RS + 16);
-        const uint32_t e = *reinterpret_cast<const uint32_t*>(oth + r * RS + (p ? 32 : 12));
-        const Chunk sh = p ? shift_next(ct, e) : shift_prev(ct, e);
-        Chunk fz{}, bz{};
+        const uint32_t base = 16 + 8 * odd;  // the tile row's 8 bytes
+        auto ld2 = [&](const int8_t* q) { return *reinterpret_cast<const uint2*>(q); };
+        const uint2 o = ld2(own + r * RS + base);
+        const uint2 ct = ld2(oth + r * RS + base);
+        const uint2 up = ld2(oth + (r - 1) * RS + base);
+        const uint2 dn = ld2(oth + (r + 1) * RS + base);
+        // the in-row neighbours: next site (p = 1) or previous (p = 0), with
+        // the halo byte beyond the row's 8 bytes
+        const uint32_t e = *reinterpret_cast<const uint32_t*>(oth + r * RS + (p ? base + 8 : base - 4));
+        const uint32_t s0 = p ? __builtin_amdgcn_alignbyte(ct.y, ct.x, 1) : __builtin_amdgcn_alignbyte(ct.x, e, 3);
+        const uint32_t s1 = p ? __builtin_amdgcn_alignbyte(e, ct.y, 1) : __builtin_amdgcn_alignbyte(ct.y, ct.x, 3);
+        uint2 fz = make_uint2(0u, 0u), bz = make_uint2(0u, 0u);
         if (D == 3) {
-          fz = lds16(oth + (r - TR) * RS + 16);
-          bz = lds16(oth + (r + TR) * RS + 16);
+          fz = ld2(oth + (r - TR) * RS + base);
+          bz = ld2(oth + (r + TR) * RS + base);
         }
-        uint32_t kk[4];
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-          const uint32_t ow = o.w[w];
-          uint32_t k2 = ((ow ^ ct.w[w]) & kBit1) + ((ow ^ sh.w[w]) & kBit1) +
-                        ((ow ^ up.w[w]) & kBit1) + ((ow ^ dn.w[w]) & kBit1);
-          if (D == 3) k2 += ((ow ^ fz.w[w]) & kBit1) + ((ow ^ bz.w[w]) & kBit1);
-          kk[w] = k2 >> 1;
-        }
-        const Chunk nw = HB ? heatbath_chunk(tab, key, t, c, jbase, o, kk, 2 * D, h)
-                            : update_chunk_now(tab, key, t, c, jbase, o, kk, h);
-        *reinterpret_cast<uint2*>(own + r * RS + 16 + 8 * odd) =
-            odd ? make_uint2(nw.w[2], nw.w[3]) : make_uint2(nw.w[0], nw.w[1]);
+        auto count = [&](uint32_t ow, uint32_t c0, uint32_t sh, uint32_t u, uint32_t d,
+                         uint32_t f, uint32_t bk) {
+          uint32_t k2 = ((ow ^ c0) & kBit1) + ((ow ^ sh) & kBit1) + ((ow ^ u) & kBit1) +
+                        ((ow ^ d) & kBit1);
+          if (D == 3) k2 += ((ow ^ f) & kBit1) + ((ow ^ bk) & kBit1);
+          return k2 >> 1;
+        };
+        const uint32_t k0 = count(o.x, ct.x, s0, up.x, dn.x, fz.x, bz.x);
+        const uint32_t k1 = count(o.y, ct.y, s1, up.y, dn.y, fz.y, bz.y);
+        const uint2 nw = HB ? heatbath_half(tab, key, t, c, jbase, 2 * odd, o.x, o.y, k0, k1, 2 * D, h)
+                            : update_half_now(tab, key, t, c, jbase, 2 * odd, o.x, o.y, k0, k1, h);
+        *reinterpret_cast<uint2*>(own + r * RS + base) = nw;
       }
       __syncthreads();
     }
