@@ -233,6 +233,21 @@ class OracleLattice:
             raise ValueError(f"oracle_sweeps_rule rejected its arguments (rc={rc})")
         self.t += n_sweeps
 
+    def tile_pass(self, beta: float, tile: int, hits: int, tile_colour: int,
+                  rule: str = "metropolis", t: int | None = None):
+        """One half of a tiled k-hit sweep: the pass over tile colour
+        `tile_colour` alone, with sweep counter t (default self.t, which is
+        not advanced)."""
+        f = lib().oracle_tile_pass
+        f.argtypes = [C.POINTER(_Params), C.c_void_p, C.c_void_p, C.c_double, C.c_uint64, C.c_int,
+                      C.c_int, C.c_int, C.c_int]
+        f.restype = C.c_int
+        r = {"metropolis": 0, "heatbath": 1}[rule]
+        rc = f(C.byref(self.p), self.s.ctypes.data, self._Jp, float(beta),
+               int(self.t if t is None else t), r, int(tile), int(hits), int(tile_colour))
+        if rc != 0:
+            raise ValueError(f"oracle_tile_pass rejected its arguments (rc={rc})")
+
     def renormalize(self):
         lib().oracle_renormalize(C.byref(self.p), self.s.ctypes.data)
 

@@ -714,39 +714,75 @@ static int ising_rule_site(const oracle_params *p, const int8_t *s, const void *
   return u32 < Tm[m + 2 * d] ? -s[i] : s[i];
 }
 
-/* n_sweeps sweeps of an Ising lattice with integer couplings under `rule`,
- * plain (tile = 0: colour 0 then colour 1, hit 0) or tiled k-hit (tile T,
- * hits k >= 1).  The counter of sweep q is t0 + q. */
-ORACLE_API int oracle_sweeps_rule(const oracle_params *p, int8_t *s, const void *J, double beta,
-                                  uint64_t t0, int64_t n_sweeps, int rule, int tile, int hits) {
-  if (!valid(p) || p->n != 1 || p->J_kind == J_FP32 || (rule != 0 && rule != 1)) return -1;
-  if (n_sweeps < 0 || t0 + (uint64_t)n_sweeps > 0x100000000ull) return -1;
-  if (tile < 0 || (tile > 0 && (p->L % tile || ((p->L / tile) & 1) || hits < 1 || hits > (1 << 23))))
-    return -1;
+/* Thresholds of both rules for dE = 2 J0 m (Metropolis) and h = J0 m (heat
+ * bath), m = -2d..2d. */
+static void rule_tables(const oracle_params *p, double beta, uint64_t Tm[13], uint64_t Th[13]) {
   int d = p->d;
-  int64_t N = n_sites(p);
-  uint64_t Tm[13], Th[13];
   for (int m = -2 * d; m <= 2 * d; ++m) {
     Tm[m + 2 * d] = oracle_threshold(beta, 2.0 * p->J0 * m);
     Th[m + 2 * d] = oracle_threshold_hb(beta, p->J0 * m);
   }
-  int8_t *nw = (int8_t *)malloc((size_t)N);
+}
+
+/* One pass over tile colour tc (tile > 0) or over the whole lattice (tile =
+ * 0): `hits` times, every selected site of colour 0 and then every selected
+ * site of colour 1 attempts one move against the state the previous stage
+ * left; all other sites stay fixed.  nw: scratch of N bytes. */
+static void rule_pass(const oracle_params *p, int8_t *s, const void *J, const uint64_t *Tm,
+                      const uint64_t *Th, uint32_t t, int rule, int tile, int tc, int hits,
+                      int8_t *nw) {
+  int64_t N = n_sites(p);
+  for (int h = 0; h < hits; ++h)
+    for (int c = 0; c < 2; ++c) {
+      /* all selected sites at once from the same state (they are independent) */
+#pragma omp parallel for schedule(static) if (N >= 65536)
+      for (int64_t i = 0; i < N; ++i) {
+        int sel = colour_of(p, i) == c && (tile == 0 || tile_colour(p, i, tile) == tc);
+        nw[i] = sel ? (int8_t)ising_rule_site(p, s, J, Tm, Th, t, c, (uint32_t)h, rule, i) : s[i];
+      }
+      memcpy(s, nw, (size_t)N);
+    }
+}
+
+static int rule_args_ok(const oracle_params *p, int rule, int tile, int hits) {
+  if (!valid(p) || p->n != 1 || p->J_kind == J_FP32 || (rule != 0 && rule != 1)) return 0;
+  if (tile < 0 || (tile > 0 && (p->L % tile || ((p->L / tile) & 1) || hits < 1 || hits > (1 << 23))))
+    return 0;
+  return 1;
+}
+
+/* n_sweeps sweeps of an Ising lattice with integer couplings under `rule`,
+ * plain (tile = 0: colour 0 then colour 1, hit 0) or tiled k-hit (tile T,
+ * hits k >= 1: the pass over tile colour 0, then the pass over tile colour
+ * 1).  The counter of sweep q is t0 + q. */
+ORACLE_API int oracle_sweeps_rule(const oracle_params *p, int8_t *s, const void *J, double beta,
+                                  uint64_t t0, int64_t n_sweeps, int rule, int tile, int hits) {
+  if (!rule_args_ok(p, rule, tile, hits)) return -1;
+  if (n_sweeps < 0 || t0 + (uint64_t)n_sweeps > 0x100000000ull) return -1;
+  uint64_t Tm[13], Th[13];
+  rule_tables(p, beta, Tm, Th);
+  int8_t *nw = (int8_t *)malloc((size_t)n_sites(p));
   if (!nw) return -2;
   int passes = tile > 0 ? 2 : 1, k = tile > 0 ? hits : 1;
   for (int64_t q = 0; q < n_sweeps; ++q) {
     uint32_t t = (uint32_t)(t0 + (uint64_t)q);
-    for (int tc = 0; tc < passes; ++tc)
-      for (int h = 0; h < k; ++h)
-        for (int c = 0; c < 2; ++c) {
-          /* all selected sites at once from the same state (they are independent) */
-#pragma omp parallel for schedule(static) if (N >= 65536)
-          for (int64_t i = 0; i < N; ++i) {
-            int sel = colour_of(p, i) == c && (tile == 0 || tile_colour(p, i, tile) == tc);
-            nw[i] = sel ? (int8_t)ising_rule_site(p, s, J, Tm, Th, t, c, (uint32_t)h, rule, i) : s[i];
-          }
-          memcpy(s, nw, (size_t)N);
-        }
+    for (int tc = 0; tc < passes; ++tc) rule_pass(p, s, J, Tm, Th, t, rule, tile, tc, k, nw);
   }
+  free(nw);
+  return 0;
+}
+
+/* The pass over tile colour tc alone (tile > 0), with counter t: one half of
+ * a tiled sweep. */
+ORACLE_API int oracle_tile_pass(const oracle_params *p, int8_t *s, const void *J, double beta,
+                                uint64_t t, int rule, int tile, int hits, int tc) {
+  if (!rule_args_ok(p, rule, tile, hits) || tile == 0 || (tc != 0 && tc != 1)) return -1;
+  if (t > 0xffffffffull) return -1;
+  uint64_t Tm[13], Th[13];
+  rule_tables(p, beta, Tm, Th);
+  int8_t *nw = (int8_t *)malloc((size_t)n_sites(p));
+  if (!nw) return -2;
+  rule_pass(p, s, J, Tm, Th, (uint32_t)t, rule, tile, tc, hits, nw);
   free(nw);
   return 0;
 }
