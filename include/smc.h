@@ -16,7 +16,8 @@
  * Sites.  i = x + L*y + L*L*z, colour c = (x + y + z) mod 2, and the index of
  *   site i within its colour is j = i >> 1 (L even), 0 <= j < N/2.
  * Device buffers (all caller-owned, all on the device of `stream`; the
- *   library never allocates, frees or reallocates device memory):
+ *   library never allocates, frees or reallocates device memory -- its one
+ *   device array of its own is smc_measure_noalloc's static scratch):
  *   spins  Ising: int8 [2][N/2], plane c holds the spins +1/-1 of colour c.
  *          XY / Heisenberg: float [n][2][N/2], component k of site (c, j) at
  *          k*N + c*N/2 + j.  Aligned to 16 bytes.
@@ -164,6 +165,27 @@ int smc_measure(smc_lattice* h, smc_obs* out);
 /* Same, written as an smc_obs to device memory dev_obs (8-byte aligned)
  * without synchronising. */
 int smc_measure_async(smc_lattice* h, void* dev_obs);
+
+/*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): smc_measure_async's
+ * energy and magnetisation, with the same kernels, of a state given directly
+ * -- no handle and no workspace.  p, spins and J as for smc_init_lattice
+ * (p->init, seed, replica, delta, renorm_every, tile and hits are not used;
+ * SMC_FLAG_PACKED selects the packed layout); the smc_obs record goes to
+ * dev_obs (device, 8-byte aligned) with its `sweep` field set to `sweep`;
+ * asynchronous on `stream` (hipStream_t as void*, on the current device).
+ * The block partials of the reduction live in a static device array owned by
+ * the library, one per GPU for the life of the process: 16384 partials
+ * (768 KiB), enough for every int8 and continuous lattice and for packed
+ * lattices with N/2 <= 2^27 (2D L <= 16384, 3D L <= 512); larger packed
+ * lattices fail with SMC_EINVAL.  Calls no hipMalloc, hipFree or allocating
+ * routine.  Every call on a GPU uses that GPU's one array: calls that overlap
+ * on one GPU (two streams, two threads) race and must be ordered by the
+ * caller.
+ */
+int smc_measure_noalloc(const smc_params* p, const void* spins, const void* J, int64_t sweep,
+                        void* dev_obs, void* stream);
 
 /*
  * Bond correlations s_i . s_{i+mu} for every bond (the per-bond statistic

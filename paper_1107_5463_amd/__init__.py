@@ -39,7 +39,7 @@ SMC_OK, SMC_EINVAL, SMC_ERANGE, SMC_EDEVICE, SMC_ESTATE = 0, -1, -2, -3, -4
 EXPORTS = ["smc_spin_bytes", "smc_coupling_bytes", "smc_workspace_bytes", "smc_bond_bytes",
            "smc_init_lattice", "smc_set_stream", "smc_sweep", "smc_sweep_measure", "smc_half_sweep",
            "smc_measure",
-           "smc_measure_async", "smc_bond_correlations", "smc_get_samples", "smc_set_samples",
+           "smc_measure_async", "smc_measure_noalloc", "smc_bond_correlations", "smc_get_samples", "smc_set_samples",
            "smc_renormalize", "smc_validate", "smc_get_sweep_index", "smc_set_sweep_index",
            "smc_kernel_name", "smc_destroy", "smc_last_error", "smc_version",
            "smc_batch_spin_bytes", "smc_batch_coupling_bytes", "smc_batch_workspace_bytes",
@@ -111,6 +111,7 @@ def load_library():
     lib.smc_half_sweep.argtypes = [vp, C.c_double, C.c_int]
     lib.smc_measure.argtypes = [vp, C.POINTER(_ObsC)]
     lib.smc_measure_async.argtypes = [vp, vp]
+    lib.smc_measure_noalloc.argtypes = [P, vp, vp, C.c_int64, vp, vp]
     lib.smc_bond_correlations.argtypes = [vp, C.c_int, vp, vp]
     lib.smc_get_samples.argtypes = [vp, C.POINTER(C.c_int64)]
     lib.smc_set_samples.argtypes = [vp, C.c_int64]
@@ -312,6 +313,17 @@ class Lattice:
         slot (>= 64 bytes) without synchronising."""
         assert dev_slot.is_cuda and dev_slot.numel() * dev_slot.element_size() >= 64
         _check(self._lib().smc_measure_async(self._h, C.c_void_p(dev_slot.data_ptr())))
+
+    def measure_noalloc(self, dev_slot, stream=None):
+        """smc_measure_noalloc on this lattice's parameters and buffers: the
+        observables of the current state into dev_slot (>= 64 bytes) through
+        the library's static scratch instead of the handle's workspace."""
+        assert dev_slot.is_cuda and dev_slot.numel() * dev_slot.element_size() >= 64
+        st = stream if stream is not None else self.stream
+        _check(self._lib().smc_measure_noalloc(
+            C.byref(self.params), C.c_void_p(self.spins.data_ptr()),
+            None if self.J is None else C.c_void_p(self.J.data_ptr()), self.t,
+            C.c_void_p(dev_slot.data_ptr()), C.c_void_p(st.cuda_stream)))
 
     @staticmethod
     def decode_obs(buf) -> list:

@@ -150,6 +150,14 @@ hipError_t launch_measure(const MeasureLaunch& a, const void* spins, void* parti
 // Reduce nparts partials (written by a measuring sweep kernel) into dev_obs.
 hipError_t launch_finish(const MeasureLaunch& a, const void* partials, int64_t nparts,
                          void* dev_obs, hipStream_t st);
+// Partials a stand-alone measurement writes (packed spins: one per 256 words;
+// otherwise at most the bounded grid's 2048 blocks).
+int64_t measure_partials_standalone(const Geom& g, bool packed);
+// Capacity, in partials, of the library's own measurement scratch (768 KiB).
+constexpr int64_t kMeasureScratchPartials = 16384;
+// Address on the current device of that scratch: a file-scope device array,
+// one copy per GPU, looked up once per device and cached.
+hipError_t measure_scratch(void** ptr);
 
 hipError_t launch_bond_accumulate(const MeasureLaunch& a, const void* spins, void* acc,
                                   hipStream_t st);

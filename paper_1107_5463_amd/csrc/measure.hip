@@ -12,6 +12,8 @@
 #include "reduce.hpp"
 
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 namespace smc {
 
@@ -196,6 +198,37 @@ __global__ __launch_bounds__(256) void finish_kernel(const Partial* __restrict__
 }
 
 int64_t measure_partials(const Geom& g) { return (g.Nh + 255) / 256; }
+
+int64_t measure_partials_standalone(const Geom& g, bool packed) {
+  if (packed) return (g.Nh / 32 + 255) / 256;
+  return std::min<int64_t>((g.Nh + 255) / 256, kMeasureBlocks);
+}
+
+// Reduction partials of the allocation-free measurement (no handle, no
+// workspace): a file-scope device array of which each GPU holds its own copy
+// for the life of the process.  Host code must not pass `scratch` itself to
+// a kernel (on the host it only names the symbol): measure_scratch() gives
+// the device address.  Concurrent users on one GPU share it.
+static __device__ __align__(256) Partial scratch[kMeasureScratchPartials];
+
+hipError_t measure_scratch(void** ptr) {
+  static std::mutex mu;
+  static std::map<int, void*> addr;  // device -> its copy of `scratch`
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it == addr.end()) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    it = addr.emplace(dev, p).first;
+  }
+  *ptr = it->second;
+  return hipSuccess;
+}
 
 template <int D>
 static void launch_measure_d(const MeasureLaunch& a, const void* spins, Partial* parts,

@@ -276,17 +276,30 @@ IsingLaunch ising_args(smc_lattice* h, double beta) {
   return a;
 }
 
-// E and M of the current state into dev_obs (any spin format).
-hipError_t measure_any(smc_lattice* h, int64_t sweep, void* dev_obs) {
-  if (is_packed(&h->p)) {
+// E and M of a state (any spin format) into dev_obs, the block partials in
+// `partials` (a handle's workspace, or the library's scratch).
+hipError_t measure_state(const smc_params& p, const Geom& g, const void* spins, const void* J,
+                         void* partials, int64_t sweep, void* dev_obs, hipStream_t st) {
+  MeasureLaunch m;
+  m.g = g;
+  m.n = p.n;
+  m.J_kind = p.J_kind;
+  m.J = p.J_kind == SMC_J_UNIFORM ? nullptr : J;
+  m.J0 = p.J0;
+  m.sweep = sweep;
+  if (is_packed(&p)) {
     int64_t nparts = 0;
-    const hipError_t e = launch_measure_packed(h->g, h->p.J_kind, (const uint32_t*)h->spins,
-                                               (const uint32_t*)h->J, h->partials, &nparts,
-                                               h->stream);
+    const hipError_t e = launch_measure_packed(g, p.J_kind, (const uint32_t*)spins,
+                                               (const uint32_t*)m.J, partials, &nparts, st);
     if (e != hipSuccess) return e;
-    return launch_finish(measure_args(h, sweep), h->partials, nparts, dev_obs, h->stream);
+    return launch_finish(m, partials, nparts, dev_obs, st);
   }
-  return launch_measure(measure_args(h, sweep), h->spins, h->partials, dev_obs, h->stream);
+  return launch_measure(m, spins, partials, dev_obs, st);
+}
+
+// E and M of the handle's current state into dev_obs.
+hipError_t measure_any(smc_lattice* h, int64_t sweep, void* dev_obs) {
+  return measure_state(h->p, h->g, h->spins, h->J, h->partials, sweep, dev_obs, h->stream);
 }
 
 ContLaunch cont_args(const smc_lattice* h, double beta) {
@@ -629,6 +642,29 @@ int smc_measure_async(smc_lattice* h, void* dev_obs) {
   if (!h) return fail(SMC_EINVAL, "handle is NULL");
   if (!dev_obs || ((uintptr_t)dev_obs & 7)) return fail(SMC_EINVAL, "dev_obs must be 8-byte aligned");
   return check(measure_any(h, h->t, dev_obs),
+               "measurement launch");
+}
+
+int smc_measure_noalloc(const smc_params* p, const void* spins, const void* J, int64_t sweep,
+                        void* dev_obs, void* stream) {
+  g_err.clear();
+  std::string why;
+  if (!params_ok(p, why)) return fail(SMC_EINVAL, why);
+  if (!spins || ((uintptr_t)spins & 15)) return fail(SMC_EINVAL, "spins must be non-NULL and 16-byte aligned");
+  if (p->J_kind != SMC_J_UNIFORM && (!J || ((uintptr_t)J & 15)))
+    return fail(SMC_EINVAL, "J must be non-NULL and 16-byte aligned for PM / FP32 couplings");
+  if (!dev_obs || ((uintptr_t)dev_obs & 7)) return fail(SMC_EINVAL, "dev_obs must be 8-byte aligned");
+  const Geom g = make_geom(p);
+  const int64_t need = measure_partials_standalone(g, is_packed(p));
+  if (need > kMeasureScratchPartials)
+    return fail(SMC_EINVAL, "lattice too large for the allocation-free measurement: it needs " +
+                                std::to_string(need) + " reduction partials, the library's scratch holds " +
+                                std::to_string(kMeasureScratchPartials) +
+                                " (packed spins: N/2 <= 2^27 sites); use smc_measure_async");
+  void* scr = nullptr;
+  const int rc = check(measure_scratch(&scr), "measurement scratch address");
+  if (rc != SMC_OK) return rc;
+  return check(measure_state(*p, g, spins, J, scr, sweep, dev_obs, (hipStream_t)stream),
                "measurement launch");
 }
 

@@ -186,3 +186,30 @@ def test_tile_sizes_accepted(smc_host, d, L, T):
     lib = smc_host.load_library()
     p = smc_host.make_params(d, 1, L, 1, tile=T, hits=3)
     assert lib.smc_spin_bytes(C.byref(p)) == L ** d
+
+
+def test_noalloc_measure_rejects_before_touching_the_device(smc_host):
+    """smc_measure_noalloc validates its arguments on the host: bad parameters,
+    misaligned pointers, and a packed lattice whose reduction needs more
+    partials than the library's static scratch holds (N/2 > 2^27) fail with
+    SMC_EINVAL and a message before any HIP call (the pointers here are never
+    dereferenced)."""
+    lib = smc_host.load_library()
+    dev = C.c_void_p(1 << 20)  # aligned, never used
+    big = smc_host.make_params(2, 1, 32768, 1, flags=smc_host.FLAG_PACKED)
+    assert lib.smc_measure_noalloc(C.byref(big), dev, None, 0, dev, None) == smc_host.SMC_EINVAL
+    msg = lib.smc_last_error()
+    assert b"too large for the allocation-free measurement" in msg and b"16384" in msg, msg
+    ok = smc_host.make_params(2, 1, 64, 1)
+    assert lib.smc_measure_noalloc(C.byref(ok), C.c_void_p((1 << 20) + 4), None, 0, dev,
+                                   None) == smc_host.SMC_EINVAL
+    assert b"16-byte aligned" in lib.smc_last_error()
+    assert lib.smc_measure_noalloc(C.byref(ok), dev, None, 0, C.c_void_p((1 << 20) + 4),
+                                   None) == smc_host.SMC_EINVAL
+    assert b"dev_obs" in lib.smc_last_error()
+    pm = smc_host.make_params(2, 1, 64, 1, J_kind=smc_host.J_PM)
+    assert lib.smc_measure_noalloc(C.byref(pm), dev, None, 0, dev, None) == smc_host.SMC_EINVAL
+    assert b"J must be" in lib.smc_last_error()
+    bad = smc_host.make_params(2, 1, 31, 1)
+    assert lib.smc_measure_noalloc(C.byref(bad), dev, None, 0, dev, None) == smc_host.SMC_EINVAL
+    assert lib.smc_measure_noalloc(None, dev, None, 0, dev, None) == smc_host.SMC_EINVAL
