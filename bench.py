@@ -77,7 +77,7 @@ def parse():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="ising2d")
     ap.add_argument("--steps", type=int, default=None,
                     help="timed steps of 10 sweeps + 1 measurement (default: 100, i.e. 1000 "
-                         "sweeps; batched and chains: 1000, i.e. 10^4 sweeps)")
+                         "sweeps; batched and chains: 1 step of 10^4 sweeps)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--sweeps-per-step", type=int, default=None,
                     help="sweeps per timed step (default 10; batched: 10000 in one launch)")
@@ -529,9 +529,11 @@ def run_chains(args, wl, torch, smc):
     Js[:, col, i >> 1] = J_nat
     ch = smc.Chains(d, L, nch, wl["seed"], J=torch.from_numpy(Js).cuda())
     st = ch.stream
-    K = args.steps if args.steps is not None else 1000
+    # one step = one sampling call of S sweeps (default: the workload's 10^4
+    # sweeps in one launch)
+    K = args.steps if args.steps is not None else 1
     W = args.warmup
-    S = args.sweeps_per_step if args.sweeps_per_step is not None else 10
+    S = args.sweeps_per_step if args.sweeps_per_step is not None else 10000
     beta = wl["beta"]
     for _ in range(W):
         ch.sample(beta, S)
@@ -546,10 +548,10 @@ def run_chains(args, wl, torch, smc):
     ev[1].record(st)
     torch.cuda.synchronize()
     sweeps = K * S
-    mean = acc.double() / (nch * sweeps)
+    mean = ch.mean(acc, nch * sweeps)
     g = torch.randn(mean.shape, dtype=torch.float64, device=mean.device,
                     generator=torch.Generator(device=mean.device).manual_seed(1))
-    gc = float((g * mean).sum())
+    gc = ch.dot(g, mean)
     cov_acc = torch.zeros_like(mean)
     G_acc = torch.zeros(2, dtype=torch.float64, device=mean.device)
     ch.spins.copy_(start)
@@ -580,7 +582,8 @@ def run_chains(args, wl, torch, smc):
                         f"N({wl['J_mean']}, {wl['J_sigma']}^2) (seed {wl['seed']}), beta={beta}, "
                         f"{sweeps} sweeps with the bond products summed after every sweep "
                         "(forward), then the covariance replay of the same sweeps (backward)",
-            "chains": nch, "L": L, "sweeps": sweeps,
+            "chains": nch, "L": L, "sweeps": sweeps, "sweeps_per_launch": S,
+            "kernel": ch.kernel(),
         },
         "backward": {"value": round(attempts / (bwd_ms * 1e6), 2), "unit": "attempts/ns",
                      "ms": round(bwd_ms, 3)},

@@ -324,10 +324,53 @@ int smc_chains_sample(smc_chains* h, double beta, int64_t n_sweeps, int64_t* dev
  * smc_chains_sample call started from, it visits the same configurations,
  * so that Cov(G, x_b) = cov_acc[b] / S - (G_acc[0] / S) <x_b> over its
  * S = n_chains n_sweeps samples, and the vector-Jacobian product of the
- * correlations is beta Cov(G, x_b).  g_center (e.g. sum_b g_b <x_b>) only
+ * correlations is beta Cov(G, x_b).  g_center is one double in device
+ * memory (NULL: 0), e.g. sum_b g_b <x_b> from smc_chains_dot; it only
  * conditions the sums. */
 int smc_chains_covariance(smc_chains* h, double beta, int64_t n_sweeps, const double* dev_g,
-                          double g_center, double* dev_cov_acc, double* dev_G_acc);
+                          const double* dev_g_center, double* dev_cov_acc, double* dev_G_acc);
+
+/* Finishing the estimates (FP64 device arithmetic over the d N bonds, every
+ * sum in a fixed order; all asynchronous on the handle's stream; arrays over
+ * bonds in the coupling layout, double 8-byte and float 4-byte aligned).
+ * With S = n_samples samples (chains x sweeps):
+ *   smc_chains_mean      mean[b] = bond_sum[b] / S  (<x_b>; d ln Z / d J_b = beta <x_b>)
+ *   smc_chains_dot       out[0] = sum_b a[b] w[b]
+ *   smc_chains_vjp       the vector-jacobian product of <x> from a covariance
+ *                        replay with weights g: Cov(G, x_b) = cov_acc[b] / S -
+ *                        (G_acc[0] / S) mean[b]; grad_J[b] = (float)(beta Cov(G, x_b))
+ *                        (d<x_a>/dJ_b = beta Cov(x_a, x_b)), grad_beta[0] =
+ *                        sum_b J[b] Cov(G, x_b)  (d<x_a>/dbeta = Cov(x_a, sum_b J_b x_b))
+ *   smc_chains_lnz_grad  d ln Z / d J_b = scale beta mean[b] into grad_J_f32 (float)
+ *                        or grad_J_f64 (double) -- exactly one of them non-NULL --
+ *                        and d ln Z / d beta = scale sum_b J[b] mean[b] into
+ *                        grad_beta[0]; scale: one double in device memory (NULL: 1)
+ *   smc_chains_fit_step  moment matching, ascent of the log-likelihood of data with
+ *                        bond correlations target: J[b] += (float)(lr beta (target[b]
+ *                        - mean[b]))
+ * (Eq. (1): Z = sum_s exp(beta sum_b J_b x_b).) */
+int smc_chains_mean(smc_chains* h, const int64_t* dev_bond_sum, int64_t n_samples, double* dev_mean);
+int smc_chains_dot(smc_chains* h, const double* dev_a, const double* dev_w, double* dev_out);
+int smc_chains_vjp(smc_chains* h, double beta, int64_t n_samples, const double* dev_cov_acc,
+                   const double* dev_G_acc, const double* dev_mean, const float* dev_J,
+                   float* dev_grad_J, double* dev_grad_beta);
+int smc_chains_lnz_grad(smc_chains* h, double beta, const double* dev_mean, const float* dev_J,
+                        const double* dev_scale, float* dev_grad_J_f32, double* dev_grad_J_f64,
+                        double* dev_grad_beta);
+int smc_chains_fit_step(smc_chains* h, double beta, double lr, const double* dev_target,
+                        const double* dev_mean, float* dev_J);
+
+/* One colour's half of sweep t for every chain (no accumulation; t is not
+ * advanced).  Test hook for the counted near-threshold protocol of FP32
+ * couplings (Eq. (2) decisions compared half-sweep by half-sweep).
+ * Asynchronous. */
+int smc_chains_half_sweep(smc_chains* h, double beta, int colour);
+
+/* Kernel the handle's sweeps launch: "chains_pair" (at most 1024 site pairs
+ * per colour, N <= 4096: one pair of sites per lane, state and couplings in
+ * registers) or "chains_lds" (larger lattices, or SMC_CHAINS_KERNEL=lds in the
+ * environment at init). */
+const char* smc_chains_kernel_name(const smc_chains* h);
 
 int smc_chains_get_sweep_index(const smc_chains* h, uint64_t* t);
 int smc_chains_set_sweep_index(smc_chains* h, uint64_t t);

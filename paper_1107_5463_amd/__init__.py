@@ -49,7 +49,10 @@ EXPORTS = ["smc_spin_bytes", "smc_coupling_bytes", "smc_workspace_bytes", "smc_b
            "smc_batch_destroy",
            "smc_chains_spin_bytes", "smc_chains_coupling_bytes", "smc_chains_bond_bytes",
            "smc_chains_workspace_bytes", "smc_chains_init", "smc_chains_sample",
-           "smc_chains_covariance", "smc_chains_get_sweep_index", "smc_chains_set_sweep_index",
+           "smc_chains_covariance", "smc_chains_half_sweep", "smc_chains_kernel_name",
+           "smc_chains_mean", "smc_chains_dot", "smc_chains_vjp", "smc_chains_lnz_grad",
+           "smc_chains_fit_step",
+           "smc_chains_get_sweep_index", "smc_chains_set_sweep_index",
            "smc_chains_destroy", "smc_pack_spins", "smc_unpack_spins"]
 
 
@@ -147,7 +150,15 @@ def load_library():
     lib.smc_chains_init.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32, C.c_int32, C.c_uint64,
                                     C.c_uint32, C.c_int32, vp, vp, vp, sz, vp]
     lib.smc_chains_sample.argtypes = [vp, C.c_double, C.c_int64, vp]
-    lib.smc_chains_covariance.argtypes = [vp, C.c_double, C.c_int64, vp, C.c_double, vp, vp]
+    lib.smc_chains_covariance.argtypes = [vp, C.c_double, C.c_int64, vp, vp, vp, vp]
+    lib.smc_chains_mean.argtypes = [vp, vp, C.c_int64, vp]
+    lib.smc_chains_dot.argtypes = [vp, vp, vp, vp]
+    lib.smc_chains_vjp.argtypes = [vp, C.c_double, C.c_int64, vp, vp, vp, vp, vp, vp]
+    lib.smc_chains_lnz_grad.argtypes = [vp, C.c_double, vp, vp, vp, vp, vp, vp]
+    lib.smc_chains_fit_step.argtypes = [vp, C.c_double, C.c_double, vp, vp, vp]
+    lib.smc_chains_half_sweep.argtypes = [vp, C.c_double, C.c_int]
+    lib.smc_chains_kernel_name.argtypes = [vp]
+    lib.smc_chains_kernel_name.restype = C.c_char_p
     lib.smc_chains_get_sweep_index.argtypes = [vp, C.POINTER(C.c_uint64)]
     lib.smc_chains_set_sweep_index.argtypes = [vp, C.c_uint64]
     lib.smc_chains_destroy.argtypes = [vp]
@@ -157,7 +168,8 @@ def load_library():
     lib.smc_version.restype = C.c_char_p
     for f in EXPORTS:
         if f not in ("smc_spin_bytes", "smc_coupling_bytes", "smc_workspace_bytes", "smc_bond_bytes",
-                     "smc_last_error", "smc_version", "smc_kernel_name", "smc_batch_spin_bytes",
+                     "smc_last_error", "smc_version", "smc_kernel_name", "smc_chains_kernel_name",
+                     "smc_batch_spin_bytes",
                      "smc_batch_coupling_bytes", "smc_batch_workspace_bytes"):
             getattr(lib, f).restype = C.c_int
     _LIB = lib
@@ -574,19 +586,107 @@ class Chains:
             ptr = C.c_void_p(bond_sum.data_ptr())
         _check(load_library().smc_chains_sample(self._h, float(beta), int(n_sweeps), ptr))
 
-    def covariance(self, beta: float, n_sweeps: int, g, g_center: float, cov_acc, G_acc):
+    def half_sweep(self, beta: float, colour: int):
+        """One colour's half of sweep t of every chain (t is not advanced)."""
+        _check(load_library().smc_chains_half_sweep(self._h, float(beta), int(colour)))
+
+    def kernel(self) -> str:
+        return load_library().smc_chains_kernel_name(self._h).decode()
+
+    def covariance(self, beta: float, n_sweeps: int, g, g_center, cov_acc, G_acc):
         """Replay of n_sweeps sampling sweeps accumulating (G - g_center) x_b
         into cov_acc and G - g_center, (G - g_center)^2 into G_acc (float64
-        device tensors [d, 2, N/2] and [2]), G = sum_b g_b x_b."""
+        device tensors [d, 2, N/2] and [2]), G = sum_b g_b x_b; g_center: a
+        float64 device tensor of one element (e.g. from dot), or None (0)."""
         t = self.torch
         for a in (g, cov_acc, G_acc):
-            assert a.dtype == t.float64 and a.is_contiguous() and a.is_cuda
-        assert g.numel() == self.d * self.N and cov_acc.numel() == self.d * self.N
+            self._bonds_f64(a, full=a is not G_acc)
         assert G_acc.numel() >= 2
+        gc = None
+        if g_center is not None:
+            self._bonds_f64(g_center, full=False)
+            gc = C.c_void_p(g_center.data_ptr())
         _check(load_library().smc_chains_covariance(self._h, float(beta), int(n_sweeps),
-                                                    C.c_void_p(g.data_ptr()), float(g_center),
+                                                    C.c_void_p(g.data_ptr()), gc,
                                                     C.c_void_p(cov_acc.data_ptr()),
                                                     C.c_void_p(G_acc.data_ptr())))
+
+    # -- finishing the estimates (the library's FP64 kernels) ---------------
+    def _bonds_f64(self, a, full=True):
+        t = self.torch
+        assert a.dtype == t.float64 and a.is_contiguous() and a.is_cuda
+        if full:
+            assert a.numel() == self.d * self.N
+
+    def _bonds_f32(self, a):
+        t = self.torch
+        assert a.dtype == t.float32 and a.is_contiguous() and a.is_cuda
+        assert a.numel() == self.d * self.N
+
+    def mean(self, bond_sum, n_samples: int):
+        """<x_b> = bond_sum / n_samples (float64 [d, 2, N/2])."""
+        t = self.torch
+        assert bond_sum.dtype == t.int64 and bond_sum.is_contiguous() and bond_sum.is_cuda
+        out = t.empty((self.d, 2, self.N // 2), dtype=t.float64, device=self.device)
+        _check(load_library().smc_chains_mean(self._h, C.c_void_p(bond_sum.data_ptr()),
+                                              int(n_samples), C.c_void_p(out.data_ptr())))
+        return out
+
+    def dot(self, a, w):
+        """sum_b a_b w_b as a one-element float64 device tensor."""
+        t = self.torch
+        self._bonds_f64(a)
+        self._bonds_f64(w)
+        out = t.empty(1, dtype=t.float64, device=self.device)
+        _check(load_library().smc_chains_dot(self._h, C.c_void_p(a.data_ptr()),
+                                             C.c_void_p(w.data_ptr()), C.c_void_p(out.data_ptr())))
+        return out
+
+    def vjp(self, beta: float, n_samples: int, cov_acc, G_acc, mean, J):
+        """(beta Cov(G, x_b) as float32, sum_b J_b Cov(G, x_b) as a one-element
+        float64 tensor) from a covariance replay's sums."""
+        t = self.torch
+        for a in (cov_acc, mean):
+            self._bonds_f64(a)
+        self._bonds_f64(G_acc, full=False)
+        self._bonds_f32(J)
+        gJ = t.empty((self.d, 2, self.N // 2), dtype=t.float32, device=self.device)
+        gb = t.empty(1, dtype=t.float64, device=self.device)
+        _check(load_library().smc_chains_vjp(self._h, float(beta), int(n_samples),
+                                             C.c_void_p(cov_acc.data_ptr()), C.c_void_p(G_acc.data_ptr()),
+                                             C.c_void_p(mean.data_ptr()), C.c_void_p(J.data_ptr()),
+                                             C.c_void_p(gJ.data_ptr()), C.c_void_p(gb.data_ptr())))
+        return gJ, gb
+
+    def lnz_grad(self, beta: float, mean, J, scale=None, dtype=None):
+        """(scale beta <x_b>, scale sum_b J_b <x_b>): the gradients of ln Z in J
+        (float32 or float64 per dtype) and beta (one-element float64);
+        scale: a one-element float64 device tensor or None (1)."""
+        t = self.torch
+        self._bonds_f64(mean)
+        self._bonds_f32(J)
+        dt = dtype or t.float32
+        gJ = t.empty((self.d, 2, self.N // 2), dtype=dt, device=self.device)
+        gb = t.empty(1, dtype=t.float64, device=self.device)
+        sp = None
+        if scale is not None:
+            self._bonds_f64(scale, full=False)
+            sp = C.c_void_p(scale.data_ptr())
+        f32 = C.c_void_p(gJ.data_ptr()) if dt == t.float32 else None
+        f64 = C.c_void_p(gJ.data_ptr()) if dt == t.float64 else None
+        _check(load_library().smc_chains_lnz_grad(self._h, float(beta), C.c_void_p(mean.data_ptr()),
+                                                  C.c_void_p(J.data_ptr()), sp, f32, f64,
+                                                  C.c_void_p(gb.data_ptr())))
+        return gJ, gb
+
+    def fit_step(self, beta: float, lr: float, target, mean, J):
+        """Moment matching, in place: J += lr beta (target - <x>)."""
+        self._bonds_f64(target)
+        self._bonds_f64(mean)
+        self._bonds_f32(J)
+        _check(load_library().smc_chains_fit_step(self._h, float(beta), float(lr),
+                                                  C.c_void_p(target.data_ptr()),
+                                                  C.c_void_p(mean.data_ptr()), C.c_void_p(J.data_ptr())))
 
     @property
     def t(self) -> int:

@@ -8,12 +8,16 @@ product across bond b, real couplings J_b):
     d <x_a> / d J_b  = beta Cov(x_a, x_b)
     d <x_a> / d beta = Cov(x_a, sum_b J_b x_b)
 
-Expectations are estimated by the chains of a `Chains` object (all in the
-library's kernels): `smc_chains_sample` sums x_b over chains and sweeps;
-`smc_chains_covariance` replays the same sweeps from the saved start state and
-counter (counter-based random numbers make the replay exact) and sums
-G x_b for G = sum_a g_a x_a, the vector-Jacobian product's weights.  Nothing
-is stored per sample.
+Every step runs in the library's kernels: `smc_chains_sample` sums x_b over
+chains and sweeps; `smc_chains_mean` forms <x_b>; `smc_chains_covariance`
+replays the same sweeps from the saved start state and counter
+(counter-based random numbers make the replay exact) and sums (G - c) x_b for
+G = sum_a g_a x_a, the vector-Jacobian product's weights, centred on
+c = sum_a g_a <x_a> from `smc_chains_dot`; `smc_chains_vjp`,
+`smc_chains_lnz_grad` and `smc_chains_fit_step` finish the gradients and the
+moment-matching update in FP64.  Nothing is stored per sample.  This module
+allocates the tensors, converts the cotangents to the library's dtypes and
+calls the binding -- no arithmetic of the method runs in torch.
 
 All arrays over bonds have the coupling layout [d, 2, N/2] (bond (mu, c, j)
 from site (c, j) of colour plane c to its +mu neighbour).
@@ -31,7 +35,11 @@ def _sample_mean(chains: Chains, beta: float, n_sweeps: int, n_burn: int):
         chains.sample(beta, n_burn)
     acc = chains.bond_zeros()
     chains.sample(beta, n_sweeps, acc)
-    return acc.double() / float(chains.n_chains * n_sweeps)
+    return chains.mean(acc, chains.n_chains * n_sweeps)
+
+
+def _f32(J):
+    return J.detach().to(torch.float32).contiguous()
 
 
 class BondCorrelations(torch.autograd.Function):
@@ -49,7 +57,8 @@ class BondCorrelations(torch.autograd.Function):
         mean = _sample_mean(chains, b, n_sweeps, 0)
         ctx.chains, ctx.b, ctx.n_sweeps, ctx.t0 = chains, b, n_sweeps, t0
         ctx.beta_dtype = beta.dtype if torch.is_tensor(beta) else torch.float64
-        ctx.save_for_backward(J.detach().clone(), mean, start)
+        ctx.J_dtype = J.dtype
+        ctx.save_for_backward(_f32(J).clone(), mean, start)
         return mean.to(J.dtype)
 
     @staticmethod
@@ -62,18 +71,16 @@ class BondCorrelations(torch.autograd.Function):
         ch.spins.copy_(start)
         ch.t = ctx.t0
         g = grad.to(torch.float64).contiguous()
-        g_center = float((g * mean).sum())
+        center = ch.dot(g, mean)
         cov_acc = torch.zeros_like(mean)
         G_acc = torch.zeros(2, dtype=torch.float64, device=mean.device)
-        ch.covariance(ctx.b, ctx.n_sweeps, g, g_center, cov_acc, G_acc)
-        S = float(ch.n_chains * ctx.n_sweeps)
-        cov = cov_acc / S - (G_acc[0] / S) * mean  # Cov(G, x_b)
+        ch.covariance(ctx.b, ctx.n_sweeps, g, center, cov_acc, G_acc)
+        grad_J, grad_beta = ch.vjp(ctx.b, ch.n_chains * ctx.n_sweeps, cov_acc, G_acc, mean, J)
         ch.spins.copy_(end)
         ch.t = t_end
         ch.set_couplings(J_now)
-        grad_J = (ctx.b * cov).to(J.dtype)
-        grad_beta = (J.to(torch.float64) * cov).sum().to(ctx.beta_dtype)
-        return grad_J, grad_beta, None, None, None
+        return (grad_J.to(ctx.J_dtype), grad_beta.reshape(()).to(ctx.beta_dtype), None, None,
+                None)
 
 
 def bond_correlations(J, beta, chains: Chains, n_sweeps: int, n_burn: int = 0):
@@ -95,17 +102,18 @@ class LogPartition(torch.autograd.Function):
         b = float(beta)
         chains.set_couplings(J.detach())
         mean = _sample_mean(chains, b, n_sweeps, n_burn)
-        ctx.b = b
+        ctx.chains, ctx.b = chains, b
         ctx.beta_dtype = beta.dtype if torch.is_tensor(beta) else torch.float64
-        ctx.save_for_backward(J.detach(), mean)
+        ctx.J_dtype = J.dtype
+        ctx.save_for_backward(_f32(J), mean)
         return torch.zeros((), dtype=J.dtype, device=J.device)
 
     @staticmethod
     def backward(ctx, grad):
         J, mean = ctx.saved_tensors
-        gJ = (grad.to(torch.float64) * ctx.b * mean).to(J.dtype)
-        gb = (grad.to(torch.float64) * (J.to(torch.float64) * mean).sum()).to(ctx.beta_dtype)
-        return gJ, gb, None, None, None
+        scale = grad.detach().to(torch.float64).reshape(1).contiguous()
+        gJ, gb = ctx.chains.lnz_grad(ctx.b, mean, J, scale=scale)
+        return gJ.to(ctx.J_dtype), gb.reshape(()).to(ctx.beta_dtype), None, None, None
 
 
 def log_partition(J, beta, chains: Chains, n_sweeps: int, n_burn: int = 0):
@@ -115,10 +123,12 @@ def log_partition(J, beta, chains: Chains, n_sweeps: int, n_burn: int = 0):
 
 
 def log_partition_grad(J, beta: float, chains: Chains, n_sweeps: int, n_burn: int = 0):
-    """(d ln Z / d J, d ln Z / d beta) = (beta <x>, sum_b J_b <x_b>)."""
+    """(d ln Z / d J, d ln Z / d beta) = (beta <x>, sum_b J_b <x_b>): a float64
+    tensor over the bonds and a Python float."""
     chains.set_couplings(J)
     mean = _sample_mean(chains, float(beta), n_sweeps, n_burn)
-    return float(beta) * mean, float((J.to(torch.float64) * mean).sum())
+    gJ, gb = chains.lnz_grad(float(beta), mean, _f32(J), dtype=torch.float64)
+    return gJ, float(gb.item())
 
 
 def fit_couplings(target, beta: float, chains: Chains, steps: int, lr: float, n_sweeps: int,
@@ -127,10 +137,11 @@ def fit_couplings(target, beta: float, chains: Chains, steps: int, lr: float, n_
     correlations `target`, whose gradient in J is beta (target - <x>_J).
     Returns the fitted couplings (float32, coupling layout)."""
     J = (J_init if J_init is not None else chains.J).detach().to(torch.float32).clone()
+    tgt = target.detach().to(torch.float64).contiguous()
     for _ in range(steps):
         chains.set_couplings(J)
         model = _sample_mean(chains, float(beta), n_sweeps, n_burn)
-        J = J + (lr * float(beta) * (target.to(torch.float64) - model)).to(torch.float32)
+        chains.fit_step(float(beta), float(lr), tgt, model, J)
         if history is not None:
             history.append(J.clone())
     return J

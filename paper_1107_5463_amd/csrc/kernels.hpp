@@ -177,14 +177,33 @@ struct ChainsLaunch {
   float beta;
   uint32_t n_chains;
   FastDiv divR, divL;  // plane row length L/2, edge L
+  int pair_kernel;     // one pair of sites per lane, state in registers (N/4 <= 1024)
 };
+// Whether the pair kernel takes lattice g (at most 1024 site pairs per colour).
+bool chains_pair_supported(const Geom& g);
 size_t chains_lds_bytes(const Geom& g, int mode);
 // Raise the dynamic-LDS limit of the chain kernels for lattice g.
 hipError_t chains_allow_lds(const Geom& g);
 hipError_t launch_chains_sample(const ChainsLaunch& a, int8_t* spins, uint32_t t0,
                                 uint32_t n_sweeps, int64_t* bond_sum, hipStream_t st);
+// Finishing the derivative estimates over the d N bonds (FP64, deterministic).
+hipError_t launch_chains_mean(const Geom& g, const int64_t* sum, int64_t n_samples, double* mean,
+                              hipStream_t st);
+hipError_t launch_chains_dot(const Geom& g, const double* a, const double* w, double* out,
+                             hipStream_t st);
+hipError_t launch_chains_vjp(const Geom& g, const double* cov_acc, const double* G_acc,
+                             const double* mean, const float* J, int64_t n_samples, double beta,
+                             float* grad_J, double* grad_beta, hipStream_t st);
+hipError_t launch_chains_lnz_grad(const Geom& g, const double* mean, const float* J, double beta,
+                                  const double* scale, float* gJ32, double* gJ64,
+                                  double* grad_beta, hipStream_t st);
+hipError_t launch_chains_fit_step(const Geom& g, const double* target, const double* mean,
+                                  double rate, float* J, hipStream_t st);
+// One colour's half of sweep t (no accumulation; t is not advanced).
+hipError_t launch_chains_half_sweep(const ChainsLaunch& a, int8_t* spins, uint32_t t, int colour,
+                                    hipStream_t st);
 hipError_t launch_chains_covariance(const ChainsLaunch& a, int8_t* spins, uint32_t t0,
-                                    uint32_t n_sweeps, const double* g, double gc, double* part,
+                                    uint32_t n_sweeps, const double* g, const double* gc, double* part,
                                     double* gpart, double* cov_acc, double* G_acc,
                                     hipStream_t st);
 

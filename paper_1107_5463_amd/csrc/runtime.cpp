@@ -1239,6 +1239,7 @@ struct smc_chains {
   double* gpart;  // [n_chains][2]
   hipStream_t stream;
   uint64_t t;
+  int pair_kernel;  // the register-resident pair kernel (SMC_CHAINS_KERNEL=lds forces the other)
 };
 
 namespace {
@@ -1274,8 +1275,12 @@ ChainsLaunch chains_args(const smc_chains* h, double beta) {
   a.n_chains = (uint32_t)h->n_chains;
   a.divR = make_fastdiv((uint32_t)h->g.R);
   a.divL = make_fastdiv((uint32_t)h->g.L);
+  a.pair_kernel = h->pair_kernel;
   return a;
 }
+
+bool al8(const void* p) { return p && !((uintptr_t)p & 7); }
+bool al4(const void* p) { return p && !((uintptr_t)p & 3); }
 
 }  // namespace
 
@@ -1343,6 +1348,9 @@ int smc_chains_init(smc_chains** out, int32_t d, int32_t L, int32_t n_chains, ui
                        round_up((size_t)n_chains * chains_sites(d, L) * d * sizeof(double), kAlign));
   h->stream = (hipStream_t)stream;
   h->t = 0;
+  h->pair_kernel = chains_pair_supported(h->g) ? 1 : 0;
+  if (const char* v = std::getenv("SMC_CHAINS_KERNEL"))
+    if (std::string(v) == "lds") h->pair_kernel = 0;
   int rc = check(chains_allow_lds(h->g), "chains LDS attribute");
   const size_t N = chains_sites(d, L);
   for (int32_t k = 0; rc == SMC_OK && init != SMC_INIT_KEEP && k < n_chains; ++k) {
@@ -1383,12 +1391,27 @@ int smc_chains_sample(smc_chains* h, double beta, int64_t n_sweeps, int64_t* dev
   return SMC_OK;
 }
 
+int smc_chains_half_sweep(smc_chains* h, double beta, int colour) {
+  if (!h) return fail(SMC_EINVAL, "handle is NULL");
+  if (!beta_ok(beta)) return fail(SMC_EINVAL, "beta must be >= 0 (or +inf), not NaN");
+  if (colour != 0 && colour != 1) return fail(SMC_EINVAL, "colour must be 0 or 1");
+  if (h->t >= 4294967296ull) return fail(SMC_ERANGE, "sweep counter is past 2^32 - 1");
+  return check(launch_chains_half_sweep(chains_args(h, beta), (int8_t*)h->spins, (uint32_t)h->t,
+                                        colour, h->stream),
+               "chains half-sweep launch");
+}
+
+const char* smc_chains_kernel_name(const smc_chains* h) {
+  if (!h) return "";
+  return h->pair_kernel ? "chains_pair" : "chains_lds";
+}
+
 int smc_chains_covariance(smc_chains* h, double beta, int64_t n_sweeps, const double* dev_g,
-                          double g_center, double* dev_cov_acc, double* dev_G_acc) {
+                          const double* dev_g_center, double* dev_cov_acc, double* dev_G_acc) {
   if (!h) return fail(SMC_EINVAL, "handle is NULL");
   if (!beta_ok(beta)) return fail(SMC_EINVAL, "beta must be >= 0 (or +inf), not NaN");
   if (n_sweeps < 0) return fail(SMC_EINVAL, "n_sweeps must be >= 0");
-  if (!std::isfinite(g_center)) return fail(SMC_EINVAL, "g_center must be finite");
+  if ((uintptr_t)dev_g_center & 7) return fail(SMC_EINVAL, "g_center must be 8-byte aligned (or NULL)");
   if (!dev_g || !dev_cov_acc || !dev_G_acc || ((uintptr_t)dev_g & 7) ||
       ((uintptr_t)dev_cov_acc & 7) || ((uintptr_t)dev_G_acc & 7))
     return fail(SMC_EINVAL, "g, cov_acc and G_acc must be non-NULL and 8-byte aligned");
@@ -1397,12 +1420,70 @@ int smc_chains_covariance(smc_chains* h, double beta, int64_t n_sweeps, const do
   if (n_sweeps == 0) return SMC_OK;
   const ChainsLaunch a = chains_args(h, beta);
   const int rc = check(launch_chains_covariance(a, (int8_t*)h->spins, (uint32_t)h->t,
-                                                (uint32_t)n_sweeps, dev_g, g_center, h->part,
+                                                (uint32_t)n_sweeps, dev_g, dev_g_center, h->part,
                                                 h->gpart, dev_cov_acc, dev_G_acc, h->stream),
                        "chains covariance launch");
   if (rc != SMC_OK) return rc;
   h->t += (uint64_t)n_sweeps;
   return SMC_OK;
+}
+
+int smc_chains_mean(smc_chains* h, const int64_t* dev_bond_sum, int64_t n_samples,
+                    double* dev_mean) {
+  if (!h) return fail(SMC_EINVAL, "handle is NULL");
+  if (n_samples < 1) return fail(SMC_EINVAL, "n_samples must be >= 1");
+  if (!al8(dev_bond_sum) || !al8(dev_mean))
+    return fail(SMC_EINVAL, "bond_sum and mean must be non-NULL and 8-byte aligned");
+  return check(launch_chains_mean(h->g, dev_bond_sum, n_samples, dev_mean, h->stream),
+               "chains mean launch");
+}
+
+int smc_chains_dot(smc_chains* h, const double* dev_a, const double* dev_w, double* dev_out) {
+  if (!h) return fail(SMC_EINVAL, "handle is NULL");
+  if (!al8(dev_a) || !al8(dev_w) || !al8(dev_out))
+    return fail(SMC_EINVAL, "a, b and out must be non-NULL and 8-byte aligned");
+  return check(launch_chains_dot(h->g, dev_a, dev_w, dev_out, h->stream), "chains dot launch");
+}
+
+int smc_chains_vjp(smc_chains* h, double beta, int64_t n_samples, const double* dev_cov_acc,
+                   const double* dev_G_acc, const double* dev_mean, const float* dev_J,
+                   float* dev_grad_J, double* dev_grad_beta) {
+  if (!h) return fail(SMC_EINVAL, "handle is NULL");
+  if (!std::isfinite(beta) || beta < 0.0) return fail(SMC_EINVAL, "beta must be finite and >= 0");
+  if (n_samples < 1) return fail(SMC_EINVAL, "n_samples must be >= 1");
+  if (!al8(dev_cov_acc) || !al8(dev_G_acc) || !al8(dev_mean) || !al8(dev_grad_beta) ||
+      !al4(dev_J) || !al4(dev_grad_J))
+    return fail(SMC_EINVAL, "buffers must be non-NULL and aligned (double 8, float 4 bytes)");
+  return check(launch_chains_vjp(h->g, dev_cov_acc, dev_G_acc, dev_mean, dev_J, n_samples, beta,
+                                 dev_grad_J, dev_grad_beta, h->stream),
+               "chains vjp launch");
+}
+
+int smc_chains_lnz_grad(smc_chains* h, double beta, const double* dev_mean, const float* dev_J,
+                        const double* dev_scale, float* dev_grad_J_f32, double* dev_grad_J_f64,
+                        double* dev_grad_beta) {
+  if (!h) return fail(SMC_EINVAL, "handle is NULL");
+  if (!std::isfinite(beta) || beta < 0.0) return fail(SMC_EINVAL, "beta must be finite and >= 0");
+  if (!al8(dev_mean) || !al4(dev_J) || !al8(dev_grad_beta) || ((uintptr_t)dev_scale & 7))
+    return fail(SMC_EINVAL, "mean, J and grad_beta must be non-NULL and aligned");
+  if ((dev_grad_J_f32 != nullptr) == (dev_grad_J_f64 != nullptr))
+    return fail(SMC_EINVAL, "exactly one of grad_J_f32 and grad_J_f64 must be given");
+  if ((dev_grad_J_f32 && !al4(dev_grad_J_f32)) || (dev_grad_J_f64 && !al8(dev_grad_J_f64)))
+    return fail(SMC_EINVAL, "grad_J must be aligned");
+  return check(launch_chains_lnz_grad(h->g, dev_mean, dev_J, beta, dev_scale, dev_grad_J_f32,
+                                      dev_grad_J_f64, dev_grad_beta, h->stream),
+               "chains ln Z gradient launch");
+}
+
+int smc_chains_fit_step(smc_chains* h, double beta, double lr, const double* dev_target,
+                        const double* dev_mean, float* dev_J) {
+  if (!h) return fail(SMC_EINVAL, "handle is NULL");
+  if (!std::isfinite(beta) || beta < 0.0) return fail(SMC_EINVAL, "beta must be finite and >= 0");
+  if (!std::isfinite(lr)) return fail(SMC_EINVAL, "lr must be finite");
+  if (!al8(dev_target) || !al8(dev_mean) || !al4(dev_J))
+    return fail(SMC_EINVAL, "target, mean (8) and J (4) must be non-NULL and aligned");
+  return check(launch_chains_fit_step(h->g, dev_target, dev_mean, lr * beta, dev_J, h->stream),
+               "chains fit step launch");
 }
 
 int smc_chains_get_sweep_index(const smc_chains* h, uint64_t* t) {

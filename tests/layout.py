@@ -35,3 +35,27 @@ def to_natural(a: np.ndarray, d: int, L: int) -> np.ndarray:
     N = L ** d
     flat = a.reshape(a.shape[:-2] + (N,))
     return flat[..., split_index(d, L)]
+
+
+@functools.lru_cache(maxsize=8)
+def natural_neighbours(d: int, L: int) -> np.ndarray:
+    """[N, 2d] natural indices of the +x, -x, +y, -y(, +z, -z) neighbours
+    (periodic)."""
+    N = L ** d
+    i = np.arange(N, dtype=np.int64)
+    co = [i % L, (i // L) % L] + ([i // (L * L)] if d == 3 else [])
+    out = np.empty((N, 2 * d), dtype=np.int64)
+    for mu in range(d):
+        for k, step in enumerate((1, -1)):
+            c2 = list(co)
+            c2[mu] = (co[mu] + step) % L
+            out[:, 2 * mu + k] = sum(c2[a] * L ** a for a in range(d))
+    return out
+
+
+def natural_colours(d: int, L: int) -> np.ndarray:
+    """Colour (x + y + z) % 2 of each natural site."""
+    N = L ** d
+    i = np.arange(N, dtype=np.int64)
+    s = i % L + (i // L) % L + (i // (L * L) if d == 3 else 0)
+    return (s & 1).astype(np.int8)

@@ -143,7 +143,14 @@ def test_chain_init_rejects_bad_arguments(smc_host):
     assert lib.smc_chains_init(C.byref(h), 2, 8, 4, 0, 0, 0, None, None, None, 0, None) == smc_host.SMC_EINVAL
     assert b"J must be" in lib.smc_last_error()
     assert lib.smc_chains_sample(None, 0.4, 1, None) == smc_host.SMC_EINVAL
-    assert lib.smc_chains_covariance(None, 0.4, 1, None, 0.0, None, None) == smc_host.SMC_EINVAL
+    assert lib.smc_chains_covariance(None, 0.4, 1, None, None, None, None) == smc_host.SMC_EINVAL
+    assert lib.smc_chains_half_sweep(None, 0.4, 0) == smc_host.SMC_EINVAL
+    assert lib.smc_chains_mean(None, None, 1, None) == smc_host.SMC_EINVAL
+    assert lib.smc_chains_dot(None, None, None, None) == smc_host.SMC_EINVAL
+    assert lib.smc_chains_vjp(None, 0.4, 1, None, None, None, None, None, None) == smc_host.SMC_EINVAL
+    assert lib.smc_chains_lnz_grad(None, 0.4, None, None, None, None, None, None) == smc_host.SMC_EINVAL
+    assert lib.smc_chains_fit_step(None, 0.4, 1.0, None, None, None) == smc_host.SMC_EINVAL
+    assert lib.smc_chains_kernel_name(None) == b""
 
 
 @pytest.mark.parametrize("kw,msg", [
