@@ -18,7 +18,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# SMC_ORACLE_LIB: another build of the same source (the sanitizer leg of the
+# tests loads an AddressSanitizer / UBSan build this way)
+LIB_PATH = os.environ.get("SMC_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 
 J_UNIFORM, J_PM, J_FP32 = 0, 1, 2
 

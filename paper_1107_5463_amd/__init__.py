@@ -25,7 +25,9 @@ __all__ = ["Lattice", "Batch", "Chains", "SmcError", "load_library", "lib_path",
            "J_FP32", "EXPORTS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "libsmc.so")
+# SMC_LIBRARY: another build of the same sources (the tests' sanitizer leg
+# loads one whose host code is built with AddressSanitizer and UBSan)
+_LIB_PATH = os.environ.get("SMC_LIBRARY") or os.path.join(_HERE, "libsmc.so")
 
 J_UNIFORM, J_PM, J_FP32 = 0, 1, 2
 INIT_HOT, INIT_COLD, INIT_KEEP = 0, 1, 2
