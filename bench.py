@@ -39,8 +39,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0
 # VALU peak in 32-bit lane operations per second: the FP32 vector rate of
 # 157.3 TFLOP/s counts an FMA as two flops, i.e. 78.6e12 lane operations/s
-# (256 CUs x 2.4 GHz x 128 lanes)
+# (256 CUs x 2.4 GHz x 128 lanes: two VALU instructions per SIMD quad-cycle)
 VALU_PEAK_TOPS = 78.6
+# One VALU instruction per SIMD per quad-cycle (a wave64 instruction over the
+# 16-lane SIMD): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 lane
+# operations/s, the issue ceiling of code whose instructions do not pair
+VALU_ISSUE_PEAK_TOPS = 39.3
 
 # Proposal widths giving 50 +- 5 % acceptance at the benchmark temperatures
 # (found with the oracle on small lattices; checked by a CPU test).
@@ -60,14 +64,15 @@ WORKLOADS = {
 # Source files of each dominant kernel (a counter summary is valid only for
 # the sources it was taken on).
 KERNEL_SOURCES = {
-    "ising_stream": ["ising.hip", "chunk.hpp", "device.hpp", "kernels.hpp", "reduce.hpp"],
-    "ising_fused": ["fused.hip", "chunk.hpp", "device.hpp", "kernels.hpp", "reduce.hpp"],
-    "ising_packed": ["packed.hip", "chunk.hpp", "device.hpp", "kernels.hpp", "reduce.hpp"],
-    "ising_tiles": ["tiles.hip", "chunk.hpp", "device.hpp", "kernels.hpp"],
-    "xy_stream": ["continuous.hip", "chunk.hpp", "device.hpp", "kernels.hpp"],
-    "heisenberg_stream": ["continuous.hip", "chunk.hpp", "device.hpp", "kernels.hpp"],
-    "batch": ["batch.hip", "chunk.hpp", "device.hpp", "kernels.hpp", "reduce.hpp"],
-    "chains": ["chains.hip", "chunk.hpp", "device.hpp", "kernels.hpp"],
+    "ising_stream": ["ising.hip", "chunk.hpp", "device.hpp", "launch_args.hpp", "reduce.hpp"],
+    "ising_fused": ["fused.hip", "chunk.hpp", "device.hpp", "launch_args.hpp", "reduce.hpp"],
+    "ising_packed": ["packed.hip", "chunk.hpp", "device.hpp", "launch_args.hpp", "reduce.hpp"],
+    "ising_tiles": ["tiles.hip", "chunk.hpp", "device.hpp", "launch_args.hpp"],
+    "xy_stream": ["continuous.hip", "chunk.hpp", "device.hpp", "launch_args.hpp"],
+    "heisenberg_stream": ["continuous.hip", "chunk.hpp", "device.hpp", "launch_args.hpp"],
+    "batch": ["batch.hip", "chunk.hpp", "device.hpp", "launch_args.hpp", "reduce.hpp"],
+    "chains": ["chains.hip", "chunk.hpp", "device.hpp", "launch_args.hpp"],
+    "probe": ["probe.hip", "device.hpp"],
 }
 
 
@@ -99,6 +104,13 @@ def parse():
                     help="approximate host time of the oracle baseline (0 = skip)")
     ap.add_argument("--no-batched", action="store_true",
                     help="default 2D line: skip the batched spin-glass comparison attached to it")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="default 2D line: skip the 3D Ising, XY, Heisenberg and chains objects "
+                         "attached to it")
+    ap.add_argument("--probes", action="store_true",
+                    help="measure the ceilings instead of a workload: device copies of 32 MiB, "
+                         "256 MiB and 1 GiB, Philox4x32-10 blocks alone, and the integer VALU "
+                         "issue rate (probe kernels of the library)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one 1 GiB device copy before the timed region (calibrates the "
                          "HBM byte counters of a profiler run)")
@@ -124,6 +136,15 @@ def measured_traffic(kernel, workload):
     if rec.get("sources_sha256_16") != sources_digest(kernel):
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def measured_probe(name):
+    """A ceiling measured on the box by a committed probe (profiles/probe_*.json)."""
+    path = os.path.join(ROOT, "profiles", f"probe_{name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        return json.load(fh).get("value")
 
 
 def host_cpu():
@@ -252,12 +273,18 @@ def valu_roofline(kname, workload, kernel_ms, bytes_per_launch, variant=None):
     achieved = None
     if rec is not None:
         achieved = rec["valu_lane_ops_per_launch"] / (kernel_ms * 1e-3) / 1e12
+    probe = measured_probe("valu_issue")
     return {
         "bound": "alu",
         "achieved": None if achieved is None else round(achieved, 2),
         "peak": VALU_PEAK_TOPS,
         "unit": "Tops/s",
         "frac": None if achieved is None else round(achieved / VALU_PEAK_TOPS, 4),
+        "issue_peak": VALU_ISSUE_PEAK_TOPS,
+        "frac_issue": None if achieved is None else round(achieved / VALU_ISSUE_PEAK_TOPS, 4),
+        "probe_ceiling": probe,
+        "frac_probe": None if (achieved is None or not probe) else round(achieved / probe, 4),
+        "lane_ops_per_attempt": None if rec is None else rec.get("lane_ops_per_attempt"),
         "traffic": measured_traffic(kname, workload),
         "kernel": kname,
         "kernel_avg_us": round(kernel_ms * 1e3, 3),
@@ -614,6 +641,62 @@ def run_chains(args, wl, torch, smc):
     return result
 
 
+PROBE_LANES = 1 << 20
+PROBE_PHILOX_BLOCKS = 512
+PROBE_VALU_ITERS = 4096
+
+
+def run_probes(args, torch, smc):
+    """Ceilings measured on this GPU: device copies (read + write GB/s, best of
+    10), Philox blocks per ns with nothing else to do, and the issued VALU
+    lane-operation rate of independent integer chains (instructions per lane
+    and iteration from the committed counter record of the probe kernel)."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    buf = torch.empty(PROBE_LANES, dtype=torch.int32, device=dev)
+    st = torch.cuda.current_stream(dev)
+
+    def best_ms(kind, reps):
+        smc.probe(kind, PROBE_LANES, reps, buf)
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            smc.probe(kind, PROBE_LANES, reps, buf)
+            e1.record(st)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        return best
+
+    ph_ms = best_ms("philox", PROBE_PHILOX_BLOCKS)
+    va_ms = best_ms("valu", PROBE_VALU_ITERS)
+    rec = None
+    path = os.path.join(ROOT, "profiles", "probe_valu_counts.json")
+    if os.path.exists(path):
+        with open(path) as fh:
+            r = json.load(fh)
+        if r.get("sources_sha256_16") == sources_digest("probe"):
+            rec = r
+    out = {
+        "metric": "ceilings measured by probes",
+        "copy_GBps": {f"{mb}MiB": copy_ceiling(torch, dev, mb << 20) for mb in (32, 256, 1024)},
+        "philox_blocks_per_ns": round(PROBE_LANES * PROBE_PHILOX_BLOCKS / (ph_ms * 1e6), 1),
+        "philox_ms": round(ph_ms, 4),
+        "valu_ms": round(va_ms, 4),
+        "probe_lanes": PROBE_LANES,
+    }
+    if rec is not None:
+        # issued VALU instructions (per lane) of one iteration or one block
+        ops = rec["valu_per_lane_iteration"] * PROBE_LANES * PROBE_VALU_ITERS
+        out["valu_issue_Tops"] = round(ops / (va_ms * 1e-3) / 1e12, 2)
+        out["valu_per_philox_block"] = rec.get("valu_per_philox_block")
+        if rec.get("valu_per_philox_block"):
+            pops = rec["valu_per_philox_block"] * PROBE_LANES * PROBE_PHILOX_BLOCKS
+            out["philox_Tops"] = round(pops / (ph_ms * 1e-3) / 1e12, 2)
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -626,6 +709,9 @@ def main():
     import paper_1107_5463_amd as smc
 
     smc.load_library()
+    if args.probes:
+        print(json.dumps(run_probes(args, torch, smc)), flush=True)
+        return
     wl = WORKLOADS[args.workload]
     if args.workload == "batched":
         result = run_batched(args, wl, torch, smc)
@@ -643,7 +729,47 @@ def main():
             result["batched"] = {k: bres[k] for k in ("value", "unit", "ms_per_step", "batched_vs_plain",
                                                       "plain", "roofline")}
             result["batched"]["workload"] = bres["config"]["workload"]
+        if args.workload == "ising2d" and not special and not args.no_extra:
+            attach_other_workloads(args, result, torch, smc)
     print(json.dumps(result), flush=True)
+
+
+def attach_other_workloads(args, result, torch, smc):
+    """The other throughput configurations, each with its own roofline, as
+    objects of the default line (same GPU, same run; no CPU baseline): 3D
+    Ising L = 512 (one bit per site, with its int8 two-pass line), 2D XY
+    L = 4096 and 3D Heisenberg L = 256 (FP32 spins), and the derivative
+    chains (256 chains of L = 64, forward and backward).  The batched
+    spin-glass rate is set against the plain sweeps of the large lattices."""
+    keep = ("value", "unit", "ms_per_step", "dtype", "roofline", "pct_hbm_peak")
+    for name in ("ising3d", "xy", "heisenberg"):
+        a = argparse.Namespace(**vars(args))
+        a.workload, a.steps, a.sweeps_per_step, a.cpu_seconds = name, None, None, 0
+        r = run_lattice(a, WORKLOADS[name], torch, smc)
+        o = {k: r[k] for k in keep}
+        o["workload"] = r["config"]["workload"]
+        o["kernel"], o["rows_per_band"] = r["config"]["kernel"], r["config"]["rows_per_band"]
+        if "int8_two_pass" in r:
+            o["int8_two_pass"] = r["int8_two_pass"]
+        result[name] = o
+        torch.cuda.empty_cache()
+    a = argparse.Namespace(**vars(args))
+    a.workload, a.steps, a.sweeps_per_step, a.cpu_seconds = "chains", None, None, 0
+    r = run_chains(a, WORKLOADS["chains"], torch, smc)
+    result["chains"] = {k: r[k] for k in ("value", "unit", "ms_per_step", "dtype", "roofline",
+                                          "backward")}
+    result["chains"]["workload"] = r["config"]["workload"]
+    result["chains"]["kernel"] = r["config"]["kernel"]
+    b = result.get("batched")
+    if b is not None:
+        plain = {"ising2d_packed": result["value"],
+                 "ising2d_int8": result.get("int8_two_pass", {}).get("value"),
+                 "ising3d_packed": result["ising3d"]["value"],
+                 "ising3d_int8": result["ising3d"].get("int8_two_pass", {}).get("value")}
+        # per attempt: the batched launch against the plain sweep of one large
+        # lattice (3D: the same lattice dimension as the batch)
+        b["vs_plain_large"] = {k: (round(b["value"] / v, 3) if v else None)
+                               for k, v in plain.items()}
 
 
 if __name__ == "__main__":

@@ -382,6 +382,15 @@ int smc_chains_destroy(smc_chains* h);
 int smc_pack_spins(const void* src_int8, void* dst_words, int64_t n_sites, void* stream);
 int smc_unpack_spins(const void* src_words, void* dst_int8, int64_t n_sites, void* stream);
 
+/* Measurement probes for the ceilings the sweep kernels are reported
+ * against (asynchronous): kind 0 draws `reps` Philox4x32-10 blocks per lane
+ * back to back (the random-number cost of every Ising kernel); kind 1 runs
+ * `reps` iterations of eight independent chains of 32-bit xor / permute /
+ * shift / add per lane (the practical integer VALU issue rate).  n_lanes a
+ * positive multiple of 256; each lane writes one folded word to
+ * dev_out[n_lanes] (uint32, caller-owned). */
+int smc_probe(int32_t kind, uint32_t n_lanes, uint32_t reps, void* dev_out, void* stream);
+
 /* The calling thread's last error message ("" if none). */
 const char* smc_last_error(void);
 const char* smc_version(void);

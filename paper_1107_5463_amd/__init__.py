@@ -55,7 +55,7 @@ EXPORTS = ["smc_spin_bytes", "smc_coupling_bytes", "smc_workspace_bytes", "smc_b
            "smc_chains_mean", "smc_chains_dot", "smc_chains_vjp", "smc_chains_lnz_grad",
            "smc_chains_fit_step",
            "smc_chains_get_sweep_index", "smc_chains_set_sweep_index",
-           "smc_chains_destroy", "smc_pack_spins", "smc_unpack_spins"]
+           "smc_chains_destroy", "smc_pack_spins", "smc_unpack_spins", "smc_probe"]
 
 
 class SmcError(RuntimeError):
@@ -164,6 +164,7 @@ def load_library():
     lib.smc_chains_get_sweep_index.argtypes = [vp, C.POINTER(C.c_uint64)]
     lib.smc_chains_set_sweep_index.argtypes = [vp, C.c_uint64]
     lib.smc_chains_destroy.argtypes = [vp]
+    lib.smc_probe.argtypes = [C.c_int32, C.c_uint32, C.c_uint32, vp, vp]
     lib.smc_pack_spins.argtypes = [vp, vp, C.c_int64, vp]
     lib.smc_unpack_spins.argtypes = [vp, vp, C.c_int64, vp]
     lib.smc_last_error.restype = C.c_char_p
@@ -724,6 +725,16 @@ def unpack_spins(src, stream=None):
     _check(load_library().smc_unpack_spins(C.c_void_p(src.data_ptr()), C.c_void_p(out.data_ptr()),
                                            n, C.c_void_p(st.cuda_stream)))
     return out
+
+
+def probe(kind: str, n_lanes: int, reps: int, out, stream=None):
+    """Launch a measurement probe ("philox" or "valu"); out: int32 device
+    tensor of n_lanes elements."""
+    import torch
+    assert out.dtype == torch.int32 and out.is_cuda and out.numel() >= n_lanes
+    st = stream if stream is not None else torch.cuda.current_stream(out.device)
+    _check(load_library().smc_probe({"philox": 0, "valu": 1}[kind], int(n_lanes), int(reps),
+                                    C.c_void_p(out.data_ptr()), C.c_void_p(st.cuda_stream)))
 
 
 def version() -> str:

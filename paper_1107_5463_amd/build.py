@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsmc.so")
 SOURCES = ["ising.hip", "fused.hip", "packed.hip", "tiles.hip", "batch.hip", "chains.hip", "continuous.hip", "init.hip", "measure.hip",
-           "runtime.cpp"]
+           "probe.hip", "runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

@@ -5,42 +5,16 @@
 #include <stdint.h>
 
 #include "device.hpp"
+#include "launch_args.hpp"
 
 namespace smc {
 
-struct RngKey {
-  uint32_t k0, k1;   // seed low / high word
-  uint32_t replica;  // counter word 2
-};
-
-// Exact unsigned 32-bit division by a runtime constant (Granlund-Montgomery):
-// q = (hi + ((n - hi) >> 1)) >> (l - 1) with hi = umulhi(m, n).
-struct FastDiv {
-  uint32_t d, m, s;
-};
 FastDiv make_fastdiv(uint32_t d);
 
 // Raises kernel fn's dynamic-LDS limit on the current device to at least
 // `bytes`, never lowering it: handles of different sizes share the kernels,
 // and a later, smaller handle must not take LDS from an earlier one.
 hipError_t allow_dynamic_lds(const void* fn, size_t bytes);
-
-enum IsingVariant { kVariantAuto = 0, kVariantSite = 1, kVariantChunk = 2, kVariantStream = 3,
-                    kVariantFusedWave = 4 };  // fused schedule: wave-segment kernel (no barriers)
-
-struct IsingLaunch {
-  Geom g;
-  RngKey key;
-  IsingTable tab;    // integer thresholds (uniform and +-1 couplings)
-  int J_kind;        // 0 uniform, 1 +-1 int8, 2 FP32
-  const void* J;     // [d][2][N/2] or null
-  float beta;        // FP32 couplings only
-  int variant;       // IsingVariant
-  uint32_t rows_per_band;  // streaming kernel: rows walked by one lane (divides L)
-  int heatbath;      // rule: 0 Metropolis, 1 heat bath (table holds p_+ thresholds)
-  FastDiv divQ;      // chunks per plane row
-  FastDiv divL;      // edge length
-};
 
 uint32_t stream_rows_per_band(const Geom& g, uint32_t min_waves);
 int ising_variant_used(const IsingLaunch& a);  // the variant a launch resolves to
@@ -58,25 +32,6 @@ hipError_t launch_ising_half_sweep(const IsingLaunch& a, int8_t* spins, uint32_t
 // Chunk kernel requires L % 32 == 0 (plane rows are whole 16-byte chunks).
 bool ising_chunk_supported(const Geom& g, int J_kind);
 
-struct ContLaunch {
-  Geom g;
-  int n;             // 2 or 3
-  RngKey key;
-  int J_kind;
-  float J0;
-  const void* J;
-  float beta;
-  float delta;       // XY max angle
-  float one_minus_cos_cap;  // Heisenberg 1 - cos(theta_max)
-  int fast_math;
-  int variant;              // ContVariant
-  uint32_t rows_per_band;   // streaming kernel band height
-  FastDiv divQ;             // lanes per plane row (R / sites per lane)
-  FastDiv divL;             // edge length
-  double J0d;               // uniform coupling in FP64 (fused measurement)
-};
-
-enum ContVariant { kContAuto = 0, kContRow = 1, kContStream = 2 };
 uint32_t cont_sites_per_lane(int n);
 bool cont_stream_supported(const Geom& g, int n, uint32_t H);
 uint32_t cont_rows_per_band(const Geom& g, int n, uint32_t min_waves);
@@ -97,30 +52,6 @@ hipError_t launch_init_continuous(const Geom& g, int n, RngKey key, int hot, flo
 hipError_t launch_init_couplings(const Geom& g, int J_kind, RngKey key, double J0, double sigma,
                                  void* J, hipStream_t st);
 
-// One lattice of a batch (device table, written by the host runtime).
-struct BatchDesc {
-  uint32_t L, R, Nh, replica;
-  uint32_t divR_m, divR_s, divL_m, divL_s;  // FastDiv constants for R and L
-  uint32_t th_lo, th_hi;                    // threshold bytes (always-accept classes: 0xFF)
-  uint32_t spin_off_lo, spin_off_hi;        // byte offset of its [2][Nh] spins
-  uint32_t J_off_lo, J_off_hi;              // byte offset of its [d][2][Nh] couplings
-  uint32_t frac[7];                         // refinement fractions (2^24: always)
-  uint32_t al_lo, al_hi;                    // byte k = 0xFF if class k always accepts
-  uint32_t pad;
-  double J0;
-};
-
-struct BatchLaunch {
-  int d;
-  bool pm;                 // +-1 couplings (else uniform)
-  uint32_t n_lattices;
-  uint32_t threads;        // workgroup size (one workgroup per lattice)
-  size_t max_sites;        // dynamic LDS bytes: the largest L^d
-  const BatchDesc* descs;  // device
-  const uint32_t* order;   // device: workgroup -> lattice
-  RngKey key;              // replica is taken from each descriptor
-};
-
 // With dev_obs, E and M of every lattice after every `every` sweeps (record m
 // at dev_obs[m * n_lattices + lattice]; with n_sweeps = 0 one record).
 hipError_t launch_batch(const BatchLaunch& a, int8_t* spins, const int8_t* J, uint32_t t0,
@@ -132,15 +63,6 @@ size_t batch_lds_bytes(size_t max_sites, uint32_t threads);
 // The kernel a batch launch uses (for building graph nodes); its arguments are
 // (descs, order, key, spins, J, t0, n_sweeps, every, n_lattices, obs).
 const void* batch_kernel_fn(int d, bool pm, bool measure);
-
-struct MeasureLaunch {
-  Geom g;
-  int n;
-  int J_kind;
-  const void* J;
-  double J0;
-  int64_t sweep;  // sweep counter of the measured state
-};
 
 // Number of per-block partials the measurement writes (workspace sizing).
 int64_t measure_partials(const Geom& g);
@@ -169,16 +91,6 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t st);
 hipError_t launch_validate(const MeasureLaunch& a, const void* spins, uint32_t* dev_count,
                            hipStream_t st);
 
-// Independent chains of one small Ising lattice with shared FP32 couplings.
-struct ChainsLaunch {
-  Geom g;
-  RngKey key;        // key.replica = replica of chain 0
-  const float* J;    // [d][2][Nh]
-  float beta;
-  uint32_t n_chains;
-  FastDiv divR, divL;  // plane row length L/2, edge L
-  int pair_kernel;     // one pair of sites per lane, state in registers (N/4 <= 1024)
-};
 // Whether the pair kernel takes lattice g (at most 1024 site pairs per colour).
 bool chains_pair_supported(const Geom& g);
 size_t chains_lds_bytes(const Geom& g, int mode);
@@ -186,6 +98,9 @@ size_t chains_lds_bytes(const Geom& g, int mode);
 hipError_t chains_allow_lds(const Geom& g);
 hipError_t launch_chains_sample(const ChainsLaunch& a, int8_t* spins, uint32_t t0,
                                 uint32_t n_sweeps, int64_t* bond_sum, hipStream_t st);
+// Measurement probes: kind 0 Philox blocks, kind 1 integer VALU chains; reps
+// blocks or iterations per lane, n_lanes a multiple of 256, out[n_lanes].
+hipError_t launch_probe(int kind, uint32_t n_lanes, uint32_t reps, uint32_t* out, hipStream_t st);
 // Finishing the derivative estimates over the d N bonds (FP64, deterministic).
 hipError_t launch_chains_mean(const Geom& g, const int64_t* sum, int64_t n_samples, double* mean,
                               hipStream_t st);

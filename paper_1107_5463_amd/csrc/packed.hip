@@ -100,35 +100,119 @@ __device__ __forceinline__ void prefix_planes(const uint32_t P[8], uint32_t B[8]
   }
 }
 
-// Per-lane tie queue entries: site (5 bits), row in band (6), class (3),
-// spin was -1 (1).
+// Per-lane queue of the words with exact ties: a slot holds the word's tie
+// mask and its count planes (for the classes of the tied sites) and the row
+// in the band.  A word is queued without a branch (its slot is written and the
+// count advances only if it has ties); the ties are resolved when the queue is
+// full and at the end of the band.
+constexpr uint32_t kTieWords = 4;
+
 struct PackedTies {
-  uint16_t* slot;
+  uint4* ent;       // ent[slot * stride]: (ties, k0, k1, k2)
+  uint8_t* rows;    // rows[slot * stride]: row in the band
   uint32_t stride, n, base, W;  // base: word index of the lane's column in row 0
   int64_t dE, dM;
 };
 
-template <int D>
+template <int D, bool MEASURE>
 __device__ __forceinline__ void packed_tie_flush(PackedTies& q, const TabRegs& tab,
                                                  const RngKey& key, uint32_t t, uint32_t c,
                                                  uint32_t* own) {
-  for (uint32_t i = 0; i < q.n; ++i) {
-    const uint32_t e = q.slot[i * q.stride];
-    const uint32_t b = e & 31u, row = (e >> 5) & 63u, k = (e >> 11) & 7u;
-    const uint32_t wi = q.base + row * q.W;
-    const uint32_t js = wi * 32u + b;
-    const Rand4 rr = philox(js, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
-    if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) {
-      own[wi] ^= 1u << b;  // the lane's own word, stored earlier by this lane
-      const int v = (e >> 14) & 1u ? -1 : 1;
-      q.dE += 4 * (int64_t)(D - (int)k);
-      q.dM -= 2 * (int64_t)v;
+  for (uint32_t e = 0; e < q.n; ++e) {
+    const uint4 en = q.ent[e * q.stride];
+    const uint32_t wi = q.base + (uint32_t)q.rows[e * q.stride] * q.W;
+    uint32_t m = en.x;
+    uint32_t word = 0, flips = 0;
+    if (MEASURE) word = own[wi];
+    while (m) {
+      const uint32_t b = __builtin_ctz(m);
+      m &= m - 1;
+      const uint32_t k = ((en.y >> b) & 1u) | (((en.z >> b) & 1u) << 1) | (((en.w >> b) & 1u) << 2);
+      const uint32_t js = wi * 32u + b;
+      const Rand4 rr = philox(js, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
+      if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) {
+        flips |= 1u << b;
+        if (MEASURE) {
+          const int v = (word >> b) & 1u ? -1 : 1;  // a tied site was left unflipped
+          q.dE += 4 * (int64_t)(D - (int)k);
+          q.dM -= 2 * (int64_t)v;
+        }
+      }
     }
+    if (flips) own[wi] ^= flips;  // the lane's own word, stored earlier by this lane
   }
   q.n = 0;
 }
 
-constexpr uint32_t kPackedTieSlots = 32;  // per-lane tie queue (a full queue is flushed by its lane)
+// Threshold bits of the refusable classes for the fast decision: class 0
+// (and class 2 in 3D) as all-ones / zero masks held in vector registers,
+// class 1 as a scalar byte (one scalar operand per instruction).
+struct FastTab {
+  uint32_t v0[8], v2[8];
+  uint32_t th1;
+};
+
+__device__ __forceinline__ uint32_t vgpr_copy(uint32_t s) {
+  uint32_t v;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+  return v;
+}
+
+template <int D>
+__device__ __forceinline__ FastTab fast_tab(const TabRegs& tab) {
+  FastTab f;
+  const uint32_t t0 = table_byte(tab.th_lo, tab.th_hi, 0), t2 = table_byte(tab.th_lo, tab.th_hi, 2);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    f.v0[b] = vgpr_copy(0u - ((t0 >> b) & 1u));
+    f.v2[b] = D == 3 ? vgpr_copy(0u - ((t2 >> b) & 1u)) : 0u;
+  }
+  f.th1 = table_byte(tab.th_lo, tab.th_hi, 1);
+  return f;
+}
+
+// The 32 prefix bytes of a word's sites as bit planes B[0..7] (bit b of each
+// site's byte), from the word's two Philox blocks.
+__device__ __forceinline__ void word_prefix(const RngKey& key, uint32_t t, uint32_t c, uint32_t wi,
+                                            uint32_t B[8]) {
+  const uint32_t blk = wi * 2u;  // Philox blocks of sites 32 wi .. 32 wi + 31
+  const Rand4 ra = philox(blk, t, key.replica, tag(c, kIsingPrefix), key.k0, key.k1);
+  const Rand4 rb = philox(blk + 1u, t, key.replica, tag(c, kIsingPrefix), key.k0, key.k1);
+  const uint32_t P[8] = {ra.w[0], ra.w[1], ra.w[2], ra.w[3], rb.w[0], rb.w[1], rb.w[2], rb.w[3]};
+  prefix_planes(P, B);
+}
+
+// Decision when only the classes k < d can refuse a move (J0 > 0, where
+// Delta E = 4 J0 (d - k)); classes whose threshold reaches 2^32 keep the
+// table's threshold byte 0xFF with a full refinement fraction, so they accept
+// on every draw here too (a prefix of 0xFF is a tie whose refinement always
+// accepts).  Per site the threshold bit X_b of its class is a select by the
+// count planes; the compare runs from the least significant bit up,
+// lt = [prefix < threshold] by its borrow, eq = [prefix == threshold].
+template <int D>
+__device__ __forceinline__ uint32_t packed_decide_fast(const FastTab& ft, const RngKey& key,
+                                                       uint32_t t, uint32_t c, uint32_t wi,
+                                                       uint32_t k0, uint32_t k1, uint32_t k2,
+                                                       uint32_t& ties) {
+  uint32_t B[8];
+  word_prefix(key, t, c, wi, B);
+  // v_bitop3 truth tables (operands a, b, c): 0xCA = a ? b : c;
+  // 0x8E = (~a & b) | (~(a ^ b) & c), the borrow of a - b into c;
+  // 0x82 = c & ~(a ^ b)
+  uint32_t lt = 0, eq = ~0u;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const uint32_t s1 = __builtin_amdgcn_readfirstlane(0u - ((ft.th1 >> b) & 1u));
+    uint32_t X = __builtin_amdgcn_bitop3_b32(k0, s1, ft.v0[b], 0xCA);
+    if (D == 3) X = __builtin_amdgcn_bitop3_b32(k1, ft.v2[b], X, 0xCA);
+    lt = __builtin_amdgcn_bitop3_b32(B[b], X, lt, 0x8E);
+    eq = __builtin_amdgcn_bitop3_b32(B[b], X, eq, 0x82);
+  }
+  // refusable: k < d (2D: k1 = k2 = 0; 3D: k2 = 0 and not k = 3)
+  const uint32_t refus = D == 2 ? ~(k1 | k2) : ~(k2 | (k1 & k0));
+  ties = refus & eq;
+  return ~(refus & ~lt);  // ties are refused here and resolved by their refinement draws
+}
 
 // Decision for the 32 sites of one word from the count planes k0, k1, k2:
 // returns the flip mask, with the exact ties (in `ties`) refused.
@@ -137,12 +221,8 @@ __device__ __forceinline__ uint32_t packed_decide(const TabRegs& tab, const RngK
                                                   uint32_t t, uint32_t c, uint32_t wi,
                                                   uint32_t k0, uint32_t k1, uint32_t k2,
                                                   uint32_t& ties) {
-  const uint32_t blk = wi * 2u;  // Philox blocks of sites 32 wi .. 32 wi + 31
-  const Rand4 ra = philox(blk, t, key.replica, tag(c, kIsingPrefix), key.k0, key.k1);
-  const Rand4 rb = philox(blk + 1u, t, key.replica, tag(c, kIsingPrefix), key.k0, key.k1);
-  const uint32_t P[8] = {ra.w[0], ra.w[1], ra.w[2], ra.w[3], rb.w[0], rb.w[1], rb.w[2], rb.w[3]};
   uint32_t B[8];
-  prefix_planes(P, B);
+  word_prefix(key, t, c, wi, B);
   // Per-site threshold bit planes: T[b] holds bit b of the threshold byte of
   // each site's class, then one bit-sliced compare of the prefix planes
   // against them.  With J0 > 0 only the classes k < d (Delta E = 4 J0 (d - k)
@@ -193,25 +273,18 @@ __device__ __forceinline__ uint32_t packed_decide(const TabRegs& tab, const RngK
   return ~rej;  // ties are refused here; the caller queues them once the word is stored
 }
 
-// Queue the exact ties of a word already stored (a full queue is flushed by
-// its lane first: a flush writes its flips to the plane, so the word must be
-// there already).
-template <int D>
-__device__ __forceinline__ void packed_queue_ties(PackedTies& q, uint32_t ties, uint32_t row,
-                                                  uint32_t o, uint32_t k0, uint32_t k1,
-                                                  uint32_t k2, const TabRegs& tab,
-                                                  const RngKey& key, uint32_t t, uint32_t c,
-                                                  uint32_t* own) {
-  uint32_t m = ties;
-  do {
-    if (q.n == kPackedTieSlots) packed_tie_flush<D>(q, tab, key, t, c, own);
-    const uint32_t b = __builtin_ctz(m);
-    m &= m - 1;
-    const uint32_t k = ((k0 >> b) & 1u) | (((k1 >> b) & 1u) << 1) | (((k2 >> b) & 1u) << 2);
-    const uint32_t neg = (o >> b) & 1u;
-    q.slot[q.n * q.stride] = (uint16_t)(b | (row << 5) | (k << 11) | (neg << 14));
-    q.n += 1;
-  } while (m);
+// Queue a stored word's exact ties: its slot is written in any case and the
+// count advances only if there are ties; a full queue is resolved at once (its
+// flips go to words already stored).
+template <int D, bool MEASURE>
+__device__ __forceinline__ void packed_queue_word(PackedTies& q, uint32_t ties, uint32_t row,
+                                                  uint32_t k0, uint32_t k1, uint32_t k2,
+                                                  const TabRegs& tab, const RngKey& key,
+                                                  uint32_t t, uint32_t c, uint32_t* own) {
+  q.ent[q.n * q.stride] = make_uint4(ties, k0, k1, k2);
+  q.rows[q.n * q.stride] = (uint8_t)row;
+  q.n += ties != 0u ? 1u : 0u;
+  if (q.n == kTieWords) packed_tie_flush<D, MEASURE>(q, tab, key, t, c, own);
 }
 
 // Unsatisfied-bond count planes of 32 sites from their 2d neighbour words
@@ -243,7 +316,9 @@ __device__ __forceinline__ int32_t popc(uint32_t v) { return __builtin_popcount(
 // The plain launches of a band height chosen for eight waves per SIMD ask the
 // compiler for that occupancy (64 registers); the +-1-coupling 3D kernel would
 // spill there and keeps the default.
-template <int D, bool PM, bool MEASURE>
+// FAST: only the classes k < d can refuse a move (J0 > 0), decided by
+// packed_decide_fast; otherwise packed_decide.
+template <int D, bool PM, bool MEASURE, bool FAST>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void packed_stream_kernel(const Geom g, const RngKey key,
                                                             const IsingTable table,
@@ -253,7 +328,8 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
                                                             const uint32_t* __restrict__ J,
                                                             const uint32_t t, const uint32_t c,
                                                             Partial* __restrict__ parts) {
-  __shared__ uint16_t tie_slots[kPackedTieSlots * 256];
+  __shared__ uint4 tie_ent[kTieWords * 256];
+  __shared__ uint8_t tie_rows[kTieWords * 256];
   const uint32_t tid = xcd_remap(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
   const uint32_t band = fdiv(tid, divW);
   int64_t Esum = 0, Msum = 0;
@@ -261,8 +337,11 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
   const uint32_t Wh = (uint32_t)(g.Nh / 32);  // words per plane
   uint32_t* own = s + (uint64_t)c * Wh;
   const TabRegs tab = tab_regs(table);
+  FastTab ft;
+  if (FAST) ft = fast_tab<D>(tab);
   PackedTies tq;
-  tq.slot = tie_slots + threadIdx.x;
+  tq.ent = tie_ent + threadIdx.x;
+  tq.rows = tie_rows + threadIdx.x;
   tq.stride = 256;
   tq.n = 0;
   tq.base = 0;
@@ -344,10 +423,11 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
       uint32_t k0, k1, k2;
       count_planes<D>(u, k0, k1, k2);
       uint32_t ties;
-      const uint32_t flip = packed_decide<D>(tab, key, t, c, rowb + q, k0, k1, k2, ties);
+      const uint32_t flip = FAST ? packed_decide_fast<D>(ft, key, t, c, rowb + q, k0, k1, k2, ties)
+                                 : packed_decide<D>(tab, key, t, c, rowb + q, k0, k1, k2, ties);
       const uint32_t on = o ^ flip;
       *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(own) + ((rowb + q) << 2)) = on;
-      if (ties) packed_queue_ties<D>(tq, ties, i, o, k0, k1, k2, tab, key, t, c, own);
+      packed_queue_word<D, MEASURE>(tq, ties, i, k0, k1, k2, tab, key, t, c, own);
       if (MEASURE) {
         // colour 1 after its update: each bond has one colour-1 end; the
         // colour-0 word at the same position covers each colour-0 site once
@@ -365,7 +445,7 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
       ct = dn;
     }
   }
-  packed_tie_flush<D>(tq, tab, key, t, c, own);  // the band's queued ties
+  packed_tie_flush<D, MEASURE>(tq, tab, key, t, c, own);  // the band's queued ties
   if (MEASURE) {
     Esum += tq.dE;
     Msum += tq.dM;
@@ -400,17 +480,24 @@ hipError_t launch_packed_half_sweep(const IsingLaunch& a, uint32_t* spins, const
   const dim3 grid((unsigned)((lanes + 255) / 256)), block(256);
   const FastDiv dW = make_fastdiv(W), dL = make_fastdiv((uint32_t)a.g.L);
   const bool pm = a.J_kind == 1;
+  // the fast decision when every class k >= d always accepts (J0 > 0)
+  bool fast = true;
+  for (int k = a.g.d; k <= 2 * a.g.d; ++k)
+    if ((((k < 4 ? a.tab.al_lo : a.tab.al_hi) >> (8 * (k & 3))) & 0xFFu) != 0xFFu) fast = false;
   Partial* pp = (Partial*)partials;
-#define SMC_PK(DD, PMM, MM)                                                                     \
-  hipLaunchKernelGGL((packed_stream_kernel<DD, PMM, MM>), grid, block, 0, st, a.g, a.key, a.tab, \
+#define SMC_PK(DD, PMM, MM, FF)                                                                     \
+  hipLaunchKernelGGL((packed_stream_kernel<DD, PMM, MM, FF>), grid, block, 0, st, a.g, a.key, a.tab, \
                      dW, dL, H, nbands, spins, J, t, c, pp)
+#define SMC_PKF(DD, PMM, MM) \
+  do { if (fast) SMC_PK(DD, PMM, MM, true); else SMC_PK(DD, PMM, MM, false); } while (0)
   if (a.g.d == 2) {
-    if (pm) { if (pp) SMC_PK(2, true, true); else SMC_PK(2, true, false); }
-    else { if (pp) SMC_PK(2, false, true); else SMC_PK(2, false, false); }
+    if (pm) { if (pp) SMC_PKF(2, true, true); else SMC_PKF(2, true, false); }
+    else { if (pp) SMC_PKF(2, false, true); else SMC_PKF(2, false, false); }
   } else {
-    if (pm) { if (pp) SMC_PK(3, true, true); else SMC_PK(3, true, false); }
-    else { if (pp) SMC_PK(3, false, true); else SMC_PK(3, false, false); }
+    if (pm) { if (pp) SMC_PKF(3, true, true); else SMC_PKF(3, true, false); }
+    else { if (pp) SMC_PKF(3, false, true); else SMC_PKF(3, false, false); }
   }
+#undef SMC_PKF
 #undef SMC_PK
   if (pp && nparts) *nparts = grid.x;
   return hipGetLastError();

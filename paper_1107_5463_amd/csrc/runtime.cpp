@@ -668,6 +668,15 @@ int smc_measure_noalloc(const smc_params* p, const void* spins, const void* J, i
                "measurement launch");
 }
 
+int smc_probe(int32_t kind, uint32_t n_lanes, uint32_t reps, void* dev_out, void* stream) {
+  g_err.clear();
+  if (kind != 0 && kind != 1) return fail(SMC_EINVAL, "kind must be 0 (Philox) or 1 (VALU)");
+  if (n_lanes == 0 || n_lanes % 256) return fail(SMC_EINVAL, "n_lanes must be a positive multiple of 256");
+  if (!dev_out || ((uintptr_t)dev_out & 3)) return fail(SMC_EINVAL, "out must be 4-byte aligned");
+  return check(launch_probe(kind, n_lanes, reps, (uint32_t*)dev_out, (hipStream_t)stream),
+               "probe launch");
+}
+
 int smc_measure(smc_lattice* h, smc_obs* out) {
   if (!h) return fail(SMC_EINVAL, "handle is NULL");
   if (!out) return fail(SMC_EINVAL, "out is NULL");
