@@ -270,6 +270,21 @@ int smc_batch_sweep_series(smc_batch* b, int64_t n_sweeps, int64_t measure_every
  * not depend on the choice.  Synchronises the stream. */
 int smc_batch_autotune(smc_batch* b, int32_t* threads_out, int32_t* largest_first_out);
 
+/* The launch schedule: lanes per workgroup (one workgroup per lattice; a
+ * multiple of 64 in [64, 1024], default 256) and the lattice order (largest
+ * first or as given), as smc_batch_autotune sets them.  Results do not depend
+ * on the schedule. */
+int smc_batch_set_schedule(smc_batch* b, int32_t threads, int32_t largest_first);
+int smc_batch_get_schedule(const smc_batch* b, int32_t* threads, int32_t* largest_first);
+
+/* 1 if lattice r takes the packed path at the handle's current workgroup size
+ * (3D, L % 8 == 0, L <= 40, at most two 32-site words of a colour per lane:
+ * one bit per site in LDS, the bit-sliced decision of SMC_FLAG_PACKED -- Sec.
+ * 2, multi-spin coding; the chain is the same), 0 if it takes the one byte
+ * per site path (also for every lattice when SMC_BATCH_PACKED=0 was set at
+ * init), negative on error. */
+int smc_batch_lattice_packed(const smc_batch* b, int32_t r);
+
 /* With enable != 0 later smc_batch_sweep calls replay one instantiated
  * hipGraph holding the launch (rebuilt when n_sweeps, dev_obs or the
  * sweep counter's host copy change shape). */

@@ -46,7 +46,8 @@ EXPORTS = ["smc_spin_bytes", "smc_coupling_bytes", "smc_workspace_bytes", "smc_b
            "smc_kernel_name", "smc_destroy", "smc_last_error", "smc_version",
            "smc_batch_spin_bytes", "smc_batch_coupling_bytes", "smc_batch_workspace_bytes",
            "smc_batch_offsets", "smc_batch_init", "smc_batch_sweep", "smc_batch_sweep_series",
-           "smc_batch_autotune",
+           "smc_batch_autotune", "smc_batch_lattice_packed", "smc_batch_set_schedule",
+           "smc_batch_get_schedule",
            "smc_batch_use_graph", "smc_batch_get_sweep_index", "smc_batch_set_sweep_index",
            "smc_batch_destroy",
            "smc_chains_spin_bytes", "smc_chains_coupling_bytes", "smc_chains_bond_bytes",
@@ -140,6 +141,9 @@ def load_library():
     lib.smc_batch_sweep_series.argtypes = [vp, C.c_int64, C.c_int64, vp]
     lib.smc_batch_autotune.argtypes = [vp, i32p, i32p]
     lib.smc_batch_use_graph.argtypes = [vp, C.c_int32]
+    lib.smc_batch_lattice_packed.argtypes = [vp, C.c_int32]
+    lib.smc_batch_set_schedule.argtypes = [vp, C.c_int32, C.c_int32]
+    lib.smc_batch_get_schedule.argtypes = [vp, i32p, i32p]
     lib.smc_batch_get_sweep_index.argtypes = [vp, C.POINTER(C.c_uint64)]
     lib.smc_batch_set_sweep_index.argtypes = [vp, C.c_uint64]
     lib.smc_batch_destroy.argtypes = [vp]
@@ -468,6 +472,30 @@ class Batch:
                                   C.c_void_p(self.spins.data_ptr()),
                                   None if self.J is None else C.c_void_p(self.J.data_ptr()),
                                   C.c_void_p(ws), wb, C.c_void_p(self.stream.cuda_stream)))
+
+    def schedule(self):
+        """(lanes per workgroup, largest lattice first)."""
+        th, lf = C.c_int32(), C.c_int32()
+        _check(load_library().smc_batch_get_schedule(self._h, C.byref(th), C.byref(lf)))
+        return int(th.value), bool(lf.value)
+
+    def set_schedule(self, threads: int, largest_first: bool = True):
+        _check(load_library().smc_batch_set_schedule(self._h, int(threads), 1 if largest_first else 0))
+
+    @property
+    def threads(self) -> int:
+        return self.schedule()[0]
+
+    @threads.setter
+    def threads(self, value: int):
+        self.set_schedule(value, self.schedule()[1])
+
+    def packed(self, r: int) -> bool:
+        """Whether lattice r takes the packed (one bit per site) path."""
+        rc = load_library().smc_batch_lattice_packed(self._h, int(r))
+        if rc < 0:
+            _check(rc)
+        return rc == 1
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

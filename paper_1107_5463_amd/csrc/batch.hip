@@ -27,11 +27,333 @@
 #include <type_traits>
 
 #include "chunk.hpp"
+#include "packed.hpp"
 #include "reduce.hpp"
 
 namespace smc {
 
 constexpr uint32_t kBatchTieSlots = 4;  // deferred ties per lane before a flush
+
+// ---------------------------------------------------------------------------
+// Packed path (3D lattices with L % 8 == 0, at most two 32-site words of a
+// colour per lane): the lattice sits in LDS at one bit per site -- word w of
+// colour c holds sites 32 w .. 32 w + 31 of that plane, the two colours'
+// words interleaved (byte 8 (w + 1) + 4 c, a zero pad word at each end) --
+// with the signs of each site's 2d bonds as six words aligned with it (the
+// -mu bonds gathered from the neighbours' planes when the lattice is
+// staged).  A lane owns words w = lane and w = lane + blockDim of both
+// colours for the whole call.  The neighbour words of the other colour come
+// from funnel shifts of LDS words: in-row x +- 1 (with the wrap at row ends
+// and the row parity as per-word masks), y +- 1 (a shift by R = L / 2 sites,
+// with the rows at y = L - 1 or 0 taking the wrapped source), and z +- 1 (a
+// whole word: L^2 / 2 sites is a multiple of 32).  Counts, the decision with
+// its prefix bit planes and exact ties, and the random bytes per site are
+// those of the packed single-lattice kernel, so every lattice keeps the
+// chain of its replica bit for bit.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kPackedBatchWordsPerLane = 2;
+constexpr uint32_t kPackedBatchTieWords = 4;
+
+__host__ __device__ inline bool batch_packed_ok(int d, uint32_t L, uint32_t threads) {
+  if (d != 3 || L % 4u != 0u || L > 40u) return false;
+  const uint32_t Wp = L * L * L / 64u;  // words per colour
+  return Wp <= kPackedBatchWordsPerLane * threads;
+}
+
+// LDS bytes of the packed path for edge L: interleaved spin words with pads,
+// aligned bond-sign words (+-1 couplings), the per-lane tie queue.
+__host__ __device__ inline size_t batch_packed_lds_bytes(uint32_t L, bool pm, uint32_t threads) {
+  const size_t Wp = (size_t)L * L * L / 64;
+  const size_t sb = (8 * (Wp + 2) + 15) / 16 * 16;
+  const size_t jb = pm ? 48 * Wp : 0;
+  return sb + jb + (size_t)threads * kPackedBatchTieWords * 20;
+}
+
+struct PackedWord {  // per-call constants of one word of the lane
+  uint32_t E, S, Pm0, Ymp, Ymm;  // row end / start, rows of colour-0 parity 1, y = L-1 / y = 0
+  uint32_t Zmp, Zmm;             // sites at z = L-1 / z = 0 (used when z-planes split words)
+  uint32_t ayp, aym;             // LDS byte addresses (colour 0) of the y wrap sources
+  uint32_t azp, azm;             // z +- 1 sources (low words of the funnels)
+  uint32_t azpw, azmw;           // z wrap sources (z-planes that split words)
+  uint32_t a0;                   // LDS byte address of word w, colour 0
+  uint32_t aj;                   // LDS byte address of its bond-sign words
+  bool valid;
+};
+
+// Funnel shifts of the wrap and z gathers (site offset mod 32).  LR = L^2/2
+// sites per z-plane of one colour; when LR % 32 == 0 the z neighbours are
+// whole words (zs == 0).
+struct PackedZ {
+  uint32_t ysw, ysmw;     // y wraps: R - LR, LR - R
+  uint32_t zs, zsw;       // +z: LR, LR (1 - L)
+  uint32_t zsm, zsmw;     // -z: -LR, LR (L - 1)
+};
+
+// Neighbour words (+x, -x, +y, -y, +z, -z) of word `pw` of colour C from the
+// other colour's words.
+template <uint32_t C>
+__device__ __forceinline__ void packed_neighbours(const unsigned char* lds, const PackedWord& pw,
+                                                  uint32_t R, const PackedZ& pz, uint32_t nb[6]) {
+  constexpr uint32_t O = 4u * (1u - C);  // the other colour's word in a pair
+  auto ldw = [&](uint32_t a) -> uint32_t { return *reinterpret_cast<const uint32_t*>(lds + a); };
+  const uint32_t wp = ldw(pw.a0 - 8 + O), wc = ldw(pw.a0 + O), wn = ldw(pw.a0 + 8 + O);
+  const uint32_t next = __builtin_amdgcn_alignbit(wn, wc, 1u);        // site + 1
+  const uint32_t prev = __builtin_amdgcn_alignbit(wc, wp, 31u);       // site - 1
+  const uint32_t wst = __builtin_amdgcn_alignbit(wc, wp, 33u - R);    // site - (R - 1): row start
+  const uint32_t wen = __builtin_amdgcn_alignbit(wn, wc, R - 1u);     // site + (R - 1): row end
+  // row parity of colour C: p = 1 rows take x + 1 = in-row index + 1
+  const uint32_t Pm = C == 0 ? pw.Pm0 : ~pw.Pm0;
+  nb[0] = __builtin_amdgcn_bitop3_b32(Pm, __builtin_amdgcn_bitop3_b32(pw.E, wst, next, 0xCA), wc, 0xCA);
+  nb[1] = __builtin_amdgcn_bitop3_b32(Pm, wc, __builtin_amdgcn_bitop3_b32(pw.S, wen, prev, 0xCA), 0xCA);
+  const uint32_t yp = __builtin_amdgcn_alignbit(wn, wc, R);
+  const uint32_t ypw = __builtin_amdgcn_alignbit(ldw(pw.ayp + 8 + O), ldw(pw.ayp + O), pz.ysw);
+  nb[2] = __builtin_amdgcn_bitop3_b32(pw.Ymp, ypw, yp, 0xCA);
+  const uint32_t ym = __builtin_amdgcn_alignbit(wc, wp, 32u - R);
+  const uint32_t ymw = __builtin_amdgcn_alignbit(ldw(pw.aym + 8 + O), ldw(pw.aym + O), pz.ysmw);
+  nb[3] = __builtin_amdgcn_bitop3_b32(pw.Ymm, ymw, ym, 0xCA);
+  if (pz.zs == 0u) {  // z-planes hold whole words
+    nb[4] = ldw(pw.azp + O);
+    nb[5] = ldw(pw.azm + O);
+  } else {
+    const uint32_t zp = __builtin_amdgcn_alignbit(ldw(pw.azp + 8 + O), ldw(pw.azp + O), pz.zs);
+    const uint32_t zpw = __builtin_amdgcn_alignbit(ldw(pw.azpw + 8 + O), ldw(pw.azpw + O), pz.zsw);
+    nb[4] = __builtin_amdgcn_bitop3_b32(pw.Zmp, zpw, zp, 0xCA);
+    const uint32_t zm = __builtin_amdgcn_alignbit(ldw(pw.azm + 8 + O), ldw(pw.azm + O), pz.zsm);
+    const uint32_t zmw = __builtin_amdgcn_alignbit(ldw(pw.azmw + 8 + O), ldw(pw.azmw + O), pz.zsmw);
+    nb[5] = __builtin_amdgcn_bitop3_b32(pw.Zmm, zmw, zm, 0xCA);
+  }
+}
+
+// Count planes of word `pw` of colour C: unsatisfied bonds (spin bits differ,
+// xor the bond's sign bit).
+template <uint32_t C, bool PM>
+__device__ __forceinline__ uint32_t packed_word_counts(const unsigned char* lds, const PackedWord& pw,
+                                                       uint32_t R, const PackedZ& pz, uint32_t& k0,
+                                                       uint32_t& k1, uint32_t& k2) {
+  const uint32_t o = *reinterpret_cast<const uint32_t*>(lds + pw.a0 + 4u * C);
+  uint32_t nb[6];
+  packed_neighbours<C>(lds, pw, R, pz, nb);
+  uint32_t u[6];
+#pragma unroll
+  for (int m = 0; m < 6; ++m) {
+    const uint32_t js = PM ? *reinterpret_cast<const uint32_t*>(lds + pw.aj + 4u * (2u * m + C)) : 0u;
+    u[m] = o ^ nb[m] ^ js;
+  }
+  count_planes<3>(u, k0, k1, k2);
+  return o;
+}
+
+template <bool PM, bool MEASURE>
+__device__ void batch_packed_lattice(unsigned char* lds, const BatchDesc* dp, uint32_t li,
+                                     const RngKey& key0, int8_t* gs, const int8_t* gJ,
+                                     uint32_t L, uint32_t R, uint32_t Nh, uint32_t replica,
+                                     const TabRegs& tab, uint32_t t0, uint32_t n_sweeps,
+                                     uint32_t every, uint32_t n_lattices, ObsOut* obs) {
+  constexpr int D = 3;
+  const uint32_t T = blockDim.x, q = threadIdx.x;
+  const uint32_t Wp = Nh / 32u;
+  const uint32_t LR = L * R;  // sites of a z-plane of one colour (a multiple of 32)
+  const uint32_t SB = 0, JB = (8u * (Wp + 2u) + 15u) / 16u * 16u;
+  const uint32_t TQ = JB + (PM ? 48u * Wp : 0u);
+  uint4* tq_ent = reinterpret_cast<uint4*>(lds + TQ) + q;
+  uint16_t* tq_w = reinterpret_cast<uint16_t*>(lds + TQ + 16u * kPackedBatchTieWords * T) + q;
+  const RngKey key{key0.k0, key0.k1, replica};
+
+  // stage the spins: sign bits of 32 int8 sites per word, zero pad words
+  for (uint32_t i = q; i < 2u * Wp; i += T) {
+    const uint32_t c = i & 1u, w = i >> 1;
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(gs + (size_t)c * Nh + 32u * w);
+    uint32_t v = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v |= gather7(src[k]) << (4 * k);
+    *reinterpret_cast<uint32_t*>(lds + SB + 8u * (w + 1u) + 4u * c) = v;
+  }
+  if (q < 2u) {
+    *reinterpret_cast<uint32_t*>(lds + SB + 4u * q) = 0u;
+    *reinterpret_cast<uint32_t*>(lds + SB + 8u * (Wp + 1u) + 4u * q) = 0u;
+  }
+  // in-plane index of the -mu neighbour of site (c, j)
+  const uint32_t sYw = (L - 1) * R, sZ = L * R, sZw = (L - 1) * L * R;
+  auto minus_nb = [&](uint32_t c, uint32_t j, int mu) -> uint32_t {
+    const uint32_t r = j / R, rowb = r * R, jx = j - rowb;
+    const uint32_t z = r / L, y = r - z * L;
+    const uint32_t p = (c + y + z) & 1u;
+    if (mu == 0) return jx + p == 0 ? rowb + R - 1 : j + p - 1;
+    if (mu == 1) return y == 0 ? j + sYw : j - R;
+    return z == 0 ? j + sZw : j - sZ;
+  };
+  if (PM) {
+    for (uint32_t i = q; i < 2u * Wp; i += T) {
+      const uint32_t c = i & 1u, w = i >> 1;
+#pragma unroll
+      for (int mu = 0; mu < 3; ++mu) {
+        // +mu bond of the site itself: J[mu][c][j]
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(gJ + (size_t)(2 * mu + c) * Nh + 32u * w);
+        uint32_t vp = 0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) vp |= gather7(src[k]) << (4 * k);
+        // -mu bond: the +mu bond of the -mu neighbour, J[mu][1 - c][nb]
+        const int8_t* Jn = gJ + (size_t)(2 * mu + 1 - c) * Nh;
+        uint32_t vm = 0;
+        for (uint32_t b = 0; b < 32u; ++b)
+          vm |= (Jn[minus_nb(c, 32u * w + b, mu)] < 0 ? 1u : 0u) << b;
+        *reinterpret_cast<uint32_t*>(lds + JB + 48u * w + 4u * (2u * (2u * mu) + c)) = vp;
+        *reinterpret_cast<uint32_t*>(lds + JB + 48u * w + 4u * (2u * (2u * mu + 1u) + c)) = vm;
+      }
+    }
+  }
+  // funnel shifts of the wrap and z gathers
+  PackedZ pz;
+  pz.ysw = (R - LR) & 31u;
+  pz.ysmw = (LR - R) & 31u;
+  pz.zs = LR & 31u;
+  pz.zsw = (uint32_t)((int32_t)LR * (1 - (int32_t)L)) & 31u;
+  pz.zsm = (0u - LR) & 31u;
+  pz.zsmw = (LR * (L - 1u)) & 31u;
+  // the lane's words: row masks, wrap and z sources
+  PackedWord pw[kPackedBatchWordsPerLane];
+#pragma unroll
+  for (uint32_t p = 0; p < kPackedBatchWordsPerLane; ++p) {
+    const uint32_t w = q + p * T;
+    PackedWord& x = pw[p];
+    x.valid = w < Wp;
+    const uint32_t wv = x.valid ? w : 0u;
+    x.E = x.S = x.Pm0 = x.Ymp = x.Ymm = x.Zmp = x.Zmm = 0;
+    for (uint32_t b = 0; b < 32u; ++b) {
+      const uint32_t j = 32u * wv + b;
+      const uint32_t r = j / R, jx = j - r * R;
+      const uint32_t z = r / L, y = r - z * L;
+      x.E |= (jx == R - 1 ? 1u : 0u) << b;
+      x.S |= (jx == 0 ? 1u : 0u) << b;
+      x.Pm0 |= ((y + z) & 1u) << b;
+      x.Ymp |= (y == L - 1 ? 1u : 0u) << b;
+      x.Ymm |= (y == 0 ? 1u : 0u) << b;
+      x.Zmp |= (z == L - 1 ? 1u : 0u) << b;
+      x.Zmm |= (z == 0 ? 1u : 0u) << b;
+    }
+    // Wrap and z sources: bit i of a gather at site offset off is site
+    // 32 w + i + off, from the funnel of words w + floor(off / 32) and the
+    // next; that low word is clamped to the pads (-1 .. Wp - 1) where the
+    // word has no site that uses the gather.  y wraps: rows y = L - 1 take
+    // off = R - LR, rows y = 0 off = LR - R; z (when z-planes split words):
+    // +-LR, and the wrapped LR (1 - L) / LR (L - 1) for the last / first
+    // z-plane.
+    auto lo = [&](int32_t off) -> uint32_t {  // LDS byte address of the clamped low word
+      const int32_t i = (int32_t)wv + (off >> 5);
+      return SB + 8u * (uint32_t)((i < -1 ? -1 : (i > (int32_t)Wp - 1 ? (int32_t)Wp - 1 : i)) + 1);
+    };
+    const int32_t lr = (int32_t)LR, l = (int32_t)L, rr = (int32_t)R;
+    x.ayp = lo(rr - lr);
+    x.aym = lo(lr - rr);
+    if (pz.zs == 0u) {  // z-planes hold whole words: the z neighbours are words
+      const uint32_t zw = LR / 32u;  // words per z-plane
+      const uint32_t izp = wv + zw >= Wp ? wv + zw - Wp : wv + zw;
+      const uint32_t izm = wv < zw ? wv + Wp - zw : wv - zw;
+      x.azp = SB + 8u * (izp + 1u);
+      x.azm = SB + 8u * (izm + 1u);
+      x.azpw = x.azmw = SB;
+    } else {
+      x.azp = lo(lr);
+      x.azpw = lo(lr * (1 - l));
+      x.azm = lo(-lr);
+      x.azmw = lo(lr * (l - 1));
+    }
+    x.a0 = SB + 8u * (wv + 1u);
+    x.aj = JB + 48u * wv;
+  }
+  // thresholds of this lattice: the fast decision when only classes k < d can
+  // refuse (every class k >= d always accepts)
+  bool fast = true;
+#pragma unroll
+  for (int k = D; k <= 2 * D; ++k) fast = fast && table_byte(tab.al_lo, tab.al_hi, k) == 0xFFu;
+  FastTab ft = fast_tab<D>(tab);
+  __syncthreads();
+
+  uint32_t nq = 0;
+  auto flush = [&](uint32_t c, uint32_t t) {
+    for (uint32_t e = 0; e < nq; ++e) {
+      const uint4 en = tq_ent[e * T];
+      const uint32_t w = tq_w[e * T];
+      uint32_t m = en.x, flips = 0;
+      while (m) {
+        const uint32_t b = __builtin_ctz(m);
+        m &= m - 1;
+        const uint32_t k = ((en.y >> b) & 1u) | (((en.z >> b) & 1u) << 1) | (((en.w >> b) & 1u) << 2);
+        const Rand4 rr = philox(32u * w + b, t, replica, tag(c, kIsingRefine), key.k0, key.k1);
+        if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) flips |= 1u << b;
+      }
+      *reinterpret_cast<uint32_t*>(lds + SB + 8u * (w + 1u) + 4u * c) ^= flips;
+    }
+    nq = 0;
+  };
+  auto half = [&](auto cc, uint32_t t) {
+    constexpr uint32_t C = decltype(cc)::value;
+#pragma unroll
+    for (uint32_t p = 0; p < kPackedBatchWordsPerLane; ++p) {
+      if (!pw[p].valid) continue;
+      uint32_t k0, k1, k2;
+      const uint32_t o = packed_word_counts<C, PM>(lds, pw[p], R, pz, k0, k1, k2);
+      const uint32_t w = q + p * T;
+      uint32_t ties;
+      const uint32_t flip = fast ? packed_decide_fast<D>(ft, key, t, C, w, k0, k1, k2, ties)
+                                 : packed_decide<D>(tab, key, t, C, w, k0, k1, k2, ties);
+      *reinterpret_cast<uint32_t*>(lds + pw[p].a0 + 4u * C) = o ^ flip;
+      tq_ent[nq * T] = make_uint4(ties, k0, k1, k2);
+      tq_w[nq * T] = (uint16_t)w;
+      nq += ties != 0u ? 1u : 0u;
+      if (nq == kPackedBatchTieWords) flush(C, t);
+    }
+    flush(C, t);
+    __syncthreads();
+  };
+  auto measure = [&](uint32_t slot, int64_t sweep) {
+    int64_t Esum = 0, Msum = 0;
+#pragma unroll
+    for (uint32_t p = 0; p < kPackedBatchWordsPerLane; ++p) {
+      if (!pw[p].valid) continue;
+      uint32_t k0, k1, k2;
+      const uint32_t o1 = packed_word_counts<1, PM>(lds, pw[p], R, pz, k0, k1, k2);
+      const uint32_t o0 = *reinterpret_cast<const uint32_t*>(lds + pw[p].a0);
+      const int32_t ks = __builtin_popcount(k0) + 2 * __builtin_popcount(k1) + 4 * __builtin_popcount(k2);
+      Esum += 2 * (int64_t)ks - 32 * 2 * D;
+      Msum += 64 - 2 * (int64_t)(__builtin_popcount(o1) + __builtin_popcount(o0));
+    }
+    __shared__ Partial part[1];
+    block_partial_int(Esum, Msum, part, 0);
+    if (q == 0) {
+      ObsOut o;
+      o.E_int = part[0].Ei;
+      o.M_int = part[0].Mi;
+      o.E = (double)part[0].Ei * dp->J0;
+      o.M[0] = (double)part[0].Mi;
+      o.M[1] = 0.0;
+      o.M[2] = 0.0;
+      o.absM = fabs((double)part[0].Mi);
+      o.sweep = sweep;
+      obs[(uint64_t)slot * n_lattices + li] = o;
+    }
+  };
+  for (uint32_t sw = 0; sw < n_sweeps; ++sw) {
+    const uint32_t t = t0 + sw;
+    half(std::integral_constant<uint32_t, 0>(), t);
+    half(std::integral_constant<uint32_t, 1>(), t);
+    if (MEASURE && (sw + 1) % every == 0) measure((sw + 1) / every - 1, (int64_t)t + 1);
+  }
+  if (MEASURE && n_sweeps == 0) measure(0, (int64_t)t0);
+  __syncthreads();
+  // write both planes back as +-1 bytes
+  for (uint32_t i = q; i < 2u * Wp; i += T) {
+    const uint32_t c = i & 1u, w = i >> 1;
+    const uint32_t v = *reinterpret_cast<const uint32_t*>(lds + SB + 8u * (w + 1u) + 4u * c);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(gs + (size_t)c * Nh + 32u * w);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t spread = (((v >> (4 * k)) & 0xFu) * 0x00204081u) & kOnes;
+      dst[k] = kOnes | (spread * 0xFEu);
+    }
+  }
+}
+
 
 template <int D, bool PM, bool MEASURE>
 __global__ __launch_bounds__(1024) void batch_kernel(const BatchDesc* __restrict__ descs,
@@ -67,6 +389,26 @@ __global__ __launch_bounds__(1024) void batch_kernel(const BatchDesc* __restrict
   int8_t* gs = spins + soff;
   const int8_t* gJ = J + joff;
   const uint32_t N = 2 * Nh;  // L^d, a multiple of 4 (L even)
+  if constexpr (D == 3) {
+    if (__builtin_amdgcn_readfirstlane(dp->packed) && batch_packed_ok(D, L, blockDim.x)) {
+      TabRegs tab;
+      tab.th_lo = th_lo;
+      tab.th_hi = th_hi;
+      tab.al_lo = al_lo;
+      tab.al_hi = al_hi;
+      tab.fr.f0 = __builtin_amdgcn_readfirstlane(dp->frac[0]);
+      tab.fr.f1 = __builtin_amdgcn_readfirstlane(dp->frac[1]);
+      tab.fr.f2 = __builtin_amdgcn_readfirstlane(dp->frac[2]);
+      tab.fr.f3 = __builtin_amdgcn_readfirstlane(dp->frac[3]);
+      tab.fr.f4 = __builtin_amdgcn_readfirstlane(dp->frac[4]);
+      tab.fr.f5 = __builtin_amdgcn_readfirstlane(dp->frac[5]);
+      tab.fr.f6 = __builtin_amdgcn_readfirstlane(dp->frac[6]);
+      batch_packed_lattice<PM, MEASURE>(reinterpret_cast<unsigned char*>(lat_words), dp, li, key, gs,
+                                        gJ, L, R, Nh, replica, tab, t0, n_sweeps, every,
+                                        n_lattices, obs);
+      return;
+    }
+  }
 
   // Stage both planes into LDS as one byte per site: bit 0 = spin -1, bit
   // 1 + m = coupling of bond m negative (m = +x, -x, +y, -y, +z, -z), so the
@@ -497,14 +839,31 @@ __global__ __launch_bounds__(1024) void batch_kernel(const BatchDesc* __restrict
 
 }
 
-size_t batch_lds_bytes(size_t max_sites, uint32_t threads) {
-  return (max_sites + 15) / 16 * 16 + (size_t)threads * kBatchTieSlots * 4;
+bool batch_lattice_packed(int d, uint32_t L, uint32_t threads) {
+  return batch_packed_ok(d, L, threads);
+}
+
+size_t batch_lds_bytes(int d, bool pm, bool packed, const uint32_t* L, uint32_t n,
+                       uint32_t threads) {
+  size_t bytes = 0;
+  for (uint32_t r = 0; r < n; ++r) {
+    size_t need;
+    if (packed && batch_packed_ok(d, L[r], threads)) {
+      need = batch_packed_lds_bytes(L[r], pm, threads);
+    } else {
+      size_t N = 1;
+      for (int k = 0; k < d; ++k) N *= L[r];
+      need = (N + 15) / 16 * 16 + (size_t)threads * kBatchTieSlots * 4;
+    }
+    bytes = need > bytes ? need : bytes;
+  }
+  return bytes;
 }
 
 hipError_t launch_batch(const BatchLaunch& a, int8_t* spins, const int8_t* J, uint32_t t0,
                         uint32_t n_sweeps, uint32_t every, void* dev_obs, hipStream_t st) {
   const dim3 grid(a.n_lattices), block(a.threads);
-  const size_t lds = batch_lds_bytes(a.max_sites, a.threads);
+  const size_t lds = a.lds_bytes;
 #define SMC_BK(DD, PMM, MM)                                                                      \
   hipLaunchKernelGGL((batch_kernel<DD, PMM, MM>), grid, block, lds, st, a.descs, a.order, a.key, \
                      spins, J, t0, n_sweeps, every, a.n_lattices, (ObsOut*)dev_obs)

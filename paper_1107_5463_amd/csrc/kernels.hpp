@@ -57,9 +57,14 @@ hipError_t launch_init_couplings(const Geom& g, int J_kind, RngKey key, double J
 hipError_t launch_batch(const BatchLaunch& a, int8_t* spins, const int8_t* J, uint32_t t0,
                         uint32_t n_sweeps, uint32_t every, void* dev_obs, hipStream_t st);
 hipError_t batch_allow_lds(size_t bytes);
-// Dynamic LDS of a batch launch: the largest lattice's planes plus the
-// per-lane tie queues.
-size_t batch_lds_bytes(size_t max_sites, uint32_t threads);
+// Dynamic LDS of a batch launch with `threads` lanes per workgroup: the most
+// any lattice needs -- its planes at one byte per site plus the per-lane tie
+// queues, or, on the packed path, its planes and bond signs at one bit per
+// site plus that path's tie queues.
+size_t batch_lds_bytes(int d, bool pm, bool packed, const uint32_t* L, uint32_t n,
+                       uint32_t threads);
+// Whether a lattice of edge L takes the packed (one bit per site) path.
+bool batch_lattice_packed(int d, uint32_t L, uint32_t threads);
 // The kernel a batch launch uses (for building graph nodes); its arguments are
 // (descs, order, key, spins, J, t0, n_sweeps, every, n_lattices, obs).
 const void* batch_kernel_fn(int d, bool pm, bool measure);

@@ -66,7 +66,7 @@ struct BatchDesc {
   uint32_t J_off_lo, J_off_hi;              // byte offset of its [d][2][Nh] couplings
   uint32_t frac[7];                         // refinement fractions (2^24: always)
   uint32_t al_lo, al_hi;                    // byte k = 0xFF if class k always accepts
-  uint32_t pad;
+  uint32_t packed;                          // 1: may take the packed path (one bit per site)
   double J0;
 };
 
@@ -75,7 +75,8 @@ struct BatchLaunch {
   bool pm;                 // +-1 couplings (else uniform)
   uint32_t n_lattices;
   uint32_t threads;        // workgroup size (one workgroup per lattice)
-  size_t max_sites;        // dynamic LDS bytes: the largest L^d
+  size_t max_sites;        // the largest L^d
+  size_t lds_bytes;        // dynamic LDS of a workgroup (batch_lds_bytes)
   const BatchDesc* descs;  // device
   const uint32_t* order;   // device: workgroup -> lattice
   RngKey key;              // replica is taken from each descriptor

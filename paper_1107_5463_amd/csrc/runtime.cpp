@@ -842,6 +842,8 @@ struct smc_batch {
   double J0;
   int32_t n;
   std::vector<int32_t> L;
+  std::vector<uint32_t> Lu;  // the edges as unsigned (LDS sizing)
+  bool packed;               // lattices may take the packed path (SMC_BATCH_PACKED=0 disables)
   std::vector<int64_t> soff, joff;
   std::vector<BatchDesc> desc;
   std::vector<uint32_t> orders;  // [largest first | as given]
@@ -917,6 +919,8 @@ int batch_launch(smc_batch* b, int8_t* spins, uint32_t t0, uint32_t n_sweeps, ui
   a.n_lattices = (uint32_t)b->n;
   a.threads = threads;
   a.max_sites = b->max_sites;
+  a.lds_bytes = batch_lds_bytes(b->d, b->J_kind == SMC_J_PM, b->packed, b->Lu.data(), (uint32_t)b->n,
+                                threads);
   a.descs = b->desc_dev;
   a.order = b->order_dev + (largest_first ? 0 : b->n);
   a.key = RngKey{(uint32_t)(b->seed & 0xffffffffu), (uint32_t)(b->seed >> 32), 0u};
@@ -949,7 +953,9 @@ int batch_graph_sweep(smc_batch* b, uint32_t n_sweeps, uint32_t every, void* dev
   kp.func = const_cast<void*>(batch_kernel_fn(b->d, b->J_kind == SMC_J_PM, dev_obs != nullptr));
   kp.gridDim = dim3((unsigned)b->n);
   kp.blockDim = dim3(b->threads);
-  kp.sharedMemBytes = (unsigned)batch_lds_bytes(b->max_sites, b->threads);
+  kp.sharedMemBytes =
+      (unsigned)batch_lds_bytes(b->d, b->J_kind == SMC_J_PM, b->packed, b->Lu.data(), (uint32_t)b->n,
+                                b->threads);
   kp.kernelParams = args;
   kp.extra = nullptr;
   const bool same = b->exec && b->graph_n == (int64_t)n_sweeps && b->graph_obs == dev_obs &&
@@ -1051,6 +1057,10 @@ int smc_batch_init(smc_batch** out, int32_t d, int32_t J_kind, uint64_t seed, do
   b->J0 = J0;
   b->n = n;
   b->L.assign(L, L + n);
+  b->Lu.assign(L, L + n);
+  b->packed = true;
+  if (const char* v = std::getenv("SMC_BATCH_PACKED"))
+    if (std::string(v) == "0") b->packed = false;
   size_t jb;
   batch_layout(d, n, L, b->soff, b->joff, b->spin_bytes, jb);
   b->spins = spins;
@@ -1098,6 +1108,7 @@ int smc_batch_init(smc_batch** out, int32_t d, int32_t J_kind, uint64_t seed, do
     x.J_off_lo = (uint32_t)((uint64_t)b->joff[r] & 0xffffffffu);
     x.J_off_hi = (uint32_t)((uint64_t)b->joff[r] >> 32);
     x.J0 = J0;
+    x.packed = b->packed ? 1u : 0u;
   }
   std::vector<uint32_t> idx(n);
   std::iota(idx.begin(), idx.end(), 0u);
@@ -1108,7 +1119,11 @@ int smc_batch_init(smc_batch** out, int32_t d, int32_t J_kind, uint64_t seed, do
   b->orders.insert(b->orders.end(), idx.begin(), idx.end());
   // the largest workgroup (1024 lanes) with the largest lattice may pass the
   // default 64 KiB of dynamic LDS
-  int rc = check(batch_allow_lds(batch_lds_bytes(b->max_sites, 1024)), "batch LDS attribute");
+  size_t lds_max = 0;
+  for (uint32_t th = 64; th <= 1024; th *= 2)
+    lds_max = std::max(lds_max, batch_lds_bytes(d, J_kind == SMC_J_PM, b->packed, b->Lu.data(),
+                                                (uint32_t)n, th));
+  int rc = check(batch_allow_lds(lds_max), "batch LDS attribute");
   if (rc == SMC_OK)
     rc = check(hipMemcpyAsync(b->desc_dev, b->desc.data(), sizeof(BatchDesc) * n,
                               hipMemcpyHostToDevice, b->stream), "descriptor upload");
@@ -1204,6 +1219,28 @@ int smc_batch_autotune(smc_batch* b, int32_t* threads_out, int32_t* largest_firs
   if (threads_out) *threads_out = (int32_t)best_threads;
   if (largest_first_out) *largest_first_out = best_largest ? 1 : 0;
   return SMC_OK;
+}
+
+int smc_batch_set_schedule(smc_batch* b, int32_t threads, int32_t largest_first) {
+  if (!b) return fail(SMC_EINVAL, "handle is NULL");
+  if (threads < 64 || threads > 1024 || threads % 64)
+    return fail(SMC_EINVAL, "threads must be a multiple of 64 in [64, 1024]");
+  b->threads = (uint32_t)threads;
+  b->largest_first = largest_first != 0;
+  return SMC_OK;
+}
+
+int smc_batch_get_schedule(const smc_batch* b, int32_t* threads, int32_t* largest_first) {
+  if (!b) return fail(SMC_EINVAL, "handle is NULL");
+  if (threads) *threads = (int32_t)b->threads;
+  if (largest_first) *largest_first = b->largest_first ? 1 : 0;
+  return SMC_OK;
+}
+
+int smc_batch_lattice_packed(const smc_batch* b, int32_t r) {
+  if (!b) return fail(SMC_EINVAL, "handle is NULL");
+  if (r < 0 || r >= b->n) return fail(SMC_EINVAL, "lattice index out of range");
+  return b->packed && batch_lattice_packed(b->d, (uint32_t)b->L[r], b->threads) ? 1 : 0;
 }
 
 int smc_batch_use_graph(smc_batch* b, int32_t enable) {

@@ -186,3 +186,60 @@ def test_batch_lds_limit_survives_a_smaller_batch(smc_gpu, oracle_mod):
     small.sweep(2)
     big.sweep(2)
     _check(smc_gpu, oracle_mod, big, 2, [256, 8], [0.45, 0.7], 1, 2, 31)
+
+
+def _c3_like(n):
+    L = [[8, 12, 16, 24, 32][r % 5] for r in range(n)]
+    beta = [0.5 + 2.5 * (r % 32) / 31 for r in range(n)]
+    return L, beta
+
+
+@pytest.mark.parametrize("threads", [64, 256, 1024])
+def test_packed_and_byte_paths_run_the_same_chains(smc_gpu, monkeypatch, threads):
+    """The spin-glass workload's mix (3D +-J, L in {8, 12, 16, 24, 32}, 32
+    temperatures): lattices take the packed path where a lane holds at most
+    two 32-site words of a colour (z-planes of whole words for L % 8 == 0,
+    split words for L = 12), else the byte path; with the packed path
+    switched off every lattice takes the byte path.  Final states and the E/M
+    series inside the launch are equal."""
+    import torch
+    n = 45
+    L, beta = _c3_like(n)
+    out = {}
+    for packed in (True, False):
+        if packed:
+            monkeypatch.delenv("SMC_BATCH_PACKED", raising=False)
+        else:
+            monkeypatch.setenv("SMC_BATCH_PACKED", "0")
+        b = smc_gpu.Batch(3, L, beta, seed=61)
+        b.threads = threads
+        obs = torch.zeros((5, n, 8), dtype=torch.int64, device=b.device)
+        b.sweep(25, obs, every=5)
+        want = [(Lr % 4 == 0 and (Lr ** 3 // 64) <= 2 * threads) if packed else False for Lr in L]
+        assert [b.packed(r) for r in range(n)] == want
+        out[packed] = (b.spins.clone(), obs.clone())
+    assert torch.equal(out[True][0], out[False][0])
+    assert torch.equal(out[True][1], out[False][1])
+
+
+@pytest.mark.parametrize("J0,betas", [(1.0, [0.0, float("inf"), 0.7, 2.9]),
+                                      (-1.0, [0.3, 1.1, 2.2, float("inf")])])
+def test_packed_batch_matches_oracle(smc_gpu, oracle_mod, J0, betas):
+    """The packed path against the oracle, lattice by lattice, at the special
+    temperatures and with J0 < 0 (classes with more than d unsatisfied bonds
+    refusable: the general bit-sliced decision)."""
+    import torch
+    L = [8, 16, 24, 32, 4, 12, 20, 28]
+    beta = [betas[r % len(betas)] for r in range(len(L))]
+    b = smc_gpu.Batch(3, L, beta, seed=71, J0=J0)
+    assert all(b.packed(r) for r in range(len(L)))
+    obs = torch.zeros((len(L), 8), dtype=torch.int64, device=b.device)
+    b.sweep(6, obs)
+    recs = smc_gpu.Lattice.decode_obs(obs)
+    for r in range(len(L)):
+        ref = oracle_mod.OracleLattice(3, 1, L[r], 71, J_kind=1, J0=J0, replica=r)
+        ref.sweep(beta[r], 6)
+        got = layout.to_natural(b.spins_of(r).cpu().numpy(), 3, L[r])
+        assert np.array_equal(got, ref.s), (r, L[r], beta[r])
+        o = ref.measure()
+        assert (recs[r].E_int, recs[r].M_int) == (o.E_int, o.M_int), r
