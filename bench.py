@@ -66,11 +66,12 @@ WORKLOADS = {
 KERNEL_SOURCES = {
     "ising_stream": ["ising.hip", "chunk.hpp", "device.hpp", "launch_args.hpp", "reduce.hpp"],
     "ising_fused": ["fused.hip", "chunk.hpp", "device.hpp", "launch_args.hpp", "reduce.hpp"],
-    "ising_packed": ["packed.hip", "chunk.hpp", "device.hpp", "launch_args.hpp", "reduce.hpp"],
+    "ising_packed": ["packed.hip", "packed.hpp", "chunk.hpp", "device.hpp", "launch_args.hpp",
+                     "reduce.hpp"],
     "ising_tiles": ["tiles.hip", "chunk.hpp", "device.hpp", "launch_args.hpp"],
     "xy_stream": ["continuous.hip", "chunk.hpp", "device.hpp", "launch_args.hpp"],
     "heisenberg_stream": ["continuous.hip", "chunk.hpp", "device.hpp", "launch_args.hpp"],
-    "batch": ["batch.hip", "chunk.hpp", "device.hpp", "launch_args.hpp", "reduce.hpp"],
+    "batch": ["batch.hip", "packed.hpp", "chunk.hpp", "device.hpp", "launch_args.hpp", "reduce.hpp"],
     "chains": ["chains.hip", "chunk.hpp", "device.hpp", "launch_args.hpp"],
     "probe": ["probe.hip", "device.hpp"],
 }
@@ -107,6 +108,9 @@ def parse():
     ap.add_argument("--no-extra", action="store_true",
                     help="default 2D line: skip the 3D Ising, XY, Heisenberg and chains objects "
                          "attached to it")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default band heights (the default run times every band "
+                         "height of the lattice's kernel first and keeps the fastest)")
     ap.add_argument("--probes", action="store_true",
                     help="measure the ceilings instead of a workload: device copies of 32 MiB, "
                          "256 MiB and 1 GiB, Philox4x32-10 blocks alone, and the integer VALU "
@@ -305,6 +309,9 @@ def run_lattice(args, wl, torch, smc):
         kw = dict(packed=packed, heatbath=args.heatbath, tile=args.tile,
                   hits=args.hits if args.tile else 0)
     lat = smc.Lattice(d, n, L, seed=wl["seed"], fused=fused, **kw)
+    default_rows = lat.kernel()[1]
+    if not args.no_autotune:
+        lat.autotune(wl["beta"])
     if args.copy_probe:
         copy_probe(torch, lat.device)
     K = args.steps if args.steps is not None else 100
@@ -352,6 +359,7 @@ def run_lattice(args, wl, torch, smc):
                         + (f", delta={wl['delta']}, renormalise every {wl['renorm']}" if n > 1 else ""),
             "d": d, "n": n, "L": L, "sweeps": sweeps, "measure_every": S,
             "schedule": schedule, "kernel": kname, "rows_per_band": band_rows,
+            "rows_autotuned": not args.no_autotune, "rows_default": default_rows,
         },
         "roofline": roof,
         "pct_hbm_peak": round(100 * bytes_per_launch / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 2),
@@ -366,6 +374,8 @@ def run_lattice(args, wl, torch, smc):
     if packed and not args.no_int8_line:
         # the same chain with int8 spins: the HBM-bound two-pass schedule
         lat8 = smc.Lattice(d, n, L, seed=wl["seed"])
+        if not args.no_autotune:
+            lat8.autotune(beta)
         ms8, _, obs8 = timed_steps(lat8, beta, K, W, S, torch)
         k8, rows8 = lat8.kernel()
         l8, b8, sch8 = kernel_model(k8, n, N, sweeps, 0, 1)
@@ -749,6 +759,7 @@ def attach_other_workloads(args, result, torch, smc):
         o = {k: r[k] for k in keep}
         o["workload"] = r["config"]["workload"]
         o["kernel"], o["rows_per_band"] = r["config"]["kernel"], r["config"]["rows_per_band"]
+        o["rows_autotuned"] = r["config"]["rows_autotuned"]
         if "int8_two_pass" in r:
             o["int8_two_pass"] = r["int8_two_pass"]
         result[name] = o

@@ -214,6 +214,23 @@ int smc_get_sweep_index(const smc_lattice* h, uint64_t* t);
 int smc_set_sweep_index(smc_lattice* h, uint64_t t);
 int smc_set_samples(smc_lattice* h, int64_t samples);
 
+/*
+ * Pick the band height of the handle's banded kernel (int8 or packed Ising
+ * streaming kernels, the continuous streaming kernel, the fused schedule):
+ * every height the kernel takes (powers of two dividing L) is timed over a
+ * few sweeps at inverse temperature beta on the handle's own spin buffer
+ * (where placement in memory decides much of the speed), whose state is kept
+ * in `scratch` -- a caller-owned device buffer of at least smc_spin_bytes(p)
+ * bytes, 16-byte aligned -- and copied back, so the state and the sweep
+ * counter are left as they were; the fastest height is kept.  Every height gives the same chain.  With
+ * SMC_AUTOTUNE_CACHE naming a file, a choice stored there for the same
+ * kernel, shape and device is taken without timing (scratch may then be
+ * NULL), and new choices are added to it.  rows_out (optional) receives the
+ * chosen height, 0 if the handle's kernel has no bands.  Synchronises.
+ */
+int smc_autotune(smc_lattice* h, double beta, void* scratch, size_t scratch_bytes,
+                 uint32_t* rows_out);
+
 /* Name of the kernel the handle's sweeps launch ("ising_fused",
  * "ising_stream", "ising_chunk", "ising_site", "xy_site", "heisenberg_site")
  * and, for the banded Ising kernels, the rows each lane walks (0 otherwise). */
@@ -265,9 +282,13 @@ int smc_batch_sweep(smc_batch* b, int64_t n_sweeps, void* dev_obs);
  * EINVAL on a bad measure_every or a misaligned dev_obs. */
 int smc_batch_sweep_series(smc_batch* b, int64_t n_sweeps, int64_t measure_every, void* dev_obs);
 
-/* Time the workgroup sizes 64..1024 and the lattice orders (largest first,
- * as given) on a scratch copy of the spins and keep the fastest.  Results do
- * not depend on the choice.  Synchronises the stream. */
+/* Time the workgroup sizes 64..1024, the lattice orders (largest first, as
+ * given) and the paths (one bit per site where a lattice takes it, or one
+ * byte per site throughout) on a scratch copy of the spins and keep the
+ * fastest.  Results do not depend on the choice.  With SMC_AUTOTUNE_CACHE
+ * naming a file, a choice stored there for the same batch shape and device
+ * is taken without timing, and new choices are added to it.  Synchronises
+ * the stream. */
 int smc_batch_autotune(smc_batch* b, int32_t* threads_out, int32_t* largest_first_out);
 
 /* The launch schedule: lanes per workgroup (one workgroup per lattice; a

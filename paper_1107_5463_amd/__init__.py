@@ -43,7 +43,7 @@ EXPORTS = ["smc_spin_bytes", "smc_coupling_bytes", "smc_workspace_bytes", "smc_b
            "smc_measure",
            "smc_measure_async", "smc_measure_noalloc", "smc_bond_correlations", "smc_get_samples", "smc_set_samples",
            "smc_renormalize", "smc_validate", "smc_get_sweep_index", "smc_set_sweep_index",
-           "smc_kernel_name", "smc_destroy", "smc_last_error", "smc_version",
+           "smc_kernel_name", "smc_autotune", "smc_destroy", "smc_last_error", "smc_version",
            "smc_batch_spin_bytes", "smc_batch_coupling_bytes", "smc_batch_workspace_bytes",
            "smc_batch_offsets", "smc_batch_init", "smc_batch_sweep", "smc_batch_sweep_series",
            "smc_batch_autotune", "smc_batch_lattice_packed", "smc_batch_set_schedule",
@@ -125,6 +125,7 @@ def load_library():
     lib.smc_validate.argtypes = [vp]
     lib.smc_get_sweep_index.argtypes = [vp, C.POINTER(C.c_uint64)]
     lib.smc_set_sweep_index.argtypes = [vp, C.c_uint64]
+    lib.smc_autotune.argtypes = [vp, C.c_double, vp, sz, C.POINTER(C.c_uint32)]
     lib.smc_kernel_name.argtypes = [vp, C.POINTER(C.c_uint32)]
     lib.smc_kernel_name.restype = C.c_char_p
     lib.smc_destroy.argtypes = [vp]
@@ -303,6 +304,16 @@ class Lattice:
         rows = C.c_uint32()
         name = self._lib().smc_kernel_name(self._h, C.byref(rows)).decode()
         return name, int(rows.value)
+
+    def autotune(self, beta: float) -> int:
+        """Time the band heights of this lattice's kernel on a scratch copy of
+        the spins and keep the fastest (smc_autotune); returns the height (0:
+        the kernel has no bands).  The state is left as it was."""
+        scratch = self.torch.empty_like(self.spins)
+        rows = C.c_uint32()
+        _check(self._lib().smc_autotune(self._h, float(beta), C.c_void_p(scratch.data_ptr()),
+                                        scratch.numel() * scratch.element_size(), C.byref(rows)))
+        return int(rows.value)
 
     def set_stream(self, stream):
         self.stream = stream

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
@@ -462,9 +463,187 @@ int sweeps_impl(smc_lattice* h, double beta, int64_t n_sweeps, void* dev_obs) {
   return SMC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuning of schedules, with a cache of the choices in the file named by
+// SMC_AUTOTUNE_CACHE (lines "key value"; the key names the kernel, the shape
+// and the device).
+// ---------------------------------------------------------------------------
+std::mutex g_cache_mu;
+
+std::string device_tag() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return "dev?";
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "dev?";
+  return std::string(prop.gcnArchName) + ",cu" + std::to_string(prop.multiProcessorCount);
+}
+
+std::map<std::string, std::string> cache_read(const char* path) {
+  std::map<std::string, std::string> m;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return m;
+  char line[1024];
+  while (std::fgets(line, sizeof(line), f)) {
+    std::string l(line);
+    while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+    const size_t sp = l.find(' ');
+    if (sp == std::string::npos || sp == 0) continue;
+    m[l.substr(0, sp)] = l.substr(sp + 1);
+  }
+  std::fclose(f);
+  return m;
+}
+
+bool cache_get(const std::string& key, std::string& value) {
+  const char* path = std::getenv("SMC_AUTOTUNE_CACHE");
+  if (!path || !*path) return false;
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  const auto m = cache_read(path);
+  const auto it = m.find(key);
+  if (it == m.end()) return false;
+  value = it->second;
+  return true;
+}
+
+void cache_put(const std::string& key, const std::string& value) {
+  const char* path = std::getenv("SMC_AUTOTUNE_CACHE");
+  if (!path || !*path) return;
+  std::lock_guard<std::mutex> lock(g_cache_mu);
+  auto m = cache_read(path);
+  m[key] = value;
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return;
+  for (const auto& kv : m) std::fprintf(f, "%s %s\n", kv.first.c_str(), kv.second.c_str());
+  std::fclose(f);
+  std::rename(tmp.c_str(), path);
+}
+
+// The band height field of the handle's banded kernel and its candidates
+// (powers of two dividing L that the kernel takes); nullptr if the handle's
+// sweeps run a kernel without bands.
+uint32_t* band_field(smc_lattice* h, std::vector<uint32_t>& cand, const char** what) {
+  cand.clear();
+  const Geom& g = h->g;
+  auto pow2 = [&](uint32_t lo, uint32_t hi, auto ok) {
+    for (uint32_t H = lo; H <= hi; H *= 2)
+      if ((uint32_t)g.L % H == 0 && ok(H)) cand.push_back(H);
+  };
+  if (h->p.tile > 0) return nullptr;
+  if (h->use_fused) {
+    *what = "fused";
+    pow2(4, 64, [&](uint32_t H) { return ising_fused_supported(g, h->p.J_kind, H); });
+    return &h->fused_rows;
+  }
+  if (is_packed(&h->p)) {
+    *what = "packed";
+    pow2(1, 64, [](uint32_t) { return true; });
+    return &h->packed_rows;
+  }
+  if (h->p.n > 1) {
+    ContLaunch a = cont_args(h, 0.0);
+    if (cont_variant_used(a) != kContStream) return nullptr;
+    *what = h->p.n == 2 ? "xy_stream" : "heisenberg_stream";
+    pow2(4, 64, [&](uint32_t H) { return cont_stream_supported(g, h->p.n, H); });
+    return &h->cont_rows;
+  }
+  IsingLaunch a = ising_args(h, 0.0);
+  if (ising_variant_used(a) != kVariantStream) return nullptr;
+  *what = "ising_stream";
+  pow2(4, 64, [&](uint32_t H) {
+    a.rows_per_band = H;
+    return ising_variant_used(a) == kVariantStream;
+  });
+  return &h->rows_per_band;
+}
+
 }  // namespace
 
 extern "C" {
+
+int smc_autotune(smc_lattice* h, double beta, void* scratch, size_t scratch_bytes,
+                 uint32_t* rows_out) {
+  if (!h) return fail(SMC_EINVAL, "handle is NULL");
+  if (!beta_ok(beta) || std::isinf(beta)) return fail(SMC_EINVAL, "beta must be finite and >= 0");
+  std::vector<uint32_t> cand;
+  const char* what = "";
+  uint32_t* field = band_field(h, cand, &what);
+  if (!field || cand.empty()) {
+    if (rows_out) *rows_out = 0;
+    return SMC_OK;
+  }
+  const std::string key = std::string(what) + ":d" + std::to_string(h->p.d) + ":n" +
+                          std::to_string(h->p.n) + ":L" + std::to_string(h->p.L) + ":J" +
+                          std::to_string(h->p.J_kind) + ":" + device_tag();
+  std::string cached;
+  if (cache_get(key, cached)) {
+    const uint32_t v = (uint32_t)std::strtoul(cached.c_str(), nullptr, 10);
+    if (std::find(cand.begin(), cand.end(), v) != cand.end()) {
+      *field = v;
+      if (rows_out) *rows_out = v;
+      return SMC_OK;
+    }
+  }
+  const size_t sb = spin_bytes(&h->p);
+  if (!scratch || ((uintptr_t)scratch & 15) || scratch_bytes < sb)
+    return fail(SMC_EINVAL, "scratch must be 16-byte aligned and hold " + std::to_string(sb) +
+                                " bytes (a copy of the spins)");
+  int rc = check(hipMemcpyAsync(scratch, h->spins, sb, hipMemcpyDeviceToDevice, h->stream),
+                 "scratch copy");
+  if (rc != SMC_OK) return rc;
+  hipEvent_t e0, e1;
+  if ((rc = check(hipEventCreate(&e0), "event create")) != SMC_OK) return rc;
+  if ((rc = check(hipEventCreate(&e1), "event create")) != SMC_OK) {
+    (void)hipEventDestroy(e0);
+    return rc;
+  }
+  // sweeps of the handle's own buffer (its placement in memory and in the
+  // Infinity Cache is what the timed sweeps will see), restored from the
+  // scratch copy afterwards; enough of them for about 10^9 attempts per timing
+  const uint64_t t_saved = h->t;
+  const uint32_t saved_rows = *field;
+  const double N = (double)n_sites(&h->p);
+  const int64_t K = std::max<int64_t>(2, std::min<int64_t>(64, (int64_t)std::ceil(1e9 / N)));
+  const char* vb = std::getenv("SMC_AUTOTUNE_VERBOSE");
+  const bool verbose = vb && *vb && *vb != '0';
+  float best = 1e30f;
+  uint32_t best_H = saved_rows;
+  for (size_t i = 0; i < cand.size() && rc == SMC_OK; ++i) {
+    *field = cand[i];
+    rc = sweeps_impl(h, beta, 1, nullptr);
+    for (int rep = 0; rep < 2 && rc == SMC_OK; ++rep) {
+      rc = check(hipEventRecord(e0, h->stream), "event record");
+      if (rc == SMC_OK) rc = sweeps_impl(h, beta, K, nullptr);
+      if (rc == SMC_OK) rc = check(hipEventRecord(e1, h->stream), "event record");
+      if (rc == SMC_OK) rc = check(hipEventSynchronize(e1), "event synchronise");
+      float ms = 0.0f;
+      if (rc == SMC_OK) rc = check(hipEventElapsedTime(&ms, e0, e1), "event time");
+      if (rc == SMC_OK && verbose)
+        std::fprintf(stderr, "smc_autotune %s: rows %u, %lld sweeps, %.3f ms\n", what, cand[i],
+                     (long long)K, ms);
+      if (rc == SMC_OK && ms < best) {
+        best = ms;
+        best_H = cand[i];
+      }
+    }
+    h->t = t_saved;
+  }
+  h->t = t_saved;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  const int rc_restore = check(hipMemcpyAsync(h->spins, scratch, sb, hipMemcpyDeviceToDevice,
+                                              h->stream), "state restore");
+  if (rc == SMC_OK) rc = rc_restore;
+  if (rc == SMC_OK) rc = check(hipStreamSynchronize(h->stream), "stream synchronise");
+  if (rc != SMC_OK) {
+    *field = saved_rows;
+    return rc;
+  }
+  *field = best_H;
+  cache_put(key, std::to_string(best_H));
+  if (rows_out) *rows_out = best_H;
+  return SMC_OK;
+}
 
 size_t smc_spin_bytes(const smc_params* p) {
   std::string why;
@@ -1178,8 +1357,40 @@ int smc_batch_sweep(smc_batch* b, int64_t n_sweeps, void* dev_obs) {
   return smc_batch_sweep_series(b, n_sweeps, n_sweeps > 0 ? n_sweeps : 1, dev_obs);
 }
 
+// Upload the descriptor table with every lattice's packed-path flag set to
+// b->packed.
+static int batch_upload_desc(smc_batch* b) {
+  for (auto& x : b->desc) x.packed = b->packed ? 1u : 0u;
+  return check(hipMemcpyAsync(b->desc_dev, b->desc.data(), sizeof(BatchDesc) * b->desc.size(),
+                              hipMemcpyHostToDevice, b->stream), "descriptor upload");
+}
+
 int smc_batch_autotune(smc_batch* b, int32_t* threads_out, int32_t* largest_first_out) {
   if (!b) return fail(SMC_EINVAL, "handle is NULL");
+  // the cache key: shape of the batch (edges in order) and the device
+  uint64_t hsh = 1469598103934665603ull;
+  for (int32_t r = 0; r < b->n; ++r) hsh = (hsh ^ (uint64_t)b->L[r]) * 1099511628211ull;
+  char hx[24];
+  std::snprintf(hx, sizeof(hx), "%016llx", (unsigned long long)hsh);
+  const std::string key = "batch:d" + std::to_string(b->d) + ":J" + std::to_string(b->J_kind) +
+                          ":n" + std::to_string(b->n) + ":L" + hx + ":" + device_tag();
+  const bool packed_allowed = b->packed;
+  std::string cached;
+  if (cache_get(key, cached)) {
+    unsigned th = 0;
+    int lf = 0, pk = 0;
+    if (std::sscanf(cached.c_str(), "%u,%d,%d", &th, &lf, &pk) == 3 && th >= 64 && th <= 1024 &&
+        th % 64 == 0) {
+      b->threads = th;
+      b->largest_first = lf != 0;
+      b->packed = packed_allowed && pk != 0;
+      const int rc = batch_upload_desc(b);
+      if (rc != SMC_OK) return rc;
+      if (threads_out) *threads_out = (int32_t)th;
+      if (largest_first_out) *largest_first_out = lf != 0 ? 1 : 0;
+      return SMC_OK;
+    }
+  }
   int rc = check(hipMemcpyAsync(b->scratch, b->spins, b->spin_bytes, hipMemcpyDeviceToDevice,
                                 b->stream), "scratch copy");
   if (rc != SMC_OK) return rc;
@@ -1192,30 +1403,45 @@ int smc_batch_autotune(smc_batch* b, int32_t* threads_out, int32_t* largest_firs
   float best = 1e30f;
   uint32_t best_threads = b->threads;
   bool best_largest = b->largest_first;
+  bool best_packed = b->packed;
   const uint32_t cand[5] = {64, 128, 256, 512, 1024};
-  for (int lf = 1; lf >= 0 && rc == SMC_OK; --lf) {
-    for (int c = 0; c < 5 && rc == SMC_OK; ++c) {
-      // the chain on the scratch copy is discarded: any counter will do
-      rc = batch_launch(b, (int8_t*)b->scratch, (uint32_t)b->t, 1, 1, nullptr, cand[c], lf != 0);
-      if (rc != SMC_OK) break;
-      rc = check(hipEventRecord(e0, b->stream), "event record");
-      if (rc == SMC_OK) rc = batch_launch(b, (int8_t*)b->scratch, (uint32_t)b->t, 4, 1, nullptr, cand[c], lf != 0);
-      if (rc == SMC_OK) rc = check(hipEventRecord(e1, b->stream), "event record");
-      if (rc == SMC_OK) rc = check(hipEventSynchronize(e1), "event synchronise");
-      float ms = 0.0f;
-      if (rc == SMC_OK) rc = check(hipEventElapsedTime(&ms, e0, e1), "event time");
-      if (rc == SMC_OK && ms < best) {
-        best = ms;
-        best_threads = cand[c];
-        best_largest = lf != 0;
+  // workgroup size x lattice order x path (one bit per site where a lattice
+  // allows it, or one byte per site throughout)
+  for (int pk = packed_allowed ? 1 : 0; pk >= 0 && rc == SMC_OK; --pk) {
+    b->packed = pk != 0;
+    rc = batch_upload_desc(b);
+    for (int lf = 1; lf >= 0 && rc == SMC_OK; --lf) {
+      for (int c = 0; c < 5 && rc == SMC_OK; ++c) {
+        // the chain on the scratch copy is discarded: any counter will do
+        rc = batch_launch(b, (int8_t*)b->scratch, (uint32_t)b->t, 1, 1, nullptr, cand[c], lf != 0);
+        if (rc != SMC_OK) break;
+        for (int rep = 0; rep < 2 && rc == SMC_OK; ++rep) {
+          rc = check(hipEventRecord(e0, b->stream), "event record");
+          if (rc == SMC_OK)
+            rc = batch_launch(b, (int8_t*)b->scratch, (uint32_t)b->t, 8, 1, nullptr, cand[c], lf != 0);
+          if (rc == SMC_OK) rc = check(hipEventRecord(e1, b->stream), "event record");
+          if (rc == SMC_OK) rc = check(hipEventSynchronize(e1), "event synchronise");
+          float ms = 0.0f;
+          if (rc == SMC_OK) rc = check(hipEventElapsedTime(&ms, e0, e1), "event time");
+          if (rc == SMC_OK && ms < best) {
+            best = ms;
+            best_threads = cand[c];
+            best_largest = lf != 0;
+            best_packed = pk != 0;
+          }
+        }
       }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  b->packed = best_packed;
+  if (rc == SMC_OK) rc = batch_upload_desc(b);
   if (rc != SMC_OK) return rc;
   b->threads = best_threads;
   b->largest_first = best_largest;
+  cache_put(key, std::to_string(best_threads) + "," + (best_largest ? "1" : "0") + "," +
+                     (best_packed ? "1" : "0"));
   if (threads_out) *threads_out = (int32_t)best_threads;
   if (largest_first_out) *largest_first_out = best_largest ? 1 : 0;
   return SMC_OK;
