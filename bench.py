@@ -260,11 +260,14 @@ def hbm_roofline(kname, workload, bytes_per_launch, kernel_ms):
     }
 
 
-def valu_roofline(kname, workload, kernel_ms, bytes_per_launch, variant=None):
+def valu_roofline(kname, workload, kernel_ms, bytes_per_launch, attempts_per_launch,
+                  variant=None):
     """VALU-bound kernels: issued 32-bit lane operations per second from the
     committed VALU instruction count per launch (rocprofv3 SQ_INSTS_VALU x 64
     lanes), valid only for the kernel sources and the variant (schedule, rule)
-    it was taken on."""
+    it was taken on.  A count taken on launches of another length (sweeps per
+    launch) is scaled by the attempts per launch; `counted_attempts_per_launch`
+    then differs from `attempts_per_launch`."""
     rec = None
     path = os.path.join(ROOT, "profiles", f"{kname}_{workload}_valu.json")
     if os.path.exists(path):
@@ -276,7 +279,8 @@ def valu_roofline(kname, workload, kernel_ms, bytes_per_launch, variant=None):
                 rec = r
     achieved = None
     if rec is not None:
-        achieved = rec["valu_lane_ops_per_launch"] / (kernel_ms * 1e-3) / 1e12
+        lane_ops = rec["valu_lane_ops_per_launch"] * attempts_per_launch / rec["attempts_per_launch"]
+        achieved = lane_ops / (kernel_ms * 1e-3) / 1e12
     probe = measured_probe("valu_issue")
     return {
         "bound": "alu",
@@ -289,6 +293,8 @@ def valu_roofline(kname, workload, kernel_ms, bytes_per_launch, variant=None):
         "probe_ceiling": probe,
         "frac_probe": None if (achieved is None or not probe) else round(achieved / probe, 4),
         "lane_ops_per_attempt": None if rec is None else rec.get("lane_ops_per_attempt"),
+        "attempts_per_launch": int(attempts_per_launch),
+        "counted_attempts_per_launch": None if rec is None else rec["attempts_per_launch"],
         "traffic": measured_traffic(kname, workload),
         "kernel": kname,
         "kernel_avg_us": round(kernel_ms * 1e3, 3),
@@ -331,7 +337,8 @@ def run_lattice(args, wl, torch, smc):
         variant = None
         if kname == "ising_tiles":
             variant = f"T={args.tile} k={args.hits} {'heat bath' if args.heatbath else 'Metropolis'}"
-        roof = valu_roofline(kname, args.workload, kernel_ms, bytes_per_launch, variant)
+        roof = valu_roofline(kname, args.workload, kernel_ms, bytes_per_launch,
+                             attempts / launches, variant)
     else:
         roof = hbm_roofline(kname, args.workload, bytes_per_launch, kernel_ms)
     what = {1: "Ising", 2: "XY", 3: "Heisenberg"}[n]
@@ -521,7 +528,8 @@ def run_batched(args, wl, torch, smc):
         "batched_vs_plain": round(value / plain_value, 1),
         # spins and couplings cross HBM once per launch (staged in LDS for all
         # sweeps): VALU-bound
-        "roofline": valu_roofline("batch", "batched", total_ms / max(K, 1), 2 * cbytes),
+        "roofline": valu_roofline("batch", "batched", total_ms / max(K, 1), 2 * cbytes,
+                                  sites * S),
         "wall_s": round(wall, 3),
     }
     if args.cpu_seconds > 0:
@@ -626,7 +634,8 @@ def run_chains(args, wl, torch, smc):
                      "ms": round(bwd_ms, 3)},
         # each launch (S sweeps) reads and writes every chain's spins once and
         # stages the shared couplings from L2: VALU / LDS-bound
-        "roofline": valu_roofline("chains", "chains", fwd_ms / max(K, 1), 2 * nch * N),
+        "roofline": valu_roofline("chains", "chains", fwd_ms / max(K, 1), 2 * nch * N,
+                                  nch * N * S),
     }
     if args.cpu_seconds > 0:
         sys.path.insert(0, ROOT)
