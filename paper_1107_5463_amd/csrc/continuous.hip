@@ -16,9 +16,22 @@
 
 namespace smc {
 
+// Metropolis acceptance of a continuous-spin move (Eq. (2)): dE <= 0, or
+// u_acc < exp(-beta dE).  The accurate path takes exp(-beta dE) as
+// 2^(-b dE) with b = beta log2(e) rounded once from FP64 (`beta_log2e`) and
+// the hardware base-2 exponential: the argument carries two FP32 roundings
+// (relative 2^-23) and the exponential about one ulp, so p is off by less
+// than p (x ln2 2^-23 + 2^-23) <= 2e-7 -- below the FP32 rounding of dE
+// itself for the fields of these models.  Both sides are evaluated and or-ed,
+// with no branch.
 template <bool FAST>
-__device__ __forceinline__ float exp_f(float x) {
-  return FAST ? __expf(x) : expf(x);
+__device__ __forceinline__ bool cont_accept(float dE, uint32_t wacc, float beta, float bl2e) {
+  const float p = FAST ? __expf(-beta * dE) : __builtin_amdgcn_exp2f(-bl2e * dE);
+  return (dE <= 0.0f) | (u01f(wacc) < p);
+}
+
+__device__ __forceinline__ float beta_log2e(float beta) {
+  return (float)((double)beta * 1.44269504088896340736);
 }
 template <bool FAST>
 __device__ __forceinline__ void sincos_f(float x, float* s, float* c) {
@@ -134,7 +147,8 @@ __device__ __forceinline__ void row_block(uint32_t segs, uint32_t& r, uint32_t& 
 template <bool FAST>
 __device__ __forceinline__ bool xy_update(float& s0, float& s1, const float h[3],
                                           const uint32_t wacc, const uint32_t wprop,
-                                          const float beta, const float delta) {
+                                          const float beta, const float bl2e,
+                                          const float delta) {
   // rotation angle delta (2u - 1): in radians for the hardware sin / cos of
   // the fast path, in turns for the series otherwise
   float sD, cD;
@@ -145,7 +159,7 @@ __device__ __forceinline__ bool xy_update(float& s0, float& s1, const float h[3]
   const float n0 = s0 * cD - s1 * sD;
   const float n1 = s1 * cD + s0 * sD;
   const float dE = -((n0 - s0) * h[0] + (n1 - s1) * h[1]);
-  const bool accept = dE <= 0.0f || u01f(wacc) < exp_f<FAST>(-beta * dE);
+  const bool accept = cont_accept<FAST>(dE, wacc, beta, bl2e);
   if (accept) {
     s0 = n0;
     s1 = n1;
@@ -159,12 +173,15 @@ __device__ __forceinline__ bool xy_update(float& s0, float& s1, const float h[3]
 template <bool FAST>
 __device__ __forceinline__ bool heis_update(float sv[3], const float h[3], const uint32_t w0,
                                             const uint32_t w1, const uint32_t w2,
-                                            const float beta, const float omc) {
+                                            const float beta, const float bl2e,
+                                            const float omc) {
   // sin alpha from 1 - cos alpha directly: (1 - c)(1 + c) keeps its relative
-  // precision for small caps, where 1 - c^2 would cancel
+  // precision for small caps, where 1 - c^2 would cancel.  The argument is at
+  // least omc 2^-24 (a normal number), so the hardware square root (about one
+  // ulp) needs no denormal scaling.
   const float omca = u01f(w1) * omc;
   const float ca = 1.0f - omca;
-  const float sa = sqrtf(omca * (2.0f - omca));
+  const float sa = __builtin_amdgcn_sqrtf(omca * (2.0f - omca));
   // frame axis: smallest |s_k|, lowest k on ties
   const float a0 = fabsf(sv[0]), a1 = fabsf(sv[1]), a2 = fabsf(sv[2]);
   int k = 0;
@@ -190,7 +207,7 @@ __device__ __forceinline__ bool heis_update(float sv[3], const float h[3], const
 #pragma unroll
   for (int q = 0; q < 3; ++q) nv[q] = ca * sv[q] + sa * (cph * e1[q] + sph * e2[q]);
   const float dE = -((nv[0] - sv[0]) * h[0] + (nv[1] - sv[1]) * h[1] + (nv[2] - sv[2]) * h[2]);
-  const bool accept = dE <= 0.0f || u01f(w0) < exp_f<FAST>(-beta * dE);
+  const bool accept = cont_accept<FAST>(dE, w0, beta, bl2e);
   if (accept) {
     sv[0] = nv[0];
     sv[1] = nv[1];
@@ -226,7 +243,7 @@ __global__ __launch_bounds__(256) void xy_kernel(const Geom g, const RngKey key,
     float s0 = own[st.j], s1 = own[Nfull + st.j];
     const bool odd = PAIRED ? half == 1 : (st.j & 1) != 0;
     if (xy_update<FAST>(s0, s1, h, odd ? rnd.w[2] : rnd.w[0], odd ? rnd.w[3] : rnd.w[1], beta,
-                        delta)) {
+                        beta_log2e(beta), delta)) {
       own[st.j] = s0;
       own[Nfull + st.j] = s1;
     }
@@ -250,7 +267,7 @@ __global__ __launch_bounds__(256) void heis_kernel(const Geom g, const RngKey ke
   float h[3];
   field_row<D, 3, JK>(g, s, J, J0, c, st, h);
   float sv[3] = {own[st.j], own[Nfull + st.j], own[2 * Nfull + st.j]};
-  if (heis_update<FAST>(sv, h, rnd.w[0], rnd.w[1], rnd.w[2], beta, omc)) {
+  if (heis_update<FAST>(sv, h, rnd.w[0], rnd.w[1], rnd.w[2], beta, beta_log2e(beta), omc)) {
     own[st.j] = sv[0];
     own[Nfull + st.j] = sv[1];
     own[2 * Nfull + st.j] = sv[2];
@@ -280,6 +297,8 @@ __device__ __forceinline__ void ldv(const float* base, uint32_t idx, float* o) {
   if (V == 4) {
     const float4 v = *reinterpret_cast<const float4*>(at(base, idx));
     o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+  } else if (V == 1) {
+    o[0] = *at(base, idx);
   } else {
     const float2 v = *reinterpret_cast<const float2*>(at(base, idx));
     o[0] = v.x; o[1] = v.y;
@@ -289,24 +308,26 @@ template <int V>
 __device__ __forceinline__ void stv(float* base, uint32_t idx, const float* o) {
   if (V == 4)
     *reinterpret_cast<float4*>(at(base, idx)) = make_float4(o[0], o[1], o[2], o[3]);
+  else if (V == 1)
+    *at(base, idx) = o[0];
   else
     *reinterpret_cast<float2*>(at(base, idx)) = make_float2(o[0], o[1]);
 }
-
-template <int N>
-constexpr int cont_v() { return N == 2 ? 4 : 2; }
 
 // MEASURE (colour 1 only): each lane also sums, in FP64, the energy of the
 // bonds of its updated sites and the magnetisation of its sites plus the
 // colour-0 sites at the same positions (the per-site formula of the
 // measurement kernel); block sums go to parts[block].
-template <int D, int N, int JK, bool FAST, bool MEASURE>
+// V sites per lane: XY 4 or 2 (a lane holds whole Philox blocks of two
+// sites), Heisenberg 2 or 1.
+template <int D, int N, int JK, bool FAST, bool MEASURE, int V>
 __global__ __launch_bounds__(256) void cont_stream_kernel(
     const Geom g, const RngKey key, const void* __restrict__ J, const float J0, const float beta,
     const float param, const FastDiv divQ, const FastDiv divL, const uint32_t H,
     const uint32_t nbands, float* __restrict__ s, const uint32_t t, const uint32_t c,
     const double J0d, Partial* __restrict__ parts) {
-  constexpr int V = cont_v<N>();
+  static_assert(N == 2 ? (V == 2 || V == 4) : (V == 1 || V == 2), "sites per lane");
+  const float bl2e = beta_log2e(beta);
   const uint32_t tid = xcd_remap(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
   const uint32_t band = fdiv(tid, divQ);
   double Esum = 0.0, Msum[3] = {0.0, 0.0, 0.0};
@@ -421,10 +442,10 @@ __global__ __launch_bounds__(256) void cont_stream_kernel(
         if (N == 2) {
           const Rand4& rw = rnd[k >> 1];
           xy_update<FAST>(Ow[b][0][k], Ow[b][1][k], h, (k & 1) ? rw.w[2] : rw.w[0],
-                          (k & 1) ? rw.w[3] : rw.w[1], beta, param);
+                          (k & 1) ? rw.w[3] : rw.w[1], beta, bl2e, param);
         } else {
           float sv[3] = {Ow[b][0][k], Ow[b][1][k], Ow[b][2][k]};
-          heis_update<FAST>(sv, h, rnd[k].w[0], rnd[k].w[1], rnd[k].w[2], beta, param);
+          heis_update<FAST>(sv, h, rnd[k].w[0], rnd[k].w[1], rnd[k].w[2], beta, bl2e, param);
           Ow[b][0][k] = sv[0];
           Ow[b][1][k] = sv[1];
           Ow[b][2][k] = sv[2];
@@ -540,40 +561,42 @@ static hipError_t launch_cont_stream(const ContLaunch& a, float* s, uint32_t t, 
   const uint64_t threads = (uint64_t)nbands * a.divQ.d;
   const dim3 grid((unsigned)((threads + 255) / 256));
   const float param = a.n == 2 ? a.delta : a.one_minus_cos_cap;
-#define SMC_CS(N, F, M)                                                                         \
-  hipLaunchKernelGGL((cont_stream_kernel<D, N, JK, F, M>), grid, dim3(256), 0, st, a.g, a.key,  \
-                     a.J, a.J0, a.beta, param, a.divQ, a.divL, H, nbands, s, t, c, a.J0d,        \
+  const bool meas = partials != nullptr;
+  if (meas && nparts) *nparts = grid.x;
+#define SMC_CS(N, F, M, V)                                                                         \
+  hipLaunchKernelGGL((cont_stream_kernel<D, N, JK, F, M, V>), grid, dim3(256), 0, st, a.g, a.key,  \
+                     a.J, a.J0, a.beta, param, a.divQ, a.divL, H, nbands, s, t, c, a.J0d,           \
                      (Partial*)partials)
-  if (partials) {
-    if (nparts) *nparts = grid.x;
-    if (a.n == 2) {
-      if (a.fast_math) SMC_CS(2, true, true); else SMC_CS(2, false, true);
-    } else {
-      if (a.fast_math) SMC_CS(3, true, true); else SMC_CS(3, false, true);
-    }
+#define SMC_CSV(N, V)                                                 \
+  do {                                                                \
+    if (meas) { if (a.fast_math) SMC_CS(N, true, true, V); else SMC_CS(N, false, true, V); } \
+    else { if (a.fast_math) SMC_CS(N, true, false, V); else SMC_CS(N, false, false, V); }   \
+  } while (0)
+  if (a.n == 2) {
+    if (a.sites_per_lane == 2) SMC_CSV(2, 2); else SMC_CSV(2, 4);
   } else {
-    if (a.n == 2) {
-      if (a.fast_math) SMC_CS(2, true, false); else SMC_CS(2, false, false);
-    } else {
-      if (a.fast_math) SMC_CS(3, true, false); else SMC_CS(3, false, false);
-    }
+    if (a.sites_per_lane == 1) SMC_CSV(3, 1); else SMC_CSV(3, 2);
   }
+#undef SMC_CSV
 #undef SMC_CS
   return hipGetLastError();
 }
 
-uint32_t cont_sites_per_lane(int n) { return n == 2 ? (uint32_t)cont_v<2>() : (uint32_t)cont_v<3>(); }
+uint32_t cont_default_sites_per_lane(int n) { return n == 2 ? 4u : 2u; }
 
-bool cont_stream_supported(const Geom& g, int n, uint32_t H) {
-  const uint32_t V = cont_sites_per_lane(n);
-  return (uint32_t)g.R % V == 0 && H >= 4 && H % 4 == 0 && (uint32_t)g.L % H == 0 &&
+bool cont_sites_per_lane_ok(int n, uint32_t V) {
+  return n == 2 ? (V == 2 || V == 4) : (V == 1 || V == 2);
+}
+
+bool cont_stream_supported(const Geom& g, uint32_t V, uint32_t H) {
+  return V >= 1 && (uint32_t)g.R % V == 0 && H >= 4 && H % 4 == 0 && (uint32_t)g.L % H == 0 &&
          g.Nh < ((int64_t)1 << 30);  // 32-bit byte offsets within a plane
 }
 
 // Band height of the streaming kernel: the largest divisor of L up to 64 that
 // still gives at least `min_waves` waves.
-uint32_t cont_rows_per_band(const Geom& g, int n, uint32_t min_waves) {
-  const uint32_t Q = (uint32_t)g.R / cont_sites_per_lane(n);
+uint32_t cont_rows_per_band(const Geom& g, uint32_t V, uint32_t min_waves) {
+  const uint32_t Q = (uint32_t)g.R / V;
   uint32_t best = 4;
   for (uint32_t H = 4; H <= 64; H *= 2) {
     if (g.L % H) break;
@@ -585,7 +608,7 @@ uint32_t cont_rows_per_band(const Geom& g, int n, uint32_t min_waves) {
 
 int cont_variant_used(const ContLaunch& a) {
   if (a.variant == kContRow) return kContRow;
-  return cont_stream_supported(a.g, a.n, a.rows_per_band) ? kContStream : kContRow;
+  return cont_stream_supported(a.g, a.sites_per_lane, a.rows_per_band) ? kContStream : kContRow;
 }
 
 template <int D>

@@ -32,9 +32,10 @@ hipError_t launch_ising_half_sweep(const IsingLaunch& a, int8_t* spins, uint32_t
 // Chunk kernel requires L % 32 == 0 (plane rows are whole 16-byte chunks).
 bool ising_chunk_supported(const Geom& g, int J_kind);
 
-uint32_t cont_sites_per_lane(int n);
-bool cont_stream_supported(const Geom& g, int n, uint32_t H);
-uint32_t cont_rows_per_band(const Geom& g, int n, uint32_t min_waves);
+uint32_t cont_default_sites_per_lane(int n);
+bool cont_sites_per_lane_ok(int n, uint32_t V);
+bool cont_stream_supported(const Geom& g, uint32_t V, uint32_t H);
+uint32_t cont_rows_per_band(const Geom& g, uint32_t V, uint32_t min_waves);
 int cont_variant_used(const ContLaunch& a);
 // Colour-1 half-sweep of the continuous streaming kernel with E and M of the
 // resulting state reduced on the way (partials per block); false if the

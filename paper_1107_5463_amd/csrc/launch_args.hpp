@@ -50,6 +50,7 @@ struct ContLaunch {
   int fast_math;
   int variant;              // ContVariant
   uint32_t rows_per_band;   // streaming kernel band height
+  uint32_t sites_per_lane;  // streaming kernel: XY 4 or 2, Heisenberg 2 or 1
   FastDiv divQ;             // lanes per plane row (R / sites per lane)
   FastDiv divL;             // edge length
   double J0d;               // uniform coupling in FP64 (fused measurement)

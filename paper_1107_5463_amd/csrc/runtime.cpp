@@ -62,6 +62,7 @@ struct smc_lattice {
   uint32_t packed_rows;      // packed kernel band height (SMC_PACKED_ROWS overrides)
   int cont_variant;          // ContVariant (SMC_CONT_KERNEL overrides the automatic choice)
   uint32_t cont_rows;        // continuous streaming band height (SMC_CONT_ROWS overrides)
+  uint32_t cont_spl;         // continuous streaming sites per lane (SMC_CONT_SPL overrides)
   FastDiv divQc;             // continuous streaming lanes per plane row
   // workspace carve-up
   void* obs_slot;      // smc_obs (64 B)
@@ -319,6 +320,7 @@ ContLaunch cont_args(const smc_lattice* h, double beta) {
   a.fast_math = (h->p.flags & SMC_FLAG_FAST_MATH) ? 1 : 0;
   a.variant = h->cont_variant;
   a.rows_per_band = h->cont_rows;
+  a.sites_per_lane = h->cont_spl;
   a.divQ = h->divQc;
   a.divL = h->divL;
   return a;
@@ -544,7 +546,7 @@ uint32_t* band_field(smc_lattice* h, std::vector<uint32_t>& cand, const char** w
     ContLaunch a = cont_args(h, 0.0);
     if (cont_variant_used(a) != kContStream) return nullptr;
     *what = h->p.n == 2 ? "xy_stream" : "heisenberg_stream";
-    pow2(4, 64, [&](uint32_t H) { return cont_stream_supported(g, h->p.n, H); });
+    pow2(4, 64, [&](uint32_t H) { return cont_stream_supported(g, h->cont_spl, H); });
     return &h->cont_rows;
   }
   IsingLaunch a = ising_args(h, 0.0);
@@ -755,14 +757,18 @@ int smc_init_lattice(smc_lattice** out, const smc_params* p, void* spins, void* 
     if (s == "row") h->cont_variant = kContRow;
     if (s == "stream") h->cont_variant = kContStream;
   }
-  h->cont_rows = p->n > 1 ? cont_rows_per_band(h->g, p->n, 2048) : 4;
+  h->cont_spl = p->n > 1 ? cont_default_sites_per_lane(p->n) : 1;
+  if (const char* v = std::getenv("SMC_CONT_SPL")) {
+    const long V = std::strtol(v, nullptr, 10);
+    if (p->n > 1 && V > 0 && cont_sites_per_lane_ok(p->n, (uint32_t)V)) h->cont_spl = (uint32_t)V;
+  }
+  h->cont_rows = p->n > 1 ? cont_rows_per_band(h->g, h->cont_spl, 2048) : 4;
   if (const char* v = std::getenv("SMC_CONT_ROWS")) {
     const long H = std::strtol(v, nullptr, 10);
     if (H >= 4 && H <= 64 && H % 4 == 0 && H <= h->g.L && h->g.L % H == 0) h->cont_rows = (uint32_t)H;
   }
   {
-    const uint32_t V = p->n > 1 ? cont_sites_per_lane(p->n) : 1;
-    const uint32_t Qc = (uint32_t)h->g.R / V;
+    const uint32_t Qc = (uint32_t)h->g.R / h->cont_spl;
     h->divQc = make_fastdiv(Qc > 0 ? Qc : 1);
   }
   h->use_fused = p->n == 1 && !is_packed(p) && p->tile == 0 && !(p->flags & SMC_FLAG_HEATBATH) &&
@@ -966,12 +972,7 @@ const char* smc_kernel_name(const smc_lattice* h, uint32_t* rows_per_band) {
   if (rows_per_band) *rows_per_band = 0;
   if (!h) return "";
   if (h->p.n > 1) {
-    ContLaunch a;
-    std::memset(&a, 0, sizeof(a));
-    a.g = h->g;
-    a.n = h->p.n;
-    a.variant = h->cont_variant;
-    a.rows_per_band = h->cont_rows;
+    const ContLaunch a = cont_args(h, 0.0);
     const bool stream = cont_variant_used(a) == kContStream;
     if (stream && rows_per_band) *rows_per_band = h->cont_rows;
     if (h->p.n == 2) return stream ? "xy_stream" : "xy_site";

@@ -65,22 +65,36 @@ CASES = [  # d, n, L, beta, delta, J_kind, fast
 
 # the streaming kernel at several band heights: many bands and blocks, ragged
 # last block (lanes past the last band idle)
-STREAM_CASES = [  # d, n, L, beta, delta, J_kind, fast, rows
-    (2, 2, 128, 1.12, 1.63, 0, False, 16),
-    (2, 2, 96, 1.0, 1.5, 2, False, 8),
-    (2, 3, 64, 0.8, 0.7, 1, False, 32),
-    (3, 3, 32, 0.693, 2.058, 0, False, 8),
-    (3, 2, 24, 0.6, 1.5, 2, False, 4),
-    (3, 3, 12, 0.7, 1.2, 1, False, 4),
+# (and at both sites-per-lane choices of each model: XY 4 or 2, Heisenberg 2
+# or 1; None = the default)
+STREAM_CASES = [  # d, n, L, beta, delta, J_kind, fast, rows, sites per lane
+    (2, 2, 128, 1.12, 1.63, 0, False, 16, None),
+    (2, 2, 96, 1.0, 1.5, 2, False, 8, None),
+    (2, 3, 64, 0.8, 0.7, 1, False, 32, None),
+    (3, 3, 32, 0.693, 2.058, 0, False, 8, None),
+    (3, 2, 24, 0.6, 1.5, 2, False, 4, None),
+    (3, 3, 12, 0.7, 1.2, 1, False, 4, None),
+    (2, 2, 128, 1.12, 1.63, 0, False, 16, 2),
+    (3, 2, 24, 0.6, 1.5, 2, False, 4, 2),
+    (2, 3, 64, 0.8, 0.7, 1, False, 32, 1),
+    (3, 3, 32, 0.693, 2.058, 0, False, 8, 1),
+    (3, 3, 12, 0.7, 1.2, 1, False, 4, 1),
+    (3, 3, 16, 0.693, 2.058, 0, True, 4, 1),
+    (3, 3, 32, 0.693, 2.058, 0, False, 8, 2),
+    (2, 2, 64, 1.12, 1.63, 0, False, 8, 4),
 ]
 
 
-def _set_kernel(monkeypatch, kernel, rows=None):
+def _set_kernel(monkeypatch, kernel, rows=None, spl=None):
     monkeypatch.setenv("SMC_CONT_KERNEL", kernel)
     if rows is None:
         monkeypatch.delenv("SMC_CONT_ROWS", raising=False)
     else:
         monkeypatch.setenv("SMC_CONT_ROWS", str(rows))
+    if spl is None:
+        monkeypatch.delenv("SMC_CONT_SPL", raising=False)
+    else:
+        monkeypatch.setenv("SMC_CONT_SPL", str(spl))
 
 
 @pytest.mark.parametrize("kernel", ["row", "stream"])
@@ -91,10 +105,10 @@ def test_half_sweep_protocol(smc_gpu, oracle_mod, d, n, L, beta, delta, kind, fa
     _protocol(smc_gpu, oracle_mod, d, n, L, beta, delta, kind, fast, kernel)
 
 
-@pytest.mark.parametrize("d,n,L,beta,delta,kind,fast,rows", STREAM_CASES)
-def test_stream_kernel_protocol(smc_gpu, oracle_mod, d, n, L, beta, delta, kind, fast, rows,
+@pytest.mark.parametrize("d,n,L,beta,delta,kind,fast,rows,spl", STREAM_CASES)
+def test_stream_kernel_protocol(smc_gpu, oracle_mod, d, n, L, beta, delta, kind, fast, rows, spl,
                                 monkeypatch):
-    _set_kernel(monkeypatch, "stream", rows)
+    _set_kernel(monkeypatch, "stream", rows, spl)
     lat = _protocol(smc_gpu, oracle_mod, d, n, L, beta, delta, kind, fast, "stream")
     assert lat.kernel()[1] == rows
 
