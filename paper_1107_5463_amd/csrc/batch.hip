@@ -35,8 +35,8 @@ namespace smc {
 constexpr uint32_t kBatchTieSlots = 4;  // deferred ties per lane before a flush
 
 // ---------------------------------------------------------------------------
-// Packed path (3D lattices with L % 8 == 0, at most two 32-site words of a
-// colour per lane): the lattice sits in LDS at one bit per site -- word w of
+// Packed path (3D lattices with L % 4 == 0, L <= 40, at most two 32-site
+// words of a colour per lane): the lattice sits in LDS at one bit per site -- word w of
 // colour c holds sites 32 w .. 32 w + 31 of that plane, the two colours'
 // words interleaved (byte 8 (w + 1) + 4 c, a zero pad word at each end) --
 // with the signs of each site's 2d bonds as six words aligned with it (the
@@ -46,7 +46,9 @@ constexpr uint32_t kBatchTieSlots = 4;  // deferred ties per lane before a flush
 // from funnel shifts of LDS words: in-row x +- 1 (with the wrap at row ends
 // and the row parity as per-word masks), y +- 1 (a shift by R = L / 2 sites,
 // with the rows at y = L - 1 or 0 taking the wrapped source), and z +- 1 (a
-// whole word: L^2 / 2 sites is a multiple of 32).  Counts, the decision with
+// shift by L^2 / 2 sites: a whole word when L % 8 == 0, otherwise a funnel
+// shift with the planes at z = L - 1 or 0 taking the wrapped source).
+// Counts, the decision with
 // its prefix bit planes and exact ties, and the random bytes per site are
 // those of the packed single-lattice kernel, so every lattice keeps the
 // chain of its replica bit for bit.
