@@ -34,9 +34,11 @@ namespace smc {
 
 // Per-lane queue of the words with exact ties: a slot holds the word's tie
 // mask and its count planes (for the classes of the tied sites) and the row
-// in the band.  A word is queued without a branch (its slot is written and the
-// count advances only if it has ties); the ties are resolved when the queue is
-// full and at the end of the band.
+// in the band -- or, when only the classes k < d can refuse a move (k2 = 0 at
+// every tied site, the fast decision) and WSLOT is set, the tie mask, k0, k1
+// and the word's index.  A word is queued without a branch (its slot is
+// written and the count advances only if it has ties); the ties are resolved
+// when the queue is full and at the end of the band.
 constexpr uint32_t kTieWords = 4;
 
 struct PackedTies {
@@ -46,20 +48,26 @@ struct PackedTies {
   int64_t dE, dM;
 };
 
-template <int D, bool MEASURE>
+// Class k of tied site b of a queued word.
+template <bool WSLOT>
+__device__ __forceinline__ uint32_t tie_class(const uint4& en, uint32_t b) {
+  return ((en.y >> b) & 1u) | (((en.z >> b) & 1u) << 1) | (WSLOT ? 0u : ((en.w >> b) & 1u) << 2);
+}
+
+template <int D, bool MEASURE, bool WSLOT = false>
 __device__ __forceinline__ void packed_tie_flush(PackedTies& q, const TabRegs& tab,
                                                  const RngKey& key, uint32_t t, uint32_t c,
                                                  uint32_t* own) {
   for (uint32_t e = 0; e < q.n; ++e) {
     const uint4 en = q.ent[e * q.stride];
-    const uint32_t wi = q.base + (uint32_t)q.rows[e * q.stride] * q.W;
+    const uint32_t wi = WSLOT ? en.w : q.base + (uint32_t)q.rows[e * q.stride] * q.W;
     uint32_t m = en.x;
     uint32_t word = 0, flips = 0;
     if (MEASURE) word = own[wi];
     while (m) {
       const uint32_t b = __builtin_ctz(m);
       m &= m - 1;
-      const uint32_t k = ((en.y >> b) & 1u) | (((en.z >> b) & 1u) << 1) | (((en.w >> b) & 1u) << 2);
+      const uint32_t k = tie_class<WSLOT>(en, b);
       const uint32_t js = wi * 32u + b;
       const Rand4 rr = philox(js, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
       if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) {
@@ -79,15 +87,75 @@ __device__ __forceinline__ void packed_tie_flush(PackedTies& q, const TabRegs& t
 // Queue a stored word's exact ties: its slot is written in any case and the
 // count advances only if there are ties; a full queue is resolved at once (its
 // flips go to words already stored).
-template <int D, bool MEASURE>
+template <int D, bool MEASURE, bool WSLOT = false>
 __device__ __forceinline__ void packed_queue_word(PackedTies& q, uint32_t ties, uint32_t row,
-                                                  uint32_t k0, uint32_t k1, uint32_t k2,
-                                                  const TabRegs& tab, const RngKey& key,
-                                                  uint32_t t, uint32_t c, uint32_t* own) {
-  q.ent[q.n * q.stride] = make_uint4(ties, k0, k1, k2);
-  q.rows[q.n * q.stride] = (uint8_t)row;
+                                                  uint32_t wi, uint32_t k0, uint32_t k1,
+                                                  uint32_t k2, const TabRegs& tab,
+                                                  const RngKey& key, uint32_t t, uint32_t c,
+                                                  uint32_t* own) {
+  q.ent[q.n * q.stride] = make_uint4(ties, k0, k1, WSLOT ? wi : k2);
+  if (!WSLOT) q.rows[q.n * q.stride] = (uint8_t)row;
   q.n += ties != 0u ? 1u : 0u;
-  if (q.n == kTieWords) packed_tie_flush<D, MEASURE>(q, tab, key, t, c, own);
+  if (q.n == kTieWords) packed_tie_flush<D, MEASURE, WSLOT>(q, tab, key, t, c, own);
+}
+
+// End-of-band resolution shared by the wave (WSLOT slots): the wave's queued
+// words are numbered in lane order (a ballot prefix sum of the lanes' queue
+// lengths), lane i draws the refinements of the tied sites of word i and
+// leaves the word's flips in its slot, and each lane then applies the flips
+// of its own words -- so the wave waits for about one refinement draw per
+// lane instead of the largest number of draws of any one lane, and every
+// spin word is still written by the lane that owns it.  `idx` is the wave's
+// list of at most 64 kTieWords entries (lane | slot << 6) in LDS.
+template <int D>
+__device__ __forceinline__ void packed_tie_flush_wave(PackedTies& q, const TabRegs& tab,
+                                                      const RngKey& key, uint32_t t, uint32_t c,
+                                                      uint32_t* own, uint8_t* idx,
+                                                      uint4* wave_ent) {
+  static_assert(kTieWords <= 4, "queue length fits the two slot bits of an index entry");
+  const uint32_t lane = __lane_id();
+  const uint32_t n = q.n;
+  const uint64_t b0 = __ballot(n & 1u), b1 = __ballot(n & 2u), b2 = __ballot(n & 4u);
+  auto below = [&](uint64_t b) -> uint32_t {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+  };
+  const uint32_t first = below(b0) + 2u * below(b1) + 4u * below(b2);
+  const uint32_t total = (uint32_t)__popcll(b0) + 2u * (uint32_t)__popcll(b1) +
+                         4u * (uint32_t)__popcll(b2);
+  if (total == 0u) return;
+#pragma unroll
+  for (uint32_t e = 0; e < kTieWords; ++e)
+    if (e < n) idx[first + e] = (uint8_t)(lane | (e << 6));
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  for (uint32_t r0 = 0; r0 < total; r0 += 64u) {
+    const uint32_t i = r0 + lane;
+    if (i < total) {
+      const uint32_t id = idx[i];
+      uint4* slot = wave_ent + (id >> 6) * q.stride + (id & 63u);
+      const uint4 en = *slot;
+      uint32_t m = en.x, flips = 0;
+      while (m) {
+        const uint32_t b = __builtin_ctz(m);
+        m &= m - 1;
+        const Rand4 rr = philox(en.w * 32u + b, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
+        if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, tie_class<true>(en, b))) flips |= 1u << b;
+      }
+      slot->x = flips;
+    }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+  for (uint32_t e = 0; e < kTieWords; ++e) {
+    if (e < n) {
+      const uint4 en = q.ent[e * q.stride];
+      if (en.x) own[en.w] ^= en.x;  // the lane's own word, stored earlier by this lane
+    }
+  }
+  q.n = 0;
 }
 
 __device__ __forceinline__ int32_t popc(uint32_t v) { return __builtin_popcount(v); }
@@ -96,8 +164,9 @@ __device__ __forceinline__ int32_t popc(uint32_t v) { return __builtin_popcount(
 // compiler for that occupancy (64 registers); the +-1-coupling 3D kernel would
 // spill there and keeps the default.
 // FAST: only the classes k < d can refuse a move (J0 > 0), decided by
-// packed_decide_fast; otherwise packed_decide.
-template <int D, bool PM, bool MEASURE, bool FAST>
+// packed_decide_fast; otherwise packed_decide.  WAVE (FAST plain launches):
+// the end-of-band ties are resolved by the whole wave (packed_tie_flush_wave).
+template <int D, bool PM, bool MEASURE, bool FAST, bool WAVE>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void packed_stream_kernel(const Geom g, const RngKey key,
                                                             const IsingTable table,
@@ -107,8 +176,10 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
                                                             const uint32_t* __restrict__ J,
                                                             const uint32_t t, const uint32_t c,
                                                             Partial* __restrict__ parts) {
+  static_assert(!WAVE || (FAST && !MEASURE), "wave resolution: fast plain launches");
   __shared__ uint4 tie_ent[kTieWords * 256];
-  __shared__ uint8_t tie_rows[kTieWords * 256];
+  __shared__ uint8_t tie_rows[WAVE ? 1 : kTieWords * 256];
+  __shared__ uint8_t tie_idx[WAVE ? kTieWords * 256 : 1];
   const uint32_t tid = xcd_remap(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
   const uint32_t band = fdiv(tid, divW);
   int64_t Esum = 0, Msum = 0;
@@ -120,7 +191,7 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
   if (FAST) ft = fast_tab<D>(tab);
   PackedTies tq;
   tq.ent = tie_ent + threadIdx.x;
-  tq.rows = tie_rows + threadIdx.x;
+  tq.rows = tie_rows + (WAVE ? 0u : threadIdx.x);
   tq.stride = 256;
   tq.n = 0;
   tq.base = 0;
@@ -206,7 +277,7 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
                                  : packed_decide<D>(tab, key, t, c, rowb + q, k0, k1, k2, ties);
       const uint32_t on = o ^ flip;
       *reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(own) + ((rowb + q) << 2)) = on;
-      packed_queue_word<D, MEASURE>(tq, ties, i, k0, k1, k2, tab, key, t, c, own);
+      packed_queue_word<D, MEASURE, WAVE>(tq, ties, i, rowb + q, k0, k1, k2, tab, key, t, c, own);
       if (MEASURE) {
         // colour 1 after its update: each bond has one colour-1 end; the
         // colour-0 word at the same position covers each colour-0 site once
@@ -224,7 +295,11 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
       ct = dn;
     }
   }
-  packed_tie_flush<D, MEASURE>(tq, tab, key, t, c, own);  // the band's queued ties
+  if (WAVE)  // the band's queued ties
+    packed_tie_flush_wave<D>(tq, tab, key, t, c, own, tie_idx + (threadIdx.x & ~63u) * kTieWords,
+                             tie_ent + (threadIdx.x & ~63u));
+  else
+    packed_tie_flush<D, MEASURE>(tq, tab, key, t, c, own);
   if (MEASURE) {
     Esum += tq.dE;
     Msum += tq.dM;
@@ -264,11 +339,16 @@ hipError_t launch_packed_half_sweep(const IsingLaunch& a, uint32_t* spins, const
   for (int k = a.g.d; k <= 2 * a.g.d; ++k)
     if ((((k < 4 ? a.tab.al_lo : a.tab.al_hi) >> (8 * (k & 3))) & 0xFFu) != 0xFFu) fast = false;
   Partial* pp = (Partial*)partials;
-#define SMC_PK(DD, PMM, MM, FF)                                                                     \
-  hipLaunchKernelGGL((packed_stream_kernel<DD, PMM, MM, FF>), grid, block, 0, st, a.g, a.key, a.tab, \
+  const bool wave = a.packed_ties == 0;
+#define SMC_PK(DD, PMM, MM, FF, WW)                                                                     \
+  hipLaunchKernelGGL((packed_stream_kernel<DD, PMM, MM, FF, WW>), grid, block, 0, st, a.g, a.key, a.tab, \
                      dW, dL, H, nbands, spins, J, t, c, pp)
-#define SMC_PKF(DD, PMM, MM) \
-  do { if (fast) SMC_PK(DD, PMM, MM, true); else SMC_PK(DD, PMM, MM, false); } while (0)
+#define SMC_PKF(DD, PMM, MM)                                        \
+  do {                                                              \
+    if (!fast) SMC_PK(DD, PMM, MM, false, false);                   \
+    else if (MM || !wave) SMC_PK(DD, PMM, MM, true, false);         \
+    else SMC_PK(DD, PMM, false, true, true);                        \
+  } while (0)
   if (a.g.d == 2) {
     if (pm) { if (pp) SMC_PKF(2, true, true); else SMC_PKF(2, true, false); }
     else { if (pp) SMC_PKF(2, false, true); else SMC_PKF(2, false, false); }

@@ -60,6 +60,7 @@ struct smc_lattice {
   bool use_fused;            // SMC_FLAG_SCHEDULE_FUSED and the fused kernel supports the shape
   uint32_t fused_rows;       // fused kernel band height (SMC_FUSED_ROWS overrides)
   uint32_t packed_rows;      // packed kernel band height (SMC_PACKED_ROWS overrides)
+  int packed_ties;           // packed kernel ties: 0 by the wave, 1 by each lane (SMC_PACKED_TIES)
   int cont_variant;          // ContVariant (SMC_CONT_KERNEL overrides the automatic choice)
   uint32_t cont_rows;        // continuous streaming band height (SMC_CONT_ROWS overrides)
   uint32_t cont_spl;         // continuous streaming sites per lane (SMC_CONT_SPL overrides)
@@ -275,6 +276,7 @@ IsingLaunch ising_args(smc_lattice* h, double beta) {
   a.divQ = h->divQ;
   a.divL = h->divL;
   a.heatbath = (h->p.flags & SMC_FLAG_HEATBATH) ? 1 : 0;
+  a.packed_ties = h->packed_ties;
   return a;
 }
 
@@ -747,6 +749,12 @@ int smc_init_lattice(smc_lattice** out, const smc_params* p, void* spins, void* 
     if (H >= 1 && H <= 64 && H <= h->g.L && h->g.L % H == 0) h->fused_rows = (uint32_t)H;
   }
   h->packed_rows = packed_rows_per_band(h->g, 8192);
+  h->packed_ties = 0;
+  if (const char* v = std::getenv("SMC_PACKED_TIES")) {
+    const std::string s(v);
+    if (s == "lane") h->packed_ties = 1;
+    if (s == "wave") h->packed_ties = 0;
+  }
   if (const char* v = std::getenv("SMC_PACKED_ROWS")) {
     const long H = std::strtol(v, nullptr, 10);
     if (H >= 1 && H <= 64 && H <= h->g.L && h->g.L % H == 0) h->packed_rows = (uint32_t)H;

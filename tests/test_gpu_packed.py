@@ -56,9 +56,11 @@ SHAPES = [  # d, L, J_kind, beta, sweeps
 ]
 
 
+@pytest.mark.parametrize("ties", ["wave", "lane"])
 @pytest.mark.parametrize("d,L,kind,beta,n", SHAPES)
-def test_sweeps_match_oracle(smc_gpu, oracle_mod, d, L, kind, beta, n, monkeypatch):
-    print(f"packed sweeps d={d} L={L} kind={kind} beta={beta}", flush=True)
+def test_sweeps_match_oracle(smc_gpu, oracle_mod, d, L, kind, beta, n, ties, monkeypatch):
+    monkeypatch.setenv("SMC_PACKED_TIES", ties)
+    print(f"packed sweeps d={d} L={L} kind={kind} beta={beta} ties={ties}", flush=True)
     lat = smc_gpu.Lattice(d, 1, L, seed=L + kind, J_kind=kind, packed=True)
     assert lat.kernel()[0] == "ising_packed"
     ref = oracle_mod.OracleLattice(d, 1, L, L + kind, J_kind=kind)
@@ -69,9 +71,11 @@ def test_sweeps_match_oracle(smc_gpu, oracle_mod, d, L, kind, beta, n, monkeypat
     assert (o.E_int, o.M_int) == (r.E_int, r.M_int)
 
 
+@pytest.mark.parametrize("ties", ["wave", "lane"])
 @pytest.mark.parametrize("rows", ["1", "4", "16", "64"])
-def test_band_heights_give_the_same_chain(smc_gpu, oracle_mod, rows, monkeypatch):
+def test_band_heights_give_the_same_chain(smc_gpu, oracle_mod, rows, ties, monkeypatch):
     monkeypatch.setenv("SMC_PACKED_ROWS", rows)
+    monkeypatch.setenv("SMC_PACKED_TIES", ties)
     lat = smc_gpu.Lattice(2, 1, 128, seed=4, packed=True)
     assert lat.kernel() == ("ising_packed", int(rows))
     ref = oracle_mod.OracleLattice(2, 1, 128, 4)
@@ -94,6 +98,26 @@ def test_sweep_measure_matches_oracle(smc_gpu, oracle_mod, d, L):
         r = ref.measure()
         assert (got[k].E_int, got[k].M_int) == (r.E_int, r.M_int), k
     assert [o.sweep for o in got] == [1, 5, 5]
+
+
+@pytest.mark.parametrize("ties", ["wave", "lane"])
+def test_many_ties_per_wave(smc_gpu, oracle_mod, ties, monkeypatch):
+    """Bands of 64 rows at beta = 2 on a 2D L=4096 lattice (a wave is one
+    plane row's 64 word columns): a lane meets a tied word every 8 to 25 words
+    (a refusable site ties with probability 2^-8, and 30-90 % of the sites are
+    refusable), so a wave ends its band with about 100-190 queued words --
+    more than one round of the wave's resolution -- and some lanes resolve a
+    full queue on the spot."""
+    monkeypatch.setenv("SMC_PACKED_ROWS", "64")
+    monkeypatch.setenv("SMC_PACKED_TIES", ties)
+    L = 4096
+    print(f"packed many ties L={L} ties={ties}", flush=True)
+    lat = smc_gpu.Lattice(2, 1, L, seed=7, packed=True)
+    assert lat.kernel() == ("ising_packed", 64)
+    ref = oracle_mod.OracleLattice(2, 1, L, 7)
+    lat.sweep(2.0, 3)
+    ref.sweep(2.0, 3)
+    assert np.array_equal(nat(smc_gpu, lat), ref.s)
 
 
 def test_special_temperatures(smc_gpu, oracle_mod):
