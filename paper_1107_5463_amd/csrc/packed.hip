@@ -41,6 +41,8 @@ namespace smc {
 // when the queue is full and at the end of the band.
 constexpr uint32_t kTieWords = 4;
 
+__device__ __forceinline__ int32_t popc(uint32_t v) { return __builtin_popcount(v); }
+
 struct PackedTies {
   uint4* ent;       // ent[slot * stride]: (ties, k0, k1, k2)
   uint8_t* rows;    // rows[slot * stride]: row in the band
@@ -106,8 +108,10 @@ __device__ __forceinline__ void packed_queue_word(PackedTies& q, uint32_t ties, 
 // of its own words -- so the wave waits for about one refinement draw per
 // lane instead of the largest number of draws of any one lane, and every
 // spin word is still written by the lane that owns it.  `idx` is the wave's
-// list of at most 64 kTieWords entries (lane | slot << 6) in LDS.
-template <int D>
+// list of at most 64 kTieWords entries (lane | slot << 6) in LDS.  MEASURE:
+// the owner adds what its words' tie flips change -- each flipped site with
+// k unsatisfied bonds raises E by 4 (d - k) and moves M by -2 s.
+template <int D, bool MEASURE>
 __device__ __forceinline__ void packed_tie_flush_wave(PackedTies& q, const TabRegs& tab,
                                                       const RngKey& key, uint32_t t, uint32_t c,
                                                       uint32_t* own, uint8_t* idx,
@@ -152,20 +156,26 @@ __device__ __forceinline__ void packed_tie_flush_wave(PackedTies& q, const TabRe
   for (uint32_t e = 0; e < kTieWords; ++e) {
     if (e < n) {
       const uint4 en = q.ent[e * q.stride];
-      if (en.x) own[en.w] ^= en.x;  // the lane's own word, stored earlier by this lane
+      if (en.x) {  // the lane's own word, stored earlier by this lane
+        const uint32_t word = own[en.w];
+        own[en.w] = word ^ en.x;
+        if (MEASURE) {
+          const int64_t nf = popc(en.x);
+          q.dE += 4 * (D * nf - popc(en.x & en.y) - 2 * (int64_t)popc(en.x & en.z));
+          q.dM -= 2 * (nf - 2 * (int64_t)popc(en.x & word));  // a set bit is s = -1
+        }
+      }
     }
   }
   q.n = 0;
 }
 
-__device__ __forceinline__ int32_t popc(uint32_t v) { return __builtin_popcount(v); }
-
 // The plain launches of a band height chosen for eight waves per SIMD ask the
 // compiler for that occupancy (64 registers); the +-1-coupling 3D kernel would
 // spill there and keeps the default.
 // FAST: only the classes k < d can refuse a move (J0 > 0), decided by
-// packed_decide_fast; otherwise packed_decide.  WAVE (FAST plain launches):
-// the end-of-band ties are resolved by the whole wave (packed_tie_flush_wave).
+// packed_decide_fast; otherwise packed_decide.  WAVE (with FAST): the
+// end-of-band ties are resolved by the whole wave (packed_tie_flush_wave).
 template <int D, bool PM, bool MEASURE, bool FAST, bool WAVE>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void packed_stream_kernel(const Geom g, const RngKey key,
@@ -176,7 +186,7 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
                                                             const uint32_t* __restrict__ J,
                                                             const uint32_t t, const uint32_t c,
                                                             Partial* __restrict__ parts) {
-  static_assert(!WAVE || (FAST && !MEASURE), "wave resolution: fast plain launches");
+  static_assert(!WAVE || FAST, "wave resolution: the fast decision's slot layout");
   __shared__ uint4 tie_ent[kTieWords * 256];
   __shared__ uint8_t tie_rows[WAVE ? 1 : kTieWords * 256];
   __shared__ uint8_t tie_idx[WAVE ? kTieWords * 256 : 1];
@@ -296,8 +306,9 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
     }
   }
   if (WAVE)  // the band's queued ties
-    packed_tie_flush_wave<D>(tq, tab, key, t, c, own, tie_idx + (threadIdx.x & ~63u) * kTieWords,
-                             tie_ent + (threadIdx.x & ~63u));
+    packed_tie_flush_wave<D, MEASURE>(tq, tab, key, t, c, own,
+                                      tie_idx + (threadIdx.x & ~63u) * kTieWords,
+                                      tie_ent + (threadIdx.x & ~63u));
   else
     packed_tie_flush<D, MEASURE>(tq, tab, key, t, c, own);
   if (MEASURE) {
@@ -346,8 +357,8 @@ hipError_t launch_packed_half_sweep(const IsingLaunch& a, uint32_t* spins, const
 #define SMC_PKF(DD, PMM, MM)                                        \
   do {                                                              \
     if (!fast) SMC_PK(DD, PMM, MM, false, false);                   \
-    else if (MM || !wave) SMC_PK(DD, PMM, MM, true, false);         \
-    else SMC_PK(DD, PMM, false, true, true);                        \
+    else if (!wave) SMC_PK(DD, PMM, MM, true, false);               \
+    else SMC_PK(DD, PMM, MM, true, true);                           \
   } while (0)
   if (a.g.d == 2) {
     if (pm) { if (pp) SMC_PKF(2, true, true); else SMC_PKF(2, true, false); }

@@ -84,9 +84,11 @@ def test_band_heights_give_the_same_chain(smc_gpu, oracle_mod, rows, ties, monke
     assert np.array_equal(nat(smc_gpu, lat), ref.s)
 
 
+@pytest.mark.parametrize("ties", ["wave", "lane"])
 @pytest.mark.parametrize("d,L", [(2, 128), (3, 64)])
-def test_sweep_measure_matches_oracle(smc_gpu, oracle_mod, d, L):
+def test_sweep_measure_matches_oracle(smc_gpu, oracle_mod, d, L, ties, monkeypatch):
     import torch
+    monkeypatch.setenv("SMC_PACKED_TIES", ties)
     lat = smc_gpu.Lattice(d, 1, L, seed=33, packed=True)
     ref = oracle_mod.OracleLattice(d, 1, L, 33)
     slots = torch.zeros((3, 8), dtype=torch.int64, device=lat.device)
@@ -112,11 +114,19 @@ def test_many_ties_per_wave(smc_gpu, oracle_mod, ties, monkeypatch):
     monkeypatch.setenv("SMC_PACKED_TIES", ties)
     L = 4096
     print(f"packed many ties L={L} ties={ties}", flush=True)
+    import torch
     lat = smc_gpu.Lattice(2, 1, L, seed=7, packed=True)
     assert lat.kernel() == ("ising_packed", 64)
     ref = oracle_mod.OracleLattice(2, 1, L, 7)
-    lat.sweep(2.0, 3)
-    ref.sweep(2.0, 3)
+    lat.sweep(2.0, 2)
+    ref.sweep(2.0, 2)
+    assert np.array_equal(nat(smc_gpu, lat), ref.s)
+    # a measured sweep: the tie flips' share of E and M
+    slot = torch.zeros((1, 8), dtype=torch.int64, device=lat.device)
+    lat.sweep_measure(2.0, 1, slot[0])
+    ref.sweep(2.0, 1)
+    got, r = smc_gpu.Lattice.decode_obs(slot)[0], ref.measure()
+    assert (got.E_int, got.M_int) == (r.E_int, r.M_int)
     assert np.array_equal(nat(smc_gpu, lat), ref.s)
 
 
