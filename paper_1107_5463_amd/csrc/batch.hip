@@ -36,12 +36,12 @@ constexpr uint32_t kBatchTieSlots = 4;  // deferred ties per lane before a flush
 
 // ---------------------------------------------------------------------------
 // Packed path (3D lattices with L % 4 == 0, L <= 40, at most two 32-site
-// words of a colour per lane): the lattice sits in LDS at one bit per site -- word w of
-// colour c holds sites 32 w .. 32 w + 31 of that plane, the two colours'
-// words interleaved (byte 8 (w + 1) + 4 c, a zero pad word at each end) --
-// with the signs of each site's 2d bonds as six words aligned with it (the
-// -mu bonds gathered from the neighbours' planes when the lattice is
-// staged).  A lane owns words w = lane and w = lane + blockDim of both
+// words of a colour per lane): the lattice sits in LDS at one bit per site --
+// word w of colour c holds sites 32 w .. 32 w + 31 of that plane, the two
+// colours' words side by side (byte 12 (w + 1) + 4 c, a zero pad pair at each
+// end) -- with the signs of each site's 2d bonds as six words aligned with it
+// (the -mu bonds gathered from the neighbours' planes when the lattice is
+// staged; 52 bytes per word).  A lane owns words w = lane and w = lane + blockDim of both
 // colours for the whole call.  The neighbour words of the other colour come
 // from funnel shifts of LDS words: in-row x +- 1 (with the wrap at row ends
 // and the row parity as per-word masks), y +- 1 (a shift by R = L / 2 sites,
@@ -55,6 +55,10 @@ constexpr uint32_t kBatchTieSlots = 4;  // deferred ties per lane before a flush
 // ---------------------------------------------------------------------------
 constexpr uint32_t kPackedBatchWordsPerLane = 2;
 constexpr uint32_t kPackedBatchTieWords = 4;
+// LDS strides of a word's spin pair (colour 0, colour 1, unused) and of its
+// twelve bond-sign words (+ one unused): an odd number of dwords, so that 32
+// lanes reading consecutive words touch 32 different banks.
+constexpr uint32_t kPkSpin = 12, kPkBond = 52;
 
 __host__ __device__ inline bool batch_packed_ok(int d, uint32_t L, uint32_t threads) {
   if (d != 3 || L % 4u != 0u || L > 40u) return false;
@@ -66,8 +70,8 @@ __host__ __device__ inline bool batch_packed_ok(int d, uint32_t L, uint32_t thre
 // aligned bond-sign words (+-1 couplings), the per-lane tie queue.
 __host__ __device__ inline size_t batch_packed_lds_bytes(uint32_t L, bool pm, uint32_t threads) {
   const size_t Wp = (size_t)L * L * L / 64;
-  const size_t sb = (8 * (Wp + 2) + 15) / 16 * 16;
-  const size_t jb = pm ? 48 * Wp : 0;
+  const size_t sb = (kPkSpin * (Wp + 2) + 15) / 16 * 16;
+  const size_t jb = pm ? (kPkBond * Wp + 15) / 16 * 16 : 0;
   return sb + jb + (size_t)threads * kPackedBatchTieWords * 20;
 }
 
@@ -98,7 +102,7 @@ __device__ __forceinline__ void packed_neighbours(const unsigned char* lds, cons
                                                   uint32_t R, const PackedZ& pz, uint32_t nb[6]) {
   constexpr uint32_t O = 4u * (1u - C);  // the other colour's word in a pair
   auto ldw = [&](uint32_t a) -> uint32_t { return *reinterpret_cast<const uint32_t*>(lds + a); };
-  const uint32_t wp = ldw(pw.a0 - 8 + O), wc = ldw(pw.a0 + O), wn = ldw(pw.a0 + 8 + O);
+  const uint32_t wp = ldw(pw.a0 - kPkSpin + O), wc = ldw(pw.a0 + O), wn = ldw(pw.a0 + kPkSpin + O);
   const uint32_t next = __builtin_amdgcn_alignbit(wn, wc, 1u);        // site + 1
   const uint32_t prev = __builtin_amdgcn_alignbit(wc, wp, 31u);       // site - 1
   const uint32_t wst = __builtin_amdgcn_alignbit(wc, wp, 33u - R);    // site - (R - 1): row start
@@ -108,20 +112,20 @@ __device__ __forceinline__ void packed_neighbours(const unsigned char* lds, cons
   nb[0] = __builtin_amdgcn_bitop3_b32(Pm, __builtin_amdgcn_bitop3_b32(pw.E, wst, next, 0xCA), wc, 0xCA);
   nb[1] = __builtin_amdgcn_bitop3_b32(Pm, wc, __builtin_amdgcn_bitop3_b32(pw.S, wen, prev, 0xCA), 0xCA);
   const uint32_t yp = __builtin_amdgcn_alignbit(wn, wc, R);
-  const uint32_t ypw = __builtin_amdgcn_alignbit(ldw(pw.ayp + 8 + O), ldw(pw.ayp + O), pz.ysw);
+  const uint32_t ypw = __builtin_amdgcn_alignbit(ldw(pw.ayp + kPkSpin + O), ldw(pw.ayp + O), pz.ysw);
   nb[2] = __builtin_amdgcn_bitop3_b32(pw.Ymp, ypw, yp, 0xCA);
   const uint32_t ym = __builtin_amdgcn_alignbit(wc, wp, 32u - R);
-  const uint32_t ymw = __builtin_amdgcn_alignbit(ldw(pw.aym + 8 + O), ldw(pw.aym + O), pz.ysmw);
+  const uint32_t ymw = __builtin_amdgcn_alignbit(ldw(pw.aym + kPkSpin + O), ldw(pw.aym + O), pz.ysmw);
   nb[3] = __builtin_amdgcn_bitop3_b32(pw.Ymm, ymw, ym, 0xCA);
   if (pz.zs == 0u) {  // z-planes hold whole words
     nb[4] = ldw(pw.azp + O);
     nb[5] = ldw(pw.azm + O);
   } else {
-    const uint32_t zp = __builtin_amdgcn_alignbit(ldw(pw.azp + 8 + O), ldw(pw.azp + O), pz.zs);
-    const uint32_t zpw = __builtin_amdgcn_alignbit(ldw(pw.azpw + 8 + O), ldw(pw.azpw + O), pz.zsw);
+    const uint32_t zp = __builtin_amdgcn_alignbit(ldw(pw.azp + kPkSpin + O), ldw(pw.azp + O), pz.zs);
+    const uint32_t zpw = __builtin_amdgcn_alignbit(ldw(pw.azpw + kPkSpin + O), ldw(pw.azpw + O), pz.zsw);
     nb[4] = __builtin_amdgcn_bitop3_b32(pw.Zmp, zpw, zp, 0xCA);
-    const uint32_t zm = __builtin_amdgcn_alignbit(ldw(pw.azm + 8 + O), ldw(pw.azm + O), pz.zsm);
-    const uint32_t zmw = __builtin_amdgcn_alignbit(ldw(pw.azmw + 8 + O), ldw(pw.azmw + O), pz.zsmw);
+    const uint32_t zm = __builtin_amdgcn_alignbit(ldw(pw.azm + kPkSpin + O), ldw(pw.azm + O), pz.zsm);
+    const uint32_t zmw = __builtin_amdgcn_alignbit(ldw(pw.azmw + kPkSpin + O), ldw(pw.azmw + O), pz.zsmw);
     nb[5] = __builtin_amdgcn_bitop3_b32(pw.Zmm, zmw, zm, 0xCA);
   }
 }
@@ -155,8 +159,8 @@ __device__ void batch_packed_lattice(unsigned char* lds, const BatchDesc* dp, ui
   const uint32_t T = blockDim.x, q = threadIdx.x;
   const uint32_t Wp = Nh / 32u;
   const uint32_t LR = L * R;  // sites of a z-plane of one colour (a multiple of 32)
-  const uint32_t SB = 0, JB = (8u * (Wp + 2u) + 15u) / 16u * 16u;
-  const uint32_t TQ = JB + (PM ? 48u * Wp : 0u);
+  const uint32_t SB = 0, JB = (kPkSpin * (Wp + 2u) + 15u) / 16u * 16u;
+  const uint32_t TQ = JB + (PM ? (kPkBond * Wp + 15u) / 16u * 16u : 0u);
   uint4* tq_ent = reinterpret_cast<uint4*>(lds + TQ) + q;
   uint16_t* tq_w = reinterpret_cast<uint16_t*>(lds + TQ + 16u * kPackedBatchTieWords * T) + q;
   const RngKey key{key0.k0, key0.k1, replica};
@@ -168,11 +172,11 @@ __device__ void batch_packed_lattice(unsigned char* lds, const BatchDesc* dp, ui
     uint32_t v = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) v |= gather7(src[k]) << (4 * k);
-    *reinterpret_cast<uint32_t*>(lds + SB + 8u * (w + 1u) + 4u * c) = v;
+    *reinterpret_cast<uint32_t*>(lds + SB + kPkSpin * (w + 1u) + 4u * c) = v;
   }
   if (q < 2u) {
     *reinterpret_cast<uint32_t*>(lds + SB + 4u * q) = 0u;
-    *reinterpret_cast<uint32_t*>(lds + SB + 8u * (Wp + 1u) + 4u * q) = 0u;
+    *reinterpret_cast<uint32_t*>(lds + SB + kPkSpin * (Wp + 1u) + 4u * q) = 0u;
   }
   // in-plane index of the -mu neighbour of site (c, j)
   const uint32_t sYw = (L - 1) * R, sZ = L * R, sZw = (L - 1) * L * R;
@@ -199,8 +203,8 @@ __device__ void batch_packed_lattice(unsigned char* lds, const BatchDesc* dp, ui
         uint32_t vm = 0;
         for (uint32_t b = 0; b < 32u; ++b)
           vm |= (Jn[minus_nb(c, 32u * w + b, mu)] < 0 ? 1u : 0u) << b;
-        *reinterpret_cast<uint32_t*>(lds + JB + 48u * w + 4u * (2u * (2u * mu) + c)) = vp;
-        *reinterpret_cast<uint32_t*>(lds + JB + 48u * w + 4u * (2u * (2u * mu + 1u) + c)) = vm;
+        *reinterpret_cast<uint32_t*>(lds + JB + kPkBond * w + 4u * (2u * (2u * mu) + c)) = vp;
+        *reinterpret_cast<uint32_t*>(lds + JB + kPkBond * w + 4u * (2u * (2u * mu + 1u) + c)) = vm;
       }
     }
   }
@@ -242,7 +246,7 @@ __device__ void batch_packed_lattice(unsigned char* lds, const BatchDesc* dp, ui
     // z-plane.
     auto lo = [&](int32_t off) -> uint32_t {  // LDS byte address of the clamped low word
       const int32_t i = (int32_t)wv + (off >> 5);
-      return SB + 8u * (uint32_t)((i < -1 ? -1 : (i > (int32_t)Wp - 1 ? (int32_t)Wp - 1 : i)) + 1);
+      return SB + kPkSpin * (uint32_t)((i < -1 ? -1 : (i > (int32_t)Wp - 1 ? (int32_t)Wp - 1 : i)) + 1);
     };
     const int32_t lr = (int32_t)LR, l = (int32_t)L, rr = (int32_t)R;
     x.ayp = lo(rr - lr);
@@ -251,8 +255,8 @@ __device__ void batch_packed_lattice(unsigned char* lds, const BatchDesc* dp, ui
       const uint32_t zw = LR / 32u;  // words per z-plane
       const uint32_t izp = wv + zw >= Wp ? wv + zw - Wp : wv + zw;
       const uint32_t izm = wv < zw ? wv + Wp - zw : wv - zw;
-      x.azp = SB + 8u * (izp + 1u);
-      x.azm = SB + 8u * (izm + 1u);
+      x.azp = SB + kPkSpin * (izp + 1u);
+      x.azm = SB + kPkSpin * (izm + 1u);
       x.azpw = x.azmw = SB;
     } else {
       x.azp = lo(lr);
@@ -260,8 +264,8 @@ __device__ void batch_packed_lattice(unsigned char* lds, const BatchDesc* dp, ui
       x.azm = lo(-lr);
       x.azmw = lo(lr * (l - 1));
     }
-    x.a0 = SB + 8u * (wv + 1u);
-    x.aj = JB + 48u * wv;
+    x.a0 = SB + kPkSpin * (wv + 1u);
+    x.aj = JB + kPkBond * wv;
   }
   // thresholds of this lattice: the fast decision when only classes k < d can
   // refuse (every class k >= d always accepts)
@@ -284,7 +288,7 @@ __device__ void batch_packed_lattice(unsigned char* lds, const BatchDesc* dp, ui
         const Rand4 rr = philox(32u * w + b, t, replica, tag(c, kIsingRefine), key.k0, key.k1);
         if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) flips |= 1u << b;
       }
-      *reinterpret_cast<uint32_t*>(lds + SB + 8u * (w + 1u) + 4u * c) ^= flips;
+      *reinterpret_cast<uint32_t*>(lds + SB + kPkSpin * (w + 1u) + 4u * c) ^= flips;
     }
     nq = 0;
   };
@@ -346,7 +350,7 @@ __device__ void batch_packed_lattice(unsigned char* lds, const BatchDesc* dp, ui
   // write both planes back as +-1 bytes
   for (uint32_t i = q; i < 2u * Wp; i += T) {
     const uint32_t c = i & 1u, w = i >> 1;
-    const uint32_t v = *reinterpret_cast<const uint32_t*>(lds + SB + 8u * (w + 1u) + 4u * c);
+    const uint32_t v = *reinterpret_cast<const uint32_t*>(lds + SB + kPkSpin * (w + 1u) + 4u * c);
     uint32_t* dst = reinterpret_cast<uint32_t*>(gs + (size_t)c * Nh + 32u * w);
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
