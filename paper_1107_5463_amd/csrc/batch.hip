@@ -54,7 +54,6 @@ constexpr uint32_t kBatchTieSlots = 4;  // deferred ties per lane before a flush
 // chain of its replica bit for bit.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kPackedBatchWordsPerLane = 2;
-constexpr uint32_t kPackedBatchTieWords = 4;
 // LDS strides of a word's spin pair (colour 0, colour 1, unused) and of its
 // twelve bond-sign words (+ one unused): an odd number of dwords, so that 32
 // lanes reading consecutive words touch 32 different banks.
@@ -66,13 +65,16 @@ __host__ __device__ inline bool batch_packed_ok(int d, uint32_t L, uint32_t thre
   return Wp <= kPackedBatchWordsPerLane * threads;
 }
 
-// LDS bytes of the packed path for edge L: interleaved spin words with pads,
-// aligned bond-sign words (+-1 couplings), the per-lane tie queue.
+// LDS bytes of the packed path for edge L: the spin pairs with their pads and
+// the aligned bond-sign words (+-1 couplings).  (A lane's tied words -- at
+// most one per word it owns -- wait in registers until the end of the
+// half-sweep.)
 __host__ __device__ inline size_t batch_packed_lds_bytes(uint32_t L, bool pm, uint32_t threads) {
   const size_t Wp = (size_t)L * L * L / 64;
   const size_t sb = (kPkSpin * (Wp + 2) + 15) / 16 * 16;
   const size_t jb = pm ? (kPkBond * Wp + 15) / 16 * 16 : 0;
-  return sb + jb + (size_t)threads * kPackedBatchTieWords * 20;
+  (void)threads;
+  return sb + jb;
 }
 
 struct PackedWord {  // per-call constants of one word of the lane
@@ -160,9 +162,6 @@ __device__ void batch_packed_lattice(unsigned char* lds, const BatchDesc* dp, ui
   const uint32_t Wp = Nh / 32u;
   const uint32_t LR = L * R;  // sites of a z-plane of one colour (a multiple of 32)
   const uint32_t SB = 0, JB = (kPkSpin * (Wp + 2u) + 15u) / 16u * 16u;
-  const uint32_t TQ = JB + (PM ? (kPkBond * Wp + 15u) / 16u * 16u : 0u);
-  uint4* tq_ent = reinterpret_cast<uint4*>(lds + TQ) + q;
-  uint16_t* tq_w = reinterpret_cast<uint16_t*>(lds + TQ + 16u * kPackedBatchTieWords * T) + q;
   const RngKey key{key0.k0, key0.k1, replica};
 
   // stage the spins: sign bits of 32 int8 sites per word, zero pad words
@@ -275,27 +274,26 @@ __device__ void batch_packed_lattice(unsigned char* lds, const BatchDesc* dp, ui
   FastTab ft = fast_tab<D>(tab);
   __syncthreads();
 
-  uint32_t nq = 0;
-  auto flush = [&](uint32_t c, uint32_t t) {
-    for (uint32_t e = 0; e < nq; ++e) {
-      const uint4 en = tq_ent[e * T];
-      const uint32_t w = tq_w[e * T];
-      uint32_t m = en.x, flips = 0;
-      while (m) {
-        const uint32_t b = __builtin_ctz(m);
-        m &= m - 1;
-        const uint32_t k = ((en.y >> b) & 1u) | (((en.z >> b) & 1u) << 1) | (((en.w >> b) & 1u) << 2);
-        const Rand4 rr = philox(32u * w + b, t, replica, tag(c, kIsingRefine), key.k0, key.k1);
-        if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) flips |= 1u << b;
-      }
-      *reinterpret_cast<uint32_t*>(lds + SB + kPkSpin * (w + 1u) + 4u * c) ^= flips;
+  // a word's exact ties wait in registers (tie mask and count planes) until
+  // the lane's words of the colour are stored, then take their refinement
+  // draws; a lane writes only its own words, so the fix-up is race-free
+  auto resolve = [&](uint32_t c, uint32_t t, uint32_t w, uint32_t a, const uint4& en) {
+    uint32_t m = en.x, flips = 0;
+    while (m) {
+      const uint32_t b = __builtin_ctz(m);
+      m &= m - 1;
+      const uint32_t k = ((en.y >> b) & 1u) | (((en.z >> b) & 1u) << 1) | (((en.w >> b) & 1u) << 2);
+      const Rand4 rr = philox(32u * w + b, t, replica, tag(c, kIsingRefine), key.k0, key.k1);
+      if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) flips |= 1u << b;
     }
-    nq = 0;
+    *reinterpret_cast<uint32_t*>(lds + a + 4u * c) ^= flips;
   };
   auto half = [&](auto cc, uint32_t t) {
     constexpr uint32_t C = decltype(cc)::value;
+    uint4 tie[kPackedBatchWordsPerLane];
 #pragma unroll
     for (uint32_t p = 0; p < kPackedBatchWordsPerLane; ++p) {
+      tie[p] = make_uint4(0u, 0u, 0u, 0u);
       if (!pw[p].valid) continue;
       uint32_t k0, k1, k2;
       const uint32_t o = packed_word_counts<C, PM>(lds, pw[p], R, pz, k0, k1, k2);
@@ -304,12 +302,11 @@ __device__ void batch_packed_lattice(unsigned char* lds, const BatchDesc* dp, ui
       const uint32_t flip = fast ? packed_decide_fast<D>(ft, key, t, C, w, k0, k1, k2, ties)
                                  : packed_decide<D>(tab, key, t, C, w, k0, k1, k2, ties);
       *reinterpret_cast<uint32_t*>(lds + pw[p].a0 + 4u * C) = o ^ flip;
-      tq_ent[nq * T] = make_uint4(ties, k0, k1, k2);
-      tq_w[nq * T] = (uint16_t)w;
-      nq += ties != 0u ? 1u : 0u;
-      if (nq == kPackedBatchTieWords) flush(C, t);
+      tie[p] = make_uint4(ties, k0, k1, k2);
     }
-    flush(C, t);
+#pragma unroll
+    for (uint32_t p = 0; p < kPackedBatchWordsPerLane; ++p)
+      if (tie[p].x) resolve(C, t, q + p * T, pw[p].a0, tie[p]);
     __syncthreads();
   };
   auto measure = [&](uint32_t slot, int64_t sweep) {
