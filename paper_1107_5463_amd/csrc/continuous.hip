@@ -386,12 +386,25 @@ __global__ __launch_bounds__(256) void cont_stream_kernel(
       ldv<V>(oth[m], zoff(zp_row, y0 + 1), Bz[1][m]);
     }
   }
+  // 3D: plane offsets of the rows the loop touches, stepped by R per row (a
+  // row past L - 1 wraps to row 0 of its z-plane) -- row y, y - 1, y + 2,
+  // y + 3, and the z - 1 / z + 1 planes' rows y and y + 2 -- instead of a
+  // multiply per row and stream (in 2D the running offsets cost more
+  // registers than the multiplies cost issue slots)
+  constexpr bool STEP = D == 3;
+  const uint32_t zR = zrow * R, zmR = zm_row * R, zpR = zp_row * R;
+  auto step = [&](uint32_t off, uint32_t yy, uint32_t base) -> uint32_t {
+    return yy + 1 == L ? base : off + R;
+  };
+  uint32_t ry = roff(y0), rym = roff(ym1), ry2 = roff(y0 + 2), ry3 = roff(y0 + 3);
+  uint32_t zm0 = zoff(zm_row, y0) - col, zm2 = zoff(zm_row, y0 + 2) - col;
+  uint32_t zp2 = zoff(zp_row, y0 + 2) - col;
   for (uint32_t i = 0; i < H; i += 4) {
 #pragma unroll
     for (int ph = 0; ph < 4; ++ph) {
       const uint32_t y = y0 + i + ph;  // y0 and i are multiples of 4
       const bool p = ((pz + (uint32_t)ph) & 1u) != 0;
-      const uint32_t rowoff = roff(y);
+      const uint32_t rowoff = STEP ? ry : roff(y);
       const uint32_t jrow = rowoff + col;
       const int up = (ph + 3) & 3, ct = ph, dn = (ph + 1) & 3, b = ph & 1;
       Rand4 rnd[N == 2 ? V / 2 : V];
@@ -423,7 +436,7 @@ __global__ __launch_bounds__(256) void cont_stream_kernel(
         // +y, -y
         if (JK != 0) {
           jp = bond<JK>(J, J0, Nh, 1, c, j);
-          jm = bond<JK>(J, J0, Nh, 1, 1 - c, roff(y + L - 1) + col + k);
+          jm = bond<JK>(J, J0, Nh, 1, 1 - c, (STEP ? rym : roff(y + L - 1)) + col + k);
         }
 #pragma unroll
         for (int m = 0; m < N; ++m) h[m] += jp * Ro[dn][m][k];
@@ -432,7 +445,7 @@ __global__ __launch_bounds__(256) void cont_stream_kernel(
         if (D == 3) {
           if (JK != 0) {
             jp = bond<JK>(J, J0, Nh, 2, c, j);
-            jm = bond<JK>(J, J0, Nh, 2, 1 - c, zoff(zm_row, y) + k);
+            jm = bond<JK>(J, J0, Nh, 2, 1 - c, zm0 + col + k);
           }
 #pragma unroll
           for (int m = 0; m < N; ++m) h[m] += jp * Bz[b][m][k];
@@ -484,8 +497,8 @@ __global__ __launch_bounds__(256) void cont_stream_kernel(
             if (JK != 0) {
               uint32_t im;
               if (mu == 0) im = rowoff + (p ? col + k : (k > 0 ? col + k - 1 : e_prev));
-              else if (mu == 1) im = roff(y + L - 1) + col + k;
-              else im = zoff(zm_row, y) + k;
+              else if (mu == 1) im = (STEP ? rym : roff(y + L - 1)) + col + k;
+              else im = zm0 + col + k;
               if (JK == 1) {
                 const int8_t* Jb = (const int8_t*)J;
                 jp = J0d * Jb[((int64_t)mu * 2 + 1) * Nh + j];
@@ -507,14 +520,22 @@ __global__ __launch_bounds__(256) void cont_stream_kernel(
       // element and z-neighbours (rows past the band are read, never used)
 #pragma unroll
       for (int m = 0; m < N; ++m) {
-        ldv<V>(oth[m], roff(y + 3) + col, Ro[up][m]);
-        ldv<V>(own[m], roff(y + 2) + col, Ow[b][m]);
-        Ed[b][m] = *at(oth[m], roff(y + 2) + (b ? edge_odd : edge_even));
+        const uint32_t r3 = STEP ? ry3 : roff(y + 3), r2 = STEP ? ry2 : roff(y + 2);
+        ldv<V>(oth[m], r3 + col, Ro[up][m]);
+        ldv<V>(own[m], r2 + col, Ow[b][m]);
+        Ed[b][m] = *at(oth[m], r2 + (b ? edge_odd : edge_even));
         if (D == 3) {
-          ldv<V>(oth[m], zoff(zm_row, y + 2), Fz[b][m]);
-          ldv<V>(oth[m], zoff(zp_row, y + 2), Bz[b][m]);
+          ldv<V>(oth[m], zm2 + col, Fz[b][m]);
+          ldv<V>(oth[m], zp2 + col, Bz[b][m]);
         }
       }
+      rym = ry;
+      ry = step(ry, y, zR);
+      ry2 = ry3;
+      ry3 = step(ry3, y + 3, zR);
+      zm0 = step(zm0, y, zmR);
+      zm2 = step(zm2, y + 2, zmR);
+      zp2 = step(zp2, y + 2, zpR);
     }
   }
   }
