@@ -209,13 +209,16 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
   tq.dE = 0;
   tq.dM = 0;
   if (band < nbands) {
-    const uint32_t q = tid - band * W;
+    // the band's index arithmetic in 24-bit multiplies (full rate): every
+    // factor is below 2^24 -- a plane has at most 2^24 rows (packed_supported)
+    auto mul = [](uint32_t a, uint32_t b) -> uint32_t { return __umul24(a, b); };
+    const uint32_t q = tid - mul(band, W);
     const uint32_t L = (uint32_t)g.L;
-    const uint32_t r0 = band * H;
+    const uint32_t r0 = mul(band, H);
     uint32_t z = 0, y0 = r0;
     if (D == 3) {
       z = fdiv(r0, divL);
-      y0 = r0 - z * L;
+      y0 = r0 - mul(z, L);
     }
     const uint32_t* oth = s + (uint64_t)(1 - c) * Wh;
     // word w of a plane at a 32-bit byte offset from the plane's (uniform)
@@ -223,26 +226,26 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
     auto ldw = [](const uint32_t* base, uint32_t w) -> uint32_t {
       return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(base) + (w << 2));
     };
-    const uint32_t zrow = L * z;
+    const uint32_t zrow = mul(L, z);
     const uint32_t qn = q + 1 == W ? 0u : q + 1, qp = q == 0 ? W - 1 : q - 1;
     auto rw = [&](uint32_t zr, uint32_t y) -> uint32_t {  // word index of (row, q); y < 2L
-      return (zr + (y >= L ? y - L : y)) * W;
+      return mul(zr + (y >= L ? y - L : y), W);
     };
     uint32_t zm_row = 0, zp_row = 0;
     if (D == 3) {
-      zm_row = L * (z == 0 ? L - 1 : z - 1);
-      zp_row = L * (z + 1 == L ? 0 : z + 1);
+      zm_row = mul(L, z == 0 ? L - 1 : z - 1);
+      zp_row = mul(L, z + 1 == L ? 0 : z + 1);
     }
     tq.base = rw(zrow, y0) + q;
     // J planes: J[mu][cc] at (2 mu + cc) * Wh
     const uint32_t pz = (c + z) & 1u;
     // a band stays inside its z-plane (H divides L): the rows' word offsets
     // step by W, and only the y + 1 neighbour of row L - 1 wraps (to row 0)
-    const uint32_t row0 = rw(zrow, y0), wrap0 = zrow * W;
+    const uint32_t row0 = rw(zrow, y0), wrap0 = mul(zrow, W);
     uint32_t up = ldw(oth, rw(zrow, y0 + L - 1) + q);
     uint32_t ct = ldw(oth, row0 + q);
     uint32_t rowb = row0;
-    uint32_t zmb = (zm_row + y0) * W, zpb = (zp_row + y0) * W;  // z - 1 and z + 1 rows (3D)
+    uint32_t zmb = mul(zm_row + y0, W), zpb = mul(zp_row + y0, W);  // z - 1 and z + 1 rows (3D)
     for (uint32_t i = 0; i < H; ++i, rowb += W, zmb += W, zpb += W) {
       const uint32_t y = y0 + i;
       const uint32_t p = (pz + y) & 1u;
@@ -332,7 +335,8 @@ uint32_t packed_rows_per_band(const Geom& g, uint32_t min_waves) {
 }
 
 bool packed_supported(const Geom& g, int J_kind) {
-  return (g.d == 2 || g.d == 3) && J_kind != 2 && g.L % 64 == 0;
+  // at most 2^24 rows per plane: the kernel's index products are 24-bit
+  return (g.d == 2 || g.d == 3) && J_kind != 2 && g.L % 64 == 0 && g.rows <= ((int64_t)1 << 24);
 }
 
 hipError_t launch_packed_half_sweep(const IsingLaunch& a, uint32_t* spins, const uint32_t* J,

@@ -135,7 +135,10 @@ bool params_ok(const smc_params* p, std::string& why) {
   if (p->flags & SMC_FLAG_PACKED) {
     if (p->n != 1) { why = "packed spins are Ising only (n = 1)"; return false; }
     if (p->J_kind == SMC_J_FP32) { why = "packed spins take uniform or +-1 couplings"; return false; }
-    if (p->L % 64) { why = "packed spins need L % 64 == 0"; return false; }
+    if (!packed_supported(make_geom(p), p->J_kind)) {
+      why = "packed spins need L % 64 == 0 and at most 2^24 rows of L sites per colour plane";
+      return false;
+    }
   }
   return true;
 }
