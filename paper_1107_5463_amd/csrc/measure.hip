@@ -151,14 +151,28 @@ __global__ __launch_bounds__(256) void finish_kernel(const Partial* __restrict__
                                                      const int int_couplings, const double J0,
                                                      const int64_t sweep,
                                                      ObsOut* __restrict__ obs) {
-  Partial v{0, 0, 0.0, {0.0, 0.0, 0.0}};
-  for (int64_t b = threadIdx.x; b < nparts; b += 256) {
-    const Partial p = parts[b];
-    v.Ei += p.Ei;
-    v.Mi += p.Mi;
-    v.E += p.E;
-    for (int k = 0; k < 3; ++k) v.M[k] += p.M[k];
+  // four independent running sums per thread (partials b, b + 256, b + 512,
+  // b + 768 of each stride of 1024), so four loads are in flight instead of
+  // one; they are combined in a fixed order, so the result stays deterministic
+  auto add = [](Partial& a, const Partial& p) {
+    a.Ei += p.Ei;
+    a.Mi += p.Mi;
+    a.E += p.E;
+    for (int k = 0; k < 3; ++k) a.M[k] += p.M[k];
+  };
+  Partial acc[4];
+  for (int u = 0; u < 4; ++u) acc[u] = Partial{0, 0, 0.0, {0.0, 0.0, 0.0}};
+  int64_t b = threadIdx.x;
+  for (; b + 768 < nparts; b += 1024) {
+    Partial p[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) p[u] = parts[b + 256 * u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) add(acc[u], p[u]);
   }
+  for (; b < nparts; b += 256) add(acc[0], parts[b]);
+  Partial v = acc[0];
+  for (int u = 1; u < 4; ++u) add(v, acc[u]);
   __shared__ Partial sh[256];
   sh[threadIdx.x] = v;
   __syncthreads();

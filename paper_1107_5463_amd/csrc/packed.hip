@@ -48,6 +48,9 @@ struct PackedTies {
   uint8_t* rows;    // rows[slot * stride]: row in the band
   uint32_t stride, n, base, W;  // base: word index of the lane's column in row 0
   int64_t dE, dM;
+  // wave resolution of a measured launch: flipped tied sites, their k0 and
+  // k1 bits, and how many of them held s = -1 (k2 = 0 at every tied site)
+  uint32_t tf, tk0, tk1, tset;
 };
 
 // Class k of tied site b of a queued word.
@@ -159,10 +162,11 @@ __device__ __forceinline__ void packed_tie_flush_wave(PackedTies& q, const TabRe
       if (en.x) {  // the lane's own word, stored earlier by this lane
         const uint32_t word = own[en.w];
         own[en.w] = word ^ en.x;
-        if (MEASURE) {
-          const int64_t nf = popc(en.x);
-          q.dE += 4 * (D * nf - popc(en.x & en.y) - 2 * (int64_t)popc(en.x & en.z));
-          q.dM -= 2 * (nf - 2 * (int64_t)popc(en.x & word));  // a set bit is s = -1
+        if (MEASURE) {  // counts, widened once at the end of the band
+          q.tf += popc(en.x);
+          q.tk0 += popc(en.x & en.y);
+          q.tk1 += popc(en.x & en.z);
+          q.tset += popc(en.x & word);  // a set bit is s = -1
         }
       }
     }
@@ -193,6 +197,10 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
   const uint32_t tid = xcd_remap(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
   const uint32_t band = fdiv(tid, divW);
   int64_t Esum = 0, Msum = 0;
+  // measured launches: per-lane 32-bit counts (v_bcnt_u32_b32 adds its
+  // popcount to an accumulator), widened once per band -- unsatisfied bonds
+  // by weight 1, 2, 4 of the count planes, set spin bits, words measured
+  uint32_t cn0 = 0, cn1 = 0, cn2 = 0, cset = 0, cwords = 0;
   const uint32_t W = divW.d;
   const uint32_t Wh = (uint32_t)(g.Nh / 32);  // words per plane
   uint32_t* own = s + (uint64_t)c * Wh;
@@ -208,6 +216,7 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
   tq.W = W;
   tq.dE = 0;
   tq.dM = 0;
+  tq.tf = tq.tk0 = tq.tk1 = tq.tset = 0;
   if (band < nbands) {
     // the band's index arithmetic in 24-bit multiplies (full rate): every
     // factor is below 2^24 -- a plane has at most 2^24 rows (packed_supported)
@@ -300,9 +309,11 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
         for (int m = 0; m < 2 * D; ++m) v[m] = u[m] ^ fl;
         uint32_t n0, n1, n2;
         count_planes<D>(v, n0, n1, n2);
-        const int32_t ksum = popc(n0) + 2 * popc(n1) + 4 * popc(n2);
-        Esum += -(int64_t)(32 * 2 * D) + 2 * (int64_t)ksum;
-        Msum += (32 - 2 * popc(on)) + (32 - 2 * popc(ct));
+        cn0 += popc(n0);
+        cn1 += popc(n1);
+        cn2 += popc(n2);
+        cset += popc(on) + popc(ct);
+        ++cwords;
       }
       up = ct;
       ct = dn;
@@ -315,8 +326,14 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
   else
     packed_tie_flush<D, MEASURE>(tq, tab, key, t, c, own);
   if (MEASURE) {
-    Esum += tq.dE;
-    Msum += tq.dM;
+    // each measured word: 32 colour-1 sites with 2d bonds (E = -2d per site
+    // plus 2 per unsatisfied bond) and the 32 + 32 sites of both colours' words
+    // each flipped tied site with k unsatisfied bonds raises E by 4 (d - k)
+    // and moves M by -2 s
+    const int64_t tk = (int64_t)tq.tk0 + 2 * (int64_t)tq.tk1;
+    Esum = -(int64_t)(64 * D) * cwords + 2 * ((int64_t)cn0 + 2 * (int64_t)cn1 + 4 * (int64_t)cn2) +
+           tq.dE + 4 * ((int64_t)D * tq.tf - tk);
+    Msum = (int64_t)64 * cwords - 2 * (int64_t)cset + tq.dM - 2 * ((int64_t)tq.tf - 2 * (int64_t)tq.tset);
     block_partial_int(Esum, Msum, parts, blockIdx.x);
   }
 }
