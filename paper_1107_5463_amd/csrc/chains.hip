@@ -91,7 +91,7 @@ __global__ __launch_bounds__(1024) void chains_kernel(const ChainsLaunch a, int8
   int8_t* lat = reinterpret_cast<int8_t*>(smem + kRed * sizeof(double) + (size_t)nb * kAcc +
                                           (JL ? (size_t)nb * 4 : 0));
   const float* J = JL ? Jl : a.J;
-  const float beta = a.beta;
+  const float bl2e = beta_log2e(a.beta);
 
   for (uint32_t w = threadIdx.x; w < N / 4; w += blockDim.x)
     reinterpret_cast<uint32_t*>(lat)[w] = reinterpret_cast<const uint32_t*>(gs)[w];
@@ -129,7 +129,7 @@ __global__ __launch_bounds__(1024) void chains_kernel(const ChainsLaunch a, int8
             h += jm * (float)oth[nb[2 * mu + 1]];
           }
           const float dE = 2.0f * (float)si * h;
-          const bool accept = dE <= 0.0f || u01f(word_of(r.w, j & 3u)) < expf(-beta * dE);
+          const bool accept = metropolis_fp32(dE, u01f(word_of(r.w, j & 3u)), bl2e);
           if (accept) own[j] = (int8_t)(-si);
           if (MODE != 2 && c == 1) {
             // the sweep's configuration is final at this colour-1 site: the
@@ -239,7 +239,7 @@ __device__ __forceinline__ uint32_t swap_pair_lanes(uint32_t v) {
 // s_i ^ s_j = -2 per unsatisfied bond, so sum x_b = samples + that sum.
 // Same decisions as chains_kernel: local field summed in FP32 over +x, -x,
 // +y, -y, +z, -z (the terms are exact sign flips of J), dE = 2 s h, accept
-// iff dE <= 0 or u < expf(-beta dE).
+// iff dE <= 0 or u < exp(-beta dE) (metropolis_fp32).
 // MODE 0: sample (bond sums), 1: covariance replay, 2: sweeps only (with
 // only_colour >= 0 and one sweep: that colour's half of sweep t0 alone).
 template <int D, int MODE>
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(1024) void chains_pair_kernel(const ChainsLaunch a,
   int8_t* gs = spins + (uint64_t)chain * N;
   double* red = reinterpret_cast<double*>(smem);
   int8_t* lat = reinterpret_cast<int8_t*>(smem + kRed * sizeof(double));
-  const float beta = a.beta;
+  const float bl2e = beta_log2e(a.beta);
 
   for (uint32_t w = q; w < N / 4; w += blockDim.x)
     reinterpret_cast<uint32_t*>(lat)[w] = reinterpret_cast<const uint32_t*>(gs)[w];
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(1024) void chains_pair_kernel(const ChainsLaunch a,
         for (int m = 1; m < B; ++m) h += signed_by(Jv[c][b][m], nv[m]);
         const int si = sv[c][b];
         const float dE = 2.0f * signed_by(h, si);
-        const bool accept = dE <= 0.0f || u01f(wd[c][b]) < expf(-beta * dE);
+        const bool accept = metropolis_fp32(dE, u01f(wd[c][b]), bl2e);
         const int sn = accept ? -si : si;
         sv[c][b] = sn;
         if (active && accept) lat[c * NhU + 2 * q + b] = (int8_t)sn;

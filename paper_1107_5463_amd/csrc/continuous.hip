@@ -16,22 +16,12 @@
 
 namespace smc {
 
-// Metropolis acceptance of a continuous-spin move (Eq. (2)): dE <= 0, or
-// u_acc < exp(-beta dE).  The accurate path takes exp(-beta dE) as
-// 2^(-b dE) with b = beta log2(e) rounded once from FP64 (`beta_log2e`) and
-// the hardware base-2 exponential: the argument carries two FP32 roundings
-// (relative 2^-23) and the exponential about one ulp, so p is off by less
-// than p (x ln2 2^-23 + 2^-23) <= 2e-7 -- below the FP32 rounding of dE
-// itself for the fields of these models.  Both sides are evaluated and or-ed,
-// with no branch.
+// Metropolis acceptance of a continuous-spin move (Eq. (2)): the accurate
+// path is metropolis_fp32; fast math takes the library's __expf.
 template <bool FAST>
 __device__ __forceinline__ bool cont_accept(float dE, uint32_t wacc, float beta, float bl2e) {
-  const float p = FAST ? __expf(-beta * dE) : __builtin_amdgcn_exp2f(-bl2e * dE);
-  return (dE <= 0.0f) | (u01f(wacc) < p);
-}
-
-__device__ __forceinline__ float beta_log2e(float beta) {
-  return (float)((double)beta * 1.44269504088896340736);
+  if (FAST) return (dE <= 0.0f) | (u01f(wacc) < __expf(-beta * dE));
+  return metropolis_fp32(dE, u01f(wacc), bl2e);
 }
 template <bool FAST>
 __device__ __forceinline__ void sincos_f(float x, float* s, float* c) {

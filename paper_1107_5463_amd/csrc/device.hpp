@@ -65,6 +65,20 @@ __device__ __forceinline__ double u01d(uint32_t w) {
   return (double)((w >> 9) * 2u + 1u) * 5.9604644775390625e-8;
 }
 
+// Metropolis acceptance of a move with an FP32 energy change (Eq. (2)):
+// dE <= 0, or u < exp(-beta dE).  exp(-beta dE) is taken as 2^(-b dE) with
+// b = beta log2(e) rounded once from FP64 (`beta_log2e`) and the hardware
+// base-2 exponential: the argument carries two FP32 roundings (relative
+// 2^-23) and the exponential about one ulp, so p is off by less than
+// p (x ln2 2^-23 + 2^-23) <= 2e-7 -- below the FP32 rounding of dE itself.
+// Both sides are evaluated and or-ed, with no branch.
+__device__ __forceinline__ float beta_log2e(float beta) {
+  return (float)((double)beta * 1.44269504088896340736);
+}
+__device__ __forceinline__ bool metropolis_fp32(float dE, float u, float bl2e) {
+  return (dE <= 0.0f) | (u < __builtin_amdgcn_exp2f(-bl2e * dE));
+}
+
 // ---------------------------------------------------------------------------
 // Geometry of the colour-split layout.  Site i = x + L*y + L*L*z has colour
 // c = (x+y+z)&1 and index j = i>>1 in plane c.  Plane rows: row r = y + L*z

@@ -89,7 +89,7 @@ __global__ __launch_bounds__(256) void ising_site_kernel(const Geom g, const Rng
     } else {
       const Rand4 r = philox((uint32_t)(j >> 2), t, key.replica, tag(c, kContinuous), key.k0,
                              key.k1);
-      accept = u01f(pick4(r, (uint32_t)j & 3u)) < expf(-beta * dE);
+      accept = metropolis_fp32(dE, u01f(pick4(r, (uint32_t)j & 3u)), beta_log2e(beta));
     }
   } else {
     const uint32_t k = (uint32_t)kunsat;
