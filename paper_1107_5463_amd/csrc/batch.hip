@@ -200,6 +200,7 @@ __device__ void batch_packed_lattice(unsigned char* lds, const BatchDesc* dp, ui
         // -mu bond: the +mu bond of the -mu neighbour, J[mu][1 - c][nb]
         const int8_t* Jn = gJ + (size_t)(2 * mu + 1 - c) * Nh;
         uint32_t vm = 0;
+#pragma unroll 1  // set-up only: unrolled, it raised the kernel's registers into spills
         for (uint32_t b = 0; b < 32u; ++b)
           vm |= (Jn[minus_nb(c, 32u * w + b, mu)] < 0 ? 1u : 0u) << b;
         *reinterpret_cast<uint32_t*>(lds + JB + kPkBond * w + 4u * (2u * (2u * mu) + c)) = vp;
@@ -224,6 +225,7 @@ __device__ void batch_packed_lattice(unsigned char* lds, const BatchDesc* dp, ui
     x.valid = w < Wp;
     const uint32_t wv = x.valid ? w : 0u;
     x.E = x.S = x.Pm0 = x.Ymp = x.Ymm = x.Zmp = x.Zmm = 0;
+#pragma unroll 1  // as above
     for (uint32_t b = 0; b < 32u; ++b) {
       const uint32_t j = 32u * wv + b;
       const uint32_t r = j / R, jx = j - r * R;
