@@ -243,3 +243,27 @@ def test_packed_batch_matches_oracle(smc_gpu, oracle_mod, J0, betas):
         assert np.array_equal(got, ref.s), (r, L[r], beta[r])
         o = ref.measure()
         assert (recs[r].E_int, recs[r].M_int) == (o.E_int, o.M_int), r
+
+
+@pytest.mark.parametrize("threads", [512, 1024])
+def test_packed_batch_largest_lattices(smc_gpu, oracle_mod, threads):
+    """The largest lattices the packed path takes, L = 36 (split z-plane
+    words) and L = 40 (1000 words a colour: two per lane at 512 lanes, the
+    last lane's second word past the plane), beside one L = 4, against the
+    oracle at beta_c-like and low temperatures."""
+    import torch
+    L = [40, 36, 4]
+    beta = [0.25, 0.9, 0.4]
+    b = smc_gpu.Batch(3, L, beta, seed=83)
+    b.threads = threads
+    assert all(b.packed(r) for r in range(len(L)))
+    obs = torch.zeros((len(L), 8), dtype=torch.int64, device=b.device)
+    b.sweep(4, obs)
+    recs = smc_gpu.Lattice.decode_obs(obs)
+    for r in range(len(L)):
+        ref = oracle_mod.OracleLattice(3, 1, L[r], 83, J_kind=1, replica=r)
+        ref.sweep(beta[r], 4)
+        got = layout.to_natural(b.spins_of(r).cpu().numpy(), 3, L[r])
+        assert np.array_equal(got, ref.s), (r, L[r], beta[r])
+        o = ref.measure()
+        assert (recs[r].E_int, recs[r].M_int) == (o.E_int, o.M_int), r
