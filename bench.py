@@ -68,7 +68,8 @@ KERNEL_SOURCES = {
     "ising_fused": ["fused.hip", "chunk.hpp", "device.hpp", "launch_args.hpp", "reduce.hpp"],
     "ising_packed": ["packed.hip", "packed.hpp", "chunk.hpp", "device.hpp", "launch_args.hpp",
                      "reduce.hpp"],
-    "ising_tiles": ["tiles.hip", "chunk.hpp", "device.hpp", "launch_args.hpp"],
+    "ising_tiles": ["tiles.hip", "packed.hpp", "chunk.hpp", "device.hpp", "launch_args.hpp"],
+    "ising_tiles_packed": ["tiles.hip", "packed.hpp", "chunk.hpp", "device.hpp", "launch_args.hpp"],
     "xy_stream": ["continuous.hip", "chunk.hpp", "device.hpp", "launch_args.hpp"],
     "heisenberg_stream": ["continuous.hip", "chunk.hpp", "device.hpp", "launch_args.hpp"],
     "batch": ["batch.hip", "packed.hpp", "chunk.hpp", "device.hpp", "launch_args.hpp", "reduce.hpp"],
@@ -232,7 +233,7 @@ def timed_steps(lat, beta, K, W, S, torch):
 
 def kernel_model(kname, n, N, sweeps, tile, hits):
     """(launches, algorithmic HBM bytes per launch, schedule) of the dominant kernel."""
-    if kname == "ising_tiles":
+    if kname in ("ising_tiles", "ising_tiles_packed"):
         # one launch per tile colour: its half of both planes read and written once
         return 2 * sweeps, 1.0 * N, f"tiled k-hit, T={tile}, k={hits}"
     if kname == "ising_packed":
@@ -333,9 +334,9 @@ def run_lattice(args, wl, torch, smc):
     # the step time also holds the measurement finish (and renormalisation)
     # kernels: a conservative average of the dominant kernel
     kernel_ms = total_ms / launches
-    if kname in ("ising_packed", "ising_tiles"):
+    if kname in ("ising_packed", "ising_tiles", "ising_tiles_packed"):
         variant = None
-        if kname == "ising_tiles":
+        if kname in ("ising_tiles", "ising_tiles_packed"):
             variant = f"T={args.tile} k={args.hits} {'heat bath' if args.heatbath else 'Metropolis'}"
         roof = valu_roofline(kname, args.workload, kernel_ms, bytes_per_launch,
                              attempts / launches, variant)

@@ -145,6 +145,7 @@ size_t tile_lds_bytes(int d, uint32_t T);
 bool tile_supported(const Geom& g, uint32_t T);
 hipError_t tile_allow_lds(int d, size_t bytes);
 hipError_t launch_tile_pass(const IsingLaunch& a, bool heatbath, uint32_t T, uint32_t hits,
-                            int8_t* spins, uint32_t t, uint32_t tc, hipStream_t st);
+                            int8_t* spins, uint32_t t, uint32_t tc, hipStream_t st, bool packed);
+bool tile_packed_supported(const Geom& g, uint32_t T, bool heatbath);
 
 }  // namespace smc

@@ -108,12 +108,14 @@ __device__ __forceinline__ FastTab fast_tab(const TabRegs& tab) {
 }
 
 // The 32 prefix bytes of a word's sites as bit planes B[0..7] (bit b of each
-// site's byte), from the word's two Philox blocks.
+// site's byte), from the word's two Philox blocks (hit h of the tiled
+// schedule: h in bits 8.. of the counter's last word).
 __device__ __forceinline__ void word_prefix(const RngKey& key, uint32_t t, uint32_t c, uint32_t wi,
-                                            uint32_t B[8]) {
+                                            uint32_t B[8], uint32_t hit = 0) {
   const uint32_t blk = wi * 2u;  // Philox blocks of sites 32 wi .. 32 wi + 31
-  const Rand4 ra = philox(blk, t, key.replica, tag(c, kIsingPrefix), key.k0, key.k1);
-  const Rand4 rb = philox(blk + 1u, t, key.replica, tag(c, kIsingPrefix), key.k0, key.k1);
+  const uint32_t tg = tag(c, kIsingPrefix) | (hit << 8);
+  const Rand4 ra = philox(blk, t, key.replica, tg, key.k0, key.k1);
+  const Rand4 rb = philox(blk + 1u, t, key.replica, tg, key.k0, key.k1);
   const uint32_t P[8] = {ra.w[0], ra.w[1], ra.w[2], ra.w[3], rb.w[0], rb.w[1], rb.w[2], rb.w[3]};
   prefix_planes(P, B);
 }
@@ -129,9 +131,9 @@ template <int D>
 __device__ __forceinline__ uint32_t packed_decide_fast(const FastTab& ft, const RngKey& key,
                                                        uint32_t t, uint32_t c, uint32_t wi,
                                                        uint32_t k0, uint32_t k1, uint32_t k2,
-                                                       uint32_t& ties) {
+                                                       uint32_t& ties, uint32_t hit = 0) {
   uint32_t B[8];
-  word_prefix(key, t, c, wi, B);
+  word_prefix(key, t, c, wi, B, hit);
   // v_bitop3 truth tables (operands a, b, c): 0xCA = a ? b : c;
   // 0x8E = (~a & b) | (~(a ^ b) & c), the borrow of a - b into c;
   // 0x82 = c & ~(a ^ b)
@@ -156,9 +158,9 @@ template <int D>
 __device__ __forceinline__ uint32_t packed_decide(const TabRegs& tab, const RngKey& key,
                                                   uint32_t t, uint32_t c, uint32_t wi,
                                                   uint32_t k0, uint32_t k1, uint32_t k2,
-                                                  uint32_t& ties) {
+                                                  uint32_t& ties, uint32_t hit = 0) {
   uint32_t B[8];
-  word_prefix(key, t, c, wi, B);
+  word_prefix(key, t, c, wi, B, hit);
   // Per-site threshold bit planes: T[b] holds bit b of the threshold byte of
   // each site's class, then one bit-sliced compare of the prefix planes
   // against them.  With J0 > 0 only the classes k < d (Delta E = 4 J0 (d - k)

@@ -61,6 +61,7 @@ struct smc_lattice {
   uint32_t fused_rows;       // fused kernel band height (SMC_FUSED_ROWS overrides)
   uint32_t packed_rows;      // packed kernel band height (SMC_PACKED_ROWS overrides)
   int packed_ties;           // packed kernel ties: 0 by the wave, 1 by each lane (SMC_PACKED_TIES)
+  bool tile_packed;          // tiled schedule: bit-packed tiles where they apply (SMC_TILE_KERNEL=byte: off)
   int cont_variant;          // ContVariant (SMC_CONT_KERNEL overrides the automatic choice)
   uint32_t cont_rows;        // continuous streaming band height (SMC_CONT_ROWS overrides)
   uint32_t cont_spl;         // continuous streaming sites per lane (SMC_CONT_SPL overrides)
@@ -439,7 +440,8 @@ int tiled_sweeps(smc_lattice* h, double beta, int64_t n_sweeps, void* dev_obs) {
   for (int64_t k = 0; k < n_sweeps; ++k) {
     for (uint32_t tc = 0; tc < 2; ++tc) {
       const int rc = check(launch_tile_pass(a, hb, (uint32_t)h->p.tile, (uint32_t)h->p.hits,
-                                            (int8_t*)h->spins, (uint32_t)h->t, tc, h->stream),
+                                            (int8_t*)h->spins, (uint32_t)h->t, tc, h->stream,
+                                            h->tile_packed),
                            "tile pass launch");
       if (rc != SMC_OK) return rc;
     }
@@ -753,6 +755,8 @@ int smc_init_lattice(smc_lattice** out, const smc_params* p, void* spins, void* 
   }
   h->packed_rows = packed_rows_per_band(h->g, 8192);
   h->packed_ties = 0;
+  h->tile_packed = true;
+  if (const char* v = std::getenv("SMC_TILE_KERNEL")) h->tile_packed = std::string(v) != "byte";
   if (const char* v = std::getenv("SMC_PACKED_TIES")) {
     const std::string s(v);
     if (s == "lane") h->packed_ties = 1;
@@ -995,7 +999,9 @@ const char* smc_kernel_name(const smc_lattice* h, uint32_t* rows_per_band) {
   }
   if (h->p.tile > 0) {
     if (rows_per_band) *rows_per_band = (uint32_t)h->p.tile;
-    return "ising_tiles";
+    const bool hb = (h->p.flags & SMC_FLAG_HEATBATH) != 0;
+    return h->tile_packed && tile_packed_supported(h->g, (uint32_t)h->p.tile, hb) ? "ising_tiles_packed"
+                                                                                : "ising_tiles";
   }
   if (h->use_fused) {
     if (rows_per_band) *rows_per_band = h->fused_rows;

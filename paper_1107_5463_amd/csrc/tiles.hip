@@ -20,6 +20,7 @@
 // k the unsatisfied bonds), with the same prefix-byte / 24-bit refinement
 // draw as the Metropolis rule.
 #include "chunk.hpp"
+#include "packed.hpp"
 
 namespace smc {
 
@@ -388,6 +389,138 @@ __global__ __launch_bounds__(256) void tile16_kernel(const Geom g, const RngKey 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Bit-packed tiles (2D, T % 64 == 0, Metropolis, uniform couplings): a tile
+// and its boundary layer sit in LDS at one bit per site.  Per colour, LDS row
+// r (0 .. T + 1; rows 0 and T + 1 are the boundary rows) holds the T / 64
+// words of the tile row's T / 2 same-colour sites (site 32 i + b of the row
+// in bit b of word i, bit 1 = spin -1), framed by a word with the site before
+// the row in bit 31 and one with the site after it in bit 0, so the in-row
+// neighbours are funnel shifts, as in the packed streaming kernel.  A lane
+// owns one word of a tile row of each colour for all k hits and decides its
+// 32 sites with that kernel's bit-sliced decision, drawing the same prefix
+// bytes (the hit in the counter); exact ties take their refinement draws at
+// once.  Every site makes the int8 tile kernel's decision, so the chain is
+// the same bit for bit.  T = 64 (a tile is one wave, four to a workgroup) or
+// T = 128 (a tile is one 256-lane workgroup).
+// ---------------------------------------------------------------------------
+template <bool FAST>
+__global__ __launch_bounds__(256) void tile_packed_kernel(const Geom g, const RngKey key,
+                                                          const IsingTable table, const uint32_t T,
+                                                          const uint32_t hits, const uint32_t t,
+                                                          const uint32_t tc, const uint32_t ntiles,
+                                                          int8_t* __restrict__ s) {
+  extern __shared__ __align__(16) int8_t lds_raw[];
+  const uint32_t L = (uint32_t)g.L, R = (uint32_t)g.R;
+  const uint32_t WT = T / 64;            // tile words per row and colour
+  const uint32_t RW = WT + 2;            // LDS words per row: frame, tile words, frame
+  const uint32_t TR = T + 2;             // rows with the boundary rows
+  const uint32_t PL = TR * RW;           // LDS words per colour
+  const uint32_t items = T * WT;         // words a colour of one tile
+  const uint32_t G = blockDim.x / items; // tiles of the workgroup (>= 1)
+  const uint32_t gi = threadIdx.x / items, li = threadIdx.x - gi * items;
+  const uint32_t bt = blockIdx.x * G + gi;  // tile of this lane among the colour's tiles
+  const bool valid = bt < ntiles;
+  uint32_t* lw = reinterpret_cast<uint32_t*>(lds_raw) + gi * 2u * PL;
+  const uint32_t nt = L / T, half = nt / 2;
+  const uint32_t bv = valid ? bt : 0u;
+  const uint32_t ty = bv / half;
+  const uint32_t tx = 2 * (bv - ty * half) + ((ty + tc) & 1u);
+  const uint32_t X0 = tx * T, Y0 = ty * T;
+  const uint32_t xw0 = X0 / 2;           // in-row index of the tile row's first site
+  const uint64_t Nh = (uint64_t)g.Nh;
+  auto prow = [&](uint32_t r) -> uint32_t { return (Y0 + L - 1 + r) % L; };  // plane row of LDS row r
+
+  // stage: the tile words of every row (boundary rows included) and the frames
+  if (valid) {
+    for (uint32_t it = li; it < 2u * PL; it += items) {
+      const uint32_t cc = it / PL, rest = it - cc * PL;
+      const uint32_t r = rest / RW, i = rest - r * RW;
+      const int8_t* src = s + cc * Nh + (uint64_t)prow(r) * R;
+      uint32_t v = 0;
+      if (i == 0) {
+        v = src[xw0 == 0 ? R - 1 : xw0 - 1] < 0 ? 0x80000000u : 0u;
+      } else if (i == RW - 1) {
+        const uint32_t xr = xw0 + T / 2;
+        v = src[xr == R ? 0 : xr] < 0 ? 1u : 0u;
+      } else {
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(src + xw0 + 32u * (i - 1));
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v |= gather7(q[k]) << (4 * k);
+      }
+      lw[it] = v;
+    }
+  }
+  __syncthreads();
+
+  const TabRegs tab = tab_regs(table);
+  FastTab ft;
+  if (FAST) ft = fast_tab<2>(tab);
+  const uint32_t ry = 1 + li / WT, i = 1 + li % WT;  // the lane's LDS row and word
+  const uint32_t y = Y0 + ry - 1;
+  const uint32_t rb = ry * RW + i;
+  const uint32_t wi = (y * R + xw0) / 32u + (i - 1);  // global word index (R % 32 == 0)
+  for (uint32_t h = 0; h < hits; ++h) {
+#pragma unroll
+    for (uint32_t c = 0; c < 2; ++c) {
+      if (valid) {
+        uint32_t* own = lw + c * PL;
+        const uint32_t* oth = lw + (1 - c) * PL;
+        const uint32_t p = (c + y) & 1u;
+        const uint32_t o = own[rb], ct = oth[rb], en = oth[rb + 1], ep = oth[rb - 1];
+        const uint32_t up = oth[rb - RW], dn = oth[rb + RW];
+        // x + 1 neighbours (p = 1: next in-row site) and x - 1 (p = 0: previous)
+        const uint32_t sh_next = __builtin_amdgcn_alignbit(en, ct, 1u);
+        const uint32_t sh_prev = __builtin_amdgcn_alignbit(ct, ep, 31u);
+        const uint32_t u[6] = {o ^ mask_sel(ct, sh_next, p), o ^ mask_sel(sh_prev, ct, p), o ^ dn,
+                               o ^ up, 0u, 0u};
+        uint32_t k0, k1, k2, ties;
+        count_planes<2>(u, k0, k1, k2);
+        uint32_t flip = FAST ? packed_decide_fast<2>(ft, key, t, c, wi, k0, k1, k2, ties, h)
+                             : packed_decide<2>(tab, key, t, c, wi, k0, k1, k2, ties, h);
+        while (ties) {  // exact ties: the 24-bit refinement against the class's fraction
+          const uint32_t b = __builtin_ctz(ties);
+          ties &= ties - 1;
+          const uint32_t k = ((k0 >> b) & 1u) | (((k1 >> b) & 1u) << 1) | (((k2 >> b) & 1u) << 2);
+          const Rand4 rr = philox(wi * 32u + b, t, key.replica, tag(c, kIsingRefine) | (h << 8),
+                                  key.k0, key.k1);
+          if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) flip |= 1u << b;
+        }
+        own[rb] = o ^ flip;
+      }
+      __syncthreads();
+    }
+  }
+
+  // write back the tile rows of both colours as +-1 bytes
+  if (valid) {
+    for (uint32_t it = li; it < 2u * items; it += items) {
+      const uint32_t cc = it / items, rest = it - cc * items;
+      const uint32_t r = 1 + rest / WT, w = 1 + rest % WT;
+      const uint32_t v = lw[cc * PL + r * RW + w];
+      uint32_t* dst = reinterpret_cast<uint32_t*>(s + cc * Nh + (uint64_t)(Y0 + r - 1) * R + xw0 +
+                                                  32u * (w - 1));
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint32_t spread = (((v >> (4 * k)) & 0xFu) * 0x00204081u) & kOnes;
+        dst[k] = kOnes | (spread * 0xFEu);
+      }
+    }
+  }
+}
+
+bool tile_packed_supported(const Geom& g, uint32_t T, bool heatbath) {
+  return g.d == 2 && !heatbath && (T == 64 || T == 128) && (uint32_t)g.L % T == 0 &&
+         ((uint32_t)g.L / T) % 2 == 0;
+}
+
+// 256 lanes a workgroup: four tiles of 64 (64 words a colour each) or one of 128
+static uint32_t tile_packed_group(uint32_t T) { return T == 64 ? 4u : 1u; }
+
+static size_t tile_packed_lds_bytes(uint32_t T) {
+  return (size_t)tile_packed_group(T) * 2 * (T + 2) * (T / 64 + 2) * 4;
+}
+
 size_t tile_lds_bytes(int d, uint32_t T) {
   const size_t TR = T + 2;
   if (T == 16) {  // 48-byte rows, 256 / 16^(d-1) tiles per workgroup
@@ -420,11 +553,26 @@ hipError_t tile_allow_lds(int d, size_t bytes) {
   return hipSuccess;
 }
 
-// One tile-colour pass (k hits) of the tiled schedule.
+// One tile-colour pass (k hits) of the tiled schedule; `packed`: the bit-packed
+// kernel where it applies.
 hipError_t launch_tile_pass(const IsingLaunch& a, bool heatbath, uint32_t T, uint32_t hits,
-                            int8_t* spins, uint32_t t, uint32_t tc, hipStream_t st) {
+                            int8_t* spins, uint32_t t, uint32_t tc, hipStream_t st, bool packed) {
   const uint32_t nt = (uint32_t)a.g.L / T;
   const uint32_t tiles = (a.g.d == 3 ? nt * nt * nt : nt * nt) / 2;
+  if (packed && tile_packed_supported(a.g, T, heatbath)) {
+    // the fast decision when every class k >= d always accepts (J0 > 0)
+    bool fast = true;
+    for (int k = a.g.d; k <= 2 * a.g.d; ++k)
+      if ((((k < 4 ? a.tab.al_lo : a.tab.al_hi) >> (8 * (k & 3))) & 0xFFu) != 0xFFu) fast = false;
+    const uint32_t G = tile_packed_group(T);
+    const dim3 grid((tiles + G - 1) / G), block(256);
+    const size_t lds = tile_packed_lds_bytes(T);
+    if (fast)
+      hipLaunchKernelGGL((tile_packed_kernel<true>), grid, block, lds, st, a.g, a.key, a.tab, T, hits, t, tc, tiles, spins);
+    else
+      hipLaunchKernelGGL((tile_packed_kernel<false>), grid, block, lds, st, a.g, a.key, a.tab, T, hits, t, tc, tiles, spins);
+    return hipGetLastError();
+  }
   if (T == 16) {
     const uint32_t G = a.g.d == 3 ? 1 : 16;
     const dim3 grid((tiles + G - 1) / G), block(256);

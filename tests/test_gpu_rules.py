@@ -41,11 +41,16 @@ TILED = [  # d, L, tile, hits, heatbath, beta, sweeps
 ]
 
 
+def _tile_kernel_name(d, T, hb):
+    # 2D Metropolis tiles of 64 or 128 take the bit-packed tile kernel
+    return "ising_tiles_packed" if d == 2 and not hb and T in (64, 128) else "ising_tiles"
+
+
 @pytest.mark.parametrize("d,L,T,k,hb,beta,n", TILED)
 def test_tiled_schedule_matches_oracle(smc_gpu, oracle_mod, d, L, T, k, hb, beta, n):
     print(f"tiles d={d} L={L} T={T} k={k} hb={hb}", flush=True)
     lat = smc_gpu.Lattice(d, 1, L, seed=7, heatbath=hb, tile=T, hits=k)
-    assert lat.kernel() == ("ising_tiles", T)
+    assert lat.kernel() == (_tile_kernel_name(d, T, hb), T)
     ref = oracle_mod.OracleLattice(d, 1, L, 7)
     lat.sweep(beta, n)
     ref.sweep_rule(beta, n, "heatbath" if hb else "metropolis", T, k)
@@ -53,6 +58,47 @@ def test_tiled_schedule_matches_oracle(smc_gpu, oracle_mod, d, L, T, k, hb, beta
     o, r = lat.measure(), ref.measure()
     assert (o.E_int, o.M_int) == (r.E_int, r.M_int)
     assert lat.t == n
+
+
+PACKED_TILES = [  # L, tile, hits, J0, beta, sweeps
+    (128, 64, 3, 1.0, BETA_C, 3),     # two tiles a colour: one workgroup, two of its four tiles idle
+    (384, 64, 2, 1.0, 0.6, 2),        # 18 tiles a colour: the last workgroup half filled
+    (128, 64, 4, 1.0, 2.0, 3),        # low temperature: mostly refusable moves, many exact ties
+    (256, 128, 2, 1.0, BETA_C, 2),    # one 128-tile a workgroup, two words a tile row
+    (128, 64, 3, -1.0, 0.5, 3),       # J0 < 0: the general bit-sliced decision
+]
+
+
+@pytest.mark.parametrize("L,T,k,J0,beta,n", PACKED_TILES)
+def test_packed_tiles_match_oracle(smc_gpu, oracle_mod, L, T, k, J0, beta, n):
+    """The bit-packed tile kernel (2D, Metropolis, T = 64 or 128) against the
+    oracle's tiled schedule, bit for bit, with the measurement after it."""
+    print(f"packed tiles L={L} T={T} k={k} J0={J0} beta={beta}", flush=True)
+    lat = smc_gpu.Lattice(2, 1, L, seed=13, J0=J0, tile=T, hits=k)
+    assert lat.kernel() == ("ising_tiles_packed", T)
+    ref = oracle_mod.OracleLattice(2, 1, L, 13, J0=J0)
+    lat.sweep(beta, n)
+    ref.sweep_rule(beta, n, "metropolis", T, k)
+    assert np.array_equal(nat(lat), ref.s)
+    o, r = lat.measure(), ref.measure()
+    assert (o.E_int, o.M_int) == (r.E_int, r.M_int)
+
+
+@pytest.mark.parametrize("T", [64, 128])
+def test_packed_and_byte_tiles_run_the_same_chain(smc_gpu, monkeypatch, T):
+    """Both tile kernels on a 2D L=1024 lattice, k = 5 hits: the same states."""
+    import torch
+    states = {}
+    for kernel in ("byte", "packed"):
+        if kernel == "byte":
+            monkeypatch.setenv("SMC_TILE_KERNEL", "byte")
+        else:
+            monkeypatch.delenv("SMC_TILE_KERNEL", raising=False)
+        lat = smc_gpu.Lattice(2, 1, 1024, seed=17, tile=T, hits=5)
+        assert lat.kernel()[0] == ("ising_tiles" if kernel == "byte" else "ising_tiles_packed")
+        lat.sweep(BETA_C, 3)
+        states[kernel] = lat.spins.clone()
+    assert torch.equal(states["byte"], states["packed"])
 
 
 def test_tiled_sweep_measure(smc_gpu, oracle_mod):
