@@ -128,12 +128,9 @@ __device__ __forceinline__ void word_prefix(const RngKey& key, uint32_t t, uint3
 // count planes; the compare runs from the least significant bit up,
 // lt = [prefix < threshold] by its borrow, eq = [prefix == threshold].
 template <int D>
-__device__ __forceinline__ uint32_t packed_decide_fast(const FastTab& ft, const RngKey& key,
-                                                       uint32_t t, uint32_t c, uint32_t wi,
-                                                       uint32_t k0, uint32_t k1, uint32_t k2,
-                                                       uint32_t& ties, uint32_t hit = 0) {
-  uint32_t B[8];
-  word_prefix(key, t, c, wi, B, hit);
+__device__ __forceinline__ uint32_t packed_compare_fast(const FastTab& ft, const uint32_t B[8],
+                                                        uint32_t k0, uint32_t k1, uint32_t k2,
+                                                        uint32_t& ties) {
   // v_bitop3 truth tables (operands a, b, c): 0xCA = a ? b : c;
   // 0x8E = (~a & b) | (~(a ^ b) & c), the borrow of a - b into c;
   // 0x82 = c & ~(a ^ b)
@@ -152,15 +149,24 @@ __device__ __forceinline__ uint32_t packed_decide_fast(const FastTab& ft, const 
   return ~(refus & ~lt);  // ties are refused here and resolved by their refinement draws
 }
 
+// The fast decision for the 32 sites of word wi of a plane (prefix bytes from
+// the word's two Philox blocks).
+template <int D>
+__device__ __forceinline__ uint32_t packed_decide_fast(const FastTab& ft, const RngKey& key,
+                                                       uint32_t t, uint32_t c, uint32_t wi,
+                                                       uint32_t k0, uint32_t k1, uint32_t k2,
+                                                       uint32_t& ties, uint32_t hit = 0) {
+  uint32_t B[8];
+  word_prefix(key, t, c, wi, B, hit);
+  return packed_compare_fast<D>(ft, B, k0, k1, k2, ties);
+}
+
 // Decision for the 32 sites of one word from the count planes k0, k1, k2:
 // returns the flip mask, with the exact ties (in `ties`) refused.
 template <int D>
-__device__ __forceinline__ uint32_t packed_decide(const TabRegs& tab, const RngKey& key,
-                                                  uint32_t t, uint32_t c, uint32_t wi,
-                                                  uint32_t k0, uint32_t k1, uint32_t k2,
-                                                  uint32_t& ties, uint32_t hit = 0) {
-  uint32_t B[8];
-  word_prefix(key, t, c, wi, B, hit);
+__device__ __forceinline__ uint32_t packed_compare(const TabRegs& tab, const uint32_t B[8],
+                                                   uint32_t k0, uint32_t k1, uint32_t k2,
+                                                   uint32_t& ties) {
   // Per-site threshold bit planes: T[b] holds bit b of the threshold byte of
   // each site's class, then one bit-sliced compare of the prefix planes
   // against them.  With J0 > 0 only the classes k < d (Delta E = 4 J0 (d - k)
@@ -209,6 +215,17 @@ __device__ __forceinline__ uint32_t packed_decide(const TabRegs& tab, const RngK
   const uint32_t rej = refus & ~lt;  // prefix >= threshold (ties included)
   ties = refus & eq;
   return ~rej;  // ties are refused here; the caller queues them once the word is stored
+}
+
+// The general decision for the 32 sites of word wi of a plane.
+template <int D>
+__device__ __forceinline__ uint32_t packed_decide(const TabRegs& tab, const RngKey& key,
+                                                  uint32_t t, uint32_t c, uint32_t wi,
+                                                  uint32_t k0, uint32_t k1, uint32_t k2,
+                                                  uint32_t& ties, uint32_t hit = 0) {
+  uint32_t B[8];
+  word_prefix(key, t, c, wi, B, hit);
+  return packed_compare<D>(tab, B, k0, k1, k2, ties);
 }
 
 // Unsatisfied-bond count planes of 32 sites from their 2d neighbour words

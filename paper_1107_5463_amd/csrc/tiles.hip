@@ -509,8 +509,147 @@ __global__ __launch_bounds__(256) void tile_packed_kernel(const Geom g, const Rn
   }
 }
 
+// ---------------------------------------------------------------------------
+// Bit-packed 16 x 16 tiles (2D, Metropolis): a tile row holds 8 sites of a
+// colour, so a word packs four tile rows -- word i of a tile's colour holds
+// rows 4i .. 4i + 3 of the tile, site s of row r in bit 8 r + s (bit 1 = spin
+// -1).  Per tile and colour, LDS holds the column [above, w0, w1, w2, w3,
+// below] (the boundary row above the tile in bits 24..31 of `above`, the one
+// below in bits 0..7 of `below`, so the y neighbours of word i are 8-bit
+// funnel shifts of its column) and per word the sites left and right of its
+// rows (bit 8 r and bit 8 r + 7), which complete the in-row neighbours, a
+// shift by one within each byte.  Row r of a word has parity (c + r) & 1
+// (tiles start at even rows), a per-byte mask.  A row's 8 prefix bytes are
+// words 2 h0, 2 h0 + 1 of its 16-site Philox block, as in the int8 16 x 16
+// kernel, so a word takes four blocks; the transpose to bit planes and the
+// compare are the packed kernel's.  Exact ties take their refinement draws at
+// once.  Four lanes a tile, 64 tiles a workgroup.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kT16Words = 14;  // per tile and colour: column (6), left (4), right (4)
+
+template <bool FAST>
+__global__ __launch_bounds__(256) void tile16_packed_kernel(const Geom g, const RngKey key,
+                                                            const IsingTable table,
+                                                            const uint32_t hits, const uint32_t t,
+                                                            const uint32_t tc, const uint32_t ntiles,
+                                                            int8_t* __restrict__ s) {
+  __shared__ uint32_t lw[64 * 2 * kT16Words];
+  const uint32_t L = (uint32_t)g.L, R = (uint32_t)g.R;
+  const uint32_t gi = threadIdx.x >> 2, i = threadIdx.x & 3u;  // tile of the workgroup, word
+  const uint32_t bt = blockIdx.x * 64u + gi;
+  const bool valid = bt < ntiles;
+  const uint32_t half = L / 32;  // tiles of one colour per tile row
+  const uint32_t bv = valid ? bt : 0u;
+  const uint32_t ty = bv / half;
+  const uint32_t tx = 2 * (bv - ty * half) + ((ty + tc) & 1u);
+  const uint32_t Y0 = ty * 16, x0 = tx * 8;  // first row; in-row index of the tile row's first site
+  const uint64_t Nh = (uint64_t)g.Nh;
+  uint32_t* tw = lw + gi * 2u * kT16Words;   // colour c at tw + c * kT16Words
+  auto bits8 = [&](const int8_t* row) -> uint32_t {  // sign bits of 8 sites
+    const uint2 v = *reinterpret_cast<const uint2*>(row);
+    return gather7(v.x) | (gather7(v.y) << 4);
+  };
+  // stage: lane i of the tile fills word i of both colours, its left and right
+  // sites, and (lanes 0 and 3) the boundary rows
+  if (valid) {
+#pragma unroll
+    for (uint32_t cc = 0; cc < 2; ++cc) {
+      uint32_t* col = tw + cc * kT16Words;
+      const int8_t* pl = s + cc * Nh;
+      uint32_t w = 0, lh = 0, rh = 0;
+      const uint32_t xl = x0 == 0 ? R - 1 : x0 - 1, xr = x0 + 8 == R ? 0 : x0 + 8;
+#pragma unroll
+      for (uint32_t r = 0; r < 4; ++r) {
+        const int8_t* row = pl + (uint64_t)(Y0 + 4 * i + r) * R;
+        w |= bits8(row + x0) << (8 * r);
+        lh |= (row[xl] < 0 ? 1u : 0u) << (8 * r);
+        rh |= (row[xr] < 0 ? 0x80u : 0u) << (8 * r);
+      }
+      col[1 + i] = w;
+      col[6 + i] = lh;
+      col[10 + i] = rh;
+      if (i == 0) col[0] = bits8(pl + (uint64_t)(Y0 == 0 ? L - 1 : Y0 - 1) * R + x0) << 24;
+      if (i == 3) col[5] = bits8(pl + (uint64_t)(Y0 + 16 == L ? 0 : Y0 + 16) * R + x0);
+    }
+  }
+  __syncthreads();
+
+  const TabRegs tab = tab_regs(table);
+  FastTab ft;
+  if (FAST) ft = fast_tab<2>(tab);
+  const uint32_t j0 = (Y0 + 4 * i) * R + x0;  // in-colour index of the word's first site
+  for (uint32_t h = 0; h < hits; ++h) {
+#pragma unroll
+    for (uint32_t c = 0; c < 2; ++c) {
+      if (valid) {
+        uint32_t* own = tw + c * kT16Words;
+        const uint32_t* oth = tw + (1 - c) * kT16Words;
+        const uint32_t o = own[1 + i], ct = oth[1 + i];
+        const uint32_t up = __builtin_amdgcn_alignbit(ct, oth[i], 24u);    // rows r - 1
+        const uint32_t dn = __builtin_amdgcn_alignbit(oth[2 + i], ct, 8u);  // rows r + 1
+        const uint32_t sh_next = ((ct >> 1) & 0x7F7F7F7Fu) | oth[10 + i];   // site + 1 in its row
+        const uint32_t sh_prev = ((ct << 1) & 0xFEFEFEFEu) | oth[6 + i];    // site - 1
+        // rows of parity 1 (x + 1 = next site): rows 1, 3 for colour 0, rows 0, 2 for colour 1
+        constexpr uint32_t P1[2] = {0xFF00FF00u, 0x00FF00FFu};
+        const uint32_t pm = P1[c];
+        const uint32_t nxp = (ct & ~pm) | (sh_next & pm);
+        const uint32_t nxm = (sh_prev & ~pm) | (ct & pm);
+        const uint32_t u[6] = {o ^ nxp, o ^ nxm, o ^ dn, o ^ up, 0u, 0u};
+        uint32_t k0, k1, k2, ties;
+        count_planes<2>(u, k0, k1, k2);
+        // prefix bytes: row r's 8 sites are words 2 h0, 2 h0 + 1 of block j >> 4
+        uint32_t P[8];
+#pragma unroll
+        for (uint32_t r = 0; r < 4; ++r) {
+          const uint32_t jr = j0 + r * R;
+          const Rand4 rb = philox(jr >> 4, t, key.replica, tag(c, kIsingPrefix) | (h << 8), key.k0,
+                                  key.k1);
+          const bool h0 = ((jr >> 3) & 1u) != 0;
+          P[2 * r] = h0 ? rb.w[2] : rb.w[0];
+          P[2 * r + 1] = h0 ? rb.w[3] : rb.w[1];
+        }
+        uint32_t B[8];
+        prefix_planes(P, B);
+        uint32_t flip = FAST ? packed_compare_fast<2>(ft, B, k0, k1, k2, ties)
+                             : packed_compare<2>(tab, B, k0, k1, k2, ties);
+        while (ties) {  // exact ties: the 24-bit refinement against the class's fraction
+          const uint32_t b = __builtin_ctz(ties);
+          ties &= ties - 1;
+          const uint32_t k = ((k0 >> b) & 1u) | (((k1 >> b) & 1u) << 1) | (((k2 >> b) & 1u) << 2);
+          const uint32_t js = j0 + (b >> 3) * R + (b & 7u);
+          const Rand4 rr = philox(js, t, key.replica, tag(c, kIsingRefine) | (h << 8), key.k0,
+                                  key.k1);
+          if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) flip |= 1u << b;
+        }
+        own[1 + i] = o ^ flip;
+      }
+      __syncthreads();
+    }
+  }
+
+  // write back word i of both colours: four rows of 8 sites as +-1 bytes
+  if (valid) {
+#pragma unroll
+    for (uint32_t cc = 0; cc < 2; ++cc) {
+      const uint32_t v = tw[cc * kT16Words + 1 + i];
+#pragma unroll
+      for (uint32_t r = 0; r < 4; ++r) {
+        const uint32_t byte = (v >> (8 * r)) & 0xFFu;
+        uint32_t q[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const uint32_t spread = (((byte >> (4 * k)) & 0xFu) * 0x00204081u) & kOnes;
+          q[k] = kOnes | (spread * 0xFEu);
+        }
+        *reinterpret_cast<uint2*>(s + cc * Nh + (uint64_t)(Y0 + 4 * i + r) * R + x0) =
+            make_uint2(q[0], q[1]);
+      }
+    }
+  }
+}
+
 bool tile_packed_supported(const Geom& g, uint32_t T, bool heatbath) {
-  return g.d == 2 && !heatbath && (T == 64 || T == 128) && (uint32_t)g.L % T == 0 &&
+  return g.d == 2 && !heatbath && (T == 16 || T == 64 || T == 128) && (uint32_t)g.L % T == 0 &&
          ((uint32_t)g.L / T) % 2 == 0;
 }
 
@@ -564,6 +703,14 @@ hipError_t launch_tile_pass(const IsingLaunch& a, bool heatbath, uint32_t T, uin
     bool fast = true;
     for (int k = a.g.d; k <= 2 * a.g.d; ++k)
       if ((((k < 4 ? a.tab.al_lo : a.tab.al_hi) >> (8 * (k & 3))) & 0xFFu) != 0xFFu) fast = false;
+    if (T == 16) {
+      const dim3 grid((tiles + 63) / 64), block(256);
+      if (fast)
+        hipLaunchKernelGGL((tile16_packed_kernel<true>), grid, block, 0, st, a.g, a.key, a.tab, hits, t, tc, tiles, spins);
+      else
+        hipLaunchKernelGGL((tile16_packed_kernel<false>), grid, block, 0, st, a.g, a.key, a.tab, hits, t, tc, tiles, spins);
+      return hipGetLastError();
+    }
     const uint32_t G = tile_packed_group(T);
     const dim3 grid((tiles + G - 1) / G), block(256);
     const size_t lds = tile_packed_lds_bytes(T);

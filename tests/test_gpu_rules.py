@@ -42,8 +42,8 @@ TILED = [  # d, L, tile, hits, heatbath, beta, sweeps
 
 
 def _tile_kernel_name(d, T, hb):
-    # 2D Metropolis tiles of 64 or 128 take the bit-packed tile kernel
-    return "ising_tiles_packed" if d == 2 and not hb and T in (64, 128) else "ising_tiles"
+    # 2D Metropolis tiles of 16, 64 or 128 take the bit-packed tile kernels
+    return "ising_tiles_packed" if d == 2 and not hb and T in (16, 64, 128) else "ising_tiles"
 
 
 @pytest.mark.parametrize("d,L,T,k,hb,beta,n", TILED)
@@ -66,13 +66,17 @@ PACKED_TILES = [  # L, tile, hits, J0, beta, sweeps
     (128, 64, 4, 1.0, 2.0, 3),        # low temperature: mostly refusable moves, many exact ties
     (256, 128, 2, 1.0, BETA_C, 2),    # one 128-tile a workgroup, two words a tile row
     (128, 64, 3, -1.0, 0.5, 3),       # J0 < 0: the general bit-sliced decision
+    (64, 16, 3, 1.0, BETA_C, 3),      # the paper's 16 x 16 tiles: 8 tiles a colour, one workgroup
+    (1056, 16, 2, 1.0, 0.6, 2),       # 2178 tiles a colour: 35 workgroups, the last partly filled
+    (96, 16, 4, 1.0, 2.0, 3),         # low temperature: many exact ties
+    (64, 16, 3, -1.0, 0.5, 3),        # J0 < 0
 ]
 
 
 @pytest.mark.parametrize("L,T,k,J0,beta,n", PACKED_TILES)
 def test_packed_tiles_match_oracle(smc_gpu, oracle_mod, L, T, k, J0, beta, n):
-    """The bit-packed tile kernel (2D, Metropolis, T = 64 or 128) against the
-    oracle's tiled schedule, bit for bit, with the measurement after it."""
+    """The bit-packed tile kernels (2D, Metropolis, T = 16, 64 or 128) against
+    the oracle's tiled schedule, bit for bit, with the measurement after it."""
     print(f"packed tiles L={L} T={T} k={k} J0={J0} beta={beta}", flush=True)
     lat = smc_gpu.Lattice(2, 1, L, seed=13, J0=J0, tile=T, hits=k)
     assert lat.kernel() == ("ising_tiles_packed", T)
@@ -84,7 +88,7 @@ def test_packed_tiles_match_oracle(smc_gpu, oracle_mod, L, T, k, J0, beta, n):
     assert (o.E_int, o.M_int) == (r.E_int, r.M_int)
 
 
-@pytest.mark.parametrize("T", [64, 128])
+@pytest.mark.parametrize("T", [16, 64, 128])
 def test_packed_and_byte_tiles_run_the_same_chain(smc_gpu, monkeypatch, T):
     """Both tile kernels on a 2D L=1024 lattice, k = 5 hits: the same states."""
     import torch
