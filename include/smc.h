@@ -231,9 +231,15 @@ int smc_set_samples(smc_lattice* h, int64_t samples);
 int smc_autotune(smc_lattice* h, double beta, void* scratch, size_t scratch_bytes,
                  uint32_t* rows_out);
 
-/* Name of the kernel the handle's sweeps launch ("ising_fused",
- * "ising_stream", "ising_chunk", "ising_site", "xy_site", "heisenberg_site")
- * and, for the banded Ising kernels, the rows each lane walks (0 otherwise). */
+/* Name of the kernel the handle's sweeps launch -- Ising: "ising_packed"
+ * (one bit per site), "ising_fused", "ising_stream", "ising_chunk",
+ * "ising_site", and for the tiled schedule "ising_tiles" (int8 tiles) or
+ * "ising_tiles_packed" (tiles at one bit per site in LDS: 2D Metropolis, tile
+ * edge 16, 64 or 128); XY / Heisenberg: "xy_stream", "xy_site",
+ * "heisenberg_stream", "heisenberg_site" -- and in rows_per_band (optional)
+ * the rows each lane walks for the banded kernels (packed, fused, stream,
+ * xy_stream, heisenberg_stream), the tile edge for the tiled schedule, 0
+ * otherwise. */
 const char* smc_kernel_name(const smc_lattice* h, uint32_t* rows_per_band);
 
 /* Free the handle (never the caller's buffers). */

@@ -44,7 +44,7 @@ constexpr uint32_t kTieWords = 4;
 __device__ __forceinline__ int32_t popc(uint32_t v) { return __builtin_popcount(v); }
 
 struct PackedTies {
-  uint4* ent;       // ent[slot * stride]: (ties, k0, k1, k2)
+  uint4* ent;       // ent[slot * stride]: (ties, k0, k1, k2), or (ties, k0, k1, word index) with WSLOT
   uint8_t* rows;    // rows[slot * stride]: row in the band
   uint32_t stride, n, base, W;  // base: word index of the lane's column in row 0
   int64_t dE, dM;
