@@ -19,6 +19,10 @@
 // neighbours with sign(J) s_nb = +1 (= 2d - k for s = +1, k for s = -1, with
 // k the unsatisfied bonds), with the same prefix-byte / 24-bit refinement
 // draw as the Metropolis rule.
+//
+// 2D Metropolis tiles of edge 16, 64 or 128 take the bit-packed kernels at the
+// end of this file, which hold the tile at one bit per site in LDS and make
+// the same decisions bit for bit.
 #include "chunk.hpp"
 #include "packed.hpp"
 
