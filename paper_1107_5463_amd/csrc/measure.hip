@@ -163,14 +163,33 @@ __global__ __launch_bounds__(256) void finish_kernel(const Partial* __restrict__
   Partial acc[4];
   for (int u = 0; u < 4; ++u) acc[u] = Partial{0, 0, 0.0, {0.0, 0.0, 0.0}};
   int64_t b = threadIdx.x;
-  for (; b + 768 < nparts; b += 1024) {
-    Partial p[4];
+  if (ising && int_couplings) {
+    // integer E and M only: 16 of a partial's 48 bytes (one CU reads them all)
+    for (; b + 768 < nparts; b += 1024) {
+      longlong2 p[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) p[u] = parts[b + 256 * u];
+      for (int u = 0; u < 4; ++u) p[u] = *reinterpret_cast<const longlong2*>(parts + b + 256 * u);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) add(acc[u], p[u]);
+      for (int u = 0; u < 4; ++u) {
+        acc[u].Ei += p[u].x;
+        acc[u].Mi += p[u].y;
+      }
+    }
+    for (; b < nparts; b += 256) {
+      const longlong2 p = *reinterpret_cast<const longlong2*>(parts + b);
+      acc[0].Ei += p.x;
+      acc[0].Mi += p.y;
+    }
+  } else {
+    for (; b + 768 < nparts; b += 1024) {
+      Partial p[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) p[u] = parts[b + 256 * u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) add(acc[u], p[u]);
+    }
+    for (; b < nparts; b += 256) add(acc[0], parts[b]);
   }
-  for (; b < nparts; b += 256) add(acc[0], parts[b]);
   Partial v = acc[0];
   for (int u = 1; u < 4; ++u) add(v, acc[u]);
   __shared__ Partial sh[256];
