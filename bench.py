@@ -758,8 +758,9 @@ def attach_other_workloads(args, result, torch, smc):
     """The other throughput configurations, each with its own roofline, as
     objects of the default line (same GPU, same run; no CPU baseline): 3D
     Ising L = 512 (one bit per site, with its int8 two-pass line), 2D XY
-    L = 4096 and 3D Heisenberg L = 256 (FP32 spins), and the derivative
-    chains (256 chains of L = 64, forward and backward).  The batched
+    L = 4096 and 3D Heisenberg L = 256 (FP32 spins), the tiled k-hit schedule
+    on the 2D lattice (T = 16 and 64, k = 100), and the derivative chains (256
+    chains of L = 64, forward and backward).  The batched
     spin-glass rate is set against the plain sweeps of the large lattices."""
     keep = ("value", "unit", "ms_per_step", "dtype", "roofline", "pct_hbm_peak")
     for name in ("ising3d", "xy", "heisenberg"):
@@ -773,6 +774,19 @@ def attach_other_workloads(args, result, torch, smc):
         if "int8_two_pass" in r:
             o["int8_two_pass"] = r["int8_two_pass"]
         result[name] = o
+        torch.cuda.empty_cache()
+    # the paper's tiled k-hit schedule (k = 100, Metropolis) on the 2D lattice:
+    # its 16 x 16 tiles (int8 in LDS) and tiles of 64 (bit-packed in LDS)
+    for T in (16, 64):
+        a = argparse.Namespace(**vars(args))
+        a.workload, a.cpu_seconds = "ising2d", 0
+        a.tile, a.hits, a.heatbath = T, 100, False
+        a.steps, a.warmup, a.sweeps_per_step = 2, 1, 2
+        r = run_lattice(a, WORKLOADS["ising2d"], torch, smc)
+        o = {k: r[k] for k in ("value", "unit", "ms_per_step", "dtype", "roofline")}
+        o["workload"] = r["config"]["workload"]
+        o["kernel"] = r["config"]["kernel"]
+        result[f"tiles{T}"] = o
         torch.cuda.empty_cache()
     a = argparse.Namespace(**vars(args))
     a.workload, a.steps, a.sweeps_per_step, a.cpu_seconds = "chains", None, None, 0

@@ -104,35 +104,65 @@ __device__ __forceinline__ void packed_queue_word(PackedTies& q, uint32_t ties, 
   if (q.n == kTieWords) packed_tie_flush<D, MEASURE, WSLOT>(q, tab, key, t, c, own);
 }
 
-// End-of-band resolution shared by the wave (WSLOT slots): the wave's queued
-// words are numbered in lane order (a ballot prefix sum of the lanes' queue
-// lengths), lane i draws the refinements of the tied sites of word i and
-// leaves the word's flips in its slot, and each lane then applies the flips
-// of its own words -- so the wave waits for about one refinement draw per
-// lane instead of the largest number of draws of any one lane, and every
-// spin word is still written by the lane that owns it.  `idx` is the wave's
-// list of at most 64 kTieWords entries (lane | slot << 6) in LDS.  MEASURE:
-// the owner adds what its words' tie flips change -- each flipped site with
-// k unsatisfied bonds raises E by 4 (d - k) and moves M by -2 s.
+// End-of-band resolution shared by the wave (WSLOT slots): the wave's tied
+// sites are numbered in lane order (a ballot prefix sum of the lanes' counts
+// of tied sites), lane i draws the refinement of tied site i and clears that
+// site's bit in its word's slot if the move stays refused, and each lane then
+// applies the flips left in the slots of its own words -- so the wave waits
+// for one refinement draw per 64 tied sites, and every spin word is still
+// written by the lane that owns it.  A wave with a lane holding 8 or more
+// tied sites, or more than 64 kTieWords tied sites in all, numbers its tied
+// words instead and lane i draws every tied site of word i.  `idx` is the
+// wave's list of at most 64 kTieWords entries in LDS: lane | slot << 6, and
+// the site's bit << 8 when the sites are numbered.  MEASURE: the owner adds
+// what its words' tie flips change -- each flipped site with k unsatisfied
+// bonds raises E by 4 (d - k) and moves M by -2 s.
 template <int D, bool MEASURE>
 __device__ __forceinline__ void packed_tie_flush_wave(PackedTies& q, const TabRegs& tab,
                                                       const RngKey& key, uint32_t t, uint32_t c,
-                                                      uint32_t* own, uint8_t* idx,
+                                                      uint32_t* own, uint16_t* idx,
                                                       uint4* wave_ent) {
   static_assert(kTieWords <= 4, "queue length fits the two slot bits of an index entry");
+  constexpr uint32_t kCap = kTieWords * 64u;  // entries of a wave's list
   const uint32_t lane = __lane_id();
   const uint32_t n = q.n;
-  const uint64_t b0 = __ballot(n & 1u), b1 = __ballot(n & 2u), b2 = __ballot(n & 4u);
+  uint32_t m[kTieWords], ns = 0;
+#pragma unroll
+  for (uint32_t e = 0; e < kTieWords; ++e) {
+    m[e] = e < n ? q.ent[e * q.stride].x : 0u;
+    ns += popc(m[e]);
+  }
   auto below = [&](uint64_t b) -> uint32_t {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
   };
-  const uint32_t first = below(b0) + 2u * below(b1) + 4u * below(b2);
-  const uint32_t total = (uint32_t)__popcll(b0) + 2u * (uint32_t)__popcll(b1) +
-                         4u * (uint32_t)__popcll(b2);
+  // exclusive prefix sum over the lanes and total of v < 8
+  auto prefix = [&](uint32_t v, uint32_t& total) -> uint32_t {
+    const uint64_t b0 = __ballot(v & 1u), b1 = __ballot(v & 2u), b2 = __ballot(v & 4u);
+    total = (uint32_t)__popcll(b0) + 2u * (uint32_t)__popcll(b1) + 4u * (uint32_t)__popcll(b2);
+    return below(b0) + 2u * below(b1) + 4u * below(b2);
+  };
+  uint32_t total = 0, first = 0;
+  const bool few = __ballot(ns >= 8u) == 0;  // every lane's count fits three bits
+  if (few) first = prefix(ns, total);
+  const bool by_site = few && total <= kCap;
+  if (!by_site) first = prefix(n, total);
   if (total == 0u) return;
+  if (by_site) {
+    uint32_t k = first;
 #pragma unroll
-  for (uint32_t e = 0; e < kTieWords; ++e)
-    if (e < n) idx[first + e] = (uint8_t)(lane | (e << 6));
+    for (uint32_t e = 0; e < kTieWords; ++e) {
+      uint32_t mm = m[e];
+      while (mm) {
+        const uint32_t b = __builtin_ctz(mm);
+        mm &= mm - 1;
+        idx[k++] = (uint16_t)(lane | (e << 6) | (b << 8));
+      }
+    }
+  } else {
+#pragma unroll
+    for (uint32_t e = 0; e < kTieWords; ++e)
+      if (e < n) idx[first + e] = (uint16_t)(lane | (e << 6));
+  }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -140,16 +170,24 @@ __device__ __forceinline__ void packed_tie_flush_wave(PackedTies& q, const TabRe
     const uint32_t i = r0 + lane;
     if (i < total) {
       const uint32_t id = idx[i];
-      uint4* slot = wave_ent + (id >> 6) * q.stride + (id & 63u);
+      uint4* slot = wave_ent + ((id >> 6) & 3u) * q.stride + (id & 63u);
       const uint4 en = *slot;
-      uint32_t m = en.x, flips = 0;
-      while (m) {
-        const uint32_t b = __builtin_ctz(m);
-        m &= m - 1;
+      if (by_site) {
+        // the slot still holds the word's tie mask; only this lane changes bit b
+        const uint32_t b = id >> 8;
         const Rand4 rr = philox(en.w * 32u + b, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
-        if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, tie_class<true>(en, b))) flips |= 1u << b;
+        if (!((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, tie_class<true>(en, b))))
+          atomicAnd(&slot->x, ~(1u << b));
+      } else {
+        uint32_t mm = en.x, flips = 0;
+        while (mm) {
+          const uint32_t b = __builtin_ctz(mm);
+          mm &= mm - 1;
+          const Rand4 rr = philox(en.w * 32u + b, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
+          if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, tie_class<true>(en, b))) flips |= 1u << b;
+        }
+        slot->x = flips;
       }
-      slot->x = flips;
     }
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -193,7 +231,7 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
   static_assert(!WAVE || FAST, "wave resolution: the fast decision's slot layout");
   __shared__ uint4 tie_ent[kTieWords * 256];
   __shared__ uint8_t tie_rows[WAVE ? 1 : kTieWords * 256];
-  __shared__ uint8_t tie_idx[WAVE ? kTieWords * 256 : 1];
+  __shared__ uint16_t tie_idx[WAVE ? kTieWords * 256 : 1];
   const uint32_t tid = xcd_remap(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
   const uint32_t band = fdiv(tid, divW);
   int64_t Esum = 0, Msum = 0;

@@ -29,14 +29,22 @@ __device__ __forceinline__ uint32_t class_mask(uint32_t k0, uint32_t k1, uint32_
 // Exchange of a word-index bit with bit k of the bit position (d = 2^k,
 // m = the positions whose bit k is 0) between the words a (index bit 0) and
 // b (index bit 1): afterwards a holds the bits whose position bit k was 0, b
-// those whose bit k was 1, and position bit k tells which word a bit came from.
-// (v_bitop3 with the table 0xE4 selects its first operand where the third is
-// 1 and its second elsewhere; the builtin keeps the compiler from splitting
-// the selects into separate masks.)
+// those whose bit k was 1, and position bit k tells which word a bit came
+// from.  One rotation serves both outputs: with b' = b rotated left by d, a
+// takes b' where m is 0 (b' equals b << d there), and b comes out rotated
+// left by d as the select of b' where m is 1 and a elsewhere (a position p
+// with bit k set of the rotated word is position p - d, bit k clear, of the
+// plain one, whose bits are a's at p and b's at p - d).  Words that carry a
+// rotation by r go through later exchanges unchanged as long as the later
+// masks repeat with a period dividing r.  (v_bitop3 with the table 0xE4
+// selects its first operand where the third is 1 and its second elsewhere;
+// the builtin keeps the compiler from splitting the selects into separate
+// masks.)
 template <int D>
-__device__ __forceinline__ void cross_swap(uint32_t& a, uint32_t& b, uint32_t m) {
-  const uint32_t na = __builtin_amdgcn_bitop3_b32(a, b << D, m, 0xE4);
-  const uint32_t nb = __builtin_amdgcn_bitop3_b32(a >> D, b, m, 0xE4);
+__device__ __forceinline__ void cross_swap_rot(uint32_t& a, uint32_t& b, uint32_t m) {
+  const uint32_t br = __builtin_amdgcn_alignbit(b, b, 32 - D);  // b rotated left by D
+  const uint32_t na = __builtin_amdgcn_bitop3_b32(a, br, m, 0xE4);
+  const uint32_t nb = __builtin_amdgcn_bitop3_b32(br, a, m, 0xE4);
   a = na;
   b = nb;
 }
@@ -48,7 +56,11 @@ __device__ __forceinline__ void cross_swap(uint32_t& a, uint32_t& b, uint32_t m)
 // (b2 b1 b0), position (w2 w1 w0 i1 i0).  A 4x4 byte transpose (v_perm)
 // among the words of equal w0 trades (w2 w1) for (i1 i0); three cross-word
 // bit swaps then trade the word bits (w0, i1, i0) for the bit-in-byte bits
-// (b2, b1, b0), which leaves every bit at its site's position.
+// (b2, b1, b0), which leaves every bit at its site's position -- plane b
+// rotated left by b (4 b2 + 2 b1 + b0, the rotations its swaps left on it),
+// which one rotation per plane takes back.  The masks 0x33333333 and
+// 0x55555555 repeat every 4 and 2 bits, so the rotations by 4 and 2 that
+// the earlier swaps leave do not disturb the later ones.
 __device__ __forceinline__ void prefix_planes(const uint32_t P[8], uint32_t B[8]) {
   uint32_t Q[2][4];  // Q[w0][i]: byte k = byte i of P[2k + w0]
 #pragma unroll
@@ -65,18 +77,20 @@ __device__ __forceinline__ void prefix_planes(const uint32_t P[8], uint32_t B[8]
   }
   // w0 <-> b2 (position bit 2), i1 <-> b1, i0 <-> b0
 #pragma unroll
-  for (int i = 0; i < 4; ++i) cross_swap<4>(Q[0][i], Q[1][i], 0x0F0F0F0Fu);
+  for (int i = 0; i < 4; ++i) cross_swap_rot<4>(Q[0][i], Q[1][i], 0x0F0F0F0Fu);
 #pragma unroll
   for (int c2 = 0; c2 < 2; ++c2) {
-    cross_swap<2>(Q[c2][0], Q[c2][2], 0x33333333u);
-    cross_swap<2>(Q[c2][1], Q[c2][3], 0x33333333u);
+    cross_swap_rot<2>(Q[c2][0], Q[c2][2], 0x33333333u);
+    cross_swap_rot<2>(Q[c2][1], Q[c2][3], 0x33333333u);
     // Q[c2][2 c1 + i0] now holds bit b2 = c2, b1 = c1 of the sites' bytes
 #pragma unroll
-    for (int c1 = 0; c1 < 2; ++c1) {
-      cross_swap<1>(Q[c2][2 * c1], Q[c2][2 * c1 + 1], 0x55555555u);
-      B[4 * c2 + 2 * c1] = Q[c2][2 * c1];
-      B[4 * c2 + 2 * c1 + 1] = Q[c2][2 * c1 + 1];
-    }
+    for (int c1 = 0; c1 < 2; ++c1) cross_swap_rot<1>(Q[c2][2 * c1], Q[c2][2 * c1 + 1], 0x55555555u);
+  }
+  B[0] = Q[0][0];
+#pragma unroll
+  for (int b = 1; b < 8; ++b) {
+    const uint32_t v = Q[b >> 2][b & 3];
+    B[b] = __builtin_amdgcn_alignbit(v, v, b);  // rotated right by b
   }
 }
 
