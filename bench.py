@@ -776,7 +776,7 @@ def attach_other_workloads(args, result, torch, smc):
         result[name] = o
         torch.cuda.empty_cache()
     # the paper's tiled k-hit schedule (k = 100, Metropolis) on the 2D lattice:
-    # its 16 x 16 tiles (int8 in LDS) and tiles of 64 (bit-packed in LDS)
+    # its 16 x 16 tiles and tiles of 64, both at one bit per site in LDS
     for T in (16, 64):
         a = argparse.Namespace(**vars(args))
         a.workload, a.cpu_seconds = "ising2d", 0

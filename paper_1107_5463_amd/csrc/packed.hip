@@ -218,7 +218,10 @@ __device__ __forceinline__ void packed_tie_flush_wave(PackedTies& q, const TabRe
 // FAST: only the classes k < d can refuse a move (J0 > 0), decided by
 // packed_decide_fast; otherwise packed_decide.  WAVE (with FAST): the
 // end-of-band ties are resolved by the whole wave (packed_tie_flush_wave).
-template <int D, bool PM, bool MEASURE, bool FAST, bool WAVE>
+// UB (with WAVE): a plane row is a multiple of 64 words, so the 64 lanes of a
+// wave share their band, and the band's row arithmetic runs once per wave in
+// scalar registers.
+template <int D, bool PM, bool MEASURE, bool FAST, bool WAVE, bool UB>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void packed_stream_kernel(const Geom g, const RngKey key,
                                                             const IsingTable table,
@@ -229,11 +232,12 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
                                                             const uint32_t t, const uint32_t c,
                                                             Partial* __restrict__ parts) {
   static_assert(!WAVE || FAST, "wave resolution: the fast decision's slot layout");
+  static_assert(!UB || WAVE, "a wave-uniform band only with the wave's tie resolution");
   __shared__ uint4 tie_ent[kTieWords * 256];
   __shared__ uint8_t tie_rows[WAVE ? 1 : kTieWords * 256];
   __shared__ uint16_t tie_idx[WAVE ? kTieWords * 256 : 1];
   const uint32_t tid = xcd_remap(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
-  const uint32_t band = fdiv(tid, divW);
+  const uint32_t band = fdiv(UB ? __builtin_amdgcn_readfirstlane(tid) : tid, divW);
   int64_t Esum = 0, Msum = 0;
   // measured launches: per-lane 32-bit counts (v_bcnt_u32_b32 adds its
   // popcount to an accumulator), widened once per band -- unsatisfied bonds
@@ -410,14 +414,16 @@ hipError_t launch_packed_half_sweep(const IsingLaunch& a, uint32_t* spins, const
     if ((((k < 4 ? a.tab.al_lo : a.tab.al_hi) >> (8 * (k & 3))) & 0xFFu) != 0xFFu) fast = false;
   Partial* pp = (Partial*)partials;
   const bool wave = a.packed_ties == 0;
-#define SMC_PK(DD, PMM, MM, FF, WW)                                                                     \
-  hipLaunchKernelGGL((packed_stream_kernel<DD, PMM, MM, FF, WW>), grid, block, 0, st, a.g, a.key, a.tab, \
+  const bool uniform_band = W % 64 == 0;  // every wave inside one band
+#define SMC_PK(DD, PMM, MM, FF, WW, UU)                                                                     \
+  hipLaunchKernelGGL((packed_stream_kernel<DD, PMM, MM, FF, WW, UU>), grid, block, 0, st, a.g, a.key, a.tab, \
                      dW, dL, H, nbands, spins, J, t, c, pp)
 #define SMC_PKF(DD, PMM, MM)                                        \
   do {                                                              \
-    if (!fast) SMC_PK(DD, PMM, MM, false, false);                   \
-    else if (!wave) SMC_PK(DD, PMM, MM, true, false);               \
-    else SMC_PK(DD, PMM, MM, true, true);                           \
+    if (!fast) SMC_PK(DD, PMM, MM, false, false, false);            \
+    else if (!wave) SMC_PK(DD, PMM, MM, true, false, false);        \
+    else if (!uniform_band) SMC_PK(DD, PMM, MM, true, true, false); \
+    else SMC_PK(DD, PMM, MM, true, true, true);                     \
   } while (0)
   if (a.g.d == 2) {
     if (pm) { if (pp) SMC_PKF(2, true, true); else SMC_PKF(2, true, false); }

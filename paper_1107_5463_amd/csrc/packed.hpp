@@ -96,10 +96,11 @@ __device__ __forceinline__ void prefix_planes(const uint32_t P[8], uint32_t B[8]
 
 // Threshold bits of the refusable classes for the fast decision: class 0
 // (and class 2 in 3D) as all-ones / zero masks held in vector registers,
-// class 1 as a scalar byte (one scalar operand per instruction).
+// class 1 as all-ones / zero masks in scalar registers (one scalar operand
+// per instruction).
 struct FastTab {
   uint32_t v0[8], v2[8];
-  uint32_t th1;
+  uint32_t s1[8];
 };
 
 __device__ __forceinline__ uint32_t vgpr_copy(uint32_t s) {
@@ -117,7 +118,9 @@ __device__ __forceinline__ FastTab fast_tab(const TabRegs& tab) {
     f.v0[b] = vgpr_copy(0u - ((t0 >> b) & 1u));
     f.v2[b] = D == 3 ? vgpr_copy(0u - ((t2 >> b) & 1u)) : 0u;
   }
-  f.th1 = table_byte(tab.th_lo, tab.th_hi, 1);
+  const uint32_t t1 = table_byte(tab.th_lo, tab.th_hi, 1);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) f.s1[b] = __builtin_amdgcn_readfirstlane(0u - ((t1 >> b) & 1u));
   return f;
 }
 
@@ -151,8 +154,7 @@ __device__ __forceinline__ uint32_t packed_compare_fast(const FastTab& ft, const
   uint32_t lt = 0, eq = ~0u;
 #pragma unroll
   for (int b = 0; b < 8; ++b) {
-    const uint32_t s1 = __builtin_amdgcn_readfirstlane(0u - ((ft.th1 >> b) & 1u));
-    uint32_t X = __builtin_amdgcn_bitop3_b32(k0, s1, ft.v0[b], 0xCA);
+    uint32_t X = __builtin_amdgcn_bitop3_b32(k0, ft.s1[b], ft.v0[b], 0xCA);
     if (D == 3) X = __builtin_amdgcn_bitop3_b32(k1, ft.v2[b], X, 0xCA);
     lt = __builtin_amdgcn_bitop3_b32(B[b], X, lt, 0x8E);
     eq = __builtin_amdgcn_bitop3_b32(B[b], X, eq, 0x82);

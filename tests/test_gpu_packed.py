@@ -130,6 +130,27 @@ def test_many_ties_per_wave(smc_gpu, oracle_mod, ties, monkeypatch):
     assert np.array_equal(nat(smc_gpu, lat), ref.s)
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+def test_wave_uniform_bands_match_oracle(smc_gpu, oracle_mod, kind):
+    """2D L=4096: a plane row is 64 words, so every wave lies inside one band
+    and the kernel keeps the band's row arithmetic in scalar registers; plain
+    and measured sweeps with uniform and +-1 couplings, bit for bit."""
+    import torch
+    L = 4096
+    print(f"packed wave-uniform bands L={L} kind={kind}", flush=True)
+    lat = smc_gpu.Lattice(2, 1, L, seed=21 + kind, J_kind=kind, packed=True)
+    assert lat.kernel()[0] == "ising_packed"
+    ref = oracle_mod.OracleLattice(2, 1, L, 21 + kind, J_kind=kind)
+    lat.sweep(BETA_C, 2)
+    ref.sweep(BETA_C, 2)
+    slot = torch.zeros((1, 8), dtype=torch.int64, device=lat.device)
+    lat.sweep_measure(BETA_C, 1, slot[0])
+    ref.sweep(BETA_C, 1)
+    got, r = smc_gpu.Lattice.decode_obs(slot)[0], ref.measure()
+    assert (got.E_int, got.M_int) == (r.E_int, r.M_int)
+    assert np.array_equal(nat(smc_gpu, lat), ref.s)
+
+
 def test_special_temperatures(smc_gpu, oracle_mod):
     for beta in (0.0, float("inf")):
         lat = smc_gpu.Lattice(2, 1, 64, seed=9, packed=True)
