@@ -104,27 +104,32 @@ __device__ __forceinline__ void packed_queue_word(PackedTies& q, uint32_t ties, 
   if (q.n == kTieWords) packed_tie_flush<D, MEASURE, WSLOT>(q, tab, key, t, c, own);
 }
 
-// End-of-band resolution shared by the wave (WSLOT slots): the wave's tied
-// sites are numbered in lane order (a ballot prefix sum of the lanes' counts
-// of tied sites), lane i draws the refinement of tied site i and clears that
-// site's bit in its word's slot if the move stays refused, and each lane then
-// applies the flips left in the slots of its own words -- so the wave waits
-// for one refinement draw per 64 tied sites, and every spin word is still
-// written by the lane that owns it.  A wave with a lane holding 8 or more
-// tied sites, or more than 64 kTieWords tied sites in all, numbers its tied
-// words instead and lane i draws every tied site of word i.  `idx` is the
-// wave's list of at most 64 kTieWords entries in LDS: lane | slot << 6, and
-// the site's bit << 8 when the sites are numbered.  MEASURE: the owner adds
-// what its words' tie flips change -- each flipped site with k unsatisfied
-// bonds raises E by 4 (d - k) and moves M by -2 s.
+// End-of-band resolution shared by the workgroup (WSLOT slots): the
+// workgroup's tied sites are numbered in thread order (a ballot prefix sum of
+// the lanes' counts of tied sites within each wave, the waves' totals through
+// LDS), thread i draws the refinement of tied site i and clears that site's
+// bit in its word's slot if the move stays refused, and each lane then
+// applies the flips left in the slots of its own words.  The workgroup so
+// spends one round of refinement draws per 256 tied sites: a band of 4 rows
+// leaves about 30 per wave, so two of the four waves draw and two wait at the
+// barrier, and every spin word is still written by the lane that owns it.
+// A workgroup with a lane holding 8 or more tied sites, or more than
+// 256 kTieWords tied sites in all, resolves wave by wave instead: the wave
+// numbers its tied words and lane i draws every tied site of word i.  `idx`
+// is the workgroup's list of 256 kTieWords entries in LDS -- thread | slot
+// << 8 | the site's bit << 10 when sites are numbered, lane | slot << 6 in a
+// wave's quarter when words are -- and `wsum` four words of LDS for the
+// waves' totals.  Every thread of the workgroup calls this once.  MEASURE:
+// the owner adds what its words' tie flips change -- each flipped site with
+// k unsatisfied bonds raises E by 4 (d - k) and moves M by -2 s.
 template <int D, bool MEASURE>
-__device__ __forceinline__ void packed_tie_flush_wave(PackedTies& q, const TabRegs& tab,
-                                                      const RngKey& key, uint32_t t, uint32_t c,
-                                                      uint32_t* own, uint16_t* idx,
-                                                      uint4* wave_ent) {
+__device__ __forceinline__ void packed_tie_flush_group(PackedTies& q, const TabRegs& tab,
+                                                       const RngKey& key, uint32_t t, uint32_t c,
+                                                       uint32_t* own, uint16_t* idx,
+                                                       uint4* ent, uint32_t* wsum) {
   static_assert(kTieWords <= 4, "queue length fits the two slot bits of an index entry");
-  constexpr uint32_t kCap = kTieWords * 64u;  // entries of a wave's list
-  const uint32_t lane = __lane_id();
+  constexpr uint32_t kCap = kTieWords * 256u;  // entries of the workgroup's list
+  const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
   const uint32_t n = q.n;
   uint32_t m[kTieWords], ns = 0;
 #pragma unroll
@@ -135,50 +140,63 @@ __device__ __forceinline__ void packed_tie_flush_wave(PackedTies& q, const TabRe
   auto below = [&](uint64_t b) -> uint32_t {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
   };
-  // exclusive prefix sum over the lanes and total of v < 8
+  // exclusive prefix sum over the wave's lanes and the wave's total of v < 8
   auto prefix = [&](uint32_t v, uint32_t& total) -> uint32_t {
     const uint64_t b0 = __ballot(v & 1u), b1 = __ballot(v & 2u), b2 = __ballot(v & 4u);
     total = (uint32_t)__popcll(b0) + 2u * (uint32_t)__popcll(b1) + 4u * (uint32_t)__popcll(b2);
     return below(b0) + 2u * below(b1) + 4u * below(b2);
   };
-  uint32_t total = 0, first = 0;
+  uint32_t wtotal = 0, first = 0;
   const bool few = __ballot(ns >= 8u) == 0;  // every lane's count fits three bits
-  if (few) first = prefix(ns, total);
-  const bool by_site = few && total <= kCap;
-  if (!by_site) first = prefix(n, total);
-  if (total == 0u) return;
-  if (by_site) {
-    uint32_t k = first;
+  if (few) first = prefix(ns, wtotal);
+  if (lane == 0) wsum[wave] = few ? wtotal : kCap + 1u;
+  __syncthreads();
+  const uint32_t s0 = wsum[0], s1 = wsum[1], s2 = wsum[2], s3 = wsum[3];
+  const uint32_t total = s0 + s1 + s2 + s3;  // above kCap if any wave could not number
+  if (total == 0u) return;  // the same for every thread: no barrier follows
+  if (total <= kCap) {
+    uint32_t k = first + (wave > 0 ? s0 : 0u) + (wave > 1 ? s1 : 0u) + (wave > 2 ? s2 : 0u);
 #pragma unroll
     for (uint32_t e = 0; e < kTieWords; ++e) {
       uint32_t mm = m[e];
       while (mm) {
         const uint32_t b = __builtin_ctz(mm);
         mm &= mm - 1;
-        idx[k++] = (uint16_t)(lane | (e << 6) | (b << 8));
+        idx[k++] = (uint16_t)(threadIdx.x | (e << 8) | (b << 10));
       }
     }
-  } else {
-#pragma unroll
-    for (uint32_t e = 0; e < kTieWords; ++e)
-      if (e < n) idx[first + e] = (uint16_t)(lane | (e << 6));
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  for (uint32_t r0 = 0; r0 < total; r0 += 64u) {
-    const uint32_t i = r0 + lane;
-    if (i < total) {
-      const uint32_t id = idx[i];
-      uint4* slot = wave_ent + ((id >> 6) & 3u) * q.stride + (id & 63u);
-      const uint4 en = *slot;
-      if (by_site) {
-        // the slot still holds the word's tie mask; only this lane changes bit b
-        const uint32_t b = id >> 8;
+    __syncthreads();
+    for (uint32_t r0 = 0; r0 < total; r0 += 256u) {
+      const uint32_t i = r0 + threadIdx.x;
+      if (i < total) {
+        // the slot still holds the word's tie mask; only this thread changes bit b
+        const uint32_t id = idx[i], b = id >> 10;
+        uint4* slot = ent + ((id >> 8) & 3u) * q.stride + (id & 255u);
+        const uint4 en = *slot;
         const Rand4 rr = philox(en.w * 32u + b, t, key.replica, tag(c, kIsingRefine), key.k0, key.k1);
         if (!((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, tie_class<true>(en, b))))
           atomicAnd(&slot->x, ~(1u << b));
-      } else {
+      }
+    }
+    __syncthreads();
+  } else {
+    uint16_t* widx = idx + wave * 64u * kTieWords;
+    uint4* went = ent + wave * 64u;
+    uint32_t wt = 0;
+    const uint32_t wfirst = prefix(n, wt);
+    if (wt == 0u) return;  // the same for the wave's lanes; nothing else waits for them
+#pragma unroll
+    for (uint32_t e = 0; e < kTieWords; ++e)
+      if (e < n) widx[wfirst + e] = (uint16_t)(lane | (e << 6));
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (uint32_t r0 = 0; r0 < wt; r0 += 64u) {
+      const uint32_t i = r0 + lane;
+      if (i < wt) {
+        const uint32_t id = widx[i];
+        uint4* slot = went + (id >> 6) * q.stride + (id & 63u);
+        const uint4 en = *slot;
         uint32_t mm = en.x, flips = 0;
         while (mm) {
           const uint32_t b = __builtin_ctz(mm);
@@ -189,10 +207,10 @@ __device__ __forceinline__ void packed_tie_flush_wave(PackedTies& q, const TabRe
         slot->x = flips;
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
   for (uint32_t e = 0; e < kTieWords; ++e) {
     if (e < n) {
@@ -217,7 +235,8 @@ __device__ __forceinline__ void packed_tie_flush_wave(PackedTies& q, const TabRe
 // spill there and keeps the default.
 // FAST: only the classes k < d can refuse a move (J0 > 0), decided by
 // packed_decide_fast; otherwise packed_decide.  WAVE (with FAST): the
-// end-of-band ties are resolved by the whole wave (packed_tie_flush_wave).
+// end-of-band ties are resolved by the whole workgroup
+// (packed_tie_flush_group).
 // UB (with WAVE): a plane row is a multiple of 64 words, so the 64 lanes of a
 // wave share their band, and the band's row arithmetic runs once per wave in
 // scalar registers.
@@ -236,6 +255,7 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
   __shared__ uint4 tie_ent[kTieWords * 256];
   __shared__ uint8_t tie_rows[WAVE ? 1 : kTieWords * 256];
   __shared__ uint16_t tie_idx[WAVE ? kTieWords * 256 : 1];
+  __shared__ uint32_t tie_sum[WAVE ? 4 : 1];
   const uint32_t tid = xcd_remap(blockIdx.x, gridDim.x) * 256u + threadIdx.x;
   const uint32_t band = fdiv(UB ? __builtin_amdgcn_readfirstlane(tid) : tid, divW);
   int64_t Esum = 0, Msum = 0;
@@ -361,10 +381,8 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
       ct = dn;
     }
   }
-  if (WAVE)  // the band's queued ties
-    packed_tie_flush_wave<D, MEASURE>(tq, tab, key, t, c, own,
-                                      tie_idx + (threadIdx.x & ~63u) * kTieWords,
-                                      tie_ent + (threadIdx.x & ~63u));
+  if (WAVE)  // the band's queued ties, every thread of the workgroup
+    packed_tie_flush_group<D, MEASURE>(tq, tab, key, t, c, own, tie_idx, tie_ent, tie_sum);
   else
     packed_tie_flush<D, MEASURE>(tq, tab, key, t, c, own);
   if (MEASURE) {
