@@ -317,17 +317,31 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
     uint32_t ct = ldw(oth, row0 + q);
     uint32_t rowb = row0;
     uint32_t zmb = mul(zm_row + y0, W), zpb = mul(zp_row + y0, W);  // z - 1 and z + 1 rows (3D)
-    for (uint32_t i = 0; i < H; ++i, rowb += W, zmb += W, zpb += W) {
+    // one row of the band; pc is the row's parity p (1: the x+1 neighbour is
+    // the next in-row site), a compile-time constant when the caller knows it
+    auto row = [&](uint32_t i, auto pc) {
       const uint32_t y = y0 + i;
-      const uint32_t p = (pz + y) & 1u;
+      const uint32_t p = pc;
       const uint32_t dn = ldw(oth, (y + 1 == L ? wrap0 : rowb + W) + q);
       const uint32_t o = ldw(own, rowb + q);
-      const uint32_t en = ldw(oth, rowb + qn), ep = ldw(oth, rowb + qp);
       // x+1 neighbours (p = 1: next in-row site) and x-1 (p = 0: previous)
-      const uint32_t sh_next = __builtin_amdgcn_alignbit(en, ct, 1u);
-      const uint32_t sh_prev = __builtin_amdgcn_alignbit(ct, ep, 31u);
-      const uint32_t nxp = mask_sel(ct, sh_next, p);
-      const uint32_t nxm = mask_sel(sh_prev, ct, p);
+      uint32_t nxp, nxm;
+      if constexpr (!std::is_same<decltype(pc), uint32_t>::value) {
+        // known parity: only the word on the side where the row leaves this one
+        if constexpr (decltype(pc)::value == 1) {
+          nxp = __builtin_amdgcn_alignbit(ldw(oth, rowb + qn), ct, 1u);
+          nxm = ct;
+        } else {
+          nxp = ct;
+          nxm = __builtin_amdgcn_alignbit(ct, ldw(oth, rowb + qp), 31u);
+        }
+      } else {
+        const uint32_t en = ldw(oth, rowb + qn), ep = ldw(oth, rowb + qp);
+        const uint32_t sh_next = __builtin_amdgcn_alignbit(en, ct, 1u);
+        const uint32_t sh_prev = __builtin_amdgcn_alignbit(ct, ep, 31u);
+        nxp = mask_sel(ct, sh_next, p);
+        nxm = mask_sel(sh_prev, ct, p);
+      }
       uint32_t u[6];
       u[0] = o ^ nxp;
       u[1] = o ^ nxm;
@@ -379,6 +393,27 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
       }
       up = ct;
       ct = dn;
+      rowb += W;
+      zmb += W;
+      zpb += W;
+    };
+    using P0 = std::integral_constant<uint32_t, 0>;
+    using P1 = std::integral_constant<uint32_t, 1>;
+    if (UB && (H & 1u) == 0u) {
+      // the wave's rows share their parity, which alternates along the band
+      if ((pz + y0) & 1u) {
+        for (uint32_t i = 0; i < H; i += 2) {
+          row(i, P1());
+          row(i + 1, P0());
+        }
+      } else {
+        for (uint32_t i = 0; i < H; i += 2) {
+          row(i, P0());
+          row(i + 1, P1());
+        }
+      }
+    } else {
+      for (uint32_t i = 0; i < H; ++i) row(i, (pz + y0 + i) & 1u);
     }
   }
   if (WAVE)  // the band's queued ties, every thread of the workgroup
