@@ -394,6 +394,84 @@ __global__ __launch_bounds__(256) void tile16_kernel(const Geom g, const RngKey 
 }
 
 // ---------------------------------------------------------------------------
+// Exact ties of a bit-packed tile pass under the fast decision (J0 > 0: only
+// the classes k < 2 refuse, so a tied site's class is k0 + 2 k1), resolved by
+// the workgroup instead of by each lane: ballot prefix sums of the lanes'
+// counts of tied sites number the sites within each wave, the four waves'
+// totals go through LDS, thread i draws the refinement of tied site i and
+// flips the site in its owner's LDS word (an LDS atomic xor) if the move is
+// accepted after all.  A pass leaves about 30 tied sites a workgroup, so one
+// wave draws where every wave did (a lane's own ties cost its wave one draw
+// each, and some lane of a wave almost always has one).  A workgroup with a
+// lane holding 8 or more tied sites, or more than kTileTieCap in all, lets
+// each lane draw its own.  Every thread of the 256-thread workgroup calls
+// this once per pass, after storing its word with the ties refused; the
+// caller's barrier after the pass orders the flips before the next reads.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kTileTieCap = 512;  // entries of the workgroup's list of tied sites
+
+struct TileTies {
+  uint4 ent[256];             // per thread: k0, k1, first site, LDS index of its word
+  uint16_t idx[kTileTieCap];  // thread | bit << 8
+  uint32_t wsum[4];           // the waves' counts of tied sites
+};
+
+// ROWS8: bit b of a word is site base + (b >> 3) R + (b & 7) (four tile rows
+// of 8 sites), else site base + b.
+template <bool ROWS8>
+__device__ __forceinline__ void tile_ties_group(TileTies& tt, uint32_t ties, uint32_t k0,
+                                                uint32_t k1, uint32_t base, uint32_t R,
+                                                uint32_t* words, uint32_t off, const TabRegs& tab,
+                                                const RngKey& key, uint32_t t, uint32_t c,
+                                                uint32_t h) {
+  auto accepts = [&](uint32_t bs, uint32_t b, uint32_t kc) -> bool {
+    const uint32_t js = ROWS8 ? bs + (b >> 3) * R + (b & 7u) : bs + b;
+    const Rand4 rr = philox(js, t, key.replica, tag(c, kIsingRefine) | (h << 8), key.k0, key.k1);
+    return (rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, kc);
+  };
+  auto below = [](uint64_t b) -> uint32_t {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+  };
+  const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
+  const uint32_t ns = (uint32_t)__builtin_popcount(ties);
+  tt.ent[threadIdx.x] = make_uint4(k0, k1, base, off);
+  const bool few = __ballot(ns >= 8u) == 0;  // every lane's count fits three bits
+  uint32_t wtotal = 0, first = 0;
+  if (few) {
+    const uint64_t b0 = __ballot(ns & 1u), b1 = __ballot(ns & 2u), b2 = __ballot(ns & 4u);
+    wtotal = (uint32_t)__popcll(b0) + 2u * (uint32_t)__popcll(b1) + 4u * (uint32_t)__popcll(b2);
+    first = below(b0) + 2u * below(b1) + 4u * below(b2);
+  }
+  if (lane == 0) tt.wsum[wave] = few ? wtotal : kTileTieCap + 1u;
+  __syncthreads();
+  const uint32_t s0 = tt.wsum[0], s1 = tt.wsum[1], s2 = tt.wsum[2], s3 = tt.wsum[3];
+  const uint32_t total = s0 + s1 + s2 + s3;  // above kTileTieCap if any wave could not number
+  if (total == 0u) return;  // the same for every thread
+  if (total <= kTileTieCap) {
+    uint32_t k = first + (wave > 0 ? s0 : 0u) + (wave > 1 ? s1 : 0u) + (wave > 2 ? s2 : 0u);
+    for (uint32_t m = ties; m; m &= m - 1)
+      tt.idx[k++] = (uint16_t)(threadIdx.x | ((uint32_t)__builtin_ctz(m) << 8));
+    __syncthreads();
+    for (uint32_t r0 = 0; r0 < total; r0 += 256u) {
+      const uint32_t i = r0 + threadIdx.x;
+      if (i < total) {
+        const uint32_t id = tt.idx[i], b = id >> 8;
+        const uint4 en = tt.ent[id & 255u];
+        if (accepts(en.z, b, ((en.x >> b) & 1u) | (((en.y >> b) & 1u) << 1)))
+          atomicXor(words + en.w, 1u << b);
+      }
+    }
+  } else {
+    uint32_t flips = 0;
+    for (uint32_t m = ties; m; m &= m - 1) {
+      const uint32_t b = (uint32_t)__builtin_ctz(m);
+      if (accepts(base, b, ((k0 >> b) & 1u) | (((k1 >> b) & 1u) << 1))) flips |= 1u << b;
+    }
+    if (flips) words[off] ^= flips;  // the lane's own word
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Bit-packed tiles (2D, T % 64 == 0, Metropolis, uniform couplings): a tile
 // and its boundary layer sit in LDS at one bit per site.  Per colour, LDS row
 // r (0 .. T + 1; rows 0 and T + 1 are the boundary rows) holds the T / 64
@@ -403,8 +481,9 @@ __global__ __launch_bounds__(256) void tile16_kernel(const Geom g, const RngKey 
 // neighbours are funnel shifts, as in the packed streaming kernel.  A lane
 // owns one word of a tile row of each colour for all k hits and decides its
 // 32 sites with that kernel's bit-sliced decision, drawing the same prefix
-// bytes (the hit in the counter); exact ties take their refinement draws at
-// once.  Every site makes the int8 tile kernel's decision, so the chain is
+// bytes (the hit in the counter); exact ties take their refinement draws
+// before the pass ends (shared by the workgroup under the fast decision,
+// tile_ties_group).  Every site makes the int8 tile kernel's decision, so the chain is
 // the same bit for bit.  T = 64 (a tile is one wave, four to a workgroup) or
 // T = 128 (a tile is one 256-lane workgroup).
 // ---------------------------------------------------------------------------
@@ -464,9 +543,12 @@ __global__ __launch_bounds__(256) void tile_packed_kernel(const Geom g, const Rn
   const uint32_t y = Y0 + ry - 1;
   const uint32_t rb = ry * RW + i;
   const uint32_t wi = (y * R + xw0) / 32u + (i - 1);  // global word index (R % 32 == 0)
+  __shared__ TileTies tt;
+  uint32_t* const words = reinterpret_cast<uint32_t*>(lds_raw);
   for (uint32_t h = 0; h < hits; ++h) {
 #pragma unroll
     for (uint32_t c = 0; c < 2; ++c) {
+      uint32_t ties = 0, k0 = 0, k1 = 0, off = 0;
       if (valid) {
         uint32_t* own = lw + c * PL;
         const uint32_t* oth = lw + (1 - c) * PL;
@@ -478,11 +560,11 @@ __global__ __launch_bounds__(256) void tile_packed_kernel(const Geom g, const Rn
         const uint32_t sh_prev = __builtin_amdgcn_alignbit(ct, ep, 31u);
         const uint32_t u[6] = {o ^ mask_sel(ct, sh_next, p), o ^ mask_sel(sh_prev, ct, p), o ^ dn,
                                o ^ up, 0u, 0u};
-        uint32_t k0, k1, k2, ties;
+        uint32_t k2;
         count_planes<2>(u, k0, k1, k2);
         uint32_t flip = FAST ? packed_decide_fast<2>(ft, key, t, c, wi, k0, k1, k2, ties, h)
                              : packed_decide<2>(tab, key, t, c, wi, k0, k1, k2, ties, h);
-        while (ties) {  // exact ties: the 24-bit refinement against the class's fraction
+        while (!FAST && ties) {  // exact ties: the 24-bit refinement against the class's fraction
           const uint32_t b = __builtin_ctz(ties);
           ties &= ties - 1;
           const uint32_t k = ((k0 >> b) & 1u) | (((k1 >> b) & 1u) << 1) | (((k2 >> b) & 1u) << 2);
@@ -490,8 +572,10 @@ __global__ __launch_bounds__(256) void tile_packed_kernel(const Geom g, const Rn
                                   key.k0, key.k1);
           if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) flip |= 1u << b;
         }
-        own[rb] = o ^ flip;
+        own[rb] = o ^ flip;  // with the fast decision, ties refused until resolved below
+        off = (uint32_t)(own - words) + rb;
       }
+      if (FAST) tile_ties_group<false>(tt, ties, k0, k1, wi * 32u, R, words, off, tab, key, t, c, h);
       __syncthreads();
     }
   }
@@ -526,8 +610,9 @@ __global__ __launch_bounds__(256) void tile_packed_kernel(const Geom g, const Rn
 // (tiles start at even rows), a per-byte mask.  A row's 8 prefix bytes are
 // words 2 h0, 2 h0 + 1 of its 16-site Philox block, as in the int8 16 x 16
 // kernel, so a word takes four blocks; the transpose to bit planes and the
-// compare are the packed kernel's.  Exact ties take their refinement draws at
-// once.  Four lanes a tile, 64 tiles a workgroup.
+// compare are the packed kernel's.  Exact ties take their refinement draws
+// before the pass ends, as in the tiles of 64.  Four lanes a tile, 64 tiles a
+// workgroup.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kT16Words = 14;  // per tile and colour: column (6), left (4), right (4)
 
@@ -582,9 +667,11 @@ __global__ __launch_bounds__(256) void tile16_packed_kernel(const Geom g, const 
   FastTab ft;
   if (FAST) ft = fast_tab<2>(tab);
   const uint32_t j0 = (Y0 + 4 * i) * R + x0;  // in-colour index of the word's first site
+  __shared__ TileTies tt;
   for (uint32_t h = 0; h < hits; ++h) {
 #pragma unroll
     for (uint32_t c = 0; c < 2; ++c) {
+      uint32_t ties = 0, k0 = 0, k1 = 0;
       if (valid) {
         uint32_t* own = tw + c * kT16Words;
         const uint32_t* oth = tw + (1 - c) * kT16Words;
@@ -599,7 +686,7 @@ __global__ __launch_bounds__(256) void tile16_packed_kernel(const Geom g, const 
         const uint32_t nxp = (ct & ~pm) | (sh_next & pm);
         const uint32_t nxm = (sh_prev & ~pm) | (ct & pm);
         const uint32_t u[6] = {o ^ nxp, o ^ nxm, o ^ dn, o ^ up, 0u, 0u};
-        uint32_t k0, k1, k2, ties;
+        uint32_t k2;
         count_planes<2>(u, k0, k1, k2);
         // prefix bytes: row r's 8 sites are words 2 h0, 2 h0 + 1 of block j >> 4
         uint32_t P[8];
@@ -616,7 +703,7 @@ __global__ __launch_bounds__(256) void tile16_packed_kernel(const Geom g, const 
         prefix_planes(P, B);
         uint32_t flip = FAST ? packed_compare_fast<2>(ft, B, k0, k1, k2, ties)
                              : packed_compare<2>(tab, B, k0, k1, k2, ties);
-        while (ties) {  // exact ties: the 24-bit refinement against the class's fraction
+        while (!FAST && ties) {  // exact ties: the 24-bit refinement against the class's fraction
           const uint32_t b = __builtin_ctz(ties);
           ties &= ties - 1;
           const uint32_t k = ((k0 >> b) & 1u) | (((k1 >> b) & 1u) << 1) | (((k2 >> b) & 1u) << 2);
@@ -625,8 +712,11 @@ __global__ __launch_bounds__(256) void tile16_packed_kernel(const Geom g, const 
                                   key.k1);
           if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) flip |= 1u << b;
         }
-        own[1 + i] = o ^ flip;
+        own[1 + i] = o ^ flip;  // with the fast decision, ties refused until resolved below
       }
+      if (FAST)
+        tile_ties_group<true>(tt, ties, k0, k1, j0, R, lw,
+                              gi * 2u * kT16Words + c * kT16Words + 1u + i, tab, key, t, c, h);
       __syncthreads();
     }
   }
