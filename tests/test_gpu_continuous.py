@@ -7,7 +7,7 @@ FP32), run one half-sweep, and require
   * spin components within 1e-5 of the oracle's at every site that both
     updated;
 sites inside the 1e-6 band are counted and reported, not failed.  Longer
-runs diverge chaotically, so they are compared statistically (4 sigma).
+runs diverge chaotically, so they are compared statistically (3 sigma).
 """
 import numpy as np
 import pytest
