@@ -33,7 +33,9 @@ struct IsingLaunch {
   int variant;       // IsingVariant
   uint32_t rows_per_band;  // streaming kernel: rows walked by one lane (divides L)
   int heatbath;      // rule: 0 Metropolis, 1 heat bath (table holds p_+ thresholds)
-  int packed_ties;   // packed kernel: 0 end-of-band ties resolved by the workgroup, 1 by each lane
+  int packed_ties;   // bit-packed kernels' exact ties: 0 resolved by the workgroup, 1 by each
+                     // lane, 2 by the workgroup's fallback (tied words numbered per wave;
+                     // the tile kernels: each lane)
   FastDiv divQ;      // chunks per plane row
   FastDiv divL;      // edge length
 };

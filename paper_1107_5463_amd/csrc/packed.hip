@@ -114,8 +114,9 @@ __device__ __forceinline__ void packed_queue_word(PackedTies& q, uint32_t ties, 
 // leaves about 30 per wave, so two of the four waves draw and two wait at the
 // barrier, and every spin word is still written by the lane that owns it.
 // A workgroup with a lane holding 8 or more tied sites, or more than
-// 256 kTieWords tied sites in all, resolves wave by wave instead: the wave
-// numbers its tied words and lane i draws every tied site of word i.  `idx`
+// `cap` tied sites in all (at most 256 kTieWords; 0 takes this path always),
+// resolves wave by wave instead: the wave numbers its tied words and lane i
+// draws every tied site of word i.  `idx`
 // is the workgroup's list of 256 kTieWords entries in LDS -- thread | slot
 // << 8 | the site's bit << 10 when sites are numbered, lane | slot << 6 in a
 // wave's quarter when words are -- and `wsum` four words of LDS for the
@@ -126,7 +127,7 @@ template <int D, bool MEASURE>
 __device__ __forceinline__ void packed_tie_flush_group(PackedTies& q, const TabRegs& tab,
                                                        const RngKey& key, uint32_t t, uint32_t c,
                                                        uint32_t* own, uint16_t* idx,
-                                                       uint4* ent, uint32_t* wsum) {
+                                                       uint4* ent, uint32_t* wsum, uint32_t cap) {
   static_assert(kTieWords <= 4, "queue length fits the two slot bits of an index entry");
   constexpr uint32_t kCap = kTieWords * 256u;  // entries of the workgroup's list
   const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
@@ -154,7 +155,7 @@ __device__ __forceinline__ void packed_tie_flush_group(PackedTies& q, const TabR
   const uint32_t s0 = wsum[0], s1 = wsum[1], s2 = wsum[2], s3 = wsum[3];
   const uint32_t total = s0 + s1 + s2 + s3;  // above kCap if any wave could not number
   if (total == 0u) return;  // the same for every thread: no barrier follows
-  if (total <= kCap) {
+  if (total <= cap) {
     uint32_t k = first + (wave > 0 ? s0 : 0u) + (wave > 1 ? s1 : 0u) + (wave > 2 ? s2 : 0u);
 #pragma unroll
     for (uint32_t e = 0; e < kTieWords; ++e) {
@@ -249,6 +250,7 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
                                                             uint32_t* __restrict__ s,
                                                             const uint32_t* __restrict__ J,
                                                             const uint32_t t, const uint32_t c,
+                                                            const uint32_t tie_cap,
                                                             Partial* __restrict__ parts) {
   static_assert(!WAVE || FAST, "wave resolution: the fast decision's slot layout");
   static_assert(!UB || WAVE, "a wave-uniform band only with the wave's tie resolution");
@@ -417,7 +419,7 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
     }
   }
   if (WAVE)  // the band's queued ties, every thread of the workgroup
-    packed_tie_flush_group<D, MEASURE>(tq, tab, key, t, c, own, tie_idx, tie_ent, tie_sum);
+    packed_tie_flush_group<D, MEASURE>(tq, tab, key, t, c, own, tie_idx, tie_ent, tie_sum, tie_cap);
   else
     packed_tie_flush<D, MEASURE>(tq, tab, key, t, c, own);
   if (MEASURE) {
@@ -466,11 +468,13 @@ hipError_t launch_packed_half_sweep(const IsingLaunch& a, uint32_t* spins, const
   for (int k = a.g.d; k <= 2 * a.g.d; ++k)
     if ((((k < 4 ? a.tab.al_lo : a.tab.al_hi) >> (8 * (k & 3))) & 0xFFu) != 0xFFu) fast = false;
   Partial* pp = (Partial*)partials;
-  const bool wave = a.packed_ties == 0;
+  const bool wave = a.packed_ties != 1;
+  // the workgroup's list of tied sites (packed_ties 2: its fallback always)
+  const uint32_t tie_cap = a.packed_ties == 2 ? 0u : kTieWords * 256u;
   const bool uniform_band = W % 64 == 0;  // every wave inside one band
 #define SMC_PK(DD, PMM, MM, FF, WW, UU)                                                                     \
   hipLaunchKernelGGL((packed_stream_kernel<DD, PMM, MM, FF, WW, UU>), grid, block, 0, st, a.g, a.key, a.tab, \
-                     dW, dL, H, nbands, spins, J, t, c, pp)
+                     dW, dL, H, nbands, spins, J, t, c, tie_cap, pp)
 #define SMC_PKF(DD, PMM, MM)                                        \
   do {                                                              \
     if (!fast) SMC_PK(DD, PMM, MM, false, false, false);            \

@@ -60,7 +60,7 @@ struct smc_lattice {
   bool use_fused;            // SMC_FLAG_SCHEDULE_FUSED and the fused kernel supports the shape
   uint32_t fused_rows;       // fused kernel band height (SMC_FUSED_ROWS overrides)
   uint32_t packed_rows;      // packed kernel band height (SMC_PACKED_ROWS overrides)
-  int packed_ties;           // packed kernel ties: 0 by the workgroup, 1 by each lane (SMC_PACKED_TIES)
+  int packed_ties;           // packed kernels' ties: 0 group, 1 lane, 2 group fallback (SMC_PACKED_TIES)
   bool tile_packed;          // tiled schedule: bit-packed tiles where they apply (SMC_TILE_KERNEL=byte: off)
   int cont_variant;          // ContVariant (SMC_CONT_KERNEL overrides the automatic choice)
   uint32_t cont_rows;        // continuous streaming band height (SMC_CONT_ROWS overrides)
@@ -761,6 +761,7 @@ int smc_init_lattice(smc_lattice** out, const smc_params* p, void* spins, void* 
     const std::string s(v);
     if (s == "lane") h->packed_ties = 1;
     if (s == "group" || s == "wave") h->packed_ties = 0;
+    if (s == "fallback") h->packed_ties = 2;
   }
   if (const char* v = std::getenv("SMC_PACKED_ROWS")) {
     const long H = std::strtol(v, nullptr, 10);

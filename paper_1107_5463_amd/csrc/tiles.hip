@@ -403,8 +403,8 @@ __global__ __launch_bounds__(256) void tile16_kernel(const Geom g, const RngKey 
 // accepted after all.  A pass leaves about 30 tied sites a workgroup, so one
 // wave draws where every wave did (a lane's own ties cost its wave one draw
 // each, and some lane of a wave almost always has one).  A workgroup with a
-// lane holding 8 or more tied sites, or more than kTileTieCap in all, lets
-// each lane draw its own.  Every thread of the 256-thread workgroup calls
+// lane holding 8 or more tied sites, or more than `cap` in all (at most
+// kTileTieCap; 0 takes this path always), lets each lane draw its own.  Every thread of the 256-thread workgroup calls
 // this once per pass, after storing its word with the ties refused; the
 // caller's barrier after the pass orders the flips before the next reads.
 // ---------------------------------------------------------------------------
@@ -423,7 +423,7 @@ __device__ __forceinline__ void tile_ties_group(TileTies& tt, uint32_t ties, uin
                                                 uint32_t k1, uint32_t base, uint32_t R,
                                                 uint32_t* words, uint32_t off, const TabRegs& tab,
                                                 const RngKey& key, uint32_t t, uint32_t c,
-                                                uint32_t h) {
+                                                uint32_t h, uint32_t cap) {
   auto accepts = [&](uint32_t bs, uint32_t b, uint32_t kc) -> bool {
     const uint32_t js = ROWS8 ? bs + (b >> 3) * R + (b & 7u) : bs + b;
     const Rand4 rr = philox(js, t, key.replica, tag(c, kIsingRefine) | (h << 8), key.k0, key.k1);
@@ -447,7 +447,7 @@ __device__ __forceinline__ void tile_ties_group(TileTies& tt, uint32_t ties, uin
   const uint32_t s0 = tt.wsum[0], s1 = tt.wsum[1], s2 = tt.wsum[2], s3 = tt.wsum[3];
   const uint32_t total = s0 + s1 + s2 + s3;  // above kTileTieCap if any wave could not number
   if (total == 0u) return;  // the same for every thread
-  if (total <= kTileTieCap) {
+  if (total <= cap) {
     uint32_t k = first + (wave > 0 ? s0 : 0u) + (wave > 1 ? s1 : 0u) + (wave > 2 ? s2 : 0u);
     for (uint32_t m = ties; m; m &= m - 1)
       tt.idx[k++] = (uint16_t)(threadIdx.x | ((uint32_t)__builtin_ctz(m) << 8));
@@ -492,6 +492,7 @@ __global__ __launch_bounds__(256) void tile_packed_kernel(const Geom g, const Rn
                                                           const IsingTable table, const uint32_t T,
                                                           const uint32_t hits, const uint32_t t,
                                                           const uint32_t tc, const uint32_t ntiles,
+                                                          const uint32_t tie_cap,
                                                           int8_t* __restrict__ s) {
   extern __shared__ __align__(16) int8_t lds_raw[];
   const uint32_t L = (uint32_t)g.L, R = (uint32_t)g.R;
@@ -575,7 +576,8 @@ __global__ __launch_bounds__(256) void tile_packed_kernel(const Geom g, const Rn
         own[rb] = o ^ flip;  // with the fast decision, ties refused until resolved below
         off = (uint32_t)(own - words) + rb;
       }
-      if (FAST) tile_ties_group<false>(tt, ties, k0, k1, wi * 32u, R, words, off, tab, key, t, c, h);
+      if (FAST)
+        tile_ties_group<false>(tt, ties, k0, k1, wi * 32u, R, words, off, tab, key, t, c, h, tie_cap);
       __syncthreads();
     }
   }
@@ -621,6 +623,7 @@ __global__ __launch_bounds__(256) void tile16_packed_kernel(const Geom g, const 
                                                             const IsingTable table,
                                                             const uint32_t hits, const uint32_t t,
                                                             const uint32_t tc, const uint32_t ntiles,
+                                                            const uint32_t tie_cap,
                                                             int8_t* __restrict__ s) {
   __shared__ uint32_t lw[64 * 2 * kT16Words];
   const uint32_t L = (uint32_t)g.L, R = (uint32_t)g.R;
@@ -716,7 +719,8 @@ __global__ __launch_bounds__(256) void tile16_packed_kernel(const Geom g, const 
       }
       if (FAST)
         tile_ties_group<true>(tt, ties, k0, k1, j0, R, lw,
-                              gi * 2u * kT16Words + c * kT16Words + 1u + i, tab, key, t, c, h);
+                              gi * 2u * kT16Words + c * kT16Words + 1u + i, tab, key, t, c, h,
+                              tie_cap);
       __syncthreads();
     }
   }
@@ -797,21 +801,27 @@ hipError_t launch_tile_pass(const IsingLaunch& a, bool heatbath, uint32_t T, uin
     bool fast = true;
     for (int k = a.g.d; k <= 2 * a.g.d; ++k)
       if ((((k < 4 ? a.tab.al_lo : a.tab.al_hi) >> (8 * (k & 3))) & 0xFFu) != 0xFFu) fast = false;
+    // the workgroup's list of tied sites (packed_ties other than 0: each lane its own)
+    const uint32_t tie_cap = a.packed_ties == 0 ? kTileTieCap : 0u;
     if (T == 16) {
       const dim3 grid((tiles + 63) / 64), block(256);
       if (fast)
-        hipLaunchKernelGGL((tile16_packed_kernel<true>), grid, block, 0, st, a.g, a.key, a.tab, hits, t, tc, tiles, spins);
+        hipLaunchKernelGGL((tile16_packed_kernel<true>), grid, block, 0, st, a.g, a.key, a.tab, hits, t, tc, tiles,
+                           tie_cap, spins);
       else
-        hipLaunchKernelGGL((tile16_packed_kernel<false>), grid, block, 0, st, a.g, a.key, a.tab, hits, t, tc, tiles, spins);
+        hipLaunchKernelGGL((tile16_packed_kernel<false>), grid, block, 0, st, a.g, a.key, a.tab, hits, t, tc, tiles,
+                           tie_cap, spins);
       return hipGetLastError();
     }
     const uint32_t G = tile_packed_group(T);
     const dim3 grid((tiles + G - 1) / G), block(256);
     const size_t lds = tile_packed_lds_bytes(T);
     if (fast)
-      hipLaunchKernelGGL((tile_packed_kernel<true>), grid, block, lds, st, a.g, a.key, a.tab, T, hits, t, tc, tiles, spins);
+      hipLaunchKernelGGL((tile_packed_kernel<true>), grid, block, lds, st, a.g, a.key, a.tab, T, hits, t, tc, tiles,
+                         tie_cap, spins);
     else
-      hipLaunchKernelGGL((tile_packed_kernel<false>), grid, block, lds, st, a.g, a.key, a.tab, T, hits, t, tc, tiles, spins);
+      hipLaunchKernelGGL((tile_packed_kernel<false>), grid, block, lds, st, a.g, a.key, a.tab, T, hits, t, tc, tiles,
+                         tie_cap, spins);
     return hipGetLastError();
   }
   if (T == 16) {

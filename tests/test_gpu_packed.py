@@ -56,7 +56,7 @@ SHAPES = [  # d, L, J_kind, beta, sweeps
 ]
 
 
-@pytest.mark.parametrize("ties", ["wave", "lane"])
+@pytest.mark.parametrize("ties", ["wave", "lane", "fallback"])
 @pytest.mark.parametrize("d,L,kind,beta,n", SHAPES)
 def test_sweeps_match_oracle(smc_gpu, oracle_mod, d, L, kind, beta, n, ties, monkeypatch):
     monkeypatch.setenv("SMC_PACKED_TIES", ties)
@@ -71,7 +71,7 @@ def test_sweeps_match_oracle(smc_gpu, oracle_mod, d, L, kind, beta, n, ties, mon
     assert (o.E_int, o.M_int) == (r.E_int, r.M_int)
 
 
-@pytest.mark.parametrize("ties", ["wave", "lane"])
+@pytest.mark.parametrize("ties", ["wave", "lane", "fallback"])
 @pytest.mark.parametrize("rows", ["1", "4", "16", "64"])
 def test_band_heights_give_the_same_chain(smc_gpu, oracle_mod, rows, ties, monkeypatch):
     monkeypatch.setenv("SMC_PACKED_ROWS", rows)
@@ -84,7 +84,7 @@ def test_band_heights_give_the_same_chain(smc_gpu, oracle_mod, rows, ties, monke
     assert np.array_equal(nat(smc_gpu, lat), ref.s)
 
 
-@pytest.mark.parametrize("ties", ["wave", "lane"])
+@pytest.mark.parametrize("ties", ["wave", "lane", "fallback"])
 @pytest.mark.parametrize("d,L", [(2, 128), (3, 64)])
 def test_sweep_measure_matches_oracle(smc_gpu, oracle_mod, d, L, ties, monkeypatch):
     import torch
@@ -102,7 +102,7 @@ def test_sweep_measure_matches_oracle(smc_gpu, oracle_mod, d, L, ties, monkeypat
     assert [o.sweep for o in got] == [1, 5, 5]
 
 
-@pytest.mark.parametrize("ties", ["wave", "lane"])
+@pytest.mark.parametrize("ties", ["wave", "lane", "fallback"])
 def test_many_ties_per_wave(smc_gpu, oracle_mod, ties, monkeypatch):
     """Bands of 64 rows at beta = 2 on a 2D L=4096 lattice (a wave is one
     plane row's 64 word columns): a lane meets a tied word every 8 to 25 words

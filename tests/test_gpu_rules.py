@@ -73,11 +73,15 @@ PACKED_TILES = [  # L, tile, hits, J0, beta, sweeps
 ]
 
 
+@pytest.mark.parametrize("ties", ["group", "lane"])
 @pytest.mark.parametrize("L,T,k,J0,beta,n", PACKED_TILES)
-def test_packed_tiles_match_oracle(smc_gpu, oracle_mod, L, T, k, J0, beta, n):
+def test_packed_tiles_match_oracle(smc_gpu, oracle_mod, monkeypatch, L, T, k, J0, beta, n, ties):
     """The bit-packed tile kernels (2D, Metropolis, T = 16, 64 or 128) against
-    the oracle's tiled schedule, bit for bit, with the measurement after it."""
-    print(f"packed tiles L={L} T={T} k={k} J0={J0} beta={beta}", flush=True)
+    the oracle's tiled schedule, bit for bit, with the measurement after it;
+    exact ties resolved by the workgroup, or (its fallback) each lane drawing
+    its own."""
+    monkeypatch.setenv("SMC_PACKED_TIES", ties)
+    print(f"packed tiles L={L} T={T} k={k} J0={J0} beta={beta} ties={ties}", flush=True)
     lat = smc_gpu.Lattice(2, 1, L, seed=13, J0=J0, tile=T, hits=k)
     assert lat.kernel() == ("ising_tiles_packed", T)
     ref = oracle_mod.OracleLattice(2, 1, L, 13, J0=J0)
