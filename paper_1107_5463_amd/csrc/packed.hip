@@ -238,10 +238,12 @@ __device__ __forceinline__ void packed_tie_flush_group(PackedTies& q, const TabR
 // packed_decide_fast; otherwise packed_decide.  WAVE (with FAST): the
 // end-of-band ties are resolved by the whole workgroup
 // (packed_tie_flush_group).
-// UB (with WAVE): a plane row is a multiple of 64 words, so the 64 lanes of a
-// wave share their band, and the band's row arithmetic runs once per wave in
-// scalar registers.
-template <int D, bool PM, bool MEASURE, bool FAST, bool WAVE, bool UB>
+// WM (with WAVE): kWaveBand when a plane row is a multiple of 64 words, so
+// the 64 lanes of a wave share their band and the band's row arithmetic runs
+// once per wave in scalar registers; kWaveFallback to resolve the ties by the
+// workgroup resolution's fallback always (a test of that path).
+constexpr int kWaveAny = 0, kWaveBand = 1, kWaveFallback = 2;
+template <int D, bool PM, bool MEASURE, bool FAST, bool WAVE, int WM>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void packed_stream_kernel(const Geom g, const RngKey key,
                                                             const IsingTable table,
@@ -250,10 +252,10 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
                                                             uint32_t* __restrict__ s,
                                                             const uint32_t* __restrict__ J,
                                                             const uint32_t t, const uint32_t c,
-                                                            const uint32_t tie_cap,
                                                             Partial* __restrict__ parts) {
+  constexpr bool UB = WM == kWaveBand;
   static_assert(!WAVE || FAST, "wave resolution: the fast decision's slot layout");
-  static_assert(!UB || WAVE, "a wave-uniform band only with the wave's tie resolution");
+  static_assert(WM == kWaveAny || WAVE, "wave modes only with the workgroup's tie resolution");
   __shared__ uint4 tie_ent[kTieWords * 256];
   __shared__ uint8_t tie_rows[WAVE ? 1 : kTieWords * 256];
   __shared__ uint16_t tie_idx[WAVE ? kTieWords * 256 : 1];
@@ -419,7 +421,8 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
     }
   }
   if (WAVE)  // the band's queued ties, every thread of the workgroup
-    packed_tie_flush_group<D, MEASURE>(tq, tab, key, t, c, own, tie_idx, tie_ent, tie_sum, tie_cap);
+    packed_tie_flush_group<D, MEASURE>(tq, tab, key, t, c, own, tie_idx, tie_ent, tie_sum,
+                                       WM == kWaveFallback ? 0u : kTieWords * 256u);
   else
     packed_tie_flush<D, MEASURE>(tq, tab, key, t, c, own);
   if (MEASURE) {
@@ -469,18 +472,17 @@ hipError_t launch_packed_half_sweep(const IsingLaunch& a, uint32_t* spins, const
     if ((((k < 4 ? a.tab.al_lo : a.tab.al_hi) >> (8 * (k & 3))) & 0xFFu) != 0xFFu) fast = false;
   Partial* pp = (Partial*)partials;
   const bool wave = a.packed_ties != 1;
-  // the workgroup's list of tied sites (packed_ties 2: its fallback always)
-  const uint32_t tie_cap = a.packed_ties == 2 ? 0u : kTieWords * 256u;
   const bool uniform_band = W % 64 == 0;  // every wave inside one band
 #define SMC_PK(DD, PMM, MM, FF, WW, UU)                                                                     \
   hipLaunchKernelGGL((packed_stream_kernel<DD, PMM, MM, FF, WW, UU>), grid, block, 0, st, a.g, a.key, a.tab, \
-                     dW, dL, H, nbands, spins, J, t, c, tie_cap, pp)
-#define SMC_PKF(DD, PMM, MM)                                        \
-  do {                                                              \
-    if (!fast) SMC_PK(DD, PMM, MM, false, false, false);            \
-    else if (!wave) SMC_PK(DD, PMM, MM, true, false, false);        \
-    else if (!uniform_band) SMC_PK(DD, PMM, MM, true, true, false); \
-    else SMC_PK(DD, PMM, MM, true, true, true);                     \
+                     dW, dL, H, nbands, spins, J, t, c, pp)
+#define SMC_PKF(DD, PMM, MM)                                                   \
+  do {                                                                         \
+    if (!fast) SMC_PK(DD, PMM, MM, false, false, kWaveAny);                    \
+    else if (!wave) SMC_PK(DD, PMM, MM, true, false, kWaveAny);                \
+    else if (a.packed_ties == 2) SMC_PK(DD, PMM, MM, true, true, kWaveFallback); \
+    else if (!uniform_band) SMC_PK(DD, PMM, MM, true, true, kWaveAny);         \
+    else SMC_PK(DD, PMM, MM, true, true, kWaveBand);                           \
   } while (0)
   if (a.g.d == 2) {
     if (pm) { if (pp) SMC_PKF(2, true, true); else SMC_PKF(2, true, false); }
