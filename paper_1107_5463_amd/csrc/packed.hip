@@ -240,9 +240,12 @@ __device__ __forceinline__ void packed_tie_flush_group(PackedTies& q, const TabR
 // (packed_tie_flush_group).
 // WM (with WAVE): kWaveBand when a plane row is a multiple of 64 words, so
 // the 64 lanes of a wave share their band and the band's row arithmetic runs
-// once per wave in scalar registers; kWaveFallback to resolve the ties by the
-// workgroup resolution's fallback always (a test of that path).
-constexpr int kWaveAny = 0, kWaveBand = 1, kWaveFallback = 2;
+// once per wave in scalar registers; kWaveParity when a row is fewer words
+// that divide 64, the band height is even and a wave's bands lie in one
+// z-plane, so the wave's rows still share their parity; kWaveFallback to
+// resolve the ties by the workgroup resolution's fallback always (a test of
+// that path).
+constexpr int kWaveAny = 0, kWaveBand = 1, kWaveFallback = 2, kWaveParity = 3;
 template <int D, bool PM, bool MEASURE, bool FAST, bool WAVE, int WM>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void packed_stream_kernel(const Geom g, const RngKey key,
@@ -254,6 +257,7 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
                                                             const uint32_t t, const uint32_t c,
                                                             Partial* __restrict__ parts) {
   constexpr bool UB = WM == kWaveBand;
+  constexpr bool WP = UB || WM == kWaveParity;  // the wave's rows share their parity
   static_assert(!WAVE || FAST, "wave resolution: the fast decision's slot layout");
   static_assert(WM == kWaveAny || WAVE, "wave modes only with the workgroup's tie resolution");
   __shared__ uint4 tie_ent[kTieWords * 256];
@@ -403,9 +407,10 @@ __attribute__((amdgpu_waves_per_eu((MEASURE || (D == 3 && PM)) ? 1 : 8))) void p
     };
     using P0 = std::integral_constant<uint32_t, 0>;
     using P1 = std::integral_constant<uint32_t, 1>;
-    if (UB && (H & 1u) == 0u) {
+    if (WP && (H & 1u) == 0u) {
       // the wave's rows share their parity, which alternates along the band
-      if ((pz + y0) & 1u) {
+      // (the bands start at even rows of one z-plane)
+      if (__builtin_amdgcn_readfirstlane((pz + y0) & 1u)) {
         for (uint32_t i = 0; i < H; i += 2) {
           row(i, P1());
           row(i + 1, P0());
@@ -473,6 +478,9 @@ hipError_t launch_packed_half_sweep(const IsingLaunch& a, uint32_t* spins, const
   Partial* pp = (Partial*)partials;
   const bool wave = a.packed_ties != 1;
   const bool uniform_band = W % 64 == 0;  // every wave inside one band
+  // a wave's 64 / W bands start at even rows of one z-plane
+  const bool wave_parity = 64 % W == 0 && H % 2 == 0 &&
+                           (a.g.d == 2 || (uint32_t)a.g.L % ((64 / W) * H) == 0);
 #define SMC_PK(DD, PMM, MM, FF, WW, UU)                                                                     \
   hipLaunchKernelGGL((packed_stream_kernel<DD, PMM, MM, FF, WW, UU>), grid, block, 0, st, a.g, a.key, a.tab, \
                      dW, dL, H, nbands, spins, J, t, c, pp)
@@ -481,6 +489,7 @@ hipError_t launch_packed_half_sweep(const IsingLaunch& a, uint32_t* spins, const
     if (!fast) SMC_PK(DD, PMM, MM, false, false, kWaveAny);                    \
     else if (!wave) SMC_PK(DD, PMM, MM, true, false, kWaveAny);                \
     else if (a.packed_ties == 2) SMC_PK(DD, PMM, MM, true, true, kWaveFallback); \
+    else if (!uniform_band && wave_parity) SMC_PK(DD, PMM, MM, true, true, kWaveParity); \
     else if (!uniform_band) SMC_PK(DD, PMM, MM, true, true, kWaveAny);         \
     else SMC_PK(DD, PMM, MM, true, true, kWaveBand);                           \
   } while (0)
