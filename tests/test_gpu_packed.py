@@ -151,6 +151,30 @@ def test_wave_uniform_bands_match_oracle(smc_gpu, oracle_mod, kind):
     assert np.array_equal(nat(smc_gpu, lat), ref.s)
 
 
+@pytest.mark.parametrize("rows", ["2", "4"])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_wave_parity_bands_3d_match_oracle(smc_gpu, oracle_mod, rows, kind, monkeypatch):
+    """3D L=128: a plane row is 2 words, so a wave holds 32 bands; with an even
+    band height they lie in one z-plane and share their rows' parity, which
+    the kernel then takes as a compile-time constant.  Plain and measured
+    sweeps, uniform and +-1 couplings, bit for bit."""
+    import torch
+    monkeypatch.setenv("SMC_PACKED_ROWS", rows)
+    L = 128
+    print(f"packed wave-parity bands 3D L={L} rows={rows} kind={kind}", flush=True)
+    lat = smc_gpu.Lattice(3, 1, L, seed=41 + kind, J_kind=kind, packed=True)
+    assert lat.kernel() == ("ising_packed", int(rows))
+    ref = oracle_mod.OracleLattice(3, 1, L, 41 + kind, J_kind=kind)
+    lat.sweep(0.2216546, 2)
+    ref.sweep(0.2216546, 2)
+    slot = torch.zeros((1, 8), dtype=torch.int64, device=lat.device)
+    lat.sweep_measure(0.2216546, 1, slot[0])
+    ref.sweep(0.2216546, 1)
+    got, r = smc_gpu.Lattice.decode_obs(slot)[0], ref.measure()
+    assert (got.E_int, got.M_int) == (r.E_int, r.M_int)
+    assert np.array_equal(nat(smc_gpu, lat), ref.s)
+
+
 def test_special_temperatures(smc_gpu, oracle_mod):
     for beta in (0.0, float("inf")):
         lat = smc_gpu.Lattice(2, 1, 64, seed=9, packed=True)
