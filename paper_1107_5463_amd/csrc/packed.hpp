@@ -189,7 +189,9 @@ __device__ __forceinline__ uint32_t packed_compare(const TabRegs& tab, const uin
   // > 0) can refuse a move: they are added without branches, a class whose
   // threshold reaches 2^32 (the table's always-accept flag, also every k < d
   // when J0 <= 0) masked out by a wave-uniform mask.  The classes k > d refuse
-  // only when J0 < 0 and are added behind wave-uniform branches.
+  // only when J0 < 0 and are added behind wave-uniform branches, as is class
+  // d (Delta E = 0, always accepted; under the heat-bath rule, whose classes
+  // count up neighbours, the class of a zero field).
   uint32_t T[8];
   uint32_t refus = 0;
   auto add_class = [&](auto kv) {
@@ -218,6 +220,7 @@ __device__ __forceinline__ uint32_t packed_compare(const TabRegs& tab, const uin
   add_class(std::integral_constant<int, 0>());
   add_class(std::integral_constant<int, 1>());
   if constexpr (D == 3) add_class(std::integral_constant<int, 2>());
+  add_class_if(std::integral_constant<int, D>());
   add_class_if(std::integral_constant<int, D + 1>());
   add_class_if(std::integral_constant<int, D + 2>());
   if constexpr (D == 3) add_class_if(std::integral_constant<int, 6>());

@@ -472,22 +472,25 @@ __device__ __forceinline__ void tile_ties_group(TileTies& tt, uint32_t ties, uin
 }
 
 // ---------------------------------------------------------------------------
-// Bit-packed tiles (2D, T % 64 == 0, Metropolis, uniform couplings): a tile
-// and its boundary layer sit in LDS at one bit per site.  Per colour, LDS row
-// r (0 .. T + 1; rows 0 and T + 1 are the boundary rows) holds the T / 64
-// words of the tile row's T / 2 same-colour sites (site 32 i + b of the row
-// in bit b of word i, bit 1 = spin -1), framed by a word with the site before
-// the row in bit 31 and one with the site after it in bit 0, so the in-row
-// neighbours are funnel shifts, as in the packed streaming kernel.  A lane
-// owns one word of a tile row of each colour for all k hits and decides its
-// 32 sites with that kernel's bit-sliced decision, drawing the same prefix
-// bytes (the hit in the counter); exact ties take their refinement draws
-// before the pass ends (shared by the workgroup under the fast decision,
-// tile_ties_group).  Every site makes the int8 tile kernel's decision, so the chain is
-// the same bit for bit.  T = 64 (a tile is one wave, four to a workgroup) or
-// T = 128 (a tile is one 256-lane workgroup).
+// Bit-packed tiles (2D, T % 64 == 0, uniform couplings, Metropolis or heat
+// bath): a tile and its boundary layer sit in LDS at one bit per site.  Per
+// colour, LDS row r (0 .. T + 1; rows 0 and T + 1 are the boundary rows)
+// holds the T / 64 words of the tile row's T / 2 same-colour sites (site
+// 32 i + b of the row in bit b of word i, bit 1 = spin -1), framed by a word
+// with the site before the row in bit 31 and one with the site after it in
+// bit 0, so the in-row neighbours are funnel shifts, as in the packed
+// streaming kernel.  A lane owns one word of a tile row of each colour for
+// all k hits and decides its 32 sites with that kernel's bit-sliced decision,
+// drawing the same prefix bytes (the hit in the counter): Metropolis by the
+// count of unsatisfied bonds, heat bath (HB) by the count of up neighbours,
+// whose class threshold the prefix must stay below for the spin to come out
+// up.  Exact ties take their refinement draws before the pass ends (shared
+// by the workgroup under the fast decision, tile_ties_group).  Every site
+// makes the int8 tile kernel's decision, so the chain is the same bit for
+// bit.  T = 64 (a tile is one wave, four to a workgroup) or T = 128 (a tile
+// is one 256-lane workgroup).
 // ---------------------------------------------------------------------------
-template <bool FAST>
+template <bool FAST, bool HB>
 __global__ __launch_bounds__(256) void tile_packed_kernel(const Geom g, const RngKey key,
                                                           const IsingTable table, const uint32_t T,
                                                           const uint32_t hits, const uint32_t t,
@@ -559,10 +562,15 @@ __global__ __launch_bounds__(256) void tile_packed_kernel(const Geom g, const Rn
         // x + 1 neighbours (p = 1: next in-row site) and x - 1 (p = 0: previous)
         const uint32_t sh_next = __builtin_amdgcn_alignbit(en, ct, 1u);
         const uint32_t sh_prev = __builtin_amdgcn_alignbit(ct, ep, 31u);
-        const uint32_t u[6] = {o ^ mask_sel(ct, sh_next, p), o ^ mask_sel(sh_prev, ct, p), o ^ dn,
-                               o ^ up, 0u, 0u};
+        const uint32_t nxp = mask_sel(ct, sh_next, p), nxm = mask_sel(sh_prev, ct, p);
+        // Metropolis: the unsatisfied bonds (class k = their count); heat
+        // bath: the up neighbours (bit 0; class = their number), whose
+        // table's threshold is that of the spin coming out up
+        const uint32_t u[6] = {HB ? ~nxp : o ^ nxp, HB ? ~nxm : o ^ nxm, HB ? ~dn : o ^ dn,
+                               HB ? ~up : o ^ up, 0u, 0u};
         uint32_t k2;
         count_planes<2>(u, k0, k1, k2);
+        // `flip`: Metropolis, the accepted flips; heat bath, the sites coming out up
         uint32_t flip = FAST ? packed_decide_fast<2>(ft, key, t, c, wi, k0, k1, k2, ties, h)
                              : packed_decide<2>(tab, key, t, c, wi, k0, k1, k2, ties, h);
         while (!FAST && ties) {  // exact ties: the 24-bit refinement against the class's fraction
@@ -573,7 +581,7 @@ __global__ __launch_bounds__(256) void tile_packed_kernel(const Geom g, const Rn
                                   key.k0, key.k1);
           if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) flip |= 1u << b;
         }
-        own[rb] = o ^ flip;  // with the fast decision, ties refused until resolved below
+        own[rb] = HB ? ~flip : o ^ flip;  // with the fast decision, ties refused until resolved below
         off = (uint32_t)(own - words) + rb;
       }
       if (FAST)
@@ -600,7 +608,7 @@ __global__ __launch_bounds__(256) void tile_packed_kernel(const Geom g, const Rn
 }
 
 // ---------------------------------------------------------------------------
-// Bit-packed 16 x 16 tiles (2D, Metropolis): a tile row holds 8 sites of a
+// Bit-packed 16 x 16 tiles (2D, Metropolis or heat bath): a tile row holds 8 sites of a
 // colour, so a word packs four tile rows -- word i of a tile's colour holds
 // rows 4i .. 4i + 3 of the tile, site s of row r in bit 8 r + s (bit 1 = spin
 // -1).  Per tile and colour, LDS holds the column [above, w0, w1, w2, w3,
@@ -618,7 +626,7 @@ __global__ __launch_bounds__(256) void tile_packed_kernel(const Geom g, const Rn
 // ---------------------------------------------------------------------------
 constexpr uint32_t kT16Words = 14;  // per tile and colour: column (6), left (4), right (4)
 
-template <bool FAST>
+template <bool FAST, bool HB>
 __global__ __launch_bounds__(256) void tile16_packed_kernel(const Geom g, const RngKey key,
                                                             const IsingTable table,
                                                             const uint32_t hits, const uint32_t t,
@@ -688,7 +696,9 @@ __global__ __launch_bounds__(256) void tile16_packed_kernel(const Geom g, const 
         const uint32_t pm = P1[c];
         const uint32_t nxp = (ct & ~pm) | (sh_next & pm);
         const uint32_t nxm = (sh_prev & ~pm) | (ct & pm);
-        const uint32_t u[6] = {o ^ nxp, o ^ nxm, o ^ dn, o ^ up, 0u, 0u};
+        // Metropolis: the unsatisfied bonds; heat bath: the up neighbours
+        const uint32_t u[6] = {HB ? ~nxp : o ^ nxp, HB ? ~nxm : o ^ nxm, HB ? ~dn : o ^ dn,
+                               HB ? ~up : o ^ up, 0u, 0u};
         uint32_t k2;
         count_planes<2>(u, k0, k1, k2);
         // prefix bytes: row r's 8 sites are words 2 h0, 2 h0 + 1 of block j >> 4
@@ -715,7 +725,7 @@ __global__ __launch_bounds__(256) void tile16_packed_kernel(const Geom g, const 
                                   key.k1);
           if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) flip |= 1u << b;
         }
-        own[1 + i] = o ^ flip;  // with the fast decision, ties refused until resolved below
+        own[1 + i] = HB ? ~flip : o ^ flip;  // with the fast decision, ties refused until resolved below
       }
       if (FAST)
         tile_ties_group<true>(tt, ties, k0, k1, j0, R, lw,
@@ -747,7 +757,8 @@ __global__ __launch_bounds__(256) void tile16_packed_kernel(const Geom g, const 
 }
 
 bool tile_packed_supported(const Geom& g, uint32_t T, bool heatbath) {
-  return g.d == 2 && !heatbath && (T == 16 || T == 64 || T == 128) && (uint32_t)g.L % T == 0 &&
+  (void)heatbath;  // both rules
+  return g.d == 2 && (T == 16 || T == 64 || T == 128) && (uint32_t)g.L % T == 0 &&
          ((uint32_t)g.L / T) % 2 == 0;
 }
 
@@ -805,23 +816,29 @@ hipError_t launch_tile_pass(const IsingLaunch& a, bool heatbath, uint32_t T, uin
     const uint32_t tie_cap = a.packed_ties == 0 ? kTileTieCap : 0u;
     if (T == 16) {
       const dim3 grid((tiles + 63) / 64), block(256);
-      if (fast)
-        hipLaunchKernelGGL((tile16_packed_kernel<true>), grid, block, 0, st, a.g, a.key, a.tab, hits, t, tc, tiles,
-                           tie_cap, spins);
+      if (heatbath)
+        hipLaunchKernelGGL((tile16_packed_kernel<false, true>), grid, block, 0, st, a.g, a.key, a.tab, hits, t,
+                           tc, tiles, tie_cap, spins);
+      else if (fast)
+        hipLaunchKernelGGL((tile16_packed_kernel<true, false>), grid, block, 0, st, a.g, a.key, a.tab, hits, t,
+                           tc, tiles, tie_cap, spins);
       else
-        hipLaunchKernelGGL((tile16_packed_kernel<false>), grid, block, 0, st, a.g, a.key, a.tab, hits, t, tc, tiles,
-                           tie_cap, spins);
+        hipLaunchKernelGGL((tile16_packed_kernel<false, false>), grid, block, 0, st, a.g, a.key, a.tab, hits, t,
+                           tc, tiles, tie_cap, spins);
       return hipGetLastError();
     }
     const uint32_t G = tile_packed_group(T);
     const dim3 grid((tiles + G - 1) / G), block(256);
     const size_t lds = tile_packed_lds_bytes(T);
-    if (fast)
-      hipLaunchKernelGGL((tile_packed_kernel<true>), grid, block, lds, st, a.g, a.key, a.tab, T, hits, t, tc, tiles,
-                         tie_cap, spins);
+    if (heatbath)
+      hipLaunchKernelGGL((tile_packed_kernel<false, true>), grid, block, lds, st, a.g, a.key, a.tab, T, hits, t,
+                         tc, tiles, tie_cap, spins);
+    else if (fast)
+      hipLaunchKernelGGL((tile_packed_kernel<true, false>), grid, block, lds, st, a.g, a.key, a.tab, T, hits, t,
+                         tc, tiles, tie_cap, spins);
     else
-      hipLaunchKernelGGL((tile_packed_kernel<false>), grid, block, lds, st, a.g, a.key, a.tab, T, hits, t, tc, tiles,
-                         tie_cap, spins);
+      hipLaunchKernelGGL((tile_packed_kernel<false, false>), grid, block, lds, st, a.g, a.key, a.tab, T, hits, t,
+                         tc, tiles, tie_cap, spins);
     return hipGetLastError();
   }
   if (T == 16) {

@@ -42,8 +42,8 @@ TILED = [  # d, L, tile, hits, heatbath, beta, sweeps
 
 
 def _tile_kernel_name(d, T, hb):
-    # 2D Metropolis tiles of 16, 64 or 128 take the bit-packed tile kernels
-    return "ising_tiles_packed" if d == 2 and not hb and T in (16, 64, 128) else "ising_tiles"
+    # 2D tiles of 16, 64 or 128 (either rule) take the bit-packed tile kernels
+    return "ising_tiles_packed" if d == 2 and T in (16, 64, 128) else "ising_tiles"
 
 
 @pytest.mark.parametrize("d,L,T,k,hb,beta,n", TILED)
@@ -92,9 +92,11 @@ def test_packed_tiles_match_oracle(smc_gpu, oracle_mod, monkeypatch, L, T, k, J0
     assert (o.E_int, o.M_int) == (r.E_int, r.M_int)
 
 
+@pytest.mark.parametrize("hb", [False, True])
 @pytest.mark.parametrize("T", [16, 64, 128])
-def test_packed_and_byte_tiles_run_the_same_chain(smc_gpu, monkeypatch, T):
-    """Both tile kernels on a 2D L=1024 lattice, k = 5 hits: the same states."""
+def test_packed_and_byte_tiles_run_the_same_chain(smc_gpu, monkeypatch, T, hb):
+    """Both tile kernels on a 2D L=1024 lattice, k = 5 hits, either rule: the
+    same states."""
     import torch
     states = {}
     for kernel in ("byte", "packed"):
@@ -102,11 +104,37 @@ def test_packed_and_byte_tiles_run_the_same_chain(smc_gpu, monkeypatch, T):
             monkeypatch.setenv("SMC_TILE_KERNEL", "byte")
         else:
             monkeypatch.delenv("SMC_TILE_KERNEL", raising=False)
-        lat = smc_gpu.Lattice(2, 1, 1024, seed=17, tile=T, hits=5)
+        lat = smc_gpu.Lattice(2, 1, 1024, seed=17, tile=T, hits=5, heatbath=hb)
         assert lat.kernel()[0] == ("ising_tiles" if kernel == "byte" else "ising_tiles_packed")
         lat.sweep(BETA_C, 3)
         states[kernel] = lat.spins.clone()
     assert torch.equal(states["byte"], states["packed"])
+
+
+PACKED_HB_TILES = [  # L, tile, hits, J0, beta, sweeps
+    (128, 64, 3, 1.0, BETA_C, 3),
+    (256, 128, 2, 1.0, 0.6, 2),
+    (128, 64, 2, -1.0, 0.5, 2),        # J0 < 0
+    (96, 16, 3, 1.0, BETA_C, 3),       # the paper's 16 x 16 tiles
+    (64, 16, 2, 1.0, 2.0, 3),          # low temperature
+    (128, 64, 2, 1.0, float("inf"), 2),  # thresholds 0, 2^31 and 2^32
+]
+
+
+@pytest.mark.parametrize("L,T,k,J0,beta,n", PACKED_HB_TILES)
+def test_packed_heatbath_tiles_match_oracle(smc_gpu, oracle_mod, L, T, k, J0, beta, n):
+    """The bit-packed tile kernels under the heat-bath rule (the class of a
+    site is its number of up neighbours) against the oracle's tiled schedule,
+    bit for bit, with the measurement after it."""
+    print(f"packed heat-bath tiles L={L} T={T} k={k} J0={J0} beta={beta}", flush=True)
+    lat = smc_gpu.Lattice(2, 1, L, seed=19, J0=J0, tile=T, hits=k, heatbath=True)
+    assert lat.kernel() == ("ising_tiles_packed", T)
+    ref = oracle_mod.OracleLattice(2, 1, L, 19, J0=J0)
+    lat.sweep(beta, n)
+    ref.sweep_rule(beta, n, "heatbath", T, k)
+    assert np.array_equal(nat(lat), ref.s)
+    o, r = lat.measure(), ref.measure()
+    assert (o.E_int, o.M_int) == (r.E_int, r.M_int)
 
 
 def test_tiled_sweep_measure(smc_gpu, oracle_mod):
