@@ -394,33 +394,37 @@ __global__ __launch_bounds__(256) void tile16_kernel(const Geom g, const RngKey 
 }
 
 // ---------------------------------------------------------------------------
-// Exact ties of a bit-packed tile pass under the fast decision (J0 > 0: only
-// the classes k < 2 refuse, so a tied site's class is k0 + 2 k1), resolved by
-// the workgroup instead of by each lane: ballot prefix sums of the lanes'
-// counts of tied sites number the sites within each wave, the four waves'
-// totals go through LDS, thread i draws the refinement of tied site i and
-// flips the site in its owner's LDS word (an LDS atomic xor) if the move is
-// accepted after all.  A pass leaves about 30 tied sites a workgroup, so one
-// wave draws where every wave did (a lane's own ties cost its wave one draw
-// each, and some lane of a wave almost always has one).  A workgroup with a
-// lane holding 8 or more tied sites, or more than `cap` in all (at most
-// kTileTieCap; 0 takes this path always), lets each lane draw its own.  Every thread of the 256-thread workgroup calls
-// this once per pass, after storing its word with the ties refused; the
-// caller's barrier after the pass orders the flips before the next reads.
+// Exact ties of a bit-packed tile pass, resolved by the workgroup instead of
+// by each lane: ballot prefix sums of the lanes' counts of tied sites number
+// the sites within each wave, the four waves' totals go through LDS, thread
+// i draws the refinement of tied site i and toggles the site in its owner's
+// LDS word (an LDS atomic xor) if the move is accepted after all -- the
+// owner stored the word with its ties refused (Metropolis: left as they
+// were; heat bath: down).  A pass leaves about 30 tied sites a workgroup, so
+// one wave draws where every wave did (a lane's own ties cost its wave one
+// draw each, and some lane of a wave almost always has one).  A workgroup
+// with a lane holding 8 or more tied sites, or more than `cap` in all (at
+// most kTileTieCap; 0 takes this path always), lets each lane draw its own.
+// Every thread of the 256-thread workgroup calls this once per pass, after
+// storing its word; the caller's barrier after the pass orders the flips
+// before the next reads.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kTileTieCap = 512;  // entries of the workgroup's list of tied sites
 
 struct TileTies {
   uint4 ent[256];             // per thread: k0, k1, first site, LDS index of its word
+  uint32_t k2[256];           // per thread: k2 (classes of 4 or more, K2)
   uint16_t idx[kTileTieCap];  // thread | bit << 8
   uint32_t wsum[4];           // the waves' counts of tied sites
 };
 
 // ROWS8: bit b of a word is site base + (b >> 3) R + (b & 7) (four tile rows
-// of 8 sites), else site base + b.
-template <bool ROWS8>
+// of 8 sites), else site base + b.  K2: a tied site's class can reach 4 (the
+// general decision), else it is k0 + 2 k1 (the fast decision: only k < 2
+// refuses).
+template <bool ROWS8, bool K2>
 __device__ __forceinline__ void tile_ties_group(TileTies& tt, uint32_t ties, uint32_t k0,
-                                                uint32_t k1, uint32_t base, uint32_t R,
+                                                uint32_t k1, uint32_t k2, uint32_t base, uint32_t R,
                                                 uint32_t* words, uint32_t off, const TabRegs& tab,
                                                 const RngKey& key, uint32_t t, uint32_t c,
                                                 uint32_t h, uint32_t cap) {
@@ -435,6 +439,7 @@ __device__ __forceinline__ void tile_ties_group(TileTies& tt, uint32_t ties, uin
   const uint32_t lane = __lane_id(), wave = threadIdx.x >> 6;
   const uint32_t ns = (uint32_t)__builtin_popcount(ties);
   tt.ent[threadIdx.x] = make_uint4(k0, k1, base, off);
+  if (K2) tt.k2[threadIdx.x] = k2;
   const bool few = __ballot(ns >= 8u) == 0;  // every lane's count fits three bits
   uint32_t wtotal = 0, first = 0;
   if (few) {
@@ -457,15 +462,17 @@ __device__ __forceinline__ void tile_ties_group(TileTies& tt, uint32_t ties, uin
       if (i < total) {
         const uint32_t id = tt.idx[i], b = id >> 8;
         const uint4 en = tt.ent[id & 255u];
-        if (accepts(en.z, b, ((en.x >> b) & 1u) | (((en.y >> b) & 1u) << 1)))
-          atomicXor(words + en.w, 1u << b);
+        const uint32_t kc = ((en.x >> b) & 1u) | (((en.y >> b) & 1u) << 1) |
+                            (K2 ? ((tt.k2[id & 255u] >> b) & 1u) << 2 : 0u);
+        if (accepts(en.z, b, kc)) atomicXor(words + en.w, 1u << b);
       }
     }
   } else {
     uint32_t flips = 0;
     for (uint32_t m = ties; m; m &= m - 1) {
       const uint32_t b = (uint32_t)__builtin_ctz(m);
-      if (accepts(base, b, ((k0 >> b) & 1u) | (((k1 >> b) & 1u) << 1))) flips |= 1u << b;
+      const uint32_t kc = ((k0 >> b) & 1u) | (((k1 >> b) & 1u) << 1) | (K2 ? ((k2 >> b) & 1u) << 2 : 0u);
+      if (accepts(base, b, kc)) flips |= 1u << b;
     }
     if (flips) words[off] ^= flips;  // the lane's own word
   }
@@ -485,7 +492,7 @@ __device__ __forceinline__ void tile_ties_group(TileTies& tt, uint32_t ties, uin
 // count of unsatisfied bonds, heat bath (HB) by the count of up neighbours,
 // whose class threshold the prefix must stay below for the spin to come out
 // up.  Exact ties take their refinement draws before the pass ends (shared
-// by the workgroup under the fast decision, tile_ties_group).  Every site
+// by the workgroup, tile_ties_group).  Every site
 // makes the int8 tile kernel's decision, so the chain is the same bit for
 // bit.  T = 64 (a tile is one wave, four to a workgroup) or T = 128 (a tile
 // is one 256-lane workgroup).
@@ -552,7 +559,7 @@ __global__ __launch_bounds__(256) void tile_packed_kernel(const Geom g, const Rn
   for (uint32_t h = 0; h < hits; ++h) {
 #pragma unroll
     for (uint32_t c = 0; c < 2; ++c) {
-      uint32_t ties = 0, k0 = 0, k1 = 0, off = 0;
+      uint32_t ties = 0, k0 = 0, k1 = 0, k2 = 0, off = 0;
       if (valid) {
         uint32_t* own = lw + c * PL;
         const uint32_t* oth = lw + (1 - c) * PL;
@@ -568,24 +575,16 @@ __global__ __launch_bounds__(256) void tile_packed_kernel(const Geom g, const Rn
         // table's threshold is that of the spin coming out up
         const uint32_t u[6] = {HB ? ~nxp : o ^ nxp, HB ? ~nxm : o ^ nxm, HB ? ~dn : o ^ dn,
                                HB ? ~up : o ^ up, 0u, 0u};
-        uint32_t k2;
         count_planes<2>(u, k0, k1, k2);
-        // `flip`: Metropolis, the accepted flips; heat bath, the sites coming out up
-        uint32_t flip = FAST ? packed_decide_fast<2>(ft, key, t, c, wi, k0, k1, k2, ties, h)
-                             : packed_decide<2>(tab, key, t, c, wi, k0, k1, k2, ties, h);
-        while (!FAST && ties) {  // exact ties: the 24-bit refinement against the class's fraction
-          const uint32_t b = __builtin_ctz(ties);
-          ties &= ties - 1;
-          const uint32_t k = ((k0 >> b) & 1u) | (((k1 >> b) & 1u) << 1) | (((k2 >> b) & 1u) << 2);
-          const Rand4 rr = philox(wi * 32u + b, t, key.replica, tag(c, kIsingRefine) | (h << 8),
-                                  key.k0, key.k1);
-          if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) flip |= 1u << b;
-        }
-        own[rb] = HB ? ~flip : o ^ flip;  // with the fast decision, ties refused until resolved below
+        // `flip`: Metropolis, the accepted flips; heat bath, the sites coming
+        // out up -- exact ties refused, resolved below
+        const uint32_t flip = FAST ? packed_decide_fast<2>(ft, key, t, c, wi, k0, k1, k2, ties, h)
+                                   : packed_decide<2>(tab, key, t, c, wi, k0, k1, k2, ties, h);
+        own[rb] = HB ? ~flip : o ^ flip;
         off = (uint32_t)(own - words) + rb;
       }
-      if (FAST)
-        tile_ties_group<false>(tt, ties, k0, k1, wi * 32u, R, words, off, tab, key, t, c, h, tie_cap);
+      tile_ties_group<false, !FAST>(tt, ties, k0, k1, k2, wi * 32u, R, words, off, tab, key, t, c, h,
+                                    tie_cap);
       __syncthreads();
     }
   }
@@ -682,7 +681,7 @@ __global__ __launch_bounds__(256) void tile16_packed_kernel(const Geom g, const 
   for (uint32_t h = 0; h < hits; ++h) {
 #pragma unroll
     for (uint32_t c = 0; c < 2; ++c) {
-      uint32_t ties = 0, k0 = 0, k1 = 0;
+      uint32_t ties = 0, k0 = 0, k1 = 0, k2 = 0;
       if (valid) {
         uint32_t* own = tw + c * kT16Words;
         const uint32_t* oth = tw + (1 - c) * kT16Words;
@@ -699,7 +698,6 @@ __global__ __launch_bounds__(256) void tile16_packed_kernel(const Geom g, const 
         // Metropolis: the unsatisfied bonds; heat bath: the up neighbours
         const uint32_t u[6] = {HB ? ~nxp : o ^ nxp, HB ? ~nxm : o ^ nxm, HB ? ~dn : o ^ dn,
                                HB ? ~up : o ^ up, 0u, 0u};
-        uint32_t k2;
         count_planes<2>(u, k0, k1, k2);
         // prefix bytes: row r's 8 sites are words 2 h0, 2 h0 + 1 of block j >> 4
         uint32_t P[8];
@@ -714,23 +712,14 @@ __global__ __launch_bounds__(256) void tile16_packed_kernel(const Geom g, const 
         }
         uint32_t B[8];
         prefix_planes(P, B);
-        uint32_t flip = FAST ? packed_compare_fast<2>(ft, B, k0, k1, k2, ties)
-                             : packed_compare<2>(tab, B, k0, k1, k2, ties);
-        while (!FAST && ties) {  // exact ties: the 24-bit refinement against the class's fraction
-          const uint32_t b = __builtin_ctz(ties);
-          ties &= ties - 1;
-          const uint32_t k = ((k0 >> b) & 1u) | (((k1 >> b) & 1u) << 1) | (((k2 >> b) & 1u) << 2);
-          const uint32_t js = j0 + (b >> 3) * R + (b & 7u);
-          const Rand4 rr = philox(js, t, key.replica, tag(c, kIsingRefine) | (h << 8), key.k0,
-                                  key.k1);
-          if ((rr.w[0] & 0xFFFFFFu) < frac_sel(tab.fr, k)) flip |= 1u << b;
-        }
-        own[1 + i] = HB ? ~flip : o ^ flip;  // with the fast decision, ties refused until resolved below
+        // exact ties refused, resolved below
+        const uint32_t flip = FAST ? packed_compare_fast<2>(ft, B, k0, k1, k2, ties)
+                                   : packed_compare<2>(tab, B, k0, k1, k2, ties);
+        own[1 + i] = HB ? ~flip : o ^ flip;
       }
-      if (FAST)
-        tile_ties_group<true>(tt, ties, k0, k1, j0, R, lw,
-                              gi * 2u * kT16Words + c * kT16Words + 1u + i, tab, key, t, c, h,
-                              tie_cap);
+      tile_ties_group<true, !FAST>(tt, ties, k0, k1, k2, j0, R, lw,
+                                   gi * 2u * kT16Words + c * kT16Words + 1u + i, tab, key, t, c,
+                                   h, tie_cap);
       __syncthreads();
     }
   }
