@@ -759,8 +759,8 @@ def attach_other_workloads(args, result, torch, smc):
     objects of the default line (same GPU, same run; no CPU baseline): 3D
     Ising L = 512 (one bit per site, with its int8 two-pass line), 2D XY
     L = 4096 and 3D Heisenberg L = 256 (FP32 spins), the tiled k-hit schedule
-    on the 2D lattice (T = 16 and 64, k = 100, Metropolis and heat bath), and
-    the derivative chains (256
+    on the 2D lattice (T = 16 and 64, k = 100, Metropolis and heat bath) and
+    on the 3D lattice (T = 16, k = 100), and the derivative chains (256
     chains of L = 64, forward and backward).  The batched
     spin-glass rate is set against the plain sweeps of the large lattices."""
     keep = ("value", "unit", "ms_per_step", "dtype", "roofline", "pct_hbm_peak")
@@ -791,6 +791,17 @@ def attach_other_workloads(args, result, torch, smc):
             o["kernel"] = r["config"]["kernel"]
             result[f"tiles{T}_heatbath" if hb else f"tiles{T}"] = o
             torch.cuda.empty_cache()
+    # and the paper's 3D row: 3D L = 512, 16^3 tiles (int8 in LDS), k = 100
+    a = argparse.Namespace(**vars(args))
+    a.workload, a.cpu_seconds = "ising3d", 0
+    a.tile, a.hits, a.heatbath = 16, 100, False
+    a.steps, a.warmup, a.sweeps_per_step = 2, 1, 1
+    r = run_lattice(a, WORKLOADS["ising3d"], torch, smc)
+    o = {k: r[k] for k in ("value", "unit", "ms_per_step", "dtype", "roofline")}
+    o["workload"] = r["config"]["workload"]
+    o["kernel"] = r["config"]["kernel"]
+    result["tiles16_3d"] = o
+    torch.cuda.empty_cache()
     a = argparse.Namespace(**vars(args))
     a.workload, a.steps, a.sweeps_per_step, a.cpu_seconds = "chains", None, None, 0
     r = run_chains(a, WORKLOADS["chains"], torch, smc)
