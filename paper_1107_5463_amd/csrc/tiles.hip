@@ -745,10 +745,159 @@ __global__ __launch_bounds__(256) void tile16_packed_kernel(const Geom g, const 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Bit-packed 16^3 tiles (3D, Metropolis or heat bath): each of the tile's 16
+// z-planes is laid out as a 16 x 16 tile of the 2D kernel above -- per colour
+// the column [above, w0, w1, w2, w3, below] and the left and right sites of
+// each word's four rows -- plus the words w0 .. w3 of the boundary planes
+// below and above the tile.  A lane owns word i of plane z (rows 4 i .. 4 i +
+// 3 of that plane); its z-neighbours are the other colour's words at the same
+// place in planes z - 1 and z + 1 (the in-row index of a site's z-neighbour
+// is its own), its y- and in-row neighbours those of the 2D kernel, with the
+// rows' parity (c + r + z) mod 2 (tiles start at even rows and planes).  A
+// tile is one wave (16 planes x 4 words), four tiles a workgroup.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kT3Planes = 18;  // the tile's 16 planes and the two boundary planes
+
+template <bool FAST, bool HB>
+__global__ __launch_bounds__(256) void tile16_packed3d_kernel(const Geom g, const RngKey key,
+                                                              const IsingTable table,
+                                                              const uint32_t hits, const uint32_t t,
+                                                              const uint32_t tc,
+                                                              const uint32_t ntiles,
+                                                              const uint32_t tie_cap,
+                                                              int8_t* __restrict__ s) {
+  constexpr uint32_t CW = kT3Planes * kT16Words;  // words of a colour of one tile
+  __shared__ uint32_t lw[4 * 2 * CW];
+  const uint32_t L = (uint32_t)g.L, R = (uint32_t)g.R;
+  const uint32_t gi = threadIdx.x >> 6, z = (threadIdx.x >> 2) & 15u, i = threadIdx.x & 3u;
+  const uint32_t bt = blockIdx.x * 4u + gi;
+  const bool valid = bt < ntiles;
+  const uint32_t nt = L / 16, half = nt / 2;
+  const uint32_t bv = valid ? bt : 0u;
+  const uint32_t tz = bv / (nt * half), rem = bv - tz * nt * half;
+  const uint32_t ty = rem / half;
+  const uint32_t tx = 2 * (rem - ty * half) + ((ty + tz + tc) & 1u);
+  const uint32_t Z0 = tz * 16, Y0 = ty * 16, x0 = tx * 8;
+  const uint32_t Zg = Z0 + z;  // the lane's plane
+  const uint64_t Nh = (uint64_t)g.Nh;
+  uint32_t* tw = lw + gi * 2u * CW;  // colour c, plane zz (0: below the tile) at tw + c CW + zz 14
+  auto bits8 = [&](const int8_t* row) -> uint32_t {  // sign bits of 8 sites
+    const uint2 v = *reinterpret_cast<const uint2*>(row);
+    return gather7(v.x) | (gather7(v.y) << 4);
+  };
+  auto rowp = [&](const int8_t* pl, uint32_t zg, uint32_t y) -> const int8_t* {
+    return pl + ((uint64_t)zg * L + y) * R;
+  };
+  // stage: lane (z, i) fills word i of plane z of both colours, its left and
+  // right sites, the boundary rows (i = 0 and 3) and the boundary planes'
+  // word i (z = 0 and 15)
+  if (valid) {
+#pragma unroll
+    for (uint32_t cc = 0; cc < 2; ++cc) {
+      uint32_t* col = tw + cc * CW + (z + 1) * kT16Words;
+      const int8_t* pl = s + cc * Nh;
+      uint32_t w = 0, lh = 0, rh = 0;
+      const uint32_t xl = x0 == 0 ? R - 1 : x0 - 1, xr = x0 + 8 == R ? 0 : x0 + 8;
+#pragma unroll
+      for (uint32_t r = 0; r < 4; ++r) {
+        const int8_t* row = rowp(pl, Zg, Y0 + 4 * i + r);
+        w |= bits8(row + x0) << (8 * r);
+        lh |= (row[xl] < 0 ? 1u : 0u) << (8 * r);
+        rh |= (row[xr] < 0 ? 0x80u : 0u) << (8 * r);
+      }
+      col[1 + i] = w;
+      col[6 + i] = lh;
+      col[10 + i] = rh;
+      if (i == 0) col[0] = bits8(rowp(pl, Zg, Y0 == 0 ? L - 1 : Y0 - 1) + x0) << 24;
+      if (i == 3) col[5] = bits8(rowp(pl, Zg, Y0 + 16 == L ? 0 : Y0 + 16) + x0);
+      if (z == 0 || z == 15) {
+        const uint32_t zb = z == 0 ? (Z0 == 0 ? L - 1 : Z0 - 1) : (Z0 + 16 == L ? 0 : Z0 + 16);
+        uint32_t wb = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < 4; ++r) wb |= bits8(rowp(pl, zb, Y0 + 4 * i + r) + x0) << (8 * r);
+        tw[cc * CW + (z == 0 ? 0u : kT3Planes - 1) * kT16Words + 1 + i] = wb;
+      }
+    }
+  }
+  __syncthreads();
+
+  const TabRegs tab = tab_regs(table);
+  FastTab ft;
+  if (FAST) ft = fast_tab<3>(tab);
+  const uint32_t j0 = ((uint32_t)Zg * L + Y0 + 4 * i) * R + x0;  // in-colour index of the word's first site
+  __shared__ TileTies tt;
+  for (uint32_t h = 0; h < hits; ++h) {
+#pragma unroll
+    for (uint32_t c = 0; c < 2; ++c) {
+      uint32_t ties = 0, k0 = 0, k1 = 0, k2 = 0;
+      if (valid) {
+        uint32_t* own = tw + c * CW + (z + 1) * kT16Words;
+        const uint32_t* oth = tw + (1 - c) * CW + (z + 1) * kT16Words;
+        const uint32_t o = own[1 + i], ct = oth[1 + i];
+        const uint32_t up = __builtin_amdgcn_alignbit(ct, oth[i], 24u);    // rows r - 1
+        const uint32_t dn = __builtin_amdgcn_alignbit(oth[2 + i], ct, 8u);  // rows r + 1
+        const uint32_t fz = oth[1 + i - kT16Words], bz = oth[1 + i + kT16Words];  // planes z -+ 1
+        const uint32_t sh_next = ((ct >> 1) & 0x7F7F7F7Fu) | oth[10 + i];   // site + 1 in its row
+        const uint32_t sh_prev = ((ct << 1) & 0xFEFEFEFEu) | oth[6 + i];    // site - 1
+        // rows of parity 1 (x + 1 = next site): rows 1, 3 when c + z is even, rows 0, 2 when odd
+        const uint32_t pm = ((c + z) & 1u) ? 0x00FF00FFu : 0xFF00FF00u;
+        const uint32_t nxp = (ct & ~pm) | (sh_next & pm);
+        const uint32_t nxm = (sh_prev & ~pm) | (ct & pm);
+        // Metropolis: the unsatisfied bonds; heat bath: the up neighbours
+        const uint32_t u[6] = {HB ? ~nxp : o ^ nxp, HB ? ~nxm : o ^ nxm, HB ? ~dn : o ^ dn,
+                               HB ? ~up : o ^ up,   HB ? ~bz : o ^ bz,   HB ? ~fz : o ^ fz};
+        count_planes<3>(u, k0, k1, k2);
+        // prefix bytes: row r's 8 sites are words 2 h0, 2 h0 + 1 of block j >> 4
+        uint32_t P[8];
+#pragma unroll
+        for (uint32_t r = 0; r < 4; ++r) {
+          const uint32_t jr = j0 + r * R;
+          const Rand4 rb = philox(jr >> 4, t, key.replica, tag(c, kIsingPrefix) | (h << 8), key.k0,
+                                  key.k1);
+          const bool h0 = ((jr >> 3) & 1u) != 0;
+          P[2 * r] = h0 ? rb.w[2] : rb.w[0];
+          P[2 * r + 1] = h0 ? rb.w[3] : rb.w[1];
+        }
+        uint32_t B[8];
+        prefix_planes(P, B);
+        // exact ties refused, resolved below
+        const uint32_t flip = FAST ? packed_compare_fast<3>(ft, B, k0, k1, k2, ties)
+                                   : packed_compare<3>(tab, B, k0, k1, k2, ties);
+        own[1 + i] = HB ? ~flip : o ^ flip;
+      }
+      tile_ties_group<true, !FAST>(tt, ties, k0, k1, k2, j0, R, lw,
+                                   gi * 2u * CW + c * CW + (z + 1) * kT16Words + 1u + i, tab, key,
+                                   t, c, h, tie_cap);
+      __syncthreads();
+    }
+  }
+
+  // write back word i of plane z of both colours: four rows of 8 sites as +-1 bytes
+  if (valid) {
+#pragma unroll
+    for (uint32_t cc = 0; cc < 2; ++cc) {
+      const uint32_t v = tw[cc * CW + (z + 1) * kT16Words + 1 + i];
+#pragma unroll
+      for (uint32_t r = 0; r < 4; ++r) {
+        const uint32_t byte = (v >> (8 * r)) & 0xFFu;
+        uint32_t q[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const uint32_t spread = (((byte >> (4 * k)) & 0xFu) * 0x00204081u) & kOnes;
+          q[k] = kOnes | (spread * 0xFEu);
+        }
+        *reinterpret_cast<uint2*>(s + cc * Nh + ((uint64_t)Zg * L + Y0 + 4 * i + r) * R + x0) =
+            make_uint2(q[0], q[1]);
+      }
+    }
+  }
+}
+
 bool tile_packed_supported(const Geom& g, uint32_t T, bool heatbath) {
   (void)heatbath;  // both rules
-  return g.d == 2 && (T == 16 || T == 64 || T == 128) && (uint32_t)g.L % T == 0 &&
-         ((uint32_t)g.L / T) % 2 == 0;
+  const bool shape = g.d == 2 ? (T == 16 || T == 64 || T == 128) : (g.d == 3 && T == 16);
+  return shape && (uint32_t)g.L % T == 0 && ((uint32_t)g.L / T) % 2 == 0;
 }
 
 // 256 lanes a workgroup: four tiles of 64 (64 words a colour each) or one of 128
@@ -803,6 +952,19 @@ hipError_t launch_tile_pass(const IsingLaunch& a, bool heatbath, uint32_t T, uin
       if ((((k < 4 ? a.tab.al_lo : a.tab.al_hi) >> (8 * (k & 3))) & 0xFFu) != 0xFFu) fast = false;
     // the workgroup's list of tied sites (packed_ties other than 0: each lane its own)
     const uint32_t tie_cap = a.packed_ties == 0 ? kTileTieCap : 0u;
+    if (T == 16 && a.g.d == 3) {
+      const dim3 grid((tiles + 3) / 4), block(256);
+      if (heatbath)
+        hipLaunchKernelGGL((tile16_packed3d_kernel<false, true>), grid, block, 0, st, a.g, a.key, a.tab,
+                           hits, t, tc, tiles, tie_cap, spins);
+      else if (fast)
+        hipLaunchKernelGGL((tile16_packed3d_kernel<true, false>), grid, block, 0, st, a.g, a.key, a.tab,
+                           hits, t, tc, tiles, tie_cap, spins);
+      else
+        hipLaunchKernelGGL((tile16_packed3d_kernel<false, false>), grid, block, 0, st, a.g, a.key, a.tab,
+                           hits, t, tc, tiles, tie_cap, spins);
+      return hipGetLastError();
+    }
     if (T == 16) {
       const dim3 grid((tiles + 63) / 64), block(256);
       if (heatbath)

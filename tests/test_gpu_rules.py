@@ -42,8 +42,10 @@ TILED = [  # d, L, tile, hits, heatbath, beta, sweeps
 
 
 def _tile_kernel_name(d, T, hb):
-    # 2D tiles of 16, 64 or 128 (either rule) take the bit-packed tile kernels
-    return "ising_tiles_packed" if d == 2 and T in (16, 64, 128) else "ising_tiles"
+    # 2D tiles of 16, 64 or 128 and 3D tiles of 16 (either rule) take the
+    # bit-packed tile kernels
+    packed = T in (16, 64, 128) if d == 2 else T == 16
+    return "ising_tiles_packed" if packed else "ising_tiles"
 
 
 @pytest.mark.parametrize("d,L,T,k,hb,beta,n", TILED)
@@ -135,6 +137,51 @@ def test_packed_heatbath_tiles_match_oracle(smc_gpu, oracle_mod, L, T, k, J0, be
     assert np.array_equal(nat(lat), ref.s)
     o, r = lat.measure(), ref.measure()
     assert (o.E_int, o.M_int) == (r.E_int, r.M_int)
+
+
+PACKED_3D_TILES = [  # L, hits, J0, heatbath, beta, sweeps
+    (32, 3, 1.0, False, 0.2216546, 2),    # 4 tiles a colour: one workgroup
+    (64, 2, 1.0, False, 0.3, 2),          # 32 tiles a colour: 8 workgroups
+    (96, 2, 1.0, False, 0.2216546, 1),    # 108 tiles a colour: the last workgroup fully used
+    (32, 3, 1.0, False, 1.0, 2),          # low temperature: many exact ties
+    (32, 2, -1.0, False, 0.3, 2),         # J0 < 0: the general decision
+    (32, 2, 1.0, True, 0.25, 2),          # heat bath
+    (64, 2, 1.0, True, 1.0, 2),           # heat bath, low temperature
+]
+
+
+@pytest.mark.parametrize("ties", ["group", "lane"])
+@pytest.mark.parametrize("L,k,J0,hb,beta,n", PACKED_3D_TILES)
+def test_packed_3d_tiles_match_oracle(smc_gpu, oracle_mod, monkeypatch, L, k, J0, hb, beta, n, ties):
+    """The bit-packed 16^3 tile kernel (either rule) against the oracle's tiled
+    schedule, bit for bit, with the measurement after it."""
+    monkeypatch.setenv("SMC_PACKED_TIES", ties)
+    print(f"packed 3D tiles L={L} k={k} J0={J0} hb={hb} beta={beta} ties={ties}", flush=True)
+    lat = smc_gpu.Lattice(3, 1, L, seed=23, J0=J0, tile=16, hits=k, heatbath=hb)
+    assert lat.kernel() == ("ising_tiles_packed", 16)
+    ref = oracle_mod.OracleLattice(3, 1, L, 23, J0=J0)
+    lat.sweep(beta, n)
+    ref.sweep_rule(beta, n, "heatbath" if hb else "metropolis", 16, k)
+    assert np.array_equal(nat(lat), ref.s)
+    o, r = lat.measure(), ref.measure()
+    assert (o.E_int, o.M_int) == (r.E_int, r.M_int)
+
+
+@pytest.mark.parametrize("hb", [False, True])
+def test_packed_and_byte_3d_tiles_run_the_same_chain(smc_gpu, monkeypatch, hb):
+    """Both 16^3 tile kernels on a 3D L=128 lattice, k = 3 hits: the same states."""
+    import torch
+    states = {}
+    for kernel in ("byte", "packed"):
+        if kernel == "byte":
+            monkeypatch.setenv("SMC_TILE_KERNEL", "byte")
+        else:
+            monkeypatch.delenv("SMC_TILE_KERNEL", raising=False)
+        lat = smc_gpu.Lattice(3, 1, 128, seed=29, tile=16, hits=3, heatbath=hb)
+        assert lat.kernel()[0] == ("ising_tiles" if kernel == "byte" else "ising_tiles_packed")
+        lat.sweep(0.2216546, 2)
+        states[kernel] = lat.spins.clone()
+    assert torch.equal(states["byte"], states["packed"])
 
 
 def test_tiled_sweep_measure(smc_gpu, oracle_mod):
