@@ -791,7 +791,7 @@ def attach_other_workloads(args, result, torch, smc):
             o["kernel"] = r["config"]["kernel"]
             result[f"tiles{T}_heatbath" if hb else f"tiles{T}"] = o
             torch.cuda.empty_cache()
-    # and the paper's 3D row: 3D L = 512, 16^3 tiles (int8 in LDS), k = 100
+    # and the paper's 3D row: 3D L = 512, 16^3 tiles at one bit per site in LDS, k = 100
     a = argparse.Namespace(**vars(args))
     a.workload, a.cpu_seconds = "ising3d", 0
     a.tile, a.hits, a.heatbath = 16, 100, False
