@@ -234,8 +234,9 @@ int smc_autotune(smc_lattice* h, double beta, void* scratch, size_t scratch_byte
 /* Name of the kernel the handle's sweeps launch -- Ising: "ising_packed"
  * (one bit per site), "ising_fused", "ising_stream", "ising_chunk",
  * "ising_site", and for the tiled schedule "ising_tiles" (int8 tiles) or
- * "ising_tiles_packed" (tiles at one bit per site in LDS: 2D, Metropolis or
- * heat bath, tile edge 16, 64 or 128); XY / Heisenberg: "xy_stream", "xy_site",
+ * "ising_tiles_packed" (tiles at one bit per site in LDS, Metropolis or heat
+ * bath: 2D tile edge 16, 64 or 128, 3D tile edge 16); XY / Heisenberg:
+ * "xy_stream", "xy_site",
  * "heisenberg_stream", "heisenberg_site" -- and in rows_per_band (optional)
  * the rows each lane walks for the banded kernels (packed, fused, stream,
  * xy_stream, heisenberg_stream), the tile edge for the tiled schedule, 0
